@@ -1,0 +1,56 @@
+"""The oracle pins must catch plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle source (on the CPU, in a
+temporary directory), builds it, and runs the pin tests against that library in
+a subprocess; at least one pin must fail.  The real oracle is untouched.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from oracle import build as obuild
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "tfs_oracle.c")
+
+# name -> (original text, planted mistake, pytest -k expression of pins expected to fail)
+MUTATIONS = {
+    "transposed_kappa": ("const sc kml = kap[m * d + l];", "const sc kml = kap[l * d + m];", "operator"),
+    "dropped_stretch_term": ("((2.0 * a * a - 1.0) / (2.0 * De) + kap[l * d + l])",
+                             "((2.0 * a * a - 1.0) / (2.0 * De))", "operator"),
+    "half_relaxation": ("diag += (kap[l * d + l] - 1.0 / (2.0 * De))",
+                        "diag += (kap[l * d + l] - 1.0 / (4.0 * De))", "operator"),
+    "bdf2_coefficient_sign": ("const double b0 = 1.5, b1 = -2.0, b2 = 0.5;",
+                              "const double b0 = 1.5, b1 = -2.0, b2 = -0.5;", "alpha_one"),
+    "eta_k_with_weight": ("const sc etak = lam[k] * dt / (b0 + lam[k] * dt);",
+                          "const sc etak = w[k] * dt / (b0 + lam[k] * dt);", "brute_force"),
+    "sdirk_diagonal": ("const double gs = 1.0 - 1.0 / sqrt(2.0);", "const double gs = 0.5;", "sdirk2 or alpha_one"),
+    "recombination_sign": ("terms[k] = w[k] * Pnew[q] - lam[k] * Knew[k * n + q];",
+                           "terms[k] = w[k] * Pnew[q] + lam[k] * Knew[k * n + q];", "brute_force or sdirk2"),
+    "stage_two_explicit_part": ("E[q] = Pn[q] + dt * (1.0 - gs) * F1[q];", "E[q] = Pn[q];", "sdirk2"),
+    "hermite_map_scale": ("else if (i1 == i2) Phi[r] = Xfull[i1 * d + i1] / sqrt(2.0);",
+                          "else if (i1 == i2) Phi[r] = Xfull[i1 * d + i1] / 2.0;", "hermite_map or operator"),
+    "mode_push_dropped_level": ("Km[k * n + q] = (-(b1 * Kn[k * n + q] + b2 * Km[k * n + q]) + w[k] * dt * rhs[q]) /",
+                                "Km[k * n + q] = (-(b1 * Kn[k * n + q]) + w[k] * dt * rhs[q]) /", "brute_force"),
+    "eta_without_b0": ("eta += b0 * w[k] * dt / (b0 + lam[k] * dt);", "eta += w[k] * dt / (b0 + lam[k] * dt);",
+                       "alpha_one or brute_force"),
+    "no_extrapolation": ("kt[q] = 2.0 * ka[q] - kb[q];", "kt[q] = ka[q];", "time_varying"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_fails_a_pin(name, tmp_path):
+    orig, bad, sel = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(orig) == 1, "mutation anchor drifted from the oracle source"
+    msrc = tmp_path / "mutant.c"
+    msrc.write_text(src.replace(orig, bad))
+    lib = str(tmp_path / "libmutant.so")
+    obuild.build(src=str(msrc), lib=lib)
+    env = dict(os.environ, TFS_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        "-q", "-x", "-p", "no:cacheprovider", "-k", sel],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"no pin caught '{name}':\n{r.stdout[-2000:]}"
