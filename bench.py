@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the time-fractional extra-stress update on one MI355X.
+
+Default workload: the 2-D FP64 configuration, 1024x1024 points, m = 32 exponential
+modes, alpha in {0.3, 0.7} (two independent fields), dt = 5e-4, 1000 time levels of a
+time-varying seeded divergence-free velocity gradient with second-order extrapolation.
+All kappa levels, the state rings and the mode rings are resident in HBM before the
+timed region; one benchmark step advances both fields by one time level (two launches
+of the fused BDF2 kernel).
+
+Prints one JSON line: point-mode updates/s, the roofline of the fused step kernel
+(algorithmic bytes per launch / average launch duration from HIP events on the plan's
+stream), and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def algorithmic_bytes_per_point(dim, m, mode_bytes, kappa_reads):
+    """Minimum HBM traffic of one step per point: two mode levels read and one written,
+    X at two levels read and one written, tau written, kappa read (1 or 2 levels)."""
+    c = dim * (dim + 1) // 2
+    return 3 * m * c * mode_bytes + 3 * c * 8 + c * 8 + kappa_reads * dim * dim * 8
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, alpha, w, lam, nthreads):
+    """Oracle on a bounded sample of the workload: every 2nd point of the grid for all
+    time levels, kappa frozen at t = 0 (the oracle's per-step work does not depend on it)."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2411_17294_amd import inputs as I
+    pts = np.arange(0, wl.npoints, 2)
+    ff = I.fourier_field(wl)
+    kap = ff.kappa_at(I.grid_multi_index(wl.grid, wl.dim, pts), wl.grid, 0.0)
+    X0 = I.initial_state(wl, pts)
+    O.run(wl.dim, w, lam, wl.De, wl.eta_p, wl.dt, 2, kap, X0, nthreads=nthreads)  # load + warm
+    t0 = time.perf_counter()
+    O.run(wl.dim, w, lam, wl.De, wl.eta_p, wl.dt, wl.nsteps, kap, X0, nthreads=nthreads)
+    el = time.perf_counter() - t0
+    rate = len(pts) * len(w) * wl.nsteps / el
+    return {"value": rate, "unit": "point-mode updates/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{len(pts)} points (every 2nd of {wl.grid}^{wl.dim}), {wl.nsteps} steps, alpha={alpha}, "
+                      f"m={len(w)}, FP64, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=990)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", type=int, default=2, help="workload id (2 = default 2-D FP64)")
+    ap.add_argument("--form", choices=["default", "fp64", "fp32_modes"], default="default")
+    ap.add_argument("--vec", type=int, default=0)
+    ap.add_argument("--grid-per-cu", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; the update is pointwise and would shard by "
+                                   "point slabs with no exchange, but multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2411_17294_amd import inputs as I
+    from paper_2411_17294_amd import tfs
+    from paper_2411_17294_amd.device_inputs import DeviceKappa, x0_ring
+
+    wl = I.WORKLOADS[args.workload]
+    form = wl.precision if args.form == "default" else args.form
+    N = wl.nsteps
+    if args.warmup < 1:
+        raise SystemExit("warmup must include the start-up step (>= 1)")
+    if args.warmup + args.steps > N:
+        raise SystemExit(f"warmup + steps must not exceed the workload's {N} time levels")
+    torch.cuda.set_device(0)
+    dev = "cuda"
+    stream = torch.cuda.current_stream()
+
+    # inputs resident in HBM
+    ff = I.fourier_field(wl)
+    dk = DeviceKappa(ff, wl.grid, wl.npoints)
+    plans, states = [], []
+    for alpha in wl.alphas:
+        w, lam, _, _, info = tfs.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * N)
+        log(f"alpha={alpha}: SOE symbol rel err {info['symbol_relerr']:.2e}")
+        p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, N, precision=form)
+        if args.vec:
+            p.tune("vec", args.vec)
+        p.tune("grid_per_cu", args.grid_per_cu)
+        X = x0_ring(wl, p.stride)
+        _, Y, tau, _ = p.alloc()
+        plans.append((alpha, w, lam, p))
+        states.append((X, Y, tau))
+    st = plans[0][3].stride
+    t0 = time.perf_counter()
+    if wl.time_varying:
+        nlev = args.warmup + args.steps
+        kap = torch.empty((nlev, wl.dim * wl.dim, st), dtype=torch.float64, device=dev)
+        for n in range(nlev):
+            dk.fill(kap[n], n * wl.dt)
+        level = lambda n: (kap[n], kap[n - 1] if n >= 1 else None)
+    else:
+        k0 = torch.empty((wl.dim * wl.dim, st), dtype=torch.float64, device=dev)
+        dk.fill(k0, 0.0)
+        level = lambda n: (k0, k0)
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
+
+    def step(n):
+        ka, kb = level(n)
+        for (_, _, _, p), (X, Y, tau) in zip(plans, states):
+            p.step(n, ka, kb, X, Y, tau)
+
+    for n in range(args.warmup):
+        step(n)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for n in range(args.warmup, args.warmup + args.steps):
+        step(n)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    ms_per_step = ms / args.steps
+    for (X, Y, tau) in states:
+        if not bool(torch.isfinite(tau[:, :wl.npoints]).all()):
+            raise SystemExit("non-finite stress in the benchmark run")
+
+    nfields = len(wl.alphas)
+    updates = nfields * wl.npoints * wl.nmodes * args.steps
+    value = updates / (ms * 1e-3)
+    mode_bytes = 8 if form == "fp64" else 4
+    bpp = algorithmic_bytes_per_point(wl.dim, wl.nmodes, mode_bytes, 2)
+    bytes_per_launch = bpp * wl.npoints
+    launches = nfields * args.steps
+    avg_launch_s = ms * 1e-3 / launches
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+
+    out = {
+        "metric": "point-mode updates/s + % HBM roofline, FP64 vs FP32-mode fwd+adjoint",
+        "value": value,
+        "unit": "point-mode updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if form == "fp64" else "f32 modes / f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": f"{wl.grid}^{wl.dim}", "alphas": list(wl.alphas),
+                   "modes": wl.nmodes, "dt": wl.dt, "time_levels": N, "form": form,
+                   "kappa": "time-varying, extrapolated" if wl.time_varying else "steady",
+                   "fields_per_step": nfields},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "bdf2_kernel", "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": avg_launch_s * 1e6},
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        nthreads = min(16, os.cpu_count() or 1)
+        alpha, w, lam, _ = plans[0]
+        out["cpu_baseline"] = cpu_baseline(wl, alpha, w, lam, nthreads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

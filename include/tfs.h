@@ -1,0 +1,182 @@
+/*
+ * tfs.h -- C ABI of the MI355X time-fractional extra-stress update.
+ *
+ * The library advances, independently at every point of a grid, the
+ * kernel-compressed time-fractional macroscopic Fokker-Planck system of a dilute
+ * Hookean polymer solution under a prescribed velocity gradient kappa = grad u
+ * (homogeneous flow: no advection, no centre-of-mass diffusion).  In tensor
+ * variables X = C - I (conformation minus identity, symmetric) the model is
+ *
+ *   dX/dt = A_kappa(D^{1-alpha} X) + S_kappa D^{1-alpha} 1,      tau = gamma D^{1-alpha} X,
+ *   A_kappa(Y) = kappa Y + Y kappa^T - Y/De,   S_kappa = kappa + kappa^T,   gamma = eta_p/De,
+ *
+ * i.e. the tested configuration operator of Sec. 3.2 (eq. conf_op_tested) with
+ * a = 1/sqrt(2), the Riemann-Liouville derivative of Sec. 1 placed on the right-hand
+ * side, and Kramers' stress for a unit-mass density.  The memory kernel
+ * t^(alpha-1)/Gamma(alpha) is replaced by sum_k w_k exp(-lambda_k t) (Sec. 2.2), each
+ * exponential carried as a fractional-mode field X_k, and time is discretised by the
+ * BDF2 scheme of Sec. 4.1 (eqs. BDF_Phi_k_n+1 and FP_discrete) after one SDIRK2 step.
+ *
+ * Every function is extern "C", never throws, and returns a tfs_status.  Device
+ * pointers are HIP device addresses; "host" pointers are ordinary memory.
+ *
+ * Packed symmetric components (c = d(d+1)/2):  2-D (xx, yy, xy);  3-D (xx, yy, zz, xy, xz, yz).
+ * Velocity gradient components (d*d):          row-major kappa_ij = d u_i / d x_j.
+ * Every field is structure-of-arrays with the point index fastest and a plane
+ * stride of `stride` elements (>= npoints) between consecutive planes.
+ */
+#ifndef TFS_H
+#define TFS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TFS_OK = 0,
+    TFS_EINVAL = 1,       /* invalid argument (message from tfs_last_error) */
+    TFS_ENOMEM = 2,       /* device or host allocation failed (plan creation only) */
+    TFS_EHIP = 3,         /* a HIP runtime call failed */
+    TFS_ENUMERIC = 4,     /* TFS_FLAG_CHECK_SYNC: a non-finite value or a non-positive-definite C appeared */
+    TFS_EUNSUPPORTED = 5  /* valid request this build does not implement */
+} tfs_status;
+
+typedef enum {
+    TFS_FP64 = 0,         /* modes stored and updated in FP64 */
+    TFS_FP32_MODES = 1    /* modes stored in FP32; recombination, solve, X, tau and all coefficients in FP64 */
+} tfs_precision;
+
+enum {
+    TFS_FLAG_CHECK_SYNC = 1u << 0  /* tfs_step synchronises and returns TFS_ENUMERIC on non-finite/non-PD diagnostics */
+};
+
+typedef struct tfs_plan_s* tfs_plan;
+
+typedef struct {
+    int32_t dim;          /* 2 or 3 */
+    int32_t nmodes;       /* m >= 1 exponential modes */
+    int64_t npoints;      /* points updated by each call (>= 0) */
+    int64_t stride;       /* plane stride in elements; 0 means npoints; must be >= npoints */
+    double alpha;         /* fractional order in (0, 1]; kept for reporting and gradients */
+    double De;            /* relaxation time (Deborah/Weissenberg number) > 0 */
+    double eta_p;         /* polymer viscosity (1-beta)/Re >= 0; gamma = eta_p/De (Sec. 1, Kramers) */
+    double dt;            /* time step > 0 */
+    int64_t max_steps;    /* time levels 0..max_steps may be produced; tfs_step accepts n < max_steps */
+    const double* w;      /* host [m] weights w_k >= 0, finite (copied) */
+    const double* lambda; /* host [m] poles lambda_k >= 0, finite (copied) */
+    int32_t precision;    /* tfs_precision */
+    uint32_t flags;       /* TFS_FLAG_* */
+    void* stream;         /* hipStream_t the plan launches on (NULL = default stream) */
+} tfs_plan_desc;
+
+/*
+ * Create a plan: validates the descriptor, copies (w, lambda), and precomputes in
+ * FP64 on the host the per-mode BDF2 factors of Sec. 4.1 (d_k = 1/(b0 + lambda_k dt),
+ * c_k = w_k dt d_k, eta_k = lambda_k dt d_k, eta = sum_k b0 c_k, b = (3/2, -2, 1/2)),
+ * the SDIRK2 start-up factors, and the table zeta^n of the spatially uniform mass
+ * mode's memory term (the mass mode Phi_000 = 1 of Sec. 3.4 and its fractional modes
+ * are the same at every point, so its contribution is one scalar per step).  These
+ * tables are uploaded once.  The plan owns them and a small reduction buffer.
+ * Errors: TFS_EINVAL (dim not 2/3, m < 1, npoints < 0, stride < npoints, alpha not in
+ * (0,1], De <= 0, eta_p < 0, dt <= 0, max_steps < 1, null or negative/non-finite w or
+ * lambda, unknown precision), TFS_ENOMEM, TFS_EHIP.  *out is NULL on error.
+ */
+tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out);
+
+/* Release a plan (NULL is accepted).  Synchronises its stream first. */
+tfs_status tfs_plan_destroy(tfs_plan plan);
+
+/* Rebind the stream later launches use. */
+tfs_status tfs_plan_set_stream(tfs_plan plan, void* stream);
+
+/*
+ * Advance every point from time level n to n+1 (0 <= n < max_steps), asynchronously
+ * on the plan's stream; no allocation, no host synchronisation (unless
+ * TFS_FLAG_CHECK_SYNC).
+ *
+ * kappa_a, kappa_b  device [d*d][stride], FP64.  The step is driven by
+ *                   kappa~ = 2 kappa_a - kappa_b  (second-order extrapolation
+ *                   E^{n+1} kappa = 2 kappa^n - kappa^{n-1}, eq. BDF_and_extrapolation:
+ *                   pass kappa^n, kappa^{n-1}), or kappa~ = kappa_a when kappa_b is NULL
+ *                   (pass the gradient of the already updated velocity kappa^{n+1}, as in
+ *                   eq. FP_discrete).  At n = 0 kappa_b is ignored.
+ * X                 device [2][c][stride] FP64 ring: slot j%2 holds level j.  The caller
+ *                   stores X^0 in slot 0 before n = 0.  Level n+1 overwrites slot (n+1)%2.
+ * Y                 device [2][m][c][stride] ring of the fractional modes in the
+ *                   representation Y_k = X_k - c_k X (FP64, or FP32 for TFS_FP32_MODES):
+ *                   slot j%2 holds level j.  Written entirely at n = 0 (levels 0 and 1);
+ *                   its input contents are ignored then.
+ * tau               device [c][stride] FP64 or NULL: tau^{n+1} = gamma D^{1-alpha} X^{n+1}.
+ * diag              device [6] FP64 or NULL: over the points at level n+1, the minimum of the
+ *                   three leading principal minors of C = I + X (Sylvester's criterion as used
+ *                   in the appendix; in 2-D the third equals the second), max ||tau||_F,
+ *                   sum ||tau||_F^2 (full tensor), and the count of non-finite X or tau
+ *                   entries.  Minima and maxima skip non-finite values.
+ * Errors: TFS_EINVAL (null plan/X/Y/kappa_a, n out of range, diag requested with
+ * npoints == 0 is fine), TFS_EHIP, TFS_ENUMERIC (only with TFS_FLAG_CHECK_SYNC).
+ */
+tfs_status tfs_step(tfs_plan plan, int64_t n, const double* kappa_a, const double* kappa_b,
+                    double* X, void* Y, double* tau, double* diag);
+
+/*
+ * Convert the mode ring slot `slot` (0 or 1) to plain fractional modes
+ * X_k = Y_k + c_k X, with X taken from the same slot of the X ring.
+ * Xk_out: device [m][c][stride] FP64.  Asynchronous on the plan's stream.
+ */
+tfs_status tfs_modes_to_plain(tfs_plan plan, int32_t slot, const double* X, const void* Y, double* Xk_out);
+
+/*
+ * Host copies of the plan's coefficient tables, FP64:
+ *   tables  [5][m]: d_k, c_k, eta_k, u_k, v_k (u_k, v_k: SDIRK2 start-up mode factors)
+ *   scalars [8]:    eta, sum_k eta_k c_k, b0 + eta/De, gamma/dt, theta, rho, sigma1, sigma2
+ *   zeta    [max_steps+1]: zeta^j (zeta^0 = zeta^1 = 0 are unused)
+ * Any pointer may be NULL.
+ */
+tfs_status tfs_plan_tables(tfs_plan plan, double* tables, double* scalars, double* zeta);
+
+/* Effective plane stride (elements) of the plan. */
+int64_t tfs_plan_stride(tfs_plan plan);
+
+/*
+ * Launch tuning; does not change results beyond rounding-order-free choices:
+ *   "vec"          points per lane: 0 = widest width the alignment of the fields allows
+ *                  (default), or 1, 2 (and 4 for TFS_FP32_MODES); a width the alignment
+ *                  does not allow falls back to 1 at launch.
+ *   "grid_per_cu"  cap on blocks per compute unit of the grid-stride launches, 1..16.
+ * Note: the diagnostic sum's rounding order depends on the grid; results of X, tau, Y do not.
+ */
+tfs_status tfs_plan_tune(tfs_plan plan, const char* key, int64_t value);
+
+/*
+ * Sum-of-exponentials fit of t^(alpha-1)/Gamma(alpha) with exactly m modes, host, FP64.
+ * The Laplace symbol s^(-alpha) = (sin(pi alpha)/pi) int exp((1-alpha)y)/(s+e^y) dy is
+ * discretised in y = ln(lambda): one lambda = 0 mode for y < y_lo, an (m-2)-point
+ * Gauss-Legendre rule on [y_lo, y_hi], one mode lambda = e^{y_hi}(1+alpha)/alpha carrying
+ * the mass and first moment of y > y_hi.  w_k > 0, lambda_k >= 0 by construction, so the
+ * approximate kernel is completely monotone (Sec. 2.2).  The window minimises the
+ * relative error of the symbol on [0.1/T, 10/dt].  alpha = 1 gives w = (1, 0, ...), lambda = 0.
+ * Outputs (host, [m] each; dw_dalpha/dlambda_dalpha may be NULL): derivatives at the
+ * fixed window.  info (host [4] or NULL): y_lo, y_hi, symbol relative error, time-domain
+ * relative error on [dt, T].
+ * Errors: TFS_EINVAL (alpha not in (0,1], m < 1, dt <= 0, T <= dt, null w/lambda).
+ */
+tfs_status tfs_soe_fit(double alpha, int32_t m, double dt, double T, double* w, double* lambda,
+                       double* dw_dalpha, double* dlambda_dalpha, double* info);
+
+/* Same rule at a given window (y_lo < y_hi). */
+tfs_status tfs_soe_gl_log(double alpha, int32_t m, double y_lo, double y_hi, double* w, double* lambda,
+                          double* dw_dalpha, double* dlambda_dalpha);
+
+/* Static description of a status code. */
+const char* tfs_status_string(tfs_status s);
+
+/* Thread-local text of the last error reported by this library ("" if none). */
+const char* tfs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFS_H */

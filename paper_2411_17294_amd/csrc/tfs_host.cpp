@@ -1,0 +1,415 @@
+// Host side of the C ABI: plan validation, FP64 coefficient tables, the mass-mode
+// memory table, the sum-of-exponentials fit, and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tfs_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tfs_status fail(tfs_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+tfs_status hip_fail(hipError_t e, const char* what) {
+  return fail(TFS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+// Neumaier-compensated accumulator.
+struct CompSum {
+  double s = 0.0, c = 0.0;
+  void add(double x) {
+    double t = s + x;
+    if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+    s = t;
+  }
+  double value() const { return s + c; }
+};
+
+// Legendre P_n(z) and P_{n-1}(z) by the three-term recurrence.
+void legendre_pair(int n, double z, double* pn, double* pnm1) {
+  double a = 1.0, b = z;  // P_0, P_1
+  if (n == 0) { *pn = 1.0; *pnm1 = 0.0; return; }
+  for (int k = 2; k <= n; ++k) {
+    const double c = ((2.0 * k - 1.0) * z * b - (k - 1.0) * a) / k;
+    a = b;
+    b = c;
+  }
+  *pn = b;
+  *pnm1 = a;
+}
+
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1]: Newton iteration on P_n from
+// the asymptotic node guesses; P_n'(z) = n (P_{n-1}(z) - z P_n(z)) / (1 - z^2),
+// weight 2 / ((1 - z^2) P_n'(z)^2).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& wq) {
+  x.assign(n, 0.0);
+  wq.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double pn, pnm1, dp;
+    for (int it = 0; it < 100; ++it) {
+      legendre_pair(n, z, &pn, &pnm1);
+      dp = n * (pnm1 - z * pn) / (1.0 - z * z);
+      const double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) <= 1e-16 * std::max(1.0, std::fabs(z))) break;
+    }
+    legendre_pair(n, z, &pn, &pnm1);
+    dp = n * (pnm1 - z * pn) / (1.0 - z * z);
+    x[n - 1 - i] = z;
+    wq[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+void soe_rule(double alpha, int m, double ylo, double yhi, double* w, double* lam, double* dw,
+              double* dlam) {
+  for (int k = 0; k < m; ++k) {
+    w[k] = 0.0; lam[k] = 0.0;
+    if (dw) dw[k] = 0.0;
+    if (dlam) dlam[k] = 0.0;
+  }
+  if (alpha == 1.0) {
+    w[0] = 1.0;
+    return;
+  }
+  const double s = std::sin(M_PI * alpha) / M_PI;
+  const double cot = M_PI * std::cos(M_PI * alpha) / std::sin(M_PI * alpha);
+  w[0] = s * std::exp((1.0 - alpha) * ylo) / (1.0 - alpha);
+  if (dw) dw[0] = w[0] * (cot - ylo + 1.0 / (1.0 - alpha));
+  if (m >= 2) {
+    const int j = m - 1;
+    lam[j] = std::exp(yhi) * (1.0 + alpha) / alpha;
+    w[j] = s * std::exp((1.0 - alpha) * yhi) * (1.0 + alpha) / (alpha * alpha);
+    if (dlam) dlam[j] = -std::exp(yhi) / (alpha * alpha);
+    if (dw) dw[j] = w[j] * (cot - yhi + 1.0 / (1.0 + alpha) - 2.0 / alpha);
+  }
+  if (m >= 3) {
+    std::vector<double> x, gw;
+    gauss_legendre(m - 2, x, gw);
+    const double half = 0.5 * (yhi - ylo), mid = 0.5 * (yhi + ylo);
+    for (int i = 0; i < m - 2; ++i) {
+      const double y = mid + half * x[i];
+      w[1 + i] = s * half * gw[i] * std::exp((1.0 - alpha) * y);
+      lam[1 + i] = std::exp(y);
+      if (dw) dw[1 + i] = w[1 + i] * (cot - y);
+    }
+  }
+}
+
+double symbol_relerr(double alpha, int m, const double* w, const double* lam, double dt, double T, int ns) {
+  const double lo = std::log(0.1 / T), hi = std::log(10.0 / dt);
+  double worst = 0.0;
+  for (int i = 0; i < ns; ++i) {
+    const double s = std::exp(lo + (hi - lo) * i / (ns - 1));
+    double K = 0.0;
+    for (int k = 0; k < m; ++k) K += w[k] / (s + lam[k]);
+    worst = std::max(worst, std::fabs(K * std::pow(s, alpha) - 1.0));
+  }
+  return worst;
+}
+
+double kernel_relerr(double alpha, int m, const double* w, const double* lam, double dt, double T, int ns) {
+  const double lo = std::log(dt), hi = std::log(T);
+  const double g = std::tgamma(alpha);
+  double worst = 0.0;
+  for (int i = 0; i < ns; ++i) {
+    const double t = std::exp(lo + (hi - lo) * i / (ns - 1));
+    double K = 0.0;
+    for (int k = 0; k < m; ++k) K += w[k] * std::exp(-lam[k] * t);
+    const double ex = std::pow(t, alpha - 1.0) / g;
+    worst = std::max(worst, std::fabs(K - ex) / ex);
+  }
+  return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tfs_last_error(void) { return g_last_error.c_str(); }
+
+const char* tfs_status_string(tfs_status s) {
+  switch (s) {
+    case TFS_OK: return "ok";
+    case TFS_EINVAL: return "invalid argument";
+    case TFS_ENOMEM: return "out of memory";
+    case TFS_EHIP: return "HIP runtime error";
+    case TFS_ENUMERIC: return "non-finite or non-positive-definite state";
+    case TFS_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+tfs_status tfs_soe_gl_log(double alpha, int32_t m, double y_lo, double y_hi, double* w, double* lambda,
+                          double* dw_dalpha, double* dlambda_dalpha) {
+  if (!(alpha > 0.0 && alpha <= 1.0)) return fail(TFS_EINVAL, "alpha must be in (0, 1]");
+  if (m < 1) return fail(TFS_EINVAL, "m must be >= 1");
+  if (!w || !lambda) return fail(TFS_EINVAL, "null output");
+  if (!(y_lo < y_hi) || !std::isfinite(y_lo) || !std::isfinite(y_hi))
+    return fail(TFS_EINVAL, "need finite y_lo < y_hi");
+  soe_rule(alpha, m, y_lo, y_hi, w, lambda, dw_dalpha, dlambda_dalpha);
+  return TFS_OK;
+}
+
+tfs_status tfs_soe_fit(double alpha, int32_t m, double dt, double T, double* w, double* lambda,
+                       double* dw_dalpha, double* dlambda_dalpha, double* info) {
+  if (!(alpha > 0.0 && alpha <= 1.0)) return fail(TFS_EINVAL, "alpha must be in (0, 1]");
+  if (m < 1) return fail(TFS_EINVAL, "m must be >= 1");
+  if (!(dt > 0.0) || !(T > dt)) return fail(TFS_EINVAL, "need 0 < dt < T");
+  if (!w || !lambda) return fail(TFS_EINVAL, "null output");
+  if (alpha == 1.0) {
+    soe_rule(alpha, m, 0.0, 1.0, w, lambda, dw_dalpha, dlambda_dalpha);
+    if (info) { info[0] = 0.0; info[1] = 1.0; info[2] = 0.0; info[3] = 0.0; }
+    return TFS_OK;
+  }
+  std::vector<double> ww(m), ll(m);
+  const double lo0 = std::log(0.1 / T), hi0 = std::log(10.0 / dt);
+  double best = std::numeric_limits<double>::infinity(), blo = lo0, bhi = hi0;
+  // coarse search over the window, then a fine search around the best cell
+  for (int i = 0; i <= 34; ++i) {
+    for (int j = 0; j <= 42; ++j) {
+      const double ylo = lo0 - 16.0 + 0.5 * i, yhi = hi0 - 2.0 + 1.0 * j;
+      soe_rule(alpha, m, ylo, yhi, ww.data(), ll.data(), nullptr, nullptr);
+      const double e = symbol_relerr(alpha, m, ww.data(), ll.data(), dt, T, 120);
+      if (e < best) { best = e; blo = ylo; bhi = yhi; }
+    }
+  }
+  const double clo = blo, chi = bhi;
+  for (int i = 0; i <= 10; ++i) {
+    for (int j = 0; j <= 20; ++j) {
+      const double ylo = clo - 0.5 + 0.1 * i, yhi = chi - 1.0 + 0.1 * j;
+      soe_rule(alpha, m, ylo, yhi, ww.data(), ll.data(), nullptr, nullptr);
+      const double e = symbol_relerr(alpha, m, ww.data(), ll.data(), dt, T, 120);
+      if (e < best) { best = e; blo = ylo; bhi = yhi; }
+    }
+  }
+  soe_rule(alpha, m, blo, bhi, w, lambda, dw_dalpha, dlambda_dalpha);
+  if (info) {
+    info[0] = blo;
+    info[1] = bhi;
+    info[2] = symbol_relerr(alpha, m, w, lambda, dt, T, 300);
+    info[3] = kernel_relerr(alpha, m, w, lambda, dt, T, 400);
+  }
+  return TFS_OK;
+}
+
+tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
+  if (!out) return fail(TFS_EINVAL, "null output plan pointer");
+  *out = nullptr;
+  if (!desc) return fail(TFS_EINVAL, "null descriptor");
+  const tfs_plan_desc& D = *desc;
+  if (D.dim != 2 && D.dim != 3) return fail(TFS_EINVAL, "dim must be 2 or 3 (got %d)", D.dim);
+  if (D.nmodes < 1) return fail(TFS_EINVAL, "nmodes must be >= 1");
+  if (D.npoints < 0) return fail(TFS_EINVAL, "npoints must be >= 0");
+  const int64_t stride = D.stride == 0 ? D.npoints : D.stride;
+  if (stride < D.npoints) return fail(TFS_EINVAL, "stride must be >= npoints");
+  if (!(D.alpha > 0.0 && D.alpha <= 1.0)) return fail(TFS_EINVAL, "alpha must be in (0, 1]");
+  if (!(D.De > 0.0) || !std::isfinite(D.De)) return fail(TFS_EINVAL, "De must be > 0");
+  if (!(D.eta_p >= 0.0) || !std::isfinite(D.eta_p)) return fail(TFS_EINVAL, "eta_p must be >= 0");
+  if (!(D.dt > 0.0) || !std::isfinite(D.dt)) return fail(TFS_EINVAL, "dt must be > 0");
+  if (D.max_steps < 1) return fail(TFS_EINVAL, "max_steps must be >= 1");
+  if (!D.w || !D.lambda) return fail(TFS_EINVAL, "null w or lambda");
+  if (D.precision != TFS_FP64 && D.precision != TFS_FP32_MODES) return fail(TFS_EINVAL, "unknown precision");
+  for (int k = 0; k < D.nmodes; ++k)
+    if (!finite_nonneg(D.w[k]) || !finite_nonneg(D.lambda[k]))
+      return fail(TFS_EINVAL, "w and lambda must be finite and >= 0 (mode %d)", k);
+
+  tfs_plan_s* p = new (std::nothrow) tfs_plan_s();
+  if (!p) return fail(TFS_ENOMEM, "plan allocation");
+  p->d = D.dim;
+  p->c = D.dim * (D.dim + 1) / 2;
+  p->m = D.nmodes;
+  p->npoints = D.npoints;
+  p->stride = stride;
+  p->max_steps = D.max_steps;
+  p->alpha = D.alpha;
+  p->De = D.De;
+  p->eta_p = D.eta_p;
+  p->dt = D.dt;
+  p->gamma = D.eta_p / D.De;
+  p->precision = D.precision;
+  p->flags = D.flags;
+  p->stream = static_cast<hipStream_t>(D.stream);
+  p->w.assign(D.w, D.w + D.nmodes);
+  p->lam.assign(D.lambda, D.lambda + D.nmodes);
+
+  const int m = p->m;
+  const double dt = p->dt, b0 = tfs::kB0;
+  const double gs = 1.0 - 1.0 / std::sqrt(2.0);
+  const double hg = dt * gs;
+  p->hg = hg;
+  p->coef.assign((size_t)tfs::kNumCoef * m, 0.0);
+  CompSum eta, s_ec, theta, rho;
+  for (int k = 0; k < m; ++k) {
+    const double wk = p->w[k], lk = p->lam[k];
+    const double dk = 1.0 / (b0 + lk * dt);
+    const double ck = wk * dt * dk;
+    const double ek = lk * dt * dk;
+    const double r = 1.0 / (1.0 + hg * lk);
+    p->coef[tfs::kRowD * m + k] = dk;
+    p->coef[tfs::kRowDC * m + k] = dk * ck;
+    p->coef[tfs::kRowEta * m + k] = ek;
+    p->coef[tfs::kRowC * m + k] = ck;
+    // start-up modes: X_k^1 = [h(1-gs) w_k r X^(1) + h gs w_k X^(2)] r;  Y_k^1 = X_k^1 - c_k X^1
+    p->coef[tfs::kRowU * m + k] = dt * (1.0 - gs) * wk * r * r;
+    p->coef[tfs::kRowV * m + k] = hg * wk * r - ck;
+    eta.add(b0 * ck);
+    s_ec.add(ek * ck);
+    theta.add(wk * r);
+    rho.add(lk * wk * r * r);
+  }
+  p->eta = eta.value();
+  p->s_ec = s_ec.value();
+  p->a_diag = b0 + p->eta / p->De;
+  p->tau_scale = p->gamma / dt;
+  p->theta = theta.value();
+  p->rho = rho.value();
+  p->sigma1 = dt * (1.0 - gs) * (p->theta - hg * p->rho);
+  p->sigma2 = dt * p->theta - hg * dt * (1.0 - gs) * p->rho;
+  p->hr = dt * (1.0 - gs) * p->rho;
+
+  // Mass-mode memory: mu_k^0 = 0, mu_k^1 from the SDIRK2 stages with mass 1, then the
+  // BDF2 push-forward mu_k^{n+1} = d_k (2 mu_k^n - mu_k^{n-1}/2) + c_k; the step n -> n+1
+  // uses zeta^{n+1} = eta - sum_k eta_k (2 mu_k^n - mu_k^{n-1}/2).
+  p->zeta.assign((size_t)p->max_steps + 1, 0.0);
+  {
+    std::vector<double> mu_m(m, 0.0), mu_n(m);
+    for (int k = 0; k < m; ++k) {
+      const double r = 1.0 / (1.0 + hg * p->lam[k]);
+      mu_n[k] = (dt * (1.0 - gs) * p->w[k] * r + hg * p->w[k]) * r;
+    }
+    for (int64_t n = 1; n < p->max_steps; ++n) {
+      CompSum acc;
+      for (int k = 0; k < m; ++k) {
+        const double h = 2.0 * mu_n[k] - 0.5 * mu_m[k];
+        acc.add(p->coef[tfs::kRowEta * m + k] * h);
+        mu_m[k] = mu_n[k];
+        mu_n[k] = p->coef[tfs::kRowD * m + k] * h + p->coef[tfs::kRowC * m + k];
+      }
+      p->zeta[n + 1] = p->eta - acc.value();
+    }
+  }
+
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
+    p->num_cus = cus;
+  e = hipMalloc(&p->d_coef, sizeof(double) * p->coef.size());
+  if (e != hipSuccess) { delete p; return fail(TFS_ENOMEM, "coefficient table: %s", hipGetErrorString(e)); }
+  e = hipMemcpy(p->d_coef, p->coef.data(), sizeof(double) * p->coef.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { (void)hipFree(p->d_coef); delete p; return hip_fail(e, "upload coefficients"); }
+  p->part_cap = tfs::max_blocks(p);
+  e = hipMalloc(&p->d_part, sizeof(double) * tfs::kNumDiag * (size_t)std::max(1, p->part_cap));
+  if (e != hipSuccess) { (void)hipFree(p->d_coef); delete p; return fail(TFS_ENOMEM, "diagnostic scratch"); }
+  *out = p;
+  return TFS_OK;
+}
+
+tfs_status tfs_plan_destroy(tfs_plan p) {
+  if (!p) return TFS_OK;
+  hipError_t e1 = hipStreamSynchronize(p->stream);
+  hipError_t e2 = hipFree(p->d_coef);
+  hipError_t e3 = hipFree(p->d_part);
+  delete p;
+  if (e1 != hipSuccess) return hip_fail(e1, "hipStreamSynchronize");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
+  if (e3 != hipSuccess) return hip_fail(e3, "hipFree");
+  return TFS_OK;
+}
+
+tfs_status tfs_plan_set_stream(tfs_plan p, void* stream) {
+  if (!p) return fail(TFS_EINVAL, "null plan");
+  p->stream = static_cast<hipStream_t>(stream);
+  return TFS_OK;
+}
+
+int64_t tfs_plan_stride(tfs_plan p) { return p ? p->stride : -1; }
+
+tfs_status tfs_plan_tune(tfs_plan p, const char* key, int64_t value) {
+  if (!p || !key) return fail(TFS_EINVAL, "null plan or key");
+  if (std::strcmp(key, "vec") == 0) {
+    const bool ok = value == 0 || value == 1 || value == 2 || (value == 4 && p->precision == TFS_FP32_MODES);
+    if (!ok) return fail(TFS_EINVAL, "vec must be 0, 1, 2 (or 4 for FP32 modes)");
+    p->vec_override = (int)value;
+    return TFS_OK;
+  }
+  if (std::strcmp(key, "grid_per_cu") == 0) {
+    if (value < 1 || value > 1024) return fail(TFS_EINVAL, "grid_per_cu must be in [1, 1024]");
+    if (value > 16) return fail(TFS_EINVAL, "grid_per_cu above 16 exceeds the diagnostic scratch");
+    p->grid_per_cu = (int)value;
+    return TFS_OK;
+  }
+  return fail(TFS_EINVAL, "unknown tuning key '%s'", key);
+}
+
+tfs_status tfs_plan_tables(tfs_plan p, double* tables, double* scalars, double* zeta) {
+  if (!p) return fail(TFS_EINVAL, "null plan");
+  const int m = p->m;
+  if (tables) {
+    const int rows[5] = {tfs::kRowD, tfs::kRowC, tfs::kRowEta, tfs::kRowU, tfs::kRowV};
+    for (int r = 0; r < 5; ++r)
+      for (int k = 0; k < m; ++k) tables[r * m + k] = p->coef[rows[r] * m + k];
+  }
+  if (scalars) {
+    const double v[8] = {p->eta, p->s_ec, p->a_diag, p->tau_scale, p->theta, p->rho, p->sigma1, p->sigma2};
+    for (int i = 0; i < 8; ++i) scalars[i] = v[i];
+  }
+  if (zeta) for (size_t i = 0; i < p->zeta.size(); ++i) zeta[i] = p->zeta[i];
+  return TFS_OK;
+}
+
+tfs_status tfs_step(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, double* X, void* Y,
+                    double* tau, double* diag) {
+  if (!p) return fail(TFS_EINVAL, "null plan");
+  if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
+                                              (long long)n, (long long)p->max_steps);
+  if (p->npoints > 0 && (!kappa_a || !X || !Y)) return fail(TFS_EINVAL, "null kappa_a, X or Y");
+  hipError_t e = (n == 0) ? tfs::launch_startup(p, kappa_a, X, Y, tau, diag)
+                          : tfs::launch_bdf2(p, n, kappa_a, kappa_b, X, Y, tau, diag);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  if (p->flags & TFS_FLAG_CHECK_SYNC) {
+    e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (diag) {
+      double h[tfs::kNumDiag];
+      e = hipMemcpy(h, diag, sizeof(h), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e, "diagnostic read-back");
+      if (h[5] != 0.0) return fail(TFS_ENUMERIC, "%g non-finite entries at level %lld", h[5], (long long)(n + 1));
+      if (p->npoints > 0 && !(h[0] > 0.0 && h[1] > 0.0 && h[2] > 0.0))
+        return fail(TFS_ENUMERIC, "conformation not positive definite at level %lld", (long long)(n + 1));
+    }
+  }
+  return TFS_OK;
+}
+
+tfs_status tfs_modes_to_plain(tfs_plan p, int32_t slot, const double* X, const void* Y, double* Xk_out) {
+  if (!p) return fail(TFS_EINVAL, "null plan");
+  if (slot != 0 && slot != 1) return fail(TFS_EINVAL, "slot must be 0 or 1");
+  if (p->npoints > 0 && (!X || !Y || !Xk_out)) return fail(TFS_EINVAL, "null pointer");
+  hipError_t e = tfs::launch_modes_to_plain(p, slot, X, Y, Xk_out);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return TFS_OK;
+}
+
+}  // extern "C"

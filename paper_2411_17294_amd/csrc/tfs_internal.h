@@ -1,0 +1,96 @@
+// Internal definitions shared by the host plan code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "tfs.h"
+
+namespace tfs {
+
+// BDF2 coefficients b_0, b_1, b_2 and the SDIRK2 diagonal (Alexander's L-stable
+// two-stage method, first step only).
+constexpr double kB0 = 1.5;
+constexpr double kB1 = -2.0;
+constexpr double kB2 = 0.5;
+
+// Rows of the device coefficient table [kNumCoef][m].
+enum CoefRow : int {
+  kRowD = 0,    // d_k = 1/(b0 + lambda_k dt)
+  kRowDC = 1,   // d_k c_k
+  kRowEta = 2,  // eta_k = lambda_k dt d_k
+  kRowC = 3,    // c_k = w_k dt d_k
+  kRowU = 4,    // start-up: coefficient of the first stage value in Y_k^1
+  kRowV = 5,    // start-up: coefficient of the second stage value in Y_k^1
+  kNumCoef = 6
+};
+
+// Number of diagnostics written per step.
+constexpr int kNumDiag = 6;
+// Threads per block of every streaming kernel.
+constexpr int kBlock = 256;
+
+// Per-step scalars of the BDF2 update, all FP64.
+struct Bdf2Scalars {
+  double a_diag;     // b0 + eta/De: diagonal of the local operator
+  double eta;        // eta = sum_k b0 c_k
+  double s_ec;       // sum_k eta_k c_k
+  double inv_De;     // 1/De
+  double zeta;       // mass-mode memory term zeta^{n+1}
+  double tau_scale;  // gamma/dt
+};
+
+// Scalars of the SDIRK2 start-up step.
+struct StartScalars {
+  double hgt;        // h gs theta: off-identity weight of the stage matrix
+  double inv_De;
+  double src1;       // h gs theta: source weight of stage 1
+  double sigma1;     // weight of A(X^(1)) in stage 2
+  double sigma2;     // weight of S in stage 2
+  double gamma;      // eta_p/De
+  double theta;
+  double hr;         // h (1 - gs) rho
+};
+
+}  // namespace tfs
+
+struct tfs_plan_s {
+  int d = 0, c = 0, m = 0;
+  int64_t npoints = 0, stride = 0, max_steps = 0;
+  double alpha = 0, De = 0, eta_p = 0, dt = 0, gamma = 0;
+  int precision = 0;
+  uint32_t flags = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  std::vector<double> w, lam;
+  std::vector<double> coef;   // host copy of [kNumCoef][m]
+  double eta = 0, s_ec = 0, a_diag = 0, tau_scale = 0;
+  double theta = 0, rho = 0, sigma1 = 0, sigma2 = 0, hg = 0, hr = 0;
+  std::vector<double> zeta;   // [max_steps + 1]
+
+  double* d_coef = nullptr;   // device [kNumCoef][m]
+  double* d_part = nullptr;   // device [part_cap][kNumDiag] block partials
+  int part_cap = 0;
+
+  // tuning (tfs_plan_tune): points per lane (0 = widest aligned), blocks per CU cap
+  int vec_override = 0;
+  int grid_per_cu = 16;
+  int num_cus = 256;
+};
+
+namespace tfs {
+
+// Launchers (tfs_kernels.hip).  They only enqueue work on plan->stream.
+hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, double* X,
+                       void* Y, double* tau, double* diag);
+hipError_t launch_startup(const tfs_plan_s* p, const double* ka, double* X, void* Y, double* tau,
+                          double* diag);
+hipError_t launch_modes_to_plain(const tfs_plan_s* p, int slot, const double* X, const void* Y,
+                                 double* Xk);
+// Upper bound of blocks the launchers use for a plan (sizes d_part).
+int max_blocks(const tfs_plan_s* p);
+
+}  // namespace tfs

@@ -1,0 +1,56 @@
+"""Device-side synthesis of the seeded inputs (plumbing, not the method).
+
+Evaluates the same divergence-free Fourier velocity-gradient field as
+``inputs.FourierField.kappa_at`` on the whole grid with torch FP64 operations,
+chunked over points, and lays out X0 in the X ring.  No part of the update runs
+here.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import inputs as I
+
+
+class DeviceKappa:
+    """kappa(x, t) of a FourierField on a full periodic grid, written into [d*d][stride] tensors."""
+
+    def __init__(self, ff: I.FourierField, grid: int, npoints: int, device="cuda", chunk=1 << 22):
+        self.ff = ff
+        self.grid = grid
+        self.dim = ff.dim
+        self.npoints = npoints
+        self.device = device
+        self.chunk = chunk
+        self.k = torch.tensor(ff.k.T.astype(np.float64), device=device)                    # [d, NF]
+        self.B = torch.tensor(ff.coef().reshape(len(ff.amp), ff.dim * ff.dim), device=device)  # [NF, d*d]
+        self.phase = torch.tensor(ff.phase, device=device)
+        self.omega = torch.tensor(ff.omega, device=device)
+
+    def fill(self, out: torch.Tensor, t: float):
+        """out: [d*d][stride] FP64; writes points [0, npoints)."""
+        d, g = self.dim, self.grid
+        for p0 in range(0, self.npoints, self.chunk):
+            p1 = min(self.npoints, p0 + self.chunk)
+            flat = torch.arange(p0, p1, device=self.device, dtype=torch.int64)
+            idx = torch.empty((p1 - p0, d), device=self.device, dtype=torch.float64)
+            r = flat.clone()
+            for a in range(d):
+                idx[:, a] = (r % g).to(torch.float64)
+                r = r // g
+            x = idx * (2.0 * math.pi / g)
+            theta = x @ self.k + self.phase[None, :] + self.omega[None, :] * t
+            out[:, p0:p1] = (torch.sin(theta) @ self.B).T
+        return out
+
+
+def x0_ring(wl: I.Workload, stride: int, device="cuda", points=None):
+    """X ring [2][c][stride] with X0 of workload wl in slot 0 (all points, or the given subset)."""
+    X0 = I.initial_state(wl, points)
+    P = X0.shape[1]
+    X = torch.zeros((2, wl.c, stride), dtype=torch.float64, device=device)
+    X[0, :, :P] = torch.from_numpy(X0).to(device)
+    return X

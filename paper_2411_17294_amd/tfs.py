@@ -1,0 +1,185 @@
+"""Python binding of libtfs.so: argument marshalling only.
+
+Every step of the update runs in the library's HIP kernels; this module only
+passes device pointers, sizes and the stream.  PyTorch supplies device memory
+and streams.  Importing it without the built library raises immediately: there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtfs.so")
+
+TFS_OK, TFS_EINVAL, TFS_ENOMEM, TFS_EHIP, TFS_ENUMERIC, TFS_EUNSUPPORTED = range(6)
+TFS_FP64, TFS_FP32_MODES = 0, 1
+TFS_FLAG_CHECK_SYNC = 1
+
+EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_step", "tfs_modes_to_plain",
+           "tfs_plan_tables", "tfs_plan_stride", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
+           "tfs_status_string", "tfs_last_error")
+
+
+class TfsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+class PlanDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nmodes", C.c_int32), ("npoints", C.c_int64), ("stride", C.c_int64),
+                ("alpha", C.c_double), ("De", C.c_double), ("eta_p", C.c_double), ("dt", C.c_double),
+                ("max_steps", C.c_int64), ("w", C.POINTER(C.c_double)), ("lam", C.POINTER(C.c_double)),
+                ("precision", C.c_int32), ("flags", C.c_uint32), ("stream", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libtfs.so (built in-tree by paper_2411_17294_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2411_17294_amd.build` "
+                          "(there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, i64, i32 = C.c_void_p, C.POINTER(C.c_double), C.c_int64, C.c_int32
+    L.tfs_plan_create.argtypes = [C.POINTER(PlanDesc), C.POINTER(C.c_void_p)]
+    L.tfs_plan_destroy.argtypes = [vp]
+    L.tfs_plan_set_stream.argtypes = [vp, vp]
+    L.tfs_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+    L.tfs_modes_to_plain.argtypes = [vp, i32, vp, vp, vp]
+    L.tfs_plan_tables.argtypes = [vp, dp, dp, dp]
+    L.tfs_plan_stride.argtypes = [vp]
+    L.tfs_plan_stride.restype = i64
+    L.tfs_plan_tune.argtypes = [vp, C.c_char_p, i64]
+    L.tfs_soe_fit.argtypes = [C.c_double, i32, C.c_double, C.c_double, dp, dp, dp, dp, dp]
+    L.tfs_soe_gl_log.argtypes = [C.c_double, i32, C.c_double, C.c_double, dp, dp, dp, dp]
+    L.tfs_status_string.argtypes = [C.c_int]
+    L.tfs_status_string.restype = C.c_char_p
+    L.tfs_last_error.restype = C.c_char_p
+    for name in ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_step", "tfs_modes_to_plain",
+                 "tfs_plan_tables", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != TFS_OK:
+        L = lib()
+        raise TfsError(status, f"{L.tfs_status_string(status).decode()}: {L.tfs_last_error().decode()}")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _tptr(t) -> Optional[int]:
+    """Device address of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor required")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor required")
+    return t.data_ptr()
+
+
+def soe_fit(alpha: float, m: int, dt: float, T: float):
+    """Product SOE fit (GL-log, Laplace-symbol window); returns (w, lam, dw, dlam, info)."""
+    w, lam, dw, dl, info = np.zeros(m), np.zeros(m), np.zeros(m), np.zeros(m), np.zeros(4)
+    check(lib().tfs_soe_fit(float(alpha), int(m), float(dt), float(T), _dptr(w), _dptr(lam), _dptr(dw),
+                            _dptr(dl), _dptr(info)))
+    return w, lam, dw, dl, {"y_lo": info[0], "y_hi": info[1], "symbol_relerr": info[2], "kernel_relerr": info[3]}
+
+
+def soe_gl_log(alpha: float, m: int, y_lo: float, y_hi: float):
+    w, lam, dw, dl = np.zeros(m), np.zeros(m), np.zeros(m), np.zeros(m)
+    check(lib().tfs_soe_gl_log(float(alpha), int(m), float(y_lo), float(y_hi), _dptr(w), _dptr(lam), _dptr(dw),
+                               _dptr(dl)))
+    return w, lam, dw, dl
+
+
+class Plan:
+    """One tfs_plan: dim, m, npoints, parameters and the (w, lambda) table."""
+
+    def __init__(self, dim, npoints, w, lam, alpha, De, eta_p, dt, max_steps, precision="fp64",
+                 stride=0, flags=0, stream=None):
+        import torch
+        self.dim = int(dim)
+        self.c = self.dim * (self.dim + 1) // 2
+        self.w = np.ascontiguousarray(w, dtype=np.float64)
+        self.lam = np.ascontiguousarray(lam, dtype=np.float64)
+        self.m = int(self.w.size)
+        self.npoints = int(npoints)
+        self.alpha, self.De, self.eta_p, self.dt = float(alpha), float(De), float(eta_p), float(dt)
+        self.max_steps = int(max_steps)
+        self.precision = {"fp64": TFS_FP64, "fp32_modes": TFS_FP32_MODES}[precision] \
+            if isinstance(precision, str) else int(precision)
+        self.mode_dtype = torch.float64 if self.precision == TFS_FP64 else torch.float32
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        d = PlanDesc(self.dim, self.m, self.npoints, int(stride), self.alpha, self.De, self.eta_p, self.dt,
+                     self.max_steps, _dptr(self.w), _dptr(self.lam), self.precision, int(flags),
+                     C.c_void_p(stream))
+        h = C.c_void_p()
+        check(lib().tfs_plan_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.stride = int(lib().tfs_plan_stride(h))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            check(lib().tfs_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        check(lib().tfs_plan_set_stream(self._h, C.c_void_p(stream)))
+
+    def tune(self, key: str, value: int):
+        check(lib().tfs_plan_tune(self._h, key.encode(), int(value)))
+
+    # -- buffers -------------------------------------------------------------------------
+    def alloc(self, device="cuda"):
+        """Zeroed X ring, Y ring, tau and diag tensors with this plan's layout."""
+        import torch
+        st = self.stride
+        X = torch.zeros((2, self.c, st), dtype=torch.float64, device=device)
+        Y = torch.zeros((2, self.m, self.c, st), dtype=self.mode_dtype, device=device)
+        tau = torch.zeros((self.c, st), dtype=torch.float64, device=device)
+        diag = torch.zeros(6, dtype=torch.float64, device=device)
+        return X, Y, tau, diag
+
+    # -- entry points --------------------------------------------------------------------
+    def step(self, n, kappa_a, kappa_b, X, Y, tau=None, diag=None):
+        check(lib().tfs_step(self._h, int(n), _tptr(kappa_a), _tptr(kappa_b), _tptr(X), _tptr(Y), _tptr(tau),
+                             _tptr(diag)))
+
+    def modes_to_plain(self, slot, X, Y, out):
+        check(lib().tfs_modes_to_plain(self._h, int(slot), _tptr(X), _tptr(Y), _tptr(out)))
+
+    def tables(self):
+        t = np.zeros((5, self.m))
+        s = np.zeros(8)
+        z = np.zeros(self.max_steps + 1)
+        check(lib().tfs_plan_tables(self._h, _dptr(t), _dptr(s), _dptr(z)))
+        return {"d": t[0], "c": t[1], "eta_k": t[2], "u": t[3], "v": t[4], "eta": s[0], "s_ec": s[1],
+                "a_diag": s[2], "tau_scale": s[3], "theta": s[4], "rho": s[5], "sigma1": s[6], "sigma2": s[7],
+                "zeta": z}

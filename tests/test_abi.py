@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI: the library loads, exports every function the header
+declares, validates descriptors before touching the GPU, and its sum-of-exponentials
+fit agrees with the oracle's independent fit.  No kernel is launched here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import soe as osoe
+from paper_2411_17294_amd import tfs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "tfs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(tfs_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    names = header_functions()
+    assert len(names) >= 10
+    L = tfs.lib()
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in tfs.h but not exported"
+    assert set(names) == set(tfs.EXPORTS)
+
+
+def _desc(**kw):
+    w = np.array([1.0, 0.5]); lam = np.array([0.0, 3.0])
+    base = dict(dim=2, nmodes=2, npoints=10, stride=0, alpha=0.5, De=1.0, eta_p=0.1, dt=1e-3, max_steps=10,
+                w=w, lam=lam, precision=0, flags=0)
+    base.update(kw)
+    d = tfs.PlanDesc(base["dim"], base["nmodes"], base["npoints"], base["stride"], base["alpha"], base["De"],
+                     base["eta_p"], base["dt"], base["max_steps"],
+                     np.ascontiguousarray(base["w"], dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double)),
+                     np.ascontiguousarray(base["lam"], dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double)),
+                     base["precision"], base["flags"], None)
+    d._keep = (base["w"], base["lam"])
+    return d
+
+
+@pytest.mark.parametrize("bad", [dict(dim=1), dict(dim=4), dict(nmodes=0), dict(npoints=-1),
+                                 dict(stride=5), dict(alpha=0.0), dict(alpha=1.5), dict(De=0.0),
+                                 dict(eta_p=-1.0), dict(dt=0.0), dict(max_steps=0), dict(precision=7),
+                                 dict(w=np.array([1.0, -0.5])), dict(lam=np.array([0.0, np.nan]))])
+def test_plan_create_rejects_invalid_descriptor(bad):
+    L = tfs.lib()
+    d = _desc(**bad)
+    h = C.c_void_p(123)
+    st = L.tfs_plan_create(C.byref(d), C.byref(h))
+    assert st == tfs.TFS_EINVAL
+    assert h.value is None
+    assert L.tfs_last_error().decode() != ""
+
+
+def test_null_arguments_are_rejected():
+    L = tfs.lib()
+    h = C.c_void_p()
+    assert L.tfs_plan_create(None, C.byref(h)) == tfs.TFS_EINVAL
+    assert L.tfs_step(None, 0, None, None, None, None, None, None) == tfs.TFS_EINVAL
+    assert L.tfs_plan_destroy(None) == tfs.TFS_OK
+    assert L.tfs_status_string(tfs.TFS_ENUMERIC).decode().startswith("non-finite")
+
+
+@pytest.mark.parametrize("alpha,m,ylo,yhi", [(0.5, 20, -9.0, 14.0), (0.2, 48, -12.0, 30.0), (0.7, 3, -3.0, 8.0),
+                                             (0.4, 1, -2.0, 5.0), (0.6, 2, -2.0, 5.0)])
+def test_product_soe_rule_matches_oracle_rule(alpha, m, ylo, yhi):
+    w, lam, dw, dl = tfs.soe_gl_log(alpha, m, ylo, yhi)
+    wo, lo, dwo, dlo = osoe.soe_gl_log(alpha, m, ylo, yhi)
+    # two independent Gauss-Legendre implementations; e^{(1-alpha) y} at |y| ~ 30 amplifies node rounding
+    assert np.max(np.abs(w - wo) / wo) < 5e-12
+    assert np.max(np.abs(lam - lo) / np.maximum(lo, 1e-300)) < 5e-12
+    assert np.max(np.abs(dw - dwo) / np.maximum(np.abs(dwo), 1e-300)) < 1e-11
+    assert np.max(np.abs(dl - dlo) / np.maximum(np.abs(dlo), 1e-300)) < 1e-12
+
+
+@pytest.mark.parametrize("alpha,m,dt,T", [(0.5, 20, 1e-3, 0.2), (0.3, 32, 5e-4, 0.5), (0.4, 40, 2e-4, 0.1),
+                                          (0.2, 48, 1e-4, 0.2), (1.0, 4, 1e-3, 0.1)])
+def test_product_soe_fit_accuracy(alpha, m, dt, T):
+    w, lam, dw, dl, info = tfs.soe_fit(alpha, m, dt, T)
+    assert np.all(w >= 0) and np.all(lam >= 0)
+    if alpha == 1.0:
+        assert w[0] == 1.0 and np.all(w[1:] == 0) and np.all(lam == 0)
+        return
+    assert np.all(w > 0)
+    _, _, oinfo = osoe.soe_fit(alpha, m, dt, T)
+    assert info["symbol_relerr"] <= 1.5 * oinfo["symbol_relerr"] + 1e-12
+    assert abs(osoe.symbol_relerr(alpha, w, lam, dt, T) - info["symbol_relerr"]) < 1e-9
+
+
+def test_soe_fit_rejects_bad_arguments():
+    with pytest.raises(tfs.TfsError) as e:
+        tfs.soe_fit(0.0, 4, 1e-3, 1.0)
+    assert e.value.status == tfs.TFS_EINVAL
+    with pytest.raises(tfs.TfsError):
+        tfs.soe_fit(0.5, 4, 1e-3, 1e-4)

@@ -1,0 +1,270 @@
+"""GPU parity of the HIP path with the CPU oracle, through the C ABI.
+
+Bar: FP64 form within 1e-12 and FP32-mode form within 1e-5, normwise per output field
+(max |gpu - oracle| / max |oracle|) for X at the last two levels, tau, the plain
+fractional modes and the diagnostics (the non-finite count exactly)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from oracle import soe as osoe
+from paper_2411_17294_amd import inputs as I
+from paper_2411_17294_amd import tfs
+from tests.gpu_helpers import relerr, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32_modes": 1e-5}
+
+
+def compare(g, o, prec, modes=True, diag=True, label="", spread=None):
+    """spread: the oracle's own response (relerr per field) to a random one-ulp relative
+    perturbation of kappa; where given, a field's bar is max(tolerance, 2 * spread), because
+    no FP64 evaluation can agree beyond the conditioning of the quantity."""
+    tol = TOL[prec]
+    errs = {"X^N": relerr(g["X"][0], o["X"][0]), "X^N-1": relerr(g["X"][1], o["X"][1]),
+            "tau": relerr(g["tau"], o["tau"])}
+    if modes and "modes" in g:
+        errs["modes"] = relerr(g["modes"], o["modes"])
+    if diag and "diag" in g:
+        gd, od = g["diag"], o["diag"][-1]
+        for i in range(5):
+            errs[f"diag{i}"] = abs(gd[i] - od[i]) / max(abs(od[i]), 1e-300)
+        assert gd[5] == od[5], (label, gd, od)
+    bars = {k: tol for k in errs}
+    if spread:
+        for k, v in spread.items():
+            bars[k] = max(tol, 2.0 * v)
+    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, "bars", {k: f"{v:.1e}" for k, v in bars.items()},
+          flush=True)
+    bad = {k: v for k, v in errs.items() if not (v <= bars[k])}
+    assert not bad, f"{label}: {bad} exceed {bars}"
+
+
+def oracle_spread(o, run_perturbed):
+    """relerr of the oracle's outputs under a random +-1 ulp relative perturbation of kappa."""
+    p = run_perturbed()
+    return {"X^N": relerr(p["X"][0], o["X"][0]), "X^N-1": relerr(p["X"][1], o["X"][1]),
+            "tau": relerr(p["tau"], o["tau"])}
+
+
+def ulp_perturbed(a, seed=0):
+    rng = np.random.default_rng(seed)
+    return a * (1.0 + rng.choice([-1.0, 1.0], a.shape) * 2.0 ** -52)
+
+
+def small_case(d, P, seed, m=7, alpha=0.45, dt=1e-3, T=0.05):
+    kappa, X0 = I.random_symmetric_case(d, P, seed, kscale=0.8, xscale=1e-2)
+    w, lam, _ = osoe.soe_fit(alpha, m, dt, T)
+    return kappa, X0, w, lam
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("P,nsteps", [(1, 1), (3, 2), (64, 13), (1037, 13), (4099, 40)])
+def test_small_random_cases(d, prec, P, nsteps):
+    kappa, X0, w, lam = small_case(d, P, 100 + P + d)
+    print(f"case d={d} prec={prec} P={P} N={nsteps}", flush=True)
+    g = run_gpu(d, w, lam, 1.0, 0.1, 1e-3, nsteps, kappa, X0, precision=prec, want_modes=True, want_diag=True)
+    o = O.run(d, w, lam, 1.0, 0.1, 1e-3, nsteps, kappa, X0, want_modes=True, want_diag=True)
+    compare(g, o, prec, label=f"d={d} {prec} P={P} N={nsteps}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("layout", ["padded_stride", "unaligned", "vec1", "vec2", "vec4"])
+def test_layouts_and_vector_widths(prec, layout):
+    d, P, N = 3, 1021, 9
+    if layout == "vec4" and prec == "fp64":
+        pytest.skip("4 points per lane exists for FP32 modes only")
+    kappa, X0, w, lam = small_case(d, P, 7)
+    kw = {}
+    if layout == "padded_stride":
+        kw = dict(stride=1100)
+    elif layout == "unaligned":
+        kw = dict(offset=1)
+    else:
+        kw = dict(vec=int(layout[-1]), stride=1024)
+    print(f"layout {layout} {prec}", flush=True)
+    g = run_gpu(d, w, lam, 0.8, 0.2, 1e-3, N, kappa, X0, precision=prec, want_modes=True, want_diag=True, **kw)
+    o = O.run(d, w, lam, 0.8, 0.2, 1e-3, N, kappa, X0, want_modes=True, want_diag=True)
+    compare(g, o, prec, label=f"{layout} {prec}")
+
+
+def _tv_kappa(d, P, nlev, dt, seed):
+    rng = np.random.default_rng(seed)
+    a, b, om = (rng.standard_normal((d * d, P)) * 0.6 for _ in range(3))
+    t = np.arange(nlev)[:, None, None] * dt
+    return np.ascontiguousarray(a[None] + b[None] * np.sin(3.0 * t + om[None]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("extrap", [True, False])
+def test_time_varying_kappa(d, prec, extrap):
+    P, N, dt = 777, 30, 2e-3
+    kap = _tv_kappa(d, P, N + 1, dt, 5 + d)
+    _, X0 = I.random_symmetric_case(d, P, 9, xscale=1e-2)
+    w, lam, _ = osoe.soe_fit(0.35, 9, dt, N * dt)
+    print(f"time-varying d={d} {prec} extrap={extrap}", flush=True)
+    g = run_gpu(d, w, lam, 1.3, 0.1, dt, N, kap, X0, precision=prec, extrap=extrap, want_modes=True, want_diag=True)
+    o = O.run(d, w, lam, 1.3, 0.1, dt, N, kap, X0, extrap=extrap, want_modes=True, want_diag=True)
+    compare(g, o, prec, label=f"tv d={d} {prec} extrap={extrap}")
+
+
+def test_alpha_one_and_single_mode():
+    """alpha = 1 (w = 1, lambda = 0, one mode): the Oldroyd-B limit on the GPU."""
+    d, P, N = 3, 300, 25
+    kappa, X0 = I.random_symmetric_case(d, P, 11, kscale=0.7, xscale=1e-2)
+    g = run_gpu(d, [1.0], [0.0], 0.9, 0.1, 2e-3, N, kappa, X0, alpha=1.0, want_modes=True, want_diag=True)
+    o = O.run(d, [1.0], [0.0], 0.9, 0.1, 2e-3, N, kappa, X0, want_modes=True, want_diag=True)
+    compare(g, o, "fp64", label="alpha=1")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+def test_workload_64sq_full_grid(prec):
+    """64x64, alpha = 0.5, m = 20, 200 steps, dt = 1e-3, De = 1, eta_p = 0.1: every point."""
+    wl = I.WORKLOADS[1]
+    ff = I.fourier_field(wl)
+    pts = np.arange(wl.npoints)
+    kap = ff.kappa_at(I.grid_multi_index(wl.grid, 2, pts), wl.grid, 0.0)
+    X0 = I.initial_state(wl)
+    w, lam, info = osoe.soe_fit(wl.alphas[0], wl.nmodes, wl.dt, wl.dt * wl.nsteps)
+    print("workload 64^2", prec, info, flush=True)
+    g = run_gpu(2, w, lam, wl.De, wl.eta_p, wl.dt, wl.nsteps, kap, X0, precision=prec, want_modes=True,
+                want_diag=True, alpha=wl.alphas[0])
+    o = O.run(2, w, lam, wl.De, wl.eta_p, wl.dt, wl.nsteps, kap, X0, want_modes=True, want_diag=True)
+    compare(g, o, prec, label=f"64^2 {prec}")
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.7])
+def test_workload_1024sq_subdomain(alpha):
+    """1024x1024, m = 32, 1000 steps, dt = 5e-4, time-varying kappa with extrapolation: the full
+    grid runs on the GPU in the benchmark's launch configuration; the strided 32x32 subset is
+    compared with the oracle (points are independent, so the subset is exact)."""
+    from paper_2411_17294_amd.device_inputs import DeviceKappa, x0_ring
+    wl = I.WORKLOADS[2]
+    N = wl.nsteps
+    ff = I.fourier_field(wl)
+    w, lam, info = osoe.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * N)
+    plan = tfs.Plan(2, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, N)
+    X = x0_ring(wl, plan.stride)
+    _, Y, tau, _ = plan.alloc()
+    dk = DeviceKappa(ff, wl.grid, wl.npoints)
+    ring = [torch.zeros((4, plan.stride), dtype=torch.float64, device="cuda") for _ in range(2)]
+    dk.fill(ring[0], 0.0)
+    print(f"workload 1024^2 alpha={alpha}", info, flush=True)
+    for n in range(N):
+        if n >= 1:
+            dk.fill(ring[n % 2], n * wl.dt)
+        plan.step(n, ring[n % 2], ring[(n - 1) % 2] if n >= 1 else None, X, Y, tau)
+    torch.cuda.synchronize()
+    sub = I.subdomain_points(wl)
+    idx = I.grid_multi_index(wl.grid, 2, sub)
+    kap = np.stack([ff.kappa_at(idx, wl.grid, n * wl.dt) for n in range(N + 1)])
+    X0 = I.initial_state(wl, sub)
+    o = O.run(2, w, lam, wl.De, wl.eta_p, wl.dt, N, kap, X0)
+    spread = oracle_spread(o, lambda: O.run(2, w, lam, wl.De, wl.eta_p, wl.dt, N, ulp_perturbed(kap), X0))
+    subt = torch.from_numpy(sub).cuda()
+    g = {"X": np.stack([X[N % 2][:, subt].cpu().numpy(), X[(N - 1) % 2][:, subt].cpu().numpy()]),
+         "tau": tau[:, subt].cpu().numpy()}
+    compare(g, o, "fp64", modes=False, diag=False, label=f"1024^2 alpha={alpha}", spread=spread)
+
+
+def test_device_kappa_matches_host_generator():
+    from paper_2411_17294_amd.device_inputs import DeviceKappa
+    for cid in (1, 2, 3):
+        wl = I.WORKLOADS[cid]
+        ff = I.fourier_field(wl)
+        n = min(wl.npoints, 1 << 20)
+        dk = DeviceKappa(ff, wl.grid, n)
+        out = torch.zeros((wl.dim ** 2, n), dtype=torch.float64, device="cuda")
+        dk.fill(out, 0.37)
+        pts = np.random.default_rng(cid).integers(0, n, 500)
+        ref = ff.kappa_at(I.grid_multi_index(wl.grid, wl.dim, pts), wl.grid, 0.37)
+        assert relerr(out[:, torch.from_numpy(pts).cuda()].cpu().numpy(), ref) < 1e-13
+
+
+def test_rerun_is_bitwise_identical():
+    d, P, N = 3, 5000, 12
+    kappa, X0, w, lam = small_case(d, P, 21)
+    a = run_gpu(d, w, lam, 1.0, 0.1, 1e-3, N, kappa, X0, want_modes=True, want_diag=True)
+    b = run_gpu(d, w, lam, 1.0, 0.1, 1e-3, N, kappa, X0, want_modes=True, want_diag=True)
+    for k in ("X", "tau", "modes", "diag"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_restart_from_saved_levels_is_bitwise_identical():
+    """Stopping after level n and continuing from the saved rings gives the same result."""
+    d, P = 2, 2000
+    kappa, X0, w, lam = small_case(d, P, 31)
+    plan = tfs.Plan(d, P, w, lam, 0.45, 1.0, 0.1, 1e-3, 30)
+    X, Y, tau, _ = plan.alloc()
+    X[0] = torch.from_numpy(X0).cuda()
+    kd = torch.from_numpy(kappa).cuda()
+    for n in range(20):
+        plan.step(n, kd, kd, X, Y, tau)
+    Xs, Ys = X.clone(), Y.clone()
+    for n in range(20, 30):
+        plan.step(n, kd, kd, X, Y, tau)
+    ref = (X.clone(), tau.clone())
+    X.copy_(Xs); Y.copy_(Ys)
+    for n in range(20, 30):
+        plan.step(n, kd, kd, X, Y, tau)
+    torch.cuda.synchronize()
+    assert torch.equal(X, ref[0]) and torch.equal(tau, ref[1])
+
+
+def test_check_sync_flags_non_finite_state():
+    d, P = 2, 256
+    kappa, X0, w, lam = small_case(d, P, 41)
+    plan = tfs.Plan(d, P, w, lam, 0.45, 1.0, 0.1, 1e-3, 10, flags=tfs.TFS_FLAG_CHECK_SYNC)
+    X, Y, tau, diag = plan.alloc()
+    X[0] = torch.from_numpy(X0).cuda()
+    kd = torch.from_numpy(kappa).cuda()
+    plan.step(0, kd, None, X, Y, tau, diag)
+    plan.step(1, kd, kd, X, Y, tau, diag)
+    X[1, 0, 17] = float("nan")            # corrupt level 1 at one point, from the host
+    with pytest.raises(tfs.TfsError) as e:
+        plan.step(2, kd, kd, X, Y, tau, diag)
+    assert e.value.status == tfs.TFS_ENUMERIC
+    assert diag[5].item() >= 1
+
+
+def test_non_positive_definite_state_is_reported():
+    d, P = 2, 64
+    kappa, X0, w, lam = small_case(d, P, 43)
+    X0[0, 5] = -1.5                        # C_xx = 1 + X_xx < 0 at one point
+    g = run_gpu(d, w, lam, 1.0, 0.1, 1e-3, 1, kappa, X0, want_diag=True)
+    assert g["diag"][0] < 0
+    with pytest.raises(tfs.TfsError) as e:
+        run_gpu(d, w, lam, 1.0, 0.1, 1e-3, 1, kappa, X0, want_diag=True, flags=tfs.TFS_FLAG_CHECK_SYNC)
+    assert e.value.status == tfs.TFS_ENUMERIC
+
+
+def test_step_argument_errors():
+    d, P = 2, 16
+    kappa, X0, w, lam = small_case(d, P, 51)
+    plan = tfs.Plan(d, P, w, lam, 0.45, 1.0, 0.1, 1e-3, 4)
+    X, Y, tau, _ = plan.alloc()
+    kd = torch.from_numpy(kappa).cuda()
+    for n in (-1, 4, 100):
+        with pytest.raises(tfs.TfsError) as e:
+            plan.step(n, kd, None, X, Y, tau)
+        assert e.value.status == tfs.TFS_EINVAL
+    with pytest.raises(tfs.TfsError):
+        plan.step(0, None, None, X, Y, tau)
+
+
+def test_empty_plan():
+    w, lam, _ = osoe.soe_fit(0.5, 4, 1e-3, 0.1)
+    plan = tfs.Plan(3, 0, w, lam, 0.5, 1.0, 0.1, 1e-3, 3)
+    diag = torch.full((6,), -7.0, dtype=torch.float64, device="cuda")
+    dummy = torch.zeros(8, dtype=torch.float64, device="cuda")
+    for n in range(3):
+        plan.step(n, dummy, dummy, dummy, dummy, None, diag)
+    torch.cuda.synchronize()
+    d = diag.cpu().numpy()
+    assert math.isinf(d[0]) and d[3] == 0 and d[4] == 0 and d[5] == 0
