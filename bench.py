@@ -64,6 +64,7 @@ def main():
     ap.add_argument("--workload", type=int, default=2, help="workload id (2 = default 2-D FP64)")
     ap.add_argument("--form", choices=["default", "fp64", "fp32_modes"], default="default")
     ap.add_argument("--vec", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=-1, help="mode-ring tile (points); -1 = library default")
     ap.add_argument("--grid-per-cu", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -99,7 +100,8 @@ def main():
     for alpha in wl.alphas:
         w, lam, _, _, info = tfs.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * N)
         log(f"alpha={alpha}: SOE symbol rel err {info['symbol_relerr']:.2e}")
-        p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, N, precision=form)
+        p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, N, precision=form,
+                     tile=None if args.tile < 0 else args.tile)
         if args.vec:
             p.tune("vec", args.vec)
         p.tune("grid_per_cu", args.grid_per_cu)
@@ -145,6 +147,19 @@ def main():
         if not bool(torch.isfinite(tau[:, :wl.npoints]).all()):
             raise SystemExit("non-finite stress in the benchmark run")
 
+    # reference: a plain device-to-device copy of 2 GiB (read + write) on the same stream
+    csrc = torch.empty(1 << 28, dtype=torch.float64, device=dev)
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        cdst.copy_(csrc)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * csrc.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del csrc, cdst
+
     nfields = len(wl.alphas)
     updates = nfields * wl.npoints * wl.nmodes * args.steps
     value = updates / (ms * 1e-3)
@@ -171,11 +186,11 @@ def main():
         "config": {"workload": wl.name, "grid": f"{wl.grid}^{wl.dim}", "alphas": list(wl.alphas),
                    "modes": wl.nmodes, "dt": wl.dt, "time_levels": N, "form": form,
                    "kappa": "time-varying, extrapolated" if wl.time_varying else "steady",
-                   "fields_per_step": nfields},
+                   "fields_per_step": nfields, "mode_tile": plans[0][3].tile},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "bdf2_kernel", "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": avg_launch_s * 1e6},
+                     "avg_launch_us": avg_launch_s * 1e6, "measured_copy_GBs": copy_gbs},
         "wall_s": wall,
     }
     if not args.no_cpu_baseline:

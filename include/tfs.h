@@ -23,7 +23,12 @@
  * Packed symmetric components (c = d(d+1)/2):  2-D (xx, yy, xy);  3-D (xx, yy, zz, xy, xz, yz).
  * Velocity gradient components (d*d):          row-major kappa_ij = d u_i / d x_j.
  * Every field is structure-of-arrays with the point index fastest and a plane
- * stride of `stride` elements (>= npoints) between consecutive planes.
+ * stride of `stride` elements (>= npoints) between consecutive planes.  The
+ * fractional-mode ring may instead be tiled: with tile T > 0 the points are cut into
+ * tiles of T consecutive points and mode (slot, k, s) of point p lives at element
+ *     ((slot * (stride/T) + p/T) * m * c + k * c + s) * T + p % T,
+ * so all modes of a tile are contiguous (T = 0 is the plain [2][m][c][stride] layout).
+ * Tiling keeps the number of concurrently streamed DRAM regions small.
  */
 #ifndef TFS_H
 #define TFS_H
@@ -58,7 +63,9 @@ typedef struct {
     int32_t dim;          /* 2 or 3 */
     int32_t nmodes;       /* m >= 1 exponential modes */
     int64_t npoints;      /* points updated by each call (>= 0) */
-    int64_t stride;       /* plane stride in elements; 0 means npoints; must be >= npoints */
+    int64_t stride;       /* plane stride in elements; 0 means npoints rounded up to a multiple of tile;
+                             must be >= npoints and, with tile > 0, a multiple of tile */
+    int64_t tile;         /* mode-ring tile in points: 0 (untiled) or a positive multiple of 4 */
     double alpha;         /* fractional order in (0, 1]; kept for reporting and gradients */
     double De;            /* relaxation time (Deborah/Weissenberg number) > 0 */
     double eta_p;         /* polymer viscosity (1-beta)/Re >= 0; gamma = eta_p/De (Sec. 1, Kramers) */
@@ -81,7 +88,8 @@ typedef struct {
  * tables are uploaded once.  The plan owns them and a small reduction buffer.
  * Errors: TFS_EINVAL (dim not 2/3, m < 1, npoints < 0, stride < npoints, alpha not in
  * (0,1], De <= 0, eta_p < 0, dt <= 0, max_steps < 1, null or negative/non-finite w or
- * lambda, unknown precision), TFS_ENOMEM, TFS_EHIP.  *out is NULL on error.
+ * lambda, unknown precision, tile negative or not a multiple of 4, stride not a multiple
+ * of a positive tile), TFS_ENOMEM, TFS_EHIP.  *out is NULL on error.
  */
 tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out);
 
@@ -104,10 +112,10 @@ tfs_status tfs_plan_set_stream(tfs_plan plan, void* stream);
  *                   eq. FP_discrete).  At n = 0 kappa_b is ignored.
  * X                 device [2][c][stride] FP64 ring: slot j%2 holds level j.  The caller
  *                   stores X^0 in slot 0 before n = 0.  Level n+1 overwrites slot (n+1)%2.
- * Y                 device [2][m][c][stride] ring of the fractional modes in the
- *                   representation Y_k = X_k - c_k X (FP64, or FP32 for TFS_FP32_MODES):
- *                   slot j%2 holds level j.  Written entirely at n = 0 (levels 0 and 1);
- *                   its input contents are ignored then.
+ * Y                 device ring of the fractional modes, 2 * m * c * stride elements in the
+ *                   plan's (possibly tiled) layout, in the representation Y_k = X_k - c_k X
+ *                   (FP64, or FP32 for TFS_FP32_MODES): slot j%2 holds level j.  Written
+ *                   entirely at n = 0 (levels 0 and 1); its input contents are ignored then.
  * tau               device [c][stride] FP64 or NULL: tau^{n+1} = gamma D^{1-alpha} X^{n+1}.
  * diag              device [6] FP64 or NULL: over the points at level n+1, the minimum of the
  *                   three leading principal minors of C = I + X (Sylvester's criterion as used
@@ -123,7 +131,7 @@ tfs_status tfs_step(tfs_plan plan, int64_t n, const double* kappa_a, const doubl
 /*
  * Convert the mode ring slot `slot` (0 or 1) to plain fractional modes
  * X_k = Y_k + c_k X, with X taken from the same slot of the X ring.
- * Xk_out: device [m][c][stride] FP64.  Asynchronous on the plan's stream.
+ * Xk_out: device [m][c][stride] FP64, untiled.  Asynchronous on the plan's stream.
  */
 tfs_status tfs_modes_to_plain(tfs_plan plan, int32_t slot, const double* X, const void* Y, double* Xk_out);
 
@@ -139,12 +147,15 @@ tfs_status tfs_plan_tables(tfs_plan plan, double* tables, double* scalars, doubl
 /* Effective plane stride (elements) of the plan. */
 int64_t tfs_plan_stride(tfs_plan plan);
 
+/* Mode-ring tile of the plan (points; 0 = untiled). */
+int64_t tfs_plan_tile(tfs_plan plan);
+
 /*
  * Launch tuning; does not change results beyond rounding-order-free choices:
  *   "vec"          points per lane: 0 = widest width the alignment of the fields allows
  *                  (default), or 1, 2 (and 4 for TFS_FP32_MODES); a width the alignment
  *                  does not allow falls back to 1 at launch.
- *   "grid_per_cu"  cap on blocks per compute unit of the grid-stride launches, 1..16.
+ *   "grid_per_cu"  cap on blocks per compute unit of the grid-stride launches, 1..64.
  * Note: the diagnostic sum's rounding order depends on the grid; results of X, tau, Y do not.
  */
 tfs_status tfs_plan_tune(tfs_plan plan, const char* key, int64_t value);

@@ -221,8 +221,11 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   if (D.dim != 2 && D.dim != 3) return fail(TFS_EINVAL, "dim must be 2 or 3 (got %d)", D.dim);
   if (D.nmodes < 1) return fail(TFS_EINVAL, "nmodes must be >= 1");
   if (D.npoints < 0) return fail(TFS_EINVAL, "npoints must be >= 0");
-  const int64_t stride = D.stride == 0 ? D.npoints : D.stride;
+  if (D.tile < 0 || D.tile % 4 != 0) return fail(TFS_EINVAL, "tile must be 0 or a positive multiple of 4");
+  int64_t stride = D.stride;
+  if (stride == 0) stride = D.tile > 0 ? (D.npoints + D.tile - 1) / D.tile * D.tile : D.npoints;
   if (stride < D.npoints) return fail(TFS_EINVAL, "stride must be >= npoints");
+  if (D.tile > 0 && stride % D.tile != 0) return fail(TFS_EINVAL, "stride must be a multiple of tile");
   if (!(D.alpha > 0.0 && D.alpha <= 1.0)) return fail(TFS_EINVAL, "alpha must be in (0, 1]");
   if (!(D.De > 0.0) || !std::isfinite(D.De)) return fail(TFS_EINVAL, "De must be > 0");
   if (!(D.eta_p >= 0.0) || !std::isfinite(D.eta_p)) return fail(TFS_EINVAL, "eta_p must be >= 0");
@@ -241,6 +244,7 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   p->m = D.nmodes;
   p->npoints = D.npoints;
   p->stride = stride;
+  p->tile = D.tile > 0 ? D.tile : stride;
   p->max_steps = D.max_steps;
   p->alpha = D.alpha;
   p->De = D.De;
@@ -346,6 +350,8 @@ tfs_status tfs_plan_set_stream(tfs_plan p, void* stream) {
 
 int64_t tfs_plan_stride(tfs_plan p) { return p ? p->stride : -1; }
 
+int64_t tfs_plan_tile(tfs_plan p) { return p ? (p->tile == p->stride ? 0 : p->tile) : -1; }
+
 tfs_status tfs_plan_tune(tfs_plan p, const char* key, int64_t value) {
   if (!p || !key) return fail(TFS_EINVAL, "null plan or key");
   if (std::strcmp(key, "vec") == 0) {
@@ -355,8 +361,7 @@ tfs_status tfs_plan_tune(tfs_plan p, const char* key, int64_t value) {
     return TFS_OK;
   }
   if (std::strcmp(key, "grid_per_cu") == 0) {
-    if (value < 1 || value > 1024) return fail(TFS_EINVAL, "grid_per_cu must be in [1, 1024]");
-    if (value > 16) return fail(TFS_EINVAL, "grid_per_cu above 16 exceeds the diagnostic scratch");
+    if (value < 1 || value > tfs::kMaxBlocksPerCU) return fail(TFS_EINVAL, "grid_per_cu must be in [1, 64]");
     p->grid_per_cu = (int)value;
     return TFS_OK;
   }

@@ -31,6 +31,9 @@ enum CoefRow : int {
 constexpr int kNumDiag = 6;
 // Threads per block of every streaming kernel.
 constexpr int kBlock = 256;
+// Upper bound of blocks per compute unit of the grid-stride launches (sizes the
+// diagnostic scratch).
+constexpr int kMaxBlocksPerCU = 64;
 
 // Per-step scalars of the BDF2 update, all FP64.
 struct Bdf2Scalars {
@@ -59,6 +62,7 @@ struct StartScalars {
 struct tfs_plan_s {
   int d = 0, c = 0, m = 0;
   int64_t npoints = 0, stride = 0, max_steps = 0;
+  int64_t tile = 0;           // mode-ring tile (points); equals stride when untiled
   double alpha = 0, De = 0, eta_p = 0, dt = 0, gamma = 0;
   int precision = 0;
   uint32_t flags = 0;

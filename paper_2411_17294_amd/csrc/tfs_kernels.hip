@@ -145,14 +145,16 @@ __device__ __forceinline__ double mul_rn(double a, double b) {
 template <typename T, int V> struct VecOf { using type = T __attribute__((ext_vector_type(V))); };
 template <typename T> struct VecOf<T, 1> { using type = T; };
 
-template <bool FULL, typename T, int V>
+// NT: streaming (non-temporal) access for data touched once per step.
+template <bool FULL, typename T, int V, bool NT = false>
 __device__ __forceinline__ void load_v(const T* __restrict__ p, int nv, T (&o)[V]) {
   if constexpr (FULL) {
     if constexpr (V == 1) {
-      o[0] = *p;
+      o[0] = NT ? __builtin_nontemporal_load(p) : *p;
     } else {
       using vt = typename VecOf<T, V>::type;
-      const vt v = *reinterpret_cast<const vt*>(p);
+      const vt* q = reinterpret_cast<const vt*>(p);
+      const vt v = NT ? __builtin_nontemporal_load(q) : *q;
 #pragma unroll
       for (int i = 0; i < V; ++i) o[i] = v[i];
     }
@@ -164,17 +166,18 @@ __device__ __forceinline__ void load_v(const T* __restrict__ p, int nv, T (&o)[V
   }
 }
 
-template <bool FULL, typename T, int V>
+template <bool FULL, typename T, int V, bool NT = false>
 __device__ __forceinline__ void store_v(T* p, int nv, const T (&x)[V]) {
   if constexpr (FULL) {
     if constexpr (V == 1) {
-      *p = x[0];
+      if constexpr (NT) __builtin_nontemporal_store(x[0], p); else *p = x[0];
     } else {
       using vt = typename VecOf<T, V>::type;
       vt v;
 #pragma unroll
       for (int i = 0; i < V; ++i) v[i] = x[i];
-      *reinterpret_cast<vt*>(p) = v;
+      if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<vt*>(p));
+      else *reinterpret_cast<vt*>(p) = v;
     }
   } else {
 #pragma unroll
@@ -289,12 +292,12 @@ struct Bdf2Args {
   const double* kb;     // kappa_b or null
   const double* Xn;     // X^n      [c][stride]
   double* Xm;           // X^{n-1} in, X^{n+1} out (same slot)
-  const MT* Yn;         // Y^n      [m][c][stride]
+  const MT* Yn;         // Y^n slot (m * c * stride elements, tiled)
   MT* Ym;               // Y^{n-1} in, Y^{n+1} out (same slot)
   double* tau;          // [c][stride] or null
   const double* coef;   // [kNumCoef][m]
   double* part;         // block partials or null
-  int64_t npts, stride;
+  int64_t npts, stride, tile;
   int m;
   Bdf2Scalars s;
 };
@@ -323,12 +326,16 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, int64_t p0, in
 #pragma unroll
     for (int v = 0; v < V; ++v) { Gs[s][v] = 0.0; Ge[s][v] = 0.0; }
 
-  const int64_t mstride = (int64_t)C * st;
+  // mode (k, s) of the group: tile base + (k C + s) T
+  const int64_t T = a.tile;
+  const int64_t toff = (p0 / T) * (int64_t)m * C * T + (p0 % T);
+  const MT* yn0 = a.Yn + toff;
+  MT* ym0 = a.Ym + toff;
   MT cn[C][V], cm[C][V];
 #pragma unroll
   for (int s = 0; s < C; ++s) {
-    load_v<FULL, MT, V>(a.Yn + s * st + p0, nv, cn[s]);
-    load_v<FULL, MT, V>(a.Ym + s * st + p0, nv, cm[s]);
+    load_v<FULL, MT, V, true>(yn0 + s * T, nv, cn[s]);
+    load_v<FULL, MT, V, true>(ym0 + s * T, nv, cm[s]);
   }
   for (int k = 0; k < m; ++k) {
     const double dk = a.coef[kRowD * m + k];
@@ -336,15 +343,15 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, int64_t p0, in
     const double ek = a.coef[kRowEta * m + k];
     MT nn[C][V], nm[C][V];
     if (k + 1 < m) {
-      const MT* yn1 = a.Yn + (int64_t)(k + 1) * mstride + p0;
-      const MT* ym1 = a.Ym + (int64_t)(k + 1) * mstride + p0;
+      const MT* yn1 = yn0 + (int64_t)(k + 1) * C * T;
+      const MT* ym1 = ym0 + (int64_t)(k + 1) * C * T;
 #pragma unroll
       for (int s = 0; s < C; ++s) {
-        load_v<FULL, MT, V>(yn1 + s * st, nv, nn[s]);
-        load_v<FULL, MT, V>(ym1 + s * st, nv, nm[s]);
+        load_v<FULL, MT, V, true>(yn1 + s * T, nv, nn[s]);
+        load_v<FULL, MT, V, true>(ym1 + s * T, nv, nm[s]);
       }
     }
-    MT* yo = a.Ym + (int64_t)k * mstride + p0;
+    MT* yo = ym0 + (int64_t)k * C * T;
 #pragma unroll
     for (int s = 0; s < C; ++s) {
       MT out[V];
@@ -354,7 +361,7 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, int64_t p0, in
         out[v] = (MT)(dk * h + dck * P[s][v]);
         two_sum_acc(Gs[s][v], Ge[s][v], mul_rn(ek, h));
       }
-      store_v<FULL, MT, V>(yo + s * st, nv, out);
+      store_v<FULL, MT, V, true>(yo + s * T, nv, out);
     }
     if (k + 1 < m) {
 #pragma unroll
@@ -442,11 +449,11 @@ template <typename MT>
 struct StartArgs {
   const double* ka;  // kappa^0
   double* X;         // ring [2][c][stride]: reads slot 0, writes slot 1
-  MT* Y;             // ring [2][m][c][stride]: writes both slots
+  MT* Y;             // ring, 2 slots of m * c * stride elements (tiled): writes both slots
   double* tau;
   const double* coef;
   double* part;
-  int64_t npts, stride;
+  int64_t npts, stride, tile;
   int m;
   StartScalars s;
 };
@@ -508,9 +515,10 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, int64_t p0, 
     if (a.tau) store_v<FULL, double, V>(a.tau + s * st + p0, nv, Tout[s]);
   }
   // modes: Y_k^0 = -c_k X^0 (slot 0), Y_k^1 = u_k X^(1) + v_k X^(2) (slot 1)
-  const int64_t mstride = (int64_t)C * st;
-  MT* Y0 = a.Y;
-  MT* Y1 = a.Y + (int64_t)m * mstride;
+  const int64_t T = a.tile;
+  const int64_t toff = (p0 / T) * (int64_t)m * C * T + (p0 % T);
+  MT* Y0 = a.Y + toff;
+  MT* Y1 = a.Y + (int64_t)m * C * st + toff;
   for (int k = 0; k < m; ++k) {
     const double ck = a.coef[kRowC * m + k];
     const double uk = a.coef[kRowU * m + k];
@@ -523,8 +531,8 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, int64_t p0, 
         o0[v] = (MT)(-ck * X0[s][v]);
         o1[v] = (MT)(uk * X1[s][v] + vk * X2[s][v]);
       }
-      store_v<FULL, MT, V>(Y0 + k * mstride + s * st + p0, nv, o0);
-      store_v<FULL, MT, V>(Y1 + k * mstride + s * st + p0, nv, o1);
+      store_v<FULL, MT, V, true>(Y0 + ((int64_t)k * C + s) * T, nv, o0);
+      store_v<FULL, MT, V, true>(Y1 + ((int64_t)k * C + s) * T, nv, o1);
     }
   }
 }
@@ -550,14 +558,15 @@ __global__ __launch_bounds__(kBlock) void start_kernel(const StartArgs<MT> a) {
 template <typename MT>
 __global__ __launch_bounds__(kBlock) void plain_kernel(const double* __restrict__ X, const MT* __restrict__ Y,
                                                        const double* __restrict__ coef, double* __restrict__ out,
-                                                       int64_t npts, int64_t stride, int m, int c) {
+                                                       int64_t npts, int64_t stride, int64_t tile, int m, int c) {
   const int64_t total = (int64_t)m * c * npts;
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += (int64_t)gridDim.x * kBlock) {
     const int64_t p = t % npts;
     const int64_t ks = t / npts;
     const int s = (int)(ks % c);
     const int k = (int)(ks / c);
-    out[ks * stride + p] = (double)Y[ks * stride + p] + coef[kRowC * m + k] * X[s * stride + p];
+    const int64_t yi = ((p / tile) * m * c + ks) * tile + p % tile;
+    out[ks * stride + p] = (double)Y[yi] + coef[kRowC * m + k] * X[s * stride + p];
   }
 }
 
@@ -572,19 +581,19 @@ int grid_for(const tfs_plan_s* p, int64_t ngroups) {
 
 bool aligned(const void* ptr, size_t bytes) { return ptr == nullptr || ((uintptr_t)ptr % bytes) == 0; }
 
-// Points per lane: the requested width, else the widest default one (4 for 2-D FP32
-// modes, else 2; 3-D FP32 at 4 points per lane exceeds the register file) for which every
-// plane start and every group start is aligned to the vector size of each field
-// (modes: V * sizeof(MT); FP64 fields: V * 8).
+// Points per lane: the requested width, else the widest one (4 for FP32 modes, 2 for
+// FP64: 16-byte mode accesses, fastest on MI355X) for which every plane start and every
+// group start is aligned to the vector size of each field (modes: V * sizeof(MT); FP64
+// fields: V * 8).
 template <int D, typename MT>
 int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const void* X, const void* Y,
              const void* tau) {
-  const int widest = (sizeof(MT) == 4 && (D == 2 || p->vec_override == 4)) ? 4 : 2;
+  const int widest = sizeof(MT) == 4 ? 4 : 2;
   const int cand[3] = {widest, 2, 1};
   for (int V : cand) {
     if (V > widest) continue;
     if (p->vec_override && V != p->vec_override) continue;
-    if (p->stride % V) continue;
+    if (p->stride % V || p->tile % V) continue;
     const size_t bm = (size_t)V * sizeof(MT), bd = (size_t)V * 8;
     if (aligned(k0, bd) && aligned(k1, bd) && aligned(X, bd) && aligned(Y, bm) && aligned(tau, bd)) return V;
   }
@@ -623,6 +632,7 @@ hipError_t bdf2_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const
   a.part = p->d_part;
   a.npts = p->npoints;
   a.stride = st;
+  a.tile = p->tile;
   a.m = p->m;
   a.s.a_diag = p->a_diag;
   a.s.eta = p->eta;
@@ -663,6 +673,7 @@ hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, double* X, void
   a.part = p->d_part;
   a.npts = p->npoints;
   a.stride = p->stride;
+  a.tile = p->tile;
   a.m = p->m;
   a.s.hgt = p->hg * p->theta;
   a.s.inv_De = 1.0 / p->De;
@@ -683,7 +694,7 @@ hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, double* X, void
 
 }  // namespace
 
-int max_blocks(const tfs_plan_s* p) { return p->num_cus * 16; }
+int max_blocks(const tfs_plan_s* p) { return p->num_cus * kMaxBlocksPerCU; }
 
 hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, double* X, void* Y,
                        double* tau, double* diag) {
@@ -720,11 +731,11 @@ hipError_t launch_modes_to_plain(const tfs_plan_s* p, int slot, const double* X,
   if (p->precision == TFS_FP64) {
     const double* Ys = static_cast<const double*>(Y) + (int64_t)slot * p->m * p->c * st;
     hipLaunchKernelGGL(plain_kernel<double>, dim3(grid), dim3(kBlock), 0, p->stream, Xs, Ys, p->d_coef, Xk,
-                       p->npoints, st, p->m, p->c);
+                       p->npoints, st, p->tile, p->m, p->c);
   } else {
     const float* Ys = static_cast<const float*>(Y) + (int64_t)slot * p->m * p->c * st;
     hipLaunchKernelGGL(plain_kernel<float>, dim3(grid), dim3(kBlock), 0, p->stream, Xs, Ys, p->d_coef, Xk,
-                       p->npoints, st, p->m, p->c);
+                       p->npoints, st, p->tile, p->m, p->c);
   }
   return hipGetLastError();
 }

@@ -21,8 +21,13 @@ TFS_FP64, TFS_FP32_MODES = 0, 1
 TFS_FLAG_CHECK_SYNC = 1
 
 EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_step", "tfs_modes_to_plain",
-           "tfs_plan_tables", "tfs_plan_stride", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
+           "tfs_plan_tables", "tfs_plan_stride", "tfs_plan_tile", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
            "tfs_status_string", "tfs_last_error")
+
+
+# Mode-ring tile (points) used when the caller does not choose one; measured best on
+# MI355X for the 2-D (c = 3) and 3-D (c = 6) update.
+DEFAULT_TILE = {2: 4096, 3: 8192}
 
 
 class TfsError(RuntimeError):
@@ -33,6 +38,7 @@ class TfsError(RuntimeError):
 
 class PlanDesc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("nmodes", C.c_int32), ("npoints", C.c_int64), ("stride", C.c_int64),
+                ("tile", C.c_int64),
                 ("alpha", C.c_double), ("De", C.c_double), ("eta_p", C.c_double), ("dt", C.c_double),
                 ("max_steps", C.c_int64), ("w", C.POINTER(C.c_double)), ("lam", C.POINTER(C.c_double)),
                 ("precision", C.c_int32), ("flags", C.c_uint32), ("stream", C.c_void_p)]
@@ -59,6 +65,8 @@ def lib():
     L.tfs_plan_tables.argtypes = [vp, dp, dp, dp]
     L.tfs_plan_stride.argtypes = [vp]
     L.tfs_plan_stride.restype = i64
+    L.tfs_plan_tile.argtypes = [vp]
+    L.tfs_plan_tile.restype = i64
     L.tfs_plan_tune.argtypes = [vp, C.c_char_p, i64]
     L.tfs_soe_fit.argtypes = [C.c_double, i32, C.c_double, C.c_double, dp, dp, dp, dp, dp]
     L.tfs_soe_gl_log.argtypes = [C.c_double, i32, C.c_double, C.c_double, dp, dp, dp, dp]
@@ -112,7 +120,7 @@ class Plan:
     """One tfs_plan: dim, m, npoints, parameters and the (w, lambda) table."""
 
     def __init__(self, dim, npoints, w, lam, alpha, De, eta_p, dt, max_steps, precision="fp64",
-                 stride=0, flags=0, stream=None):
+                 stride=0, tile=None, flags=0, stream=None):
         import torch
         self.dim = int(dim)
         self.c = self.dim * (self.dim + 1) // 2
@@ -127,13 +135,16 @@ class Plan:
         self.mode_dtype = torch.float64 if self.precision == TFS_FP64 else torch.float32
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
-        d = PlanDesc(self.dim, self.m, self.npoints, int(stride), self.alpha, self.De, self.eta_p, self.dt,
+        if tile is None:
+            tile = DEFAULT_TILE[self.dim]
+        d = PlanDesc(self.dim, self.m, self.npoints, int(stride), int(tile), self.alpha, self.De, self.eta_p, self.dt,
                      self.max_steps, _dptr(self.w), _dptr(self.lam), self.precision, int(flags),
                      C.c_void_p(stream))
         h = C.c_void_p()
         check(lib().tfs_plan_create(C.byref(d), C.byref(h)))
         self._h = h
         self.stride = int(lib().tfs_plan_stride(h))
+        self.tile = int(lib().tfs_plan_tile(h))
 
     @property
     def handle(self):
@@ -158,22 +169,53 @@ class Plan:
 
     # -- buffers -------------------------------------------------------------------------
     def alloc(self, device="cuda"):
-        """Zeroed X ring, Y ring, tau and diag tensors with this plan's layout."""
+        """Zeroed X ring, Y ring (flat, in the plan's tiled layout), tau and diag tensors."""
         import torch
         st = self.stride
         X = torch.zeros((2, self.c, st), dtype=torch.float64, device=device)
-        Y = torch.zeros((2, self.m, self.c, st), dtype=self.mode_dtype, device=device)
+        Y = torch.zeros((2 * self.m * self.c * st,), dtype=self.mode_dtype, device=device)
         tau = torch.zeros((self.c, st), dtype=torch.float64, device=device)
         diag = torch.zeros(6, dtype=torch.float64, device=device)
         return X, Y, tau, diag
 
     # -- entry points --------------------------------------------------------------------
+    def _need(self, t, name, numel, dtype):
+        """The C ABI takes raw pointers; refuse tensors smaller than the plan's layout."""
+        if t is None:
+            return
+        if t.dtype != dtype:
+            raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+        if t.numel() < numel:
+            raise ValueError(f"{name}: {t.numel()} elements, the plan's layout needs {numel}")
+
     def step(self, n, kappa_a, kappa_b, X, Y, tau=None, diag=None):
+        import torch
+        if self.npoints > 0:
+            st, c, d = self.stride, self.c, self.dim
+            self._need(kappa_a, "kappa_a", d * d * st, torch.float64)
+            self._need(kappa_b, "kappa_b", d * d * st, torch.float64)
+            self._need(X, "X", 2 * c * st, torch.float64)
+            self._need(Y, "Y", 2 * self.m * c * st, self.mode_dtype)
+            self._need(tau, "tau", c * st, torch.float64)
+        self._need(diag, "diag", 6, torch.float64)
         check(lib().tfs_step(self._h, int(n), _tptr(kappa_a), _tptr(kappa_b), _tptr(X), _tptr(Y), _tptr(tau),
                              _tptr(diag)))
 
     def modes_to_plain(self, slot, X, Y, out):
+        import torch
+        st, c = self.stride, self.c
+        self._need(X, "X", 2 * c * st, torch.float64)
+        self._need(Y, "Y", 2 * self.m * c * st, self.mode_dtype)
+        self._need(out, "out", self.m * c * st, torch.float64)
         check(lib().tfs_modes_to_plain(self._h, int(slot), _tptr(X), _tptr(Y), _tptr(out)))
+
+    def kappa_tensor(self, kappa=None, device="cuda"):
+        """[d*d][stride] FP64 device tensor, optionally filled from a host [d*d][npoints] array."""
+        import torch
+        t = torch.zeros((self.dim * self.dim, self.stride), dtype=torch.float64, device=device)
+        if kappa is not None:
+            t[:, :self.npoints] = torch.as_tensor(np.ascontiguousarray(kappa)).to(device)
+        return t
 
     def tables(self):
         t = np.zeros((5, self.m))

@@ -74,19 +74,23 @@ def test_small_random_cases(d, prec, P, nsteps):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
-@pytest.mark.parametrize("layout", ["padded_stride", "unaligned", "vec1", "vec2", "vec4"])
+@pytest.mark.parametrize("layout", ["untiled_padded", "untiled", "tile4", "tile512_padded", "tile1024",
+                                    "unaligned", "vec1", "vec2", "vec4"])
 def test_layouts_and_vector_widths(prec, layout):
     d, P, N = 3, 1021, 9
     if layout == "vec4" and prec == "fp64":
         pytest.skip("4 points per lane exists for FP32 modes only")
     kappa, X0, w, lam = small_case(d, P, 7)
-    kw = {}
-    if layout == "padded_stride":
-        kw = dict(stride=1100)
-    elif layout == "unaligned":
-        kw = dict(offset=1)
-    else:
-        kw = dict(vec=int(layout[-1]), stride=1024)
+    kw = {
+        "untiled_padded": dict(tile=0, stride=1100),
+        "untiled": dict(tile=0),
+        "tile4": dict(tile=4),
+        "tile512_padded": dict(tile=512, stride=2048),
+        "tile1024": dict(tile=1024),
+        "unaligned": dict(offset=1),
+    }.get(layout, None)
+    if kw is None:
+        kw = dict(vec=int(layout[-1]), stride=1024, tile=1024)
     print(f"layout {layout} {prec}", flush=True)
     g = run_gpu(d, w, lam, 0.8, 0.2, 1e-3, N, kappa, X0, precision=prec, want_modes=True, want_diag=True, **kw)
     o = O.run(d, w, lam, 0.8, 0.2, 1e-3, N, kappa, X0, want_modes=True, want_diag=True)
@@ -202,8 +206,8 @@ def test_restart_from_saved_levels_is_bitwise_identical():
     kappa, X0, w, lam = small_case(d, P, 31)
     plan = tfs.Plan(d, P, w, lam, 0.45, 1.0, 0.1, 1e-3, 30)
     X, Y, tau, _ = plan.alloc()
-    X[0] = torch.from_numpy(X0).cuda()
-    kd = torch.from_numpy(kappa).cuda()
+    X[0, :, :P] = torch.from_numpy(X0).cuda()
+    kd = plan.kappa_tensor(kappa)
     for n in range(20):
         plan.step(n, kd, kd, X, Y, tau)
     Xs, Ys = X.clone(), Y.clone()
@@ -222,8 +226,8 @@ def test_check_sync_flags_non_finite_state():
     kappa, X0, w, lam = small_case(d, P, 41)
     plan = tfs.Plan(d, P, w, lam, 0.45, 1.0, 0.1, 1e-3, 10, flags=tfs.TFS_FLAG_CHECK_SYNC)
     X, Y, tau, diag = plan.alloc()
-    X[0] = torch.from_numpy(X0).cuda()
-    kd = torch.from_numpy(kappa).cuda()
+    X[0, :, :P] = torch.from_numpy(X0).cuda()
+    kd = plan.kappa_tensor(kappa)
     plan.step(0, kd, None, X, Y, tau, diag)
     plan.step(1, kd, kd, X, Y, tau, diag)
     X[1, 0, 17] = float("nan")            # corrupt level 1 at one point, from the host
@@ -249,13 +253,15 @@ def test_step_argument_errors():
     kappa, X0, w, lam = small_case(d, P, 51)
     plan = tfs.Plan(d, P, w, lam, 0.45, 1.0, 0.1, 1e-3, 4)
     X, Y, tau, _ = plan.alloc()
-    kd = torch.from_numpy(kappa).cuda()
+    kd = plan.kappa_tensor(kappa)
     for n in (-1, 4, 100):
         with pytest.raises(tfs.TfsError) as e:
             plan.step(n, kd, None, X, Y, tau)
         assert e.value.status == tfs.TFS_EINVAL
     with pytest.raises(tfs.TfsError):
         plan.step(0, None, None, X, Y, tau)
+    with pytest.raises(ValueError):                    # a kappa smaller than the plan's layout
+        plan.step(0, kd[:, :P].contiguous(), None, X, Y, tau)
 
 
 def test_empty_plan():
