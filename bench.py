@@ -36,6 +36,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(profile_name):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, or None when
+    there is none or the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile_name + ".md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", "rocprofv3")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = b"".join(open(os.path.join(ROOT, "paper_2411_17294_amd", "csrc", f), "rb").read()
+                   for f in ("tfs_kernels.hip", "tfs_internal.h"))
+    if fields.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(wl, alpha, w, lam, nthreads):
     """Oracle on a bounded sample of the workload: every 2nd point of the grid for all
     time levels, kappa frozen at t = 0 (the oracle's per-step work does not depend on it)."""
@@ -169,6 +191,8 @@ def main():
     launches = nfields * args.steps
     avg_launch_s = ms * 1e-3 / launches
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    profile = "bdf2_kernel_" + wl.name + ("" if form == wl.precision else "_" + form)
+    traffic = profiled_traffic(profile)
 
     out = {
         "metric": "point-mode updates/s + % HBM roofline, FP64 vs FP32-mode fwd+adjoint",
@@ -188,7 +212,7 @@ def main():
                    "kappa": "time-varying, extrapolated" if wl.time_varying else "steady",
                    "fields_per_step": nfields, "mode_tile": plans[0][3].tile},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "bdf2_kernel", "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": avg_launch_s * 1e6, "measured_copy_GBs": copy_gbs},
         "wall_s": wall,

@@ -484,6 +484,23 @@ def test_positive_definiteness_and_determinism_on_smallest_workload():
     assert np.array_equal(r1["X"], r2["X"]) and np.array_equal(r1["tau"], r2["tau"])
 
 
+@pytest.mark.parametrize("d", [2, 3])
+def test_diagnostics_match_library_determinants(d):
+    """Diagnostics: leading principal minors of C = I + X (numpy determinants), max and sum of
+    ||tau||_F^2 over the full tensor, non-finite count, at the last step."""
+    kap, X0 = I.random_symmetric_case(d, 50, 80 + d, kscale=0.6, xscale=0.05)
+    w, lam, _ = soe.soe_fit(0.5, 6, 1e-3, 0.02)
+    r = O.run(d, w, lam, 1.0, 0.1, 1e-3, 7, kap, X0, want_diag=True, want_traj=True)
+    X = full_from_packed(d, r["traj"][-1])            # [d, d, P]
+    T = full_from_packed(d, r["tau"])
+    C = np.moveaxis(X, -1, 0) + np.eye(d)
+    minors = [np.linalg.det(C[:, :q, :q]) for q in (1, 2, d)]
+    f2 = np.sum(np.moveaxis(T, -1, 0) ** 2, axis=(1, 2))
+    ref = [m.min() for m in minors] + [np.sqrt(f2).max(), f2.sum(), 0.0]
+    got = r["diag"][-1]
+    assert np.allclose(got, ref, rtol=1e-13, atol=0)
+
+
 def test_complex_step_matches_real_run_and_finite_differences():
     """The complex build reproduces the real run and its imaginary part is the derivative."""
     rng = np.random.default_rng(70)
