@@ -129,6 +129,68 @@ tfs_status tfs_step(tfs_plan plan, int64_t n, const double* kappa_a, const doubl
                     double* X, void* Y, double* tau, double* diag);
 
 /*
+ * tfs_step with explicit time levels instead of the two-slot rings, so that a caller can
+ * keep every level (checkpointed recomputation for the adjoint).  Same update, same
+ * layouts per level:
+ *   X_n, X_nm1, X_out    [c][stride] FP64: levels n, n-1 (unused at n = 0) and n+1;
+ *                        X_out must not alias X_n (it may alias X_nm1).
+ *   Y_n, Y_nm1, Y_out    m * c * stride mode elements each (plan precision and tiling):
+ *                        levels n, n-1 and n+1; Y_out may alias Y_nm1 but not Y_n.
+ *                        At n = 0 the start-up writes level 0 into Y_nm1 and level 1 into
+ *                        Y_out, and Y_n is unused.
+ * Errors as tfs_step, plus TFS_EINVAL for the forbidden aliases.
+ */
+tfs_status tfs_step_levels(tfs_plan plan, int64_t n, const double* kappa_a, const double* kappa_b,
+                           const double* X_n, const double* X_nm1, double* X_out,
+                           const void* Y_n, void* Y_nm1, void* Y_out, double* tau, double* diag);
+
+/*
+ * Adjoint of one step (reverse mode), for a scalar loss L of the stresses.  The forward
+ * BDF2 step and the SDIRK2 start-up are linear in (X, Y); this call applies the transpose of
+ * step n -> n+1 and accumulates the gradients of the step's coefficients.  It is the
+ * derivative of the scheme of Sec. 4.1; the paper itself does not differentiate it.
+ *
+ * Call it for n = N-1, N-2, ..., 0 after zeroing Xbar and Hbar, with the forward levels of
+ * the same run (recomputed from checkpoints by the caller):
+ *   X_n, X_nm1, X_np1   [c][stride] FP64 forward levels n, n-1, n+1 (X_n = X^0 at n = 0;
+ *                       X_nm1, X_np1 unused at n = 0)
+ *   Y_n, Y_nm1          forward mode levels n, n-1 (tiled layout; unused at n = 0)
+ *   kappa_a, kappa_b    as passed to the forward step n
+ *   Xbar                device [2][c][stride] FP64 adjoint ring.  Before step n, slot (n+1)%2
+ *                       holds dL/dX^{n+1} from the later steps and slot n%2 the part of dL/dX^n
+ *                       from step n+1; after it, slot n%2 holds dL/dX^n complete and slot
+ *                       (n+1)%2 the part of dL/dX^{n-1} from step n.  After n = 0, slot 0 is
+ *                       dL/dX^0.
+ *   Hbar                device mode-adjoint ring (2 slots, plan precision and tiling) holding
+ *                       H_k^(j) = dL/d(2 Y_k^j - Y_k^{j-1}/2); slot j%2 holds H^(j).
+ *   taubar              device [c][stride] FP64 dL/dtau^{n+1} (or NULL: no direct loss on it)
+ *   kappabar_a/_b       device [d*d][stride] FP64, accumulated: dL/dkappa_a, dL/dkappa_b of
+ *                       this step (NULL to skip).  Passing the same buffer for both gives the
+ *                       derivative with respect to a kappa shared by both arguments.
+ *   pbar                device [tfs_pbar_size] FP64, accumulated: gradients of the per-mode
+ *                       factors, the scalar factors and zeta^{n+1}; convert with
+ *                       tfs_pbar_to_params.
+ * Asynchronous on the plan's stream.  Errors: TFS_EINVAL (null required pointer, n out of
+ * range), TFS_EHIP.
+ */
+tfs_status tfs_step_adjoint(tfs_plan plan, int64_t n, const double* kappa_a, const double* kappa_b,
+                            const double* X_n, const double* X_nm1, const double* X_np1,
+                            const void* Y_n, const void* Y_nm1, double* Xbar, void* Hbar,
+                            const double* taubar, double* kappabar_a, double* kappabar_b, double* pbar);
+
+/* Length of the pbar accumulator of a plan: 6 m + 16 + max_steps + 1. */
+int64_t tfs_pbar_size(tfs_plan plan);
+
+/*
+ * Host chain rule from an accumulated pbar (host copy) to the gradients with respect to the
+ * weights and poles (dL_dw, dL_dlambda: host [m]), the relaxation time De and eta_p (host
+ * scalars), through every coefficient the plan derived from them: the BDF2 factors, the
+ * SDIRK2 start-up factors and the mass-mode memory table.  Any output may be NULL.
+ */
+tfs_status tfs_pbar_to_params(tfs_plan plan, const double* pbar_host, double* dL_dw, double* dL_dlambda,
+                              double* dL_dDe, double* dL_deta_p);
+
+/*
  * Convert the mode ring slot `slot` (0 or 1) to plain fractional modes
  * X_k = Y_k + c_k X, with X taken from the same slot of the X ring.
  * Xk_out: device [m][c][stride] FP64, untiled.  Asynchronous on the plan's stream.

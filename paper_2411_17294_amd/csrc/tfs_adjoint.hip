@@ -1,0 +1,749 @@
+// Adjoint (reverse-mode) kernels of the time-fractional extra-stress update (gfx950).
+//
+// The forward BDF2 step is linear in the state, so its transpose runs backwards in time
+// with the same streaming structure.  The mode history h^_k = 2 Y_k^n - Y_k^{n-1}/2 enters
+// Y_k^{n+1} = d_k h^_k + d_k c_k P and G = sum_k eta_k h^_k + s P; its adjoint
+//     H_k^(n) = dL/dh^_k(step n) = d_k Ybar_k^{n+1} + eta_k Gbar^(n),
+//     Ybar_k^{j} = 2 H_k^(j) - H_k^(j+1)/2,
+// is itself a two-level recurrence: each backward step reads H^(n+1), H^(n+2) and writes
+// H^(n) into the slot of H^(n+2).  The forward modes of levels n, n-1 are read only for
+// the gradients of the per-mode coefficients (d_k, d_k c_k, eta_k).
+//
+// Per point the local part is reversed by hand: tau = q (eta X^{n+1} - G), the pivoted solve
+// M X^{n+1} = R with M = a I - eta K(kappa~) (adjoint: M^T Rbar = Xbar), R = P - A(G) +
+// zeta S, A(G) = K(kappa~) G - G/De.  Gradients with respect to kappa~ use, for a packed
+// adjoint v and symmetric Z, v . packed(kappa Z + Z kappa^T) = 2 <V Z, kappa> with V the
+// symmetric matrix holding v on the diagonal and v/2 off it.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "tfs_device.h"
+#include "tfs_internal.h"
+
+namespace tfs {
+namespace {
+using namespace dev;
+
+// K(kappa) as an explicit packed c x c matrix (column t = K applied to the t-th unit tensor).
+template <int D>
+__device__ __forceinline__ void build_K(const double (&k)[D * D], double (&Km)[Sym<D>::C][Sym<D>::C]) {
+  build_M<D>(k, 0.0, -1.0, Km);
+}
+
+// kb += f * 2 V Z, V the symmetric matrix of packed v (v/2 off the diagonal), Z symmetric packed.
+template <int D>
+__device__ __forceinline__ void kgrad_VZ(double (&kb)[D * D], double f, const double (&v)[Sym<D>::C],
+                                         const double (&z)[Sym<D>::C]) {
+  constexpr int C = Sym<D>::C;
+  double Vm[D][D], Zm[D][D];
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+    const double hv = (i == j) ? v[s] : 0.5 * v[s];
+    Vm[i][j] = hv; Vm[j][i] = hv;
+    Zm[i][j] = z[s]; Zm[j][i] = z[s];
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < D; ++l) acc += Vm[i][l] * Zm[l][j];
+      kb[i * D + j] += 2.0 * f * acc;
+    }
+}
+
+// kb += f * 2 V  (gradient of v . packed(kappa + kappa^T)).
+template <int D>
+__device__ __forceinline__ void kgrad_V(double (&kb)[D * D], double f, const double (&v)[Sym<D>::C]) {
+#pragma unroll
+  for (int s = 0; s < Sym<D>::C; ++s) {
+    const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+    if (i == j) {
+      kb[i * D + i] += 2.0 * f * v[s];
+    } else {
+      kb[i * D + j] += f * v[s];
+      kb[j * D + i] += f * v[s];
+    }
+  }
+}
+
+template <int C>
+__device__ __forceinline__ double dot(const double (&a)[C], const double (&b)[C]) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < C; ++i) s += a[i] * b[i];
+  return s;
+}
+
+// Solve M^T x = r (r becomes x) for a packed c x c M given row-major.
+template <int N>
+__device__ __forceinline__ void solve_transposed(const double (&M)[N][N], double (&r)[N]) {
+  double Mt[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) Mt[i][j] = M[j][i];
+  solve_pivot<N>(Mt, r);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Block partial: the per-mode sums (3 rows of m, accumulated per wave in LDS) and the
+// per-lane scalar sums, folded over the block in a fixed order and written to part[block].
+__device__ inline void write_block_partial(double* __restrict__ part, int m, const double* smode,
+                                           const double (&sc)[kNumAdjScalars]) {
+  __shared__ double shs[kBlock / 64][kNumAdjScalars];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  double red[kNumAdjScalars];
+#pragma unroll
+  for (int i = 0; i < kNumAdjScalars; ++i) red[i] = wave_sum(sc[i]);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < kNumAdjScalars; ++i) shs[wave][i] = red[i];
+  __syncthreads();
+  const int np = 3 * m + kNumAdjScalars;
+  double* o = part + (size_t)blockIdx.x * np;
+  for (int j = threadIdx.x; j < 3 * m; j += kBlock) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += smode[w * 3 * m + j];
+    o[j] = s;
+  }
+  if (threadIdx.x < kNumAdjScalars) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += shs[w][threadIdx.x];
+    o[3 * m + threadIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------------------------ BDF2 step adjoint
+template <typename MT>
+struct AdjArgs {
+  const double* ka;
+  const double* kb;      // null: kappa~ = kappa_a
+  const double* Xn;      // forward X^n
+  const double* Xm;      // forward X^{n-1}
+  const double* Xp;      // forward X^{n+1}
+  const MT* Yn;          // forward Y^n (tiled)
+  const MT* Ym;          // forward Y^{n-1}
+  double* Xb_new;        // adjoint slot (n+1)%2: in Xbar^{n+1}, out partial Xbar^{n-1}
+  double* Xb_cur;        // adjoint slot n%2: in partial Xbar^n, out complete Xbar^n
+  const MT* H1;          // H^(n+1) slot (n+1)%2
+  MT* H2;                // H^(n+2) in, H^(n) out: slot n%2
+  const double* taubar;  // [c][stride] or null
+  double* kba;           // kappa_a adjoint (+=) or null
+  double* kbb;           // kappa_b adjoint (+=) or null
+  int kb_same;           // kba == kbb
+  const double* coef;
+  double* part;
+  int64_t npts, stride, tile;
+  int m;
+  Bdf2Scalars s;
+};
+
+template <int D, typename MT, int V, bool FULL>
+__device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, int64_t p0, int nv, double* smode,
+                                          double (&sc)[kNumAdjScalars]) {
+  constexpr int C = Sym<D>::C;
+  const int64_t st = a.stride;
+  const int m = a.m;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+
+  double P[C][V], Gb[C][V], Pb[C][V], AGb[C][V], tb[C][V], kbar[D * D][V], kt[D * D][V];
+  // forward per-point quantities and the local reverse pass up to Gbar
+#pragma unroll
+  for (int q = 0; q < D * D; ++q) {
+    double x[V];
+    load_v<FULL, double, V>(a.ka + q * st + p0, nv, x);
+    if (a.kb) {
+      double y[V];
+      load_v<FULL, double, V>(a.kb + q * st + p0, nv, y);
+#pragma unroll
+      for (int v = 0; v < V; ++v) kt[q][v] = 2.0 * x[v] - y[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) kt[q][v] = x[v];
+    }
+  }
+  double Xp[C][V], Xbn[C][V];
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    double xn[V], xm[V];
+    load_v<FULL, double, V>(a.Xn + s * st + p0, nv, xn);
+    load_v<FULL, double, V>(a.Xm + s * st + p0, nv, xm);
+    load_v<FULL, double, V>(a.Xp + s * st + p0, nv, Xp[s]);
+    load_v<FULL, double, V>(a.Xb_new + s * st + p0, nv, Xbn[s]);
+    if (a.taubar) load_v<FULL, double, V>(a.taubar + s * st + p0, nv, tb[s]);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      P[s][v] = 2.0 * xn[v] - 0.5 * xm[v];
+      if (!a.taubar) tb[s][v] = 0.0;
+    }
+  }
+  const double q = a.s.tau_scale, eta = a.s.eta;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    if (!(FULL || v < nv)) {
+#pragma unroll
+      for (int s = 0; s < C; ++s) { Gb[s][v] = 0.0; Pb[s][v] = 0.0; AGb[s][v] = 0.0; tb[s][v] = 0.0; }
+#pragma unroll
+      for (int t = 0; t < D * D; ++t) kbar[t][v] = 0.0;
+      continue;
+    }
+    double k[D * D], xb[C], xp[C], rb[C], M[C][C], Kx[C], S[C];
+#pragma unroll
+    for (int t = 0; t < D * D; ++t) { k[t] = kt[t][v]; kbar[t][v] = 0.0; }
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      xp[s] = Xp[s][v];
+      xb[s] = Xbn[s][v] + q * eta * tb[s][v];     // tau = q (eta X+ - G)
+      rb[s] = xb[s];
+      const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+      S[s] = k[i * D + j] + k[j * D + i];
+    }
+    {
+      double tv[C];
+#pragma unroll
+      for (int s = 0; s < C; ++s) tv[s] = tb[s][v];
+      sc[1] += q * dot<C>(tv, xp);                  // d tau / d eta (X+ part)
+      sc[4] += eta * dot<C>(tv, xp);                // d tau / d q (X+ part; the G part follows the modes)
+    }
+    build_M<D>(k, a.s.a_diag, eta, M);
+    solve_transposed<C>(M, rb);                     // Rbar = M^{-T} Xbar
+    apply_K<D>(k, xp, Kx);
+    sc[0] += -dot<C>(rb, xp);                       // a
+    sc[1] += dot<C>(rb, Kx);                        // eta (matrix)
+    double kb_[D * D];
+#pragma unroll
+    for (int t = 0; t < D * D; ++t) kb_[t] = 0.0;
+    kgrad_VZ<D>(kb_, eta, rb, xp);                  // M = a I - eta K(kappa)
+    sc[5] += dot<C>(rb, S);                         // zeta
+    kgrad_V<D>(kb_, a.s.zeta, rb);                  // R = ... + zeta S
+    // A(G) = K G - G/De with AGbar = -Rbar:  Gbar = K^T AGbar - AGbar/De - q taubar
+    double Km[C][C];
+    build_K<D>(k, Km);
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      double acc = 0.0;
+#pragma unroll
+      for (int s = 0; s < C; ++s) acc += Km[s][t] * (-rb[s]);
+      Gb[t][v] = acc + a.s.inv_De * rb[t] - q * tb[t][v];
+      AGb[t][v] = -rb[t];
+      Pb[t][v] = rb[t];
+    }
+    double pv[C], gbv[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) { pv[s] = P[s][v]; gbv[s] = Gb[s][v]; }
+    sc[2] += dot<C>(gbv, pv);                       // G = G^ + s P
+#pragma unroll
+    for (int s = 0; s < C; ++s) Pb[s][v] += a.s.s_ec * Gb[s][v];
+#pragma unroll
+    for (int t = 0; t < D * D; ++t) kbar[t][v] = kb_[t];
+  }
+
+  // transposed mode recurrence, streaming
+  const int64_t T = a.tile;
+  const int64_t toff = (p0 / T) * (int64_t)m * C * T + (p0 % T);
+  const MT* h1p = a.H1 + toff;
+  MT* h2p = a.H2 + toff;
+  const MT* ynp = a.Yn + toff;
+  const MT* ymp = a.Ym + toff;
+  double Gh[C][V];
+#pragma unroll
+  for (int s = 0; s < C; ++s)
+#pragma unroll
+    for (int v = 0; v < V; ++v) Gh[s][v] = 0.0;
+  MT c1[C][V], c2[C][V], cn[C][V], cm[C][V];
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    load_v<FULL, MT, V, true>(h1p + s * T, nv, c1[s]);
+    load_v<FULL, MT, V, true>(h2p + s * T, nv, c2[s]);
+    load_v<FULL, MT, V, true>(ynp + s * T, nv, cn[s]);
+    load_v<FULL, MT, V, true>(ymp + s * T, nv, cm[s]);
+  }
+  for (int k = 0; k < m; ++k) {
+    const double dk = a.coef[kRowD * m + k];
+    const double ek = a.coef[kRowDC * m + k];
+    const double hk = a.coef[kRowEta * m + k];
+    MT n1[C][V], n2[C][V], nn[C][V], nm[C][V];
+    if (k + 1 < m) {
+      const int64_t o = (int64_t)(k + 1) * C * T;
+#pragma unroll
+      for (int s = 0; s < C; ++s) {
+        load_v<FULL, MT, V, true>(h1p + o + s * T, nv, n1[s]);
+        load_v<FULL, MT, V, true>(h2p + o + s * T, nv, n2[s]);
+        load_v<FULL, MT, V, true>(ynp + o + s * T, nv, nn[s]);
+        load_v<FULL, MT, V, true>(ymp + o + s * T, nv, nm[s]);
+      }
+    }
+    double ad = 0.0, ae = 0.0, ah = 0.0;
+    MT* out = h2p + (int64_t)k * C * T;
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      MT w[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double yb = 2.0 * (double)c1[s][v] - 0.5 * (double)c2[s][v];   // Ybar_k^{n+1}
+        const double hh = 2.0 * (double)cn[s][v] - 0.5 * (double)cm[s][v];  // forward h^_k
+        Gh[s][v] += hk * hh;
+        w[v] = (MT)(dk * yb + hk * Gb[s][v]);
+        Pb[s][v] += ek * yb;
+        ad += yb * hh;
+        ae += yb * P[s][v];
+        ah += Gb[s][v] * hh;
+      }
+      store_v<FULL, MT, V, true>(out + s * T, nv, w);
+    }
+    ad = wave_sum(ad);
+    ae = wave_sum(ae);
+    ah = wave_sum(ah);
+    if (lane == 0) {
+      smode[wave * 3 * m + k] += ad;
+      smode[wave * 3 * m + m + k] += ae;
+      smode[wave * 3 * m + 2 * m + k] += ah;
+    }
+    if (k + 1 < m) {
+#pragma unroll
+      for (int s = 0; s < C; ++s)
+#pragma unroll
+        for (int v = 0; v < V; ++v) { c1[s][v] = n1[s][v]; c2[s][v] = n2[s][v]; cn[s][v] = nn[s][v]; cm[s][v] = nm[s][v]; }
+    }
+  }
+
+  // terms that need G = G^ + s P
+  double Xcur[C][V], Xnew[C][V];
+#pragma unroll
+  for (int s = 0; s < C; ++s) load_v<FULL, double, V>(a.Xb_cur + s * st + p0, nv, Xcur[s]);
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    double G[C], agb[C], tv[C], k[D * D];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      G[s] = Gh[s][v] + a.s.s_ec * P[s][v];
+      agb[s] = AGb[s][v];
+      tv[s] = tb[s][v];
+    }
+#pragma unroll
+    for (int t = 0; t < D * D; ++t) k[t] = kbar[t][v];
+    if (FULL || v < nv) {
+      sc[3] += -dot<C>(agb, G);                     // 1/De
+      sc[4] += -dot<C>(tv, G);                      // q (G part)
+      kgrad_VZ<D>(k, 1.0, agb, G);                  // A(G) = K(kappa) G - G/De
+    }
+#pragma unroll
+    for (int t = 0; t < D * D; ++t) kbar[t][v] = k[t];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      Xcur[s][v] += 2.0 * Pb[s][v];                 // P = 2 X^n - X^{n-1}/2
+      Xnew[s][v] = -0.5 * Pb[s][v];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    store_v<FULL, double, V>(a.Xb_cur + s * st + p0, nv, Xcur[s]);
+    store_v<FULL, double, V>(a.Xb_new + s * st + p0, nv, Xnew[s]);
+  }
+  // kappa adjoints: kappa~ = 2 kappa_a - kappa_b, or kappa_a
+#pragma unroll
+  for (int t = 0; t < D * D; ++t) {
+    double fa, fb;
+    if (!a.kb) { fa = 1.0; fb = 0.0; }
+    else if (a.kb_same) { fa = 1.0; fb = 0.0; }
+    else { fa = 2.0; fb = -1.0; }
+    if (a.kba) {
+      double x[V];
+      load_v<FULL, double, V>(a.kba + t * st + p0, nv, x);
+#pragma unroll
+      for (int v = 0; v < V; ++v) x[v] += fa * kbar[t][v];
+      store_v<FULL, double, V>(a.kba + t * st + p0, nv, x);
+    }
+    if (a.kbb && fb != 0.0) {
+      double x[V];
+      load_v<FULL, double, V>(a.kbb + t * st + p0, nv, x);
+#pragma unroll
+      for (int v = 0; v < V; ++v) x[v] += fb * kbar[t][v];
+      store_v<FULL, double, V>(a.kbb + t * st + p0, nv, x);
+    }
+  }
+}
+
+template <int D, typename MT, int V>
+__global__ __launch_bounds__(kBlock) void adj_kernel(const AdjArgs<MT> a) {
+  extern __shared__ double smode[];   // [kBlock/64][3][m]
+  for (int j = threadIdx.x; j < (kBlock / 64) * 3 * a.m; j += kBlock) smode[j] = 0.0;
+  __syncthreads();
+  double sc[kNumAdjScalars];
+#pragma unroll
+  for (int i = 0; i < kNumAdjScalars; ++i) sc[i] = 0.0;
+  const int64_t ngroups = (a.npts + V - 1) / V;
+  const int64_t gstride = (int64_t)gridDim.x * kBlock;
+  // every lane of a wave iterates the same number of times (the wave reductions need
+  // all 64 lanes), lanes past the end run a masked empty group
+  for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x - (threadIdx.x % 64); g < ngroups; g += gstride) {
+    const int64_t mine = g + (threadIdx.x % 64);
+    const int64_t p0 = mine * V;
+    int nv = (int)((a.npts - p0) < V ? (a.npts - p0) : V);
+    if (mine >= ngroups) nv = 0;
+    if (nv == V) adj_group<D, MT, V, true>(a, p0, nv, smode, sc);
+    else adj_group<D, MT, V, false>(a, nv > 0 ? p0 : 0, nv, smode, sc);
+  }
+  __syncthreads();
+  write_block_partial(a.part, a.m, smode, sc);
+}
+
+// ------------------------------------------------------------------ start-up adjoint
+template <typename MT>
+struct StartAdjArgs {
+  const double* ka;
+  const double* X0;      // forward X^0
+  double* Xb0;           // adjoint slot 0: in partial Xbar^0, out complete Xbar^0
+  const double* Xb1;     // adjoint slot 1: Xbar^1 from later steps
+  const MT* H1;          // H^(1) (slot 1)
+  const MT* H2;          // H^(2) (slot 0)
+  const double* taubar;
+  double* kba;
+  const double* coef;
+  double* part;
+  int64_t npts, stride, tile;
+  int m;
+  StartScalars s;
+};
+
+template <int D, typename MT, int V, bool FULL>
+__device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64_t p0, int nv, double* smode,
+                                                double (&sc)[kNumAdjScalars]) {
+  constexpr int C = Sym<D>::C;
+  const int64_t st = a.stride;
+  const int m = a.m;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  double X0[C][V], X1[C][V], X2[C][V], kt[D * D][V];
+#pragma unroll
+  for (int s = 0; s < C; ++s) load_v<FULL, double, V>(a.X0 + s * st + p0, nv, X0[s]);
+#pragma unroll
+  for (int q = 0; q < D * D; ++q) load_v<FULL, double, V>(a.ka + q * st + p0, nv, kt[q]);
+  // forward recomputation of the two stages
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    double k[D * D], S[C], r[C], M[C][C], AX[C], x1[C];
+#pragma unroll
+    for (int t = 0; t < D * D; ++t) k[t] = kt[t][v];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+      S[s] = k[i * D + j] + k[j * D + i];
+      r[s] = X0[s][v] + a.s.src1 * S[s];
+    }
+    build_M<D>(k, 1.0 + a.s.hgt * a.s.inv_De, a.s.hgt, M);
+    solve_pivot<C>(M, r);
+#pragma unroll
+    for (int s = 0; s < C; ++s) { x1[s] = r[s]; X1[s][v] = r[s]; }
+    apply_K<D>(k, x1, AX);
+#pragma unroll
+    for (int s = 0; s < C; ++s) r[s] = X0[s][v] + a.s.sigma1 * (AX[s] - a.s.inv_De * x1[s]) + a.s.sigma2 * S[s];
+    build_M<D>(k, 1.0 + a.s.hgt * a.s.inv_De, a.s.hgt, M);
+    solve_pivot<C>(M, r);
+#pragma unroll
+    for (int s = 0; s < C; ++s) X2[s][v] = r[s];
+  }
+  // modes: Ybar^0 = -H^(1)/2, Ybar^1 = 2 H^(1) - H^(2)/2;  Y^0 = -c X^0, Y^1 = u X^(1) + v X^(2)
+  double X0b[C][V], X1b[C][V], X2b[C][V];
+#pragma unroll
+  for (int s = 0; s < C; ++s)
+#pragma unroll
+    for (int v = 0; v < V; ++v) { X0b[s][v] = 0.0; X1b[s][v] = 0.0; X2b[s][v] = 0.0; }
+  const int64_t T = a.tile;
+  const int64_t toff = (p0 / T) * (int64_t)m * C * T + (p0 % T);
+  const MT* h1p = a.H1 + toff;
+  const MT* h2p = a.H2 + toff;
+  for (int k = 0; k < m; ++k) {
+    const double ck = a.coef[kRowC * m + k];
+    const double uk = a.coef[kRowU * m + k];
+    const double vk = a.coef[kRowV * m + k];
+    double ac = 0.0, au = 0.0, av = 0.0;
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      MT h1[V], h2[V];
+      load_v<FULL, MT, V, true>(h1p + ((int64_t)k * C + s) * T, nv, h1);
+      load_v<FULL, MT, V, true>(h2p + ((int64_t)k * C + s) * T, nv, h2);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double y0 = -0.5 * (double)h1[v];
+        const double y1 = 2.0 * (double)h1[v] - 0.5 * (double)h2[v];
+        X0b[s][v] += -ck * y0;
+        X1b[s][v] += uk * y1;
+        X2b[s][v] += vk * y1;
+        ac += -y0 * X0[s][v];
+        au += y1 * X1[s][v];
+        av += y1 * X2[s][v];
+      }
+    }
+    ac = wave_sum(ac);
+    au = wave_sum(au);
+    av = wave_sum(av);
+    if (lane == 0) {
+      smode[wave * 3 * m + k] += ac;
+      smode[wave * 3 * m + m + k] += au;
+      smode[wave * 3 * m + 2 * m + k] += av;
+    }
+  }
+  double Xb1[C][V], tb[C][V], Xb0in[C][V];
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    load_v<FULL, double, V>(a.Xb1 + s * st + p0, nv, Xb1[s]);
+    load_v<FULL, double, V>(a.Xb0 + s * st + p0, nv, Xb0in[s]);
+    if (a.taubar) load_v<FULL, double, V>(a.taubar + s * st + p0, nv, tb[s]);
+    else
+#pragma unroll
+      for (int v = 0; v < V; ++v) tb[s][v] = 0.0;
+  }
+  double kbar[D * D][V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+#pragma unroll
+    for (int t = 0; t < D * D; ++t) kbar[t][v] = 0.0;
+    if (!(FULL || v < nv)) continue;
+    double k[D * D], S[C], x0[C], x1[C], x2[C], x1b[C], x2b[C], tv[C];
+#pragma unroll
+    for (int t = 0; t < D * D; ++t) k[t] = kt[t][v];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+      S[s] = k[i * D + j] + k[j * D + i];
+      x0[s] = X0[s][v]; x1[s] = X1[s][v]; x2[s] = X2[s][v];
+      tv[s] = tb[s][v];
+      // tau^1 = gamma (theta X^(2) - hr X^(1));  X^1 = X^(2)
+      x2b[s] = X2b[s][v] + Xb1[s][v] + a.s.gamma * a.s.theta * tv[s];
+      x1b[s] = X1b[s][v] - a.s.gamma * a.s.hr * tv[s];
+    }
+    double scale_g = 0.0;
+#pragma unroll
+    for (int s = 0; s < C; ++s) scale_g += tv[s] * (a.s.theta * x2[s] - a.s.hr * x1[s]);
+    sc[5] += scale_g;                               // gamma
+    sc[6] += a.s.gamma * dot<C>(tv, x2);            // theta
+    sc[7] += -a.s.gamma * dot<C>(tv, x1);           // hr
+    double M[C][C], rb[C], Kx[C], kb_[D * D];
+#pragma unroll
+    for (int t = 0; t < D * D; ++t) kb_[t] = 0.0;
+    const double diag1 = 1.0 + a.s.hgt * a.s.inv_De;
+    // stage 2: M X^(2) = X^0 + sigma1 A(X^(1)) + sigma2 S
+    build_M<D>(k, diag1, a.s.hgt, M);
+#pragma unroll
+    for (int s = 0; s < C; ++s) rb[s] = x2b[s];
+    solve_transposed<C>(M, rb);
+    apply_K<D>(k, x2, Kx);
+    const double rx2 = dot<C>(rb, x2);
+    sc[1] += -rx2 * a.s.inv_De + dot<C>(rb, Kx);   // hgt (matrix)
+    sc[0] += -rx2 * a.s.hgt;                        // 1/De (matrix)
+    kgrad_VZ<D>(kb_, a.s.hgt, rb, x2);
+    double AX[C];
+    apply_K<D>(k, x1, AX);
+#pragma unroll
+    for (int s = 0; s < C; ++s) AX[s] -= a.s.inv_De * x1[s];
+    sc[3] += dot<C>(rb, AX);                        // sigma1
+    sc[4] += dot<C>(rb, S);                         // sigma2
+    kgrad_V<D>(kb_, a.s.sigma2, rb);
+    double x0b[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) x0b[s] = X0b[s][v] + rb[s];
+    // A(X^(1)) = K X^(1) - X^(1)/De with adjoint sigma1 Rbar2
+    double axb[C], Km[C][C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) axb[s] = a.s.sigma1 * rb[s];
+    build_K<D>(k, Km);
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      double acc = 0.0;
+#pragma unroll
+      for (int s = 0; s < C; ++s) acc += Km[s][t] * axb[s];
+      x1b[t] += acc - a.s.inv_De * axb[t];
+    }
+    sc[0] += -dot<C>(axb, x1);                      // 1/De
+    kgrad_VZ<D>(kb_, 1.0, axb, x1);
+    // stage 1: M X^(1) = X^0 + src1 S
+    build_M<D>(k, diag1, a.s.hgt, M);
+#pragma unroll
+    for (int s = 0; s < C; ++s) rb[s] = x1b[s];
+    solve_transposed<C>(M, rb);
+    apply_K<D>(k, x1, Kx);
+    const double rx1 = dot<C>(rb, x1);
+    sc[1] += -rx1 * a.s.inv_De + dot<C>(rb, Kx);
+    sc[0] += -rx1 * a.s.hgt;
+    kgrad_VZ<D>(kb_, a.s.hgt, rb, x1);
+    sc[2] += dot<C>(rb, S);                         // src1
+    kgrad_V<D>(kb_, a.s.src1, rb);
+#pragma unroll
+    for (int s = 0; s < C; ++s) X0b[s][v] = Xb0in[s][v] + x0b[s] + rb[s];
+#pragma unroll
+    for (int t = 0; t < D * D; ++t) kbar[t][v] = kb_[t];
+  }
+#pragma unroll
+  for (int s = 0; s < C; ++s) store_v<FULL, double, V>(a.Xb0 + s * st + p0, nv, X0b[s]);
+  if (a.kba) {
+#pragma unroll
+    for (int t = 0; t < D * D; ++t) {
+      double x[V];
+      load_v<FULL, double, V>(a.kba + t * st + p0, nv, x);
+#pragma unroll
+      for (int v = 0; v < V; ++v) x[v] += kbar[t][v];
+      store_v<FULL, double, V>(a.kba + t * st + p0, nv, x);
+    }
+  }
+}
+
+template <int D, typename MT, int V>
+__global__ __launch_bounds__(kBlock) void start_adj_kernel(const StartAdjArgs<MT> a) {
+  extern __shared__ double smode[];
+  for (int j = threadIdx.x; j < (kBlock / 64) * 3 * a.m; j += kBlock) smode[j] = 0.0;
+  __syncthreads();
+  double sc[kNumAdjScalars];
+#pragma unroll
+  for (int i = 0; i < kNumAdjScalars; ++i) sc[i] = 0.0;
+  const int64_t ngroups = (a.npts + V - 1) / V;
+  const int64_t gstride = (int64_t)gridDim.x * kBlock;
+  for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x - (threadIdx.x % 64); g < ngroups; g += gstride) {
+    const int64_t mine = g + (threadIdx.x % 64);
+    const int64_t p0 = mine * V;
+    int nv = (int)((a.npts - p0) < V ? (a.npts - p0) : V);
+    if (mine >= ngroups) nv = 0;
+    if (nv == V) start_adj_group<D, MT, V, true>(a, p0, nv, smode, sc);
+    else start_adj_group<D, MT, V, false>(a, nv > 0 ? p0 : 0, nv, smode, sc);
+  }
+  __syncthreads();
+  write_block_partial(a.part, a.m, smode, sc);
+}
+
+// One block per entry of the partial vector: sums the block partials in order and adds the
+// result to pbar at that entry's position (dest[j] >= 0), or at zeta_dest (dest[j] == -2).
+__global__ __launch_bounds__(kBlock) void adj_finish_kernel(const double* __restrict__ part, int nparts, int np,
+                                                            const int* __restrict__ dest, int64_t zeta_dest,
+                                                            double* __restrict__ pbar) {
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += kBlock) s += part[(size_t)b * np + j];
+  __shared__ double sh[kBlock / 64];
+  s = wave_sum(s);
+  if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+    if (dest[j] >= 0) pbar[dest[j]] += t;
+    else if (dest[j] == -2) pbar[zeta_dest] += t;
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+int grid_adj(const tfs_plan_s* p, int64_t ngroups) {
+  const int64_t cap = (int64_t)p->num_cus * p->grid_per_cu;
+  int64_t g = (ngroups + kBlock - 1) / kBlock;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <int D, typename MT, int V>
+hipError_t adj_go(const tfs_plan_s* p, const AdjArgs<MT>& a, int64_t zeta_dest, double* pbar) {
+  const int64_t ngroups = (a.npts + V - 1) / V;
+  const int grid = grid_adj(p, ngroups);
+  const size_t shm = sizeof(double) * (kBlock / 64) * 3 * p->m;
+  hipLaunchKernelGGL((adj_kernel<D, MT, V>), dim3(grid), dim3(kBlock), shm, p->stream, a);
+  const int np = 3 * p->m + kNumAdjScalars;
+  hipLaunchKernelGGL(adj_finish_kernel, dim3(np), dim3(kBlock), 0, p->stream, a.part, grid, np,
+                     p->d_dest_bdf2, zeta_dest, pbar);
+  return hipGetLastError();
+}
+
+template <int D, typename MT, int V>
+hipError_t start_adj_go(const tfs_plan_s* p, const StartAdjArgs<MT>& a, double* pbar) {
+  const int64_t ngroups = (a.npts + V - 1) / V;
+  const int grid = grid_adj(p, ngroups);
+  const size_t shm = sizeof(double) * (kBlock / 64) * 3 * p->m;
+  hipLaunchKernelGGL((start_adj_kernel<D, MT, V>), dim3(grid), dim3(kBlock), shm, p->stream, a);
+  const int np = 3 * p->m + kNumAdjScalars;
+  hipLaunchKernelGGL(adj_finish_kernel, dim3(np), dim3(kBlock), 0, p->stream, a.part, grid, np,
+                     p->d_dest_start, (int64_t)-1, pbar);
+  return hipGetLastError();
+}
+
+template <int D, typename MT>
+hipError_t adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, double* pbar) {
+  const int64_t st = p->stride;
+  const int64_t ys = (int64_t)p->m * Sym<D>::C * st;
+  const int64_t xs = (int64_t)Sym<D>::C * st;
+  const int sn = (int)(n % 2), sp = 1 - sn;
+  MT* Hb = static_cast<MT*>(L.Hbar);
+  if (n == 0) {
+    StartAdjArgs<MT> a;
+    a.ka = L.ka;
+    a.X0 = L.Xn;
+    a.Xb0 = L.Xbar;
+    a.Xb1 = L.Xbar + xs;
+    a.H1 = Hb + ys;
+    a.H2 = Hb;
+    a.taubar = L.taubar;
+    a.kba = L.kba;
+    a.coef = p->d_coef;
+    a.part = p->d_adj_part;
+    a.npts = p->npoints;
+    a.stride = st;
+    a.tile = p->tile;
+    a.m = p->m;
+    a.s.hgt = p->hg * p->theta;
+    a.s.inv_De = 1.0 / p->De;
+    a.s.src1 = p->hg * p->theta;
+    a.s.sigma1 = p->sigma1;
+    a.s.sigma2 = p->sigma2;
+    a.s.gamma = p->gamma;
+    a.s.theta = p->theta;
+    a.s.hr = p->hr;
+    return start_adj_go<D, MT, 1>(p, a, pbar);
+  }
+  AdjArgs<MT> a;
+  a.ka = L.ka;
+  a.kb = L.kb;
+  a.Xn = L.Xn;
+  a.Xm = L.Xm;
+  a.Xp = L.Xp;
+  a.Yn = static_cast<const MT*>(L.Yn);
+  a.Ym = static_cast<const MT*>(L.Ym);
+  a.Xb_new = L.Xbar + sp * xs;
+  a.Xb_cur = L.Xbar + sn * xs;
+  a.H1 = Hb + sp * ys;
+  a.H2 = Hb + sn * ys;
+  a.taubar = L.taubar;
+  a.kba = L.kba;
+  a.kbb = L.kbb;
+  a.kb_same = (L.kba != nullptr && L.kba == L.kbb) ? 1 : 0;
+  a.coef = p->d_coef;
+  a.part = p->d_adj_part;
+  a.npts = p->npoints;
+  a.stride = st;
+  a.tile = p->tile;
+  a.m = p->m;
+  a.s.a_diag = p->a_diag;
+  a.s.eta = p->eta;
+  a.s.s_ec = p->s_ec;
+  a.s.inv_De = 1.0 / p->De;
+  a.s.zeta = p->zeta[n + 1];
+  a.s.tau_scale = p->tau_scale;
+  // the zeta gradient of this step goes to pbar[zeta offset + n + 1]
+  return adj_go<D, MT, 1>(p, a, (int64_t)kPbarScalars + 6 * p->m + n + 1, pbar);
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const tfs_plan_s* p, int64_t n, const AdjLevels& L, double* pbar) {
+  if (p->npoints == 0) return hipSuccess;
+  if (p->precision == TFS_FP64)
+    return p->d == 2 ? adj_dispatch<2, double>(p, n, L, pbar) : adj_dispatch<3, double>(p, n, L, pbar);
+  return p->d == 2 ? adj_dispatch<2, float>(p, n, L, pbar) : adj_dispatch<3, float>(p, n, L, pbar);
+}
+
+}  // namespace tfs

@@ -1,0 +1,258 @@
+// Device helpers shared by the forward and adjoint kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "tfs_internal.h"
+
+namespace tfs {
+namespace dev {
+
+// ------------------------------------------------------------------ packed symmetric tensors
+template <int D> struct Sym;
+template <> struct Sym<2> {
+  static constexpr int C = 3;  // (xx, yy, xy)
+  __host__ __device__ static constexpr int i(int s) { return s == 1 ? 1 : 0; }
+  __host__ __device__ static constexpr int j(int s) { return s == 0 ? 0 : 1; }
+};
+template <> struct Sym<3> {
+  static constexpr int C = 6;  // (xx, yy, zz, xy, xz, yz)
+  __host__ __device__ static constexpr int i(int s) { return s < 3 ? s : (s == 5 ? 1 : 0); }
+  __host__ __device__ static constexpr int j(int s) { return s < 3 ? s : (s == 3 ? 1 : 2); }
+};
+
+template <int D>
+__host__ __device__ constexpr int pidx(int a, int b) {
+  for (int s = 0; s < Sym<D>::C; ++s)
+    if ((Sym<D>::i(s) == a && Sym<D>::j(s) == b) || (Sym<D>::i(s) == b && Sym<D>::j(s) == a)) return s;
+  return -1;
+}
+
+// y = kappa x + x kappa^T on packed symmetric x.
+template <int D>
+__device__ __forceinline__ void apply_K(const double (&k)[D * D], const double (&x)[Sym<D>::C],
+                                        double (&y)[Sym<D>::C]) {
+#pragma unroll
+  for (int s = 0; s < Sym<D>::C; ++s) {
+    const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < D; ++l) acc += k[i * D + l] * x[pidx<D>(l, j)] + x[pidx<D>(i, l)] * k[j * D + l];
+    y[s] = acc;
+  }
+}
+
+// M = a I - b K(kappa), the packed matrix of X -> a X - b (kappa X + X kappa^T).
+template <int D>
+__device__ __forceinline__ void build_M(const double (&k)[D * D], double a, double b,
+                                        double (&M)[Sym<D>::C][Sym<D>::C]) {
+  constexpr int C = Sym<D>::C;
+#pragma unroll
+  for (int s = 0; s < C; ++s)
+#pragma unroll
+    for (int t = 0; t < C; ++t) M[s][t] = (s == t) ? a : 0.0;
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+      M[s][pidx<D>(l, j)] -= b * k[i * D + l];
+      M[s][pidx<D>(i, l)] -= b * k[j * D + l];
+    }
+  }
+}
+
+// Solve M x = r in place (r becomes x) by Gaussian elimination with partial pivoting.
+// Row exchanges are selects, so every lane runs the same instruction stream.
+template <int N>
+__device__ __forceinline__ void solve_pivot(double (&M)[N][N], double (&r)[N]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    int p = j;
+    double best = fabs(M[j][j]);
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      const double v = fabs(M[i][j]);
+      const bool gt = v > best;
+      best = gt ? v : best;
+      p = gt ? i : p;
+    }
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      const bool sw = (p == i);
+#pragma unroll
+      for (int q = j; q < N; ++q) {
+        const double t = M[j][q];
+        M[j][q] = sw ? M[i][q] : t;
+        M[i][q] = sw ? t : M[i][q];
+      }
+      const double t = r[j];
+      r[j] = sw ? r[i] : t;
+      r[i] = sw ? t : r[i];
+    }
+    const double inv = 1.0 / M[j][j];
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      const double f = M[i][j] * inv;
+#pragma unroll
+      for (int q = j + 1; q < N; ++q) M[i][q] -= f * M[j][q];
+      r[i] -= f * r[j];
+    }
+  }
+#pragma unroll
+  for (int j = N - 1; j >= 0; --j) {
+    double s = r[j];
+#pragma unroll
+    for (int q = j + 1; q < N; ++q) s -= M[j][q] * r[q];
+    r[j] = s / M[j][j];
+  }
+}
+
+// Error-free accumulation s + e += x (Knuth's TwoSum); contraction must stay off here.
+__device__ __forceinline__ void two_sum_acc(double& s, double& e, double x) {
+#pragma clang fp contract(off)
+  const double t = s + x;
+  const double bp = t - s;
+  e += (s - (t - bp)) + (x - bp);
+  s = t;
+}
+
+__device__ __forceinline__ double mul_rn(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+
+// ------------------------------------------------------------------ vector memory access
+template <typename T, int V> struct VecOf { using type = T __attribute__((ext_vector_type(V))); };
+template <typename T> struct VecOf<T, 1> { using type = T; };
+
+// NT: streaming (non-temporal) access for data touched once per step.
+template <bool FULL, typename T, int V, bool NT = false>
+__device__ __forceinline__ void load_v(const T* __restrict__ p, int nv, T (&o)[V]) {
+  if constexpr (FULL) {
+    if constexpr (V == 1) {
+      o[0] = NT ? __builtin_nontemporal_load(p) : *p;
+    } else {
+      using vt = typename VecOf<T, V>::type;
+      const vt* q = reinterpret_cast<const vt*>(p);
+      const vt v = NT ? __builtin_nontemporal_load(q) : *q;
+#pragma unroll
+      for (int i = 0; i < V; ++i) o[i] = v[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      if (i < nv) o[i] = p[i]; else o[i] = T(0);
+    }
+  }
+}
+
+template <bool FULL, typename T, int V, bool NT = false>
+__device__ __forceinline__ void store_v(T* p, int nv, const T (&x)[V]) {
+  if constexpr (FULL) {
+    if constexpr (V == 1) {
+      if constexpr (NT) __builtin_nontemporal_store(x[0], p); else *p = x[0];
+    } else {
+      using vt = typename VecOf<T, V>::type;
+      vt v;
+#pragma unroll
+      for (int i = 0; i < V; ++i) v[i] = x[i];
+      if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<vt*>(p));
+      else *reinterpret_cast<vt*>(p) = v;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if (i < nv) p[i] = x[i];
+  }
+}
+
+// ------------------------------------------------------------------ diagnostics
+struct DiagAcc {
+  double mn1 = INFINITY, mn2 = INFINITY, mn3 = INFINITY, mx = 0.0, sum = 0.0, cnt = 0.0;
+};
+
+template <int D>
+__device__ __forceinline__ void diag_point(DiagAcc& a, const double (&x)[Sym<D>::C], const double (&t)[Sym<D>::C]) {
+  constexpr int C = Sym<D>::C;
+  double f2 = 0.0, cnt = 0.0;
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    const double w = (s < D) ? 1.0 : 2.0;  // off-diagonal entries appear twice in the full tensor
+    f2 += w * t[s] * t[s];
+    cnt += (isfinite(x[s]) ? 0.0 : 1.0) + (isfinite(t[s]) ? 0.0 : 1.0);
+  }
+  double m1, m2, m3;
+  if constexpr (D == 2) {
+    const double cxx = 1.0 + x[0], cyy = 1.0 + x[1], cxy = x[2];
+    m1 = cxx;
+    m2 = cxx * cyy - cxy * cxy;
+    m3 = m2;
+  } else {
+    const double a00 = 1.0 + x[0], a11 = 1.0 + x[1], a22 = 1.0 + x[2];
+    const double a01 = x[3], a02 = x[4], a12 = x[5];
+    m1 = a00;
+    m2 = a00 * a11 - a01 * a01;
+    m3 = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) + a02 * (a01 * a12 - a11 * a02);
+  }
+  a.mn1 = fmin(a.mn1, m1);
+  a.mn2 = fmin(a.mn2, m2);
+  a.mn3 = fmin(a.mn3, m3);
+  a.mx = fmax(a.mx, sqrt(f2));
+  a.sum += f2;
+  a.cnt += cnt;
+}
+
+__device__ __forceinline__ void diag_combine(DiagAcc& a, const DiagAcc& b) {
+  a.mn1 = fmin(a.mn1, b.mn1);
+  a.mn2 = fmin(a.mn2, b.mn2);
+  a.mn3 = fmin(a.mn3, b.mn3);
+  a.mx = fmax(a.mx, b.mx);
+  a.sum += b.sum;
+  a.cnt += b.cnt;
+}
+
+// Deterministic block reduction: butterfly within each 64-lane wave, then the waves in
+// order through LDS; thread 0 returns the block total.
+__device__ inline DiagAcc block_reduce(DiagAcc a) {
+  __shared__ double sh[kBlock / 64][kNumDiag];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    DiagAcc b;
+    b.mn1 = __shfl_xor(a.mn1, off);
+    b.mn2 = __shfl_xor(a.mn2, off);
+    b.mn3 = __shfl_xor(a.mn3, off);
+    b.mx = __shfl_xor(a.mx, off);
+    b.sum = __shfl_xor(a.sum, off);
+    b.cnt = __shfl_xor(a.cnt, off);
+    diag_combine(a, b);
+  }
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) {
+    sh[wave][0] = a.mn1; sh[wave][1] = a.mn2; sh[wave][2] = a.mn3;
+    sh[wave][3] = a.mx; sh[wave][4] = a.sum; sh[wave][5] = a.cnt;
+  }
+  __syncthreads();
+  DiagAcc r;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < kBlock / 64; ++w) {
+      DiagAcc b;
+      b.mn1 = sh[w][0]; b.mn2 = sh[w][1]; b.mn3 = sh[w][2];
+      b.mx = sh[w][3]; b.sum = sh[w][4]; b.cnt = sh[w][5];
+      diag_combine(r, b);
+    }
+  }
+  return r;
+}
+
+__device__ __forceinline__ void write_partial(double* part, int slot, const DiagAcc& r) {
+  double* o = part + (size_t)slot * kNumDiag;
+  o[0] = r.mn1; o[1] = r.mn2; o[2] = r.mn3; o[3] = r.mx; o[4] = r.sum; o[5] = r.cnt;
+}
+
+
+}  // namespace dev
+}  // namespace tfs

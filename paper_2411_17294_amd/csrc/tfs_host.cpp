@@ -326,6 +326,36 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   p->part_cap = tfs::max_blocks(p);
   e = hipMalloc(&p->d_part, sizeof(double) * tfs::kNumDiag * (size_t)std::max(1, p->part_cap));
   if (e != hipSuccess) { (void)hipFree(p->d_coef); delete p; return fail(TFS_ENOMEM, "diagnostic scratch"); }
+  // adjoint: block partials and the pbar position of every partial entry
+  const int np = 3 * m + tfs::kNumAdjScalars;
+  std::vector<int> dest_b(np, -1), dest_s(np, -1);
+  for (int j = 0; j < 3 * m; ++j) { dest_b[j] = j; dest_s[j] = 3 * m + j; }
+  const int sb = 6 * m;
+  dest_b[3 * m + 0] = sb + tfs::kPbA;
+  dest_b[3 * m + 1] = sb + tfs::kPbEta;
+  dest_b[3 * m + 2] = sb + tfs::kPbS;
+  dest_b[3 * m + 3] = sb + tfs::kPbInvDe;
+  dest_b[3 * m + 4] = sb + tfs::kPbQ;
+  dest_b[3 * m + 5] = -2;  // zeta of this step
+  dest_s[3 * m + 0] = sb + tfs::kPbInvDe;
+  dest_s[3 * m + 1] = sb + tfs::kPbHgt;
+  dest_s[3 * m + 2] = sb + tfs::kPbSrc1;
+  dest_s[3 * m + 3] = sb + tfs::kPbSigma1;
+  dest_s[3 * m + 4] = sb + tfs::kPbSigma2;
+  dest_s[3 * m + 5] = sb + tfs::kPbGamma;
+  dest_s[3 * m + 6] = sb + tfs::kPbTheta;
+  dest_s[3 * m + 7] = sb + tfs::kPbHr;
+  bool ok = hipMalloc(&p->d_adj_part, sizeof(double) * np * (size_t)std::max(1, p->part_cap)) == hipSuccess;
+  ok = ok && hipMalloc(&p->d_dest_bdf2, sizeof(int) * np) == hipSuccess;
+  ok = ok && hipMalloc(&p->d_dest_start, sizeof(int) * np) == hipSuccess;
+  ok = ok && hipMemcpy(p->d_dest_bdf2, dest_b.data(), sizeof(int) * np, hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(p->d_dest_start, dest_s.data(), sizeof(int) * np, hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    (void)hipFree(p->d_coef); (void)hipFree(p->d_part); (void)hipFree(p->d_adj_part);
+    (void)hipFree(p->d_dest_bdf2); (void)hipFree(p->d_dest_start);
+    delete p;
+    return fail(TFS_ENOMEM, "adjoint scratch");
+  }
   *out = p;
   return TFS_OK;
 }
@@ -335,6 +365,9 @@ tfs_status tfs_plan_destroy(tfs_plan p) {
   hipError_t e1 = hipStreamSynchronize(p->stream);
   hipError_t e2 = hipFree(p->d_coef);
   hipError_t e3 = hipFree(p->d_part);
+  (void)hipFree(p->d_adj_part);
+  (void)hipFree(p->d_dest_bdf2);
+  (void)hipFree(p->d_dest_start);
   delete p;
   if (e1 != hipSuccess) return hip_fail(e1, "hipStreamSynchronize");
   if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
@@ -384,14 +417,12 @@ tfs_status tfs_plan_tables(tfs_plan p, double* tables, double* scalars, double* 
   return TFS_OK;
 }
 
-tfs_status tfs_step(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, double* X, void* Y,
+namespace {
+
+tfs_status run_step(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, const tfs::Levels& L,
                     double* tau, double* diag) {
-  if (!p) return fail(TFS_EINVAL, "null plan");
-  if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
-                                              (long long)n, (long long)p->max_steps);
-  if (p->npoints > 0 && (!kappa_a || !X || !Y)) return fail(TFS_EINVAL, "null kappa_a, X or Y");
-  hipError_t e = (n == 0) ? tfs::launch_startup(p, kappa_a, X, Y, tau, diag)
-                          : tfs::launch_bdf2(p, n, kappa_a, kappa_b, X, Y, tau, diag);
+  hipError_t e = (n == 0) ? tfs::launch_startup(p, kappa_a, L, tau, diag)
+                          : tfs::launch_bdf2(p, n, kappa_a, kappa_b, L, tau, diag);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   if (p->flags & TFS_FLAG_CHECK_SYNC) {
     e = hipStreamSynchronize(p->stream);
@@ -405,6 +436,193 @@ tfs_status tfs_step(tfs_plan p, int64_t n, const double* kappa_a, const double* 
         return fail(TFS_ENUMERIC, "conformation not positive definite at level %lld", (long long)(n + 1));
     }
   }
+  return TFS_OK;
+}
+
+}  // namespace
+
+tfs_status tfs_step(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, double* X, void* Y,
+                    double* tau, double* diag) {
+  if (!p) return fail(TFS_EINVAL, "null plan");
+  if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
+                                              (long long)n, (long long)p->max_steps);
+  if (p->npoints > 0 && (!kappa_a || !X || !Y)) return fail(TFS_EINVAL, "null kappa_a, X or Y");
+  const int64_t xs = (int64_t)p->c * p->stride, ys = (int64_t)p->m * p->c * p->stride;
+  const size_t eb = p->precision == TFS_FP64 ? 8 : 4;
+  char* Yb = static_cast<char*>(Y);
+  tfs::Levels L;
+  const int sn = (int)(n % 2), sm = 1 - sn;
+  if (n == 0) {
+    L.Xn = X;
+    L.Xo = X + xs;
+    L.Ym0 = Yb;
+    L.Yo = Yb + ys * eb;
+  } else {
+    L.Xn = X + sn * xs;
+    L.Xm = X + sm * xs;
+    L.Xo = X + sm * xs;
+    L.Yn = Yb + sn * ys * eb;
+    L.Ym = Yb + sm * ys * eb;
+    L.Yo = Yb + sm * ys * eb;
+  }
+  return run_step(p, n, kappa_a, kappa_b, L, tau, diag);
+}
+
+tfs_status tfs_step_levels(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, const double* X_n,
+                           const double* X_nm1, double* X_out, const void* Y_n, void* Y_nm1, void* Y_out,
+                           double* tau, double* diag) {
+  if (!p) return fail(TFS_EINVAL, "null plan");
+  if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
+                                              (long long)n, (long long)p->max_steps);
+  if (p->npoints > 0) {
+    if (!kappa_a || !X_n || !X_out || !Y_nm1 || !Y_out) return fail(TFS_EINVAL, "null kappa_a, X or Y level");
+    if (n > 0 && (!X_nm1 || !Y_n)) return fail(TFS_EINVAL, "null level n or n-1");
+    if (X_out == X_n) return fail(TFS_EINVAL, "X_out must not alias X_n");
+    if (n > 0 && Y_out == Y_n) return fail(TFS_EINVAL, "Y_out must not alias Y_n");
+  }
+  tfs::Levels L;
+  L.Xn = X_n;
+  L.Xo = X_out;
+  if (n == 0) {
+    L.Ym0 = Y_nm1;
+    L.Yo = Y_out;
+  } else {
+    L.Xm = X_nm1;
+    L.Yn = Y_n;
+    L.Ym = Y_nm1;
+    L.Yo = Y_out;
+  }
+  return run_step(p, n, kappa_a, kappa_b, L, tau, diag);
+}
+
+int64_t tfs_pbar_size(tfs_plan p) {
+  return p ? 6 * (int64_t)p->m + tfs::kPbarScalars + p->max_steps + 1 : -1;
+}
+
+tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, const double* X_n,
+                            const double* X_nm1, const double* X_np1, const void* Y_n, const void* Y_nm1,
+                            double* Xbar, void* Hbar, const double* taubar, double* kappabar_a,
+                            double* kappabar_b, double* pbar) {
+  if (!p) return fail(TFS_EINVAL, "null plan");
+  if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
+                                              (long long)n, (long long)p->max_steps);
+  if (!pbar) return fail(TFS_EINVAL, "null pbar");
+  if (p->npoints > 0) {
+    if (!kappa_a || !X_n || !Xbar || !Hbar) return fail(TFS_EINVAL, "null kappa_a, X_n, Xbar or Hbar");
+    if (n > 0 && (!X_nm1 || !X_np1 || !Y_n || !Y_nm1)) return fail(TFS_EINVAL, "null forward level");
+  }
+  tfs::AdjLevels L;
+  L.ka = kappa_a;
+  L.kb = n > 0 ? kappa_b : nullptr;
+  L.Xn = X_n;
+  L.Xm = X_nm1;
+  L.Xp = X_np1;
+  L.Yn = Y_n;
+  L.Ym = Y_nm1;
+  L.Xbar = Xbar;
+  L.Hbar = Hbar;
+  L.taubar = taubar;
+  L.kba = kappabar_a;
+  L.kbb = kappabar_b;
+  hipError_t e = tfs::launch_adjoint(p, n, L, pbar);
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  return TFS_OK;
+}
+
+tfs_status tfs_pbar_to_params(tfs_plan p, const double* pb, double* dw, double* dlam, double* dDe, double* deta_p) {
+  if (!p || !pb) return fail(TFS_EINVAL, "null plan or pbar");
+  const int m = p->m;
+  const double h = p->dt, b0 = tfs::kB0, gs = 1.0 - 1.0 / std::sqrt(2.0), hg = h * gs, hs = h * (1.0 - gs);
+  const double iD = 1.0 / p->De;
+  const double* sc = pb + 6 * m;
+  const double* zb = pb + 6 * m + tfs::kPbarScalars;
+  std::vector<double> wb(m, 0.0), lb(m, 0.0), db(m, 0.0), cb(m, 0.0), ekb(m, 0.0);
+  for (int k = 0; k < m; ++k) {
+    db[k] = pb[k];
+    ekb[k] = pb[2 * m + k];
+    cb[k] = pb[3 * m + k];                // start-up Y^0 = -c X^0
+  }
+  // scalar chain: a = b0 + eta/De, q = gamma/dt, gamma = eta_p/De
+  double etab = sc[tfs::kPbEta] + sc[tfs::kPbA] * iD;
+  double iDb = sc[tfs::kPbInvDe] + sc[tfs::kPbA] * p->eta;
+  const double gammab = sc[tfs::kPbGamma] + sc[tfs::kPbQ] / h;
+  const double eta_pb = gammab * iD;
+  iDb += gammab * p->eta_p;
+  // start-up scalars
+  double thetab = hg * (sc[tfs::kPbHgt] + sc[tfs::kPbSrc1]) + hs * sc[tfs::kPbSigma1] + h * sc[tfs::kPbSigma2] +
+                  sc[tfs::kPbTheta];
+  double rhob = -hs * hg * sc[tfs::kPbSigma1] - hg * hs * sc[tfs::kPbSigma2] + hs * sc[tfs::kPbHr];
+  // mass-mode memory: reverse the mu recurrence driving zeta
+  {
+    const int64_t N = p->max_steps;
+    std::vector<double> mu((size_t)(N + 1) * m, 0.0);
+    for (int k = 0; k < m; ++k) {
+      const double r = 1.0 / (1.0 + hg * p->lam[k]);
+      mu[(size_t)1 * m + k] = (hs * p->w[k] * r + hg * p->w[k]) * r;
+    }
+    for (int64_t n = 1; n < N; ++n)
+      for (int k = 0; k < m; ++k) {
+        const double hh = 2.0 * mu[(size_t)n * m + k] - 0.5 * mu[(size_t)(n - 1) * m + k];
+        mu[(size_t)(n + 1) * m + k] = p->coef[tfs::kRowD * m + k] * hh + p->coef[tfs::kRowC * m + k];
+      }
+    std::vector<double> mub((size_t)(N + 1) * m, 0.0);
+    for (int64_t n = N - 1; n >= 1; --n) {
+      const double zbar = zb[n + 1];
+      etab += zbar;
+      for (int k = 0; k < m; ++k) {
+        const double hh = 2.0 * mu[(size_t)n * m + k] - 0.5 * mu[(size_t)(n - 1) * m + k];
+        const double mup = mub[(size_t)(n + 1) * m + k];
+        db[k] += mup * hh;
+        cb[k] += mup;
+        ekb[k] += -zbar * hh;
+        const double hb = p->coef[tfs::kRowD * m + k] * mup - zbar * p->coef[tfs::kRowEta * m + k];
+        mub[(size_t)n * m + k] += 2.0 * hb;
+        mub[(size_t)(n - 1) * m + k] += -0.5 * hb;
+      }
+    }
+    for (int k = 0; k < m; ++k) {
+      const double w = p->w[k], r = 1.0 / (1.0 + hg * p->lam[k]);
+      const double g = mub[(size_t)1 * m + k];
+      wb[k] += g * (hs * r * r + hg * r);
+      lb[k] += g * (-2.0 * hs * hg * w * r * r * r - hg * hg * w * r * r);
+    }
+  }
+  // per-mode start-up factors theta, rho, u_k, v_k
+  for (int k = 0; k < m; ++k) {
+    const double w = p->w[k], l = p->lam[k], r = 1.0 / (1.0 + hg * l);
+    wb[k] += thetab * r;
+    lb[k] += thetab * w * (-hg * r * r);
+    wb[k] += rhob * l * r * r;
+    lb[k] += rhob * w * r * r * (1.0 - 2.0 * hg * l * r);
+    const double ub = pb[4 * m + k], vb = pb[5 * m + k];
+    wb[k] += ub * hs * r * r;
+    lb[k] += -2.0 * ub * hs * hg * w * r * r * r;
+    wb[k] += vb * hg * r;
+    lb[k] += vb * hg * w * (-hg * r * r);
+    cb[k] += -vb;
+  }
+  // BDF2 factors: eta = sum b0 c_k, s = sum eta_k c_k, e_k = d_k c_k, c_k = w dt d_k,
+  // eta_k = lambda dt d_k, d_k = 1/(b0 + lambda dt)
+  const double sb = sc[tfs::kPbS];
+  for (int k = 0; k < m; ++k) {
+    const double w = p->w[k], l = p->lam[k];
+    const double d = p->coef[tfs::kRowD * m + k], c = p->coef[tfs::kRowC * m + k];
+    const double ek = p->coef[tfs::kRowEta * m + k];
+    double ck = cb[k] + b0 * etab + sb * ek;
+    double ekk = ekb[k] + sb * c;
+    const double eb = pb[m + k];             // d(Y)/d(d_k c_k)
+    double dk = db[k] + eb * c;
+    ck += eb * d;
+    wb[k] += ck * h * d;
+    dk += ck * w * h;
+    lb[k] += ekk * h * d;
+    dk += ekk * l * h;
+    lb[k] += dk * (-h * d * d);
+  }
+  if (dw) for (int k = 0; k < m; ++k) dw[k] = wb[k];
+  if (dlam) for (int k = 0; k < m; ++k) dlam[k] = lb[k];
+  if (dDe) *dDe = -iDb * iD * iD;
+  if (deta_p) *deta_p = eta_pb;
   return TFS_OK;
 }
 

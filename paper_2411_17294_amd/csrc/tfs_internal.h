@@ -34,6 +34,14 @@ constexpr int kBlock = 256;
 // Upper bound of blocks per compute unit of the grid-stride launches (sizes the
 // diagnostic scratch).
 constexpr int kMaxBlocksPerCU = 64;
+// Scalar sums per block of one adjoint launch, and the scalar block of pbar.
+constexpr int kNumAdjScalars = 8;
+constexpr int kPbarScalars = 16;
+// Scalar positions in pbar (after the 6 m per-mode entries).
+enum PbarScalar : int {
+  kPbA = 0, kPbEta = 1, kPbS = 2, kPbInvDe = 3, kPbQ = 4, kPbHgt = 5, kPbSrc1 = 6, kPbSigma1 = 7,
+  kPbSigma2 = 8, kPbGamma = 9, kPbTheta = 10, kPbHr = 11
+};
 
 // Per-step scalars of the BDF2 update, all FP64.
 struct Bdf2Scalars {
@@ -78,6 +86,9 @@ struct tfs_plan_s {
   double* d_coef = nullptr;   // device [kNumCoef][m]
   double* d_part = nullptr;   // device [part_cap][kNumDiag] block partials
   int part_cap = 0;
+  double* d_adj_part = nullptr;  // device [part_cap][3 m + kNumAdjScalars] adjoint block partials
+  int* d_dest_bdf2 = nullptr;    // device [3 m + kNumAdjScalars]: pbar index of each partial entry
+  int* d_dest_start = nullptr;
 
   // tuning (tfs_plan_tune): points per lane (0 = widest aligned), blocks per CU cap
   int vec_override = 0;
@@ -87,11 +98,39 @@ struct tfs_plan_s {
 
 namespace tfs {
 
-// Launchers (tfs_kernels.hip).  They only enqueue work on plan->stream.
-hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, double* X,
-                       void* Y, double* tau, double* diag);
-hipError_t launch_startup(const tfs_plan_s* p, const double* ka, double* X, void* Y, double* tau,
-                          double* diag);
+// Time-level pointers of one step: BDF2 reads (Xn, Xm, Yn, Ym) and writes (Xo, Yo); the
+// start-up reads Xn = X^0 and writes Xo = X^1, Ym0 = Y^0 and Yo = Y^1.
+struct Levels {
+  const double* Xn = nullptr;
+  const double* Xm = nullptr;
+  double* Xo = nullptr;
+  const void* Yn = nullptr;
+  const void* Ym = nullptr;
+  void* Ym0 = nullptr;
+  void* Yo = nullptr;
+};
+
+// Pointers of one adjoint step.
+struct AdjLevels {
+  const double* ka = nullptr;
+  const double* kb = nullptr;
+  const double* Xn = nullptr;   // forward X^n (X^0 at n = 0)
+  const double* Xm = nullptr;   // forward X^{n-1}
+  const double* Xp = nullptr;   // forward X^{n+1}
+  const void* Yn = nullptr;     // forward Y^n
+  const void* Ym = nullptr;     // forward Y^{n-1}
+  double* Xbar = nullptr;       // adjoint ring [2][c][stride]
+  void* Hbar = nullptr;         // mode-adjoint ring, 2 slots
+  const double* taubar = nullptr;
+  double* kba = nullptr;
+  double* kbb = nullptr;
+};
+
+// Launchers (tfs_kernels.hip, tfs_adjoint.hip).  They only enqueue work on plan->stream.
+hipError_t launch_adjoint(const tfs_plan_s* p, int64_t n, const AdjLevels& L, double* pbar);
+hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+                       double* tau, double* diag);
+hipError_t launch_startup(const tfs_plan_s* p, const double* ka, const Levels& L, double* tau, double* diag);
 hipError_t launch_modes_to_plain(const tfs_plan_s* p, int slot, const double* X, const void* Y,
                                  double* Xk);
 // Upper bound of blocks the launchers use for a plan (sizes d_part).

@@ -22,252 +22,12 @@
 #include <cmath>
 #include <cstdint>
 
+#include "tfs_device.h"
 #include "tfs_internal.h"
 
 namespace tfs {
 namespace {
-
-// ------------------------------------------------------------------ packed symmetric tensors
-template <int D> struct Sym;
-template <> struct Sym<2> {
-  static constexpr int C = 3;  // (xx, yy, xy)
-  __host__ __device__ static constexpr int i(int s) { return s == 1 ? 1 : 0; }
-  __host__ __device__ static constexpr int j(int s) { return s == 0 ? 0 : 1; }
-};
-template <> struct Sym<3> {
-  static constexpr int C = 6;  // (xx, yy, zz, xy, xz, yz)
-  __host__ __device__ static constexpr int i(int s) { return s < 3 ? s : (s == 5 ? 1 : 0); }
-  __host__ __device__ static constexpr int j(int s) { return s < 3 ? s : (s == 3 ? 1 : 2); }
-};
-
-template <int D>
-__host__ __device__ constexpr int pidx(int a, int b) {
-  for (int s = 0; s < Sym<D>::C; ++s)
-    if ((Sym<D>::i(s) == a && Sym<D>::j(s) == b) || (Sym<D>::i(s) == b && Sym<D>::j(s) == a)) return s;
-  return -1;
-}
-
-// y = kappa x + x kappa^T on packed symmetric x.
-template <int D>
-__device__ __forceinline__ void apply_K(const double (&k)[D * D], const double (&x)[Sym<D>::C],
-                                        double (&y)[Sym<D>::C]) {
-#pragma unroll
-  for (int s = 0; s < Sym<D>::C; ++s) {
-    const int i = Sym<D>::i(s), j = Sym<D>::j(s);
-    double acc = 0.0;
-#pragma unroll
-    for (int l = 0; l < D; ++l) acc += k[i * D + l] * x[pidx<D>(l, j)] + x[pidx<D>(i, l)] * k[j * D + l];
-    y[s] = acc;
-  }
-}
-
-// M = a I - b K(kappa), the packed matrix of X -> a X - b (kappa X + X kappa^T).
-template <int D>
-__device__ __forceinline__ void build_M(const double (&k)[D * D], double a, double b,
-                                        double (&M)[Sym<D>::C][Sym<D>::C]) {
-  constexpr int C = Sym<D>::C;
-#pragma unroll
-  for (int s = 0; s < C; ++s)
-#pragma unroll
-    for (int t = 0; t < C; ++t) M[s][t] = (s == t) ? a : 0.0;
-#pragma unroll
-  for (int s = 0; s < C; ++s) {
-    const int i = Sym<D>::i(s), j = Sym<D>::j(s);
-#pragma unroll
-    for (int l = 0; l < D; ++l) {
-      M[s][pidx<D>(l, j)] -= b * k[i * D + l];
-      M[s][pidx<D>(i, l)] -= b * k[j * D + l];
-    }
-  }
-}
-
-// Solve M x = r in place (r becomes x) by Gaussian elimination with partial pivoting.
-// Row exchanges are selects, so every lane runs the same instruction stream.
-template <int N>
-__device__ __forceinline__ void solve_pivot(double (&M)[N][N], double (&r)[N]) {
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    int p = j;
-    double best = fabs(M[j][j]);
-#pragma unroll
-    for (int i = j + 1; i < N; ++i) {
-      const double v = fabs(M[i][j]);
-      const bool gt = v > best;
-      best = gt ? v : best;
-      p = gt ? i : p;
-    }
-#pragma unroll
-    for (int i = j + 1; i < N; ++i) {
-      const bool sw = (p == i);
-#pragma unroll
-      for (int q = j; q < N; ++q) {
-        const double t = M[j][q];
-        M[j][q] = sw ? M[i][q] : t;
-        M[i][q] = sw ? t : M[i][q];
-      }
-      const double t = r[j];
-      r[j] = sw ? r[i] : t;
-      r[i] = sw ? t : r[i];
-    }
-    const double inv = 1.0 / M[j][j];
-#pragma unroll
-    for (int i = j + 1; i < N; ++i) {
-      const double f = M[i][j] * inv;
-#pragma unroll
-      for (int q = j + 1; q < N; ++q) M[i][q] -= f * M[j][q];
-      r[i] -= f * r[j];
-    }
-  }
-#pragma unroll
-  for (int j = N - 1; j >= 0; --j) {
-    double s = r[j];
-#pragma unroll
-    for (int q = j + 1; q < N; ++q) s -= M[j][q] * r[q];
-    r[j] = s / M[j][j];
-  }
-}
-
-// Error-free accumulation s + e += x (Knuth's TwoSum); contraction must stay off here.
-__device__ __forceinline__ void two_sum_acc(double& s, double& e, double x) {
-#pragma clang fp contract(off)
-  const double t = s + x;
-  const double bp = t - s;
-  e += (s - (t - bp)) + (x - bp);
-  s = t;
-}
-
-__device__ __forceinline__ double mul_rn(double a, double b) {
-#pragma clang fp contract(off)
-  return a * b;
-}
-
-// ------------------------------------------------------------------ vector memory access
-template <typename T, int V> struct VecOf { using type = T __attribute__((ext_vector_type(V))); };
-template <typename T> struct VecOf<T, 1> { using type = T; };
-
-// NT: streaming (non-temporal) access for data touched once per step.
-template <bool FULL, typename T, int V, bool NT = false>
-__device__ __forceinline__ void load_v(const T* __restrict__ p, int nv, T (&o)[V]) {
-  if constexpr (FULL) {
-    if constexpr (V == 1) {
-      o[0] = NT ? __builtin_nontemporal_load(p) : *p;
-    } else {
-      using vt = typename VecOf<T, V>::type;
-      const vt* q = reinterpret_cast<const vt*>(p);
-      const vt v = NT ? __builtin_nontemporal_load(q) : *q;
-#pragma unroll
-      for (int i = 0; i < V; ++i) o[i] = v[i];
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      if (i < nv) o[i] = p[i]; else o[i] = T(0);
-    }
-  }
-}
-
-template <bool FULL, typename T, int V, bool NT = false>
-__device__ __forceinline__ void store_v(T* p, int nv, const T (&x)[V]) {
-  if constexpr (FULL) {
-    if constexpr (V == 1) {
-      if constexpr (NT) __builtin_nontemporal_store(x[0], p); else *p = x[0];
-    } else {
-      using vt = typename VecOf<T, V>::type;
-      vt v;
-#pragma unroll
-      for (int i = 0; i < V; ++i) v[i] = x[i];
-      if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<vt*>(p));
-      else *reinterpret_cast<vt*>(p) = v;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < V; ++i)
-      if (i < nv) p[i] = x[i];
-  }
-}
-
-// ------------------------------------------------------------------ diagnostics
-struct DiagAcc {
-  double mn1 = INFINITY, mn2 = INFINITY, mn3 = INFINITY, mx = 0.0, sum = 0.0, cnt = 0.0;
-};
-
-template <int D>
-__device__ __forceinline__ void diag_point(DiagAcc& a, const double (&x)[Sym<D>::C], const double (&t)[Sym<D>::C]) {
-  constexpr int C = Sym<D>::C;
-  double f2 = 0.0, cnt = 0.0;
-#pragma unroll
-  for (int s = 0; s < C; ++s) {
-    const double w = (s < D) ? 1.0 : 2.0;  // off-diagonal entries appear twice in the full tensor
-    f2 += w * t[s] * t[s];
-    cnt += (isfinite(x[s]) ? 0.0 : 1.0) + (isfinite(t[s]) ? 0.0 : 1.0);
-  }
-  double m1, m2, m3;
-  if constexpr (D == 2) {
-    const double cxx = 1.0 + x[0], cyy = 1.0 + x[1], cxy = x[2];
-    m1 = cxx;
-    m2 = cxx * cyy - cxy * cxy;
-    m3 = m2;
-  } else {
-    const double a00 = 1.0 + x[0], a11 = 1.0 + x[1], a22 = 1.0 + x[2];
-    const double a01 = x[3], a02 = x[4], a12 = x[5];
-    m1 = a00;
-    m2 = a00 * a11 - a01 * a01;
-    m3 = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) + a02 * (a01 * a12 - a11 * a02);
-  }
-  a.mn1 = fmin(a.mn1, m1);
-  a.mn2 = fmin(a.mn2, m2);
-  a.mn3 = fmin(a.mn3, m3);
-  a.mx = fmax(a.mx, sqrt(f2));
-  a.sum += f2;
-  a.cnt += cnt;
-}
-
-__device__ __forceinline__ void diag_combine(DiagAcc& a, const DiagAcc& b) {
-  a.mn1 = fmin(a.mn1, b.mn1);
-  a.mn2 = fmin(a.mn2, b.mn2);
-  a.mn3 = fmin(a.mn3, b.mn3);
-  a.mx = fmax(a.mx, b.mx);
-  a.sum += b.sum;
-  a.cnt += b.cnt;
-}
-
-// Deterministic block reduction: butterfly within each 64-lane wave, then the waves in
-// order through LDS; thread 0 returns the block total.
-__device__ DiagAcc block_reduce(DiagAcc a) {
-  __shared__ double sh[kBlock / 64][kNumDiag];
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    DiagAcc b;
-    b.mn1 = __shfl_xor(a.mn1, off);
-    b.mn2 = __shfl_xor(a.mn2, off);
-    b.mn3 = __shfl_xor(a.mn3, off);
-    b.mx = __shfl_xor(a.mx, off);
-    b.sum = __shfl_xor(a.sum, off);
-    b.cnt = __shfl_xor(a.cnt, off);
-    diag_combine(a, b);
-  }
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  if (lane == 0) {
-    sh[wave][0] = a.mn1; sh[wave][1] = a.mn2; sh[wave][2] = a.mn3;
-    sh[wave][3] = a.mx; sh[wave][4] = a.sum; sh[wave][5] = a.cnt;
-  }
-  __syncthreads();
-  DiagAcc r;
-  if (threadIdx.x == 0) {
-    for (int w = 0; w < kBlock / 64; ++w) {
-      DiagAcc b;
-      b.mn1 = sh[w][0]; b.mn2 = sh[w][1]; b.mn3 = sh[w][2];
-      b.mx = sh[w][3]; b.sum = sh[w][4]; b.cnt = sh[w][5];
-      diag_combine(r, b);
-    }
-  }
-  return r;
-}
-
-__device__ __forceinline__ void write_partial(double* part, int slot, const DiagAcc& r) {
-  double* o = part + (size_t)slot * kNumDiag;
-  o[0] = r.mn1; o[1] = r.mn2; o[2] = r.mn3; o[3] = r.mx; o[4] = r.sum; o[5] = r.cnt;
-}
+using namespace dev;
 
 // One block folds the block partials in a fixed order.
 __global__ __launch_bounds__(kBlock) void diag_finish_kernel(const double* __restrict__ part, int nparts,
@@ -291,9 +51,11 @@ struct Bdf2Args {
   const double* ka;     // kappa_a [d*d][stride]
   const double* kb;     // kappa_b or null
   const double* Xn;     // X^n      [c][stride]
-  double* Xm;           // X^{n-1} in, X^{n+1} out (same slot)
-  const MT* Yn;         // Y^n slot (m * c * stride elements, tiled)
-  MT* Ym;               // Y^{n-1} in, Y^{n+1} out (same slot)
+  const double* Xm;     // X^{n-1}  [c][stride]
+  double* Xo;           // X^{n+1}  [c][stride] (may be Xm: then each lane reads before it writes)
+  const MT* Yn;         // Y^n      (m * c * stride elements, tiled)
+  const MT* Ym;         // Y^{n-1}
+  MT* Yo;               // Y^{n+1}  (may be Ym, same rule)
   double* tau;          // [c][stride] or null
   const double* coef;   // [kNumCoef][m]
   double* part;         // block partials or null
@@ -330,7 +92,8 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, int64_t p0, in
   const int64_t T = a.tile;
   const int64_t toff = (p0 / T) * (int64_t)m * C * T + (p0 % T);
   const MT* yn0 = a.Yn + toff;
-  MT* ym0 = a.Ym + toff;
+  const MT* ym0 = a.Ym + toff;
+  MT* yo0 = a.Yo + toff;
   MT cn[C][V], cm[C][V];
 #pragma unroll
   for (int s = 0; s < C; ++s) {
@@ -351,7 +114,7 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, int64_t p0, in
         load_v<FULL, MT, V, true>(ym1 + s * T, nv, nm[s]);
       }
     }
-    MT* yo = ym0 + (int64_t)k * C * T;
+    MT* yo = yo0 + (int64_t)k * C * T;
 #pragma unroll
     for (int s = 0; s < C; ++s) {
       MT out[V];
@@ -422,7 +185,7 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, int64_t p0, in
   }
 #pragma unroll
   for (int s = 0; s < C; ++s) {
-    store_v<FULL, double, V>(a.Xm + s * st + p0, nv, Xout[s]);
+    store_v<FULL, double, V>(a.Xo + s * st + p0, nv, Xout[s]);
     if (a.tau) store_v<FULL, double, V>(a.tau + s * st + p0, nv, Tout[s]);
   }
 }
@@ -448,8 +211,10 @@ __global__ __launch_bounds__(kBlock) void bdf2_kernel(const Bdf2Args<MT> a) {
 template <typename MT>
 struct StartArgs {
   const double* ka;  // kappa^0
-  double* X;         // ring [2][c][stride]: reads slot 0, writes slot 1
-  MT* Y;             // ring, 2 slots of m * c * stride elements (tiled): writes both slots
+  const double* X0;  // X^0 [c][stride]
+  double* X1;        // X^1 [c][stride] (out)
+  MT* Y0;            // Y^0 (m * c * stride elements, tiled; out)
+  MT* Y1;            // Y^1 (out)
   double* tau;
   const double* coef;
   double* part;
@@ -465,7 +230,7 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, int64_t p0, 
   const int m = a.m;
   double X0[C][V], X1[C][V], X2[C][V];
 #pragma unroll
-  for (int s = 0; s < C; ++s) load_v<FULL, double, V>(a.X + s * st + p0, nv, X0[s]);
+  for (int s = 0; s < C; ++s) load_v<FULL, double, V>(a.X0 + s * st + p0, nv, X0[s]);
   double kt[D * D][V];
 #pragma unroll
   for (int q = 0; q < D * D; ++q) load_v<FULL, double, V>(a.ka + q * st + p0, nv, kt[q]);
@@ -511,14 +276,14 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, int64_t p0, 
   }
 #pragma unroll
   for (int s = 0; s < C; ++s) {
-    store_v<FULL, double, V>(a.X + (C + s) * st + p0, nv, X2[s]);
+    store_v<FULL, double, V>(a.X1 + s * st + p0, nv, X2[s]);
     if (a.tau) store_v<FULL, double, V>(a.tau + s * st + p0, nv, Tout[s]);
   }
   // modes: Y_k^0 = -c_k X^0 (slot 0), Y_k^1 = u_k X^(1) + v_k X^(2) (slot 1)
   const int64_t T = a.tile;
   const int64_t toff = (p0 / T) * (int64_t)m * C * T + (p0 % T);
-  MT* Y0 = a.Y + toff;
-  MT* Y1 = a.Y + (int64_t)m * C * st + toff;
+  MT* Y0 = a.Y0 + toff;
+  MT* Y1 = a.Y1 + toff;
   for (int k = 0; k < m; ++k) {
     const double ck = a.coef[kRowC * m + k];
     const double uk = a.coef[kRowU * m + k];
@@ -586,8 +351,7 @@ bool aligned(const void* ptr, size_t bytes) { return ptr == nullptr || ((uintptr
 // group start is aligned to the vector size of each field (modes: V * sizeof(MT); FP64
 // fields: V * 8).
 template <int D, typename MT>
-int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const void* X, const void* Y,
-             const void* tau) {
+int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const Levels& L, const void* tau) {
   const int widest = sizeof(MT) == 4 ? 4 : 2;
   const int cand[3] = {widest, 2, 1};
   for (int V : cand) {
@@ -595,7 +359,9 @@ int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const void* X,
     if (p->vec_override && V != p->vec_override) continue;
     if (p->stride % V || p->tile % V) continue;
     const size_t bm = (size_t)V * sizeof(MT), bd = (size_t)V * 8;
-    if (aligned(k0, bd) && aligned(k1, bd) && aligned(X, bd) && aligned(Y, bm) && aligned(tau, bd)) return V;
+    if (aligned(k0, bd) && aligned(k1, bd) && aligned(L.Xn, bd) && aligned(L.Xm, bd) && aligned(L.Xo, bd) &&
+        aligned(L.Yn, bm) && aligned(L.Ym, bm) && aligned(L.Ym0, bm) && aligned(L.Yo, bm) && aligned(tau, bd))
+      return V;
   }
   return 1;
 }
@@ -614,19 +380,18 @@ hipError_t bdf2_go(const tfs_plan_s* p, const Bdf2Args<MT>& a, bool diag, double
 }
 
 template <int D, typename MT>
-hipError_t bdf2_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, double* X, void* Y,
+hipError_t bdf2_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
                          double* tau, double* diag) {
-  constexpr int C = Sym<D>::C;
   const int64_t st = p->stride;
-  const int sn = (int)(n % 2), sm = 1 - sn;
   Bdf2Args<MT> a;
   a.ka = ka;
   a.kb = kb;
-  a.Xn = X + (int64_t)sn * C * st;
-  a.Xm = X + (int64_t)sm * C * st;
-  MT* Yb = static_cast<MT*>(Y);
-  a.Yn = Yb + (int64_t)sn * p->m * C * st;
-  a.Ym = Yb + (int64_t)sm * p->m * C * st;
+  a.Xn = L.Xn;
+  a.Xm = L.Xm;
+  a.Xo = L.Xo;
+  a.Yn = static_cast<const MT*>(L.Yn);
+  a.Ym = static_cast<const MT*>(L.Ym);
+  a.Yo = static_cast<MT*>(L.Yo);
   a.tau = tau;
   a.coef = p->d_coef;
   a.part = p->d_part;
@@ -640,7 +405,7 @@ hipError_t bdf2_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const
   a.s.inv_De = 1.0 / p->De;
   a.s.zeta = p->zeta[n + 1];
   a.s.tau_scale = p->tau_scale;
-  const int V = pick_vec<D, MT>(p, ka, kb, X, Y, tau);
+  const int V = pick_vec<D, MT>(p, ka, kb, L, tau);
   const bool dg = diag != nullptr;
   if constexpr (sizeof(MT) == 4) {
     if (V == 4) return bdf2_go<D, MT, 4>(p, a, dg, diag);
@@ -663,11 +428,13 @@ hipError_t start_go(const tfs_plan_s* p, const StartArgs<MT>& a, bool diag, doub
 }
 
 template <int D, typename MT>
-hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, double* X, void* Y, double* tau, double* diag) {
+hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, const Levels& L, double* tau, double* diag) {
   StartArgs<MT> a;
   a.ka = ka;
-  a.X = X;
-  a.Y = static_cast<MT*>(Y);
+  a.X0 = L.Xn;
+  a.X1 = L.Xo;
+  a.Y0 = static_cast<MT*>(L.Ym0);
+  a.Y1 = static_cast<MT*>(L.Yo);
   a.tau = tau;
   a.coef = p->d_coef;
   a.part = p->d_part;
@@ -683,7 +450,7 @@ hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, double* X, void
   a.s.gamma = p->gamma;
   a.s.theta = p->theta;
   a.s.hr = p->hr;
-  const int V = pick_vec<D, MT>(p, ka, nullptr, X, Y, tau);
+  const int V = pick_vec<D, MT>(p, ka, nullptr, L, tau);
   const bool dg = diag != nullptr;
   if constexpr (sizeof(MT) == 4) {
     if (V == 4) return start_go<D, MT, 4>(p, a, dg, diag);
@@ -696,29 +463,29 @@ hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, double* X, void
 
 int max_blocks(const tfs_plan_s* p) { return p->num_cus * kMaxBlocksPerCU; }
 
-hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, double* X, void* Y,
+hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
                        double* tau, double* diag) {
   if (p->npoints == 0) {
     if (diag) hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, p->d_part, 0, diag);
     return hipGetLastError();
   }
   if (p->precision == TFS_FP64)
-    return p->d == 2 ? bdf2_dispatch<2, double>(p, n, ka, kb, X, Y, tau, diag)
-                     : bdf2_dispatch<3, double>(p, n, ka, kb, X, Y, tau, diag);
-  return p->d == 2 ? bdf2_dispatch<2, float>(p, n, ka, kb, X, Y, tau, diag)
-                   : bdf2_dispatch<3, float>(p, n, ka, kb, X, Y, tau, diag);
+    return p->d == 2 ? bdf2_dispatch<2, double>(p, n, ka, kb, L, tau, diag)
+                     : bdf2_dispatch<3, double>(p, n, ka, kb, L, tau, diag);
+  return p->d == 2 ? bdf2_dispatch<2, float>(p, n, ka, kb, L, tau, diag)
+                   : bdf2_dispatch<3, float>(p, n, ka, kb, L, tau, diag);
 }
 
-hipError_t launch_startup(const tfs_plan_s* p, const double* ka, double* X, void* Y, double* tau, double* diag) {
+hipError_t launch_startup(const tfs_plan_s* p, const double* ka, const Levels& L, double* tau, double* diag) {
   if (p->npoints == 0) {
     if (diag) hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, p->d_part, 0, diag);
     return hipGetLastError();
   }
   if (p->precision == TFS_FP64)
-    return p->d == 2 ? start_dispatch<2, double>(p, ka, X, Y, tau, diag)
-                     : start_dispatch<3, double>(p, ka, X, Y, tau, diag);
-  return p->d == 2 ? start_dispatch<2, float>(p, ka, X, Y, tau, diag)
-                   : start_dispatch<3, float>(p, ka, X, Y, tau, diag);
+    return p->d == 2 ? start_dispatch<2, double>(p, ka, L, tau, diag)
+                     : start_dispatch<3, double>(p, ka, L, tau, diag);
+  return p->d == 2 ? start_dispatch<2, float>(p, ka, L, tau, diag)
+                   : start_dispatch<3, float>(p, ka, L, tau, diag);
 }
 
 hipError_t launch_modes_to_plain(const tfs_plan_s* p, int slot, const double* X, const void* Y, double* Xk) {

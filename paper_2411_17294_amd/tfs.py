@@ -20,7 +20,8 @@ TFS_OK, TFS_EINVAL, TFS_ENOMEM, TFS_EHIP, TFS_ENUMERIC, TFS_EUNSUPPORTED = range
 TFS_FP64, TFS_FP32_MODES = 0, 1
 TFS_FLAG_CHECK_SYNC = 1
 
-EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_step", "tfs_modes_to_plain",
+EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_step", "tfs_step_levels",
+           "tfs_step_adjoint", "tfs_pbar_size", "tfs_pbar_to_params", "tfs_modes_to_plain",
            "tfs_plan_tables", "tfs_plan_stride", "tfs_plan_tile", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
            "tfs_status_string", "tfs_last_error")
 
@@ -61,6 +62,11 @@ def lib():
     L.tfs_plan_destroy.argtypes = [vp]
     L.tfs_plan_set_stream.argtypes = [vp, vp]
     L.tfs_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+    L.tfs_step_levels.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.tfs_step_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.tfs_pbar_size.argtypes = [vp]
+    L.tfs_pbar_size.restype = i64
+    L.tfs_pbar_to_params.argtypes = [vp, dp, dp, dp, dp, dp]
     L.tfs_modes_to_plain.argtypes = [vp, i32, vp, vp, vp]
     L.tfs_plan_tables.argtypes = [vp, dp, dp, dp]
     L.tfs_plan_stride.argtypes = [vp]
@@ -73,7 +79,8 @@ def lib():
     L.tfs_status_string.argtypes = [C.c_int]
     L.tfs_status_string.restype = C.c_char_p
     L.tfs_last_error.restype = C.c_char_p
-    for name in ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_step", "tfs_modes_to_plain",
+    for name in ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_step", "tfs_step_levels",
+                 "tfs_step_adjoint", "tfs_pbar_to_params", "tfs_modes_to_plain",
                  "tfs_plan_tables", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -200,6 +207,53 @@ class Plan:
         self._need(diag, "diag", 6, torch.float64)
         check(lib().tfs_step(self._h, int(n), _tptr(kappa_a), _tptr(kappa_b), _tptr(X), _tptr(Y), _tptr(tau),
                              _tptr(diag)))
+
+    def step_levels(self, n, kappa_a, kappa_b, X_n, X_nm1, X_out, Y_n, Y_nm1, Y_out, tau=None, diag=None):
+        import torch
+        if self.npoints > 0:
+            st, c, d = self.stride, self.c, self.dim
+            for t, nm in ((kappa_a, "kappa_a"), (kappa_b, "kappa_b")):
+                self._need(t, nm, d * d * st, torch.float64)
+            for t, nm in ((X_n, "X_n"), (X_nm1, "X_nm1"), (X_out, "X_out"), (tau, "tau")):
+                self._need(t, nm, c * st, torch.float64)
+            for t, nm in ((Y_n, "Y_n"), (Y_nm1, "Y_nm1"), (Y_out, "Y_out")):
+                self._need(t, nm, self.m * c * st, self.mode_dtype)
+        self._need(diag, "diag", 6, torch.float64)
+        check(lib().tfs_step_levels(self._h, int(n), _tptr(kappa_a), _tptr(kappa_b), _tptr(X_n), _tptr(X_nm1),
+                                    _tptr(X_out), _tptr(Y_n), _tptr(Y_nm1), _tptr(Y_out), _tptr(tau), _tptr(diag)))
+
+    @property
+    def pbar_size(self):
+        return int(lib().tfs_pbar_size(self._h))
+
+    def step_adjoint(self, n, kappa_a, kappa_b, X_n, X_nm1, X_np1, Y_n, Y_nm1, Xbar, Hbar, pbar,
+                     taubar=None, kappabar_a=None, kappabar_b=None):
+        import torch
+        if self.npoints > 0:
+            st, c, d = self.stride, self.c, self.dim
+            for t, nm in ((kappa_a, "kappa_a"), (kappa_b, "kappa_b"), (kappabar_a, "kappabar_a"),
+                          (kappabar_b, "kappabar_b")):
+                self._need(t, nm, d * d * st, torch.float64)
+            for t, nm in ((X_n, "X_n"), (X_nm1, "X_nm1"), (X_np1, "X_np1"), (taubar, "taubar")):
+                self._need(t, nm, c * st, torch.float64)
+            for t, nm in ((Y_n, "Y_n"), (Y_nm1, "Y_nm1")):
+                self._need(t, nm, self.m * c * st, self.mode_dtype)
+            self._need(Xbar, "Xbar", 2 * c * st, torch.float64)
+            self._need(Hbar, "Hbar", 2 * self.m * c * st, self.mode_dtype)
+        self._need(pbar, "pbar", self.pbar_size, torch.float64)
+        check(lib().tfs_step_adjoint(self._h, int(n), _tptr(kappa_a), _tptr(kappa_b), _tptr(X_n), _tptr(X_nm1),
+                                     _tptr(X_np1), _tptr(Y_n), _tptr(Y_nm1), _tptr(Xbar), _tptr(Hbar),
+                                     _tptr(taubar), _tptr(kappabar_a), _tptr(kappabar_b), _tptr(pbar)))
+
+    def pbar_to_params(self, pbar_host):
+        """(dL/dw [m], dL/dlambda [m], dL/dDe, dL/deta_p) from a host copy of pbar."""
+        pb = np.ascontiguousarray(pbar_host, dtype=np.float64)
+        if pb.size < self.pbar_size:
+            raise ValueError("pbar too short")
+        dw, dl = np.zeros(self.m), np.zeros(self.m)
+        dDe, dep = C.c_double(0.0), C.c_double(0.0)
+        check(lib().tfs_pbar_to_params(self._h, _dptr(pb), _dptr(dw), _dptr(dl), C.pointer(dDe), C.pointer(dep)))
+        return dw, dl, dDe.value, dep.value
 
     def modes_to_plain(self, slot, X, Y, out):
         import torch

@@ -1,0 +1,86 @@
+"""Adjoint on the GPU against the oracle's complex-step derivatives (exact to rounding).
+
+Loss: 1/2 sum ||tau^N - tau*||_F^2.  Compared: dL/dkappa (field), dL/dX0 (field), dL/dDe,
+dL/deta_p, dL/dalpha (through the fit's dw/dalpha, dlambda/dalpha at a fixed window) and
+the per-mode dL/dw_k, dL/dlambda_k.  FP64 bar: 1e-9 normwise; FP32-mode bar: 1e-5."""
+import numpy as np
+import pytest
+
+from oracle import soe as osoe
+from paper_2411_17294_amd import inputs as I
+from tests.gpu_helpers import relerr
+from tests.grad_helpers import gpu_gradients, oracle_gradients
+
+pytestmark = pytest.mark.gpu
+
+BAR = {"fp64": 1e-9, "fp32_modes": 1e-5}
+
+
+def setup(d, P, m, seed, alpha=0.45, dt=2e-3, T=0.05):
+    kappa, X0 = I.random_symmetric_case(d, P, seed, kscale=0.7, xscale=2e-2)
+    w, lam, info = osoe.soe_fit(alpha, m, dt, T)
+    _, _, dw, dl = osoe.soe_gl_log(alpha, m, info["y_lo"], info["y_hi"])
+    rng = np.random.default_rng(seed + 1)
+    target = rng.standard_normal((d * (d + 1) // 2, P)) * 1e-3
+    return kappa, X0, w, lam, dw, dl, target
+
+
+def compare(g, o, prec, per_mode=True, label=""):
+    errs = {"kappa": relerr(g["kappa"], o["kappa"]), "X0": relerr(g["X0"], o["X0"]),
+            "De": abs(g["De"] - o["De"]) / abs(o["De"]), "eta_p": abs(g["eta_p"] - o["eta_p"]) / abs(o["eta_p"])}
+    if "alpha" in o:
+        errs["alpha"] = abs(g["alpha"] - o["alpha"]) / abs(o["alpha"])
+    if per_mode and "w" in o:
+        errs["w"] = relerr(g["w"], o["w"])
+        errs["lam"] = relerr(g["lam"], o["lam"])
+    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= BAR[prec]}
+    assert not bad, f"{label}: {bad}"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("P,N", [(1, 1), (5, 2), (37, 12)])
+def test_adjoint_matches_oracle_steady(d, prec, P, N):
+    m = 5
+    kappa, X0, w, lam, dw, dl, target = setup(d, P, m, 300 + 10 * d + P)
+    print(f"adjoint d={d} {prec} P={P} N={N}", flush=True)
+    o = oracle_gradients(d, w, lam, 1.1, 0.1, 2e-3, N, kappa, X0, target, dw_da=dw, dl_da=dl, per_mode=True)
+    g = gpu_gradients(d, w, lam, 0.45, 1.1, 0.1, 2e-3, N, kappa, X0, target, precision=prec, dw_da=dw, dl_da=dl)
+    compare(g, o, prec, label=f"adj d={d} {prec} P={P} N={N}")
+
+
+@pytest.mark.parametrize("extrap", [True, False])
+@pytest.mark.parametrize("d", [2, 3])
+def test_adjoint_time_varying_kappa(d, extrap):
+    P, N, m, dt = 23, 15, 6, 2e-3
+    rng = np.random.default_rng(40 + d)
+    a, b, om = (rng.standard_normal((d * d, P)) * 0.6 for _ in range(3))
+    t = np.arange(N + 1)[:, None, None] * dt
+    kap = np.ascontiguousarray(a[None] + b[None] * np.sin(3.0 * t + om[None]))
+    _, X0, w, lam, dw, dl, target = setup(d, P, m, 60 + d)
+    print(f"adjoint tv d={d} extrap={extrap}", flush=True)
+    o = oracle_gradients(d, w, lam, 0.9, 0.2, dt, N, kap, X0, target, dw_da=dw, dl_da=dl, extrap=extrap)
+    g = gpu_gradients(d, w, lam, 0.45, 0.9, 0.2, dt, N, kap, X0, target, dw_da=dw, dl_da=dl, extrap=extrap)
+    compare(g, o, "fp64", per_mode=False, label=f"adj tv d={d} extrap={extrap}")
+
+
+def test_adjoint_alpha_against_gpu_finite_differences():
+    """Central differences of the GPU forward in alpha (h = 1e-4 relative, the fit refitted at
+    the nominal window) and in De."""
+    d, P, N, m = 3, 200, 20, 8
+    kappa, X0, w, lam, dw, dl, target = setup(d, P, m, 77)
+    alpha, dt, T = 0.45, 2e-3, 0.05
+    _, _, info = osoe.soe_fit(alpha, m, dt, T)
+    g = gpu_gradients(d, w, lam, alpha, 1.1, 0.1, dt, N, kappa, X0, target, dw_da=dw, dl_da=dl)
+
+    def L(al, De):
+        wa, la, _, _ = osoe.soe_gl_log(al, m, info["y_lo"], info["y_hi"])
+        return gpu_gradients(d, wa, la, al, De, 0.1, dt, N, kappa, X0, target)["loss"]
+    h = 1e-4 * alpha
+    fd_a = (L(alpha + h, 1.1) - L(alpha - h, 1.1)) / (2 * h)
+    hD = 1e-4 * 1.1
+    fd_D = (L(alpha, 1.1 + hD) - L(alpha, 1.1 - hD)) / (2 * hD)
+    print("FD alpha", fd_a, g["alpha"], "De", fd_D, g["De"], flush=True)
+    assert abs(fd_a - g["alpha"]) <= 1e-6 * abs(fd_a)
+    assert abs(fd_D - g["De"]) <= 1e-6 * abs(fd_D)
