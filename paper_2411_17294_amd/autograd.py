@@ -1,0 +1,208 @@
+"""Differentiation form: checkpointed forward + adjoint behind torch.autograd.
+
+`fractional_stress(kappa, X0, alpha, De, eta_p, spec)` returns the final stress tau^N
+[c][P] of N time steps and back-propagates dL/dtau^N to the velocity gradient kappa
+(steady, or an additive steady perturbation of a time-varying field), the initial state
+X0, the fractional order alpha, the relaxation time De and eta_p.
+
+alpha enters through the sum-of-exponentials rule at a fixed window (product fitter,
+`tfs_soe_gl_log`), whose dw/dalpha and dlambda/dalpha are exact.  Every step of the
+forward and of the adjoint runs in the library's HIP kernels; this module only
+schedules them and keeps checkpoints:
+
+* forward: the two-slot rings advance N steps; every K steps both ring levels are copied
+  into a checkpoint;
+* backward, segment by segment from the last: restore the checkpoint, recompute the K
+  steps into per-level buffers (tfs_step_levels), then run the adjoint steps back
+  through the segment (tfs_step_adjoint).
+
+Memory: N/K checkpoints of two mode levels plus K+2 mode levels of one segment.
+Points are independent, so `run_slabs` processes a grid in point slabs with the same
+code and sums the parameter gradients.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, Optional
+
+import numpy as np
+import torch
+
+from . import tfs
+
+
+@dataclasses.dataclass
+class Spec:
+    dim: int
+    nmodes: int
+    dt: float
+    nsteps: int
+    y_lo: float                 # sum-of-exponentials window (fixed while differentiating alpha)
+    y_hi: float
+    ckpt_every: int = 50
+    precision: str = "fp32_modes"
+    tile: Optional[int] = None
+    extrap: bool = True
+    # time-varying base field: kappa_levels(n, out) writes level n into out [d*d][stride];
+    # the differentiable kappa input is then an additive steady perturbation
+    kappa_levels: Optional[Callable] = None
+
+
+class Checkpointed:
+    """Forward with checkpoints and the reverse sweep for one set of points."""
+
+    def __init__(self, spec: Spec, npoints: int, alpha: float, De: float, eta_p: float, device="cuda"):
+        self.spec = spec
+        self.P = int(npoints)
+        self.alpha, self.De, self.eta_p = float(alpha), float(De), float(eta_p)
+        w, lam, dw, dl = tfs.soe_gl_log(alpha, spec.nmodes, spec.y_lo, spec.y_hi)
+        self.w, self.lam, self.dw, self.dl = w, lam, dw, dl
+        self.plan = tfs.Plan(spec.dim, self.P, w, lam, alpha, De, eta_p, spec.dt, spec.nsteps,
+                             precision=spec.precision, tile=spec.tile)
+        self.dev = device
+        self.c = spec.dim * (spec.dim + 1) // 2
+        self.st = self.plan.stride
+        self.mt = self.plan.mode_dtype
+        self.ys = self.plan.m * self.c * self.st
+
+    # -- velocity gradient of level n ---------------------------------------------------------
+    def _kappa(self, pert, n, buf):
+        if self.spec.kappa_levels is None:
+            return pert
+        self.spec.kappa_levels(n, buf)
+        buf[:, :self.P] += pert[:, :self.P]
+        return buf
+
+    def _levels(self, pert, n, bufs):
+        """(kappa_a, kappa_b) of step n; bufs is a 2-slot ring of level buffers."""
+        if self.spec.kappa_levels is None:
+            return pert, (pert if self.spec.extrap else None)
+        if self.spec.extrap:
+            ka = self._kappa(pert, n, bufs[n % 2])
+            kb = self._kappa(pert, n - 1, bufs[(n - 1) % 2]) if n >= 1 else None
+            return ka, kb
+        return self._kappa(pert, n + 1, bufs[0]), None
+
+    def forward(self, kappa, X0):
+        """kappa: [d*d][P] FP64 device (steady field, or perturbation); X0: [c][P]. Returns tau^N."""
+        sp, P, st = self.spec, self.P, self.st
+        d2 = sp.dim * sp.dim
+        self.kappa_pad = torch.zeros((d2, st), dtype=torch.float64, device=self.dev)
+        self.kappa_pad[:, :P] = kappa
+        self.kbufs = [torch.zeros((d2, st), dtype=torch.float64, device=self.dev) for _ in range(2)]
+        X = torch.zeros((2, self.c, st), dtype=torch.float64, device=self.dev)
+        X[0, :, :P] = X0
+        Y = torch.zeros((2 * self.ys,), dtype=self.mt, device=self.dev)
+        tau = torch.zeros((self.c, st), dtype=torch.float64, device=self.dev)
+        self.ckpt = {0: (X[0].clone(), None, None, None)}
+        K, N = sp.ckpt_every, sp.nsteps
+        for n in range(N):
+            if n > 0 and n % K == 0:
+                sn, sm = n % 2, (n - 1) % 2
+                self.ckpt[n] = (X[sn].clone(), X[sm].clone(), Y[sn * self.ys:(sn + 1) * self.ys].clone(),
+                                Y[sm * self.ys:(sm + 1) * self.ys].clone())
+            ka, kb = self._levels(self.kappa_pad, n, self.kbufs)
+            self.plan.step(n, ka, kb, X, Y, tau)
+        return tau[:, :P].clone()
+
+    def backward(self, tau_bar):
+        """Returns (dL/dkappa [d*d][P], dL/dX0 [c][P], dL/dalpha, dL/dDe, dL/deta_p)."""
+        sp, P, st, c = self.spec, self.P, self.st, self.c
+        d2 = sp.dim * sp.dim
+        K, N = sp.ckpt_every, sp.nsteps
+        taubar = torch.zeros((c, st), dtype=torch.float64, device=self.dev)
+        taubar[:, :P] = tau_bar
+        Xbar = torch.zeros((2, c, st), dtype=torch.float64, device=self.dev)
+        Hbar = torch.zeros((2 * self.ys,), dtype=self.mt, device=self.dev)
+        pbar = torch.zeros(self.plan.pbar_size, dtype=torch.float64, device=self.dev)
+        kbar = torch.zeros((d2, st), dtype=torch.float64, device=self.dev)
+        starts = sorted(self.ckpt)
+        seg_len = K + 1
+        Xseg = [torch.zeros((c, st), dtype=torch.float64, device=self.dev) for _ in range(seg_len + 1)]
+        Yseg = [torch.zeros((self.ys,), dtype=self.mt, device=self.dev) for _ in range(seg_len + 1)]
+        kb_fwd = [torch.zeros((d2, st), dtype=torch.float64, device=self.dev) for _ in range(2)]
+        kb_adj = [torch.zeros((d2, st), dtype=torch.float64, device=self.dev) for _ in range(2)]
+        tau_tmp = torch.zeros((c, st), dtype=torch.float64, device=self.dev)
+        for s0 in reversed(starts):
+            s1 = min(s0 + K, N)
+            # local index i <-> level s0 - 1 + i: slot 0 = level s0-1, slot 1 = level s0, ...
+            Xc, Xp, Yc, Yp = self.ckpt[s0]
+            Xseg[1].copy_(Xc)
+            if s0 > 0:
+                Xseg[0].copy_(Xp)
+                Yseg[1].copy_(Yc)
+                Yseg[0].copy_(Yp)
+            for n in range(s0, s1):
+                i = n - s0 + 1
+                ka, kb = self._levels(self.kappa_pad, n, kb_fwd)
+                if n == 0:
+                    self.plan.step_levels(0, ka, kb, Xseg[i], None, Xseg[i + 1], None, Yseg[i], Yseg[i + 1], tau_tmp)
+                else:
+                    self.plan.step_levels(n, ka, kb, Xseg[i], Xseg[i - 1], Xseg[i + 1], Yseg[i], Yseg[i - 1],
+                                          Yseg[i + 1], tau_tmp)
+            for n in range(s1 - 1, s0 - 1, -1):
+                i = n - s0 + 1
+                ka, kb = self._levels(self.kappa_pad, n, kb_adj)
+                tb = taubar if n == N - 1 else None
+                if n == 0:
+                    # the start-up wrote level 0 of the modes into Yseg[i]; its adjoint needs X^0 only
+                    self.plan.step_adjoint(0, ka, kb, Xseg[i], None, Xseg[i + 1], None, None, Xbar, Hbar, pbar,
+                                           taubar=tb, kappabar_a=kbar, kappabar_b=kbar)
+                else:
+                    self.plan.step_adjoint(n, ka, kb, Xseg[i], Xseg[i - 1], Xseg[i + 1], Yseg[i], Yseg[i - 1],
+                                           Xbar, Hbar, pbar, taubar=tb, kappabar_a=kbar, kappabar_b=kbar)
+        gw, gl, gDe, gep = self.plan.pbar_to_params(pbar.cpu().numpy())
+        galpha = float(np.dot(gw, self.dw) + np.dot(gl, self.dl))
+        return kbar[:, :P].clone(), Xbar[0, :, :P].clone(), galpha, gDe, gep
+
+    def release(self):
+        self.ckpt = {}
+        self.plan.close()
+
+
+class TfsFunction(torch.autograd.Function):
+    """tau^N = F(kappa, X0, alpha, De, eta_p); see the module docstring."""
+
+    @staticmethod
+    def forward(ctx, kappa, X0, alpha, De, eta_p, spec):
+        run = Checkpointed(spec, X0.shape[1], float(alpha), float(De), float(eta_p), device=X0.device)
+        tau = run.forward(kappa.detach(), X0.detach())
+        ctx.run = run
+        return tau
+
+    @staticmethod
+    def backward(ctx, tau_bar):
+        run = ctx.run
+        gk, gx, ga, gD, ge = run.backward(tau_bar.detach().to(torch.float64).contiguous())
+        run.release()
+        dev, dt = gk.device, torch.float64
+        return gk, gx, torch.tensor(ga, dtype=dt, device=dev), torch.tensor(gD, dtype=dt, device=dev), \
+            torch.tensor(ge, dtype=dt, device=dev), None
+
+
+def fractional_stress(kappa, X0, alpha, De, eta_p, spec: Spec):
+    """Differentiable final stress; alpha, De, eta_p are 0-d tensors (or floats)."""
+    to_t = lambda x: x if torch.is_tensor(x) else torch.tensor(float(x), dtype=torch.float64, device=X0.device)
+    return TfsFunction.apply(kappa, X0, to_t(alpha), to_t(De), to_t(eta_p), spec)
+
+
+def run_slabs(spec: Spec, slabs, alpha, De, eta_p, loss_grad, device="cuda"):
+    """Forward + backward slab by slab (points are independent).
+
+    slabs: iterable of (kappa [d*d][P], X0 [c][P]) device tensors, or callables returning them.
+    loss_grad(tau [c][P], slab_index) -> (loss_value, dL/dtau).
+    Returns dict: loss, alpha, De, eta_p gradients (summed), and per-slab (kappa, X0) gradients
+    if keep_fields."""
+    total = {"loss": 0.0, "alpha": 0.0, "De": 0.0, "eta_p": 0.0}
+    for j, sl in enumerate(slabs):
+        kappa, X0 = sl() if callable(sl) else sl
+        run = Checkpointed(spec, X0.shape[1], alpha, De, eta_p, device=device)
+        tau = run.forward(kappa, X0)
+        lv, tb = loss_grad(tau, j)
+        _, _, ga, gD, ge = run.backward(tb)
+        run.release()
+        total["loss"] += lv
+        total["alpha"] += ga
+        total["De"] += gD
+        total["eta_p"] += ge
+    return total

@@ -1,0 +1,133 @@
+"""Checkpointed forward + adjoint behind torch.autograd (differentiation form)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import soe as osoe
+from paper_2411_17294_amd import inputs as I
+from paper_2411_17294_amd.autograd import Checkpointed, Spec, fractional_stress
+from tests.gpu_helpers import relerr
+from tests.grad_helpers import gpu_gradients, oracle_gradients, pack_weights
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(d, P, seed, m=6, alpha=0.5, dt=2e-3, N=17):
+    kappa, X0 = I.random_symmetric_case(d, P, seed, kscale=0.6, xscale=2e-2)
+    _, _, info = osoe.soe_fit(alpha, m, dt, dt * N)
+    target = np.random.default_rng(seed).standard_normal((d * (d + 1) // 2, P)) * 1e-3
+    return kappa, X0, info, target
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("K", [1, 4, 17, 50])
+def test_checkpointed_equals_uncheckpointed_and_oracle(prec, K):
+    d, P, N, m, alpha, De, eta_p, dt = 3, 41, 17, 6, 0.5, 1.2, 0.1, 2e-3
+    kappa, X0, info, target = _case(d, P, 5, m=m, alpha=alpha, dt=dt, N=N)
+    spec = Spec(dim=d, nmodes=m, dt=dt, nsteps=N, y_lo=info["y_lo"], y_hi=info["y_hi"], ckpt_every=K,
+                precision=prec)
+    kt = torch.from_numpy(kappa).cuda().requires_grad_(True)
+    xt = torch.from_numpy(X0).cuda().requires_grad_(True)
+    at = torch.tensor(alpha, dtype=torch.float64, device="cuda", requires_grad=True)
+    Dt = torch.tensor(De, dtype=torch.float64, device="cuda", requires_grad=True)
+    et = torch.tensor(eta_p, dtype=torch.float64, device="cuda", requires_grad=True)
+    tau = fractional_stress(kt, xt, at, Dt, et, spec)
+    wts = torch.from_numpy(pack_weights(d)[:, None]).cuda()
+    L = 0.5 * torch.sum(wts * (tau - torch.from_numpy(target).cuda()) ** 2)
+    L.backward()
+    w, lam, dw, dl = osoe.soe_gl_log(alpha, m, info["y_lo"], info["y_hi"])
+    ref = gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precision=prec, dw_da=dw, dl_da=dl)
+    ek = relerr(kt.grad.cpu().numpy(), ref["kappa"])
+    ex = relerr(xt.grad.cpu().numpy(), ref["X0"])
+    print(f"checkpointed K={K} {prec}: kappa {ek:.2e} X0 {ex:.2e}", flush=True)
+    assert ek < 1e-13 and ex < 1e-13
+    assert at.grad.item() == pytest.approx(ref["alpha"], rel=1e-13)
+    assert Dt.grad.item() == pytest.approx(ref["De"], rel=1e-13)
+    assert et.grad.item() == pytest.approx(ref["eta_p"], rel=1e-13)
+    if prec == "fp64" and K == 4:
+        o = oracle_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, dw_da=dw, dl_da=dl)
+        assert relerr(kt.grad.cpu().numpy(), o["kappa"]) < 1e-9
+        assert relerr(xt.grad.cpu().numpy(), o["X0"]) < 1e-9
+        assert abs(at.grad.item() - o["alpha"]) < 1e-9 * abs(o["alpha"])
+        assert abs(Dt.grad.item() - o["De"]) < 1e-9 * abs(o["De"])
+
+
+def test_time_varying_perturbation_gradient():
+    """kappa^n = f(t_n) + p with p the differentiable steady perturbation."""
+    d, P, N, m, dt = 2, 30, 12, 5, 2e-3
+    rng = np.random.default_rng(9)
+    a, b, om = (rng.standard_normal((d * d, P)) * 0.5 for _ in range(3))
+    levels = np.stack([a + b * np.sin(4.0 * n * dt + om) for n in range(N + 1)])
+    _, X0, info, target = _case(d, P, 11, m=m, dt=dt, N=N)
+    lev_t = torch.from_numpy(levels).cuda()
+
+    def kappa_levels(n, out):
+        out.zero_()
+        out[:, :P] = lev_t[n]
+    spec = Spec(dim=d, nmodes=m, dt=dt, nsteps=N, y_lo=info["y_lo"], y_hi=info["y_hi"], ckpt_every=5,
+                precision="fp64", kappa_levels=kappa_levels)
+    pert = torch.zeros((d * d, P), dtype=torch.float64, device="cuda", requires_grad=True)
+    xt = torch.from_numpy(X0).cuda()
+    tau = fractional_stress(pert, xt, 0.5, 1.0, 0.1, spec)
+    wts = torch.from_numpy(pack_weights(d)[:, None]).cuda()
+    L = 0.5 * torch.sum(wts * (tau - torch.from_numpy(target).cuda()) ** 2)
+    L.backward()
+    w, lam, dw, dl = osoe.soe_gl_log(0.5, m, info["y_lo"], info["y_hi"])
+    o = oracle_gradients(d, w, lam, 1.0, 0.1, dt, N, levels, X0, target)
+    assert relerr(pert.grad.cpu().numpy(), o["kappa"]) < 1e-9
+
+
+def test_workload_128cube_differentiation():
+    """128^3, FP32 modes, alpha = 0.6, m = 32, 400 steps, dt = 2.5e-4, checkpoints every 50.
+    Loss: misfit of tau^N against a target made with alpha = 0.55 and De * 1.05 (same kappa,
+    X0 and fit window).  Checked: dL/dalpha and dL/dDe against central differences of the
+    GPU forward (h = 1e-4 relative); dL/dkappa and dL/dX0 on the strided 16^3 subset against
+    the oracle's complex-step derivatives of that subset's loss."""
+    from paper_2411_17294_amd.device_inputs import DeviceKappa
+    wl = I.WORKLOADS[4]
+    alpha, N, m, dt = wl.alphas[0], wl.nsteps, wl.nmodes, wl.dt
+    _, _, info = osoe.soe_fit(alpha, m, dt, dt * N)
+    ff = I.fourier_field(wl)
+    P = wl.npoints
+    kd = torch.zeros((9, P), dtype=torch.float64, device="cuda")
+    DeviceKappa(ff, wl.grid, P).fill(kd, 0.0)
+    X0 = torch.from_numpy(I.initial_state(wl)).cuda()
+    spec = Spec(dim=3, nmodes=m, dt=dt, nsteps=N, y_lo=info["y_lo"], y_hi=info["y_hi"],
+                ckpt_every=wl.ckpt_every, precision="fp32_modes")
+
+    def fwd(al, De):
+        r = Checkpointed(spec, P, al, De, wl.eta_p)
+        t = r.forward(kd, X0)
+        r.release()
+        return t
+    target = fwd(wl.target_alpha, wl.De * wl.target_De_factor)
+    wts = torch.from_numpy(pack_weights(3)[:, None]).cuda()
+    lossf = lambda t: 0.5 * float(torch.sum(wts * (t - target) ** 2))
+    run = Checkpointed(spec, P, alpha, wl.De, wl.eta_p)
+    tau = run.forward(kd, X0)
+    L0 = lossf(tau)
+    gk, gx, ga, gD, ge = run.backward(wts * (tau - target))
+    run.release()
+    torch.cuda.synchronize()
+    ha, hD = 1e-4 * alpha, 1e-4 * wl.De
+    fd_a = (lossf(fwd(alpha + ha, wl.De)) - lossf(fwd(alpha - ha, wl.De))) / (2 * ha)
+    fd_D = (lossf(fwd(alpha, wl.De + hD)) - lossf(fwd(alpha, wl.De - hD))) / (2 * hD)
+    print(f"128^3: L={L0:.6e} dL/dalpha adj {ga:.10e} fd {fd_a:.10e}; dL/dDe adj {gD:.10e} fd {fd_D:.10e}",
+          flush=True)
+    # FP32 mode storage: the finite difference of the FP32-mode forward resolves ~1e-5
+    assert abs(ga - fd_a) <= 1e-4 * abs(fd_a)
+    assert abs(gD - fd_D) <= 1e-4 * abs(fd_D)
+    # fields on the subset, against the oracle (each point's gradient depends on that point only)
+    sub = I.subdomain_points(wl)
+    subt = torch.from_numpy(sub).cuda()
+    w, lam, dw, dl = osoe.soe_gl_log(alpha, m, info["y_lo"], info["y_hi"])
+    kap_s = kd[:, subt].cpu().numpy()
+    X0_s = X0[:, subt].cpu().numpy()
+    tgt_s = target[:, subt].cpu().numpy()
+    o = oracle_gradients(3, w, lam, wl.De, wl.eta_p, dt, N, kap_s, X0_s, tgt_s)
+    ek = relerr(gk[:, subt].cpu().numpy(), o["kappa"])
+    ex = relerr(gx[:, subt].cpu().numpy(), o["X0"])
+    print(f"128^3 subset: dL/dkappa rel err {ek:.2e}, dL/dX0 rel err {ex:.2e}", flush=True)
+    assert ek < 1e-5 and ex < 1e-5
