@@ -61,11 +61,12 @@ typedef struct tfs_plan_s* tfs_plan;
 
 typedef struct {
     int32_t dim;          /* 2 or 3 */
-    int32_t nmodes;       /* m >= 1 exponential modes */
+    int32_t nmodes;       /* 1 <= m <= 256 exponential modes */
     int64_t npoints;      /* points updated by each call (>= 0) */
     int64_t stride;       /* plane stride in elements; 0 means npoints rounded up to a multiple of tile;
                              must be >= npoints and, with tile > 0, a multiple of tile */
-    int64_t tile;         /* mode-ring tile in points: 0 (untiled) or a positive multiple of 4 */
+    int64_t tile;         /* mode-ring tile in points: 0 (untiled) or a positive multiple of 4; with
+                             more than one tile, (tile + 256) * m * c * 8 must stay below 2^31 */
     double alpha;         /* fractional order in (0, 1]; kept for reporting and gradients */
     double De;            /* relaxation time (Deborah/Weissenberg number) > 0 */
     double eta_p;         /* polymer viscosity (1-beta)/Re >= 0; gamma = eta_p/De (Sec. 1, Kramers) */
@@ -217,6 +218,7 @@ int64_t tfs_plan_tile(tfs_plan plan);
  *   "vec"          points per lane: 0 = widest width the alignment of the fields allows
  *                  (default), or 1, 2 (and 4 for TFS_FP32_MODES); a width the alignment
  *                  does not allow falls back to 1 at launch.
+ *   "adj_vec"      points per lane of the BDF2 adjoint: 0 (default, 1), 1 or 2.
  *   "grid_per_cu"  cap on blocks per compute unit of the grid-stride launches, 1..64.
  * Note: the diagnostic sum's rounding order depends on the grid; results of X, tau, Y do not.
  */

@@ -32,6 +32,31 @@ __device__ __forceinline__ void build_K(const double (&k)[D * D], double (&Km)[S
   build_M<D>(k, 0.0, -1.0, Km);
 }
 
+// u = K(kappa)^T v on packed tensors: u . z = v . packed(kappa Z + Z kappa^T) for every
+// symmetric Z.  With V the symmetric matrix of packed v (v/2 off the diagonal) that inner
+// product is <kappa^T V + V kappa, Z>, so u is that matrix packed with its off-diagonal
+// entries counted twice.
+template <int D>
+__device__ __forceinline__ void apply_KT(const double (&k)[D * D], const double (&v)[Sym<D>::C],
+                                         double (&u)[Sym<D>::C]) {
+  constexpr int C = Sym<D>::C;
+  double Vm[D][D];
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+    const double hv = (i == j) ? v[s] : 0.5 * v[s];
+    Vm[i][j] = hv; Vm[j][i] = hv;
+  }
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < D; ++l) acc += k[l * D + i] * Vm[l][j] + Vm[i][l] * k[l * D + j];
+    u[s] = (i == j) ? acc : 2.0 * acc;
+  }
+}
+
 // kb += f * 2 V Z, V the symmetric matrix of packed v (v/2 off the diagonal), Z symmetric packed.
 template <int D>
 __device__ __forceinline__ void kgrad_VZ(double (&kb)[D * D], double f, const double (&v)[Sym<D>::C],
@@ -96,6 +121,33 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// v moved across lanes by the DPP pattern CTRL (a permutation inside each row of 16 lanes).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave (every lane active), the same on every lane and in a
+// fixed order: butterflies inside each row of 16 lanes (DPP: swap neighbours, swap pairs,
+// rotate by 4, rotate by 8), then the four row sums in row order.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm(1,0,3,2)
+  v += dpp_mov<0x4E>(v);    // quad_perm(2,3,0,1)
+  v += dpp_mov<0x124>(v);   // row_ror:4
+  v += dpp_mov<0x128>(v);   // row_ror:8
+  return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
+}
+
 // Block partial: the per-mode sums (3 rows of m, accumulated per wave in LDS) and the
 // per-lane scalar sums, folded over the block in a fixed order and written to part[block].
 __device__ inline void write_block_partial(double* __restrict__ part, int m, const double* smode,
@@ -142,260 +194,266 @@ struct AdjArgs {
   double* kbb;           // kappa_b adjoint (+=) or null
   int kb_same;           // kba == kbb
   const double* coef;
-  double* part;
-  int64_t npts, stride, tile;
-  int m;
+  double* part;          // block partials: this launch writes part[part0 + block]
+  int64_t p_begin;       // first point of this launch
+  int64_t ngroups;       // groups of V points from p_begin
+  int64_t stride, tile;
+  int m, part0;
   Bdf2Scalars s;
 };
 
+// Per-lane values kept in LDS across the mode stream (they are needed again after it):
+// Rbar (c values) and the kappa~ adjoint of the local part (d*d values), per point.
+template <int D>
+struct AdjSlots {
+  static constexpr int N = Sym<D>::C + D * D;
+};
+
 template <int D, typename MT, int V, bool FULL>
-__device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, int64_t p0, int nv, double* smode,
-                                          double (&sc)[kNumAdjScalars]) {
+__device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& w, int nv, double* smode,
+                                          double* slot, double (&sc)[kNumAdjScalars]) {
   constexpr int C = Sym<D>::C;
+  constexpr int NS = AdjSlots<D>::N;
   const int64_t st = a.stride;
   const int m = a.m;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  auto lds = [&](int v, int j) -> double& { return slot[(v * NS + j) * kBlock + threadIdx.x]; };
+  const double q = a.s.tau_scale, eta = a.s.eta;
 
-  double P[C][V], Gb[C][V], Pb[C][V], AGb[C][V], tb[C][V], kbar[D * D][V], kt[D * D][V];
-  // forward per-point quantities and the local reverse pass up to Gbar
+  // ---- local part, point by point: Rbar = M^{-T} Xbar and everything that needs kappa~
+  double Gb[C][V], Pb[C][V];
+  {
+    double kt[D * D][V], Xp[C][V], Xbn[C][V], tb[C][V];
 #pragma unroll
-  for (int q = 0; q < D * D; ++q) {
-    double x[V];
-    load_v<FULL, double, V>(a.ka + q * st + p0, nv, x);
-    if (a.kb) {
-      double y[V];
-      load_v<FULL, double, V>(a.kb + q * st + p0, nv, y);
+    for (int t = 0; t < D * D; ++t) {
+      double x[V];
+      load_v<FULL, double, V>(at(a.ka + t * st + w.pw, w.ox), nv, x);
+      if (a.kb) {
+        double y[V];
+        load_v<FULL, double, V>(at(a.kb + t * st + w.pw, w.ox), nv, y);
 #pragma unroll
-      for (int v = 0; v < V; ++v) kt[q][v] = 2.0 * x[v] - y[v];
-    } else {
+        for (int v = 0; v < V; ++v) kt[t][v] = 2.0 * x[v] - y[v];
+      } else {
 #pragma unroll
-      for (int v = 0; v < V; ++v) kt[q][v] = x[v];
+        for (int v = 0; v < V; ++v) kt[t][v] = x[v];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      load_v<FULL, double, V>(at(a.Xp + s * st + w.pw, w.ox), nv, Xp[s]);
+      load_v<FULL, double, V>(at(a.Xb_new + s * st + w.pw, w.ox), nv, Xbn[s]);
+      if (a.taubar) load_v<FULL, double, V>(at(a.taubar + s * st + w.pw, w.ox), nv, tb[s]);
+      else
+#pragma unroll
+        for (int v = 0; v < V; ++v) tb[s][v] = 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      double k[D * D], xp[C], rb[C], tv[C], S[C];
+#pragma unroll
+      for (int t = 0; t < D * D; ++t) k[t] = kt[t][v];
+#pragma unroll
+      for (int s = 0; s < C; ++s) {
+        xp[s] = Xp[s][v];
+        tv[s] = tb[s][v];
+        rb[s] = Xbn[s][v] + q * eta * tv[s];        // tau = q (eta X+ - G)
+        const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+        S[s] = k[i * D + j] + k[j * D + i];
+      }
+      sc[1] += q * dot<C>(tv, xp);                  // d tau / d eta (X+ part)
+      sc[4] += eta * dot<C>(tv, xp);                // d tau / d q (X+ part; the G part follows the modes)
+      {
+        double M[C][C];
+        build_M<D>(k, a.s.a_diag, eta, M);
+        solve_transposed<C>(M, rb);                 // Rbar = M^{-T} Xbar
+      }
+      double Kx[C];
+      apply_K<D>(k, xp, Kx);
+      sc[0] += -dot<C>(rb, xp);                     // a
+      sc[1] += dot<C>(rb, Kx);                      // eta (matrix)
+      sc[5] += dot<C>(rb, S);                       // zeta
+      double kb_[D * D];
+#pragma unroll
+      for (int t = 0; t < D * D; ++t) kb_[t] = 0.0;
+      kgrad_VZ<D>(kb_, eta, rb, xp);                // M = a I - eta K(kappa)
+      kgrad_V<D>(kb_, a.s.zeta, rb);                // R = ... + zeta S
+      // A(G) = K G - G/De with AGbar = -Rbar:  Gbar = K^T AGbar - AGbar/De - q taubar
+      double u[C];
+      apply_KT<D>(k, rb, u);
+#pragma unroll
+      for (int t = 0; t < C; ++t) {
+        Gb[t][v] = -u[t] + a.s.inv_De * rb[t] - q * tv[t];
+        Pb[t][v] = rb[t] + a.s.s_ec * Gb[t][v];     // P enters R directly and through G = G^ + s P
+      }
+#pragma unroll
+      for (int s = 0; s < C; ++s) lds(v, s) = rb[s];
+#pragma unroll
+      for (int t = 0; t < D * D; ++t) lds(v, C + t) = kb_[t];
     }
   }
-  double Xp[C][V], Xbn[C][V];
+
+  double P[C][V];
 #pragma unroll
   for (int s = 0; s < C; ++s) {
     double xn[V], xm[V];
-    load_v<FULL, double, V>(a.Xn + s * st + p0, nv, xn);
-    load_v<FULL, double, V>(a.Xm + s * st + p0, nv, xm);
-    load_v<FULL, double, V>(a.Xp + s * st + p0, nv, Xp[s]);
-    load_v<FULL, double, V>(a.Xb_new + s * st + p0, nv, Xbn[s]);
-    if (a.taubar) load_v<FULL, double, V>(a.taubar + s * st + p0, nv, tb[s]);
+    load_v<FULL, double, V>(at(a.Xn + s * st + w.pw, w.ox), nv, xn);
+    load_v<FULL, double, V>(at(a.Xm + s * st + w.pw, w.ox), nv, xm);
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      P[s][v] = 2.0 * xn[v] - 0.5 * xm[v];
-      if (!a.taubar) tb[s][v] = 0.0;
-    }
+    for (int v = 0; v < V; ++v) P[s][v] = 2.0 * xn[v] - 0.5 * xm[v];
   }
-  const double q = a.s.tau_scale, eta = a.s.eta;
+  {
+    double g = 0.0;
 #pragma unroll
-  for (int v = 0; v < V; ++v) {
-    if (!(FULL || v < nv)) {
+    for (int s = 0; s < C; ++s)
 #pragma unroll
-      for (int s = 0; s < C; ++s) { Gb[s][v] = 0.0; Pb[s][v] = 0.0; AGb[s][v] = 0.0; tb[s][v] = 0.0; }
-#pragma unroll
-      for (int t = 0; t < D * D; ++t) kbar[t][v] = 0.0;
-      continue;
-    }
-    double k[D * D], xb[C], xp[C], rb[C], M[C][C], Kx[C], S[C];
-#pragma unroll
-    for (int t = 0; t < D * D; ++t) { k[t] = kt[t][v]; kbar[t][v] = 0.0; }
-#pragma unroll
-    for (int s = 0; s < C; ++s) {
-      xp[s] = Xp[s][v];
-      xb[s] = Xbn[s][v] + q * eta * tb[s][v];     // tau = q (eta X+ - G)
-      rb[s] = xb[s];
-      const int i = Sym<D>::i(s), j = Sym<D>::j(s);
-      S[s] = k[i * D + j] + k[j * D + i];
-    }
-    {
-      double tv[C];
-#pragma unroll
-      for (int s = 0; s < C; ++s) tv[s] = tb[s][v];
-      sc[1] += q * dot<C>(tv, xp);                  // d tau / d eta (X+ part)
-      sc[4] += eta * dot<C>(tv, xp);                // d tau / d q (X+ part; the G part follows the modes)
-    }
-    build_M<D>(k, a.s.a_diag, eta, M);
-    solve_transposed<C>(M, rb);                     // Rbar = M^{-T} Xbar
-    apply_K<D>(k, xp, Kx);
-    sc[0] += -dot<C>(rb, xp);                       // a
-    sc[1] += dot<C>(rb, Kx);                        // eta (matrix)
-    double kb_[D * D];
-#pragma unroll
-    for (int t = 0; t < D * D; ++t) kb_[t] = 0.0;
-    kgrad_VZ<D>(kb_, eta, rb, xp);                  // M = a I - eta K(kappa)
-    sc[5] += dot<C>(rb, S);                         // zeta
-    kgrad_V<D>(kb_, a.s.zeta, rb);                  // R = ... + zeta S
-    // A(G) = K G - G/De with AGbar = -Rbar:  Gbar = K^T AGbar - AGbar/De - q taubar
-    double Km[C][C];
-    build_K<D>(k, Km);
-#pragma unroll
-    for (int t = 0; t < C; ++t) {
-      double acc = 0.0;
-#pragma unroll
-      for (int s = 0; s < C; ++s) acc += Km[s][t] * (-rb[s]);
-      Gb[t][v] = acc + a.s.inv_De * rb[t] - q * tb[t][v];
-      AGb[t][v] = -rb[t];
-      Pb[t][v] = rb[t];
-    }
-    double pv[C], gbv[C];
-#pragma unroll
-    for (int s = 0; s < C; ++s) { pv[s] = P[s][v]; gbv[s] = Gb[s][v]; }
-    sc[2] += dot<C>(gbv, pv);                       // G = G^ + s P
-#pragma unroll
-    for (int s = 0; s < C; ++s) Pb[s][v] += a.s.s_ec * Gb[s][v];
-#pragma unroll
-    for (int t = 0; t < D * D; ++t) kbar[t][v] = kb_[t];
+      for (int v = 0; v < V; ++v) g += Gb[s][v] * P[s][v];
+    sc[2] += g;                                     // G = G^ + s P
   }
 
-  // transposed mode recurrence, streaming
+  // ---- transposed mode recurrence, streaming
   const int64_t T = a.tile;
-  const int64_t toff = (p0 / T) * (int64_t)m * C * T + (p0 % T);
-  const MT* h1p = a.H1 + toff;
-  MT* h2p = a.H2 + toff;
-  const MT* ynp = a.Yn + toff;
-  const MT* ymp = a.Ym + toff;
+  const MT* h1p = a.H1 + w.tw;
+  MT* h2p = a.H2 + w.tw;
+  const MT* ynp = a.Yn + w.tw;
+  const MT* ymp = a.Ym + w.tw;
   double Gh[C][V];
 #pragma unroll
   for (int s = 0; s < C; ++s)
 #pragma unroll
     for (int v = 0; v < V; ++v) Gh[s][v] = 0.0;
-  MT c1[C][V], c2[C][V], cn[C][V], cm[C][V];
-#pragma unroll
-  for (int s = 0; s < C; ++s) {
-    load_v<FULL, MT, V, true>(h1p + s * T, nv, c1[s]);
-    load_v<FULL, MT, V, true>(h2p + s * T, nv, c2[s]);
-    load_v<FULL, MT, V, true>(ynp + s * T, nv, cn[s]);
-    load_v<FULL, MT, V, true>(ymp + s * T, nv, cm[s]);
-  }
   for (int k = 0; k < m; ++k) {
     const double dk = a.coef[kRowD * m + k];
     const double ek = a.coef[kRowDC * m + k];
     const double hk = a.coef[kRowEta * m + k];
-    MT n1[C][V], n2[C][V], nn[C][V], nm[C][V];
-    if (k + 1 < m) {
-      const int64_t o = (int64_t)(k + 1) * C * T;
-#pragma unroll
-      for (int s = 0; s < C; ++s) {
-        load_v<FULL, MT, V, true>(h1p + o + s * T, nv, n1[s]);
-        load_v<FULL, MT, V, true>(h2p + o + s * T, nv, n2[s]);
-        load_v<FULL, MT, V, true>(ynp + o + s * T, nv, nn[s]);
-        load_v<FULL, MT, V, true>(ymp + o + s * T, nv, nm[s]);
-      }
-    }
-    double ad = 0.0, ae = 0.0, ah = 0.0;
-    MT* out = h2p + (int64_t)k * C * T;
+    MT c1[C][V], c2[C][V], cn[C][V], cm[C][V];
+    const int64_t o = (int64_t)k * C * T;
+    const uint32_t om = opaque(w.om);
+    const MT* b1 = opaque_ptr(h1p + o);
+    MT* b2 = opaque_ptr(h2p + o);
+    const MT* bn = opaque_ptr(ynp + o);
+    const MT* bm = opaque_ptr(ymp + o);
 #pragma unroll
     for (int s = 0; s < C; ++s) {
-      MT w[V];
+      load_v<FULL, MT, V, true>(at(b1 + s * T, om), nv, c1[s]);
+      load_v<FULL, MT, V, true>(at(b2 + s * T, om), nv, c2[s]);
+      load_v<FULL, MT, V, true>(at(bn + s * T, om), nv, cn[s]);
+      load_v<FULL, MT, V, true>(at(bm + s * T, om), nv, cm[s]);
+    }
+    double ad = 0.0, ae = 0.0, ah = 0.0;
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      MT hv[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        const double yb = 2.0 * (double)c1[s][v] - 0.5 * (double)c2[s][v];   // Ybar_k^{n+1}
-        const double hh = 2.0 * (double)cn[s][v] - 0.5 * (double)cm[s][v];  // forward h^_k
+        const double yb = 2.0 * (double)c1[s][v] - 0.5 * (double)c2[s][v];
+        const double hh = 2.0 * (double)cn[s][v] - 0.5 * (double)cm[s][v];
         Gh[s][v] += hk * hh;
-        w[v] = (MT)(dk * yb + hk * Gb[s][v]);
+        hv[v] = (MT)(dk * yb + hk * Gb[s][v]);
         Pb[s][v] += ek * yb;
         ad += yb * hh;
         ae += yb * P[s][v];
         ah += Gb[s][v] * hh;
       }
-      store_v<FULL, MT, V, true>(out + s * T, nv, w);
+      store_v<FULL, MT, V, true>(at(b2 + s * T, om), nv, hv);
     }
-    ad = wave_sum(ad);
-    ae = wave_sum(ae);
-    ah = wave_sum(ah);
+    ad = wave_total(ad);
+    ae = wave_total(ae);
+    ah = wave_total(ah);
     if (lane == 0) {
       smode[wave * 3 * m + k] += ad;
       smode[wave * 3 * m + m + k] += ae;
       smode[wave * 3 * m + 2 * m + k] += ah;
     }
-    if (k + 1 < m) {
-#pragma unroll
-      for (int s = 0; s < C; ++s)
-#pragma unroll
-        for (int v = 0; v < V; ++v) { c1[s][v] = n1[s][v]; c2[s][v] = n2[s][v]; cn[s][v] = nn[s][v]; cm[s][v] = nm[s][v]; }
-    }
   }
 
-  // terms that need G = G^ + s P
-  double Xcur[C][V], Xnew[C][V];
-#pragma unroll
-  for (int s = 0; s < C; ++s) load_v<FULL, double, V>(a.Xb_cur + s * st + p0, nv, Xcur[s]);
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    double G[C], agb[C], tv[C], k[D * D];
+  // ---- terms that need G = G^ + s P, the X adjoints and the kappa adjoints
+  double kbar[D * D][V];
+  {
+    double tb[C][V];
 #pragma unroll
     for (int s = 0; s < C; ++s) {
-      G[s] = Gh[s][v] + a.s.s_ec * P[s][v];
-      agb[s] = AGb[s][v];
-      tv[s] = tb[s][v];
+      if (a.taubar) load_v<FULL, double, V>(at(a.taubar + s * st + w.pw, w.ox), nv, tb[s]);
+      else
+#pragma unroll
+        for (int v = 0; v < V; ++v) tb[s][v] = 0.0;
     }
 #pragma unroll
-    for (int t = 0; t < D * D; ++t) k[t] = kbar[t][v];
-    if (FULL || v < nv) {
-      sc[3] += -dot<C>(agb, G);                     // 1/De
+    for (int v = 0; v < V; ++v) {
+      double G[C], rb[C], tv[C], kb_[D * D];
+#pragma unroll
+      for (int s = 0; s < C; ++s) {
+        G[s] = Gh[s][v] + a.s.s_ec * P[s][v];
+        rb[s] = lds(v, s);
+        tv[s] = tb[s][v];
+      }
+#pragma unroll
+      for (int t = 0; t < D * D; ++t) kb_[t] = lds(v, C + t);
+      sc[3] += dot<C>(rb, G);                       // 1/De (AGbar = -Rbar)
       sc[4] += -dot<C>(tv, G);                      // q (G part)
-      kgrad_VZ<D>(k, 1.0, agb, G);                  // A(G) = K(kappa) G - G/De
-    }
+      kgrad_VZ<D>(kb_, -1.0, rb, G);                // A(G) = K(kappa) G - G/De
 #pragma unroll
-    for (int t = 0; t < D * D; ++t) kbar[t][v] = k[t];
-#pragma unroll
-    for (int s = 0; s < C; ++s) {
-      Xcur[s][v] += 2.0 * Pb[s][v];                 // P = 2 X^n - X^{n-1}/2
-      Xnew[s][v] = -0.5 * Pb[s][v];
+      for (int t = 0; t < D * D; ++t) kbar[t][v] = kb_[t];
     }
   }
 #pragma unroll
   for (int s = 0; s < C; ++s) {
-    store_v<FULL, double, V>(a.Xb_cur + s * st + p0, nv, Xcur[s]);
-    store_v<FULL, double, V>(a.Xb_new + s * st + p0, nv, Xnew[s]);
+    double xc[V], xw[V];
+    load_v<FULL, double, V>(at(a.Xb_cur + s * st + w.pw, w.ox), nv, xc);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      xc[v] += 2.0 * Pb[s][v];                      // P = 2 X^n - X^{n-1}/2
+      xw[v] = -0.5 * Pb[s][v];
+    }
+    store_v<FULL, double, V>(at(a.Xb_cur + s * st + w.pw, w.ox), nv, xc);
+    store_v<FULL, double, V>(at(a.Xb_new + s * st + w.pw, w.ox), nv, xw);
   }
   // kappa adjoints: kappa~ = 2 kappa_a - kappa_b, or kappa_a
+  double fa = 1.0, fb = 0.0;
+  if (a.kb && !a.kb_same) { fa = 2.0; fb = -1.0; }
 #pragma unroll
   for (int t = 0; t < D * D; ++t) {
-    double fa, fb;
-    if (!a.kb) { fa = 1.0; fb = 0.0; }
-    else if (a.kb_same) { fa = 1.0; fb = 0.0; }
-    else { fa = 2.0; fb = -1.0; }
     if (a.kba) {
       double x[V];
-      load_v<FULL, double, V>(a.kba + t * st + p0, nv, x);
+      load_v<FULL, double, V>(at(a.kba + t * st + w.pw, w.ox), nv, x);
 #pragma unroll
       for (int v = 0; v < V; ++v) x[v] += fa * kbar[t][v];
-      store_v<FULL, double, V>(a.kba + t * st + p0, nv, x);
+      store_v<FULL, double, V>(at(a.kba + t * st + w.pw, w.ox), nv, x);
     }
     if (a.kbb && fb != 0.0) {
       double x[V];
-      load_v<FULL, double, V>(a.kbb + t * st + p0, nv, x);
+      load_v<FULL, double, V>(at(a.kbb + t * st + w.pw, w.ox), nv, x);
 #pragma unroll
       for (int v = 0; v < V; ++v) x[v] += fb * kbar[t][v];
-      store_v<FULL, double, V>(a.kbb + t * st + p0, nv, x);
+      store_v<FULL, double, V>(at(a.kbb + t * st + w.pw, w.ox), nv, x);
     }
   }
 }
 
-template <int D, typename MT, int V>
+// FULL: whole waves of V-point groups (ngroups a multiple of 64).  !FULL (V = 1): the
+// points after the last whole wave; lanes past the end run an empty group, since the wave
+// reductions need all 64 lanes.
+template <int D, typename MT, int V, bool FULL>
 __global__ __launch_bounds__(kBlock) void adj_kernel(const AdjArgs<MT> a) {
-  extern __shared__ double smode[];   // [kBlock/64][3][m]
+  constexpr int C = Sym<D>::C;
+  extern __shared__ double smem[];    // [kBlock/64][3][m] mode sums, then the lane slots
+  double* smode = smem;
+  double* slot = smem + (kBlock / 64) * 3 * a.m;
   for (int j = threadIdx.x; j < (kBlock / 64) * 3 * a.m; j += kBlock) smode[j] = 0.0;
   __syncthreads();
   double sc[kNumAdjScalars];
 #pragma unroll
   for (int i = 0; i < kNumAdjScalars; ++i) sc[i] = 0.0;
-  const int64_t ngroups = (a.npts + V - 1) / V;
-  const int64_t gstride = (int64_t)gridDim.x * kBlock;
-  // every lane of a wave iterates the same number of times (the wave reductions need
-  // all 64 lanes), lanes past the end run a masked empty group
-  for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x - (threadIdx.x % 64); g < ngroups; g += gstride) {
-    const int64_t mine = g + (threadIdx.x % 64);
-    const int64_t p0 = mine * V;
-    int nv = (int)((a.npts - p0) < V ? (a.npts - p0) : V);
-    if (mine >= ngroups) nv = 0;
-    if (nv == V) adj_group<D, MT, V, true>(a, p0, nv, smode, sc);
-    else adj_group<D, MT, V, false>(a, nv > 0 ? p0 : 0, nv, smode, sc);
+  const int lane = threadIdx.x % 64;
+  const int64_t nwaves = (a.ngroups + 63) / 64;
+  const int64_t wstride = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
+       wv += wstride) {
+    const WaveAddr w = wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m);
+    const int nv = (FULL || wv * 64 + lane < a.ngroups) ? V : 0;
+    adj_group<D, MT, V, FULL>(a, w, nv, smode, slot, sc);
   }
   __syncthreads();
-  write_block_partial(a.part, a.m, smode, sc);
+  write_block_partial(a.part + (size_t)a.part0 * (3 * a.m + kNumAdjScalars), a.m, smode, sc);
 }
 
 // ------------------------------------------------------------------ start-up adjoint
@@ -648,14 +706,35 @@ int grid_adj(const tfs_plan_s* p, int64_t ngroups) {
   return (int)g;
 }
 
+size_t adj_shared_bytes(const tfs_plan_s* p, int V) {
+  const int ns = p->d == 2 ? AdjSlots<2>::N : AdjSlots<3>::N;
+  return sizeof(double) * ((size_t)(kBlock / 64) * 3 * p->m + (size_t)ns * V * kBlock);
+}
+
+// Whole waves of V-point groups with the V-wide kernel, the remaining points (fewer than
+// 64 V) with the masked V = 1 kernel; one finisher folds the block partials of both.
 template <int D, typename MT, int V>
-hipError_t adj_go(const tfs_plan_s* p, const AdjArgs<MT>& a, int64_t zeta_dest, double* pbar) {
-  const int64_t ngroups = (a.npts + V - 1) / V;
-  const int grid = grid_adj(p, ngroups);
-  const size_t shm = sizeof(double) * (kBlock / 64) * 3 * p->m;
-  hipLaunchKernelGGL((adj_kernel<D, MT, V>), dim3(grid), dim3(kBlock), shm, p->stream, a);
+hipError_t adj_go(const tfs_plan_s* p, AdjArgs<MT> a, int64_t zeta_dest, double* pbar) {
+  const int64_t nwaves = p->npoints / (64 * V);
+  const int64_t p_tail = nwaves * 64 * V, rest = p->npoints - p_tail;
+  int nb = 0, nt = 0;
+  if (nwaves > 0) {
+    a.p_begin = 0;
+    a.ngroups = nwaves * 64;
+    a.part0 = 0;
+    nb = grid_adj(p, a.ngroups);
+    hipLaunchKernelGGL((adj_kernel<D, MT, V, true>), dim3(nb), dim3(kBlock), adj_shared_bytes(p, V), p->stream, a);
+  }
+  if (rest > 0) {
+    a.p_begin = p_tail;
+    a.ngroups = rest;
+    a.part0 = nb;
+    nt = grid_adj(p, rest);
+    hipLaunchKernelGGL((adj_kernel<D, MT, 1, false>), dim3(nt), dim3(kBlock), adj_shared_bytes(p, 1), p->stream,
+                       a);
+  }
   const int np = 3 * p->m + kNumAdjScalars;
-  hipLaunchKernelGGL(adj_finish_kernel, dim3(np), dim3(kBlock), 0, p->stream, a.part, grid, np,
+  hipLaunchKernelGGL(adj_finish_kernel, dim3(np), dim3(kBlock), 0, p->stream, a.part, nb + nt, np,
                      p->d_dest_bdf2, zeta_dest, pbar);
   return hipGetLastError();
 }
@@ -670,6 +749,22 @@ hipError_t start_adj_go(const tfs_plan_s* p, const StartAdjArgs<MT>& a, double* 
   hipLaunchKernelGGL(adj_finish_kernel, dim3(np), dim3(kBlock), 0, p->stream, a.part, grid, np,
                      p->d_dest_start, (int64_t)-1, pbar);
   return hipGetLastError();
+}
+
+bool al(const void* ptr, size_t b) { return ptr == nullptr || ((uintptr_t)ptr % b) == 0; }
+
+// Points per lane of the BDF2 adjoint: the "adj_vec" tuning (0 = default 1), if every field
+// is aligned for it and its LDS slots fit in 64 KB per block.
+template <typename MT>
+int adj_vec(const tfs_plan_s* p, const AdjLevels& L) {
+  const int V = p->adj_vec_override == 2 ? 2 : 1;
+  if (V == 1) return 1;
+  if (p->stride % V || p->tile % V || adj_shared_bytes(p, V) > 65536) return 1;
+  const size_t bm = (size_t)V * sizeof(MT), bd = (size_t)V * 8;
+  if (al(L.ka, bd) && al(L.kb, bd) && al(L.Xn, bd) && al(L.Xm, bd) && al(L.Xp, bd) && al(L.Xbar, bd) &&
+      al(L.taubar, bd) && al(L.kba, bd) && al(L.kbb, bd) && al(L.Yn, bm) && al(L.Ym, bm) && al(L.Hbar, bm))
+    return V;
+  return 1;
 }
 
 template <int D, typename MT>
@@ -723,7 +818,6 @@ hipError_t adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, doub
   a.kb_same = (L.kba != nullptr && L.kba == L.kbb) ? 1 : 0;
   a.coef = p->d_coef;
   a.part = p->d_adj_part;
-  a.npts = p->npoints;
   a.stride = st;
   a.tile = p->tile;
   a.m = p->m;
@@ -734,7 +828,9 @@ hipError_t adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, doub
   a.s.zeta = p->zeta[n + 1];
   a.s.tau_scale = p->tau_scale;
   // the zeta gradient of this step goes to pbar[zeta offset + n + 1]
-  return adj_go<D, MT, 1>(p, a, (int64_t)kPbarScalars + 6 * p->m + n + 1, pbar);
+  const int64_t zd = (int64_t)kPbarScalars + 6 * p->m + n + 1;
+  if (adj_vec<MT>(p, L) == 2) return adj_go<D, MT, 2>(p, a, zd, pbar);
+  return adj_go<D, MT, 1>(p, a, zd, pbar);
 }
 
 }  // namespace

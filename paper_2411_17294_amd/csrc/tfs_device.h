@@ -125,6 +125,65 @@ __device__ __forceinline__ double mul_rn(double a, double b) {
   return a * b;
 }
 
+// ------------------------------------------------------------------ wave-uniform addressing
+// A wave handles 64 consecutive groups of V points.  Every access is a wave-uniform base
+// (kept in scalar registers) plus a 32-bit per-lane byte offset, one per layout, instead
+// of a 64-bit vector address per plane and mode.
+
+// x is equal on all lanes; make that visible to the compiler.
+__device__ __forceinline__ int64_t wave_uniform(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename T>
+__device__ __forceinline__ const T* at(const T* base, uint32_t byte_off) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ T* at(T* base, uint32_t byte_off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
+// Where a wave's points live.  Mode element (k, s) of the lane's first point is
+// base + tw + (k C + s) T elements + om bytes; a plain field element is base + pw + ox bytes.
+struct WaveAddr {
+  int64_t pw;    // first point of the wave
+  int64_t tw;    // its element offset in the tiled mode layout (tile base + offset in tile)
+  uint32_t ox;   // lane's byte offset from pw in a plain FP64 field
+  uint32_t om;   // lane's byte offset from tw in the mode layout
+};
+
+// Returns x unchanged, but the compiler can no longer treat it as loop-invariant: keeps
+// "uniform base + per-lane offset" address sums inside a loop (one offset register)
+// instead of hoisting a 64-bit per-lane address per plane out of it.
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// The same for a wave-uniform pointer: keeps base + (k C + s) T sums inside the mode loop
+// (a few scalar adds per access) instead of one hoisted scalar pair per plane.
+template <typename T>
+__device__ __forceinline__ T* opaque_ptr(T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// Tiled mode layout: [tile][m][c][T], point p at element (p / T) m c T + p % T of (0, 0).
+template <typename MT, int C, int V>
+__device__ __forceinline__ WaveAddr wave_addr(int64_t pw, int lane, int64_t T, int m) {
+  WaveAddr w;
+  const int64_t mcT = (int64_t)m * C * T;
+  const int64_t p = pw + (int64_t)lane * V;
+  w.pw = pw;
+  w.tw = (pw / T) * mcT + pw % T;
+  w.ox = (uint32_t)(lane * V * 8);
+  w.om = (uint32_t)(((p / T) * mcT + p % T - w.tw) * (int64_t)sizeof(MT));
+  return w;
+}
+
 // ------------------------------------------------------------------ vector memory access
 template <typename T, int V> struct VecOf { using type = T __attribute__((ext_vector_type(V))); };
 template <typename T> struct VecOf<T, 1> { using type = T; };

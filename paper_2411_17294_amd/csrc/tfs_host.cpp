@@ -219,13 +219,20 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   if (!desc) return fail(TFS_EINVAL, "null descriptor");
   const tfs_plan_desc& D = *desc;
   if (D.dim != 2 && D.dim != 3) return fail(TFS_EINVAL, "dim must be 2 or 3 (got %d)", D.dim);
-  if (D.nmodes < 1) return fail(TFS_EINVAL, "nmodes must be >= 1");
+  if (D.nmodes < 1 || D.nmodes > tfs::kMaxModes)
+    return fail(TFS_EINVAL, "nmodes must be in [1, %d]", tfs::kMaxModes);
   if (D.npoints < 0) return fail(TFS_EINVAL, "npoints must be >= 0");
   if (D.tile < 0 || D.tile % 4 != 0) return fail(TFS_EINVAL, "tile must be 0 or a positive multiple of 4");
   int64_t stride = D.stride;
   if (stride == 0) stride = D.tile > 0 ? (D.npoints + D.tile - 1) / D.tile * D.tile : D.npoints;
   if (stride < D.npoints) return fail(TFS_EINVAL, "stride must be >= npoints");
   if (D.tile > 0 && stride % D.tile != 0) return fail(TFS_EINVAL, "stride must be a multiple of tile");
+  if (D.tile > 0 && D.tile < stride) {
+    // lanes address the mode layout by 32-bit byte offsets from their wave's first point,
+    // which may lie one tile earlier
+    const double span = ((double)D.nmodes * (D.dim * (D.dim + 1) / 2) * (double)(D.tile + 256) + 256.0) * 8.0;
+    if (span >= 2147483648.0) return fail(TFS_EINVAL, "tile too large for nmodes (tile * nmodes * c * 8 >= 2^31)");
+  }
   if (!(D.alpha > 0.0 && D.alpha <= 1.0)) return fail(TFS_EINVAL, "alpha must be in (0, 1]");
   if (!(D.De > 0.0) || !std::isfinite(D.De)) return fail(TFS_EINVAL, "De must be > 0");
   if (!(D.eta_p >= 0.0) || !std::isfinite(D.eta_p)) return fail(TFS_EINVAL, "eta_p must be >= 0");
@@ -391,6 +398,11 @@ tfs_status tfs_plan_tune(tfs_plan p, const char* key, int64_t value) {
     const bool ok = value == 0 || value == 1 || value == 2 || (value == 4 && p->precision == TFS_FP32_MODES);
     if (!ok) return fail(TFS_EINVAL, "vec must be 0, 1, 2 (or 4 for FP32 modes)");
     p->vec_override = (int)value;
+    return TFS_OK;
+  }
+  if (std::strcmp(key, "adj_vec") == 0) {
+    if (value < 0 || value > 2) return fail(TFS_EINVAL, "adj_vec must be 0, 1 or 2");
+    p->adj_vec_override = (int)value;
     return TFS_OK;
   }
   if (std::strcmp(key, "grid_per_cu") == 0) {

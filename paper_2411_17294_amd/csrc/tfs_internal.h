@@ -30,6 +30,8 @@ enum CoefRow : int {
 // Number of diagnostics written per step.
 constexpr int kNumDiag = 6;
 // Threads per block of every streaming kernel.
+// Largest number of sum-of-exponentials modes of a plan (bounds the adjoint LDS use).
+constexpr int kMaxModes = 256;
 constexpr int kBlock = 256;
 // Upper bound of blocks per compute unit of the grid-stride launches (sizes the
 // diagnostic scratch).
@@ -92,6 +94,7 @@ struct tfs_plan_s {
 
   // tuning (tfs_plan_tune): points per lane (0 = widest aligned), blocks per CU cap
   int vec_override = 0;
+  int adj_vec_override = 0;
   int grid_per_cu = 16;
   int num_cus = 256;
 };

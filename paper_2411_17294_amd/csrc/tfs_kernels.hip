@@ -58,25 +58,28 @@ struct Bdf2Args {
   MT* Yo;               // Y^{n+1}  (may be Ym, same rule)
   double* tau;          // [c][stride] or null
   const double* coef;   // [kNumCoef][m]
-  double* part;         // block partials or null
-  int64_t npts, stride, tile;
-  int m;
+  double* part;         // block partials or null (this launch writes part[part0 + block])
+  int64_t p_begin;      // first point of this launch
+  int64_t ngroups;      // groups of V points from p_begin
+  int64_t stride, tile;
+  int m, part0;
   Bdf2Scalars s;
 };
 
-template <int D, typename MT, int V, bool FULL, bool DIAG>
-__device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, int64_t p0, int nv, DiagAcc& acc) {
+template <int D, typename MT, int V, bool DIAG>
+__device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr& w, DiagAcc& acc) {
   constexpr int C = Sym<D>::C;
   const int64_t st = a.stride;
   const int m = a.m;
+  const int64_t T = a.tile;
 
   // P = 2 X^n - X^{n-1}/2
   double P[C][V];
 #pragma unroll
   for (int s = 0; s < C; ++s) {
     double xn[V], xm[V];
-    load_v<FULL, double, V>(a.Xn + s * st + p0, nv, xn);
-    load_v<FULL, double, V>(a.Xm + s * st + p0, nv, xm);
+    load_v<true, double, V>(at(a.Xn + s * st + w.pw, w.ox), V, xn);
+    load_v<true, double, V>(at(a.Xm + s * st + w.pw, w.ox), V, xm);
 #pragma unroll
     for (int v = 0; v < V; ++v) P[s][v] = 2.0 * xn[v] - 0.5 * xm[v];
   }
@@ -88,17 +91,14 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, int64_t p0, in
 #pragma unroll
     for (int v = 0; v < V; ++v) { Gs[s][v] = 0.0; Ge[s][v] = 0.0; }
 
-  // mode (k, s) of the group: tile base + (k C + s) T
-  const int64_t T = a.tile;
-  const int64_t toff = (p0 / T) * (int64_t)m * C * T + (p0 % T);
-  const MT* yn0 = a.Yn + toff;
-  const MT* ym0 = a.Ym + toff;
-  MT* yo0 = a.Yo + toff;
+  const MT* yn0 = a.Yn + w.tw;
+  const MT* ym0 = a.Ym + w.tw;
+  MT* yo0 = a.Yo + w.tw;
   MT cn[C][V], cm[C][V];
 #pragma unroll
   for (int s = 0; s < C; ++s) {
-    load_v<FULL, MT, V, true>(yn0 + s * T, nv, cn[s]);
-    load_v<FULL, MT, V, true>(ym0 + s * T, nv, cm[s]);
+    load_v<true, MT, V, true>(at(yn0 + s * T, w.om), V, cn[s]);
+    load_v<true, MT, V, true>(at(ym0 + s * T, w.om), V, cm[s]);
   }
   for (int k = 0; k < m; ++k) {
     const double dk = a.coef[kRowD * m + k];
@@ -106,15 +106,16 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, int64_t p0, in
     const double ek = a.coef[kRowEta * m + k];
     MT nn[C][V], nm[C][V];
     if (k + 1 < m) {
-      const MT* yn1 = yn0 + (int64_t)(k + 1) * C * T;
-      const MT* ym1 = ym0 + (int64_t)(k + 1) * C * T;
+      const int64_t o = (int64_t)(k + 1) * C * T;
+      const uint32_t om = opaque(w.om);
 #pragma unroll
       for (int s = 0; s < C; ++s) {
-        load_v<FULL, MT, V, true>(yn1 + s * T, nv, nn[s]);
-        load_v<FULL, MT, V, true>(ym1 + s * T, nv, nm[s]);
+        load_v<true, MT, V, true>(at(yn0 + o + s * T, om), V, nn[s]);
+        load_v<true, MT, V, true>(at(ym0 + o + s * T, om), V, nm[s]);
       }
     }
     MT* yo = yo0 + (int64_t)k * C * T;
+    const uint32_t om = opaque(w.om);
 #pragma unroll
     for (int s = 0; s < C; ++s) {
       MT out[V];
@@ -124,7 +125,7 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, int64_t p0, in
         out[v] = (MT)(dk * h + dck * P[s][v]);
         two_sum_acc(Gs[s][v], Ge[s][v], mul_rn(ek, h));
       }
-      store_v<FULL, MT, V, true>(yo + s * T, nv, out);
+      store_v<true, MT, V, true>(at(yo + s * T, om), V, out);
     }
     if (k + 1 < m) {
 #pragma unroll
@@ -139,10 +140,10 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, int64_t p0, in
 #pragma unroll
   for (int q = 0; q < D * D; ++q) {
     double ka[V];
-    load_v<FULL, double, V>(a.ka + q * st + p0, nv, ka);
+    load_v<true, double, V>(at(a.ka + q * st + w.pw, w.ox), V, ka);
     if (a.kb) {
       double kb[V];
-      load_v<FULL, double, V>(a.kb + q * st + p0, nv, kb);
+      load_v<true, double, V>(at(a.kb + q * st + w.pw, w.ox), V, kb);
 #pragma unroll
       for (int v = 0; v < V; ++v) kt[q][v] = 2.0 * ka[v] - kb[v];
     } else {
@@ -175,35 +176,36 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, int64_t p0, in
       Tout[s][v] = a.s.tau_scale * (a.s.eta * R[s] - G[s]);
     }
     if constexpr (DIAG) {
-      if (FULL || v < nv) {
-        double xs[C], ts[C];
+      double xs[C], ts[C];
 #pragma unroll
-        for (int s = 0; s < C; ++s) { xs[s] = Xout[s][v]; ts[s] = Tout[s][v]; }
-        diag_point<D>(acc, xs, ts);
-      }
+      for (int s = 0; s < C; ++s) { xs[s] = Xout[s][v]; ts[s] = Tout[s][v]; }
+      diag_point<D>(acc, xs, ts);
     }
   }
 #pragma unroll
   for (int s = 0; s < C; ++s) {
-    store_v<FULL, double, V>(a.Xo + s * st + p0, nv, Xout[s]);
-    if (a.tau) store_v<FULL, double, V>(a.tau + s * st + p0, nv, Tout[s]);
+    store_v<true, double, V>(at(a.Xo + s * st + w.pw, w.ox), V, Xout[s]);
+    if (a.tau) store_v<true, double, V>(at(a.tau + s * st + w.pw, w.ox), V, Tout[s]);
   }
 }
 
+// Groups [0, ngroups) of V points from p_begin, 64 consecutive groups per wave; the
+// caller launches a V = 1 pass for the points after the last whole group.
 template <int D, typename MT, int V, bool DIAG>
 __global__ __launch_bounds__(kBlock) void bdf2_kernel(const Bdf2Args<MT> a) {
+  constexpr int C = Sym<D>::C;
   DiagAcc acc;
-  const int64_t ngroups = (a.npts + V - 1) / V;
-  const int64_t gstride = (int64_t)gridDim.x * kBlock;
-  for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < ngroups; g += gstride) {
-    const int64_t p0 = g * V;
-    const int nv = (int)((a.npts - p0) < V ? (a.npts - p0) : V);
-    if (nv == V) bdf2_group<D, MT, V, true, DIAG>(a, p0, nv, acc);
-    else bdf2_group<D, MT, V, false, DIAG>(a, p0, nv, acc);
+  const int lane = threadIdx.x % 64;
+  const int64_t nwaves = (a.ngroups + 63) / 64;
+  const int64_t wstride = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
+       wv += wstride) {
+    if (wv * 64 + lane < a.ngroups)
+      bdf2_group<D, MT, V, DIAG>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
   }
   if constexpr (DIAG) {
     const DiagAcc r = block_reduce(acc);
-    if (threadIdx.x == 0) write_partial(a.part, blockIdx.x, r);
+    if (threadIdx.x == 0) write_partial(a.part, a.part0 + blockIdx.x, r);
   }
 }
 
@@ -218,22 +220,23 @@ struct StartArgs {
   double* tau;
   const double* coef;
   double* part;
-  int64_t npts, stride, tile;
-  int m;
+  int64_t p_begin, ngroups;
+  int64_t stride, tile;
+  int m, part0;
   StartScalars s;
 };
 
-template <int D, typename MT, int V, bool FULL, bool DIAG>
-__device__ __forceinline__ void start_group(const StartArgs<MT>& a, int64_t p0, int nv, DiagAcc& acc) {
+template <int D, typename MT, int V, bool DIAG>
+__device__ __forceinline__ void start_group(const StartArgs<MT>& a, const WaveAddr& w, DiagAcc& acc) {
   constexpr int C = Sym<D>::C;
   const int64_t st = a.stride;
   const int m = a.m;
   double X0[C][V], X1[C][V], X2[C][V];
 #pragma unroll
-  for (int s = 0; s < C; ++s) load_v<FULL, double, V>(a.X0 + s * st + p0, nv, X0[s]);
+  for (int s = 0; s < C; ++s) load_v<true, double, V>(at(a.X0 + s * st + w.pw, w.ox), V, X0[s]);
   double kt[D * D][V];
 #pragma unroll
-  for (int q = 0; q < D * D; ++q) load_v<FULL, double, V>(a.ka + q * st + p0, nv, kt[q]);
+  for (int q = 0; q < D * D; ++q) load_v<true, double, V>(at(a.ka + q * st + w.pw, w.ox), V, kt[q]);
 
   double Tout[C][V];
 #pragma unroll
@@ -266,24 +269,21 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, int64_t p0, 
       Tout[s][v] = a.s.gamma * (a.s.theta * r[s] - a.s.hr * x1[s]);
     }
     if constexpr (DIAG) {
-      if (FULL || v < nv) {
-        double xs[C], ts[C];
+      double xs[C], ts[C];
 #pragma unroll
-        for (int s = 0; s < C; ++s) { xs[s] = X2[s][v]; ts[s] = Tout[s][v]; }
-        diag_point<D>(acc, xs, ts);
-      }
+      for (int s = 0; s < C; ++s) { xs[s] = X2[s][v]; ts[s] = Tout[s][v]; }
+      diag_point<D>(acc, xs, ts);
     }
   }
 #pragma unroll
   for (int s = 0; s < C; ++s) {
-    store_v<FULL, double, V>(a.X1 + s * st + p0, nv, X2[s]);
-    if (a.tau) store_v<FULL, double, V>(a.tau + s * st + p0, nv, Tout[s]);
+    store_v<true, double, V>(at(a.X1 + s * st + w.pw, w.ox), V, X2[s]);
+    if (a.tau) store_v<true, double, V>(at(a.tau + s * st + w.pw, w.ox), V, Tout[s]);
   }
   // modes: Y_k^0 = -c_k X^0 (slot 0), Y_k^1 = u_k X^(1) + v_k X^(2) (slot 1)
   const int64_t T = a.tile;
-  const int64_t toff = (p0 / T) * (int64_t)m * C * T + (p0 % T);
-  MT* Y0 = a.Y0 + toff;
-  MT* Y1 = a.Y1 + toff;
+  MT* Y0 = a.Y0 + w.tw;
+  MT* Y1 = a.Y1 + w.tw;
   for (int k = 0; k < m; ++k) {
     const double ck = a.coef[kRowC * m + k];
     const double uk = a.coef[kRowU * m + k];
@@ -296,26 +296,27 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, int64_t p0, 
         o0[v] = (MT)(-ck * X0[s][v]);
         o1[v] = (MT)(uk * X1[s][v] + vk * X2[s][v]);
       }
-      store_v<FULL, MT, V, true>(Y0 + ((int64_t)k * C + s) * T, nv, o0);
-      store_v<FULL, MT, V, true>(Y1 + ((int64_t)k * C + s) * T, nv, o1);
+      store_v<true, MT, V, true>(at(Y0 + ((int64_t)k * C + s) * T, w.om), V, o0);
+      store_v<true, MT, V, true>(at(Y1 + ((int64_t)k * C + s) * T, w.om), V, o1);
     }
   }
 }
 
 template <int D, typename MT, int V, bool DIAG>
 __global__ __launch_bounds__(kBlock) void start_kernel(const StartArgs<MT> a) {
+  constexpr int C = Sym<D>::C;
   DiagAcc acc;
-  const int64_t ngroups = (a.npts + V - 1) / V;
-  const int64_t gstride = (int64_t)gridDim.x * kBlock;
-  for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < ngroups; g += gstride) {
-    const int64_t p0 = g * V;
-    const int nv = (int)((a.npts - p0) < V ? (a.npts - p0) : V);
-    if (nv == V) start_group<D, MT, V, true, DIAG>(a, p0, nv, acc);
-    else start_group<D, MT, V, false, DIAG>(a, p0, nv, acc);
+  const int lane = threadIdx.x % 64;
+  const int64_t nwaves = (a.ngroups + 63) / 64;
+  const int64_t wstride = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
+       wv += wstride) {
+    if (wv * 64 + lane < a.ngroups)
+      start_group<D, MT, V, DIAG>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
   }
   if constexpr (DIAG) {
     const DiagAcc r = block_reduce(acc);
-    if (threadIdx.x == 0) write_partial(a.part, blockIdx.x, r);
+    if (threadIdx.x == 0) write_partial(a.part, a.part0 + blockIdx.x, r);
   }
 }
 
@@ -366,17 +367,35 @@ int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const Levels& 
   return 1;
 }
 
+// Whole groups of V points with the V-wide kernel, the remaining npoints % V points with
+// the V = 1 kernel; the diagnostics fold the block partials of both launches.
+template <int D, typename MT, int V, bool DIAG>
+hipError_t bdf2_launch(const tfs_plan_s* p, Bdf2Args<MT> a, int64_t p_begin, int64_t ngroups, int part0,
+                       int* nblocks) {
+  a.p_begin = p_begin;
+  a.ngroups = ngroups;
+  a.part0 = part0;
+  const int grid = grid_for(p, ngroups);
+  hipLaunchKernelGGL((bdf2_kernel<D, MT, V, DIAG>), dim3(grid), dim3(kBlock), 0, p->stream, a);
+  *nblocks = grid;
+  return hipGetLastError();
+}
+
+template <int D, typename MT, int V, bool DIAG>
+hipError_t bdf2_go_(const tfs_plan_s* p, const Bdf2Args<MT>& a, double* diag_out) {
+  const int64_t full = p->npoints / V, rest = p->npoints - full * V;
+  int nb = 0, nt = 0;
+  hipError_t e = hipSuccess;
+  if (full > 0) e = bdf2_launch<D, MT, V, DIAG>(p, a, 0, full, 0, &nb);
+  if (e == hipSuccess && rest > 0) e = bdf2_launch<D, MT, 1, DIAG>(p, a, full * V, rest, nb, &nt);
+  if (e == hipSuccess && DIAG)
+    hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, a.part, nb + nt, diag_out);
+  return e == hipSuccess ? hipGetLastError() : e;
+}
+
 template <int D, typename MT, int V>
 hipError_t bdf2_go(const tfs_plan_s* p, const Bdf2Args<MT>& a, bool diag, double* diag_out) {
-  const int64_t ngroups = (a.npts + V - 1) / V;
-  const int grid = grid_for(p, ngroups);
-  if (diag) {
-    hipLaunchKernelGGL((bdf2_kernel<D, MT, V, true>), dim3(grid), dim3(kBlock), 0, p->stream, a);
-    hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, a.part, grid, diag_out);
-  } else {
-    hipLaunchKernelGGL((bdf2_kernel<D, MT, V, false>), dim3(grid), dim3(kBlock), 0, p->stream, a);
-  }
-  return hipGetLastError();
+  return diag ? bdf2_go_<D, MT, V, true>(p, a, diag_out) : bdf2_go_<D, MT, V, false>(p, a, diag_out);
 }
 
 template <int D, typename MT>
@@ -395,7 +414,6 @@ hipError_t bdf2_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const
   a.tau = tau;
   a.coef = p->d_coef;
   a.part = p->d_part;
-  a.npts = p->npoints;
   a.stride = st;
   a.tile = p->tile;
   a.m = p->m;
@@ -414,17 +432,33 @@ hipError_t bdf2_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const
   return bdf2_go<D, MT, 1>(p, a, dg, diag);
 }
 
+template <int D, typename MT, int V, bool DIAG>
+hipError_t start_launch(const tfs_plan_s* p, StartArgs<MT> a, int64_t p_begin, int64_t ngroups, int part0,
+                       int* nblocks) {
+  a.p_begin = p_begin;
+  a.ngroups = ngroups;
+  a.part0 = part0;
+  const int grid = grid_for(p, ngroups);
+  hipLaunchKernelGGL((start_kernel<D, MT, V, DIAG>), dim3(grid), dim3(kBlock), 0, p->stream, a);
+  *nblocks = grid;
+  return hipGetLastError();
+}
+
+template <int D, typename MT, int V, bool DIAG>
+hipError_t start_go_(const tfs_plan_s* p, const StartArgs<MT>& a, double* diag_out) {
+  const int64_t full = p->npoints / V, rest = p->npoints - full * V;
+  int nb = 0, nt = 0;
+  hipError_t e = hipSuccess;
+  if (full > 0) e = start_launch<D, MT, V, DIAG>(p, a, 0, full, 0, &nb);
+  if (e == hipSuccess && rest > 0) e = start_launch<D, MT, 1, DIAG>(p, a, full * V, rest, nb, &nt);
+  if (e == hipSuccess && DIAG)
+    hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, a.part, nb + nt, diag_out);
+  return e == hipSuccess ? hipGetLastError() : e;
+}
+
 template <int D, typename MT, int V>
 hipError_t start_go(const tfs_plan_s* p, const StartArgs<MT>& a, bool diag, double* diag_out) {
-  const int64_t ngroups = (a.npts + V - 1) / V;
-  const int grid = grid_for(p, ngroups);
-  if (diag) {
-    hipLaunchKernelGGL((start_kernel<D, MT, V, true>), dim3(grid), dim3(kBlock), 0, p->stream, a);
-    hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, a.part, grid, diag_out);
-  } else {
-    hipLaunchKernelGGL((start_kernel<D, MT, V, false>), dim3(grid), dim3(kBlock), 0, p->stream, a);
-  }
-  return hipGetLastError();
+  return diag ? start_go_<D, MT, V, true>(p, a, diag_out) : start_go_<D, MT, V, false>(p, a, diag_out);
 }
 
 template <int D, typename MT>
@@ -438,7 +472,6 @@ hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, const Levels& L
   a.tau = tau;
   a.coef = p->d_coef;
   a.part = p->d_part;
-  a.npts = p->npoints;
   a.stride = p->stride;
   a.tile = p->tile;
   a.m = p->m;
@@ -461,7 +494,8 @@ hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, const Levels& L
 
 }  // namespace
 
-int max_blocks(const tfs_plan_s* p) { return p->num_cus * kMaxBlocksPerCU; }
+// a V-wide pass and a V = 1 tail pass
+int max_blocks(const tfs_plan_s* p) { return 2 * p->num_cus * kMaxBlocksPerCU; }
 
 hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
                        double* tau, double* diag) {
