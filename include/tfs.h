@@ -218,7 +218,7 @@ int64_t tfs_plan_tile(tfs_plan plan);
  *   "vec"          points per lane: 0 = widest width the alignment of the fields allows
  *                  (default), or 1, 2 (and 4 for TFS_FP32_MODES); a width the alignment
  *                  does not allow falls back to 1 at launch.
- *   "adj_vec"      points per lane of the BDF2 adjoint: 0 (default, 1), 1 or 2.
+ *   "adj_vec"      points per lane of the BDF2 adjoint: 0 (default: 2 for FP32 modes, 1 for FP64), 1 or 2.
  *   "grid_per_cu"  cap on blocks per compute unit of the grid-stride launches, 1..64.
  * Note: the diagnostic sum's rounding order depends on the grid; results of X, tau, Y do not.
  */

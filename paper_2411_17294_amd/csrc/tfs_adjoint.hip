@@ -723,7 +723,13 @@ hipError_t adj_go(const tfs_plan_s* p, AdjArgs<MT> a, int64_t zeta_dest, double*
     a.ngroups = nwaves * 64;
     a.part0 = 0;
     nb = grid_adj(p, a.ngroups);
-    hipLaunchKernelGGL((adj_kernel<D, MT, V, true>), dim3(nb), dim3(kBlock), adj_shared_bytes(p, V), p->stream, a);
+    const size_t shm = adj_shared_bytes(p, V);
+    if (shm > 65536) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&adj_kernel<D, MT, V, true>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((adj_kernel<D, MT, V, true>), dim3(nb), dim3(kBlock), shm, p->stream, a);
   }
   if (rest > 0) {
     a.p_begin = p_tail;
@@ -757,9 +763,10 @@ bool al(const void* ptr, size_t b) { return ptr == nullptr || ((uintptr_t)ptr % 
 // is aligned for it and its LDS slots fit in 64 KB per block.
 template <typename MT>
 int adj_vec(const tfs_plan_s* p, const AdjLevels& L) {
-  const int V = p->adj_vec_override == 2 ? 2 : 1;
+  const int want = p->adj_vec_override ? p->adj_vec_override : (sizeof(MT) == 4 ? 2 : 1);
+  const int V = want == 2 ? 2 : 1;
   if (V == 1) return 1;
-  if (p->stride % V || p->tile % V || adj_shared_bytes(p, V) > 65536) return 1;
+  if (p->stride % V || p->tile % V || adj_shared_bytes(p, V) > (size_t)p->lds_max) return 1;
   const size_t bm = (size_t)V * sizeof(MT), bd = (size_t)V * 8;
   if (al(L.ka, bd) && al(L.kb, bd) && al(L.Xn, bd) && al(L.Xm, bd) && al(L.Xp, bd) && al(L.Xbar, bd) &&
       al(L.taubar, bd) && al(L.kba, bd) && al(L.kbb, bd) && al(L.Yn, bm) && al(L.Ym, bm) && al(L.Hbar, bm))

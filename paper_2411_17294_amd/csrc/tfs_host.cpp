@@ -326,6 +326,9 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
     p->num_cus = cus;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) == hipSuccess && lds > 0)
+    p->lds_max = lds;
   e = hipMalloc(&p->d_coef, sizeof(double) * p->coef.size());
   if (e != hipSuccess) { delete p; return fail(TFS_ENOMEM, "coefficient table: %s", hipGetErrorString(e)); }
   e = hipMemcpy(p->d_coef, p->coef.data(), sizeof(double) * p->coef.size(), hipMemcpyHostToDevice);

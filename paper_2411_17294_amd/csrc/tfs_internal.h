@@ -97,6 +97,7 @@ struct tfs_plan_s {
   int adj_vec_override = 0;
   int grid_per_cu = 16;
   int num_cus = 256;
+  int lds_max = 65536;      // LDS bytes a block may use on the plan's device
 };
 
 namespace tfs {

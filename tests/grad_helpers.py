@@ -76,11 +76,14 @@ def oracle_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, dw_da=None,
 
 
 def gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precision="fp64", tile=None,
-                  dw_da=None, dl_da=None, extrap=True):
-    """Forward + adjoint on the GPU; kappa steady [d*d][P] or levels [nlev][d*d][P]."""
+                  dw_da=None, dl_da=None, extrap=True, tune=None):
+    """Forward + adjoint on the GPU; kappa steady [d*d][P] or levels [nlev][d*d][P].
+    tune: {key: value} passed to tfs_plan_tune (e.g. points per lane)."""
     P = X0.shape[1]
     c = d * (d + 1) // 2
     plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, max(N, 1), precision=precision, tile=tile)
+    for key, value in (tune or {}).items():
+        plan.tune(key, value)
     st, m = plan.stride, plan.m
     dev = "cuda"
     mt = plan.mode_dtype

@@ -50,6 +50,24 @@ def test_adjoint_matches_oracle_steady(d, prec, P, N):
     compare(g, o, prec, label=f"adj d={d} {prec} P={P} N={N}")
 
 
+@pytest.mark.parametrize("m", [5, 48])
+@pytest.mark.parametrize("tile", [None, 64])
+@pytest.mark.parametrize("adj_vec", [1, 2])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_adjoint_whole_waves_and_tail(d, prec, adj_vec, tile, m):
+    """389 points: whole waves of 64 groups (V = 1 or 2 points per lane) plus a masked tail;
+    with tile = 64 a wave of 128 points spans two tiles of the mode ring; m = 48 in 3-D with
+    V = 2 needs more than 64 KB of LDS per block."""
+    P, N = 389, 6
+    kappa, X0, w, lam, dw, dl, target = setup(d, P, m, 500 + d)
+    print(f"adjoint waves+tail d={d} {prec} adj_vec={adj_vec} tile={tile} m={m}", flush=True)
+    o = oracle_gradients(d, w, lam, 1.1, 0.1, 2e-3, N, kappa, X0, target, dw_da=dw, dl_da=dl)
+    g = gpu_gradients(d, w, lam, 0.45, 1.1, 0.1, 2e-3, N, kappa, X0, target, precision=prec, tile=tile,
+                      dw_da=dw, dl_da=dl, tune={"adj_vec": adj_vec})
+    compare(g, o, prec, per_mode=False, label=f"adj waves d={d} {prec} V={adj_vec} tile={tile} m={m}")
+
+
 @pytest.mark.parametrize("extrap", [True, False])
 @pytest.mark.parametrize("d", [2, 3])
 def test_adjoint_time_varying_kappa(d, extrap):
