@@ -49,13 +49,163 @@ def profiled_traffic(profile_name):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     src = b"".join(open(os.path.join(ROOT, "paper_2411_17294_amd", "csrc", f), "rb").read()
-                   for f in ("tfs_kernels.hip", "tfs_internal.h"))
+                   for f in ("tfs_kernels.hip", "tfs_device.h", "tfs_internal.h"))
     if fields.get("source_sha256") != hashlib.sha256(src).hexdigest():
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def adjoint_bytes_per_point(dim, m, mode_bytes):
+    """Minimum HBM traffic of one adjoint step per point: four mode streams read (H^(n+1),
+    H^(n+2), Y^n, Y^(n-1)) and one written (H^(n)); X at three levels read, the two adjoint
+    X slots read and written; kappa at two levels read and its adjoint read and written."""
+    c = dim * (dim + 1) // 2
+    return 5 * m * c * mode_bytes + 3 * c * 8 + 4 * c * 8 + 4 * dim * dim * 8
+
+
+def _timed(stream, fn, first, count):
+    """Average ms per call of fn(n), n = first .. first + count - 1, by HIP events on stream."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for n in range(first, first + count):
+        fn(n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / count
+
+
+def copy_rate_gbs(stream):
+    """A plain device-to-device copy of 2 GiB (read + write) on the stream: the reference
+    for the counter scale factors and a measured bandwidth ceiling."""
+    import torch
+    csrc = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        cdst.copy_(csrc)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    gbs = 10 * 2 * csrc.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del csrc, cdst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def measure_forms(stream, steps=20, which="all"):
+    """The two 3-D forms next to the headline workload.
+
+    * FP32 modes vs FP64: one forward step of the 256^3, m = 40 configuration in each form
+      (same seeded inputs), the speedup, and the relative difference of the two stresses
+      after the same steps.
+    * Forward + adjoint, 128^3, m = 32, FP32 modes: per time level the differentiation pass
+      runs one forward step (ring), one recomputed step into per-level buffers and one
+      adjoint step; each is timed and priced at its algorithmic bytes.
+    """
+    import torch
+    from paper_2411_17294_amd import inputs as I
+    from paper_2411_17294_amd import tfs
+    from paper_2411_17294_amd.device_inputs import DeviceKappa, x0_ring
+    out = {}
+    if which in ("all", "fp32_vs_fp64"):
+        out["fp32_vs_fp64_3d"] = _fp32_vs_fp64(stream, steps)
+    if which in ("all", "fwd_adjoint"):
+        out["fwd_adjoint_3d"] = _fwd_adjoint(stream, steps)
+    return out
+
+
+def _fp32_vs_fp64(stream, steps):
+    import torch
+    from paper_2411_17294_amd import inputs as I
+    from paper_2411_17294_amd import tfs
+    from paper_2411_17294_amd.device_inputs import DeviceKappa, x0_ring
+    wl = I.WORKLOADS[3]
+    alpha = wl.alphas[0]
+    w, lam, _, _, _ = tfs.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * wl.nsteps)
+    res = {}
+    taus = {}
+    for form in ("fp64", "fp32_modes"):
+        p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=form)
+        k0 = p.kappa_tensor()
+        DeviceKappa(I.fourier_field(wl), wl.grid, wl.npoints).fill(k0, 0.0)
+        X = x0_ring(wl, p.stride)
+        _, Y, tau, _ = p.alloc()
+        p.step(0, k0, None, X, Y, tau)
+        for n in range(1, 4):
+            p.step(n, k0, k0, X, Y, tau)
+        ms = _timed(stream, lambda n: p.step(n, k0, k0, X, Y, tau), 4, steps)
+        mb = 8 if form == "fp64" else 4
+        gbs = algorithmic_bytes_per_point(wl.dim, wl.nmodes, mb, 2) * wl.npoints / (ms * 1e-3) / 1e9
+        res[form] = {"ms_per_step": ms, "point_mode_updates_per_s": wl.npoints * wl.nmodes / (ms * 1e-3),
+                     "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        taus[form] = tau[:, :wl.npoints].clone()
+        del p, k0, X, Y, tau
+        torch.cuda.empty_cache()
+    diff = float((taus["fp32_modes"] - taus["fp64"]).abs().max() / taus["fp64"].abs().max())
+    del taus
+    torch.cuda.empty_cache()
+    return {"workload": wl.name, "steps": 4 + steps, **{f: res[f] for f in res},
+            "speedup_fp32_modes": res["fp64"]["ms_per_step"] / res["fp32_modes"]["ms_per_step"],
+            "tau_rel_diff_fp32_vs_fp64": diff}
+
+
+def _fwd_adjoint(stream, steps):
+    import torch
+    from paper_2411_17294_amd import inputs as I
+    from paper_2411_17294_amd import tfs
+    from paper_2411_17294_amd.device_inputs import DeviceKappa, x0_ring
+    wl = I.WORKLOADS[4]
+    alpha = wl.alphas[0]
+    w, lam, _, _, _ = tfs.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * wl.nsteps)
+    p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=wl.precision)
+    ka, kb = p.kappa_tensor(), p.kappa_tensor()
+    dk = DeviceKappa(I.fourier_field(wl), wl.grid, wl.npoints)
+    dk.fill(ka, 0.0)
+    kb.copy_(ka)
+    st, c, m = p.stride, p.c, p.m
+    X = x0_ring(wl, st)
+    _, Y, tau, _ = p.alloc()
+    Xs = [torch.zeros((c, st), dtype=torch.float64, device="cuda") for _ in range(3)]
+    Ys = [torch.zeros((m * c * st,), dtype=p.mode_dtype, device="cuda") for _ in range(3)]
+    Xs[0].copy_(X[0])
+    p.step_levels(0, ka, None, Xs[0], None, Xs[1], None, Ys[0], Ys[1], tau)
+    p.step_levels(1, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Ys[2], tau)
+    Xbar = torch.zeros((2, c, st), dtype=torch.float64, device="cuda")
+    Xbar[0, :, :wl.npoints].normal_()
+    Hbar = torch.zeros((2 * m * c * st,), dtype=p.mode_dtype, device="cuda")
+    pbar = torch.zeros(p.pbar_size, dtype=torch.float64, device="cuda")
+    kbar = torch.zeros_like(ka)
+    p.step(0, ka, None, X, Y, tau)
+
+    def fwd(n):
+        p.step(n, ka, kb, X, Y, tau)
+
+    def rec(n):
+        p.step_levels(n, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Ys[2], tau)
+
+    def adj(n):
+        p.step_adjoint(n, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Xbar, Hbar, pbar, kappabar_a=kbar,
+                       kappabar_b=kbar)
+    fb = algorithmic_bytes_per_point(wl.dim, m, 4, 2) * wl.npoints
+    ab = adjoint_bytes_per_point(wl.dim, m, 4) * wl.npoints
+    parts = {}
+    for name, fn, nbytes in (("forward", fwd, fb), ("recompute", rec, fb), ("adjoint", adj, ab)):
+        for n in range(1, 4):
+            fn(n)
+        ms = _timed(stream, fn, 4, steps)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        parts[name] = {"ms_per_step": ms, "bytes_per_launch": nbytes, "achieved_GBs": gbs,
+                       "frac": gbs / HBM_PEAK_GBS}
+    total = sum(v["ms_per_step"] for v in parts.values())
+    return {"workload": wl.name, "form": wl.precision, **parts, "ms_per_time_level": total,
+            "point_mode_updates_per_s": wl.npoints * m / (total * 1e-3),
+            "frac_all": (2 * fb + ab) / (total * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def cpu_baseline(wl, alpha, w, lam, nthreads):
@@ -89,6 +239,9 @@ def main():
     ap.add_argument("--tile", type=int, default=-1, help="mode-ring tile (points); -1 = library default")
     ap.add_argument("--grid-per-cu", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the 3-D FP32/FP64 and forward+adjoint lines")
+    ap.add_argument("--only-forms", choices=["all", "fp32_vs_fp64", "fwd_adjoint"], default=None,
+                    help="only the 3-D form measurements (for profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -103,6 +256,13 @@ def main():
     from paper_2411_17294_amd import inputs as I
     from paper_2411_17294_amd import tfs
     from paper_2411_17294_amd.device_inputs import DeviceKappa, x0_ring
+
+    if args.only_forms:
+        torch.cuda.set_device(0)
+        stream = torch.cuda.current_stream()
+        forms = measure_forms(stream, which=args.only_forms)
+        print(json.dumps({"forms": forms, "measured_copy_GBs": copy_rate_gbs(stream)}), flush=True)
+        return
 
     wl = I.WORKLOADS[args.workload]
     form = wl.precision if args.form == "default" else args.form
@@ -169,18 +329,7 @@ def main():
         if not bool(torch.isfinite(tau[:, :wl.npoints]).all()):
             raise SystemExit("non-finite stress in the benchmark run")
 
-    # reference: a plain device-to-device copy of 2 GiB (read + write) on the same stream
-    csrc = torch.empty(1 << 28, dtype=torch.float64, device=dev)
-    cdst = torch.empty_like(csrc)
-    cdst.copy_(csrc)
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record(stream)
-    for _ in range(10):
-        cdst.copy_(csrc)
-    c1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 10 * 2 * csrc.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
-    del csrc, cdst
+    copy_gbs = copy_rate_gbs(stream)
 
     nfields = len(wl.alphas)
     updates = nfields * wl.npoints * wl.nmodes * args.steps
@@ -217,6 +366,14 @@ def main():
                      "avg_launch_us": avg_launch_s * 1e6, "measured_copy_GBs": copy_gbs},
         "wall_s": wall,
     }
+    if not args.no_forms:
+        del states, plans[1:]
+        if wl.time_varying:
+            del kap
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        out["forms"] = measure_forms(stream)
+        log(f"3-D form measurements in {time.perf_counter() - t0:.1f} s")
     if not args.no_cpu_baseline:
         nthreads = min(16, os.cpu_count() or 1)
         alpha, w, lam, _ = plans[0]
