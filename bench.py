@@ -48,8 +48,8 @@ def profiled_traffic(profile_name):
         if ":" in line and not line.startswith(("|", "#", "rocprofv3")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    src = b"".join(open(os.path.join(ROOT, "paper_2411_17294_amd", "csrc", f), "rb").read()
-                   for f in ("tfs_kernels.hip", "tfs_device.h", "tfs_internal.h"))
+    names = fields.get("sources", "tfs_kernels.hip,tfs_device.h,tfs_internal.h").split(",")
+    src = b"".join(open(os.path.join(ROOT, "paper_2411_17294_amd", "csrc", f), "rb").read() for f in names)
     if fields.get("source_sha256") != hashlib.sha256(src).hexdigest():
         return None
     try:
@@ -132,20 +132,25 @@ def _fp32_vs_fp64(stream, steps):
     taus = {}
     for form in ("fp64", "fp32_modes"):
         p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=form)
-        k0 = p.kappa_tensor()
-        DeviceKappa(I.fourier_field(wl), wl.grid, wl.npoints).fill(k0, 0.0)
+        # the steady field at two levels in two buffers, as a time-varying one would be read
+        ka, kb = p.kappa_tensor(), p.kappa_tensor()
+        DeviceKappa(I.fourier_field(wl), wl.grid, wl.npoints).fill(ka, 0.0)
+        kb.copy_(ka)
         X = x0_ring(wl, p.stride)
         _, Y, tau, _ = p.alloc()
-        p.step(0, k0, None, X, Y, tau)
+        p.step(0, ka, None, X, Y, tau)
         for n in range(1, 4):
-            p.step(n, k0, k0, X, Y, tau)
-        ms = _timed(stream, lambda n: p.step(n, k0, k0, X, Y, tau), 4, steps)
+            p.step(n, ka, kb, X, Y, tau)
+        ms = _timed(stream, lambda n: p.step(n, ka, kb, X, Y, tau), 4, steps)
         mb = 8 if form == "fp64" else 4
-        gbs = algorithmic_bytes_per_point(wl.dim, wl.nmodes, mb, 2) * wl.npoints / (ms * 1e-3) / 1e9
+        nbytes = algorithmic_bytes_per_point(wl.dim, wl.nmodes, mb, 2) * wl.npoints
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        prof = "bdf2_kernel_" + ("fp64_3d_256cube_m40" if form == "fp64" else wl.name)
         res[form] = {"ms_per_step": ms, "point_mode_updates_per_s": wl.npoints * wl.nmodes / (ms * 1e-3),
-                     "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+                     "bytes_per_launch": nbytes, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic(prof)}
         taus[form] = tau[:, :wl.npoints].clone()
-        del p, k0, X, Y, tau
+        del p, ka, kb, X, Y, tau
         torch.cuda.empty_cache()
     diff = float((taus["fp32_modes"] - taus["fp64"]).abs().max() / taus["fp64"].abs().max())
     del taus
@@ -195,13 +200,15 @@ def _fwd_adjoint(stream, steps):
     fb = algorithmic_bytes_per_point(wl.dim, m, 4, 2) * wl.npoints
     ab = adjoint_bytes_per_point(wl.dim, m, 4) * wl.npoints
     parts = {}
-    for name, fn, nbytes in (("forward", fwd, fb), ("recompute", rec, fb), ("adjoint", adj, ab)):
+    for name, fn, nbytes, prof in (("forward", fwd, fb, "bdf2_kernel_fp32modes_3d_128cube_m32"),
+                                   ("recompute", rec, fb, "bdf2_kernel_fp32modes_3d_128cube_m32"),
+                                   ("adjoint", adj, ab, "adj_kernel_fp32modes_3d_128cube_m32")):
         for n in range(1, 4):
             fn(n)
         ms = _timed(stream, fn, 4, steps)
         gbs = nbytes / (ms * 1e-3) / 1e9
         parts[name] = {"ms_per_step": ms, "bytes_per_launch": nbytes, "achieved_GBs": gbs,
-                       "frac": gbs / HBM_PEAK_GBS}
+                       "frac": gbs / HBM_PEAK_GBS, "traffic": profiled_traffic(prof)}
     total = sum(v["ms_per_step"] for v in parts.values())
     return {"workload": wl.name, "form": wl.precision, **parts, "ms_per_time_level": total,
             "point_mode_updates_per_s": wl.npoints * m / (total * 1e-3),
