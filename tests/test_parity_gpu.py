@@ -177,6 +177,49 @@ def test_workload_1024sq_subdomain(alpha):
     compare(g, o, "fp64", modes=False, diag=False, label=f"1024^2 alpha={alpha}", spread=spread)
 
 
+def test_workload_256cube_fp32_modes_and_fp64():
+    """256^3, alpha = 0.4, m = 40, 500 steps, dt = 2e-4, steady kappa: both forms on the full
+    grid in the benchmark's launch configuration.  Checked: each against the FP64 oracle on
+    the strided 32^3 subdomain (FP64 within max(1e-12, conditioning), FP32 modes within
+    1e-5), and the FP32-mode form against the full-grid FP64 GPU result (1e-5)."""
+    from paper_2411_17294_amd.device_inputs import DeviceKappa, x0_ring
+    wl = I.WORKLOADS[3]
+    N, alpha = wl.nsteps, wl.alphas[0]
+    ff = I.fourier_field(wl)
+    w, lam, info = osoe.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * N)
+    sub = I.subdomain_points(wl)
+    subt = torch.from_numpy(sub).cuda()
+    full = {}
+    for prec in ("fp64", "fp32_modes"):
+        plan = tfs.Plan(3, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, N, precision=prec)
+        k0 = plan.kappa_tensor()
+        DeviceKappa(ff, wl.grid, wl.npoints).fill(k0, 0.0)
+        X = x0_ring(wl, plan.stride)
+        _, Y, tau, _ = plan.alloc()
+        print(f"workload 256^3 {prec}", info, flush=True)
+        for n in range(N):
+            plan.step(n, k0, k0 if n >= 1 else None, X, Y, tau)
+        torch.cuda.synchronize()
+        full[prec] = (X[N % 2][:, :wl.npoints].clone(), tau[:, :wl.npoints].clone())
+        del plan, k0, X, Y, tau
+        torch.cuda.empty_cache()
+    idx = I.grid_multi_index(wl.grid, 3, sub)
+    kap = ff.kappa_at(idx, wl.grid, 0.0)
+    X0 = I.initial_state(wl, sub)
+    o = O.run(3, w, lam, wl.De, wl.eta_p, wl.dt, N, kap, X0)
+    spread = oracle_spread(o, lambda: O.run(3, w, lam, wl.De, wl.eta_p, wl.dt, N, ulp_perturbed(kap), X0))
+    for prec in ("fp64", "fp32_modes"):
+        Xg, tg = full[prec]
+        g = {"X": np.stack([Xg[:, subt].cpu().numpy(), Xg[:, subt].cpu().numpy()]), "tau": tg[:, subt].cpu().numpy()}
+        o1 = {"X": np.stack([o["X"][0], o["X"][0]]), "tau": o["tau"]}
+        compare(g, o1, prec, modes=False, diag=False, label=f"256^3 {prec} vs oracle on 32^3",
+                spread=spread if prec == "fp64" else None)
+    ex = float((full["fp32_modes"][0] - full["fp64"][0]).abs().max() / full["fp64"][0].abs().max())
+    et = float((full["fp32_modes"][1] - full["fp64"][1]).abs().max() / full["fp64"][1].abs().max())
+    print(f"256^3 FP32 modes vs FP64 GPU, full grid: X {ex:.2e}, tau {et:.2e}", flush=True)
+    assert ex <= TOL["fp32_modes"] and et <= TOL["fp32_modes"]
+
+
 def test_device_kappa_matches_host_generator():
     from paper_2411_17294_amd.device_inputs import DeviceKappa
     for cid in (1, 2, 3):
