@@ -186,23 +186,36 @@ def fractional_stress(kappa, X0, alpha, De, eta_p, spec: Spec):
     return TfsFunction.apply(kappa, X0, to_t(alpha), to_t(De), to_t(eta_p), spec)
 
 
-def run_slabs(spec: Spec, slabs, alpha, De, eta_p, loss_grad, device="cuda"):
-    """Forward + backward slab by slab (points are independent).
+def run_slabs(spec: Spec, slabs, alpha, De, eta_p, loss_grad, device="cuda", keep_fields=False):
+    """Forward + backward slab by slab (points are independent, so the parameter gradients
+    are sums over slabs and the field gradients are slab-local).
 
-    slabs: iterable of (kappa [d*d][P], X0 [c][P]) device tensors, or callables returning them.
+    slabs: iterable of (kappa [d*d][P], X0 [c][P]) or (kappa, X0, kappa_levels) device
+    tensors, or callables returning them; kappa_levels(n, out) replaces spec.kappa_levels
+    for that slab (a time-varying base field evaluated on the slab's points).
     loss_grad(tau [c][P], slab_index) -> (loss_value, dL/dtau).
-    Returns dict: loss, alpha, De, eta_p gradients (summed), and per-slab (kappa, X0) gradients
-    if keep_fields."""
+    Returns dict: loss, alpha, De, eta_p (summed over slabs) and, with keep_fields, the
+    per-slab (dL/dkappa, dL/dX0) on the host."""
     total = {"loss": 0.0, "alpha": 0.0, "De": 0.0, "eta_p": 0.0}
+    fields = []
     for j, sl in enumerate(slabs):
-        kappa, X0 = sl() if callable(sl) else sl
-        run = Checkpointed(spec, X0.shape[1], alpha, De, eta_p, device=device)
+        item = sl() if callable(sl) else sl
+        kappa, X0 = item[0], item[1]
+        sp = spec
+        if len(item) > 2 and item[2] is not None:
+            sp = dataclasses.replace(spec, kappa_levels=item[2])
+        run = Checkpointed(sp, X0.shape[1], alpha, De, eta_p, device=device)
         tau = run.forward(kappa, X0)
         lv, tb = loss_grad(tau, j)
-        _, _, ga, gD, ge = run.backward(tb)
+        gk, gx, ga, gD, ge = run.backward(tb)
         run.release()
+        if keep_fields:
+            fields.append((gk.cpu(), gx.cpu()))
+        del run, tau, tb, gk, gx
         total["loss"] += lv
         total["alpha"] += ga
         total["De"] += gD
         total["eta_p"] += ge
+    if keep_fields:
+        total["fields"] = fields
     return total

@@ -18,11 +18,12 @@ from . import inputs as I
 class DeviceKappa:
     """kappa(x, t) of a FourierField on a full periodic grid, written into [d*d][stride] tensors."""
 
-    def __init__(self, ff: I.FourierField, grid: int, npoints: int, device="cuda", chunk=1 << 22):
+    def __init__(self, ff: I.FourierField, grid: int, npoints: int, device="cuda", chunk=1 << 22, offset=0):
         self.ff = ff
         self.grid = grid
         self.dim = ff.dim
         self.npoints = npoints
+        self.offset = int(offset)   # first flat grid index (a slab of the grid)
         self.device = device
         self.chunk = chunk
         self.k = torch.tensor(ff.k.T.astype(np.float64), device=device)                    # [d, NF]
@@ -31,11 +32,11 @@ class DeviceKappa:
         self.omega = torch.tensor(ff.omega, device=device)
 
     def fill(self, out: torch.Tensor, t: float):
-        """out: [d*d][stride] FP64; writes points [0, npoints)."""
+        """out: [d*d][stride] FP64; column j gets grid point offset + j, j < npoints."""
         d, g = self.dim, self.grid
         for p0 in range(0, self.npoints, self.chunk):
             p1 = min(self.npoints, p0 + self.chunk)
-            flat = torch.arange(p0, p1, device=self.device, dtype=torch.int64)
+            flat = torch.arange(self.offset + p0, self.offset + p1, device=self.device, dtype=torch.int64)
             idx = torch.empty((p1 - p0, d), device=self.device, dtype=torch.float64)
             r = flat.clone()
             for a in range(d):

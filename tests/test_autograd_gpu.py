@@ -131,3 +131,54 @@ def test_workload_128cube_differentiation():
     ex = relerr(gx[:, subt].cpu().numpy(), o["X0"])
     print(f"128^3 subset: dL/dkappa rel err {ek:.2e}, dL/dX0 rel err {ex:.2e}", flush=True)
     assert ek < 1e-5 and ex < 1e-5
+
+
+def test_slabs_match_one_run_time_varying_384cube_field():
+    """Point slabs of the 384^3 configuration's time-varying field (alpha = 0.2, m = 48,
+    dt = 1e-4, FP32 modes): three slabs of 20000 consecutive grid points run one after the
+    other give the same parameter gradients (up to summation order) and bitwise the same
+    field gradients as one run over all 60000 points; dL/dkappa and dL/dX0 at 40 of the
+    points match the oracle's complex-step derivatives."""
+    from paper_2411_17294_amd.autograd import run_slabs
+    from paper_2411_17294_amd.device_inputs import DeviceKappa
+    wl = I.WORKLOADS[5]
+    alpha, m, dt, N, K = wl.alphas[0], wl.nmodes, wl.dt, 24, 10
+    _, _, info = osoe.soe_fit(alpha, m, dt, dt * N)
+    ff = I.fourier_field(wl)
+    off, S, nslab = 7 * 384 * 384 + 1000, 20000, 3
+    P = S * nslab
+    pts = np.arange(off, off + P)
+    X0 = torch.from_numpy(I.initial_state(wl, pts)).cuda()
+    zero_k = torch.zeros((9, P), dtype=torch.float64, device="cuda")
+    wts = torch.from_numpy(pack_weights(3)[:, None]).cuda()
+
+    def levels_fn(o, n_pts):
+        dk = DeviceKappa(ff, wl.grid, n_pts, offset=o)
+        return lambda n, out: dk.fill(out, n * dt)
+    spec = Spec(dim=3, nmodes=m, dt=dt, nsteps=N, y_lo=info["y_lo"], y_hi=info["y_hi"], ckpt_every=K,
+                precision="fp32_modes")
+
+    def loss_grad(tau, j):
+        return 0.5 * float(torch.sum(wts * tau * tau)), (wts * tau).contiguous()
+    one = run_slabs(spec, [(zero_k, X0, levels_fn(off, P))], alpha, wl.De, wl.eta_p, loss_grad, keep_fields=True)
+    sl = [(zero_k[:, j * S:(j + 1) * S].contiguous(), X0[:, j * S:(j + 1) * S].contiguous(), levels_fn(off + j * S, S))
+          for j in range(nslab)]
+    many = run_slabs(spec, sl, alpha, wl.De, wl.eta_p, loss_grad, keep_fields=True)
+    for key in ("loss", "alpha", "De", "eta_p"):
+        print(f"slabs {key}: one {one[key]:.15e} slabs {many[key]:.15e}", flush=True)
+        assert many[key] == pytest.approx(one[key], rel=1e-12)
+    gk1, gx1 = one["fields"][0]
+    gk = torch.cat([f[0] for f in many["fields"]], dim=1)
+    gx = torch.cat([f[1] for f in many["fields"]], dim=1)
+    assert torch.equal(gk, gk1) and torch.equal(gx, gx1)
+    # oracle on a subset of the points (each point's gradient depends on that point only)
+    sub = np.random.default_rng(5).choice(P, 40, replace=False)
+    idx = I.grid_multi_index(wl.grid, 3, pts[sub])
+    kap = np.stack([ff.kappa_at(idx, wl.grid, n * dt) for n in range(N + 1)])
+    w, lam, dw, dl = osoe.soe_gl_log(alpha, m, info["y_lo"], info["y_hi"])
+    o = oracle_gradients(3, w, lam, wl.De, wl.eta_p, dt, N, kap, X0[:, sub].cpu().numpy(),
+                         np.zeros((6, len(sub))))
+    ek = relerr(gk1[:, sub].numpy(), o["kappa"])
+    ex = relerr(gx1[:, sub].numpy(), o["X0"])
+    print(f"slab subset vs oracle: dL/dkappa {ek:.2e}, dL/dX0 {ex:.2e}", flush=True)
+    assert ek < 1e-5 and ex < 1e-5
