@@ -117,7 +117,14 @@ def measure_forms(stream, steps=20, which="all"):
         out["fp32_vs_fp64_3d"] = _fp32_vs_fp64(stream, steps)
     if which in ("all", "fwd_adjoint"):
         out["fwd_adjoint_3d"] = _fwd_adjoint(stream, steps)
+    if which in ("all", "slab384"):
+        out["fwd_adjoint_384cube_slab"] = _fwd_adjoint(stream, steps, workload=5, npoints=SLAB_384)
     return out
+
+
+# The 384^3 configuration runs as 64 point slabs of 884736 points (checkpoints of a whole
+# slab, 2000 steps every 100, fit in one device's HBM).
+SLAB_384 = 384 ** 3 // 64
 
 
 def _fp32_vs_fp64(stream, steps):
@@ -160,21 +167,26 @@ def _fp32_vs_fp64(stream, steps):
             "tau_rel_diff_fp32_vs_fp64": diff}
 
 
-def _fwd_adjoint(stream, steps):
+def _fwd_adjoint(stream, steps, workload=4, npoints=None):
+    """Forward (ring), recompute (levels) and adjoint steps of a differentiation workload on
+    npoints points (default: the whole grid; a slab of the grid for the 384^3 case)."""
+    import numpy as np
     import torch
     from paper_2411_17294_amd import inputs as I
     from paper_2411_17294_amd import tfs
-    from paper_2411_17294_amd.device_inputs import DeviceKappa, x0_ring
-    wl = I.WORKLOADS[4]
+    from paper_2411_17294_amd.device_inputs import DeviceKappa
+    wl = I.WORKLOADS[workload]
+    P = wl.npoints if npoints is None else npoints
     alpha = wl.alphas[0]
     w, lam, _, _, _ = tfs.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * wl.nsteps)
-    p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=wl.precision)
+    p = tfs.Plan(wl.dim, P, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=wl.precision)
     ka, kb = p.kappa_tensor(), p.kappa_tensor()
-    dk = DeviceKappa(I.fourier_field(wl), wl.grid, wl.npoints)
-    dk.fill(ka, 0.0)
-    kb.copy_(ka)
+    dk = DeviceKappa(I.fourier_field(wl), wl.grid, P)
+    dk.fill(ka, wl.dt if wl.time_varying else 0.0)
+    dk.fill(kb, 0.0)
     st, c, m = p.stride, p.c, p.m
-    X = x0_ring(wl, st)
+    X = torch.zeros((2, c, st), dtype=torch.float64, device="cuda")
+    X[0, :, :P] = torch.from_numpy(I.initial_state(wl, np.arange(P))).cuda()
     _, Y, tau, _ = p.alloc()
     Xs = [torch.zeros((c, st), dtype=torch.float64, device="cuda") for _ in range(3)]
     Ys = [torch.zeros((m * c * st,), dtype=p.mode_dtype, device="cuda") for _ in range(3)]
@@ -182,7 +194,7 @@ def _fwd_adjoint(stream, steps):
     p.step_levels(0, ka, None, Xs[0], None, Xs[1], None, Ys[0], Ys[1], tau)
     p.step_levels(1, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Ys[2], tau)
     Xbar = torch.zeros((2, c, st), dtype=torch.float64, device="cuda")
-    Xbar[0, :, :wl.npoints].normal_()
+    Xbar[0, :, :P].normal_()
     Hbar = torch.zeros((2 * m * c * st,), dtype=p.mode_dtype, device="cuda")
     pbar = torch.zeros(p.pbar_size, dtype=torch.float64, device="cuda")
     kbar = torch.zeros_like(ka)
@@ -197,12 +209,13 @@ def _fwd_adjoint(stream, steps):
     def adj(n):
         p.step_adjoint(n, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Xbar, Hbar, pbar, kappabar_a=kbar,
                        kappabar_b=kbar)
-    fb = algorithmic_bytes_per_point(wl.dim, m, 4, 2) * wl.npoints
-    ab = adjoint_bytes_per_point(wl.dim, m, 4) * wl.npoints
+    fb = algorithmic_bytes_per_point(wl.dim, m, 4, 2) * P
+    ab = adjoint_bytes_per_point(wl.dim, m, 4) * P
+    tag = "fp32modes_3d_128cube_m32" if workload == 4 else "fp32modes_3d_384cube_m48_slab"
     parts = {}
-    for name, fn, nbytes, prof in (("forward", fwd, fb, "bdf2_kernel_fp32modes_3d_128cube_m32"),
-                                   ("recompute", rec, fb, "bdf2_kernel_fp32modes_3d_128cube_m32"),
-                                   ("adjoint", adj, ab, "adj_kernel_fp32modes_3d_128cube_m32")):
+    for name, fn, nbytes, prof in (("forward", fwd, fb, "bdf2_kernel_" + tag),
+                                   ("recompute", rec, fb, "bdf2_kernel_" + tag),
+                                   ("adjoint", adj, ab, "adj_kernel_" + tag)):
         for n in range(1, 4):
             fn(n)
         ms = _timed(stream, fn, 4, steps)
@@ -210,9 +223,65 @@ def _fwd_adjoint(stream, steps):
         parts[name] = {"ms_per_step": ms, "bytes_per_launch": nbytes, "achieved_GBs": gbs,
                        "frac": gbs / HBM_PEAK_GBS, "traffic": profiled_traffic(prof)}
     total = sum(v["ms_per_step"] for v in parts.values())
-    return {"workload": wl.name, "form": wl.precision, **parts, "ms_per_time_level": total,
-            "point_mode_updates_per_s": wl.npoints * m / (total * 1e-3),
-            "frac_all": (2 * fb + ab) / (total * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    out = {"workload": wl.name, "form": wl.precision, "points": P, **parts, "ms_per_time_level": total,
+           "point_mode_updates_per_s": P * m / (total * 1e-3),
+           "frac_all": (2 * fb + ab) / (total * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if P != wl.npoints:
+        # kernels only: every slab runs the same three kernels per time level
+        out["kernel_seconds_whole_grid_all_steps"] = total * 1e-3 * (wl.npoints / P) * wl.nsteps
+    return out
+
+
+def differentiation_job(steps, slabs_to_run):
+    """The 384^3 differentiation workload end to end: 64 slabs of 884736 points, each a
+    checkpointed forward (checkpoints every 100 steps) and backward through
+    autograd.run_slabs, with the time-varying field evaluated per level on the slab's points.
+    Loss: 1/2 sum ||tau^N||_F^2.  Wall time includes the field synthesis and the checkpoint
+    copies; the kernels alone are measured by the slab384 form."""
+    import numpy as np
+    import torch
+    from paper_2411_17294_amd import inputs as I
+    from paper_2411_17294_amd import tfs
+    from paper_2411_17294_amd.autograd import Spec, run_slabs
+    from paper_2411_17294_amd.device_inputs import DeviceKappa
+    wl = I.WORKLOADS[5]
+    alpha, m, dt = wl.alphas[0], wl.nmodes, wl.dt
+    _, _, _, _, info = tfs.soe_fit(alpha, m, dt, dt * wl.nsteps)
+    spec = Spec(dim=3, nmodes=m, dt=dt, nsteps=steps, y_lo=info["y_lo"], y_hi=info["y_hi"],
+                ckpt_every=wl.ckpt_every, precision=wl.precision)
+    S, nslab = SLAB_384, wl.npoints // SLAB_384
+    X0_all = I.initial_state(wl)
+    ff = I.fourier_field(wl)
+    wts = torch.tensor([1.0, 1.0, 1.0, 2.0, 2.0, 2.0], dtype=torch.float64, device="cuda")[:, None]
+    zero_k = torch.zeros((9, S), dtype=torch.float64, device="cuda")
+    t_slab = []
+
+    def slab(j):
+        def make():
+            t_slab.append(time.perf_counter())
+            log(f"slab {j}/{slabs_to_run}: points [{j * S}, {(j + 1) * S})")
+            dk = DeviceKappa(ff, wl.grid, S, offset=j * S)
+            X0 = torch.from_numpy(np.ascontiguousarray(X0_all[:, j * S:(j + 1) * S])).cuda()
+            return zero_k, X0, (lambda n, out: dk.fill(out, n * dt))
+        return make
+
+    def loss_grad(tau, j):
+        return 0.5 * float(torch.sum(wts * tau * tau)), (wts * tau).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = run_slabs(spec, [slab(j) for j in range(slabs_to_run)], alpha, wl.De, wl.eta_p, loss_grad)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_slab.append(time.perf_counter())
+    per = [b - a for a, b in zip(t_slab[:-1], t_slab[1:])]
+    pts = S * slabs_to_run
+    return {"workload": wl.name, "steps": steps, "checkpoint_every": wl.ckpt_every, "slab_points": S,
+            "slabs_run": slabs_to_run, "slabs_whole_grid": nslab, "wall_s": wall,
+            "slab_wall_s": {"min": min(per), "max": max(per), "mean": sum(per) / len(per)},
+            "point_mode_updates_per_s": pts * m * steps / wall,
+            "whole_grid_projected_s": wall * nslab / slabs_to_run,
+            "loss": res["loss"], "dL_dalpha": res["alpha"], "dL_dDe": res["De"], "dL_deta_p": res["eta_p"],
+            "note": "forward + checkpointed backward per time level and point, wall clock incl. field synthesis"}
 
 
 def cpu_baseline(wl, alpha, w, lam, nthreads):
@@ -247,7 +316,10 @@ def main():
     ap.add_argument("--grid-per-cu", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the 3-D FP32/FP64 and forward+adjoint lines")
-    ap.add_argument("--only-forms", choices=["all", "fp32_vs_fp64", "fwd_adjoint"], default=None,
+    ap.add_argument("--job", type=int, default=0, metavar="STEPS",
+                    help="run the 384^3 differentiation workload end to end with STEPS time levels")
+    ap.add_argument("--job-slabs", type=int, default=64, help="slabs of the --job run (64 = whole grid)")
+    ap.add_argument("--only-forms", choices=["all", "fp32_vs_fp64", "fwd_adjoint", "slab384"], default=None,
                     help="only the 3-D form measurements (for profiling)")
     args = ap.parse_args()
 
@@ -263,6 +335,11 @@ def main():
     from paper_2411_17294_amd import inputs as I
     from paper_2411_17294_amd import tfs
     from paper_2411_17294_amd.device_inputs import DeviceKappa, x0_ring
+
+    if args.job:
+        torch.cuda.set_device(0)
+        print(json.dumps({"job": differentiation_job(args.job, args.job_slabs)}), flush=True)
+        return
 
     if args.only_forms:
         torch.cuda.set_device(0)

@@ -66,22 +66,32 @@ class Checkpointed:
         self.ys = self.plan.m * self.c * self.st
 
     # -- velocity gradient of level n ---------------------------------------------------------
-    def _kappa(self, pert, n, buf):
-        if self.spec.kappa_levels is None:
-            return pert
-        self.spec.kappa_levels(n, buf)
-        buf[:, :self.P] += pert[:, :self.P]
+    def _level_cache(self, nslots):
+        """Level buffers of a time-varying base field: slot n % nslots holds level n (+ the
+        perturbation) once filled, so consecutive steps and the adjoint sweep over a
+        recomputed segment evaluate each level once."""
+        st, d2 = self.st, self.spec.dim * self.spec.dim
+        return {"buf": [torch.zeros((d2, st), dtype=torch.float64, device=self.dev) for _ in range(nslots)],
+                "held": [None] * nslots}
+
+    def _kappa(self, pert, n, cache):
+        i = n % len(cache["buf"])
+        buf = cache["buf"][i]
+        if cache["held"][i] != n:
+            self.spec.kappa_levels(n, buf)
+            buf[:, :self.P] += pert[:, :self.P]
+            cache["held"][i] = n
         return buf
 
-    def _levels(self, pert, n, bufs):
-        """(kappa_a, kappa_b) of step n; bufs is a 2-slot ring of level buffers."""
+    def _levels(self, pert, n, cache):
+        """(kappa_a, kappa_b) of step n."""
         if self.spec.kappa_levels is None:
             return pert, (pert if self.spec.extrap else None)
         if self.spec.extrap:
-            ka = self._kappa(pert, n, bufs[n % 2])
-            kb = self._kappa(pert, n - 1, bufs[(n - 1) % 2]) if n >= 1 else None
+            ka = self._kappa(pert, n, cache)
+            kb = self._kappa(pert, n - 1, cache) if n >= 1 else None
             return ka, kb
-        return self._kappa(pert, n + 1, bufs[0]), None
+        return self._kappa(pert, n + 1, cache), None
 
     def forward(self, kappa, X0):
         """kappa: [d*d][P] FP64 device (steady field, or perturbation); X0: [c][P]. Returns tau^N."""
@@ -89,7 +99,7 @@ class Checkpointed:
         d2 = sp.dim * sp.dim
         self.kappa_pad = torch.zeros((d2, st), dtype=torch.float64, device=self.dev)
         self.kappa_pad[:, :P] = kappa
-        self.kbufs = [torch.zeros((d2, st), dtype=torch.float64, device=self.dev) for _ in range(2)]
+        cache = self._level_cache(2) if sp.kappa_levels is not None else None
         X = torch.zeros((2, self.c, st), dtype=torch.float64, device=self.dev)
         X[0, :, :P] = X0
         Y = torch.zeros((2 * self.ys,), dtype=self.mt, device=self.dev)
@@ -101,7 +111,7 @@ class Checkpointed:
                 sn, sm = n % 2, (n - 1) % 2
                 self.ckpt[n] = (X[sn].clone(), X[sm].clone(), Y[sn * self.ys:(sn + 1) * self.ys].clone(),
                                 Y[sm * self.ys:(sm + 1) * self.ys].clone())
-            ka, kb = self._levels(self.kappa_pad, n, self.kbufs)
+            ka, kb = self._levels(self.kappa_pad, n, cache)
             self.plan.step(n, ka, kb, X, Y, tau)
         return tau[:, :P].clone()
 
@@ -120,8 +130,9 @@ class Checkpointed:
         seg_len = K + 1
         Xseg = [torch.zeros((c, st), dtype=torch.float64, device=self.dev) for _ in range(seg_len + 1)]
         Yseg = [torch.zeros((self.ys,), dtype=self.mt, device=self.dev) for _ in range(seg_len + 1)]
-        kb_fwd = [torch.zeros((d2, st), dtype=torch.float64, device=self.dev) for _ in range(2)]
-        kb_adj = [torch.zeros((d2, st), dtype=torch.float64, device=self.dev) for _ in range(2)]
+        # the levels a segment needs (s0 - 1 .. s1) fit without eviction; the recompute fills
+        # them and the adjoint sweep of the same segment reuses them
+        cache = self._level_cache(K + 2) if sp.kappa_levels is not None else None
         tau_tmp = torch.zeros((c, st), dtype=torch.float64, device=self.dev)
         for s0 in reversed(starts):
             s1 = min(s0 + K, N)
@@ -134,7 +145,7 @@ class Checkpointed:
                 Yseg[0].copy_(Yp)
             for n in range(s0, s1):
                 i = n - s0 + 1
-                ka, kb = self._levels(self.kappa_pad, n, kb_fwd)
+                ka, kb = self._levels(self.kappa_pad, n, cache)
                 if n == 0:
                     self.plan.step_levels(0, ka, kb, Xseg[i], None, Xseg[i + 1], None, Yseg[i], Yseg[i + 1], tau_tmp)
                 else:
@@ -142,7 +153,7 @@ class Checkpointed:
                                           Yseg[i + 1], tau_tmp)
             for n in range(s1 - 1, s0 - 1, -1):
                 i = n - s0 + 1
-                ka, kb = self._levels(self.kappa_pad, n, kb_adj)
+                ka, kb = self._levels(self.kappa_pad, n, cache)
                 tb = taubar if n == N - 1 else None
                 if n == 0:
                     # the start-up wrote level 0 of the modes into Yseg[i]; its adjoint needs X^0 only

@@ -30,20 +30,27 @@ class DeviceKappa:
         self.B = torch.tensor(ff.coef().reshape(len(ff.amp), ff.dim * ff.dim), device=device)  # [NF, d*d]
         self.phase = torch.tensor(ff.phase, device=device)
         self.omega = torch.tensor(ff.omega, device=device)
+        # k . x + phase of every point, kept when it fits one chunk (slabs evaluated at many t)
+        self.theta0 = self._theta0(0, npoints) if npoints <= chunk else None
+
+    def _theta0(self, p0, p1):
+        d, g = self.dim, self.grid
+        flat = torch.arange(self.offset + p0, self.offset + p1, device=self.device, dtype=torch.int64)
+        idx = torch.empty((p1 - p0, d), device=self.device, dtype=torch.float64)
+        r = flat.clone()
+        for a in range(d):
+            idx[:, a] = (r % g).to(torch.float64)
+            r = r // g
+        return (idx * (2.0 * math.pi / g)) @ self.k + self.phase[None, :]
 
     def fill(self, out: torch.Tensor, t: float):
         """out: [d*d][stride] FP64; column j gets grid point offset + j, j < npoints."""
-        d, g = self.dim, self.grid
+        if self.theta0 is not None:
+            out[:, :self.npoints] = (torch.sin(self.theta0 + self.omega[None, :] * t) @ self.B).T
+            return out
         for p0 in range(0, self.npoints, self.chunk):
             p1 = min(self.npoints, p0 + self.chunk)
-            flat = torch.arange(self.offset + p0, self.offset + p1, device=self.device, dtype=torch.int64)
-            idx = torch.empty((p1 - p0, d), device=self.device, dtype=torch.float64)
-            r = flat.clone()
-            for a in range(d):
-                idx[:, a] = (r % g).to(torch.float64)
-                r = r // g
-            x = idx * (2.0 * math.pi / g)
-            theta = x @ self.k + self.phase[None, :] + self.omega[None, :] * t
+            theta = self._theta0(p0, p1) + self.omega[None, :] * t
             out[:, p0:p1] = (torch.sin(theta) @ self.B).T
         return out
 
