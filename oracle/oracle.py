@@ -50,9 +50,16 @@ def ncomp(d):
     return d * (d + 1) // 2
 
 
+_SCHEME = {"sdirk2": 0, "ghost_bdf2": 1, "exp": 2}
+
+
 def run(d, w, lam, De, eta_p, dt, nsteps, kappa, X0, extrap=True, startup="sdirk2",
         want_modes=False, want_diag=False, want_traj=False, nthreads=0):
     """Run the oracle.
+
+    startup: "sdirk2" (the paper's scheme: SDIRK2 first step, BDF2 after), "ghost_bdf2"
+    (BDF2 from a ghost level, for the convolution check) or "exp" (exponential mode update,
+    BDF2 state with a BDF1 first step).
 
     kappa: [d*d][P] (steady) or [nlev][d*d][P] (time-varying, nlev >= nsteps+1)
     X0:    [c][P]
@@ -71,7 +78,7 @@ def run(d, w, lam, De, eta_p, dt, nsteps, kappa, X0, extrap=True, startup="sdirk
     modes = np.empty((2, m, c, P)) if want_modes else None
     diag = np.empty((max(nsteps, 1), 6)) if want_diag else None
     traj = np.empty((nsteps + 1, c, P)) if want_traj else None
-    st = {"sdirk2": 0, "ghost_bdf2": 1}[startup]
+    st = _SCHEME[startup]
     rc = lib().orc_run(d, P, m, _ptr(w), _ptr(lam), float(De), float(eta_p), float(dt), int(nsteps),
                        _ptr(kappa), nlev, int(bool(extrap)), st, _ptr(X0), _ptr(X), _ptr(tau),
                        _ptr(modes), _ptr(traj), _ptr(diag), int(nthreads))
@@ -95,7 +102,7 @@ def run_complex(d, w, lam, De, eta_p, dt, nsteps, kappa, X0, extrap=True, startu
     X = np.empty((2, c, P), dtype=np.complex128)
     tau = np.empty((c, P), dtype=np.complex128)
     modes = np.empty((2, m, c, P), dtype=np.complex128) if want_modes else None
-    st = {"sdirk2": 0, "ghost_bdf2": 1}[startup]
+    st = _SCHEME[startup]
     De_c = np.array([De], dtype=np.complex128)
     ep_c = np.array([eta_p], dtype=np.complex128)
     L = lib()
@@ -114,6 +121,16 @@ def run_complex(d, w, lam, De, eta_p, dt, nsteps, kappa, X0, extrap=True, startu
     if rc != 0:
         raise RuntimeError(f"oracle complex run failed with status {rc}")
     return {"X": X, "tau": tau, "modes": modes}
+
+
+def exp_weights(z):
+    """(e, a0, a1) of the exponential mode update at z = lambda * dt (real z)."""
+    L = lib()
+    out = np.empty(3)
+    L.orc_exp_weights_of.argtypes = [C.c_double, _dp]
+    L.orc_exp_weights_of.restype = None
+    L.orc_exp_weights_of(float(z), _ptr(out))
+    return out
 
 
 def coupling_matrix(d, De, kappa_dd):

@@ -29,6 +29,14 @@
  *  - BDF2 coefficients b = (3/2, -2, 1/2); second-order extrapolation
  *    E^{n+1} f = 2 f^n - f^{n-1} (eq. BDF_and_extrapolation).
  *
+ * A second scheme (not the paper's; an extension of it) advances each mode by
+ * the exact solution of the mode equation f_k' = -lam_k f_k + w_k f (Sec. 2.2)
+ * over a step on which f is linear in time.  Since the kernel-compressed
+ * derivative sum_k (w_k f - lam_k f_k) is sum_k f_k', the state equation
+ * Phi' = A(kappa) sum_k Phi_k' is then integrated over the step as
+ * Phi^{n+1} - Phi^n = A(kappa~) sum_k (Phi_k^{n+1} - Phi_k^n), exact for constant
+ * kappa, with kappa~ at the half step (one-step scheme, no start-up step).
+ *
  * The same source is compiled twice: once with real doubles (orc_*), once with
  * C99 complex doubles (orcz_*) for complex-step derivatives (the imaginary part
  * of every output is the directional derivative along the imaginary part of
@@ -54,6 +62,38 @@ typedef double sc;
 
 #define MAXD 3
 #define MAXN 7 /* c + 1 in 3-D */
+
+#ifdef ORC_COMPLEX
+#define EXPS(x) cexp(x)
+#else
+#define EXPS(x) exp(x)
+#endif
+
+/*
+ * Exponential weights of one mode over one step.  With f linear on the step,
+ * f(t_n + u dt) = (1-u) f^n + u f^{n+1}, the mode equation integrates exactly to
+ *   f_k^{n+1} = e f_k^n + w_k dt (a0 f^n + a1 f^{n+1}),   z = lam_k dt,
+ *   e = exp(-z),  a0 = int_0^1 e^{-z(1-u)} (1-u) du,  a1 = int_0^1 e^{-z(1-u)} u du.
+ * With v = 1-u: a0 = int_0^1 v e^{-zv} dv = sum_j (-z)^j / (j! (j+2)) and
+ * a1 = int_0^1 (1-v) e^{-zv} dv = sum_j (-z)^j / (j! (j+1) (j+2)); the series are used
+ * for Re z < 1, the closed forms a0 = (1 - (1+z) e)/z^2, a1 = (z - 1 + e)/z^2 above.
+ */
+static void exp_weights(sc z, sc* e, sc* a0, sc* a1) {
+    *e = EXPS(-z);
+    if (RE(z) < 1.0) {
+        sc t = 1.0, s0 = 0.0, s1 = 0.0;     /* t = (-z)^j / j! */
+        for (int j = 0; j < 40; ++j) {
+            s0 += t / (double)(j + 2);
+            s1 += t / ((double)(j + 1) * (double)(j + 2));
+            t *= -z / (double)(j + 1);
+        }
+        *a0 = s0;
+        *a1 = s1;
+    } else {
+        *a0 = (1.0 - (1.0 + z) * (*e)) / (z * z);
+        *a1 = (z - 1.0 + *e) / (z * z);
+    }
+}
 
 /* ---- Hermite multi-index set of degrees 0 and 2 (Sec. 3.4 ordering) ---- */
 typedef struct {
@@ -237,7 +277,9 @@ static void kappa_level(const sc* kappa, long nlev, long npts, int d, long p, lo
  *   extrap       1: kappa at step n -> n+1 is 2 kappa^n - kappa^{n-1} (kappa^0 at n = 0);
  *                0: kappa^{n+1} (the gradient of the already updated velocity)
  *   startup      0: SDIRK2 first step; 1: BDF2 from n = 0 with a ghost level
- *                Phi^{-1} = Phi^0, Phi_k^{-1} = 0 (test mode for the convolution check)
+ *                Phi^{-1} = Phi^0, Phi_k^{-1} = 0 (test mode for the convolution check);
+ *                2: the exponential-mode scheme (see the header); kappa~ is then
+ *                3/2 kappa^n - 1/2 kappa^{n-1} (kappa^0 at n = 0) with extrap, else kappa^{n+1}
  *   X0           [c][npts] packed initial X = C - I
  * Outputs (any may be NULL)
  *   X_out        [2][c][npts] levels N and N-1 (N = nsteps)
@@ -253,7 +295,7 @@ int ORC(run)(int d, long npts, int m, const sc* w, const sc* lam, sc De, sc eta_
              long nsteps, const sc* kappa, long nlev, int extrap, int startup, const sc* X0,
              sc* X_out, sc* tau_out, sc* modes_out, sc* traj_out, double* diag_out, int nthreads)
 {
-    if ((d != 2 && d != 3) || npts < 0 || m < 1 || nsteps < 0) return 1;
+    if ((d != 2 && d != 3) || npts < 0 || m < 1 || nsteps < 0 || startup < 0 || startup > 2) return 1;
     if (nlev != 1 && nlev < nsteps + 1) return 1;
     const int c = d * (d + 1) / 2;
     hset h;
@@ -321,11 +363,13 @@ int ORC(run)(int d, long npts, int m, const sc* w, const sc* lam, sc De, sc eta_
             for (long step = 0; step < nsteps; ++step) {
                 /* velocity gradient driving step -> step+1 */
                 if (extrap) {
+                    /* extrapolated to t_{n+1} (BDF2 schemes) or to t_{n+1/2} (exponential) */
+                    const double fa = startup == 2 ? 1.5 : 2.0, fb = startup == 2 ? -0.5 : -1.0;
                     kappa_level(kappa, nlev, npts, d, p, step, ka);
                     if (step == 0) for (int q = 0; q < d * d; ++q) kt[q] = ka[q];
                     else {
                         kappa_level(kappa, nlev, npts, d, p, step - 1, kb);
-                        for (int q = 0; q < d * d; ++q) kt[q] = 2.0 * ka[q] - kb[q];
+                        for (int q = 0; q < d * d; ++q) kt[q] = fa * ka[q] + fb * kb[q];
                     }
                 } else {
                     kappa_level(kappa, nlev, npts, d, p, step + 1, kt);
@@ -336,7 +380,32 @@ int ORC(run)(int d, long npts, int m, const sc* w, const sc* lam, sc De, sc eta_
                 sc* Kn = Phik + (size_t)(step % 2) * m * n;
                 sc* Km = Phik + (size_t)((step + 1) % 2) * m * n;
 
-                if (step == 0 && startup == 0) {
+                if (startup == 2) {
+                    /* Phi_k^{n+1} = e_k Phi_k^n + w_k dt (a0_k Phi^n + a1_k Phi^{n+1}) and
+                     * Phi^{n+1} - Phi^n = A sum_k (Phi_k^{n+1} - Phi_k^n), i.e.
+                     * (I - q A) Phi^{n+1} = Phi^n + A sum_k ((e_k - 1) Phi_k^n + w_k dt a0_k Phi^n),
+                     * q = sum_k w_k dt a1_k. */
+                    sc q = 0.0;
+                    for (int i = 0; i < n; ++i) v[i] = 0.0;
+                    for (int k = 0; k < m; ++k) {
+                        sc e, a0, a1;
+                        exp_weights(lam[k] * dt, &e, &a0, &a1);
+                        q += w[k] * dt * a1;
+                        for (int i = 0; i < n; ++i) v[i] += (e - 1.0) * Kn[k * n + i] + w[k] * dt * a0 * Pn[i];
+                    }
+                    matvec(n, A, v, Av);
+                    for (int i = 0; i < n; ++i) rhs[i] = Pn[i] + Av[i];
+                    for (int i = 0; i < n * n; ++i) M[i] = -q * A[i];
+                    for (int i = 0; i < n; ++i) M[i * n + i] += 1.0;
+                    if (!gauss_solve(n, M, rhs)) mystatus = 2;
+                    for (int k = 0; k < m; ++k) {
+                        sc e, a0, a1;
+                        exp_weights(lam[k] * dt, &e, &a0, &a1);
+                        for (int i = 0; i < n; ++i)
+                            Km[k * n + i] = e * Kn[k * n + i] + w[k] * dt * (a0 * Pn[i] + a1 * rhs[i]);
+                    }
+                    for (int i = 0; i < n; ++i) Pm[i] = rhs[i];
+                } else if (step == 0 && startup == 0) {
                     /* SDIRK2 (Alexander) on the augmented linear system
                      *   Phi'   = A sum_k (w_k Phi - lam_k Phi_k)
                      *   Phi_k' = w_k Phi - lam_k Phi_k,  Phi_k(0) = 0.
@@ -567,6 +636,11 @@ void ORC(tensor_to_hermite_packed)(int d, const sc* Xpacked, sc* Phi_out) {
         Xf[j * d + i] = Xpacked[s];
     }
     tensor_to_hermite(&h, Xf, 1.0, Phi_out);
+}
+
+/* The exponential weights (e, a0, a1) of one mode at z = lam dt, for the pins. */
+void ORC(exp_weights_of)(sc z, sc* out3) {
+    exp_weights(z, &out3[0], &out3[1], &out3[2]);
 }
 
 /* Multi-index table of the Hermite vector (n rows of 3 ints, unused axes 0). */

@@ -15,7 +15,8 @@ from oracle import build as obuild
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "tfs_oracle.c")
 
-# name -> (original text, planted mistake, pytest -k expression of pins expected to fail)
+# name -> (original text, planted mistake, pytest -k expression of pins expected to fail[,
+#          pin file; default test_oracle_pins.py])
 MUTATIONS = {
     "transposed_kappa": ("const sc kml = kap[m * d + l];", "const sc kml = kap[l * d + m];", "operator"),
     "dropped_stretch_term": ("((2.0 * a * a - 1.0) / (2.0 * De) + kap[l * d + l])",
@@ -36,13 +37,25 @@ MUTATIONS = {
                                 "Km[k * n + q] = (-(b1 * Kn[k * n + q]) + w[k] * dt * rhs[q]) /", "brute_force"),
     "eta_without_b0": ("eta += b0 * w[k] * dt / (b0 + lam[k] * dt);", "eta += w[k] * dt / (b0 + lam[k] * dt);",
                        "alpha_one or brute_force"),
-    "no_extrapolation": ("kt[q] = 2.0 * ka[q] - kb[q];", "kt[q] = ka[q];", "time_varying"),
+    "no_extrapolation": ("kt[q] = fa * ka[q] + fb * kb[q];", "kt[q] = ka[q];", "time_varying"),
+    # exponential-mode scheme (pins in test_oracle_exp_pins.py)
+    "exp_weights_swapped": ("Km[k * n + i] = e * Kn[k * n + i] + w[k] * dt * (a0 * Pn[i] + a1 * rhs[i]);",
+                            "Km[k * n + i] = e * Kn[k * n + i] + w[k] * dt * (a1 * Pn[i] + a0 * rhs[i]);",
+                            "relaxation or general_kappa", "test_oracle_exp_pins.py"),
+    "exp_decrement_without_decay": ("v[i] += (e - 1.0) * Kn[k * n + i] + w[k] * dt * a0 * Pn[i];",
+                                    "v[i] += -Kn[k * n + i] + w[k] * dt * a0 * Pn[i];",
+                                    "relaxation or general_kappa", "test_oracle_exp_pins.py"),
+    "exp_series_term": ("s1 += t / ((double)(j + 1) * (double)(j + 2));", "s1 += t / ((double)(j + 2) * (double)(j + 2));",
+                        "weights", "test_oracle_exp_pins.py"),
+    "exp_kappa_at_full_step": ("const double fa = startup == 2 ? 1.5 : 2.0, fb = startup == 2 ? -0.5 : -1.0;",
+                               "const double fa = 2.0, fb = -1.0;", "time_varying", "test_oracle_exp_pins.py"),
 }
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_planted_mistake_fails_a_pin(name, tmp_path):
-    orig, bad, sel = MUTATIONS[name]
+    orig, bad, sel = MUTATIONS[name][:3]
+    pins = MUTATIONS[name][3] if len(MUTATIONS[name]) > 3 else "test_oracle_pins.py"
     src = open(SRC).read()
     assert src.count(orig) == 1, "mutation anchor drifted from the oracle source"
     msrc = tmp_path / "mutant.c"
@@ -50,7 +63,7 @@ def test_planted_mistake_fails_a_pin(name, tmp_path):
     lib = str(tmp_path / "libmutant.so")
     obuild.build(src=str(msrc), lib=lib)
     env = dict(os.environ, TFS_ORACLE_LIB=lib)
-    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", pins),
                         "-q", "-x", "-p", "no:cacheprovider", "-k", sel],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"no pin caught '{name}':\n{r.stdout[-2000:]}"
