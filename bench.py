@@ -58,6 +58,13 @@ def profiled_traffic(profile_name):
         return None
 
 
+def exp_bytes_per_point(dim, m, mode_bytes, kappa_reads):
+    """Minimum HBM traffic of one exponential-mode step per point: the single mode level read
+    and written in place, X^n read and X^{n+1} written, tau written, kappa read."""
+    c = dim * (dim + 1) // 2
+    return 2 * m * c * mode_bytes + 2 * c * 8 + c * 8 + kappa_reads * dim * dim * 8
+
+
 def adjoint_bytes_per_point(dim, m, mode_bytes):
     """Minimum HBM traffic of one adjoint step per point: four mode streams read (H^(n+1),
     H^(n+2), Y^n, Y^(n-1)) and one written (H^(n)); X at three levels read, the two adjoint
@@ -117,6 +124,8 @@ def measure_forms(stream, steps=20, which="all"):
         out["fp32_vs_fp64_3d"] = _fp32_vs_fp64(stream, steps)
     if which in ("all", "fwd_adjoint"):
         out["fwd_adjoint_3d"] = _fwd_adjoint(stream, steps)
+    if which in ("all", "exp_vs_bdf2"):
+        out["exp_vs_bdf2_3d"] = _exp_vs_bdf2(stream, steps)
     if which in ("all", "slab384"):
         out["fwd_adjoint_384cube_slab"] = _fwd_adjoint(stream, steps, workload=5, npoints=SLAB_384)
     return out
@@ -165,6 +174,48 @@ def _fp32_vs_fp64(stream, steps):
     return {"workload": wl.name, "steps": 4 + steps, **{f: res[f] for f in res},
             "speedup_fp32_modes": res["fp64"]["ms_per_step"] / res["fp32_modes"]["ms_per_step"],
             "tau_rel_diff_fp32_vs_fp64": diff}
+
+
+def _exp_vs_bdf2(stream, steps):
+    """The 256^3, m = 40, FP32-mode forward step with the exponential-mode scheme (one mode
+    level, two accesses per mode-component) next to the paper's BDF2 scheme, and the
+    relative difference of their stresses after the same steps (the two discretisations,
+    not rounding)."""
+    import torch
+    from paper_2411_17294_amd import inputs as I
+    from paper_2411_17294_amd import tfs
+    from paper_2411_17294_amd.device_inputs import DeviceKappa, x0_ring
+    wl = I.WORKLOADS[3]
+    alpha = wl.alphas[0]
+    w, lam, _, _, _ = tfs.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * wl.nsteps)
+    res, taus = {}, {}
+    for scheme in ("bdf2", "exp"):
+        p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps,
+                     precision=wl.precision, scheme=scheme)
+        ka, kb = p.kappa_tensor(), p.kappa_tensor()
+        DeviceKappa(I.fourier_field(wl), wl.grid, wl.npoints).fill(ka, 0.0)
+        kb.copy_(ka)
+        X = x0_ring(wl, p.stride)
+        _, Y, tau, _ = p.alloc()
+        p.step(0, ka, None, X, Y, tau)
+        for n in range(1, 4):
+            p.step(n, ka, kb, X, Y, tau)
+        ms = _timed(stream, lambda n: p.step(n, ka, kb, X, Y, tau), 4, steps)
+        bpp = (exp_bytes_per_point if scheme == "exp" else algorithmic_bytes_per_point)(wl.dim, wl.nmodes, 4, 2)
+        nbytes = bpp * wl.npoints
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        kern = "exp_kernel_" if scheme == "exp" else "bdf2_kernel_"
+        res[scheme] = {"ms_per_step": ms, "point_mode_updates_per_s": wl.npoints * wl.nmodes / (ms * 1e-3),
+                       "bytes_per_launch": nbytes, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS,
+                       "mode_memory_GB": p.mode_levels * wl.npoints * wl.nmodes * p.c * 4 / 1e9,
+                       "traffic": profiled_traffic(kern + wl.name)}
+        taus[scheme] = tau[:, :wl.npoints].clone()
+        del p, ka, kb, X, Y, tau
+        torch.cuda.empty_cache()
+    diff = float((taus["exp"] - taus["bdf2"]).abs().max() / taus["bdf2"].abs().max())
+    return {"workload": wl.name, "form": wl.precision, "steps": 4 + steps, **res,
+            "speedup_exp": res["bdf2"]["ms_per_step"] / res["exp"]["ms_per_step"],
+            "tau_rel_diff_exp_vs_bdf2": diff}
 
 
 def _fwd_adjoint(stream, steps, workload=4, npoints=None):
@@ -319,7 +370,8 @@ def main():
     ap.add_argument("--job", type=int, default=0, metavar="STEPS",
                     help="run the 384^3 differentiation workload end to end with STEPS time levels")
     ap.add_argument("--job-slabs", type=int, default=64, help="slabs of the --job run (64 = whole grid)")
-    ap.add_argument("--only-forms", choices=["all", "fp32_vs_fp64", "fwd_adjoint", "slab384"], default=None,
+    ap.add_argument("--only-forms", choices=["all", "fp32_vs_fp64", "fwd_adjoint", "slab384", "exp_vs_bdf2"],
+                    default=None,
                     help="only the 3-D form measurements (for profiling)")
     args = ap.parse_args()
 

@@ -53,6 +53,26 @@ typedef enum {
     TFS_FP32_MODES = 1    /* modes stored in FP32; recombination, solve, X, tau and all coefficients in FP64 */
 } tfs_precision;
 
+/*
+ * Time discretisation of the modes and the state.
+ *
+ * TFS_SCHEME_BDF2 -- the paper's scheme (Sec. 4.1): BDF2 for the state and the modes,
+ *   one SDIRK2 start-up step; two mode levels (a two-slot ring).
+ * TFS_SCHEME_EXP -- an extension, not the paper's scheme: each mode solves its equation
+ *   X_k' = -lambda_k X_k + w_k X (Sec. 2.2) exactly over a step on which X is linear in
+ *   time, X_k^{n+1} = e_k X_k^n + w_k dt (a0_k X^n + a1_k X^{n+1}) with z = lambda_k dt,
+ *   e_k = exp(-z), a0_k = (1 - (1+z) e_k)/z^2, a1_k = (z - 1 + e_k)/z^2; and since
+ *   D^{1-alpha} X = sum_k X_k', the state equation is integrated over the step as
+ *   X^{n+1} - X^n = A_kappa~(sum_k (X_k^{n+1} - X_k^n)) + S_kappa~ sum_k (mu_k^{n+1} - mu_k^n)
+ *   (mu_k the modes of the constant 1), exact for a constant kappa, with kappa~ at the
+ *   half step.  One step, one mode level updated in place: two mode accesses per
+ *   mode-component and step instead of three, half the mode memory.
+ */
+typedef enum {
+    TFS_SCHEME_BDF2 = 0,
+    TFS_SCHEME_EXP = 1
+} tfs_scheme;
+
 enum {
     TFS_FLAG_CHECK_SYNC = 1u << 0  /* tfs_step synchronises and returns TFS_ENUMERIC on non-finite/non-PD diagnostics */
 };
@@ -77,6 +97,7 @@ typedef struct {
     int32_t precision;    /* tfs_precision */
     uint32_t flags;       /* TFS_FLAG_* */
     void* stream;         /* hipStream_t the plan launches on (NULL = default stream) */
+    int32_t scheme;       /* tfs_scheme */
 } tfs_plan_desc;
 
 /*
@@ -89,8 +110,10 @@ typedef struct {
  * tables are uploaded once.  The plan owns them and a small reduction buffer.
  * Errors: TFS_EINVAL (dim not 2/3, m < 1, npoints < 0, stride < npoints, alpha not in
  * (0,1], De <= 0, eta_p < 0, dt <= 0, max_steps < 1, null or negative/non-finite w or
- * lambda, unknown precision, tile negative or not a multiple of 4, stride not a multiple
- * of a positive tile), TFS_ENOMEM, TFS_EHIP.  *out is NULL on error.
+ * lambda, unknown precision or scheme, tile negative or not a multiple of 4, stride not
+ * a multiple of a positive tile), TFS_ENOMEM, TFS_EHIP.  *out is NULL on error.
+ * With TFS_SCHEME_EXP the per-mode factors are e_k, a0_k and a1_k of tfs_scheme and the
+ * mass-mode table holds the increments sum_k (mu_k^{n+1} - mu_k^n).
  */
 tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out);
 
@@ -125,6 +148,12 @@ tfs_status tfs_plan_set_stream(tfs_plan plan, void* stream);
  *                   entries.  Minima and maxima skip non-finite values.
  * Errors: TFS_EINVAL (null plan/X/Y/kappa_a, n out of range, diag requested with
  * npoints == 0 is fine), TFS_EHIP, TFS_ENUMERIC (only with TFS_FLAG_CHECK_SYNC).
+ *
+ * TFS_SCHEME_EXP plans: kappa~ = (3/2) kappa_a - (1/2) kappa_b (kappa^n, kappa^{n-1}
+ * extrapolated to the half step), or kappa_a when kappa_b is NULL or n = 0.  X is the same
+ * ring (only level n is read).  Y holds ONE level, m * c * stride elements in the plan's
+ * layout, in the representation Y_k = X_k - q_k X with q_k = w_k dt a1_k, updated in place
+ * from level n to n+1; at n = 0 its input contents are ignored (the modes start at zero).
  */
 tfs_status tfs_step(tfs_plan plan, int64_t n, const double* kappa_a, const double* kappa_b,
                     double* X, void* Y, double* tau, double* diag);
@@ -140,6 +169,8 @@ tfs_status tfs_step(tfs_plan plan, int64_t n, const double* kappa_a, const doubl
  *                        At n = 0 the start-up writes level 0 into Y_nm1 and level 1 into
  *                        Y_out, and Y_n is unused.
  * Errors as tfs_step, plus TFS_EINVAL for the forbidden aliases.
+ * TFS_SCHEME_EXP plans read X_n and Y_n (ignored at n = 0) and write X_out and Y_out,
+ * which may alias Y_n; X_nm1 and Y_nm1 are unused.
  */
 tfs_status tfs_step_levels(tfs_plan plan, int64_t n, const double* kappa_a, const double* kappa_b,
                            const double* X_n, const double* X_nm1, double* X_out,
@@ -172,7 +203,7 @@ tfs_status tfs_step_levels(tfs_plan plan, int64_t n, const double* kappa_a, cons
  *                       factors, the scalar factors and zeta^{n+1}; convert with
  *                       tfs_pbar_to_params.
  * Asynchronous on the plan's stream.  Errors: TFS_EINVAL (null required pointer, n out of
- * range), TFS_EHIP.
+ * range), TFS_EHIP, TFS_EUNSUPPORTED (TFS_SCHEME_EXP plans: no adjoint in this build).
  */
 tfs_status tfs_step_adjoint(tfs_plan plan, int64_t n, const double* kappa_a, const double* kappa_b,
                             const double* X_n, const double* X_nm1, const double* X_np1,
@@ -195,6 +226,8 @@ tfs_status tfs_pbar_to_params(tfs_plan plan, const double* pbar_host, double* dL
  * Convert the mode ring slot `slot` (0 or 1) to plain fractional modes
  * X_k = Y_k + c_k X, with X taken from the same slot of the X ring.
  * Xk_out: device [m][c][stride] FP64, untiled.  Asynchronous on the plan's stream.
+ * TFS_SCHEME_EXP plans: Y is the single mode level, X_k = Y_k + q_k X with X from slot
+ * `slot` of the X ring (the slot of the level Y holds).
  */
 tfs_status tfs_modes_to_plain(tfs_plan plan, int32_t slot, const double* X, const void* Y, double* Xk_out);
 
@@ -203,7 +236,9 @@ tfs_status tfs_modes_to_plain(tfs_plan plan, int32_t slot, const double* X, cons
  *   tables  [5][m]: d_k, c_k, eta_k, u_k, v_k (u_k, v_k: SDIRK2 start-up mode factors)
  *   scalars [8]:    eta, sum_k eta_k c_k, b0 + eta/De, gamma/dt, theta, rho, sigma1, sigma2
  *   zeta    [max_steps+1]: zeta^j (zeta^0 = zeta^1 = 0 are unused)
- * Any pointer may be NULL.
+ * Any pointer may be NULL.  TFS_SCHEME_EXP plans: tables e_k, q_k, lambda_k dt, 1 - e_k,
+ * w_k dt a0_k; scalars q = sum_k q_k, sum_k ((1 - e_k) q_k - w_k dt a0_k), 1 + q/De,
+ * gamma/dt, dt sum_k (w_k - lambda_k q_k), 0, 0, 0; zeta^{n+1} = sum_k (mu_k^{n+1} - mu_k^n).
  */
 tfs_status tfs_plan_tables(tfs_plan plan, double* tables, double* scalars, double* zeta);
 

@@ -116,6 +116,31 @@ void soe_rule(double alpha, int m, double ylo, double yhi, double* w, double* la
   }
 }
 
+// Exact one-step weights of a mode for X linear on the step (TFS_SCHEME_EXP), z = lambda dt:
+// e = exp(-z), om = 1 - e, a0 = (om - z e)/z^2, a1 = (z - om)/z^2.  Below z = 0.1 the
+// quotients lose digits, so a0 and a1 come from their Taylor series there,
+// a0 = sum_j (-z)^j (j+1)/(j+2)!, a1 = sum_j (-z)^j/(j+2)!, summed from the small end.
+void exp_mode_weights(double z, double* e, double* om, double* a0, double* a1) {
+  *e = std::exp(-z);
+  *om = -std::expm1(-z);
+  if (z < 0.1) {
+    double fac[24];
+    fac[0] = 1.0;
+    for (int j = 1; j < 24; ++j) fac[j] = fac[j - 1] * j;
+    double s0 = 0.0, s1 = 0.0;
+    for (int j = 21; j >= 0; --j) {
+      const double zj = std::pow(-z, j);
+      s0 += zj * (j + 1) / fac[j + 2];
+      s1 += zj / fac[j + 2];
+    }
+    *a0 = s0;
+    *a1 = s1;
+  } else {
+    *a0 = (*om - z * *e) / (z * z);
+    *a1 = (z - *om) / (z * z);
+  }
+}
+
 double symbol_relerr(double alpha, int m, const double* w, const double* lam, double dt, double T, int ns) {
   const double lo = std::log(0.1 / T), hi = std::log(10.0 / dt);
   double worst = 0.0;
@@ -240,6 +265,7 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   if (D.max_steps < 1) return fail(TFS_EINVAL, "max_steps must be >= 1");
   if (!D.w || !D.lambda) return fail(TFS_EINVAL, "null w or lambda");
   if (D.precision != TFS_FP64 && D.precision != TFS_FP32_MODES) return fail(TFS_EINVAL, "unknown precision");
+  if (D.scheme != TFS_SCHEME_BDF2 && D.scheme != TFS_SCHEME_EXP) return fail(TFS_EINVAL, "unknown scheme");
   for (int k = 0; k < D.nmodes; ++k)
     if (!finite_nonneg(D.w[k]) || !finite_nonneg(D.lambda[k]))
       return fail(TFS_EINVAL, "w and lambda must be finite and >= 0 (mode %d)", k);
@@ -259,6 +285,7 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   p->dt = D.dt;
   p->gamma = D.eta_p / D.De;
   p->precision = D.precision;
+  p->scheme = D.scheme;
   p->flags = D.flags;
   p->stream = static_cast<hipStream_t>(D.stream);
   p->w.assign(D.w, D.w + D.nmodes);
@@ -318,6 +345,45 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
         mu_n[k] = p->coef[tfs::kRowD * m + k] * h + p->coef[tfs::kRowC * m + k];
       }
       p->zeta[n + 1] = p->eta - acc.value();
+    }
+  }
+
+  if (p->scheme == TFS_SCHEME_EXP) {
+    // Exponential mode update: Y_k^{n+1} = e_k Y_k^n + f_k X^n with Y_k = X_k - q_k X;
+    // the mass modes mu_k (of the constant 1) give zeta^{n+1} = sum_k (mu_k^{n+1} - mu_k^n).
+    CompSum q, sh, ee;
+    std::vector<double> e(m), om(m), a0(m), a1(m);
+    for (int k = 0; k < m; ++k) {
+      const double wk = p->w[k], lk = p->lam[k];
+      exp_mode_weights(lk * dt, &e[k], &om[k], &a0[k], &a1[k]);
+      const double qk = wk * dt * a1[k], rk = wk * dt * a0[k];
+      p->coef[tfs::kRowE * m + k] = e[k];
+      p->coef[tfs::kRowF * m + k] = e[k] * qk + rk;
+      p->coef[tfs::kRowLdt * m + k] = lk * dt;
+      p->coef[tfs::kRowQ * m + k] = qk;
+      p->coef[tfs::kRowOneME * m + k] = om[k];
+      p->coef[tfs::kRowR * m + k] = rk;
+      q.add(qk);
+      sh.add(om[k] * qk - rk);
+      ee.add(dt * (wk - lk * qk));
+    }
+    p->q_e = q.value();
+    p->s_h = sh.value();
+    p->eta_e = ee.value();
+    p->eta = p->q_e;
+    p->s_ec = p->s_h;
+    p->a_diag = 1.0 + p->q_e / p->De;
+    p->theta = p->rho = p->sigma1 = p->sigma2 = p->hr = 0.0;
+    std::fill(p->zeta.begin(), p->zeta.end(), 0.0);
+    std::vector<double> mu(m, 0.0);
+    for (int64_t n = 0; n < p->max_steps; ++n) {
+      CompSum inc;
+      for (int k = 0; k < m; ++k) {
+        const double next = e[k] * mu[k] + p->w[k] * dt * (a0[k] + a1[k]);
+        inc.add(next - mu[k]);
+        mu[k] = next;
+      }
+      p->zeta[n + 1] = inc.value();
     }
   }
 
@@ -420,13 +486,16 @@ tfs_status tfs_plan_tables(tfs_plan p, double* tables, double* scalars, double* 
   if (!p) return fail(TFS_EINVAL, "null plan");
   const int m = p->m;
   if (tables) {
-    const int rows[5] = {tfs::kRowD, tfs::kRowC, tfs::kRowEta, tfs::kRowU, tfs::kRowV};
+    const int rows_b[5] = {tfs::kRowD, tfs::kRowC, tfs::kRowEta, tfs::kRowU, tfs::kRowV};
+    const int rows_e[5] = {tfs::kRowE, tfs::kRowQ, tfs::kRowLdt, tfs::kRowOneME, tfs::kRowR};
+    const int* rows = p->scheme == TFS_SCHEME_EXP ? rows_e : rows_b;
     for (int r = 0; r < 5; ++r)
       for (int k = 0; k < m; ++k) tables[r * m + k] = p->coef[rows[r] * m + k];
   }
   if (scalars) {
     const double v[8] = {p->eta, p->s_ec, p->a_diag, p->tau_scale, p->theta, p->rho, p->sigma1, p->sigma2};
-    for (int i = 0; i < 8; ++i) scalars[i] = v[i];
+    const double ve[8] = {p->q_e, p->s_h, p->a_diag, p->tau_scale, p->eta_e, 0.0, 0.0, 0.0};
+    for (int i = 0; i < 8; ++i) scalars[i] = p->scheme == TFS_SCHEME_EXP ? ve[i] : v[i];
   }
   if (zeta) for (size_t i = 0; i < p->zeta.size(); ++i) zeta[i] = p->zeta[i];
   return TFS_OK;
@@ -436,8 +505,9 @@ namespace {
 
 tfs_status run_step(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, const tfs::Levels& L,
                     double* tau, double* diag) {
-  hipError_t e = (n == 0) ? tfs::launch_startup(p, kappa_a, L, tau, diag)
-                          : tfs::launch_bdf2(p, n, kappa_a, kappa_b, L, tau, diag);
+  hipError_t e = p->scheme == TFS_SCHEME_EXP ? tfs::launch_exp(p, n, kappa_a, kappa_b, L, tau, diag)
+                 : (n == 0) ? tfs::launch_startup(p, kappa_a, L, tau, diag)
+                            : tfs::launch_bdf2(p, n, kappa_a, kappa_b, L, tau, diag);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   if (p->flags & TFS_FLAG_CHECK_SYNC) {
     e = hipStreamSynchronize(p->stream);
@@ -467,6 +537,13 @@ tfs_status tfs_step(tfs_plan p, int64_t n, const double* kappa_a, const double* 
   char* Yb = static_cast<char*>(Y);
   tfs::Levels L;
   const int sn = (int)(n % 2), sm = 1 - sn;
+  if (p->scheme == TFS_SCHEME_EXP) {
+    L.Xn = X + sn * xs;
+    L.Xo = X + sm * xs;
+    L.Yn = Yb;
+    L.Yo = Yb;
+    return run_step(p, n, kappa_a, kappa_b, L, tau, diag);
+  }
   if (n == 0) {
     L.Xn = X;
     L.Xo = X + xs;
@@ -489,6 +566,19 @@ tfs_status tfs_step_levels(tfs_plan p, int64_t n, const double* kappa_a, const d
   if (!p) return fail(TFS_EINVAL, "null plan");
   if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
                                               (long long)n, (long long)p->max_steps);
+  if (p->scheme == TFS_SCHEME_EXP) {
+    if (p->npoints > 0) {
+      if (!kappa_a || !X_n || !X_out || !Y_out) return fail(TFS_EINVAL, "null kappa_a, X or Y level");
+      if (n > 0 && !Y_n) return fail(TFS_EINVAL, "null Y_n");
+      if (X_out == X_n) return fail(TFS_EINVAL, "X_out must not alias X_n");
+    }
+    tfs::Levels L;
+    L.Xn = X_n;
+    L.Xo = X_out;
+    L.Yn = n > 0 ? Y_n : Y_out;
+    L.Yo = Y_out;
+    return run_step(p, n, kappa_a, kappa_b, L, tau, diag);
+  }
   if (p->npoints > 0) {
     if (!kappa_a || !X_n || !X_out || !Y_nm1 || !Y_out) return fail(TFS_EINVAL, "null kappa_a, X or Y level");
     if (n > 0 && (!X_nm1 || !Y_n)) return fail(TFS_EINVAL, "null level n or n-1");
@@ -519,6 +609,7 @@ tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const 
                             double* Xbar, void* Hbar, const double* taubar, double* kappabar_a,
                             double* kappabar_b, double* pbar) {
   if (!p) return fail(TFS_EINVAL, "null plan");
+  if (p->scheme == TFS_SCHEME_EXP) return fail(TFS_EUNSUPPORTED, "no adjoint for the exponential-mode scheme");
   if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
                                               (long long)n, (long long)p->max_steps);
   if (!pbar) return fail(TFS_EINVAL, "null pbar");
@@ -546,6 +637,7 @@ tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const 
 
 tfs_status tfs_pbar_to_params(tfs_plan p, const double* pb, double* dw, double* dlam, double* dDe, double* deta_p) {
   if (!p || !pb) return fail(TFS_EINVAL, "null plan or pbar");
+  if (p->scheme == TFS_SCHEME_EXP) return fail(TFS_EUNSUPPORTED, "no adjoint for the exponential-mode scheme");
   const int m = p->m;
   const double h = p->dt, b0 = tfs::kB0, gs = 1.0 - 1.0 / std::sqrt(2.0), hg = h * gs, hs = h * (1.0 - gs);
   const double iD = 1.0 / p->De;

@@ -27,11 +27,21 @@ enum CoefRow : int {
   kNumCoef = 6
 };
 
+// Rows of the same table for TFS_SCHEME_EXP plans (exponential mode update).
+enum ExpRow : int {
+  kRowE = 0,      // e_k = exp(-lambda_k dt)
+  kRowF = 1,      // f_k = e_k q_k + w_k dt a0_k: coefficient of X^n in Y_k^{n+1}
+  kRowLdt = 2,    // lambda_k dt
+  kRowQ = 3,      // q_k = w_k dt a1_k (plain modes X_k = Y_k + q_k X; same row as c_k)
+  kRowOneME = 4,  // 1 - e_k
+  kRowR = 5       // w_k dt a0_k
+};
+
 // Number of diagnostics written per step.
 constexpr int kNumDiag = 6;
-// Threads per block of every streaming kernel.
 // Largest number of sum-of-exponentials modes of a plan (bounds the adjoint LDS use).
 constexpr int kMaxModes = 256;
+// Threads per block of every streaming kernel.
 constexpr int kBlock = 256;
 // Upper bound of blocks per compute unit of the grid-stride launches (sizes the
 // diagnostic scratch).
@@ -55,6 +65,19 @@ struct Bdf2Scalars {
   double tau_scale;  // gamma/dt
 };
 
+// Per-step scalars of the exponential-mode step (TFS_SCHEME_EXP), all FP64.
+struct ExpScalars {
+  double a_diag;     // 1 + q/De: diagonal of the local operator
+  double q;          // q = sum_k q_k: weight of K X^{n+1}
+  double s_h;        // sum_k ((1 - e_k) q_k - w_k dt a0_k): X^n part of the mode decrement H
+  double inv_De;
+  double zeta;       // sum_k (mu_k^{n+1} - mu_k^n): the mass modes' increment
+  double tau_scale;  // gamma/dt
+  double eta_e;      // dt sum_k (w_k - lambda_k q_k): dt D^{1-alpha} X^{n+1} = eta_e X^{n+1} - G
+  double fa, fb;     // kappa~ = fa kappa_a + fb kappa_b
+  int first;         // n = 0: Y^0 = -q_k X^0, the mode input is not read
+};
+
 // Scalars of the SDIRK2 start-up step.
 struct StartScalars {
   double hgt;        // h gs theta: off-identity weight of the stage matrix
@@ -75,6 +98,7 @@ struct tfs_plan_s {
   int64_t tile = 0;           // mode-ring tile (points); equals stride when untiled
   double alpha = 0, De = 0, eta_p = 0, dt = 0, gamma = 0;
   int precision = 0;
+  int scheme = TFS_SCHEME_BDF2;
   uint32_t flags = 0;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -83,6 +107,7 @@ struct tfs_plan_s {
   std::vector<double> coef;   // host copy of [kNumCoef][m]
   double eta = 0, s_ec = 0, a_diag = 0, tau_scale = 0;
   double theta = 0, rho = 0, sigma1 = 0, sigma2 = 0, hg = 0, hr = 0;
+  double q_e = 0, s_h = 0, eta_e = 0;   // TFS_SCHEME_EXP scalars (ExpScalars)
   std::vector<double> zeta;   // [max_steps + 1]
 
   double* d_coef = nullptr;   // device [kNumCoef][m]
@@ -135,6 +160,10 @@ hipError_t launch_adjoint(const tfs_plan_s* p, int64_t n, const AdjLevels& L, do
 hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
                        double* tau, double* diag);
 hipError_t launch_startup(const tfs_plan_s* p, const double* ka, const Levels& L, double* tau, double* diag);
+// Exponential-mode step n -> n+1 (TFS_SCHEME_EXP): reads L.Xn and L.Yn (not at n = 0),
+// writes L.Xo and L.Yo (which may be L.Yn).
+hipError_t launch_exp(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+                      double* tau, double* diag);
 hipError_t launch_modes_to_plain(const tfs_plan_s* p, int slot, const double* X, const void* Y,
                                  double* Xk);
 // Upper bound of blocks the launchers use for a plan (sizes d_part).

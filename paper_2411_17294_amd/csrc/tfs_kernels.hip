@@ -14,11 +14,15 @@
 //     Gaussian elimination with partial pivoting.
 //   * SDIRK2 start-up (first step from rest of the modes): two stage solves with the
 //     same local matrix; the level-0 and level-1 modes are written.
+//   * Exponential-mode step (an extension, not the paper's scheme): every mode solved
+//     exactly for X linear on the step, one mode level updated in place, and the state
+//     integrated as X^{n+1} - X^n = A(sum_k (X_k^{n+1} - X_k^n)) + zeta S.
 // The mode loop is a pure stream (no MFMA: about one flop per byte); global loads of
 // the next mode are issued before the stores of the current one, so several KB per
 // wave are in flight.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -320,6 +324,183 @@ __global__ __launch_bounds__(kBlock) void start_kernel(const StartArgs<MT> a) {
   }
 }
 
+// ------------------------------------------------------------------ exponential-mode step
+// Each mode is advanced exactly for X linear on the step (TFS_SCHEME_EXP):
+//   Y_k^{n+1} = e_k Y_k^n + f_k X^n                      (Y_k = X_k - q_k X, stored in place)
+//   H  = sum_k (1 - e_k) Y_k^n + s_h X^n                  (X^{n+1} - X^n = A(q X^{n+1} - H) + zeta S)
+//   G  = sum_k lambda_k dt Y_k^{n+1}                      (dt D^{1-alpha} X^{n+1} = eta_e X^{n+1} - G)
+//   [(1 + q/De) I - q (kappa~ . + . kappa~^T)] X^{n+1} = X^n - A(H) + zeta S
+//   tau^{n+1} = (gamma/dt)(eta_e X^{n+1} - G)
+// H and G are compensated FP64 sums; one read and one write per mode-component.
+// Mode loads issued ahead of the arithmetic in the exponential-mode step.
+constexpr int kExpAhead = 2;
+
+template <typename MT>
+struct ExpArgs {
+  const double* ka;     // kappa_a [d*d][stride]
+  const double* kb;     // kappa_b or null
+  const double* Xn;     // X^n     [c][stride]
+  double* Xo;           // X^{n+1} [c][stride]
+  const MT* Yn;         // Y^n (m * c * stride elements, tiled); not read at n = 0
+  MT* Yo;               // Y^{n+1} (may be Yn: each lane reads a mode before writing it)
+  double* tau;          // [c][stride] or null
+  const double* coef;   // [kNumCoef][m], ExpRow order
+  double* part;         // block partials or null (this launch writes part[part0 + block])
+  int64_t p_begin, ngroups;
+  int64_t stride, tile;
+  int m, part0;
+  ExpScalars s;
+};
+
+template <int D, typename MT, int V, bool DIAG>
+__device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& w, DiagAcc& acc) {
+  constexpr int C = Sym<D>::C;
+  const int64_t st = a.stride;
+  const int m = a.m;
+  const int64_t T = a.tile;
+  const bool first = a.s.first != 0;
+
+  double Xc[C][V];
+#pragma unroll
+  for (int s = 0; s < C; ++s) load_v<true, double, V>(at(a.Xn + s * st + w.pw, w.ox), V, Xc[s]);
+
+  // H enters the solve only (plain FP64 sum); G is the stress's near-cancelling term
+  // (compensated)
+  double H[C][V], Gs[C][V], Ge[C][V];
+#pragma unroll
+  for (int s = 0; s < C; ++s)
+#pragma unroll
+    for (int v = 0; v < V; ++v) { H[s][v] = 0.0; Gs[s][v] = 0.0; Ge[s][v] = 0.0; }
+
+  // one read stream: the loads run kExpAhead modes ahead of the arithmetic
+  const MT* yn0 = a.Yn + w.tw;
+  MT* yo0 = a.Yo + w.tw;
+  MT buf[kExpAhead + 1][C][V];
+  if (!first) {
+#pragma unroll
+    for (int j = 0; j < kExpAhead; ++j) {
+      if (j < m) {
+        const uint32_t om = opaque(w.om);
+        const MT* b = opaque_ptr(yn0 + (int64_t)j * C * T);
+#pragma unroll
+        for (int s = 0; s < C; ++s) load_v<true, MT, V, true>(at(b + s * T, om), V, buf[j][s]);
+      }
+    }
+  }
+  for (int k = 0; k < m; ++k) {
+    const double ek = a.coef[kRowE * m + k];
+    const double fk = a.coef[kRowF * m + k];
+    const double lk = a.coef[kRowLdt * m + k];
+    const double qk = a.coef[kRowQ * m + k];
+    const double ok = a.coef[kRowOneME * m + k];
+    if (!first && k + kExpAhead < m) {
+      const uint32_t om = opaque(w.om);
+      const MT* b = opaque_ptr(yn0 + (int64_t)(k + kExpAhead) * C * T);
+#pragma unroll
+      for (int s = 0; s < C; ++s) load_v<true, MT, V, true>(at(b + s * T, om), V, buf[kExpAhead][s]);
+    }
+    const uint32_t om = opaque(w.om);
+    MT* bo = opaque_ptr(yo0 + (int64_t)k * C * T);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      MT out[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double y = first ? -qk * Xc[s][v] : (double)buf[0][s][v];
+        out[v] = (MT)(ek * y + fk * Xc[s][v]);
+        H[s][v] += ok * y;
+        two_sum_acc(Gs[s][v], Ge[s][v], mul_rn(lk, (double)out[v]));
+      }
+      store_v<true, MT, V, true>(at(bo + s * T, om), V, out);
+    }
+    if (!first) {
+#pragma unroll
+      for (int j = 0; j < kExpAhead; ++j)
+#pragma unroll
+        for (int s = 0; s < C; ++s)
+#pragma unroll
+          for (int v = 0; v < V; ++v) buf[j][s][v] = buf[j + 1][s][v];
+    }
+  }
+
+  // the local solve point by point (kappa loaded per point): one c x c system live at a time.
+  // X^{n+1} and tau are stored V-wide at the end; in 3-D the finished points wait in LDS
+  // instead of registers.
+  constexpr bool kLds = (D == 3);
+  __shared__ double stage[(kLds && V > 1) ? 2 * C * (V - 1) : 1][kBlock];
+  double Xout[C][V], Tout[C][V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const uint32_t ox = w.ox + v * 8;
+    double k[D * D], Hv[C], AH[C], R[C];
+#pragma unroll
+    for (int q = 0; q < D * D; ++q) {
+      double x[1];
+      load_v<true, double, 1>(at(a.ka + q * st + w.pw, ox), 1, x);
+      k[q] = x[0];
+      if (a.kb) {
+        load_v<true, double, 1>(at(a.kb + q * st + w.pw, ox), 1, x);
+        k[q] = a.s.fa * k[q] + a.s.fb * x[0];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < C; ++s) Hv[s] = H[s][v] + a.s.s_h * Xc[s][v];
+    apply_K<D>(k, Hv, AH);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+      const double S = k[i * D + j] + k[j * D + i];
+      R[s] = Xc[s][v] - (AH[s] - a.s.inv_De * Hv[s]) + a.s.zeta * S;
+    }
+    double M[C][C];
+    build_M<D>(k, a.s.a_diag, a.s.q, M);
+    solve_pivot<C>(M, R);
+    double ts[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      ts[s] = a.s.tau_scale * (a.s.eta_e * R[s] - (Gs[s][v] + Ge[s][v]));
+      if (kLds && v + 1 < V) {
+        stage[(2 * s) * (V - 1) + v][threadIdx.x] = R[s];
+        stage[(2 * s + 1) * (V - 1) + v][threadIdx.x] = ts[s];
+      } else {
+        Xout[s][v] = R[s];
+        Tout[s][v] = ts[s];
+      }
+    }
+    if constexpr (DIAG) diag_point<D>(acc, R, ts);
+  }
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    if constexpr (kLds) {
+#pragma unroll
+      for (int v = 0; v + 1 < V; ++v) {
+        Xout[s][v] = stage[(2 * s) * (V - 1) + v][threadIdx.x];
+        Tout[s][v] = stage[(2 * s + 1) * (V - 1) + v][threadIdx.x];
+      }
+    }
+    store_v<true, double, V>(at(a.Xo + s * st + w.pw, w.ox), V, Xout[s]);
+    if (a.tau) store_v<true, double, V>(at(a.tau + s * st + w.pw, w.ox), V, Tout[s]);
+  }
+}
+
+template <int D, typename MT, int V, bool DIAG>
+__global__ __launch_bounds__(kBlock) void exp_kernel(const ExpArgs<MT> a) {
+  constexpr int C = Sym<D>::C;
+  DiagAcc acc;
+  const int lane = threadIdx.x % 64;
+  const int64_t nwaves = (a.ngroups + 63) / 64;
+  const int64_t wstride = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
+       wv += wstride) {
+    if (wv * 64 + lane < a.ngroups)
+      exp_group<D, MT, V, DIAG>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
+  }
+  if constexpr (DIAG) {
+    const DiagAcc r = block_reduce(acc);
+    if (threadIdx.x == 0) write_partial(a.part, a.part0 + blockIdx.x, r);
+  }
+}
+
 // ------------------------------------------------------------------ plain modes
 template <typename MT>
 __global__ __launch_bounds__(kBlock) void plain_kernel(const double* __restrict__ X, const MT* __restrict__ Y,
@@ -352,8 +533,9 @@ bool aligned(const void* ptr, size_t bytes) { return ptr == nullptr || ((uintptr
 // group start is aligned to the vector size of each field (modes: V * sizeof(MT); FP64
 // fields: V * 8).
 template <int D, typename MT>
-int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const Levels& L, const void* tau) {
-  const int widest = sizeof(MT) == 4 ? 4 : 2;
+int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const Levels& L, const void* tau,
+             int max_v = 4) {
+  const int widest = std::min(max_v, sizeof(MT) == 4 ? 4 : 2);
   const int cand[3] = {widest, 2, 1};
   for (int V : cand) {
     if (V > widest) continue;
@@ -492,6 +674,68 @@ hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, const Levels& L
   return start_go<D, MT, 1>(p, a, dg, diag);
 }
 
+template <int D, typename MT, int V, bool DIAG>
+hipError_t exp_launch(const tfs_plan_s* p, ExpArgs<MT> a, int64_t p_begin, int64_t ngroups, int part0,
+                      int* nblocks) {
+  a.p_begin = p_begin;
+  a.ngroups = ngroups;
+  a.part0 = part0;
+  const int grid = grid_for(p, ngroups);
+  hipLaunchKernelGGL((exp_kernel<D, MT, V, DIAG>), dim3(grid), dim3(kBlock), 0, p->stream, a);
+  *nblocks = grid;
+  return hipGetLastError();
+}
+
+template <int D, typename MT, int V, bool DIAG>
+hipError_t exp_go_(const tfs_plan_s* p, const ExpArgs<MT>& a, double* diag_out) {
+  const int64_t full = p->npoints / V, rest = p->npoints - full * V;
+  int nb = 0, nt = 0;
+  hipError_t e = hipSuccess;
+  if (full > 0) e = exp_launch<D, MT, V, DIAG>(p, a, 0, full, 0, &nb);
+  if (e == hipSuccess && rest > 0) e = exp_launch<D, MT, 1, DIAG>(p, a, full * V, rest, nb, &nt);
+  if (e == hipSuccess && DIAG)
+    hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, a.part, nb + nt, diag_out);
+  return e == hipSuccess ? hipGetLastError() : e;
+}
+
+template <int D, typename MT>
+hipError_t exp_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+                        double* tau, double* diag) {
+  ExpArgs<MT> a;
+  a.ka = ka;
+  a.kb = (n >= 1) ? kb : nullptr;
+  a.Xn = L.Xn;
+  a.Xo = L.Xo;
+  a.Yn = static_cast<const MT*>(L.Yn);
+  a.Yo = static_cast<MT*>(L.Yo);
+  a.tau = tau;
+  a.coef = p->d_coef;
+  a.part = p->d_part;
+  a.stride = p->stride;
+  a.tile = p->tile;
+  a.m = p->m;
+  a.s.a_diag = 1.0 + p->q_e / p->De;
+  a.s.q = p->q_e;
+  a.s.s_h = p->s_h;
+  a.s.inv_De = 1.0 / p->De;
+  a.s.zeta = p->zeta[n + 1];
+  a.s.tau_scale = p->tau_scale;
+  a.s.eta_e = p->eta_e;
+  a.s.fa = 1.5;
+  a.s.fb = -0.5;
+  a.s.first = n == 0 ? 1 : 0;
+  // the level-n modes are read (not at n = 0) and written: both alignments matter
+  Levels A = L;
+  A.Ym = nullptr;
+  // two compensated sums per component: in 3-D four points per lane would spill
+  const int V = pick_vec<D, MT>(p, ka, a.kb, A, tau, D == 3 ? 2 : 4);
+  if constexpr (sizeof(MT) == 4 && D == 2) {
+    if (V == 4) return diag ? exp_go_<D, MT, 4, true>(p, a, diag) : exp_go_<D, MT, 4, false>(p, a, diag);
+  }
+  if (V == 2) return diag ? exp_go_<D, MT, 2, true>(p, a, diag) : exp_go_<D, MT, 2, false>(p, a, diag);
+  return diag ? exp_go_<D, MT, 1, true>(p, a, diag) : exp_go_<D, MT, 1, false>(p, a, diag);
+}
+
 }  // namespace
 
 // a V-wide pass and a V = 1 tail pass
@@ -522,10 +766,24 @@ hipError_t launch_startup(const tfs_plan_s* p, const double* ka, const Levels& L
                    : start_dispatch<3, float>(p, ka, L, tau, diag);
 }
 
+hipError_t launch_exp(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+                      double* tau, double* diag) {
+  if (p->npoints == 0) {
+    if (diag) hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, p->d_part, 0, diag);
+    return hipGetLastError();
+  }
+  if (p->precision == TFS_FP64)
+    return p->d == 2 ? exp_dispatch<2, double>(p, n, ka, kb, L, tau, diag)
+                     : exp_dispatch<3, double>(p, n, ka, kb, L, tau, diag);
+  return p->d == 2 ? exp_dispatch<2, float>(p, n, ka, kb, L, tau, diag)
+                   : exp_dispatch<3, float>(p, n, ka, kb, L, tau, diag);
+}
+
 hipError_t launch_modes_to_plain(const tfs_plan_s* p, int slot, const double* X, const void* Y, double* Xk) {
   if (p->npoints == 0) return hipSuccess;
   const int64_t st = p->stride;
   const double* Xs = X + (int64_t)slot * p->c * st;
+  if (p->scheme == TFS_SCHEME_EXP) slot = 0;   // one mode level, paired with X slot `slot`
   const int64_t total = (int64_t)p->m * p->c * p->npoints;
   int grid = (int)((total + kBlock - 1) / kBlock);
   if (grid > 65536) grid = 65536;

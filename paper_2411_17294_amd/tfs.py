@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtfs.so")
 
 TFS_OK, TFS_EINVAL, TFS_ENOMEM, TFS_EHIP, TFS_ENUMERIC, TFS_EUNSUPPORTED = range(6)
 TFS_FP64, TFS_FP32_MODES = 0, 1
+TFS_SCHEME_BDF2, TFS_SCHEME_EXP = 0, 1
 TFS_FLAG_CHECK_SYNC = 1
 
 EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_step", "tfs_step_levels",
@@ -42,7 +43,8 @@ class PlanDesc(C.Structure):
                 ("tile", C.c_int64),
                 ("alpha", C.c_double), ("De", C.c_double), ("eta_p", C.c_double), ("dt", C.c_double),
                 ("max_steps", C.c_int64), ("w", C.POINTER(C.c_double)), ("lam", C.POINTER(C.c_double)),
-                ("precision", C.c_int32), ("flags", C.c_uint32), ("stream", C.c_void_p)]
+                ("precision", C.c_int32), ("flags", C.c_uint32), ("stream", C.c_void_p),
+                ("scheme", C.c_int32)]
 
 
 _lib = None
@@ -127,7 +129,7 @@ class Plan:
     """One tfs_plan: dim, m, npoints, parameters and the (w, lambda) table."""
 
     def __init__(self, dim, npoints, w, lam, alpha, De, eta_p, dt, max_steps, precision="fp64",
-                 stride=0, tile=None, flags=0, stream=None):
+                 stride=0, tile=None, flags=0, stream=None, scheme="bdf2"):
         import torch
         self.dim = int(dim)
         self.c = self.dim * (self.dim + 1) // 2
@@ -140,13 +142,17 @@ class Plan:
         self.precision = {"fp64": TFS_FP64, "fp32_modes": TFS_FP32_MODES}[precision] \
             if isinstance(precision, str) else int(precision)
         self.mode_dtype = torch.float64 if self.precision == TFS_FP64 else torch.float32
+        self.scheme = {"bdf2": TFS_SCHEME_BDF2, "exp": TFS_SCHEME_EXP}[scheme] \
+            if isinstance(scheme, str) else int(scheme)
+        # mode levels the caller keeps: a two-slot ring (BDF2) or one level updated in place
+        self.mode_levels = 1 if self.scheme == TFS_SCHEME_EXP else 2
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         if tile is None:
             tile = DEFAULT_TILE[self.dim]
         d = PlanDesc(self.dim, self.m, self.npoints, int(stride), int(tile), self.alpha, self.De, self.eta_p, self.dt,
                      self.max_steps, _dptr(self.w), _dptr(self.lam), self.precision, int(flags),
-                     C.c_void_p(stream))
+                     C.c_void_p(stream), self.scheme)
         h = C.c_void_p()
         check(lib().tfs_plan_create(C.byref(d), C.byref(h)))
         self._h = h
@@ -180,7 +186,7 @@ class Plan:
         import torch
         st = self.stride
         X = torch.zeros((2, self.c, st), dtype=torch.float64, device=device)
-        Y = torch.zeros((2 * self.m * self.c * st,), dtype=self.mode_dtype, device=device)
+        Y = torch.zeros((self.mode_levels * self.m * self.c * st,), dtype=self.mode_dtype, device=device)
         tau = torch.zeros((self.c, st), dtype=torch.float64, device=device)
         diag = torch.zeros(6, dtype=torch.float64, device=device)
         return X, Y, tau, diag
@@ -202,7 +208,7 @@ class Plan:
             self._need(kappa_a, "kappa_a", d * d * st, torch.float64)
             self._need(kappa_b, "kappa_b", d * d * st, torch.float64)
             self._need(X, "X", 2 * c * st, torch.float64)
-            self._need(Y, "Y", 2 * self.m * c * st, self.mode_dtype)
+            self._need(Y, "Y", self.mode_levels * self.m * c * st, self.mode_dtype)
             self._need(tau, "tau", c * st, torch.float64)
         self._need(diag, "diag", 6, torch.float64)
         check(lib().tfs_step(self._h, int(n), _tptr(kappa_a), _tptr(kappa_b), _tptr(X), _tptr(Y), _tptr(tau),
@@ -259,7 +265,7 @@ class Plan:
         import torch
         st, c = self.stride, self.c
         self._need(X, "X", 2 * c * st, torch.float64)
-        self._need(Y, "Y", 2 * self.m * c * st, self.mode_dtype)
+        self._need(Y, "Y", self.mode_levels * self.m * c * st, self.mode_dtype)
         self._need(out, "out", self.m * c * st, torch.float64)
         check(lib().tfs_modes_to_plain(self._h, int(slot), _tptr(X), _tptr(Y), _tptr(out)))
 

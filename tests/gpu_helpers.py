@@ -17,7 +17,7 @@ def relerr(a, b):
 
 def run_gpu(d, w, lam, De, eta_p, dt, nsteps, kappa, X0, precision="fp64", extrap=True, stride=0,
             offset=0, want_modes=False, want_diag=False, alpha=0.5, vec=None, flags=0, max_steps=None,
-            tile=None):
+            tile=None, scheme="bdf2"):
     """Run nsteps steps on the GPU for small host inputs.
 
     kappa: [d*d][P] steady or [nlev][d*d][P]; X0: [c][P].  offset shifts every field base
@@ -25,7 +25,7 @@ def run_gpu(d, w, lam, De, eta_p, dt, nsteps, kappa, X0, precision="fp64", extra
     c = d * (d + 1) // 2
     P = X0.shape[1]
     plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, max_steps or max(nsteps, 1), precision=precision,
-                    stride=stride, tile=tile, flags=flags)
+                    stride=stride, tile=tile, flags=flags, scheme=scheme)
     if vec is not None:
         plan.tune("vec", vec)
     st = plan.stride
@@ -38,7 +38,7 @@ def run_gpu(d, w, lam, De, eta_p, dt, nsteps, kappa, X0, precision="fp64", extra
         return buf[offset:].view(*shape)
 
     X = field((2, c, st), torch.float64)
-    Y = field((2 * m * c * st,), plan.mode_dtype)
+    Y = field((plan.mode_levels * m * c * st,), plan.mode_dtype)
     tau = field((c, st), torch.float64)
     diag = field((6,), torch.float64)
     X[0, :, :P] = torch.from_numpy(np.ascontiguousarray(X0)).to(dev)
@@ -67,7 +67,7 @@ def run_gpu(d, w, lam, De, eta_p, dt, nsteps, kappa, X0, precision="fp64", extra
            "tau": tau[:, :P].cpu().numpy()}
     if want_modes:
         mods = []
-        for lv in (N, N - 1):
+        for lv in ((N, N - 1) if plan.mode_levels == 2 else (N,)):
             o = torch.zeros((m, c, st), dtype=torch.float64, device=dev)
             plan.modes_to_plain(lv % 2, X, Y, o)
             mods.append(o[:, :, :P].cpu().numpy())

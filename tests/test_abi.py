@@ -32,14 +32,14 @@ def test_library_exports_every_declared_function():
 def _desc(**kw):
     w = np.array([1.0, 0.5]); lam = np.array([0.0, 3.0])
     base = dict(dim=2, nmodes=2, npoints=10, stride=0, tile=0, alpha=0.5, De=1.0, eta_p=0.1, dt=1e-3,
-                max_steps=10, w=w, lam=lam, precision=0, flags=0)
+                max_steps=10, w=w, lam=lam, precision=0, flags=0, scheme=0)
     base.update(kw)
     d = tfs.PlanDesc(base["dim"], base["nmodes"], base["npoints"], base["stride"], base["tile"], base["alpha"],
                      base["De"],
                      base["eta_p"], base["dt"], base["max_steps"],
                      np.ascontiguousarray(base["w"], dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double)),
                      np.ascontiguousarray(base["lam"], dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double)),
-                     base["precision"], base["flags"], None)
+                     base["precision"], base["flags"], None, base["scheme"])
     d._keep = (base["w"], base["lam"])
     return d
 
@@ -47,7 +47,8 @@ def _desc(**kw):
 @pytest.mark.parametrize("bad", [dict(dim=1), dict(dim=4), dict(nmodes=0), dict(npoints=-1),
                                  dict(stride=5), dict(tile=-4), dict(tile=6), dict(tile=8, stride=12),
                                  dict(alpha=0.0), dict(alpha=1.5), dict(De=0.0),
-                                 dict(eta_p=-1.0), dict(dt=0.0), dict(max_steps=0), dict(precision=7),
+                                 dict(eta_p=-1.0), dict(dt=0.0), dict(max_steps=0), dict(precision=7), dict(scheme=2),
+                                 dict(scheme=-1), dict(nmodes=257, w=np.ones(257), lam=np.ones(257)),
                                  dict(w=np.array([1.0, -0.5])), dict(lam=np.array([0.0, np.nan]))])
 def test_plan_create_rejects_invalid_descriptor(bad):
     L = tfs.lib()
