@@ -456,6 +456,258 @@ __global__ __launch_bounds__(kBlock) void adj_kernel(const AdjArgs<MT> a) {
   write_block_partial(a.part + (size_t)a.part0 * (3 * a.m + kNumAdjScalars), a.m, smode, sc);
 }
 
+// ------------------------------------------------------------------ exponential-mode step adjoint
+// Reverse of the TFS_SCHEME_EXP step (the forward is in the step kernels' source):
+//   Y_k^{n+1} = e_k Y_k^n + f_k X^n,  H = sum_k om_k Y_k^n + s_h X^n,  G = sum_k l_k Y_k^{n+1},
+//   M X^{n+1} = X^n - A(H) + zeta S (M = a I - q K),  tau = ts (eta_e X^{n+1} - G).
+// With Gbar = -ts taubar, Rbar = M^{-T}(Xbar^{n+1} + ts eta_e taubar), Hbar = -K^T Rbar + Rbar/De:
+//   Yhat_k = Ybar_k^{n+1} + l_k Gbar,   Ybar_k^n = e_k Yhat_k + om_k Hbar   (one level, in place)
+//   Xbar^n = Rbar + s_h Hbar + sum_k f_k Yhat_k   (at n = 0 also - sum_k q_k Ybar_k^0)
+// and per mode dL/dw_k, dL/dlambda_k through e_k, f_k, om_k, l_k (and q_k at n = 0).
+template <typename MT>
+struct ExpAdjArgs {
+  const double* ka;
+  const double* kb;      // null: kappa~ = kappa_a
+  const double* Xn;      // forward X^n
+  const double* Xp;      // forward X^{n+1}
+  const MT* Yn;          // forward Y^n (one level, tiled); not read at n = 0
+  const double* Xb_in;   // Xbar^{n+1} (ring slot (n+1)%2)
+  double* Xb_out;        // Xbar^n (ring slot n%2), overwritten
+  MT* H;                 // Ybar^{n+1} in, Ybar^n out (one level); not written at n = 0
+  const double* taubar;  // [c][stride] or null
+  double* kba;           // kappa_a adjoint (+=) or null
+  double* kbb;           // kappa_b adjoint (+=) or null
+  int kb_same;
+  const double* coef;
+  double* part;
+  int64_t p_begin, ngroups;
+  int64_t stride, tile;
+  int m, part0;
+  ExpScalars s;
+  double dt;
+};
+
+template <int D, typename MT, int V, bool FULL>
+__device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const WaveAddr& w, int nv, double* smode,
+                                              double* slot, double (&sc)[kNumAdjScalars]) {
+  constexpr int C = Sym<D>::C;
+  const int64_t st = a.stride;
+  const int m = a.m;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool first = a.s.first != 0;
+  auto lds = [&](int v, int j) -> double& { return slot[(v * C + j) * kBlock + threadIdx.x]; };
+  const double ts = a.s.tau_scale, eta_e = a.s.eta_e, q = a.s.q;
+
+  // ---- local part, point by point
+  double Gb[C][V], Hb[C][V], Xc[C][V], Xacc[C][V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const uint32_t ox = w.ox + v * 8;
+    const int nv1 = v < nv ? 1 : 0;
+    double k[D * D], xp[C], rb[C], tv[C], S[C];
+#pragma unroll
+    for (int t = 0; t < D * D; ++t) {
+      double x[1];
+      load_v<FULL, double, 1>(at(a.ka + t * st + w.pw, ox), nv1, x);
+      k[t] = x[0];
+      if (a.kb) {
+        load_v<FULL, double, 1>(at(a.kb + t * st + w.pw, ox), nv1, x);
+        k[t] = a.s.fa * k[t] + a.s.fb * x[0];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      double x[1];
+      load_v<FULL, double, 1>(at(a.Xp + s * st + w.pw, ox), nv1, x);
+      xp[s] = x[0];
+      tv[s] = 0.0;
+      if (a.taubar) {
+        load_v<FULL, double, 1>(at(a.taubar + s * st + w.pw, ox), nv1, x);
+        tv[s] = x[0];
+      }
+      load_v<FULL, double, 1>(at(a.Xb_in + s * st + w.pw, ox), nv1, x);
+      rb[s] = x[0] + ts * eta_e * tv[s];          // tau = ts (eta_e X+ - G)
+      load_v<FULL, double, 1>(at(a.Xn + s * st + w.pw, ox), nv1, x);
+      Xc[s][v] = x[0];
+      const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+      S[s] = k[i * D + j] + k[j * D + i];
+    }
+    sc[4] += ts * dot<C>(tv, xp);                  // eta_e
+    sc[6] += eta_e * dot<C>(tv, xp);               // ts (X+ part; the G part follows the modes)
+    {
+      double M[C][C];
+      build_M<D>(k, a.s.a_diag, q, M);
+      solve_transposed<C>(M, rb);                  // Rbar = M^{-T} Xbar
+    }
+    double Kx[C], u[C];
+    apply_K<D>(k, xp, Kx);
+    sc[0] += -dot<C>(rb, xp);                      // a
+    sc[1] += dot<C>(rb, Kx);                       // q (matrix)
+    sc[5] += dot<C>(rb, S);                        // zeta
+    apply_KT<D>(k, rb, u);
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      Hb[t][v] = -u[t] + a.s.inv_De * rb[t];       // R = X^n - K H + H/De
+      Gb[t][v] = -ts * tv[t];
+      Xacc[t][v] = rb[t] + a.s.s_h * Hb[t][v];
+      lds(v, t) = rb[t];
+    }
+    double hx = 0.0;
+#pragma unroll
+    for (int t = 0; t < C; ++t) hx += Hb[t][v] * Xc[t][v];
+    sc[2] += hx;                                   // s_h
+  }
+
+  // ---- mode stream: forward Y^n and the adjoint level, in place
+  const int64_t T = a.tile;
+  const MT* yp = a.Yn + w.tw;
+  MT* hp = a.H + w.tw;
+  double Hs[C][V], Gs[C][V];
+#pragma unroll
+  for (int s = 0; s < C; ++s)
+#pragma unroll
+    for (int v = 0; v < V; ++v) { Hs[s][v] = 0.0; Gs[s][v] = 0.0; }
+  for (int k = 0; k < m; ++k) {
+    const double ek = a.coef[kRowE * m + k];
+    const double fk = a.coef[kRowF * m + k];
+    const double lk = a.coef[kRowLdt * m + k];
+    const double qk = a.coef[kRowQ * m + k];
+    const double ok = a.coef[kRowOneME * m + k];
+    const double fw = a.coef[kRowFW * m + k];
+    const double fl = a.coef[kRowFL * m + k];
+    const double qw = a.coef[kRowQW * m + k];
+    const double ql = a.coef[kRowQL * m + k];
+    const double edt = ek * a.dt;
+    MT cy[C][V], ch[C][V];
+    {
+      const uint32_t om = opaque(w.om);
+      const int64_t o = (int64_t)k * C * T;
+      const MT* by = opaque_ptr(yp + o);
+      const MT* bh = opaque_ptr(hp + o);
+#pragma unroll
+      for (int s = 0; s < C; ++s) {
+        if (!first) load_v<FULL, MT, V, true>(at(by + s * T, om), nv, cy[s]);
+        load_v<FULL, MT, V, true>(at(bh + s * T, om), nv, ch[s]);
+      }
+    }
+    double gw = 0.0, gl = 0.0;
+    const uint32_t om = opaque(w.om);
+    MT* bo = opaque_ptr(hp + (int64_t)k * C * T);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      MT out[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double x = Xc[s][v];
+        const double y = first ? -qk * x : (double)cy[s][v];
+        const double yn1 = (double)(MT)(ek * y + fk * x);          // forward Y^{n+1} as stored
+        const double yh = (double)ch[s][v] + lk * Gb[s][v];        // Yhat
+        const double yb = ek * yh + ok * Hb[s][v];                 // Ybar^n
+        Hs[s][v] += ok * y;
+        Gs[s][v] += lk * yn1;
+        Xacc[s][v] += fk * yh;
+        gw += fw * (yh * x);
+        gl += edt * ((Hb[s][v] - yh) * y) + fl * (yh * x) + a.dt * (Gb[s][v] * yn1);
+        if (first) {
+          Xacc[s][v] -= qk * yb;                                   // Y^0 = -q_k X^0
+          gw += qw * (yb * x);
+          gl += ql * (yb * x);
+        }
+        out[v] = (MT)yb;
+      }
+      if (!first) store_v<FULL, MT, V, true>(at(bo + s * T, om), nv, out);
+    }
+    gw = wave_total(gw);
+    gl = wave_total(gl);
+    if (lane == 0) {
+      smode[wave * 3 * m + k] += gw;
+      smode[wave * 3 * m + m + k] += gl;
+    }
+  }
+
+  // ---- terms that need H and G, Xbar^n, and the kappa adjoints
+  double kbar[D * D][V];
+  {
+    double tb[C][V], Xp[C][V];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      load_v<FULL, double, V>(at(a.Xp + s * st + w.pw, w.ox), nv, Xp[s]);
+      if (a.taubar) load_v<FULL, double, V>(at(a.taubar + s * st + w.pw, w.ox), nv, tb[s]);
+      else
+#pragma unroll
+        for (int v = 0; v < V; ++v) tb[s][v] = 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      double Hv[C], Z[C], rb[C], tv[C], kb_[D * D];
+#pragma unroll
+      for (int s = 0; s < C; ++s) {
+        Hv[s] = Hs[s][v] + a.s.s_h * Xc[s][v];
+        Z[s] = q * Xp[s][v] - Hv[s];               // M X+ = R: -q K X+ in M, -K H in R
+        rb[s] = lds(v, s);
+        tv[s] = tb[s][v];
+      }
+      double gv = 0.0;
+#pragma unroll
+      for (int s = 0; s < C; ++s) gv += tv[s] * Gs[s][v];
+      sc[3] += dot<C>(rb, Hv);                     // 1/De
+      sc[6] += -gv;                                // ts (G part)
+#pragma unroll
+      for (int t = 0; t < D * D; ++t) kb_[t] = 0.0;
+      kgrad_VZ<D>(kb_, 1.0, rb, Z);
+      kgrad_V<D>(kb_, a.s.zeta, rb);
+#pragma unroll
+      for (int t = 0; t < D * D; ++t) kbar[t][v] = kb_[t];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < C; ++s) store_v<FULL, double, V>(at(a.Xb_out + s * st + w.pw, w.ox), nv, Xacc[s]);
+  double fa = 1.0, fb = 0.0;
+  if (a.kb && !a.kb_same) { fa = a.s.fa; fb = a.s.fb; }
+  else if (a.kb && a.kb_same) { fa = a.s.fa + a.s.fb; fb = 0.0; }
+#pragma unroll
+  for (int t = 0; t < D * D; ++t) {
+    if (a.kba) {
+      double x[V];
+      load_v<FULL, double, V>(at(a.kba + t * st + w.pw, w.ox), nv, x);
+#pragma unroll
+      for (int v = 0; v < V; ++v) x[v] += fa * kbar[t][v];
+      store_v<FULL, double, V>(at(a.kba + t * st + w.pw, w.ox), nv, x);
+    }
+    if (a.kbb && fb != 0.0) {
+      double x[V];
+      load_v<FULL, double, V>(at(a.kbb + t * st + w.pw, w.ox), nv, x);
+#pragma unroll
+      for (int v = 0; v < V; ++v) x[v] += fb * kbar[t][v];
+      store_v<FULL, double, V>(at(a.kbb + t * st + w.pw, w.ox), nv, x);
+    }
+  }
+}
+
+template <int D, typename MT, int V, bool FULL>
+__global__ __launch_bounds__(kBlock) void exp_adj_kernel(const ExpAdjArgs<MT> a) {
+  constexpr int C = Sym<D>::C;
+  extern __shared__ double smem[];    // [kBlock/64][3][m] mode sums, then Rbar per lane
+  double* smode = smem;
+  double* slot = smem + (kBlock / 64) * 3 * a.m;
+  for (int j = threadIdx.x; j < (kBlock / 64) * 3 * a.m; j += kBlock) smode[j] = 0.0;
+  __syncthreads();
+  double sc[kNumAdjScalars];
+#pragma unroll
+  for (int i = 0; i < kNumAdjScalars; ++i) sc[i] = 0.0;
+  const int lane = threadIdx.x % 64;
+  const int64_t nwaves = (a.ngroups + 63) / 64;
+  const int64_t wstride = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
+       wv += wstride) {
+    const WaveAddr w = wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m);
+    const int nv = (FULL || wv * 64 + lane < a.ngroups) ? V : 0;
+    exp_adj_group<D, MT, V, FULL>(a, w, nv, smode, slot, sc);
+  }
+  __syncthreads();
+  write_block_partial(a.part + (size_t)a.part0 * (3 * a.m + kNumAdjScalars), a.m, smode, sc);
+}
+
 // ------------------------------------------------------------------ start-up adjoint
 template <typename MT>
 struct StartAdjArgs {
@@ -774,6 +1026,86 @@ int adj_vec(const tfs_plan_s* p, const AdjLevels& L) {
   return 1;
 }
 
+size_t exp_adj_shared_bytes(const tfs_plan_s* p, int V) {
+  return sizeof(double) * ((size_t)(kBlock / 64) * 3 * p->m + (size_t)p->c * V * kBlock);
+}
+
+template <int D, typename MT, int V>
+hipError_t exp_adj_go(const tfs_plan_s* p, ExpAdjArgs<MT> a, int64_t zeta_dest, double* pbar) {
+  const int64_t nwaves = p->npoints / (64 * V);
+  const int64_t p_tail = nwaves * 64 * V, rest = p->npoints - p_tail;
+  int nb = 0, nt = 0;
+  if (nwaves > 0) {
+    a.p_begin = 0;
+    a.ngroups = nwaves * 64;
+    a.part0 = 0;
+    nb = grid_adj(p, a.ngroups);
+    const size_t shm = exp_adj_shared_bytes(p, V);
+    if (shm > 65536) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&exp_adj_kernel<D, MT, V, true>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((exp_adj_kernel<D, MT, V, true>), dim3(nb), dim3(kBlock), shm, p->stream, a);
+  }
+  if (rest > 0) {
+    a.p_begin = p_tail;
+    a.ngroups = rest;
+    a.part0 = nb;
+    nt = grid_adj(p, rest);
+    hipLaunchKernelGGL((exp_adj_kernel<D, MT, 1, false>), dim3(nt), dim3(kBlock), exp_adj_shared_bytes(p, 1),
+                       p->stream, a);
+  }
+  const int np = 3 * p->m + kNumAdjScalars;
+  hipLaunchKernelGGL(adj_finish_kernel, dim3(np), dim3(kBlock), 0, p->stream, a.part, nb + nt, np,
+                     p->d_dest_exp, zeta_dest, pbar);
+  return hipGetLastError();
+}
+
+template <int D, typename MT>
+hipError_t exp_adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, double* pbar) {
+  const int64_t st = p->stride;
+  const int64_t xs = (int64_t)Sym<D>::C * st;
+  const int sn = (int)(n % 2), sp = 1 - sn;
+  ExpAdjArgs<MT> a;
+  a.ka = L.ka;
+  a.kb = n >= 1 ? L.kb : nullptr;
+  a.Xn = L.Xn;
+  a.Xp = L.Xp;
+  a.Yn = static_cast<const MT*>(L.Yn);
+  a.Xb_in = L.Xbar + sp * xs;
+  a.Xb_out = L.Xbar + sn * xs;
+  a.H = static_cast<MT*>(L.Hbar);
+  a.taubar = L.taubar;
+  a.kba = L.kba;
+  a.kbb = L.kbb;
+  a.kb_same = (L.kba != nullptr && L.kba == L.kbb) ? 1 : 0;
+  a.coef = p->d_coef;
+  a.part = p->d_adj_part;
+  a.stride = st;
+  a.tile = p->tile;
+  a.m = p->m;
+  a.s.a_diag = 1.0 + p->q_e / p->De;
+  a.s.q = p->q_e;
+  a.s.s_h = p->s_h;
+  a.s.inv_De = 1.0 / p->De;
+  a.s.zeta = p->zeta[n + 1];
+  a.s.tau_scale = p->tau_scale;
+  a.s.eta_e = p->eta_e;
+  a.s.fa = 1.5;
+  a.s.fb = -0.5;
+  a.s.first = n == 0 ? 1 : 0;
+  a.dt = p->dt;
+  const int64_t zd = (int64_t)kPbarScalars + 6 * p->m + n + 1;
+  const int want = p->adj_vec_override ? p->adj_vec_override : (sizeof(MT) == 4 ? 2 : 1);
+  bool two = want == 2 && p->stride % 2 == 0 && p->tile % 2 == 0 && exp_adj_shared_bytes(p, 2) <= (size_t)p->lds_max;
+  const size_t bm = 2 * sizeof(MT), bd = 16;
+  two = two && al(L.ka, bd) && al(L.kb, bd) && al(L.Xn, bd) && al(L.Xp, bd) && al(L.Xbar, bd) &&
+        al(L.taubar, bd) && al(L.kba, bd) && al(L.kbb, bd) && al(L.Yn, bm) && al(L.Hbar, bm);
+  if (two) return exp_adj_go<D, MT, 2>(p, a, zd, pbar);
+  return exp_adj_go<D, MT, 1>(p, a, zd, pbar);
+}
+
 template <int D, typename MT>
 hipError_t adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, double* pbar) {
   const int64_t st = p->stride;
@@ -844,6 +1176,11 @@ hipError_t adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, doub
 
 hipError_t launch_adjoint(const tfs_plan_s* p, int64_t n, const AdjLevels& L, double* pbar) {
   if (p->npoints == 0) return hipSuccess;
+  if (p->scheme == TFS_SCHEME_EXP) {
+    if (p->precision == TFS_FP64)
+      return p->d == 2 ? exp_adj_dispatch<2, double>(p, n, L, pbar) : exp_adj_dispatch<3, double>(p, n, L, pbar);
+    return p->d == 2 ? exp_adj_dispatch<2, float>(p, n, L, pbar) : exp_adj_dispatch<3, float>(p, n, L, pbar);
+  }
   if (p->precision == TFS_FP64)
     return p->d == 2 ? adj_dispatch<2, double>(p, n, L, pbar) : adj_dispatch<3, double>(p, n, L, pbar);
   return p->d == 2 ? adj_dispatch<2, float>(p, n, L, pbar) : adj_dispatch<3, float>(p, n, L, pbar);

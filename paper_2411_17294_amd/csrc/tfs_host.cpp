@@ -120,24 +120,28 @@ void soe_rule(double alpha, int m, double ylo, double yhi, double* w, double* la
 // e = exp(-z), om = 1 - e, a0 = (om - z e)/z^2, a1 = (z - om)/z^2.  Below z = 0.1 the
 // quotients lose digits, so a0 and a1 come from their Taylor series there,
 // a0 = sum_j (-z)^j (j+1)/(j+2)!, a1 = sum_j (-z)^j/(j+2)!, summed from the small end.
-void exp_mode_weights(double z, double* e, double* om, double* a0, double* a1) {
+void exp_mode_weights(double z, double* e, double* om, double* a0, double* a1, double* b2 = nullptr) {
   *e = std::exp(-z);
   *om = -std::expm1(-z);
   if (z < 0.1) {
-    double fac[24];
+    double fac[26];
     fac[0] = 1.0;
-    for (int j = 1; j < 24; ++j) fac[j] = fac[j - 1] * j;
-    double s0 = 0.0, s1 = 0.0;
+    for (int j = 1; j < 26; ++j) fac[j] = fac[j - 1] * j;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int j = 21; j >= 0; --j) {
       const double zj = std::pow(-z, j);
       s0 += zj * (j + 1) / fac[j + 2];
       s1 += zj / fac[j + 2];
+      s2 += zj * (j + 1) * (j + 2) / fac[j + 3];
     }
     *a0 = s0;
     *a1 = s1;
+    if (b2) *b2 = s2;
   } else {
     *a0 = (*om - z * *e) / (z * z);
     *a1 = (z - *om) / (z * z);
+    // b2 = int_0^1 v^2 e^{-zv} dv = (2 om - 2 z e - z^2 e) / z^3  (= -d a0 / dz)
+    if (b2) *b2 = (2.0 * *om - z * *e * (2.0 + z)) / (z * z * z);
   }
 }
 
@@ -296,7 +300,7 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   const double gs = 1.0 - 1.0 / std::sqrt(2.0);
   const double hg = dt * gs;
   p->hg = hg;
-  p->coef.assign((size_t)tfs::kNumCoef * m, 0.0);
+  p->coef.assign((size_t)tfs::kNumCoefAll * m, 0.0);
   CompSum eta, s_ec, theta, rho;
   for (int k = 0; k < m; ++k) {
     const double wk = p->w[k], lk = p->lam[k];
@@ -352,10 +356,10 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
     // Exponential mode update: Y_k^{n+1} = e_k Y_k^n + f_k X^n with Y_k = X_k - q_k X;
     // the mass modes mu_k (of the constant 1) give zeta^{n+1} = sum_k (mu_k^{n+1} - mu_k^n).
     CompSum q, sh, ee;
-    std::vector<double> e(m), om(m), a0(m), a1(m);
+    std::vector<double> e(m), om(m), a0(m), a1(m), b2(m);
     for (int k = 0; k < m; ++k) {
       const double wk = p->w[k], lk = p->lam[k];
-      exp_mode_weights(lk * dt, &e[k], &om[k], &a0[k], &a1[k]);
+      exp_mode_weights(lk * dt, &e[k], &om[k], &a0[k], &a1[k], &b2[k]);
       const double qk = wk * dt * a1[k], rk = wk * dt * a0[k];
       p->coef[tfs::kRowE * m + k] = e[k];
       p->coef[tfs::kRowF * m + k] = e[k] * qk + rk;
@@ -363,6 +367,13 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
       p->coef[tfs::kRowQ * m + k] = qk;
       p->coef[tfs::kRowOneME * m + k] = om[k];
       p->coef[tfs::kRowR * m + k] = rk;
+      // d a0/dz = -b2, d a1/dz = -(a0 - b2); q = w dt a1, r = w dt a0, f = e q + r
+      const double dq_dl = -wk * dt * dt * (a0[k] - b2[k]);
+      const double dr_dl = -wk * dt * dt * b2[k];
+      p->coef[tfs::kRowFW * m + k] = dt * (e[k] * a1[k] + a0[k]);
+      p->coef[tfs::kRowFL * m + k] = -dt * e[k] * qk + e[k] * dq_dl + dr_dl;
+      p->coef[tfs::kRowQW * m + k] = -dt * a1[k];
+      p->coef[tfs::kRowQL * m + k] = -dq_dl;
       q.add(qk);
       sh.add(om[k] * qk - rk);
       ee.add(dt * (wk - lk * qk));
@@ -421,14 +432,26 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   dest_s[3 * m + 5] = sb + tfs::kPbGamma;
   dest_s[3 * m + 6] = sb + tfs::kPbTheta;
   dest_s[3 * m + 7] = sb + tfs::kPbHr;
+  // exponential-mode scheme: rows [0, m) dL/dw_k, [m, 2m) dL/dlambda_k, [2m, 3m) unused
+  std::vector<int> dest_e(np, -1);
+  for (int j = 0; j < 2 * m; ++j) dest_e[j] = j;
+  dest_e[3 * m + 0] = sb + tfs::kPeA;
+  dest_e[3 * m + 1] = sb + tfs::kPeQ;
+  dest_e[3 * m + 2] = sb + tfs::kPeSh;
+  dest_e[3 * m + 3] = sb + tfs::kPeInvDe;
+  dest_e[3 * m + 4] = sb + tfs::kPeEtaE;
+  dest_e[3 * m + 5] = -2;  // zeta of this step
+  dest_e[3 * m + 6] = sb + tfs::kPeTs;
   bool ok = hipMalloc(&p->d_adj_part, sizeof(double) * np * (size_t)std::max(1, p->part_cap)) == hipSuccess;
   ok = ok && hipMalloc(&p->d_dest_bdf2, sizeof(int) * np) == hipSuccess;
   ok = ok && hipMalloc(&p->d_dest_start, sizeof(int) * np) == hipSuccess;
+  ok = ok && hipMalloc(&p->d_dest_exp, sizeof(int) * np) == hipSuccess;
+  ok = ok && hipMemcpy(p->d_dest_exp, dest_e.data(), sizeof(int) * np, hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(p->d_dest_bdf2, dest_b.data(), sizeof(int) * np, hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(p->d_dest_start, dest_s.data(), sizeof(int) * np, hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) {
     (void)hipFree(p->d_coef); (void)hipFree(p->d_part); (void)hipFree(p->d_adj_part);
-    (void)hipFree(p->d_dest_bdf2); (void)hipFree(p->d_dest_start);
+    (void)hipFree(p->d_dest_bdf2); (void)hipFree(p->d_dest_start); (void)hipFree(p->d_dest_exp);
     delete p;
     return fail(TFS_ENOMEM, "adjoint scratch");
   }
@@ -444,6 +467,7 @@ tfs_status tfs_plan_destroy(tfs_plan p) {
   (void)hipFree(p->d_adj_part);
   (void)hipFree(p->d_dest_bdf2);
   (void)hipFree(p->d_dest_start);
+  (void)hipFree(p->d_dest_exp);
   delete p;
   if (e1 != hipSuccess) return hip_fail(e1, "hipStreamSynchronize");
   if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
@@ -502,6 +526,55 @@ tfs_status tfs_plan_tables(tfs_plan p, double* tables, double* scalars, double* 
 }
 
 namespace {
+
+// Host chain rule of the exponential-mode scheme: the device already summed dL/dw_k and
+// dL/dlambda_k through e_k, f_k, om_k, l_k (and q_k at level 0); what remains goes through
+// the plan's scalars a = 1 + q/De, q = sum q_k, s_h = sum (om_k q_k - r_k),
+// eta_e = dt sum (w_k - lambda_k q_k), ts = eta_p/(De dt), and the mass increments zeta.
+tfs_status exp_pbar_to_params(tfs_plan p, const double* pb, double* dw, double* dlam, double* dDe,
+                              double* deta_p) {
+  const int m = p->m;
+  const double h = p->dt, iD = 1.0 / p->De;
+  const double* sc = pb + 6 * m;
+  const double* zb = pb + 6 * m + tfs::kPbarScalars;
+  std::vector<double> wb(m), lb(m);
+  for (int k = 0; k < m; ++k) { wb[k] = pb[k]; lb[k] = pb[m + k]; }
+  const double qb = sc[tfs::kPeQ] + sc[tfs::kPeA] * iD;
+  double iDb = sc[tfs::kPeInvDe] + sc[tfs::kPeA] * p->q_e;
+  const double shb = sc[tfs::kPeSh], eeb = sc[tfs::kPeEtaE], tsb = sc[tfs::kPeTs];
+  const int64_t N = p->max_steps;
+  for (int k = 0; k < m; ++k) {
+    const double wk = p->w[k], lk = p->lam[k];
+    double e, om, a0, a1, b2;
+    exp_mode_weights(lk * h, &e, &om, &a0, &a1, &b2);
+    const double qk = wk * h * a1;
+    const double dq_dw = h * a1, dq_dl = -wk * h * h * (a0 - b2);
+    const double dr_dw = h * a0, dr_dl = -wk * h * h * b2;
+    wb[k] += qb * dq_dw + shb * (om * dq_dw - dr_dw) + eeb * h * (1.0 - lk * dq_dw);
+    lb[k] += qb * dq_dl + shb * (h * e * qk + om * dq_dl - dr_dl) - eeb * h * (qk + lk * dq_dl);
+    // mass modes: mu^{n+1} = e mu^n + g, g = w dt (a0 + a1), zeta^{n+1} = sum_k (mu^{n+1} - mu^n)
+    const double g = wk * h * (a0 + a1);
+    std::vector<double> mu((size_t)N + 1, 0.0);
+    for (int64_t n = 0; n < N; ++n) mu[n + 1] = e * mu[n] + g;
+    double mub = 0.0, eb = 0.0, gb = 0.0;
+    for (int64_t n = N - 1; n >= 0; --n) {
+      mub += zb[n + 1];            // d zeta^{n+1} / d mu^{n+1}
+      eb += mub * mu[n];
+      gb += mub;
+      mub = e * mub - zb[n + 1];   // to mu^n: through the recurrence and - mu^n in zeta^{n+1}
+    }
+    wb[k] += gb * h * (a0 + a1);
+    lb[k] += -h * e * eb - gb * wk * h * h * a0;   // d(a0 + a1)/dz = -a0
+  }
+  // ts = eta_p / (De dt), 1/De
+  const double eta_pb = tsb / (p->De * h);
+  iDb += tsb * p->eta_p / h;
+  if (dw) for (int k = 0; k < m; ++k) dw[k] = wb[k];
+  if (dlam) for (int k = 0; k < m; ++k) dlam[k] = lb[k];
+  if (dDe) *dDe = -iDb * iD * iD;
+  if (deta_p) *deta_p = eta_pb;
+  return TFS_OK;
+}
 
 tfs_status run_step(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, const tfs::Levels& L,
                     double* tau, double* diag) {
@@ -609,13 +682,16 @@ tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const 
                             double* Xbar, void* Hbar, const double* taubar, double* kappabar_a,
                             double* kappabar_b, double* pbar) {
   if (!p) return fail(TFS_EINVAL, "null plan");
-  if (p->scheme == TFS_SCHEME_EXP) return fail(TFS_EUNSUPPORTED, "no adjoint for the exponential-mode scheme");
   if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
                                               (long long)n, (long long)p->max_steps);
   if (!pbar) return fail(TFS_EINVAL, "null pbar");
   if (p->npoints > 0) {
     if (!kappa_a || !X_n || !Xbar || !Hbar) return fail(TFS_EINVAL, "null kappa_a, X_n, Xbar or Hbar");
-    if (n > 0 && (!X_nm1 || !X_np1 || !Y_n || !Y_nm1)) return fail(TFS_EINVAL, "null forward level");
+    if (p->scheme == TFS_SCHEME_EXP) {
+      if (!X_np1 || (n > 0 && !Y_n)) return fail(TFS_EINVAL, "null forward level");
+    } else if (n > 0 && (!X_nm1 || !X_np1 || !Y_n || !Y_nm1)) {
+      return fail(TFS_EINVAL, "null forward level");
+    }
   }
   tfs::AdjLevels L;
   L.ka = kappa_a;
@@ -637,7 +713,7 @@ tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const 
 
 tfs_status tfs_pbar_to_params(tfs_plan p, const double* pb, double* dw, double* dlam, double* dDe, double* deta_p) {
   if (!p || !pb) return fail(TFS_EINVAL, "null plan or pbar");
-  if (p->scheme == TFS_SCHEME_EXP) return fail(TFS_EUNSUPPORTED, "no adjoint for the exponential-mode scheme");
+  if (p->scheme == TFS_SCHEME_EXP) return exp_pbar_to_params(p, pb, dw, dlam, dDe, deta_p);
   const int m = p->m;
   const double h = p->dt, b0 = tfs::kB0, gs = 1.0 - 1.0 / std::sqrt(2.0), hg = h * gs, hs = h * (1.0 - gs);
   const double iD = 1.0 / p->De;

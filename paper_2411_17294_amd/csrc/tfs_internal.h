@@ -34,8 +34,18 @@ enum ExpRow : int {
   kRowLdt = 2,    // lambda_k dt
   kRowQ = 3,      // q_k = w_k dt a1_k (plain modes X_k = Y_k + q_k X; same row as c_k)
   kRowOneME = 4,  // 1 - e_k
-  kRowR = 5       // w_k dt a0_k
+  kRowR = 5,      // w_k dt a0_k
+  // adjoint: derivatives of the step's per-mode factors (w_k, lambda_k chain on the device)
+  kRowFW = 6,     // d f_k / d w_k
+  kRowFL = 7,     // d f_k / d lambda_k
+  kRowQW = 8,     // -d q_k / d w_k       (level 0: Y_k^0 = -q_k X^0)
+  kRowQL = 9      // -d q_k / d lambda_k
 };
+constexpr int kNumCoefAll = 10;   // rows of the table (BDF2 plans use the first kNumCoef)
+
+// Scalar positions in pbar for TFS_SCHEME_EXP plans (after the 6 m per-mode entries, of
+// which [0, m) hold dL/dw_k and [m, 2m) dL/dlambda_k from the device).
+enum PbarExpScalar : int { kPeA = 0, kPeQ = 1, kPeSh = 2, kPeInvDe = 3, kPeEtaE = 4, kPeTs = 5 };
 
 // Number of diagnostics written per step.
 constexpr int kNumDiag = 6;
@@ -104,18 +114,19 @@ struct tfs_plan_s {
   int device = 0;
 
   std::vector<double> w, lam;
-  std::vector<double> coef;   // host copy of [kNumCoef][m]
+  std::vector<double> coef;   // host copy of [kNumCoefAll][m]
   double eta = 0, s_ec = 0, a_diag = 0, tau_scale = 0;
   double theta = 0, rho = 0, sigma1 = 0, sigma2 = 0, hg = 0, hr = 0;
   double q_e = 0, s_h = 0, eta_e = 0;   // TFS_SCHEME_EXP scalars (ExpScalars)
   std::vector<double> zeta;   // [max_steps + 1]
 
-  double* d_coef = nullptr;   // device [kNumCoef][m]
+  double* d_coef = nullptr;   // device [kNumCoefAll][m]
   double* d_part = nullptr;   // device [part_cap][kNumDiag] block partials
   int part_cap = 0;
   double* d_adj_part = nullptr;  // device [part_cap][3 m + kNumAdjScalars] adjoint block partials
   int* d_dest_bdf2 = nullptr;    // device [3 m + kNumAdjScalars]: pbar index of each partial entry
   int* d_dest_start = nullptr;
+  int* d_dest_exp = nullptr;
 
   // tuning (tfs_plan_tune): points per lane (0 = widest aligned), blocks per CU cap
   int vec_override = 0;

@@ -245,7 +245,7 @@ class Plan:
             for t, nm in ((Y_n, "Y_n"), (Y_nm1, "Y_nm1")):
                 self._need(t, nm, self.m * c * st, self.mode_dtype)
             self._need(Xbar, "Xbar", 2 * c * st, torch.float64)
-            self._need(Hbar, "Hbar", 2 * self.m * c * st, self.mode_dtype)
+            self._need(Hbar, "Hbar", self.mode_levels * self.m * c * st, self.mode_dtype)
         self._need(pbar, "pbar", self.pbar_size, torch.float64)
         check(lib().tfs_step_adjoint(self._h, int(n), _tptr(kappa_a), _tptr(kappa_b), _tptr(X_n), _tptr(X_nm1),
                                      _tptr(X_np1), _tptr(Y_n), _tptr(Y_nm1), _tptr(Xbar), _tptr(Hbar),

@@ -29,11 +29,12 @@ def loss(tau, target, d):
 
 
 def oracle_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, dw_da=None, dl_da=None,
-                     per_mode=False, extrap=True):
+                     per_mode=False, extrap=True, scheme="bdf2"):
     """Returns dict: kappa [d*d][P] (derivative w.r.t. an additive steady perturbation of
     kappa at every level), X0 [c][P], De, eta_p, alpha (if dw_da given), w, lam (per_mode)."""
     wts = pack_weights(d)[:, None]
-    base = O.run(d, w, lam, De, eta_p, dt, N, kappa, X0, extrap=extrap)
+    startup = "exp" if scheme == "exp" else "sdirk2"
+    base = O.run(d, w, lam, De, eta_p, dt, N, kappa, X0, extrap=extrap, startup=startup)
     resid = base["tau"] - target
 
     def run(dk=None, dX0=None, dwv=None, dlv=None, dDe=0.0, dep=0.0):
@@ -41,7 +42,8 @@ def oracle_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, dw_da=None,
         Xc = X0.astype(complex) + (1j * H_CS * dX0 if dX0 is not None else 0)
         wc = np.asarray(w, complex) + (1j * H_CS * dwv if dwv is not None else 0)
         lc = np.asarray(lam, complex) + (1j * H_CS * dlv if dlv is not None else 0)
-        r = O.run_complex(d, wc, lc, De + 1j * H_CS * dDe, eta_p + 1j * H_CS * dep, dt, N, kc, Xc, extrap=extrap)
+        r = O.run_complex(d, wc, lc, De + 1j * H_CS * dDe, eta_p + 1j * H_CS * dep, dt, N, kc, Xc, extrap=extrap,
+                          startup=startup)
         return r["tau"].imag / H_CS          # dtau along the direction
 
     out = {"loss": loss(base["tau"], target, d)}
@@ -76,12 +78,13 @@ def oracle_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, dw_da=None,
 
 
 def gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precision="fp64", tile=None,
-                  dw_da=None, dl_da=None, extrap=True, tune=None):
+                  dw_da=None, dl_da=None, extrap=True, tune=None, scheme="bdf2"):
     """Forward + adjoint on the GPU; kappa steady [d*d][P] or levels [nlev][d*d][P].
     tune: {key: value} passed to tfs_plan_tune (e.g. points per lane)."""
     P = X0.shape[1]
     c = d * (d + 1) // 2
-    plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, max(N, 1), precision=precision, tile=tile)
+    plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, max(N, 1), precision=precision, tile=tile, scheme=scheme)
+    exp = scheme == "exp"
     for key, value in (tune or {}).items():
         plan.tune(key, value)
     st, m = plan.stride, plan.m
@@ -100,6 +103,9 @@ def gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precisi
     tau = torch.zeros((c, st), dtype=torch.float64, device=dev)
     for n in range(N):
         ka, kb = lev(n)
+        if exp:
+            plan.step_levels(n, ka, kb, Xs[n], None, Xs[n + 1], Ys[n] if n >= 1 else None, None, Ys[n + 1], tau)
+            continue
         plan.step_levels(n, ka, kb, Xs[n], Xs[n - 1] if n >= 1 else None, Xs[n + 1], Ys[n] if n >= 1 else None,
                          Ys[n - 1] if n >= 1 else Ys[0], Ys[n + 1], tau)
     torch.cuda.synchronize()
@@ -108,11 +114,15 @@ def gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precisi
     taubar = torch.zeros((c, st), dtype=torch.float64, device=dev)
     taubar[:, :P] = torch.from_numpy(wts * (tau_h - target)).to(dev)
     Xbar = torch.zeros((2, c, st), dtype=torch.float64, device=dev)
-    Hbar = torch.zeros((2 * m * c * st,), dtype=mt, device=dev)
+    Hbar = torch.zeros((plan.mode_levels * m * c * st,), dtype=mt, device=dev)
     pbar = torch.zeros(plan.pbar_size, dtype=torch.float64, device=dev)
     kbar = torch.zeros((d * d, st), dtype=torch.float64, device=dev)
     for n in range(N - 1, -1, -1):
         ka, kb = lev(n)
+        if exp:
+            plan.step_adjoint(n, ka, kb, Xs[n], None, Xs[n + 1], Ys[n] if n >= 1 else None, None, Xbar, Hbar, pbar,
+                              taubar=taubar if n == N - 1 else None, kappabar_a=kbar, kappabar_b=kbar)
+            continue
         plan.step_adjoint(n, ka, kb, Xs[n], Xs[n - 1] if n >= 1 else None, Xs[n + 1], Ys[n] if n >= 1 else None,
                           Ys[n - 1] if n >= 1 else None, Xbar, Hbar, pbar,
                           taubar=taubar if n == N - 1 else None, kappabar_a=kbar, kappabar_b=kbar)

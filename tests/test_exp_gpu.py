@@ -129,9 +129,72 @@ def test_exp_step_levels_in_place_equals_ring_step():
     assert np.array_equal(tau[:, :P].cpu().numpy(), a["tau"])
 
 
-def test_exp_adjoint_is_unsupported():
-    kappa, X0, w, lam = small_case(2, 10, 1)
-    plan = tfs.Plan(2, 10, w, lam, 0.5, 1.0, 0.1, 1e-3, 4, scheme="exp")
-    with pytest.raises(tfs.TfsError) as e:
-        plan.pbar_to_params(np.zeros(plan.pbar_size))
-    assert e.value.status == tfs.TFS_EUNSUPPORTED
+# ---------------------------------------------------------------- adjoint of the exponential scheme
+from tests.grad_helpers import gpu_gradients, oracle_gradients   # noqa: E402
+from tests.test_adjoint_gpu import BAR, compare as compare_grads, setup as grad_setup   # noqa: E402
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("P,N", [(1, 1), (5, 2), (37, 12)])
+def test_exp_adjoint_matches_oracle(d, prec, P, N):
+    """dL/dkappa, dL/dX0, dL/dDe, dL/deta_p, dL/dalpha and the per-mode dL/dw_k, dL/dlambda_k
+    against the oracle's complex-step derivatives of the exponential scheme."""
+    m = 5
+    kappa, X0, w, lam, dw, dl, target = grad_setup(d, P, m, 600 + 10 * d + P)
+    print(f"exp adjoint d={d} {prec} P={P} N={N}", flush=True)
+    o = oracle_gradients(d, w, lam, 1.1, 0.1, 2e-3, N, kappa, X0, target, dw_da=dw, dl_da=dl, per_mode=True,
+                         scheme="exp")
+    g = gpu_gradients(d, w, lam, 0.45, 1.1, 0.1, 2e-3, N, kappa, X0, target, precision=prec, dw_da=dw, dl_da=dl,
+                      scheme="exp")
+    compare_grads(g, o, prec, label=f"exp adj d={d} {prec} P={P} N={N}")
+
+
+@pytest.mark.parametrize("tile", [None, 64])
+@pytest.mark.parametrize("adj_vec", [1, 2])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_exp_adjoint_whole_waves_and_tail(d, prec, adj_vec, tile):
+    P, N, m = 389, 6, 7
+    kappa, X0, w, lam, dw, dl, target = grad_setup(d, P, m, 700 + d)
+    print(f"exp adjoint waves d={d} {prec} adj_vec={adj_vec} tile={tile}", flush=True)
+    o = oracle_gradients(d, w, lam, 1.1, 0.1, 2e-3, N, kappa, X0, target, dw_da=dw, dl_da=dl, scheme="exp")
+    g = gpu_gradients(d, w, lam, 0.45, 1.1, 0.1, 2e-3, N, kappa, X0, target, precision=prec, tile=tile,
+                      dw_da=dw, dl_da=dl, tune={"adj_vec": adj_vec}, scheme="exp")
+    compare_grads(g, o, prec, per_mode=False, label=f"exp adj waves d={d} {prec} V={adj_vec} tile={tile}")
+
+
+@pytest.mark.parametrize("extrap", [True, False])
+@pytest.mark.parametrize("d", [2, 3])
+def test_exp_adjoint_time_varying_kappa(d, extrap):
+    P, N, m, dt = 23, 15, 6, 2e-3
+    rng = np.random.default_rng(80 + d)
+    a, b, om = (rng.standard_normal((d * d, P)) * 0.6 for _ in range(3))
+    t = np.arange(N + 1)[:, None, None] * dt
+    kap = np.ascontiguousarray(a[None] + b[None] * np.sin(3.0 * t + om[None]))
+    _, X0, w, lam, dw, dl, target = grad_setup(d, P, m, 90 + d)
+    print(f"exp adjoint tv d={d} extrap={extrap}", flush=True)
+    o = oracle_gradients(d, w, lam, 0.9, 0.2, dt, N, kap, X0, target, dw_da=dw, dl_da=dl, extrap=extrap,
+                         scheme="exp")
+    g = gpu_gradients(d, w, lam, 0.45, 0.9, 0.2, dt, N, kap, X0, target, dw_da=dw, dl_da=dl, extrap=extrap,
+                      scheme="exp")
+    compare_grads(g, o, "fp64", per_mode=False, label=f"exp adj tv d={d} extrap={extrap}")
+
+
+def test_exp_adjoint_alpha_against_gpu_finite_differences():
+    d, P, N, m = 3, 200, 20, 8
+    kappa, X0, w, lam, dw, dl, target = grad_setup(d, P, m, 177)
+    alpha, dt, T = 0.45, 2e-3, 0.05
+    _, _, info = osoe.soe_fit(alpha, m, dt, T)
+    g = gpu_gradients(d, w, lam, alpha, 1.1, 0.1, dt, N, kappa, X0, target, dw_da=dw, dl_da=dl, scheme="exp")
+
+    def L(al, De):
+        wa, la, _, _ = osoe.soe_gl_log(al, m, info["y_lo"], info["y_hi"])
+        return gpu_gradients(d, wa, la, al, De, 0.1, dt, N, kappa, X0, target, scheme="exp")["loss"]
+    h = 1e-4 * alpha
+    fd_a = (L(alpha + h, 1.1) - L(alpha - h, 1.1)) / (2 * h)
+    hD = 1e-4 * 1.1
+    fd_D = (L(alpha, 1.1 + hD) - L(alpha, 1.1 - hD)) / (2 * hD)
+    print("exp FD alpha", fd_a, g["alpha"], "De", fd_D, g["De"], flush=True)
+    assert abs(fd_a - g["alpha"]) <= 1e-6 * abs(fd_a)
+    assert abs(fd_D - g["De"]) <= 1e-6 * abs(fd_D)
