@@ -16,7 +16,8 @@ schedules them and keeps checkpoints:
   steps into per-level buffers (tfs_step_levels), then run the adjoint steps back
   through the segment (tfs_step_adjoint).
 
-Memory: N/K checkpoints of two mode levels plus K+2 mode levels of one segment.
+Memory: N/K checkpoints of two mode levels (one with the exponential-mode scheme) plus K+2
+mode levels of one segment.
 Points are independent, so `run_slabs` processes a grid in point slabs with the same
 code and sums the parameter gradients.
 """
@@ -46,6 +47,8 @@ class Spec:
     # time-varying base field: kappa_levels(n, out) writes level n into out [d*d][stride];
     # the differentiable kappa input is then an additive steady perturbation
     kappa_levels: Optional[Callable] = None
+    # "bdf2" (the paper's scheme) or "exp" (exponential mode update, one mode level)
+    scheme: str = "bdf2"
 
 
 class Checkpointed:
@@ -58,7 +61,8 @@ class Checkpointed:
         w, lam, dw, dl = tfs.soe_gl_log(alpha, spec.nmodes, spec.y_lo, spec.y_hi)
         self.w, self.lam, self.dw, self.dl = w, lam, dw, dl
         self.plan = tfs.Plan(spec.dim, self.P, w, lam, alpha, De, eta_p, spec.dt, spec.nsteps,
-                             precision=spec.precision, tile=spec.tile)
+                             precision=spec.precision, tile=spec.tile, scheme=spec.scheme)
+        self.exp = spec.scheme == "exp"
         self.dev = device
         self.c = spec.dim * (spec.dim + 1) // 2
         self.st = self.plan.stride
@@ -102,15 +106,18 @@ class Checkpointed:
         cache = self._level_cache(2) if sp.kappa_levels is not None else None
         X = torch.zeros((2, self.c, st), dtype=torch.float64, device=self.dev)
         X[0, :, :P] = X0
-        Y = torch.zeros((2 * self.ys,), dtype=self.mt, device=self.dev)
+        Y = torch.zeros((self.plan.mode_levels * self.ys,), dtype=self.mt, device=self.dev)
         tau = torch.zeros((self.c, st), dtype=torch.float64, device=self.dev)
         self.ckpt = {0: (X[0].clone(), None, None, None)}
         K, N = sp.ckpt_every, sp.nsteps
         for n in range(N):
             if n > 0 and n % K == 0:
                 sn, sm = n % 2, (n - 1) % 2
-                self.ckpt[n] = (X[sn].clone(), X[sm].clone(), Y[sn * self.ys:(sn + 1) * self.ys].clone(),
-                                Y[sm * self.ys:(sm + 1) * self.ys].clone())
+                if self.exp:   # one-step scheme: level n of X and of the modes
+                    self.ckpt[n] = (X[sn].clone(), None, Y.clone(), None)
+                else:
+                    self.ckpt[n] = (X[sn].clone(), X[sm].clone(), Y[sn * self.ys:(sn + 1) * self.ys].clone(),
+                                    Y[sm * self.ys:(sm + 1) * self.ys].clone())
             ka, kb = self._levels(self.kappa_pad, n, cache)
             self.plan.step(n, ka, kb, X, Y, tau)
         return tau[:, :P].clone()
@@ -123,7 +130,7 @@ class Checkpointed:
         taubar = torch.zeros((c, st), dtype=torch.float64, device=self.dev)
         taubar[:, :P] = tau_bar
         Xbar = torch.zeros((2, c, st), dtype=torch.float64, device=self.dev)
-        Hbar = torch.zeros((2 * self.ys,), dtype=self.mt, device=self.dev)
+        Hbar = torch.zeros((self.plan.mode_levels * self.ys,), dtype=self.mt, device=self.dev)
         pbar = torch.zeros(self.plan.pbar_size, dtype=torch.float64, device=self.dev)
         kbar = torch.zeros((d2, st), dtype=torch.float64, device=self.dev)
         starts = sorted(self.ckpt)
@@ -140,13 +147,17 @@ class Checkpointed:
             Xc, Xp, Yc, Yp = self.ckpt[s0]
             Xseg[1].copy_(Xc)
             if s0 > 0:
-                Xseg[0].copy_(Xp)
                 Yseg[1].copy_(Yc)
-                Yseg[0].copy_(Yp)
+                if not self.exp:
+                    Xseg[0].copy_(Xp)
+                    Yseg[0].copy_(Yp)
             for n in range(s0, s1):
                 i = n - s0 + 1
                 ka, kb = self._levels(self.kappa_pad, n, cache)
-                if n == 0:
+                if self.exp:
+                    self.plan.step_levels(n, ka, kb, Xseg[i], None, Xseg[i + 1], Yseg[i] if n > 0 else None, None,
+                                          Yseg[i + 1], tau_tmp)
+                elif n == 0:
                     self.plan.step_levels(0, ka, kb, Xseg[i], None, Xseg[i + 1], None, Yseg[i], Yseg[i + 1], tau_tmp)
                 else:
                     self.plan.step_levels(n, ka, kb, Xseg[i], Xseg[i - 1], Xseg[i + 1], Yseg[i], Yseg[i - 1],
@@ -155,7 +166,10 @@ class Checkpointed:
                 i = n - s0 + 1
                 ka, kb = self._levels(self.kappa_pad, n, cache)
                 tb = taubar if n == N - 1 else None
-                if n == 0:
+                if self.exp:
+                    self.plan.step_adjoint(n, ka, kb, Xseg[i], None, Xseg[i + 1], Yseg[i] if n > 0 else None, None,
+                                           Xbar, Hbar, pbar, taubar=tb, kappabar_a=kbar, kappabar_b=kbar)
+                elif n == 0:
                     # the start-up wrote level 0 of the modes into Yseg[i]; its adjoint needs X^0 only
                     self.plan.step_adjoint(0, ka, kb, Xseg[i], None, Xseg[i + 1], None, None, Xbar, Hbar, pbar,
                                            taubar=tb, kappabar_a=kbar, kappabar_b=kbar)

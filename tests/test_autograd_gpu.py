@@ -21,13 +21,14 @@ def _case(d, P, seed, m=6, alpha=0.5, dt=2e-3, N=17):
     return kappa, X0, info, target
 
 
+@pytest.mark.parametrize("scheme", ["bdf2", "exp"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
 @pytest.mark.parametrize("K", [1, 4, 17, 50])
-def test_checkpointed_equals_uncheckpointed_and_oracle(prec, K):
+def test_checkpointed_equals_uncheckpointed_and_oracle(prec, K, scheme):
     d, P, N, m, alpha, De, eta_p, dt = 3, 41, 17, 6, 0.5, 1.2, 0.1, 2e-3
     kappa, X0, info, target = _case(d, P, 5, m=m, alpha=alpha, dt=dt, N=N)
     spec = Spec(dim=d, nmodes=m, dt=dt, nsteps=N, y_lo=info["y_lo"], y_hi=info["y_hi"], ckpt_every=K,
-                precision=prec)
+                precision=prec, scheme=scheme)
     kt = torch.from_numpy(kappa).cuda().requires_grad_(True)
     xt = torch.from_numpy(X0).cuda().requires_grad_(True)
     at = torch.tensor(alpha, dtype=torch.float64, device="cuda", requires_grad=True)
@@ -38,16 +39,20 @@ def test_checkpointed_equals_uncheckpointed_and_oracle(prec, K):
     L = 0.5 * torch.sum(wts * (tau - torch.from_numpy(target).cuda()) ** 2)
     L.backward()
     w, lam, dw, dl = osoe.soe_gl_log(alpha, m, info["y_lo"], info["y_hi"])
-    ref = gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precision=prec, dw_da=dw, dl_da=dl)
+    ref = gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precision=prec, dw_da=dw, dl_da=dl,
+                        scheme=scheme)
     ek = relerr(kt.grad.cpu().numpy(), ref["kappa"])
     ex = relerr(xt.grad.cpu().numpy(), ref["X0"])
-    print(f"checkpointed K={K} {prec}: kappa {ek:.2e} X0 {ex:.2e}", flush=True)
-    assert ek < 1e-13 and ex < 1e-13
-    assert at.grad.item() == pytest.approx(ref["alpha"], rel=1e-13)
-    assert Dt.grad.item() == pytest.approx(ref["De"], rel=1e-13)
-    assert et.grad.item() == pytest.approx(ref["eta_p"], rel=1e-13)
+    print(f"checkpointed K={K} {prec} {scheme}: kappa {ek:.2e} X0 {ex:.2e}", flush=True)
+    # the same kernels on the same inputs: equal up to the order of the block sums, and in the
+    # FP32-mode form up to an FP32 rounding of a recomputed mode tipping the other way
+    bar = 1e-13 if prec == "fp64" else 1e-11
+    assert ek < bar and ex < bar
+    assert at.grad.item() == pytest.approx(ref["alpha"], rel=bar)
+    assert Dt.grad.item() == pytest.approx(ref["De"], rel=bar)
+    assert et.grad.item() == pytest.approx(ref["eta_p"], rel=bar)
     if prec == "fp64" and K == 4:
-        o = oracle_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, dw_da=dw, dl_da=dl)
+        o = oracle_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, dw_da=dw, dl_da=dl, scheme=scheme)
         assert relerr(kt.grad.cpu().numpy(), o["kappa"]) < 1e-9
         assert relerr(xt.grad.cpu().numpy(), o["X0"]) < 1e-9
         assert abs(at.grad.item() - o["alpha"]) < 1e-9 * abs(o["alpha"])
