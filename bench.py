@@ -65,6 +65,15 @@ def exp_bytes_per_point(dim, m, mode_bytes, kappa_reads):
     return 2 * m * c * mode_bytes + 2 * c * 8 + c * 8 + kappa_reads * dim * dim * 8
 
 
+def exp_adjoint_bytes_per_point(dim, m, mode_bytes):
+    """Minimum HBM traffic of one adjoint step of the exponential-mode scheme per point: the
+    forward mode level read, the adjoint mode level read and written in place; X^n and
+    X^{n+1} read, Xbar^{n+1} read and Xbar^n written; kappa at two levels read and its
+    adjoint read and written."""
+    c = dim * (dim + 1) // 2
+    return 3 * m * c * mode_bytes + 2 * c * 8 + 2 * c * 8 + 4 * dim * dim * 8
+
+
 def adjoint_bytes_per_point(dim, m, mode_bytes):
     """Minimum HBM traffic of one adjoint step per point: four mode streams read (H^(n+1),
     H^(n+2), Y^n, Y^(n-1)) and one written (H^(n)); X at three levels read, the two adjoint
@@ -126,6 +135,8 @@ def measure_forms(stream, steps=20, which="all"):
         out["fwd_adjoint_3d"] = _fwd_adjoint(stream, steps)
     if which in ("all", "exp_vs_bdf2"):
         out["exp_vs_bdf2_3d"] = _exp_vs_bdf2(stream, steps)
+    if which in ("all", "fwd_adjoint_exp"):
+        out["fwd_adjoint_3d_exp"] = _fwd_adjoint(stream, steps, scheme="exp")
     if which in ("all", "slab384"):
         out["fwd_adjoint_384cube_slab"] = _fwd_adjoint(stream, steps, workload=5, npoints=SLAB_384)
     return out
@@ -218,7 +229,7 @@ def _exp_vs_bdf2(stream, steps):
             "tau_rel_diff_exp_vs_bdf2": diff}
 
 
-def _fwd_adjoint(stream, steps, workload=4, npoints=None):
+def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
     """Forward (ring), recompute (levels) and adjoint steps of a differentiation workload on
     npoints points (default: the whole grid; a slab of the grid for the 384^3 case)."""
     import numpy as np
@@ -230,7 +241,9 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None):
     P = wl.npoints if npoints is None else npoints
     alpha = wl.alphas[0]
     w, lam, _, _, _ = tfs.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * wl.nsteps)
-    p = tfs.Plan(wl.dim, P, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=wl.precision)
+    p = tfs.Plan(wl.dim, P, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=wl.precision,
+                 scheme=scheme)
+    exp = scheme == "exp"
     ka, kb = p.kappa_tensor(), p.kappa_tensor()
     dk = DeviceKappa(I.fourier_field(wl), wl.grid, P)
     dk.fill(ka, wl.dt if wl.time_varying else 0.0)
@@ -242,11 +255,15 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None):
     Xs = [torch.zeros((c, st), dtype=torch.float64, device="cuda") for _ in range(3)]
     Ys = [torch.zeros((m * c * st,), dtype=p.mode_dtype, device="cuda") for _ in range(3)]
     Xs[0].copy_(X[0])
-    p.step_levels(0, ka, None, Xs[0], None, Xs[1], None, Ys[0], Ys[1], tau)
-    p.step_levels(1, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Ys[2], tau)
+    if exp:
+        p.step_levels(0, ka, None, Xs[0], None, Xs[1], None, None, Ys[1], tau)
+        p.step_levels(1, ka, kb, Xs[1], None, Xs[2], Ys[1], None, Ys[2], tau)
+    else:
+        p.step_levels(0, ka, None, Xs[0], None, Xs[1], None, Ys[0], Ys[1], tau)
+        p.step_levels(1, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Ys[2], tau)
     Xbar = torch.zeros((2, c, st), dtype=torch.float64, device="cuda")
     Xbar[0, :, :P].normal_()
-    Hbar = torch.zeros((2 * m * c * st,), dtype=p.mode_dtype, device="cuda")
+    Hbar = torch.zeros((p.mode_levels * m * c * st,), dtype=p.mode_dtype, device="cuda")
     pbar = torch.zeros(p.pbar_size, dtype=torch.float64, device="cuda")
     kbar = torch.zeros_like(ka)
     p.step(0, ka, None, X, Y, tau)
@@ -255,18 +272,30 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None):
         p.step(n, ka, kb, X, Y, tau)
 
     def rec(n):
-        p.step_levels(n, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Ys[2], tau)
+        if exp:
+            p.step_levels(n, ka, kb, Xs[1], None, Xs[2], Ys[1], None, Ys[2], tau)
+        else:
+            p.step_levels(n, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Ys[2], tau)
 
     def adj(n):
-        p.step_adjoint(n, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Xbar, Hbar, pbar, kappabar_a=kbar,
-                       kappabar_b=kbar)
-    fb = algorithmic_bytes_per_point(wl.dim, m, 4, 2) * P
-    ab = adjoint_bytes_per_point(wl.dim, m, 4) * P
+        if exp:
+            p.step_adjoint(n, ka, kb, Xs[1], None, Xs[2], Ys[1], None, Xbar, Hbar, pbar, kappabar_a=kbar,
+                           kappabar_b=kbar)
+        else:
+            p.step_adjoint(n, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Xbar, Hbar, pbar, kappabar_a=kbar,
+                           kappabar_b=kbar)
+    if exp:
+        fb = exp_bytes_per_point(wl.dim, m, 4, 2) * P
+        ab = exp_adjoint_bytes_per_point(wl.dim, m, 4) * P
+    else:
+        fb = algorithmic_bytes_per_point(wl.dim, m, 4, 2) * P
+        ab = adjoint_bytes_per_point(wl.dim, m, 4) * P
     tag = "fp32modes_3d_128cube_m32" if workload == 4 else "fp32modes_3d_384cube_m48_slab"
+    kf, ka_ = ("exp_kernel_", "exp_adj_kernel_") if exp else ("bdf2_kernel_", "adj_kernel_")
     parts = {}
-    for name, fn, nbytes, prof in (("forward", fwd, fb, "bdf2_kernel_" + tag),
-                                   ("recompute", rec, fb, "bdf2_kernel_" + tag),
-                                   ("adjoint", adj, ab, "adj_kernel_" + tag)):
+    for name, fn, nbytes, prof in (("forward", fwd, fb, kf + tag),
+                                   ("recompute", rec, fb, kf + tag),
+                                   ("adjoint", adj, ab, ka_ + tag)):
         for n in range(1, 4):
             fn(n)
         ms = _timed(stream, fn, 4, steps)
@@ -274,7 +303,8 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None):
         parts[name] = {"ms_per_step": ms, "bytes_per_launch": nbytes, "achieved_GBs": gbs,
                        "frac": gbs / HBM_PEAK_GBS, "traffic": profiled_traffic(prof)}
     total = sum(v["ms_per_step"] for v in parts.values())
-    out = {"workload": wl.name, "form": wl.precision, "points": P, **parts, "ms_per_time_level": total,
+    out = {"workload": wl.name, "form": wl.precision, "scheme": scheme, "points": P, **parts,
+           "ms_per_time_level": total,
            "point_mode_updates_per_s": P * m / (total * 1e-3),
            "frac_all": (2 * fb + ab) / (total * 1e-3) / 1e9 / HBM_PEAK_GBS}
     if P != wl.npoints:
@@ -370,7 +400,8 @@ def main():
     ap.add_argument("--job", type=int, default=0, metavar="STEPS",
                     help="run the 384^3 differentiation workload end to end with STEPS time levels")
     ap.add_argument("--job-slabs", type=int, default=64, help="slabs of the --job run (64 = whole grid)")
-    ap.add_argument("--only-forms", choices=["all", "fp32_vs_fp64", "fwd_adjoint", "slab384", "exp_vs_bdf2"],
+    ap.add_argument("--only-forms", choices=["all", "fp32_vs_fp64", "fwd_adjoint", "slab384", "exp_vs_bdf2",
+                                             "fwd_adjoint_exp"],
                     default=None,
                     help="only the 3-D form measurements (for profiling)")
     args = ap.parse_args()

@@ -487,7 +487,15 @@ struct ExpAdjArgs {
   double dt;
 };
 
-template <int D, typename MT, int V, bool FULL>
+// TAU: this step's stress is in the loss (taubar given: the last step of a misfit).  Without
+// it Gbar = 0, and neither G nor the recomputed Y^{n+1} is needed.
+#ifndef TFS_EXP_ADJ_AHEAD
+#define TFS_EXP_ADJ_AHEAD 1
+#endif
+// modes whose forward and adjoint loads are in flight ahead of the one being updated
+constexpr int kExpAdjAhead = TFS_EXP_ADJ_AHEAD;
+
+template <int D, typename MT, int V, bool FULL, bool TAU>
 __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const WaveAddr& w, int nv, double* smode,
                                               double* slot, double (&sc)[kNumAdjScalars]) {
   constexpr int C = Sym<D>::C;
@@ -499,7 +507,7 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
   const double ts = a.s.tau_scale, eta_e = a.s.eta_e, q = a.s.q;
 
   // ---- local part, point by point
-  double Gb[C][V], Hb[C][V], Xc[C][V], Xacc[C][V];
+  double Gb[TAU ? C : 1][V], Hb[C][V], Xc[C][V], Xacc[C][V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const uint32_t ox = w.ox + v * 8;
@@ -521,7 +529,7 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
       load_v<FULL, double, 1>(at(a.Xp + s * st + w.pw, ox), nv1, x);
       xp[s] = x[0];
       tv[s] = 0.0;
-      if (a.taubar) {
+      if constexpr (TAU) {
         load_v<FULL, double, 1>(at(a.taubar + s * st + w.pw, ox), nv1, x);
         tv[s] = x[0];
       }
@@ -532,8 +540,10 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
       const int i = Sym<D>::i(s), j = Sym<D>::j(s);
       S[s] = k[i * D + j] + k[j * D + i];
     }
-    sc[4] += ts * dot<C>(tv, xp);                  // eta_e
-    sc[6] += eta_e * dot<C>(tv, xp);               // ts (X+ part; the G part follows the modes)
+    if constexpr (TAU) {
+      sc[4] += ts * dot<C>(tv, xp);                // eta_e
+      sc[6] += eta_e * dot<C>(tv, xp);             // ts (X+ part; the G part follows the modes)
+    }
     {
       double M[C][C];
       build_M<D>(k, a.s.a_diag, q, M);
@@ -548,7 +558,7 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
 #pragma unroll
     for (int t = 0; t < C; ++t) {
       Hb[t][v] = -u[t] + a.s.inv_De * rb[t];       // R = X^n - K H + H/De
-      Gb[t][v] = -ts * tv[t];
+      if constexpr (TAU) Gb[t][v] = -ts * tv[t];
       Xacc[t][v] = rb[t] + a.s.s_h * Hb[t][v];
       lds(v, t) = rb[t];
     }
@@ -556,17 +566,40 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
 #pragma unroll
     for (int t = 0; t < C; ++t) hx += Hb[t][v] * Xc[t][v];
     sc[2] += hx;                                   // s_h
+    // one c x c solve live at a time
+    __builtin_amdgcn_sched_barrier(0);
   }
 
   // ---- mode stream: forward Y^n and the adjoint level, in place
   const int64_t T = a.tile;
   const MT* yp = a.Yn + w.tw;
   MT* hp = a.H + w.tw;
-  double Hs[C][V], Gs[C][V];
+  double Hs[C][V], Gs[TAU ? C : 1][V];
 #pragma unroll
   for (int s = 0; s < C; ++s)
 #pragma unroll
-    for (int v = 0; v < V; ++v) { Hs[s][v] = 0.0; Gs[s][v] = 0.0; }
+    for (int v = 0; v < V; ++v) {
+      Hs[s][v] = 0.0;
+      if constexpr (TAU) Gs[s][v] = 0.0;
+    }
+  // ring of the next kExpAdjAhead modes' two streams
+  MT py[kExpAdjAhead][C][V], ph[kExpAdjAhead][C][V];
+#pragma unroll
+  for (int j = 0; j < kExpAdjAhead; ++j) {
+    const uint32_t om = opaque(w.om);
+    const int64_t o = (int64_t)j * C * T;
+    const MT* by = opaque_ptr(yp + o);
+    const MT* bh = opaque_ptr(hp + o);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) { py[j][s][v] = MT(0); ph[j][s][v] = MT(0); }
+      if (j < m) {
+        if (!first) load_v<FULL, MT, V, true>(at(by + s * T, om), nv, py[j][s]);
+        load_v<FULL, MT, V, true>(at(bh + s * T, om), nv, ph[j][s]);
+      }
+    }
+  }
   for (int k = 0; k < m; ++k) {
     const double ek = a.coef[kRowE * m + k];
     const double fk = a.coef[kRowF * m + k];
@@ -578,16 +611,26 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
     const double qw = a.coef[kRowQW * m + k];
     const double ql = a.coef[kRowQL * m + k];
     const double edt = ek * a.dt;
+    // mode k leaves the ring; mode k + kExpAdjAhead is loaded before this mode's arithmetic
     MT cy[C][V], ch[C][V];
-    {
+#pragma unroll
+    for (int s = 0; s < C; ++s)
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        cy[s][v] = py[0][s][v];
+        ch[s][v] = ph[0][s][v];
+#pragma unroll
+        for (int j = 0; j + 1 < kExpAdjAhead; ++j) { py[j][s][v] = py[j + 1][s][v]; ph[j][s][v] = ph[j + 1][s][v]; }
+      }
+    if (k + kExpAdjAhead < m) {
       const uint32_t om = opaque(w.om);
-      const int64_t o = (int64_t)k * C * T;
+      const int64_t o = (int64_t)(k + kExpAdjAhead) * C * T;
       const MT* by = opaque_ptr(yp + o);
       const MT* bh = opaque_ptr(hp + o);
 #pragma unroll
       for (int s = 0; s < C; ++s) {
-        if (!first) load_v<FULL, MT, V, true>(at(by + s * T, om), nv, cy[s]);
-        load_v<FULL, MT, V, true>(at(bh + s * T, om), nv, ch[s]);
+        if (!first) load_v<FULL, MT, V, true>(at(by + s * T, om), nv, py[kExpAdjAhead - 1][s]);
+        load_v<FULL, MT, V, true>(at(bh + s * T, om), nv, ph[kExpAdjAhead - 1][s]);
       }
     }
     double gw = 0.0, gl = 0.0;
@@ -600,14 +643,18 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
       for (int v = 0; v < V; ++v) {
         const double x = Xc[s][v];
         const double y = first ? -qk * x : (double)cy[s][v];
-        const double yn1 = (double)(MT)(ek * y + fk * x);          // forward Y^{n+1} as stored
-        const double yh = (double)ch[s][v] + lk * Gb[s][v];        // Yhat
+        double yh = (double)ch[s][v];                              // Yhat = Ybar^{n+1} + l_k Gbar
+        if constexpr (TAU) {
+          const double yn1 = (double)(MT)(ek * y + fk * x);        // forward Y^{n+1} as stored
+          yh += lk * Gb[s][v];
+          Gs[s][v] += lk * yn1;
+          gl += a.dt * (Gb[s][v] * yn1);
+        }
         const double yb = ek * yh + ok * Hb[s][v];                 // Ybar^n
         Hs[s][v] += ok * y;
-        Gs[s][v] += lk * yn1;
         Xacc[s][v] += fk * yh;
         gw += fw * (yh * x);
-        gl += edt * ((Hb[s][v] - yh) * y) + fl * (yh * x) + a.dt * (Gb[s][v] * yn1);
+        gl += edt * ((Hb[s][v] - yh) * y) + fl * (yh * x);
         if (first) {
           Xacc[s][v] -= qk * yb;                                   // Y^0 = -q_k X^0
           gw += qw * (yb * x);
@@ -625,33 +672,32 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
     }
   }
 
-  // ---- terms that need H and G, Xbar^n, and the kappa adjoints
+#pragma unroll
+  for (int s = 0; s < C; ++s) store_v<FULL, double, V>(at(a.Xb_out + s * st + w.pw, w.ox), nv, Xacc[s]);
+
+  // ---- terms that need H and G, and the kappa adjoints
   double kbar[D * D][V];
   {
-    double tb[C][V], Xp[C][V];
+    double Xp[C][V];
 #pragma unroll
-    for (int s = 0; s < C; ++s) {
-      load_v<FULL, double, V>(at(a.Xp + s * st + w.pw, w.ox), nv, Xp[s]);
-      if (a.taubar) load_v<FULL, double, V>(at(a.taubar + s * st + w.pw, w.ox), nv, tb[s]);
-      else
-#pragma unroll
-        for (int v = 0; v < V; ++v) tb[s][v] = 0.0;
-    }
+    for (int s = 0; s < C; ++s) load_v<FULL, double, V>(at(a.Xp + s * st + w.pw, w.ox), nv, Xp[s]);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      double Hv[C], Z[C], rb[C], tv[C], kb_[D * D];
+      double Hv[C], Z[C], rb[C], kb_[D * D];
 #pragma unroll
       for (int s = 0; s < C; ++s) {
         Hv[s] = Hs[s][v] + a.s.s_h * Xc[s][v];
         Z[s] = q * Xp[s][v] - Hv[s];               // M X+ = R: -q K X+ in M, -K H in R
         rb[s] = lds(v, s);
-        tv[s] = tb[s][v];
       }
-      double gv = 0.0;
+      if constexpr (TAU) {
+        // taubar = -Gbar / ts
+        double gv = 0.0;
 #pragma unroll
-      for (int s = 0; s < C; ++s) gv += tv[s] * Gs[s][v];
+        for (int s = 0; s < C; ++s) gv += Gb[s][v] * Gs[s][v];
+        sc[6] += gv / ts;                          // ts (G part): -taubar . G
+      }
       sc[3] += dot<C>(rb, Hv);                     // 1/De
-      sc[6] += -gv;                                // ts (G part)
 #pragma unroll
       for (int t = 0; t < D * D; ++t) kb_[t] = 0.0;
       kgrad_VZ<D>(kb_, 1.0, rb, Z);
@@ -660,8 +706,6 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
       for (int t = 0; t < D * D; ++t) kbar[t][v] = kb_[t];
     }
   }
-#pragma unroll
-  for (int s = 0; s < C; ++s) store_v<FULL, double, V>(at(a.Xb_out + s * st + w.pw, w.ox), nv, Xacc[s]);
   double fa = 1.0, fb = 0.0;
   if (a.kb && !a.kb_same) { fa = a.s.fa; fb = a.s.fb; }
   else if (a.kb && a.kb_same) { fa = a.s.fa + a.s.fb; fb = 0.0; }
@@ -684,7 +728,7 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
   }
 }
 
-template <int D, typename MT, int V, bool FULL>
+template <int D, typename MT, int V, bool FULL, bool TAU>
 __global__ __launch_bounds__(kBlock) void exp_adj_kernel(const ExpAdjArgs<MT> a) {
   constexpr int C = Sym<D>::C;
   extern __shared__ double smem[];    // [kBlock/64][3][m] mode sums, then Rbar per lane
@@ -702,7 +746,7 @@ __global__ __launch_bounds__(kBlock) void exp_adj_kernel(const ExpAdjArgs<MT> a)
        wv += wstride) {
     const WaveAddr w = wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m);
     const int nv = (FULL || wv * 64 + lane < a.ngroups) ? V : 0;
-    exp_adj_group<D, MT, V, FULL>(a, w, nv, smode, slot, sc);
+    exp_adj_group<D, MT, V, FULL, TAU>(a, w, nv, smode, slot, sc);
   }
   __syncthreads();
   write_block_partial(a.part + (size_t)a.part0 * (3 * a.m + kNumAdjScalars), a.m, smode, sc);
@@ -1030,8 +1074,8 @@ size_t exp_adj_shared_bytes(const tfs_plan_s* p, int V) {
   return sizeof(double) * ((size_t)(kBlock / 64) * 3 * p->m + (size_t)p->c * V * kBlock);
 }
 
-template <int D, typename MT, int V>
-hipError_t exp_adj_go(const tfs_plan_s* p, ExpAdjArgs<MT> a, int64_t zeta_dest, double* pbar) {
+template <int D, typename MT, int V, bool TAU>
+hipError_t exp_adj_go_(const tfs_plan_s* p, ExpAdjArgs<MT> a, int64_t zeta_dest, double* pbar) {
   const int64_t nwaves = p->npoints / (64 * V);
   const int64_t p_tail = nwaves * 64 * V, rest = p->npoints - p_tail;
   int nb = 0, nt = 0;
@@ -1042,24 +1086,30 @@ hipError_t exp_adj_go(const tfs_plan_s* p, ExpAdjArgs<MT> a, int64_t zeta_dest, 
     nb = grid_adj(p, a.ngroups);
     const size_t shm = exp_adj_shared_bytes(p, V);
     if (shm > 65536) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&exp_adj_kernel<D, MT, V, true>),
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&exp_adj_kernel<D, MT, V, true, TAU>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((exp_adj_kernel<D, MT, V, true>), dim3(nb), dim3(kBlock), shm, p->stream, a);
+    hipLaunchKernelGGL((exp_adj_kernel<D, MT, V, true, TAU>), dim3(nb), dim3(kBlock), shm, p->stream, a);
   }
   if (rest > 0) {
     a.p_begin = p_tail;
     a.ngroups = rest;
     a.part0 = nb;
     nt = grid_adj(p, rest);
-    hipLaunchKernelGGL((exp_adj_kernel<D, MT, 1, false>), dim3(nt), dim3(kBlock), exp_adj_shared_bytes(p, 1),
+    hipLaunchKernelGGL((exp_adj_kernel<D, MT, 1, false, TAU>), dim3(nt), dim3(kBlock), exp_adj_shared_bytes(p, 1),
                        p->stream, a);
   }
   const int np = 3 * p->m + kNumAdjScalars;
   hipLaunchKernelGGL(adj_finish_kernel, dim3(np), dim3(kBlock), 0, p->stream, a.part, nb + nt, np,
                      p->d_dest_exp, zeta_dest, pbar);
   return hipGetLastError();
+}
+
+template <int D, typename MT, int V>
+hipError_t exp_adj_go(const tfs_plan_s* p, const ExpAdjArgs<MT>& a, int64_t zeta_dest, double* pbar) {
+  return a.taubar ? exp_adj_go_<D, MT, V, true>(p, a, zeta_dest, pbar)
+                  : exp_adj_go_<D, MT, V, false>(p, a, zeta_dest, pbar);
 }
 
 template <int D, typename MT>
@@ -1097,7 +1147,8 @@ hipError_t exp_adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, 
   a.s.first = n == 0 ? 1 : 0;
   a.dt = p->dt;
   const int64_t zd = (int64_t)kPbarScalars + 6 * p->m + n + 1;
-  const int want = p->adj_vec_override ? p->adj_vec_override : (sizeof(MT) == 4 ? 2 : 1);
+  // one point per lane unless tuned: measured faster than two for this kernel
+  const int want = p->adj_vec_override ? p->adj_vec_override : 1;
   bool two = want == 2 && p->stride % 2 == 0 && p->tile % 2 == 0 && exp_adj_shared_bytes(p, 2) <= (size_t)p->lds_max;
   const size_t bm = 2 * sizeof(MT), bd = 16;
   two = two && al(L.ka, bd) && al(L.kb, bd) && al(L.Xn, bd) && al(L.Xp, bd) && al(L.Xbar, bd) &&
