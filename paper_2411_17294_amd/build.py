@@ -14,6 +14,11 @@ HIPCC_FLAGS = [
     "-Wall", "-Wno-unused-function",
     # packed FP32 instructions stay off: hipcc would otherwise form them from scalar code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a multiply-add fuses only within one source expression (HIP's default also fuses across
+    # statements, where the choice follows each template instance's code shape): every
+    # variant of a kernel (vector width, whole waves or masked tail) rounds a point alike,
+    # so results do not depend on where a point falls in a launch
+    "-ffp-contract=on",
 ]
 
 

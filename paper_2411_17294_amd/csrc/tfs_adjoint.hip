@@ -175,6 +175,24 @@ __device__ inline void write_block_partial(double* __restrict__ part, int m, con
   }
 }
 
+// kbar field += f * kbar of the wave's points (kbar may be null: nothing to do).  Every
+// load of the field is issued before any of its stores, so the read-modify-write costs
+// one memory latency, not one per component.
+template <int D, int V, bool FULL>
+__device__ __forceinline__ void add_kbar(double* kb, double f, int64_t st, const WaveAddr& w, int nv,
+                                         const double (&kbar)[D * D][V]) {
+  if (!kb) return;
+  double x[D * D][V];
+#pragma unroll
+  for (int t = 0; t < D * D; ++t) load_v<FULL, double, V>(at(kb + t * st + w.pw, w.ox), nv, x[t]);
+#pragma unroll
+  for (int t = 0; t < D * D; ++t)
+#pragma unroll
+    for (int v = 0; v < V; ++v) x[t][v] += f * kbar[t][v];
+#pragma unroll
+  for (int t = 0; t < D * D; ++t) store_v<FULL, double, V>(at(kb + t * st + w.pw, w.ox), nv, x[t]);
+}
+
 // ------------------------------------------------------------------ BDF2 step adjoint
 template <typename MT>
 struct AdjArgs {
@@ -322,9 +340,9 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
 #pragma unroll
     for (int v = 0; v < V; ++v) Gh[s][v] = 0.0;
   for (int k = 0; k < m; ++k) {
-    const double dk = a.coef[kRowD * m + k];
-    const double ek = a.coef[kRowDC * m + k];
-    const double hk = a.coef[kRowEta * m + k];
+    const double dk = load_uniform(a.coef + kRowD * m + k);
+    const double ek = load_uniform(a.coef + kRowDC * m + k);
+    const double hk = load_uniform(a.coef + kRowEta * m + k);
     MT c1[C][V], c2[C][V], cn[C][V], cm[C][V];
     const int64_t o = (int64_t)k * C * T;
     const uint32_t om = opaque(w.om);
@@ -410,23 +428,8 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
   // kappa adjoints: kappa~ = 2 kappa_a - kappa_b, or kappa_a
   double fa = 1.0, fb = 0.0;
   if (a.kb && !a.kb_same) { fa = 2.0; fb = -1.0; }
-#pragma unroll
-  for (int t = 0; t < D * D; ++t) {
-    if (a.kba) {
-      double x[V];
-      load_v<FULL, double, V>(at(a.kba + t * st + w.pw, w.ox), nv, x);
-#pragma unroll
-      for (int v = 0; v < V; ++v) x[v] += fa * kbar[t][v];
-      store_v<FULL, double, V>(at(a.kba + t * st + w.pw, w.ox), nv, x);
-    }
-    if (a.kbb && fb != 0.0) {
-      double x[V];
-      load_v<FULL, double, V>(at(a.kbb + t * st + w.pw, w.ox), nv, x);
-#pragma unroll
-      for (int v = 0; v < V; ++v) x[v] += fb * kbar[t][v];
-      store_v<FULL, double, V>(at(a.kbb + t * st + w.pw, w.ox), nv, x);
-    }
-  }
+  add_kbar<D, V, FULL>(a.kba, fa, st, w, nv, kbar);
+  if (a.kbb && fb != 0.0) add_kbar<D, V, FULL>(a.kbb, fb, st, w, nv, kbar);
 }
 
 // FULL: whole waves of V-point groups (ngroups a multiple of 64).  !FULL (V = 1): the
@@ -518,10 +521,17 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
       double x[1];
       load_v<FULL, double, 1>(at(a.ka + t * st + w.pw, ox), nv1, x);
       k[t] = x[0];
-      if (a.kb) {
+    }
+    if (a.kb) {
+      double kb[D * D];
+#pragma unroll
+      for (int t = 0; t < D * D; ++t) {
+        double x[1];
         load_v<FULL, double, 1>(at(a.kb + t * st + w.pw, ox), nv1, x);
-        k[t] = a.s.fa * k[t] + a.s.fb * x[0];
+        kb[t] = x[0];
       }
+#pragma unroll
+      for (int t = 0; t < D * D; ++t) k[t] = a.s.fa * k[t] + a.s.fb * kb[t];
     }
 #pragma unroll
     for (int s = 0; s < C; ++s) {
@@ -601,15 +611,15 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
     }
   }
   for (int k = 0; k < m; ++k) {
-    const double ek = a.coef[kRowE * m + k];
-    const double fk = a.coef[kRowF * m + k];
-    const double lk = a.coef[kRowLdt * m + k];
-    const double qk = a.coef[kRowQ * m + k];
-    const double ok = a.coef[kRowOneME * m + k];
-    const double fw = a.coef[kRowFW * m + k];
-    const double fl = a.coef[kRowFL * m + k];
-    const double qw = a.coef[kRowQW * m + k];
-    const double ql = a.coef[kRowQL * m + k];
+    const double ek = load_uniform(a.coef + kRowE * m + k);
+    const double fk = load_uniform(a.coef + kRowF * m + k);
+    const double lk = load_uniform(a.coef + kRowLdt * m + k);
+    const double qk = load_uniform(a.coef + kRowQ * m + k);
+    const double ok = load_uniform(a.coef + kRowOneME * m + k);
+    const double fw = load_uniform(a.coef + kRowFW * m + k);
+    const double fl = load_uniform(a.coef + kRowFL * m + k);
+    const double qw = load_uniform(a.coef + kRowQW * m + k);
+    const double ql = load_uniform(a.coef + kRowQL * m + k);
     const double edt = ek * a.dt;
     // mode k leaves the ring; mode k + kExpAdjAhead is loaded before this mode's arithmetic
     MT cy[C][V], ch[C][V];
@@ -709,23 +719,8 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
   double fa = 1.0, fb = 0.0;
   if (a.kb && !a.kb_same) { fa = a.s.fa; fb = a.s.fb; }
   else if (a.kb && a.kb_same) { fa = a.s.fa + a.s.fb; fb = 0.0; }
-#pragma unroll
-  for (int t = 0; t < D * D; ++t) {
-    if (a.kba) {
-      double x[V];
-      load_v<FULL, double, V>(at(a.kba + t * st + w.pw, w.ox), nv, x);
-#pragma unroll
-      for (int v = 0; v < V; ++v) x[v] += fa * kbar[t][v];
-      store_v<FULL, double, V>(at(a.kba + t * st + w.pw, w.ox), nv, x);
-    }
-    if (a.kbb && fb != 0.0) {
-      double x[V];
-      load_v<FULL, double, V>(at(a.kbb + t * st + w.pw, w.ox), nv, x);
-#pragma unroll
-      for (int v = 0; v < V; ++v) x[v] += fb * kbar[t][v];
-      store_v<FULL, double, V>(at(a.kbb + t * st + w.pw, w.ox), nv, x);
-    }
-  }
+  add_kbar<D, V, FULL>(a.kba, fa, st, w, nv, kbar);
+  if (a.kbb && fb != 0.0) add_kbar<D, V, FULL>(a.kbb, fb, st, w, nv, kbar);
 }
 
 template <int D, typename MT, int V, bool FULL, bool TAU>
@@ -817,9 +812,9 @@ __device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64
   const MT* h1p = a.H1 + toff;
   const MT* h2p = a.H2 + toff;
   for (int k = 0; k < m; ++k) {
-    const double ck = a.coef[kRowC * m + k];
-    const double uk = a.coef[kRowU * m + k];
-    const double vk = a.coef[kRowV * m + k];
+    const double ck = load_uniform(a.coef + kRowC * m + k);
+    const double uk = load_uniform(a.coef + kRowU * m + k);
+    const double vk = load_uniform(a.coef + kRowV * m + k);
     double ac = 0.0, au = 0.0, av = 0.0;
 #pragma unroll
     for (int s = 0; s < C; ++s) {

@@ -164,11 +164,24 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x) {
 }
 
 // The same for a wave-uniform pointer: keeps base + (k C + s) T sums inside the mode loop
-// (a few scalar adds per access) instead of one hoisted scalar pair per plane.
+// (a few scalar adds per access) instead of one hoisted scalar pair per plane.  The
+// pointer passes through the asm as a global-memory pointer: a generic one would turn
+// the accesses through it into flat instructions, which also count against the LDS and
+// scalar-load counter, so every wait on a coefficient would wait for the data loads too.
 template <typename T>
 __device__ __forceinline__ T* opaque_ptr(T* p) {
-  asm volatile("" : "+s"(p));
-  return p;
+  using G = __attribute__((address_space(1))) T;
+  G* g = (G*)p;
+  asm volatile("" : "+s"(g));
+  return (T*)g;
+}
+
+// A value that every lane reads at one address, from a table no kernel of the launch
+// writes (the per-mode coefficients): read through the constant address space it becomes
+// a scalar load with its short latency, not a vector load that every mode waits on.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)p;
 }
 
 // Tiled mode layout: [tile][m][c][T], point p at element (p / T) m c T + p % T of (0, 0).

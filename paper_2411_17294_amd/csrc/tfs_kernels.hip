@@ -105,9 +105,9 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr
     load_v<true, MT, V, true>(at(ym0 + s * T, w.om), V, cm[s]);
   }
   for (int k = 0; k < m; ++k) {
-    const double dk = a.coef[kRowD * m + k];
-    const double dck = a.coef[kRowDC * m + k];
-    const double ek = a.coef[kRowEta * m + k];
+    const double dk = load_uniform(a.coef + kRowD * m + k);
+    const double dck = load_uniform(a.coef + kRowDC * m + k);
+    const double ek = load_uniform(a.coef + kRowEta * m + k);
     MT nn[C][V], nm[C][V];
     if (k + 1 < m) {
       const int64_t o = (int64_t)(k + 1) * C * T;
@@ -289,9 +289,9 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, const WaveAd
   MT* Y0 = a.Y0 + w.tw;
   MT* Y1 = a.Y1 + w.tw;
   for (int k = 0; k < m; ++k) {
-    const double ck = a.coef[kRowC * m + k];
-    const double uk = a.coef[kRowU * m + k];
-    const double vk = a.coef[kRowV * m + k];
+    const double ck = load_uniform(a.coef + kRowC * m + k);
+    const double uk = load_uniform(a.coef + kRowU * m + k);
+    const double vk = load_uniform(a.coef + kRowV * m + k);
 #pragma unroll
     for (int s = 0; s < C; ++s) {
       MT o0[V], o1[V];
@@ -388,11 +388,11 @@ __device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& 
     }
   }
   for (int k = 0; k < m; ++k) {
-    const double ek = a.coef[kRowE * m + k];
-    const double fk = a.coef[kRowF * m + k];
-    const double lk = a.coef[kRowLdt * m + k];
-    const double qk = a.coef[kRowQ * m + k];
-    const double ok = a.coef[kRowOneME * m + k];
+    const double ek = load_uniform(a.coef + kRowE * m + k);
+    const double fk = load_uniform(a.coef + kRowF * m + k);
+    const double lk = load_uniform(a.coef + kRowLdt * m + k);
+    const double qk = load_uniform(a.coef + kRowQ * m + k);
+    const double ok = load_uniform(a.coef + kRowOneME * m + k);
     if (!first && k + kExpAhead < m) {
       const uint32_t om = opaque(w.om);
       const MT* b = opaque_ptr(yn0 + (int64_t)(k + kExpAhead) * C * T);
