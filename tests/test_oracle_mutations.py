@@ -67,3 +67,45 @@ def test_planted_mistake_fails_a_pin(name, tmp_path):
                         "-q", "-x", "-p", "no:cacheprovider", "-k", sel],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"no pin caught '{name}':\n{r.stdout[-2000:]}"
+
+
+# Mistakes planted in the spatial oracle (oracle/mfp.py; pins in test_oracle_mfp_pins.py).
+MFP_SRC = os.path.join(ROOT, "oracle", "mfp.py")
+MFP_MUTATIONS = {
+    "history_without_laplacian": ("rhs = -(B1 * phi[0] + B2 * phi[1]) + A @ hist",
+                                  "rhs = -(B1 * phi[0] + B2 * phi[1]) + (A - eps * np.kron(lap, np.eye(n))) @ hist",
+                                  "fourier_mode or convergence"),
+    "laplacian_sign": ("A = eps * np.kron(lap, np.eye(n))", "A = -eps * np.kron(lap, np.eye(n))",
+                       "fourier_mode or convergence"),
+    "sdirk_stage_without_laplacian": ("F1 = A @ np.sum(Fk, axis=0)",
+                                      "F1 = (A - eps * np.kron(lap, np.eye(n))) @ np.sum(Fk, axis=0)",
+                                      "fourier_mode"),
+    "nyquist_dropped": ("return sum(g * g for g in grids)",
+                        "return sum(np.where(np.abs(g) >= np.max(np.abs(g)) - 1e-9, 0.0, g * g) for g in grids)",
+                        "trigonometric"),
+}
+
+_RUN_MUTANT = """
+import importlib.util, sys
+import oracle
+spec = importlib.util.spec_from_file_location("oracle.mfp", sys.argv[1])
+mod = importlib.util.module_from_spec(spec)
+sys.modules["oracle.mfp"] = mod
+spec.loader.exec_module(mod)
+oracle.mfp = mod
+import pytest
+sys.exit(pytest.main([sys.argv[2], "-q", "-x", "-p", "no:cacheprovider", "-k", sys.argv[3]]))
+"""
+
+
+@pytest.mark.parametrize("name", sorted(MFP_MUTATIONS))
+def test_planted_mistake_in_spatial_oracle_fails_a_pin(name, tmp_path):
+    orig, bad, sel = MFP_MUTATIONS[name]
+    src = open(MFP_SRC).read()
+    assert src.count(orig) == 1, "mutation anchor drifted from the spatial oracle source"
+    mut = tmp_path / "mfp_mutant.py"
+    mut.write_text(src.replace(orig, bad))
+    r = subprocess.run([sys.executable, "-c", _RUN_MUTANT, str(mut),
+                        os.path.join(ROOT, "tests", "test_oracle_mfp_pins.py"), sel],
+                       cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"no pin caught '{name}':\n{r.stdout[-2000:]}{r.stderr[-2000:]}"
