@@ -124,6 +124,32 @@ tfs_status tfs_plan_destroy(tfs_plan plan);
 tfs_status tfs_plan_set_stream(tfs_plan plan, void* stream);
 
 /*
+ * Spatial form: centre-of-mass diffusion eps Laplace on a periodic grid with u = 0
+ * (Sec. 4.1, eq. FP_discrete with L = -eps Laplace - A(kappa~)), solved where it is
+ * diagonal.  Each "point" of the plan is then one real coefficient of a field in a basis
+ * of Laplace eigenfunctions (for example the real and imaginary parts of the discrete
+ * Fourier coefficients), and kappa must be the same at every point (it may change in
+ * time).  On such a coefficient -eps Laplace is the number eps |xi|^2, and the step is the
+ * pointwise one with 1/De replaced by 1/De + rate[p]: the relaxation term of A and the
+ * spatial term act alike.  The mass mode Phi_000 = 1 is the constant function, so its
+ * source term zeta^{n+1} S(kappa~) reaches only the coefficient of the constant basis
+ * function.
+ *
+ * rate          device [stride] FP64 (eps |xi|^2 of each point's basis function), or NULL
+ *               for none.  Caller-owned; it must stay valid while steps are launched.
+ * source_point  the point that holds the constant basis function's coefficient (it alone
+ *               gets the mass-mode source), or -1: every point gets it (the plain
+ *               pointwise form).
+ * Applies to tfs_step and tfs_step_levels of both schemes until it is called again;
+ * rate = NULL with source_point = -1 restores the pointwise form.  tfs_step_adjoint
+ * returns TFS_EUNSUPPORTED while a spatial form is set.  The diagnostics' minors do not
+ * describe a conformation tensor in this form; TFS_FLAG_CHECK_SYNC then checks only the
+ * non-finite count.
+ * Errors: TFS_EINVAL (null plan, source_point < -1 or >= npoints).
+ */
+tfs_status tfs_plan_set_spatial(tfs_plan plan, const double* rate, int64_t source_point);
+
+/*
  * Advance every point from time level n to n+1 (0 <= n < max_steps), asynchronously
  * on the plan's stream; no allocation, no host synchronisation (unless
  * TFS_FLAG_CHECK_SYNC).

@@ -10,7 +10,7 @@ LIB = os.path.join(HERE, "libtfs.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("tfs_kernels.hip", "tfs_adjoint.hip", "tfs_host.cpp")]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-function",
     # packed FP32 instructions stay off: hipcc would otherwise form them from scalar code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -29,19 +29,39 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def _filtered(text: str) -> str:
+    return "\n".join(l for l in text.splitlines()
+                     if "packed-fp32-ops" not in l and "not a recognized feature" not in l)
+
+
 def build(verbose: bool = False, extra=None) -> str:
+    """Compile every source to an object (in parallel), then link libtfs.so."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *(extra or []), "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc"), *SOURCES, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(HERE, "csrc", "_" + os.path.basename(src) + ".o")
+        cmd = [hipcc(), *HIPCC_FLAGS, *(extra or []), *inc, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        objs.append(obj)
+    failed = []
+    for cmd, pr in procs:
+        out = _filtered(pr.communicate()[0])
+        if pr.returncode != 0:
+            failed.append(f"{' '.join(cmd)}\n{out}")
+        elif verbose and out.strip():
+            print(out)
+    if failed:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(failed))
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
-    out = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
-                    if "packed-fp32-ops" not in l and "not a recognized feature" not in l)
+    out = _filtered(r.stdout + r.stderr)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({r.returncode}):\n{out}")
-    if verbose and out.strip():
-        print(out)
+        raise RuntimeError(f"link failed ({r.returncode}):\n{out}")
+    for obj in objs:
+        os.remove(obj)
     os.replace(tmp, LIB)
     return LIB
 

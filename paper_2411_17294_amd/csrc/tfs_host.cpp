@@ -481,6 +481,15 @@ tfs_status tfs_plan_set_stream(tfs_plan p, void* stream) {
   return TFS_OK;
 }
 
+tfs_status tfs_plan_set_spatial(tfs_plan p, const double* rate, int64_t source_point) {
+  if (!p) return fail(TFS_EINVAL, "null plan");
+  if (source_point < -1 || source_point >= p->npoints)
+    return fail(TFS_EINVAL, "source_point %lld outside [-1, npoints)", (long long)source_point);
+  p->sp_rate = rate;
+  p->sp_source = source_point;
+  return TFS_OK;
+}
+
 int64_t tfs_plan_stride(tfs_plan p) { return p ? p->stride : -1; }
 
 int64_t tfs_plan_tile(tfs_plan p) { return p ? (p->tile == p->stride ? 0 : p->tile) : -1; }
@@ -576,6 +585,8 @@ tfs_status exp_pbar_to_params(tfs_plan p, const double* pb, double* dw, double* 
   return TFS_OK;
 }
 
+bool spatial(const tfs_plan_s* p) { return p->sp_rate != nullptr || p->sp_source >= 0; }
+
 tfs_status run_step(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, const tfs::Levels& L,
                     double* tau, double* diag) {
   hipError_t e = p->scheme == TFS_SCHEME_EXP ? tfs::launch_exp(p, n, kappa_a, kappa_b, L, tau, diag)
@@ -590,7 +601,7 @@ tfs_status run_step(tfs_plan p, int64_t n, const double* kappa_a, const double* 
       e = hipMemcpy(h, diag, sizeof(h), hipMemcpyDeviceToHost);
       if (e != hipSuccess) return hip_fail(e, "diagnostic read-back");
       if (h[5] != 0.0) return fail(TFS_ENUMERIC, "%g non-finite entries at level %lld", h[5], (long long)(n + 1));
-      if (p->npoints > 0 && !(h[0] > 0.0 && h[1] > 0.0 && h[2] > 0.0))
+      if (p->npoints > 0 && !spatial(p) && !(h[0] > 0.0 && h[1] > 0.0 && h[2] > 0.0))
         return fail(TFS_ENUMERIC, "conformation not positive definite at level %lld", (long long)(n + 1));
     }
   }
@@ -685,6 +696,7 @@ tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const 
   if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
                                               (long long)n, (long long)p->max_steps);
   if (!pbar) return fail(TFS_EINVAL, "null pbar");
+  if (spatial(p)) return fail(TFS_EUNSUPPORTED, "no adjoint of the spatial form");
   if (p->npoints > 0) {
     if (!kappa_a || !X_n || !Xbar || !Hbar) return fail(TFS_EINVAL, "null kappa_a, X_n, Xbar or Hbar");
     if (p->scheme == TFS_SCHEME_EXP) {

@@ -131,6 +131,8 @@ struct tfs_plan_s {
   // tuning (tfs_plan_tune): points per lane (0 = widest aligned), blocks per CU cap
   int vec_override = 0;
   int adj_vec_override = 0;
+  const double* sp_rate = nullptr;   // spatial form: extra relaxation rate per point (caller-owned)
+  int64_t sp_source = -1;            // spatial form: the point with the mass-mode source, -1 = all
   int grid_per_cu = 16;
   int num_cus = 256;
   int lds_max = 65536;      // LDS bytes a block may use on the plan's device

@@ -50,6 +50,30 @@ __global__ __launch_bounds__(kBlock) void diag_finish_kernel(const double* __res
 }
 
 // ------------------------------------------------------------------ BDF2 step
+// Spatial form (eps Laplace where it is diagonal): each point is one coefficient of a
+// field in a basis of Laplace eigenfunctions.  -eps Laplace acts on it as the extra
+// relaxation rate eps |xi|^2, and only the constant function's coefficient carries the
+// mass-mode source (the mass mode is the constant 1).
+struct SpatialArgs {
+  const double* rate;   // [stride] extra relaxation rate per point, or null (none)
+  int64_t src;          // the point with the mass-mode source, or -1 (every point)
+};
+
+// The extra rate and the source weight (1 or 0) of the lane's V points.
+template <int V>
+__device__ __forceinline__ void load_spatial(const SpatialArgs& sp, const WaveAddr& w, double (&rate)[V],
+                                             double (&srcw)[V]) {
+  if (sp.rate) {
+    load_v<true, double, V>(at(sp.rate + w.pw, w.ox), V, rate);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) rate[v] = 0.0;
+  }
+  const int64_t p0 = w.pw + (int64_t)(w.ox / 8);
+#pragma unroll
+  for (int v = 0; v < V; ++v) srcw[v] = (sp.src < 0 || p0 + v == sp.src) ? 1.0 : 0.0;
+}
+
 template <typename MT>
 struct Bdf2Args {
   const double* ka;     // kappa_a [d*d][stride]
@@ -68,9 +92,10 @@ struct Bdf2Args {
   int64_t stride, tile;
   int m, part0;
   Bdf2Scalars s;
+  SpatialArgs sp;
 };
 
-template <int D, typename MT, int V, bool DIAG>
+template <int D, typename MT, int V, bool DIAG, bool SP>
 __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr& w, DiagAcc& acc) {
   constexpr int C = Sym<D>::C;
   const int64_t st = a.stride;
@@ -156,10 +181,16 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr
     }
   }
 
+  double rate[V], srcw[V];
+  if constexpr (SP) load_spatial<V>(a.sp, w, rate, srcw);
   double Xout[C][V], Tout[C][V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     double k[D * D], G[C], AG[C], R[C];
+    // relaxation plus the spatial rate; the mass-mode source; the diagonal of M
+    const double idv = SP ? a.s.inv_De + rate[v] : a.s.inv_De;
+    const double zw = SP ? a.s.zeta * srcw[v] : a.s.zeta;
+    const double ad = SP ? a.s.a_diag + a.s.eta * rate[v] : a.s.a_diag;
 #pragma unroll
     for (int q = 0; q < D * D; ++q) k[q] = kt[q][v];
 #pragma unroll
@@ -169,10 +200,10 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr
     for (int s = 0; s < C; ++s) {
       const int i = Sym<D>::i(s), j = Sym<D>::j(s);
       const double S = k[i * D + j] + k[j * D + i];
-      R[s] = P[s][v] - (AG[s] - a.s.inv_De * G[s]) + a.s.zeta * S;
+      R[s] = P[s][v] - (AG[s] - idv * G[s]) + zw * S;
     }
     double M[C][C];
-    build_M<D>(k, a.s.a_diag, a.s.eta, M);
+    build_M<D>(k, ad, a.s.eta, M);
     solve_pivot<C>(M, R);
 #pragma unroll
     for (int s = 0; s < C; ++s) {
@@ -195,7 +226,7 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr
 
 // Groups [0, ngroups) of V points from p_begin, 64 consecutive groups per wave; the
 // caller launches a V = 1 pass for the points after the last whole group.
-template <int D, typename MT, int V, bool DIAG>
+template <int D, typename MT, int V, bool DIAG, bool SP>
 __global__ __launch_bounds__(kBlock) void bdf2_kernel(const Bdf2Args<MT> a) {
   constexpr int C = Sym<D>::C;
   DiagAcc acc;
@@ -205,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void bdf2_kernel(const Bdf2Args<MT> a) {
   for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
        wv += wstride) {
     if (wv * 64 + lane < a.ngroups)
-      bdf2_group<D, MT, V, DIAG>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
+      bdf2_group<D, MT, V, DIAG, SP>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
   }
   if constexpr (DIAG) {
     const DiagAcc r = block_reduce(acc);
@@ -228,9 +259,10 @@ struct StartArgs {
   int64_t stride, tile;
   int m, part0;
   StartScalars s;
+  SpatialArgs sp;
 };
 
-template <int D, typename MT, int V, bool DIAG>
+template <int D, typename MT, int V, bool DIAG, bool SP>
 __device__ __forceinline__ void start_group(const StartArgs<MT>& a, const WaveAddr& w, DiagAcc& acc) {
   constexpr int C = Sym<D>::C;
   const int64_t st = a.stride;
@@ -242,10 +274,16 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, const WaveAd
 #pragma unroll
   for (int q = 0; q < D * D; ++q) load_v<true, double, V>(at(a.ka + q * st + w.pw, w.ox), V, kt[q]);
 
+  double rate[V], srcw[V];
+  if constexpr (SP) load_spatial<V>(a.sp, w, rate, srcw);
   double Tout[C][V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     double k[D * D], S[C], r[C], M[C][C], AX[C], x1[C];
+    // relaxation plus the spatial rate; the mass-mode source of the two stages
+    const double idv = SP ? a.s.inv_De + rate[v] : a.s.inv_De;
+    const double s1 = SP ? a.s.src1 * srcw[v] : a.s.src1;
+    const double s2 = SP ? a.s.sigma2 * srcw[v] : a.s.sigma2;
 #pragma unroll
     for (int q = 0; q < D * D; ++q) k[q] = kt[q][v];
 #pragma unroll
@@ -255,8 +293,8 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, const WaveAd
     }
     // stage 1: (I - h gs theta A) X1 = X0 + h gs theta S
 #pragma unroll
-    for (int s = 0; s < C; ++s) r[s] = X0[s][v] + a.s.src1 * S[s];
-    build_M<D>(k, 1.0 + a.s.hgt * a.s.inv_De, a.s.hgt, M);
+    for (int s = 0; s < C; ++s) r[s] = X0[s][v] + s1 * S[s];
+    build_M<D>(k, 1.0 + a.s.hgt * idv, a.s.hgt, M);
     solve_pivot<C>(M, r);
 #pragma unroll
     for (int s = 0; s < C; ++s) { x1[s] = r[s]; X1[s][v] = r[s]; }
@@ -264,8 +302,8 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, const WaveAd
     apply_K<D>(k, x1, AX);
 #pragma unroll
     for (int s = 0; s < C; ++s)
-      r[s] = X0[s][v] + a.s.sigma1 * (AX[s] - a.s.inv_De * x1[s]) + a.s.sigma2 * S[s];
-    build_M<D>(k, 1.0 + a.s.hgt * a.s.inv_De, a.s.hgt, M);
+      r[s] = X0[s][v] + a.s.sigma1 * (AX[s] - idv * x1[s]) + s2 * S[s];
+    build_M<D>(k, 1.0 + a.s.hgt * idv, a.s.hgt, M);
     solve_pivot<C>(M, r);
 #pragma unroll
     for (int s = 0; s < C; ++s) {
@@ -306,7 +344,7 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, const WaveAd
   }
 }
 
-template <int D, typename MT, int V, bool DIAG>
+template <int D, typename MT, int V, bool DIAG, bool SP>
 __global__ __launch_bounds__(kBlock) void start_kernel(const StartArgs<MT> a) {
   constexpr int C = Sym<D>::C;
   DiagAcc acc;
@@ -316,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void start_kernel(const StartArgs<MT> a) {
   for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
        wv += wstride) {
     if (wv * 64 + lane < a.ngroups)
-      start_group<D, MT, V, DIAG>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
+      start_group<D, MT, V, DIAG, SP>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
   }
   if constexpr (DIAG) {
     const DiagAcc r = block_reduce(acc);
@@ -350,9 +388,10 @@ struct ExpArgs {
   int64_t stride, tile;
   int m, part0;
   ExpScalars s;
+  SpatialArgs sp;
 };
 
-template <int D, typename MT, int V, bool DIAG>
+template <int D, typename MT, int V, bool DIAG, bool SP>
 __device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& w, DiagAcc& acc) {
   constexpr int C = Sym<D>::C;
   const int64_t st = a.stride;
@@ -443,6 +482,18 @@ __device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& 
         k[q] = a.s.fa * k[q] + a.s.fb * x[0];
       }
     }
+    double rate = 0.0, srcw = 1.0;                 // spatial form: extra rate, source weight
+    if constexpr (SP) {
+      if (a.sp.rate) {
+        double x[1];
+        load_v<true, double, 1>(at(a.sp.rate + w.pw, ox), 1, x);
+        rate = x[0];
+      }
+      srcw = (a.sp.src < 0 || w.pw + (int64_t)(ox / 8) == a.sp.src) ? 1.0 : 0.0;
+    }
+    const double idv = SP ? a.s.inv_De + rate : a.s.inv_De;
+    const double zw = SP ? a.s.zeta * srcw : a.s.zeta;
+    const double ad = SP ? a.s.a_diag + a.s.q * rate : a.s.a_diag;
 #pragma unroll
     for (int s = 0; s < C; ++s) Hv[s] = H[s][v] + a.s.s_h * Xc[s][v];
     apply_K<D>(k, Hv, AH);
@@ -450,10 +501,10 @@ __device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& 
     for (int s = 0; s < C; ++s) {
       const int i = Sym<D>::i(s), j = Sym<D>::j(s);
       const double S = k[i * D + j] + k[j * D + i];
-      R[s] = Xc[s][v] - (AH[s] - a.s.inv_De * Hv[s]) + a.s.zeta * S;
+      R[s] = Xc[s][v] - (AH[s] - idv * Hv[s]) + zw * S;
     }
     double M[C][C];
-    build_M<D>(k, a.s.a_diag, a.s.q, M);
+    build_M<D>(k, ad, a.s.q, M);
     solve_pivot<C>(M, R);
     double ts[C];
 #pragma unroll
@@ -483,7 +534,7 @@ __device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& 
   }
 }
 
-template <int D, typename MT, int V, bool DIAG>
+template <int D, typename MT, int V, bool DIAG, bool SP>
 __global__ __launch_bounds__(kBlock) void exp_kernel(const ExpArgs<MT> a) {
   constexpr int C = Sym<D>::C;
   DiagAcc acc;
@@ -493,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void exp_kernel(const ExpArgs<MT> a) {
   for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
        wv += wstride) {
     if (wv * 64 + lane < a.ngroups)
-      exp_group<D, MT, V, DIAG>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
+      exp_group<D, MT, V, DIAG, SP>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
   }
   if constexpr (DIAG) {
     const DiagAcc r = block_reduce(acc);
@@ -543,7 +594,8 @@ int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const Levels& 
     if (p->stride % V || p->tile % V) continue;
     const size_t bm = (size_t)V * sizeof(MT), bd = (size_t)V * 8;
     if (aligned(k0, bd) && aligned(k1, bd) && aligned(L.Xn, bd) && aligned(L.Xm, bd) && aligned(L.Xo, bd) &&
-        aligned(L.Yn, bm) && aligned(L.Ym, bm) && aligned(L.Ym0, bm) && aligned(L.Yo, bm) && aligned(tau, bd))
+        aligned(L.Yn, bm) && aligned(L.Ym, bm) && aligned(L.Ym0, bm) && aligned(L.Yo, bm) && aligned(tau, bd) &&
+        aligned(p->sp_rate, bd))
       return V;
   }
   return 1;
@@ -551,25 +603,25 @@ int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const Levels& 
 
 // Whole groups of V points with the V-wide kernel, the remaining npoints % V points with
 // the V = 1 kernel; the diagnostics fold the block partials of both launches.
-template <int D, typename MT, int V, bool DIAG>
+template <int D, typename MT, int V, bool DIAG, bool SP>
 hipError_t bdf2_launch(const tfs_plan_s* p, Bdf2Args<MT> a, int64_t p_begin, int64_t ngroups, int part0,
                        int* nblocks) {
   a.p_begin = p_begin;
   a.ngroups = ngroups;
   a.part0 = part0;
   const int grid = grid_for(p, ngroups);
-  hipLaunchKernelGGL((bdf2_kernel<D, MT, V, DIAG>), dim3(grid), dim3(kBlock), 0, p->stream, a);
+  hipLaunchKernelGGL((bdf2_kernel<D, MT, V, DIAG, SP>), dim3(grid), dim3(kBlock), 0, p->stream, a);
   *nblocks = grid;
   return hipGetLastError();
 }
 
-template <int D, typename MT, int V, bool DIAG>
+template <int D, typename MT, int V, bool DIAG, bool SP>
 hipError_t bdf2_go_(const tfs_plan_s* p, const Bdf2Args<MT>& a, double* diag_out) {
   const int64_t full = p->npoints / V, rest = p->npoints - full * V;
   int nb = 0, nt = 0;
   hipError_t e = hipSuccess;
-  if (full > 0) e = bdf2_launch<D, MT, V, DIAG>(p, a, 0, full, 0, &nb);
-  if (e == hipSuccess && rest > 0) e = bdf2_launch<D, MT, 1, DIAG>(p, a, full * V, rest, nb, &nt);
+  if (full > 0) e = bdf2_launch<D, MT, V, DIAG, SP>(p, a, 0, full, 0, &nb);
+  if (e == hipSuccess && rest > 0) e = bdf2_launch<D, MT, 1, DIAG, SP>(p, a, full * V, rest, nb, &nt);
   if (e == hipSuccess && DIAG)
     hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, a.part, nb + nt, diag_out);
   return e == hipSuccess ? hipGetLastError() : e;
@@ -577,7 +629,9 @@ hipError_t bdf2_go_(const tfs_plan_s* p, const Bdf2Args<MT>& a, double* diag_out
 
 template <int D, typename MT, int V>
 hipError_t bdf2_go(const tfs_plan_s* p, const Bdf2Args<MT>& a, bool diag, double* diag_out) {
-  return diag ? bdf2_go_<D, MT, V, true>(p, a, diag_out) : bdf2_go_<D, MT, V, false>(p, a, diag_out);
+  if (a.sp.rate || a.sp.src >= 0)
+    return diag ? bdf2_go_<D, MT, V, true, true>(p, a, diag_out) : bdf2_go_<D, MT, V, false, true>(p, a, diag_out);
+  return diag ? bdf2_go_<D, MT, V, true, false>(p, a, diag_out) : bdf2_go_<D, MT, V, false, false>(p, a, diag_out);
 }
 
 template <int D, typename MT>
@@ -600,6 +654,8 @@ hipError_t bdf2_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const
   a.tile = p->tile;
   a.m = p->m;
   a.s.a_diag = p->a_diag;
+  a.sp.rate = p->sp_rate;
+  a.sp.src = p->sp_source;
   a.s.eta = p->eta;
   a.s.s_ec = p->s_ec;
   a.s.inv_De = 1.0 / p->De;
@@ -614,25 +670,25 @@ hipError_t bdf2_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const
   return bdf2_go<D, MT, 1>(p, a, dg, diag);
 }
 
-template <int D, typename MT, int V, bool DIAG>
+template <int D, typename MT, int V, bool DIAG, bool SP>
 hipError_t start_launch(const tfs_plan_s* p, StartArgs<MT> a, int64_t p_begin, int64_t ngroups, int part0,
                        int* nblocks) {
   a.p_begin = p_begin;
   a.ngroups = ngroups;
   a.part0 = part0;
   const int grid = grid_for(p, ngroups);
-  hipLaunchKernelGGL((start_kernel<D, MT, V, DIAG>), dim3(grid), dim3(kBlock), 0, p->stream, a);
+  hipLaunchKernelGGL((start_kernel<D, MT, V, DIAG, SP>), dim3(grid), dim3(kBlock), 0, p->stream, a);
   *nblocks = grid;
   return hipGetLastError();
 }
 
-template <int D, typename MT, int V, bool DIAG>
+template <int D, typename MT, int V, bool DIAG, bool SP>
 hipError_t start_go_(const tfs_plan_s* p, const StartArgs<MT>& a, double* diag_out) {
   const int64_t full = p->npoints / V, rest = p->npoints - full * V;
   int nb = 0, nt = 0;
   hipError_t e = hipSuccess;
-  if (full > 0) e = start_launch<D, MT, V, DIAG>(p, a, 0, full, 0, &nb);
-  if (e == hipSuccess && rest > 0) e = start_launch<D, MT, 1, DIAG>(p, a, full * V, rest, nb, &nt);
+  if (full > 0) e = start_launch<D, MT, V, DIAG, SP>(p, a, 0, full, 0, &nb);
+  if (e == hipSuccess && rest > 0) e = start_launch<D, MT, 1, DIAG, SP>(p, a, full * V, rest, nb, &nt);
   if (e == hipSuccess && DIAG)
     hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, a.part, nb + nt, diag_out);
   return e == hipSuccess ? hipGetLastError() : e;
@@ -640,7 +696,9 @@ hipError_t start_go_(const tfs_plan_s* p, const StartArgs<MT>& a, double* diag_o
 
 template <int D, typename MT, int V>
 hipError_t start_go(const tfs_plan_s* p, const StartArgs<MT>& a, bool diag, double* diag_out) {
-  return diag ? start_go_<D, MT, V, true>(p, a, diag_out) : start_go_<D, MT, V, false>(p, a, diag_out);
+  if (a.sp.rate || a.sp.src >= 0)
+    return diag ? start_go_<D, MT, V, true, true>(p, a, diag_out) : start_go_<D, MT, V, false, true>(p, a, diag_out);
+  return diag ? start_go_<D, MT, V, true, false>(p, a, diag_out) : start_go_<D, MT, V, false, false>(p, a, diag_out);
 }
 
 template <int D, typename MT>
@@ -658,6 +716,8 @@ hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, const Levels& L
   a.tile = p->tile;
   a.m = p->m;
   a.s.hgt = p->hg * p->theta;
+  a.sp.rate = p->sp_rate;
+  a.sp.src = p->sp_source;
   a.s.inv_De = 1.0 / p->De;
   a.s.src1 = p->hg * p->theta;
   a.s.sigma1 = p->sigma1;
@@ -674,28 +734,37 @@ hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, const Levels& L
   return start_go<D, MT, 1>(p, a, dg, diag);
 }
 
-template <int D, typename MT, int V, bool DIAG>
+template <int D, typename MT, int V, bool DIAG, bool SP>
 hipError_t exp_launch(const tfs_plan_s* p, ExpArgs<MT> a, int64_t p_begin, int64_t ngroups, int part0,
                       int* nblocks) {
   a.p_begin = p_begin;
   a.ngroups = ngroups;
   a.part0 = part0;
   const int grid = grid_for(p, ngroups);
-  hipLaunchKernelGGL((exp_kernel<D, MT, V, DIAG>), dim3(grid), dim3(kBlock), 0, p->stream, a);
+  hipLaunchKernelGGL((exp_kernel<D, MT, V, DIAG, SP>), dim3(grid), dim3(kBlock), 0, p->stream, a);
   *nblocks = grid;
   return hipGetLastError();
 }
 
-template <int D, typename MT, int V, bool DIAG>
+template <int D, typename MT, int V, bool DIAG, bool SP>
 hipError_t exp_go_(const tfs_plan_s* p, const ExpArgs<MT>& a, double* diag_out) {
   const int64_t full = p->npoints / V, rest = p->npoints - full * V;
   int nb = 0, nt = 0;
   hipError_t e = hipSuccess;
-  if (full > 0) e = exp_launch<D, MT, V, DIAG>(p, a, 0, full, 0, &nb);
-  if (e == hipSuccess && rest > 0) e = exp_launch<D, MT, 1, DIAG>(p, a, full * V, rest, nb, &nt);
+  if (full > 0) e = exp_launch<D, MT, V, DIAG, SP>(p, a, 0, full, 0, &nb);
+  if (e == hipSuccess && rest > 0) e = exp_launch<D, MT, 1, DIAG, SP>(p, a, full * V, rest, nb, &nt);
   if (e == hipSuccess && DIAG)
     hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, a.part, nb + nt, diag_out);
   return e == hipSuccess ? hipGetLastError() : e;
+}
+
+template <int D, typename MT, bool SP>
+hipError_t exp_go(const tfs_plan_s* p, const ExpArgs<MT>& a, int V, double* diag) {
+  if constexpr (sizeof(MT) == 4 && D == 2) {
+    if (V == 4) return diag ? exp_go_<D, MT, 4, true, SP>(p, a, diag) : exp_go_<D, MT, 4, false, SP>(p, a, diag);
+  }
+  if (V == 2) return diag ? exp_go_<D, MT, 2, true, SP>(p, a, diag) : exp_go_<D, MT, 2, false, SP>(p, a, diag);
+  return diag ? exp_go_<D, MT, 1, true, SP>(p, a, diag) : exp_go_<D, MT, 1, false, SP>(p, a, diag);
 }
 
 template <int D, typename MT>
@@ -715,6 +784,8 @@ hipError_t exp_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const 
   a.tile = p->tile;
   a.m = p->m;
   a.s.a_diag = 1.0 + p->q_e / p->De;
+  a.sp.rate = p->sp_rate;
+  a.sp.src = p->sp_source;
   a.s.q = p->q_e;
   a.s.s_h = p->s_h;
   a.s.inv_De = 1.0 / p->De;
@@ -729,11 +800,8 @@ hipError_t exp_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const 
   A.Ym = nullptr;
   // two compensated sums per component: in 3-D four points per lane would spill
   const int V = pick_vec<D, MT>(p, ka, a.kb, A, tau, D == 3 ? 2 : 4);
-  if constexpr (sizeof(MT) == 4 && D == 2) {
-    if (V == 4) return diag ? exp_go_<D, MT, 4, true>(p, a, diag) : exp_go_<D, MT, 4, false>(p, a, diag);
-  }
-  if (V == 2) return diag ? exp_go_<D, MT, 2, true>(p, a, diag) : exp_go_<D, MT, 2, false>(p, a, diag);
-  return diag ? exp_go_<D, MT, 1, true>(p, a, diag) : exp_go_<D, MT, 1, false>(p, a, diag);
+  if (a.sp.rate || a.sp.src >= 0) return exp_go<D, MT, true>(p, a, V, diag);
+  return exp_go<D, MT, false>(p, a, V, diag);
 }
 
 }  // namespace

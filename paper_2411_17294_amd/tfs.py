@@ -21,8 +21,8 @@ TFS_FP64, TFS_FP32_MODES = 0, 1
 TFS_SCHEME_BDF2, TFS_SCHEME_EXP = 0, 1
 TFS_FLAG_CHECK_SYNC = 1
 
-EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_step", "tfs_step_levels",
-           "tfs_step_adjoint", "tfs_pbar_size", "tfs_pbar_to_params", "tfs_modes_to_plain",
+EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
+           "tfs_step_levels", "tfs_step_adjoint", "tfs_pbar_size", "tfs_pbar_to_params", "tfs_modes_to_plain",
            "tfs_plan_tables", "tfs_plan_stride", "tfs_plan_tile", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
            "tfs_status_string", "tfs_last_error")
 
@@ -63,6 +63,7 @@ def lib():
     L.tfs_plan_create.argtypes = [C.POINTER(PlanDesc), C.POINTER(C.c_void_p)]
     L.tfs_plan_destroy.argtypes = [vp]
     L.tfs_plan_set_stream.argtypes = [vp, vp]
+    L.tfs_plan_set_spatial.argtypes = [vp, vp, i64]
     L.tfs_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
     L.tfs_step_levels.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.tfs_step_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -81,7 +82,8 @@ def lib():
     L.tfs_status_string.argtypes = [C.c_int]
     L.tfs_status_string.restype = C.c_char_p
     L.tfs_last_error.restype = C.c_char_p
-    for name in ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_step", "tfs_step_levels",
+    for name in ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
+                 "tfs_step_levels",
                  "tfs_step_adjoint", "tfs_pbar_to_params", "tfs_modes_to_plain",
                  "tfs_plan_tables", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log"):
         getattr(L, name).restype = C.c_int
@@ -176,6 +178,15 @@ class Plan:
 
     def set_stream(self, stream):
         check(lib().tfs_plan_set_stream(self._h, C.c_void_p(stream)))
+
+    def set_spatial(self, rate=None, source_point=-1):
+        """Spatial form (tfs_plan_set_spatial): rate is a device FP64 tensor of at least
+        stride elements (eps |xi|^2 per point) or None; source_point is the point holding
+        the constant function's coefficient, or -1.  The plan keeps a reference to rate."""
+        import torch
+        self._need(rate, "rate", self.stride, torch.float64)
+        check(lib().tfs_plan_set_spatial(self._h, _tptr(rate), int(source_point)))
+        self._sp_rate = rate
 
     def tune(self, key: str, value: int):
         check(lib().tfs_plan_tune(self._h, key.encode(), int(value)))

@@ -1,0 +1,220 @@
+"""Spatial form on the GPU: centre-of-mass diffusion on a periodic grid (u = 0, kappa the
+same at every point), advanced in the Fourier layout of paper_2411_17294_amd.spectral
+through tfs_plan_set_spatial, against the spatial oracle (physical space, dense operator)
+and, on large grids, against the pointwise oracle one coefficient at a time."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mfp
+from oracle import oracle as O
+from oracle import soe as osoe
+from paper_2411_17294_amd import tfs
+from paper_2411_17294_amd.spectral import PeriodicGrid
+from tests.gpu_helpers import relerr
+from tests.mlf import mittag_leffler
+
+pytestmark = pytest.mark.gpu
+
+
+def run_spectral(grid, eps, d, w, lam, De, eta_p, dt, N, kap_levels, X0_grid, precision="fp64", scheme="bdf2",
+                 extrap=True, want_modes=False, traj=False):
+    """kap_levels: [nlev][d*d] (spatially constant); X0_grid: [c, *shape].  Returns grid
+    fields X (levels N, N-1), tau, plain modes and optionally the X trajectory."""
+    c = d * (d + 1) // 2
+    P = grid.npoints
+    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=precision, scheme=scheme)
+    st = plan.stride
+    plan.set_spatial(grid.rate(eps, st), grid.source_point)
+    X = torch.zeros((2, c, st), dtype=torch.float64, device="cuda")
+    Y = torch.zeros((plan.mode_levels * plan.m * c * st,), dtype=plan.mode_dtype, device="cuda")
+    tau = torch.zeros((c, st), dtype=torch.float64, device="cuda")
+    X[0, :, :P] = grid.to_points(torch.from_numpy(X0_grid).cuda())
+    kl = []
+    for lv in range(kap_levels.shape[0]):
+        t = torch.zeros((d * d, st), dtype=torch.float64, device="cuda")
+        t[:, :] = torch.from_numpy(kap_levels[lv]).cuda()[:, None]
+        kl.append(t)
+    path = [grid.to_grid(X[0, :, :P]).cpu().numpy()] if traj else None
+    for n in range(N):
+        if len(kl) == 1:
+            ka, kb = kl[0], (kl[0] if extrap else None)
+        elif extrap:
+            ka, kb = kl[n], (kl[n - 1] if n >= 1 else None)
+        else:
+            ka, kb = kl[n + 1], None
+        plan.step(n, ka, kb, X, Y, tau)
+        if traj:
+            path.append(grid.to_grid(X[(n + 1) % 2, :, :P]).cpu().numpy())
+    torch.cuda.synchronize()
+    out = {"X": np.stack([grid.to_grid(X[N % 2, :, :P]).cpu().numpy(),
+                          grid.to_grid(X[(N - 1) % 2, :, :P]).cpu().numpy()]),
+           "tau": grid.to_grid(tau[:, :P]).cpu().numpy(), "plan": plan}
+    if want_modes:
+        m = plan.m
+        o = torch.zeros((m, c, st), dtype=torch.float64, device="cuda")
+        plan.modes_to_plain(N % 2, X, Y, o)
+        out["modes"] = grid.to_grid(o[:, :, :P]).cpu().numpy()
+    if traj:
+        out["traj"] = np.stack(path)
+    return out
+
+
+def case(d, seed):
+    shape, extent = ((6, 8), (1.0, 2.0)) if d == 2 else ((4, 4, 6), (1.0, 2.0, 3.0))
+    c = d * (d + 1) // 2
+    rng = np.random.default_rng(seed)
+    X0 = rng.standard_normal((c,) + shape) * 0.05
+    kd = rng.standard_normal((d, d)) * 0.4
+    return shape, extent, X0, kd
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("N", [1, 2, 17])
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-12), ("fp32_modes", 1e-5)])
+def test_spectral_step_matches_spatial_oracle(d, N, prec, bar):
+    shape, extent, X0, kd = case(d, 20 + d)
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    De, eta_p, eps, dt = 0.8, 0.1, 0.02, 2e-3
+    w, lam, _ = osoe.soe_fit(0.5, 6, dt, dt * max(N, 2))
+    grid = PeriodicGrid(shape, extent)
+    g = run_spectral(grid, eps, d, w, lam, De, eta_p, dt, N, kd.reshape(1, d * d), X0, precision=prec,
+                     want_modes=True)
+    kap = np.repeat(kd.reshape(d * d, 1), P, axis=1)
+    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0.reshape(c, P), want_modes=True)
+    errs = {"X": relerr(g["X"].reshape(2, c, P), o["X"]), "tau": relerr(g["tau"].reshape(c, P), o["tau"]),
+            "modes": relerr(g["modes"].reshape(-1, c, P), o["modes"][0])}
+    print(d, N, prec, errs, flush=True)
+    assert all(e < bar for e in errs.values()), errs
+
+
+@pytest.mark.parametrize("extrap", [True, False])
+def test_spectral_step_time_varying_kappa(extrap):
+    """kappa(t) the same at every point, changing every step: extrapolated or given."""
+    d, N = 2, 12
+    shape, extent, X0, kd = case(d, 31)
+    P = int(np.prod(shape))
+    c = 3
+    rng = np.random.default_rng(5)
+    levels = np.stack([kd + 0.2 * math.sin(0.7 * n) * rng.standard_normal((d, d)) for n in range(N + 1)])
+    De, eta_p, eps, dt = 1.1, 0.1, 0.05, 3e-3
+    w, lam, _ = osoe.soe_fit(0.4, 7, dt, dt * N)
+    grid = PeriodicGrid(shape, extent)
+    g = run_spectral(grid, eps, d, w, lam, De, eta_p, dt, N, levels.reshape(N + 1, 4), X0, extrap=extrap)
+    kap = np.repeat(levels.reshape(N + 1, 4, 1), P, axis=2)
+    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0.reshape(c, P), extrap=extrap)
+    ex, et = relerr(g["X"].reshape(2, c, P), o["X"]), relerr(g["tau"].reshape(c, P), o["tau"])
+    assert ex < 1e-12 and et < 1e-12, (ex, et)
+
+
+def pointwise_coefficient(d, w, lam, De, eta_p, dt, N, kd, x0, rate, source, scheme):
+    """One coefficient of the layout by the pointwise oracle: 1/De -> 1/De + rate at the same
+    eta_p/De; without the mass-mode source (a run from x0 minus a run from 0) unless the
+    coefficient is the constant function's.  Returns (X, tau) and the scale of each (the
+    largest magnitude among the runs combined: the difference of two runs is only known to
+    the rounding of the larger one)."""
+    Dx = 1.0 / (1.0 / De + rate)
+    one = kd.reshape(d * d, 1)
+    st = {"bdf2": "sdirk2", "exp": "exp"}[scheme]
+    r = O.run(d, w, lam, Dx, eta_p * Dx / De, dt, N, one, x0[:, None], startup=st)
+    rx, rt = r["X"][0][:, 0], r["tau"][:, 0]
+    if source:
+        return rx, rt, np.max(np.abs(rx)), np.max(np.abs(rt))
+    z = O.run(d, w, lam, Dx, eta_p * Dx / De, dt, N, one, np.zeros((x0.size, 1)), startup=st)
+    zx, zt = z["X"][0][:, 0], z["tau"][:, 0]
+    return (rx - zx, rt - zt, max(np.max(np.abs(rx)), np.max(np.abs(zx))),
+            max(np.max(np.abs(rt)), np.max(np.abs(zt))))
+
+
+@pytest.mark.parametrize("scheme,d,shape,prec", [("bdf2", 2, (1024, 1024), "fp64"), ("exp", 2, (256, 256), "fp64"),
+                                                 ("bdf2", 3, (64, 64, 64), "fp32_modes"),
+                                                 ("exp", 3, (64, 64, 64), "fp32_modes")])
+def test_large_grid_sampled_coefficients(scheme, d, shape, prec):
+    """A full-size grid in the launch configuration of the benchmark form: 40 sampled
+    coefficients (the constant one, the Nyquist corner, random others) against the
+    pointwise oracle run with the coefficient's rate."""
+    c = d * (d + 1) // 2
+    grid = PeriodicGrid(shape, (1.0,) * d)
+    P = grid.npoints
+    De, eta_p, eps, dt, N, m = 0.5, 0.1, 1e-2, 1e-3, 6, 16
+    w, lam, _ = osoe.soe_fit(0.5, m, dt, 1.0)
+    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, N, precision=prec, scheme=scheme)
+    st = plan.stride
+    rate = grid.rate(eps, st)
+    plan.set_spatial(rate, grid.source_point)
+    g = torch.Generator(device="cuda").manual_seed(9)
+    X = torch.zeros((2, c, st), dtype=torch.float64, device="cuda")
+    X[0, :, :P] = torch.randn((c, P), generator=g, device="cuda", dtype=torch.float64) * 0.05
+    Y = torch.zeros((plan.mode_levels * plan.m * c * st,), dtype=plan.mode_dtype, device="cuda")
+    tau = torch.zeros((c, st), dtype=torch.float64, device="cuda")
+    kd = np.random.default_rng(3).standard_normal((d, d)) * 0.3
+    kt = torch.from_numpy(kd.reshape(d * d, 1)).cuda().expand(d * d, st).contiguous()
+    X0 = X[0, :, :P].cpu().numpy()
+    for n in range(N):
+        plan.step(n, kt, kt, X, Y, tau)
+    torch.cuda.synchronize()
+    Xg, tg = X[N % 2, :, :P].cpu().numpy(), tau[:, :P].cpu().numpy()
+    rng = np.random.default_rng(1)
+    sample = np.unique(np.concatenate([[0, 1, P - 2, P - 1], rng.choice(P, 36, replace=False)]))
+    rt = rate.cpu().numpy()
+    worst = 0.0
+    for j in sample:
+        xo, to, sx, stau = pointwise_coefficient(d, w, lam, De, eta_p, dt, N, kd, X0[:, j], rt[j], j == 0, scheme)
+        worst = max(worst, np.max(np.abs(Xg[:, j] - xo)) / sx, np.max(np.abs(tg[:, j] - to)) / stau)
+    bar = 1e-11 if prec == "fp64" else 1e-5
+    print(scheme, shape, prec, "worst sampled relative error", worst, flush=True)
+    assert worst < bar
+
+
+def test_paper_convergence_experiment_on_gpu():
+    """Sec. 5.1 on a 64 x 64 grid of the unit square: cos(2 pi x1) cos(4 pi x2) in every
+    Hermite component, eps = 1e-2, De = 0.5, alpha = 0.5, T = 1, m = 60: the weighted-norm
+    error against the Mittag-Leffler solution decays like dt^{1.5} (Fig. 2a), and the GPU
+    errors equal the spatial oracle's on an 8 x 8 grid (the mode is resolved on both)."""
+    d, alpha, De, eps, T = 2, 0.5, 0.5, 1e-2, 1.0
+    rate_x = 1.0 / De + 20 * eps * math.pi ** 2
+    norms = []
+    for dt in (1 / 50, 1 / 100, 1 / 200, 1 / 400):
+        N = int(round(T / dt))
+        w, lam, _ = osoe.soe_fit(alpha, 60, dt, T)
+        for shape in ((64, 64),) if dt != 1 / 50 else ((64, 64), (8, 8)):
+            grid = PeriodicGrid(shape, (1.0, 1.0))
+            x1, x2 = np.meshgrid(np.arange(shape[0]) / shape[0], np.arange(shape[1]) / shape[1], indexing="ij")
+            prof = np.cos(2 * math.pi * x1) * np.cos(4 * math.pi * x2)
+            X0 = np.stack([math.sqrt(2) * prof, math.sqrt(2) * prof, prof])
+            g = run_spectral(grid, eps, d, w, lam, De, 0.1, dt, N, np.zeros((1, 4)), X0, traj=True)
+            ts = np.arange(1, N + 1) * dt
+            ml = np.array([mittag_leffler(alpha, -rate_x * t ** alpha) for t in ts])
+            err = g["traj"][1:] - ml[:, None, None, None] * X0[None]
+            l2 = np.mean(np.sum(err ** 2, axis=1), axis=(1, 2))
+            nrm = math.sqrt(np.sum(dt * l2 * ts ** (2 * (1 - alpha))))
+            if shape == (8, 8):
+                o = mfp.run(d, shape, (1.0, 1.0), eps, w, lam, De, 0.1, dt, N, np.zeros((4, 64)),
+                            X0.reshape(3, 64), want_traj=True)
+                oe = o["traj"][1:].reshape(N, 3, 8, 8) - ml[:, None, None, None] * X0[None]
+                onrm = math.sqrt(np.sum(dt * np.mean(np.sum(oe ** 2, axis=1), axis=(1, 2)) * ts ** (2 * (1 - alpha))))
+                assert abs(nrm - onrm) < 1e-9 * onrm, (nrm, onrm)
+            else:
+                norms.append(nrm)
+    orders = [math.log2(norms[i] / norms[i + 1]) for i in range(len(norms) - 1)]
+    print("weighted-norm errors", norms, "orders", orders, flush=True)
+    assert all(1.3 < o < 1.7 for o in orders), (norms, orders)
+
+
+def test_set_spatial_validation_and_adjoint_refused():
+    plan = tfs.Plan(2, 100, [1.0], [0.0], 0.5, 1.0, 0.1, 1e-3, 4)
+    with pytest.raises(tfs.TfsError):
+        plan.set_spatial(None, 100)
+    with pytest.raises(tfs.TfsError):
+        plan.set_spatial(None, -2)
+    plan.set_spatial(None, 3)
+    Xb = torch.zeros((2, 3, plan.stride), dtype=torch.float64, device="cuda")
+    with pytest.raises(tfs.TfsError) as e:
+        plan.step_adjoint(0, Xb[0, :1].expand(4, plan.stride).contiguous(), None, Xb[0], None, Xb[1], None, None,
+                          Xb, torch.zeros(2 * plan.m * 3 * plan.stride, dtype=torch.float64, device="cuda"),
+                          torch.zeros(plan.pbar_size, dtype=torch.float64, device="cuda"))
+    assert "spatial" in str(e.value) or "UNSUPPORTED" in str(e.value).upper()
+    plan.set_spatial(None, -1)      # back to the pointwise form
