@@ -139,6 +139,8 @@ def measure_forms(stream, steps=20, which="all"):
         out["fwd_adjoint_3d_exp"] = _fwd_adjoint(stream, steps, scheme="exp")
     if which in ("all", "slab384"):
         out["fwd_adjoint_384cube_slab"] = _fwd_adjoint(stream, steps, workload=5, npoints=SLAB_384)
+    if which in ("all", "mfp_2d"):
+        out["mfp_spectral_2d"] = _mfp_2d(stream, steps)
     return out
 
 
@@ -227,6 +229,39 @@ def _exp_vs_bdf2(stream, steps):
     return {"workload": wl.name, "form": wl.precision, "steps": 4 + steps, **res,
             "speedup_exp": res["bdf2"]["ms_per_step"] / res["exp"]["ms_per_step"],
             "tau_rel_diff_exp_vs_bdf2": diff}
+
+
+def _mfp_2d(stream, steps):
+    """The spatial form (centre-of-mass diffusion, u = 0) at the parameters of the paper's
+    convergence experiment (Sec. 5.1: unit square, eps = 1e-2, De = 0.5, alpha = 0.5,
+    kappa = 0, initial profile cos(2 pi x1) cos(4 pi x2)) on a 1024 x 1024 periodic grid in
+    the Fourier layout (1 050 624 coefficients), m = 32, FP64, dt = 1e-3: one BDF2 step,
+    priced at the pointwise step's algorithmic bytes plus the rate field (8 B per point)."""
+    import math
+    import torch
+    from paper_2411_17294_amd import tfs
+    from paper_2411_17294_amd.spectral import PeriodicGrid
+    n, m, alpha, De, eps, dt, T = 1024, 32, 0.5, 0.5, 1e-2, 1e-3, 1.0
+    grid = PeriodicGrid((n, n), (1.0, 1.0))
+    P = grid.npoints
+    w, lam, _, _, _ = tfs.soe_fit(alpha, m, dt, T)
+    p = tfs.Plan(2, P, w, lam, alpha, De, 0.1, dt, steps + 8, precision="fp64")
+    p.set_spatial(grid.rate(eps, p.stride), grid.source_point)
+    X, Y, tau, _ = p.alloc()
+    x = torch.arange(n, dtype=torch.float64, device="cuda") / n
+    prof = torch.cos(2 * math.pi * x)[:, None] * torch.cos(4 * math.pi * x)[None, :]
+    X[0, :, :P] = grid.to_points(torch.stack([math.sqrt(2) * prof, math.sqrt(2) * prof, prof]))
+    ka = p.kappa_tensor()
+    p.step(0, ka, None, X, Y, tau)
+    for k in range(1, 4):
+        p.step(k, ka, ka, X, Y, tau)
+    ms = _timed(stream, lambda k: p.step(k, ka, ka, X, Y, tau), 4, steps)
+    nbytes = (algorithmic_bytes_per_point(2, m, 8, 2) + 8) * P
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    name = "mfp_spectral_fp64_2d_1024sq_m32"
+    return {"workload": name, "grid": [n, n], "coefficients": P, "ms_per_step": ms,
+            "point_mode_updates_per_s": P * m / (ms * 1e-3), "bytes_per_launch": nbytes, "achieved_GBs": gbs,
+            "frac": gbs / HBM_PEAK_GBS, "traffic": profiled_traffic("bdf2_kernel_" + name)}
 
 
 def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
@@ -401,7 +436,7 @@ def main():
                     help="run the 384^3 differentiation workload end to end with STEPS time levels")
     ap.add_argument("--job-slabs", type=int, default=64, help="slabs of the --job run (64 = whole grid)")
     ap.add_argument("--only-forms", choices=["all", "fp32_vs_fp64", "fwd_adjoint", "slab384", "exp_vs_bdf2",
-                                             "fwd_adjoint_exp"],
+                                             "fwd_adjoint_exp", "mfp_2d"],
                     default=None,
                     help="only the 3-D form measurements (for profiling)")
     args = ap.parse_args()
