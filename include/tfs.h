@@ -150,6 +150,50 @@ tfs_status tfs_plan_set_stream(tfs_plan plan, void* stream);
 tfs_status tfs_plan_set_spatial(tfs_plan plan, const double* rate, int64_t source_point);
 
 /*
+ * Analytic velocity gradient for fused launches: a sum of Fourier terms on the periodic
+ * grid [0, 2 pi)^d with `grid` points per axis,
+ *     kappa_ij(x, t) = sum_n coef[n][i][j] sin(k[n] . x + phase[n] + omega[n] t),
+ * x_a = 2 pi idx_a / grid, the plan's point p being the flat grid index point0 + p with
+ * idx_0 varying fastest.  A divergence-free field u = sum_n A_n e_n cos(k_n . x + ...) has
+ * coef[n][i][j] = -A_n e_n,i k_n,j.  All arrays are host memory, copied (the plan owns the
+ * device copy; the call allocates and synchronises the plan's stream).
+ */
+#define TFS_FIELD_MAX_TERMS 4096
+typedef struct tfs_field {
+    int32_t nterms;            /* number of terms, 0 .. TFS_FIELD_MAX_TERMS (0: kappa = 0) */
+    int64_t grid;              /* grid points per axis */
+    int64_t point0;            /* flat grid index of the plan's point 0 */
+    const double* k;           /* [nterms][d] wave vectors */
+    const double* phase;       /* [nterms] */
+    const double* omega;       /* [nterms] angular frequencies (all zero: a steady field) */
+    const double* coef;        /* [nterms][d][d] */
+} tfs_field;
+
+/* Errors: TFS_EINVAL (null plan or field, nterms out of range, grid < 1, the points outside
+ * the grid, a null or non-finite table), TFS_ENOMEM, TFS_EHIP. */
+tfs_status tfs_plan_set_field(tfs_plan plan, const tfs_field* field);
+
+/*
+ * Temporally fused steps (exponential-mode scheme, Sec. 2.2 modes integrated exactly for X
+ * linear on each step): advance every point from level n0 to n0 + nsteps in ONE launch,
+ * with kappa evaluated from the plan's field inside the kernel at t_n = n dt and the
+ * half-step gradient kappa~ = 3/2 kappa(t_n) - 1/2 kappa(t_{n-1}) (kappa(t_0) at n = 0), as
+ * tfs_step would with those kappa levels.  Each point's mode level, X and kappa stay in
+ * registers for all nsteps steps: HBM is read once and written once per launch.
+ *
+ * X    device [2][c][stride] ring: level n0 in slot n0 % 2 on entry; on return level
+ *      n0 + nsteps in slot (n0 + nsteps) % 2 and level n0 + nsteps - 1 in the other slot.
+ * Y    device, one mode level in the plan's layout (Y_k = X_k - q_k X), updated in place;
+ *      ignored on entry when n0 = 0.
+ * tau  device [c][stride] or NULL: tau at level n0 + nsteps.
+ * Asynchronous on the plan's stream; no allocation.  Requires a TFS_SCHEME_EXP plan with
+ * m = 16 or 32 (FP32 modes in 3-D; either precision in 2-D), no spatial form, and a field.
+ * Errors: TFS_EINVAL (null plan, no field, 0 <= n0 <= n0 + nsteps <= max_steps violated,
+ * null X or Y), TFS_EUNSUPPORTED (other scheme, m, precision or a spatial form), TFS_EHIP.
+ */
+tfs_status tfs_run_fused(tfs_plan plan, int64_t n0, int64_t nsteps, double* X, void* Y, double* tau);
+
+/*
  * Advance every point from time level n to n+1 (0 <= n < max_steps), asynchronously
  * on the plan's stream; no allocation, no host synchronisation (unless
  * TFS_FLAG_CHECK_SYNC).

@@ -1,0 +1,333 @@
+// Temporally fused exponential-mode steps for an analytic velocity gradient.
+//
+// When kappa(x, t) is a closed-form field (a sum of Fourier terms,
+//   kappa_ij(x, t) = sum_n B_n,ij sin(k_n . x + phi_n + omega_n t)  on [0, 2 pi)^d),
+// no caller interaction is needed between steps: one launch advances every point through
+// K time levels of the exponential-mode scheme (the per-point arithmetic of exp_group,
+// V = 1) with the point's whole state in registers.  The mode level (m c values), X and
+// the previous kappa stay on chip for all K steps; HBM is read once at the start and
+// written once at the end, so the launch is bound by arithmetic, not by memory.
+//
+// Per point and step: kappa at t_n evaluated from the field (FP64 sine per term), the
+// half-step gradient kappa~ = 3/2 kappa^n - 1/2 kappa^{n-1} (kappa^0 at n = 0), the mode
+// update Y_k <- e_k Y_k + f_k X with H and (compensated) G, the c x c solve and, at the last
+// step, tau.  The mode count is a template parameter so the mode array lives in registers.
+#include "tfs_device.h"
+#include "tfs_internal.h"
+
+namespace tfs {
+namespace {
+
+using namespace dev;
+
+constexpr int kFusedBlock = 128;
+// A time-varying field's terms are advanced by angle addition with their (sin, cos) in LDS
+// when a lane has at most this many of them (kRotTerms * 16 B * kFusedBlock per block); more
+// terms are evaluated with one sincos each per step.
+constexpr int kRotTerms = 64;
+// Steps between fresh sincos evaluations of the rotated terms (bounds the drift of the
+// repeated rotation to a few tens of rounding errors).
+constexpr int kReseed = 32;
+
+template <typename MT>
+struct FusedArgs {
+  double* X;              // ring [2][c][stride]: level n0 in slot n0 % 2
+  MT* Y;                  // one mode level (tiled), updated in place
+  double* tau;            // [c][stride] or null (level n0 + nsteps)
+  const double* coef;     // [kNumCoefAll][m], ExpRow order
+  const double* zeta;     // [max_steps + 1] mass-mode increments
+  const double* field;    // [nterms][d + 4 + d*d]: k_n, phi_n, omega_n, cos/sin(omega_n dt), B_n
+  int64_t npoints, stride, tile, n0, nsteps, grid, point0;
+  int nterms, steady;
+  double dt, a_diag, q, s_h, inv_De, tau_scale, eta_e, fa, fb;
+};
+
+// The other lane's value within a pair of lanes (2i, 2i + 1): DPP quad permutation [1, 0, 3, 2].
+__device__ __forceinline__ double pair_other(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0xB1, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0xB1, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over the L lanes of a point (L = 1 or 2); both lanes get the same value.
+template <int L>
+__device__ __forceinline__ double lanes_sum(double v) {
+  if constexpr (L == 2) return v + pair_other(v);
+  return v;
+}
+
+// The velocity gradient driving a step at the point x: kappa(t) when gb = 0, or the
+// half-step extrapolation ga kappa(t) + gb kappa(t - dt) (row-major d x d).  The earlier
+// sine comes from the later one by angle addition, sin(a - w dt) = sin a cos(w dt) -
+// cos a sin(w dt), so each term costs one sincos.  Lane h of the point's L lanes sums the
+// terms n = h, h + L, ...; the caller adds the lanes' sums.
+template <int D, int L>
+__device__ __forceinline__ void field_kappa(const double* f, int nterms, int h, const double (&x)[D], double t,
+                                            double ga, double gb, double (&kap)[D * D]) {
+  constexpr int W = D + 4 + D * D;
+#pragma unroll
+  for (int q = 0; q < D * D; ++q) kap[q] = 0.0;
+  for (int n = h; n < nterms; n += L) {
+    const double* r = opaque_ptr(f) + n * W;
+    double th = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) th += x[j] * r[j];
+    th = th + r[D] + r[D + 1] * t;
+    double sn, cn;
+    sincos(th, &sn, &cn);
+    double wgt = sn;
+    if (gb != 0.0) wgt = ga * sn + gb * (sn * r[D + 2] - cn * r[D + 3]);
+#pragma unroll
+    for (int q = 0; q < D * D; ++q) kap[q] += wgt * r[D + 4 + q];
+  }
+#pragma unroll
+  for (int q = 0; q < D * D; ++q) kap[q] = lanes_sum<L>(kap[q]);
+}
+
+// (sin, cos) of the lane's terms at time t into LDS (rot[i * kFusedBlock + lane]).
+template <int D, int L>
+__device__ __forceinline__ void rot_seed(const double* f, int nterms, int h, const double (&x)[D], double t,
+                                         double2* rot) {
+  constexpr int W = D + 4 + D * D;
+  int i = 0;
+  for (int n = h; n < nterms; n += L, ++i) {
+    const double* r = opaque_ptr(f) + n * W;
+    double th = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) th += x[j] * r[j];
+    th = th + r[D] + r[D + 1] * t;
+    double sn, cn;
+    sincos(th, &sn, &cn);
+    rot[i * kFusedBlock + threadIdx.x] = make_double2(sn, cn);
+  }
+}
+
+// kappa~ from the lane's rotated terms (their sin and cos at t_n), as field_kappa; then the
+// terms move to t_{n+1} (angle addition, or a fresh sincos every kReseed steps).
+template <int D, int L>
+__device__ __forceinline__ void rot_kappa(const double* f, int nterms, int h, const double (&x)[D], double t_next,
+                                          bool reseed, double ga, double gb, double2* rot,
+                                          double (&kap)[D * D]) {
+  constexpr int W = D + 4 + D * D;
+#pragma unroll
+  for (int q = 0; q < D * D; ++q) kap[q] = 0.0;
+  int i = 0;
+  for (int n = h; n < nterms; n += L, ++i) {
+    const double* r = opaque_ptr(f) + n * W;
+    const double2 sc = rot[i * kFusedBlock + threadIdx.x];
+    const double cw = r[D + 2], sw = r[D + 3];
+    double wgt = sc.x;
+    if (gb != 0.0) wgt = ga * sc.x + gb * (sc.x * cw - sc.y * sw);
+#pragma unroll
+    for (int q = 0; q < D * D; ++q) kap[q] += wgt * r[D + 4 + q];
+    double sn, cn;
+    if (reseed) {
+      double th = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) th += x[j] * r[j];
+      th = th + r[D] + r[D + 1] * t_next;
+      sincos(th, &sn, &cn);
+    } else {
+      sn = sc.x * cw + sc.y * sw;
+      cn = sc.y * cw - sc.x * sw;
+    }
+    rot[i * kFusedBlock + threadIdx.x] = make_double2(sn, cn);
+  }
+#pragma unroll
+  for (int q = 0; q < D * D; ++q) kap[q] = lanes_sum<L>(kap[q]);
+}
+
+// One point per L consecutive lanes; lane h of them holds modes [h M/L, (h+1) M/L) in
+// registers.  The lanes add their partial mode sums (H, G) and field terms, then both run
+// the point's c x c solve on the same values.
+template <int D, typename MT, int M, int L>
+__global__ __launch_bounds__(kFusedBlock) void fused_exp_kernel(const FusedArgs<MT> a) {
+  constexpr int C = Sym<D>::C;
+  constexpr int MH = M / L;
+  const int64_t g = (int64_t)blockIdx.x * kFusedBlock + threadIdx.x;
+  const int64_t p = g / L;
+  const int h = (int)(g % L);
+  if (p >= a.npoints) return;
+  const int64_t st = a.stride, T = a.tile;
+  const int64_t ym = (p / T) * (int64_t)M * C * T + p % T;   // mode (0, 0) of the point
+  const int k0 = h * MH;
+
+  double x[D];
+  {
+    int64_t r = a.point0 + p;
+    const double hx = 2.0 * 3.14159265358979323846 / (double)a.grid;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      x[j] = hx * (double)(r % a.grid);
+      r /= a.grid;
+    }
+  }
+  double X[C];
+  const int64_t s0 = a.n0 % 2;
+#pragma unroll
+  for (int s = 0; s < C; ++s) X[s] = a.X[(s0 * C + s) * st + p];
+  MT y[MH][C];
+  if (a.n0 > 0) {
+#pragma unroll
+    for (int k = 0; k < MH; ++k)
+#pragma unroll
+      for (int s = 0; s < C; ++s) y[k][s] = a.Y[ym + (int64_t)((k0 + k) * C + s) * T];
+  }
+  // a steady field is evaluated once; a time-varying one is rotated in LDS when it fits
+  extern __shared__ double2 rot[];
+  const bool rotate = !a.steady && (a.nterms + L - 1) / L <= kRotTerms;
+  double ks[D * D];
+  if (a.steady) field_kappa<D, L>(a.field, a.nterms, h, x, 0.0, 1.0, 0.0, ks);
+  if (rotate) rot_seed<D, L>(a.field, a.nterms, h, x, (double)a.n0 * a.dt, rot);
+  const int64_t sn = (a.n0 + a.nsteps) % 2;
+  double tout[C];
+#pragma unroll
+  for (int s = 0; s < C; ++s) tout[s] = 0.0;
+
+  for (int64_t j = 0; j < a.nsteps; ++j) {
+    const int64_t n = a.n0 + j;
+    const bool first = n == 0;
+    if (j + 1 == a.nsteps && h == 0) {
+      // level n0 + nsteps - 1 goes to the other slot of the ring
+#pragma unroll
+      for (int s = 0; s < C; ++s) a.X[((1 - sn) * C + s) * st + p] = X[s];
+    }
+    double k[D * D];
+    if (a.steady) {
+#pragma unroll
+      for (int q = 0; q < D * D; ++q) k[q] = first ? ks[q] : a.fa * ks[q] + a.fb * ks[q];
+    } else if (rotate) {
+      rot_kappa<D, L>(a.field, a.nterms, h, x, (double)(n + 1) * a.dt, (j + 1) % kReseed == 0, a.fa,
+                      first ? 0.0 : a.fb, rot, k);
+    } else if (first) {
+      field_kappa<D, L>(a.field, a.nterms, h, x, 0.0, 1.0, 0.0, k);
+    } else {
+      field_kappa<D, L>(a.field, a.nterms, h, x, (double)n * a.dt, a.fa, a.fb, k);
+    }
+
+    double H[C], Gs[C], Ge[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) { H[s] = 0.0; Gs[s] = 0.0; Ge[s] = 0.0; }
+    // read the coefficients again every step (scalar-cache hits) instead of holding 5 M of
+    // them in scalar registers across the step loop
+    const double* cf = opaque_ptr(a.coef) + k0;
+#pragma unroll
+    for (int kk = 0; kk < MH; ++kk) {
+      const double ek = cf[kRowE * M + kk];
+      const double fk = cf[kRowF * M + kk];
+      const double lk = cf[kRowLdt * M + kk];
+      const double qk = cf[kRowQ * M + kk];
+      const double ok = cf[kRowOneME * M + kk];
+#pragma unroll
+      for (int s = 0; s < C; ++s) {
+        const double yv = first ? -qk * X[s] : (double)y[kk][s];
+        const MT out = (MT)(ek * yv + fk * X[s]);
+        y[kk][s] = out;
+        H[s] += ok * yv;
+        two_sum_acc(Gs[s], Ge[s], mul_rn(lk, (double)out));
+      }
+      // keep each mode's five coefficients local to its iteration: hoisting all of them to
+      // the top of the step exhausts the scalar registers
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    double Hv[C], AH[C], R[C], G[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      Hv[s] = lanes_sum<L>(H[s]) + a.s_h * X[s];
+      G[s] = lanes_sum<L>(Gs[s] + Ge[s]);
+    }
+    apply_K<D>(k, Hv, AH);
+    const double zeta = a.zeta[n + 1];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      const int i = Sym<D>::i(s), jj = Sym<D>::j(s);
+      const double S = k[i * D + jj] + k[jj * D + i];
+      R[s] = X[s] - (AH[s] - a.inv_De * Hv[s]) + zeta * S;
+    }
+    double Mx[C][C];
+    build_M<D>(k, a.a_diag, a.q, Mx);
+    solve_pivot<C>(Mx, R);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      tout[s] = a.tau_scale * (a.eta_e * R[s] - G[s]);
+      X[s] = R[s];
+    }
+  }
+
+  if (h == 0) {
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      a.X[(sn * C + s) * st + p] = X[s];
+      if (a.tau) a.tau[s * st + p] = tout[s];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < MH; ++k)
+#pragma unroll
+    for (int s = 0; s < C; ++s) a.Y[ym + (int64_t)((k0 + k) * C + s) * T] = y[k][s];
+}
+
+template <int D, typename MT, int M, int L>
+hipError_t fused_go(const tfs_plan_s* p, int64_t n0, int64_t nsteps, double* X, void* Y, double* tau) {
+  FusedArgs<MT> a;
+  a.X = X;
+  a.Y = static_cast<MT*>(Y);
+  a.tau = tau;
+  a.coef = p->d_coef;
+  a.zeta = p->d_zeta;
+  a.field = p->d_field;
+  a.npoints = p->npoints;
+  a.stride = p->stride;
+  a.tile = p->tile;
+  a.n0 = n0;
+  a.nsteps = nsteps;
+  a.grid = p->field_grid;
+  a.point0 = p->field_point0;
+  a.nterms = p->field_terms;
+  a.steady = p->field_steady ? 1 : 0;
+  a.dt = p->dt;
+  a.a_diag = 1.0 + p->q_e / p->De;
+  a.q = p->q_e;
+  a.s_h = p->s_h;
+  a.inv_De = 1.0 / p->De;
+  a.tau_scale = p->tau_scale;
+  a.eta_e = p->eta_e;
+  a.fa = 1.5;
+  a.fb = -0.5;
+  const int64_t blocks = (p->npoints * L + kFusedBlock - 1) / kFusedBlock;
+  const int per_lane = (p->field_terms + L - 1) / L;
+  const size_t lds = (!p->field_steady && per_lane <= kRotTerms) ? sizeof(double2) * per_lane * kFusedBlock : 0;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_exp_kernel<D, MT, M, L>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((fused_exp_kernel<D, MT, M, L>), dim3((unsigned)blocks), dim3(kFusedBlock), lds, p->stream,
+                     a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool fused_supported(const tfs_plan_s* p) {
+  if (p->scheme != TFS_SCHEME_EXP) return false;
+  if (p->m != 16 && p->m != 32) return false;
+  return p->d == 2 || p->precision == TFS_FP32_MODES;
+}
+
+hipError_t launch_fused(const tfs_plan_s* p, int64_t n0, int64_t nsteps, double* X, void* Y, double* tau) {
+  if (p->npoints == 0 || nsteps == 0) return hipSuccess;
+  const bool f32 = p->precision == TFS_FP32_MODES;
+  // two lanes per point: each holds half of the modes and of the field's terms
+  if (p->d == 2) {
+    if (f32) return p->m == 16 ? fused_go<2, float, 16, 2>(p, n0, nsteps, X, Y, tau)
+                               : fused_go<2, float, 32, 2>(p, n0, nsteps, X, Y, tau);
+    return p->m == 16 ? fused_go<2, double, 16, 2>(p, n0, nsteps, X, Y, tau)
+                      : fused_go<2, double, 32, 2>(p, n0, nsteps, X, Y, tau);
+  }
+  return p->m == 16 ? fused_go<3, float, 16, 2>(p, n0, nsteps, X, Y, tau)
+                    : fused_go<3, float, 32, 2>(p, n0, nsteps, X, Y, tau);
+}
+
+}  // namespace tfs

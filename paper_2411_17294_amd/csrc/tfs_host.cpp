@@ -171,6 +171,9 @@ double kernel_relerr(double alpha, int m, const double* w, const double* lam, do
   return worst;
 }
 
+// The plan runs the spatial form (tfs_plan_set_spatial).
+bool spatial(const tfs_plan_s* p) { return p->sp_rate != nullptr || p->sp_source >= 0; }
+
 }  // namespace
 
 extern "C" {
@@ -468,6 +471,8 @@ tfs_status tfs_plan_destroy(tfs_plan p) {
   (void)hipFree(p->d_dest_bdf2);
   (void)hipFree(p->d_dest_start);
   (void)hipFree(p->d_dest_exp);
+  (void)hipFree(p->d_field);
+  (void)hipFree(p->d_zeta);
   delete p;
   if (e1 != hipSuccess) return hip_fail(e1, "hipStreamSynchronize");
   if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
@@ -478,6 +483,75 @@ tfs_status tfs_plan_destroy(tfs_plan p) {
 tfs_status tfs_plan_set_stream(tfs_plan p, void* stream) {
   if (!p) return fail(TFS_EINVAL, "null plan");
   p->stream = static_cast<hipStream_t>(stream);
+  return TFS_OK;
+}
+
+tfs_status tfs_plan_set_field(tfs_plan p, const tfs_field* f) {
+  if (!p || !f) return fail(TFS_EINVAL, "null plan or field");
+  if (f->nterms < 0 || f->nterms > TFS_FIELD_MAX_TERMS)
+    return fail(TFS_EINVAL, "nterms %d outside [0, %d]", f->nterms, TFS_FIELD_MAX_TERMS);
+  if (f->grid < 1) return fail(TFS_EINVAL, "grid must be positive");
+  int64_t cells = 1;
+  for (int j = 0; j < p->d; ++j) {
+    if (cells > std::numeric_limits<int64_t>::max() / f->grid) return fail(TFS_EINVAL, "grid^d overflows");
+    cells *= f->grid;
+  }
+  if (f->point0 < 0 || f->point0 > cells - p->npoints)
+    return fail(TFS_EINVAL, "points [point0, point0 + npoints) outside the grid");
+  if (f->nterms > 0 && (!f->k || !f->phase || !f->omega || !f->coef))
+    return fail(TFS_EINVAL, "null field table");
+  const int d = p->d, W = d + 4 + d * d;
+  std::vector<double> tab((size_t)std::max(1, f->nterms) * W, 0.0);
+  bool steady = true;
+  for (int n = 0; n < f->nterms; ++n) {
+    double* r = tab.data() + (size_t)n * W;
+    for (int j = 0; j < d; ++j) r[j] = f->k[n * d + j];
+    r[d] = f->phase[n];
+    r[d + 1] = f->omega[n];
+    r[d + 2] = std::cos(f->omega[n] * p->dt);   // one step back by angle addition
+    r[d + 3] = std::sin(f->omega[n] * p->dt);
+    for (int q = 0; q < d * d; ++q) r[d + 4 + q] = f->coef[n * d * d + q];
+    for (int q = 0; q < W; ++q)
+      if (!std::isfinite(r[q])) return fail(TFS_EINVAL, "non-finite field table entry");
+    if (f->omega[n] != 0.0) steady = false;
+  }
+  (void)hipSetDevice(p->device);
+  double* dz = p->d_zeta;
+  if (!dz) {
+    hipError_t e = hipMalloc(&dz, sizeof(double) * p->zeta.size());
+    if (e != hipSuccess) return fail(TFS_ENOMEM, "zeta table");
+    e = hipMemcpy(dz, p->zeta.data(), sizeof(double) * p->zeta.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(dz); return hip_fail(e, "upload zeta"); }
+    p->d_zeta = dz;
+  }
+  double* df = nullptr;
+  hipError_t e = hipMalloc(&df, sizeof(double) * tab.size());
+  if (e != hipSuccess) return fail(TFS_ENOMEM, "field table");
+  e = hipMemcpy(df, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { (void)hipFree(df); return hip_fail(e, "upload field"); }
+  e = hipStreamSynchronize(p->stream);   // launches that read the old table have finished
+  if (e != hipSuccess) { (void)hipFree(df); return hip_fail(e, "hipStreamSynchronize"); }
+  (void)hipFree(p->d_field);
+  p->d_field = df;
+  p->field_terms = f->nterms;
+  p->field_grid = f->grid;
+  p->field_point0 = f->point0;
+  p->field_steady = steady;
+  return TFS_OK;
+}
+
+tfs_status tfs_run_fused(tfs_plan p, int64_t n0, int64_t nsteps, double* X, void* Y, double* tau) {
+  if (!p) return fail(TFS_EINVAL, "null plan");
+  if (!tfs::fused_supported(p))
+    return fail(TFS_EUNSUPPORTED, "fused steps need the exponential scheme, m = 16 or 32, and FP32 modes in 3-D");
+  if (spatial(p)) return fail(TFS_EUNSUPPORTED, "no fused steps in the spatial form");
+  if (!p->d_field) return fail(TFS_EINVAL, "no field set (tfs_plan_set_field)");
+  if (n0 < 0 || nsteps < 0 || n0 > p->max_steps - nsteps)
+    return fail(TFS_EINVAL, "levels [%lld, %lld] outside [0, %lld]", (long long)n0, (long long)(n0 + nsteps),
+                (long long)p->max_steps);
+  if (p->npoints > 0 && nsteps > 0 && (!X || !Y)) return fail(TFS_EINVAL, "null X or Y");
+  hipError_t e = tfs::launch_fused(p, n0, nsteps, X, Y, tau);
+  if (e != hipSuccess) return hip_fail(e, "fused launch");
   return TFS_OK;
 }
 
@@ -584,8 +658,6 @@ tfs_status exp_pbar_to_params(tfs_plan p, const double* pb, double* dw, double* 
   if (deta_p) *deta_p = eta_pb;
   return TFS_OK;
 }
-
-bool spatial(const tfs_plan_s* p) { return p->sp_rate != nullptr || p->sp_source >= 0; }
 
 tfs_status run_step(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, const tfs::Levels& L,
                     double* tau, double* diag) {

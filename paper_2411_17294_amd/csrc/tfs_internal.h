@@ -131,6 +131,12 @@ struct tfs_plan_s {
   // tuning (tfs_plan_tune): points per lane (0 = widest aligned), blocks per CU cap
   int vec_override = 0;
   int adj_vec_override = 0;
+  // analytic velocity-gradient field of the fused launches (tfs_plan_set_field)
+  double* d_field = nullptr;         // device [field_terms][d + 2 + d*d]
+  double* d_zeta = nullptr;          // device copy of zeta
+  int field_terms = 0;
+  int64_t field_grid = 0, field_point0 = 0;
+  bool field_steady = false;
   const double* sp_rate = nullptr;   // spatial form: extra relaxation rate per point (caller-owned)
   int64_t sp_source = -1;            // spatial form: the point with the mass-mode source, -1 = all
   int grid_per_cu = 16;
@@ -170,6 +176,9 @@ struct AdjLevels {
 
 // Launchers (tfs_kernels.hip, tfs_adjoint.hip).  They only enqueue work on plan->stream.
 hipError_t launch_adjoint(const tfs_plan_s* p, int64_t n, const AdjLevels& L, double* pbar);
+// Fused exponential-mode steps with kappa from the plan's analytic field (tfs_fused.hip).
+bool fused_supported(const tfs_plan_s* p);
+hipError_t launch_fused(const tfs_plan_s* p, int64_t n0, int64_t nsteps, double* X, void* Y, double* tau);
 hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
                        double* tau, double* diag);
 hipError_t launch_startup(const tfs_plan_s* p, const double* ka, const Levels& L, double* tau, double* diag);

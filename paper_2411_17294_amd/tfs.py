@@ -22,7 +22,7 @@ TFS_SCHEME_BDF2, TFS_SCHEME_EXP = 0, 1
 TFS_FLAG_CHECK_SYNC = 1
 
 EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
-           "tfs_step_levels", "tfs_step_adjoint", "tfs_pbar_size", "tfs_pbar_to_params", "tfs_modes_to_plain",
+           "tfs_step_levels", "tfs_step_adjoint", "tfs_plan_set_field", "tfs_run_fused", "tfs_pbar_size", "tfs_pbar_to_params", "tfs_modes_to_plain",
            "tfs_plan_tables", "tfs_plan_stride", "tfs_plan_tile", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
            "tfs_status_string", "tfs_last_error")
 
@@ -47,6 +47,12 @@ class PlanDesc(C.Structure):
                 ("scheme", C.c_int32)]
 
 
+class FieldDesc(C.Structure):
+    _fields_ = [("nterms", C.c_int32), ("grid", C.c_int64), ("point0", C.c_int64), ("k", C.POINTER(C.c_double)),
+                ("phase", C.POINTER(C.c_double)), ("omega", C.POINTER(C.c_double)),
+                ("coef", C.POINTER(C.c_double))]
+
+
 _lib = None
 
 
@@ -64,6 +70,8 @@ def lib():
     L.tfs_plan_destroy.argtypes = [vp]
     L.tfs_plan_set_stream.argtypes = [vp, vp]
     L.tfs_plan_set_spatial.argtypes = [vp, vp, i64]
+    L.tfs_plan_set_field.argtypes = [vp, C.POINTER(FieldDesc)]
+    L.tfs_run_fused.argtypes = [vp, i64, i64, vp, vp, vp]
     L.tfs_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
     L.tfs_step_levels.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.tfs_step_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -83,7 +91,7 @@ def lib():
     L.tfs_status_string.restype = C.c_char_p
     L.tfs_last_error.restype = C.c_char_p
     for name in ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
-                 "tfs_step_levels",
+                 "tfs_step_levels", "tfs_plan_set_field", "tfs_run_fused",
                  "tfs_step_adjoint", "tfs_pbar_to_params", "tfs_modes_to_plain",
                  "tfs_plan_tables", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log"):
         getattr(L, name).restype = C.c_int
@@ -187,6 +195,29 @@ class Plan:
         self._need(rate, "rate", self.stride, torch.float64)
         check(lib().tfs_plan_set_spatial(self._h, _tptr(rate), int(source_point)))
         self._sp_rate = rate
+
+    def set_field(self, k, phase, omega, coef, grid, point0=0):
+        """Analytic velocity gradient of the fused launches (tfs_plan_set_field): host arrays
+        k [NF][d], phase [NF], omega [NF], coef [NF][d][d] (kappa_ij = sum_n coef_nij
+        sin(k_n . x + phase_n + omega_n t) on the grid of `grid` points per axis)."""
+        d = self.dim
+        k = np.ascontiguousarray(k, dtype=np.float64).reshape(-1, d)
+        nf = k.shape[0]
+        ph = np.ascontiguousarray(phase, dtype=np.float64).reshape(nf)
+        om = np.ascontiguousarray(omega, dtype=np.float64).reshape(nf)
+        cf = np.ascontiguousarray(coef, dtype=np.float64).reshape(nf, d * d)
+        desc = FieldDesc(nf, int(grid), int(point0), _dptr(k), _dptr(ph), _dptr(om), _dptr(cf))
+        check(lib().tfs_plan_set_field(self._h, C.byref(desc)))
+
+    def run_fused(self, n0, nsteps, X, Y, tau=None):
+        """Levels n0 -> n0 + nsteps in one launch, kappa from the plan's field (tfs_run_fused)."""
+        import torch
+        if self.npoints > 0:
+            st, c = self.stride, self.c
+            self._need(X, "X", 2 * c * st, torch.float64)
+            self._need(Y, "Y", self.mode_levels * self.m * c * st, self.mode_dtype)
+            self._need(tau, "tau", c * st, torch.float64)
+        check(lib().tfs_run_fused(self._h, int(n0), int(nsteps), _tptr(X), _tptr(Y), _tptr(tau)))
 
     def tune(self, key: str, value: int):
         check(lib().tfs_plan_tune(self._h, key.encode(), int(value)))

@@ -1,0 +1,151 @@
+"""Temporally fused exponential-mode steps (tfs_run_fused): K time levels per launch with
+kappa evaluated from the analytic Fourier field inside the kernel, against the oracle
+(kappa levels from the same field definition in numpy) and against the step-by-step GPU
+path fed with those levels.  Launches of 70 and 33 steps pass the points where the kernel
+re-evaluates the rotated field terms with a fresh sincos."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from oracle import soe as osoe
+from paper_2411_17294_amd import inputs as I
+from paper_2411_17294_amd import tfs
+from tests.gpu_helpers import relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def field_of(wl_id, steady):
+    ff = I.fourier_field(I.WORKLOADS[wl_id])
+    if steady:
+        ff.omega = np.zeros_like(ff.omega)
+    return ff
+
+
+def make_plan(d, P, m, prec, dt, N, alpha=0.5, De=1.0, eta_p=0.1):
+    w, lam, _ = osoe.soe_fit(alpha, m, dt, dt * N * 10)
+    plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, N, precision=prec, scheme="exp")
+    return plan, w, lam
+
+
+def levels(ff, grid, points, dt, N):
+    idx = I.grid_multi_index(grid, ff.dim, points)
+    return np.stack([ff.kappa_at(idx, grid, n * dt) for n in range(N + 1)])      # [N+1][d*d][P]
+
+
+def fused_run(plan, ff, grid, point0, X0, chunks):
+    """Fused launches of the given step counts from level 0; returns X ring, Y, tau."""
+    d, c, st, P = plan.dim, plan.c, plan.stride, plan.npoints
+    plan.set_field(ff.k, ff.phase, ff.omega, ff.coef(), grid, point0)
+    X, Y, tau, _ = plan.alloc()
+    X[0, :, :P] = torch.from_numpy(X0).cuda()
+    n0 = 0
+    for K in chunks:
+        plan.run_fused(n0, K, X, Y, tau)
+        n0 += K
+    torch.cuda.synchronize()
+    return X, Y, tau, n0
+
+
+def stepwise_run(plan, kap_levels, X0, N):
+    d, c, st, P = plan.dim, plan.c, plan.stride, plan.npoints
+    X, Y, tau, _ = plan.alloc()
+    X[0, :, :P] = torch.from_numpy(X0).cuda()
+    lv = []
+    for n in range(N + 1):
+        t = torch.zeros((d * d, st), dtype=torch.float64, device="cuda")
+        t[:, :P] = torch.from_numpy(kap_levels[n]).cuda()
+        lv.append(t)
+    for n in range(N):
+        plan.step(n, lv[n], lv[n - 1] if n >= 1 else None, X, Y, tau)
+    torch.cuda.synchronize()
+    return X, Y, tau
+
+
+def plain_modes(plan, X, Y, slot):
+    o = torch.zeros((plan.m, plan.c, plan.stride), dtype=torch.float64, device="cuda")
+    plan.modes_to_plain(slot, X, Y, o)
+    torch.cuda.synchronize()
+    return o[:, :, :plan.npoints].cpu().numpy()
+
+
+CASES = [(2, "fp64", 16, 32, False), (2, "fp64", 32, 32, False), (2, "fp32_modes", 32, 32, False),
+         (2, "fp32_modes", 16, 32, True), (3, "fp32_modes", 32, 12, False), (3, "fp32_modes", 16, 12, True)]
+
+
+@pytest.mark.parametrize("d,prec,m,grid,steady", CASES)
+@pytest.mark.parametrize("chunks", [(1,), (13,), (4, 1, 8), (70,), (33, 31)])
+def test_fused_matches_oracle_and_stepwise_path(d, prec, m, grid, steady, chunks):
+    wl_id = 2 if d == 2 else 5
+    ff = field_of(wl_id, steady)
+    P = grid ** d - 7                                   # not a multiple of the block or the pair
+    point0 = 5
+    N = sum(chunks)
+    dt = 2e-3
+    plan, w, lam = make_plan(d, P, m, prec, dt, N)
+    X0 = I.random_symmetric_case(d, P, 41, kscale=0.6, xscale=2e-2)[1]
+    points = np.arange(point0, point0 + P)
+    kl = levels(ff, grid, points, dt, N)
+    X, Y, tau, n_end = fused_run(plan, ff, grid, point0, X0, chunks)
+    Xs, Ys, taus = stepwise_run(plan, kl, X0, N)
+    o = O.run(d, w, lam, 1.0, 0.1, dt, N, kl, X0, startup="exp", want_modes=True)
+    bar = 1e-12 if prec == "fp64" else 1e-5
+    got = {"X": np.stack([X[N % 2, :, :P].cpu().numpy(), X[(N - 1) % 2, :, :P].cpu().numpy()]),
+           "tau": tau[:, :P].cpu().numpy(), "modes": plain_modes(plan, X, Y, N % 2)}
+    step = {"X": np.stack([Xs[N % 2, :, :P].cpu().numpy(), Xs[(N - 1) % 2, :, :P].cpu().numpy()]),
+            "tau": taus[:, :P].cpu().numpy(), "modes": plain_modes(plan, Xs, Ys, N % 2)}
+    errs = {k: relerr(got[k], o[k][0] if k == "modes" else o[k]) for k in got}
+    errs_step = {k: relerr(got[k], step[k]) for k in got}
+    print(d, prec, m, steady, chunks, "oracle", errs, "stepwise", errs_step, flush=True)
+    assert all(e < bar for e in errs.values()), errs
+    assert all(e < bar for e in errs_step.values()), errs_step
+
+
+def test_fused_full_size_128cube_sampled():
+    """The 128^3, m = 32, FP32-mode configuration with a time-varying field, 40 steps in two
+    launches, in the benchmark's launch configuration: 48 sampled points against the oracle."""
+    wl = I.WORKLOADS[4]
+    ff = field_of(5, False)
+    g, d, m, dt, N = 128, 3, 32, 2.5e-4, 40
+    P = g ** 3
+    plan, w, lam = make_plan(d, P, m, "fp32_modes", dt, N, alpha=wl.alphas[0], De=wl.De, eta_p=wl.eta_p)
+    X0 = I.initial_state(wl)
+    X, Y, tau, _ = fused_run(plan, ff, g, 0, X0, (25, 15))
+    rng = np.random.default_rng(4)
+    sample = np.unique(np.concatenate([[0, P - 1], rng.choice(P, 46, replace=False)]))
+    kl = levels(ff, g, sample, dt, N)
+    o = O.run(d, w, lam, wl.De, wl.eta_p, dt, N, kl, X0[:, sample], startup="exp", want_modes=True)
+    sel = torch.from_numpy(sample).cuda()
+    ex = relerr(X[N % 2][:, sel].cpu().numpy(), o["X"][0])
+    et = relerr(tau[:, sel].cpu().numpy(), o["tau"])
+    em = relerr(plain_modes(plan, X, Y, N % 2)[:, :, sample], o["modes"][0])
+    print("128^3 fused sample", ex, et, em, flush=True)
+    assert ex < 1e-5 and et < 1e-5 and em < 1e-5
+
+
+def test_fused_errors_and_noop():
+    ff = field_of(2, False)
+    plan, _, _ = make_plan(2, 100, 16, "fp64", 1e-3, 10)
+    X, Y, tau, _ = plan.alloc()
+    with pytest.raises(tfs.TfsError):              # no field yet
+        plan.run_fused(0, 1, X, Y, tau)
+    plan.set_field(ff.k, ff.phase, ff.omega, ff.coef(), 32, 0)
+    with pytest.raises(tfs.TfsError):              # past max_steps
+        plan.run_fused(5, 6, X, Y, tau)
+    with pytest.raises(tfs.TfsError):              # points outside the grid
+        plan.set_field(ff.k, ff.phase, ff.omega, ff.coef(), 32, 32 * 32 - 50)
+    X[0].fill_(0.25)
+    before = X.clone()
+    plan.run_fused(3, 0, X, Y, tau)                # nothing to do
+    torch.cuda.synchronize()
+    assert torch.equal(X, before)
+    bad, _, _ = make_plan(2, 100, 20, "fp64", 1e-3, 10)
+    bad.set_field(ff.k, ff.phase, ff.omega, ff.coef(), 32, 0)
+    with pytest.raises(tfs.TfsError):              # m = 20 has no fused variant
+        bad.run_fused(0, 1, *bad.alloc()[:3])
+    w, lam, _ = osoe.soe_fit(0.5, 16, 1e-3, 1e-2)
+    bdf = tfs.Plan(2, 100, w, lam, 0.5, 1.0, 0.1, 1e-3, 10)
+    bdf.set_field(ff.k, ff.phase, ff.omega, ff.coef(), 32, 0)
+    with pytest.raises(tfs.TfsError):              # the paper's BDF2 scheme keeps two mode levels
+        bdf.run_fused(0, 1, *bdf.alloc()[:3])
