@@ -141,6 +141,8 @@ def measure_forms(stream, steps=20, which="all"):
         out["fwd_adjoint_384cube_slab"] = _fwd_adjoint(stream, steps, workload=5, npoints=SLAB_384)
     if which in ("all", "mfp_2d"):
         out["mfp_spectral_2d"] = _mfp_2d(stream, steps)
+    if which in ("all", "fused"):
+        out["fused_exp"] = _fused(stream)
     return out
 
 
@@ -262,6 +264,68 @@ def _mfp_2d(stream, steps):
     return {"workload": name, "grid": [n, n], "coefficients": P, "ms_per_step": ms,
             "point_mode_updates_per_s": P * m / (ms * 1e-3), "bytes_per_launch": nbytes, "achieved_GBs": gbs,
             "frac": gbs / HBM_PEAK_GBS, "traffic": profiled_traffic("bdf2_kernel_" + name)}
+
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X
+
+
+def fused_flops_per_point_step(dim, m, nterms):
+    """Floating-point operations of one fused step per point: the mode update (7 per
+    mode-component: e y + f X, (1 - e) y into H, lambda dt Y into G), the field (per term:
+    rotation 6, half-step weight 6, the d x d accumulation 2 d^2) and the local system
+    (assembly, elimination 2c^3/3, A(H), tau: taken as 2c^3/3 + 8c^2)."""
+    c = dim * (dim + 1) // 2
+    return 7 * m * c + nterms * (12 + 2 * dim * dim) + (2 * c ** 3) // 3 + 8 * c * c
+
+
+def _fused(stream, K=50):
+    """Temporally fused steps (tfs_run_fused): the exponential scheme advanced K = 50 levels
+    per launch with kappa evaluated in the kernel from the analytic field, next to the
+    step-by-step path (one step kernel per level plus the synthesis of that level's kappa on
+    the device), for a time-varying and a steady field: 128^3, m = 32, FP32 modes with the
+    384^3 configuration's field; 1024^2, m = 32, FP64 with the 1024^2 workload's field."""
+    import numpy as np
+    import torch
+    from paper_2411_17294_amd import inputs as I
+    from paper_2411_17294_amd import tfs
+    from paper_2411_17294_amd.device_inputs import DeviceKappa
+    res = {}
+    for name, d, g, wl_id, ff_id, prec in (("3d_128cube_m32_fp32modes", 3, 128, 4, 5, "fp32_modes"),
+                                           ("2d_1024sq_m32_fp64", 2, 1024, 2, 2, "fp64")):
+        wl = I.WORKLOADS[wl_id]
+        P, m, dt = g ** d, 32, wl.dt
+        w, lam, _, _, _ = tfs.soe_fit(wl.alphas[0], m, dt, dt * wl.nsteps)
+        for steady in (False, True):
+            ff = I.fourier_field(I.WORKLOADS[ff_id])
+            if steady:
+                ff.omega = np.zeros_like(ff.omega)
+            p = tfs.Plan(d, P, w, lam, wl.alphas[0], wl.De, wl.eta_p, dt, 3 * K + 16, precision=prec,
+                         scheme="exp")
+            p.set_field(ff.k, ff.phase, ff.omega, ff.coef(), g, 0)
+            X, Y, tau, _ = p.alloc()
+            p.run_fused(0, K, X, Y, tau)
+            ms = _timed(stream, lambda n: p.run_fused(K + n * K, K, X, Y, tau), 0, 2) / K
+            ka, kb = p.kappa_tensor(), p.kappa_tensor()
+            dk = DeviceKappa(ff, g, P)
+            n0 = 3 * K
+            for n in range(n0, n0 + 3):
+                p.step(n, ka, kb, X, Y, tau)
+            ms_step = _timed(stream, lambda n: p.step(n, ka, kb, X, Y, tau), n0 + 3, 10)
+            dk.fill(ka, 0.0)
+            # a steady field is synthesised once, not per step
+            ms_fill = 0.0 if steady else _timed(stream, lambda n: dk.fill(ka, n * dt), 1, 5)
+            flops = fused_flops_per_point_step(d, m, 0 if steady else len(ff.amp)) * P
+            tf = flops / (ms * 1e-3) / 1e12
+            res[name + ("_steady" if steady else "_time_varying")] = {
+                "ms_per_step": ms, "point_mode_updates_per_s": P * m / (ms * 1e-3), "steps_per_launch": K,
+                "stepwise_kernel_ms": ms_step, "kappa_synthesis_ms_per_step": ms_fill,
+                "speedup_vs_stepwise_with_synthesis": (ms_step + ms_fill) / ms,
+                "speedup_vs_step_kernel_alone": ms_step / ms,
+                "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": tf / FP64_VECTOR_PEAK_TFLOPS}}
+            del p, X, Y, tau, ka, kb, dk
+            torch.cuda.empty_cache()
+    return res
 
 
 def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
@@ -436,7 +500,7 @@ def main():
                     help="run the 384^3 differentiation workload end to end with STEPS time levels")
     ap.add_argument("--job-slabs", type=int, default=64, help="slabs of the --job run (64 = whole grid)")
     ap.add_argument("--only-forms", choices=["all", "fp32_vs_fp64", "fwd_adjoint", "slab384", "exp_vs_bdf2",
-                                             "fwd_adjoint_exp", "mfp_2d"],
+                                             "fwd_adjoint_exp", "mfp_2d", "fused"],
                     default=None,
                     help="only the 3-D form measurements (for profiling)")
     args = ap.parse_args()
