@@ -72,14 +72,14 @@ __device__ __forceinline__ void field_kappa(const double* f, int nterms, int h, 
     const double* r = opaque_ptr(f) + n * W;
     double th = 0.0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) th += x[j] * r[j];
-    th = th + r[D] + r[D + 1] * t;
+    for (int j = 0; j < D; ++j) th += x[j] * load_uniform(r + j);
+    th = th + load_uniform(r + D) + load_uniform(r + D + 1) * t;
     double sn, cn;
     sincos(th, &sn, &cn);
     double wgt = sn;
-    if (gb != 0.0) wgt = ga * sn + gb * (sn * r[D + 2] - cn * r[D + 3]);
+    if (gb != 0.0) wgt = ga * sn + gb * (sn * load_uniform(r + D + 2) - cn * load_uniform(r + D + 3));
 #pragma unroll
-    for (int q = 0; q < D * D; ++q) kap[q] += wgt * r[D + 4 + q];
+    for (int q = 0; q < D * D; ++q) kap[q] += wgt * load_uniform(r + D + 4 + q);
   }
 #pragma unroll
   for (int q = 0; q < D * D; ++q) kap[q] = lanes_sum<L>(kap[q]);
@@ -95,8 +95,8 @@ __device__ __forceinline__ void rot_seed(const double* f, int nterms, int h, con
     const double* r = opaque_ptr(f) + n * W;
     double th = 0.0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) th += x[j] * r[j];
-    th = th + r[D] + r[D + 1] * t;
+    for (int j = 0; j < D; ++j) th += x[j] * load_uniform(r + j);
+    th = th + load_uniform(r + D) + load_uniform(r + D + 1) * t;
     double sn, cn;
     sincos(th, &sn, &cn);
     rot[i * kFusedBlock + threadIdx.x] = make_double2(sn, cn);
@@ -116,17 +116,17 @@ __device__ __forceinline__ void rot_kappa(const double* f, int nterms, int h, co
   for (int n = h; n < nterms; n += L, ++i) {
     const double* r = opaque_ptr(f) + n * W;
     const double2 sc = rot[i * kFusedBlock + threadIdx.x];
-    const double cw = r[D + 2], sw = r[D + 3];
+    const double cw = load_uniform(r + D + 2), sw = load_uniform(r + D + 3);
     double wgt = sc.x;
     if (gb != 0.0) wgt = ga * sc.x + gb * (sc.x * cw - sc.y * sw);
 #pragma unroll
-    for (int q = 0; q < D * D; ++q) kap[q] += wgt * r[D + 4 + q];
+    for (int q = 0; q < D * D; ++q) kap[q] += wgt * load_uniform(r + D + 4 + q);
     double sn, cn;
     if (reseed) {
       double th = 0.0;
 #pragma unroll
-      for (int j = 0; j < D; ++j) th += x[j] * r[j];
-      th = th + r[D] + r[D + 1] * t_next;
+      for (int j = 0; j < D; ++j) th += x[j] * load_uniform(r + j);
+      th = th + load_uniform(r + D) + load_uniform(r + D + 1) * t_next;
       sincos(th, &sn, &cn);
     } else {
       sn = sc.x * cw + sc.y * sw;
@@ -136,6 +136,38 @@ __device__ __forceinline__ void rot_kappa(const double* f, int nterms, int h, co
   }
 #pragma unroll
   for (int q = 0; q < D * D; ++q) kap[q] = lanes_sum<L>(kap[q]);
+}
+
+// The lane's modes advanced one step: Y_k <- e_k Y_k + f_k X (Y_k = -q_k X before the first
+// step), with H = sum (1 - e_k) Y_k and G = sum lambda_k dt Y_k^{new} (compensated).
+template <int C, typename MT, int M, int MH, bool FIRST>
+__device__ __forceinline__ void mode_pass(const double* coef, int k0, const double (&X)[C], MT (&y)[MH][C],
+                                          double (&H)[C], double (&Gs)[C], double (&Ge)[C]) {
+#pragma unroll
+  for (int s = 0; s < C; ++s) { H[s] = 0.0; Gs[s] = 0.0; Ge[s] = 0.0; }
+  // the coefficients are read again every step (scalar-cache hits) instead of holding 5 M
+  // of them in scalar registers across the step loop
+  const double* cf = opaque_ptr(coef) + k0;
+#pragma unroll
+  for (int kk = 0; kk < MH; ++kk) {
+    const double ek = load_uniform(cf + kRowE * M + kk);
+    const double fk = load_uniform(cf + kRowF * M + kk);
+    const double lk = load_uniform(cf + kRowLdt * M + kk);
+    const double ok = load_uniform(cf + kRowOneME * M + kk);
+    double qk = 0.0;
+    if constexpr (FIRST) qk = load_uniform(cf + kRowQ * M + kk);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      const double yv = FIRST ? -qk * X[s] : (double)y[kk][s];
+      const MT out = (MT)(ek * yv + fk * X[s]);
+      y[kk][s] = out;
+      H[s] += ok * yv;
+      two_sum_acc(Gs[s], Ge[s], mul_rn(lk, (double)out));
+    }
+    // keep each mode's coefficients local to its iteration: hoisting all of them to the
+    // top of the step exhausts the scalar registers
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 // One point per L consecutive lanes; lane h of them holds modes [h M/L, (h+1) M/L) in
@@ -207,30 +239,8 @@ __global__ __launch_bounds__(kFusedBlock) void fused_exp_kernel(const FusedArgs<
     }
 
     double H[C], Gs[C], Ge[C];
-#pragma unroll
-    for (int s = 0; s < C; ++s) { H[s] = 0.0; Gs[s] = 0.0; Ge[s] = 0.0; }
-    // read the coefficients again every step (scalar-cache hits) instead of holding 5 M of
-    // them in scalar registers across the step loop
-    const double* cf = opaque_ptr(a.coef) + k0;
-#pragma unroll
-    for (int kk = 0; kk < MH; ++kk) {
-      const double ek = cf[kRowE * M + kk];
-      const double fk = cf[kRowF * M + kk];
-      const double lk = cf[kRowLdt * M + kk];
-      const double qk = cf[kRowQ * M + kk];
-      const double ok = cf[kRowOneME * M + kk];
-#pragma unroll
-      for (int s = 0; s < C; ++s) {
-        const double yv = first ? -qk * X[s] : (double)y[kk][s];
-        const MT out = (MT)(ek * yv + fk * X[s]);
-        y[kk][s] = out;
-        H[s] += ok * yv;
-        two_sum_acc(Gs[s], Ge[s], mul_rn(lk, (double)out));
-      }
-      // keep each mode's five coefficients local to its iteration: hoisting all of them to
-      // the top of the step exhausts the scalar registers
-      __builtin_amdgcn_sched_barrier(0);
-    }
+    if (first) mode_pass<C, MT, M, MH, true>(a.coef, k0, X, y, H, Gs, Ge);
+    else mode_pass<C, MT, M, MH, false>(a.coef, k0, X, y, H, Gs, Ge);
     double Hv[C], AH[C], R[C], G[C];
 #pragma unroll
     for (int s = 0; s < C; ++s) {
