@@ -104,35 +104,27 @@ __device__ __forceinline__ void rot_seed(const double* f, int nterms, int h, con
 }
 
 // kappa~ from the lane's rotated terms (their sin and cos at t_n), as field_kappa; then the
-// terms move to t_{n+1} (angle addition, or a fresh sincos every kReseed steps).
+// terms move to t_{n+1} by angle addition (the caller re-seeds them every kReseed steps).
 template <int D, int L>
-__device__ __forceinline__ void rot_kappa(const double* f, int nterms, int h, const double (&x)[D], double t_next,
-                                          bool reseed, double ga, double gb, double2* rot,
+__device__ __forceinline__ void rot_kappa(const double* f, int nterms, int h, double ga, double gb, double2* rot,
                                           double (&kap)[D * D]) {
   constexpr int W = D + 4 + D * D;
 #pragma unroll
   for (int q = 0; q < D * D; ++q) kap[q] = 0.0;
-  int i = 0;
-  for (int n = h; n < nterms; n += L, ++i) {
-    const double* r = opaque_ptr(f) + n * W;
+  const int cnt = (nterms - h + L - 1) / L;
+  const double* fb = opaque_ptr(f) + h * W;
+  // two terms in flight in 2-D (measured faster); one in 3-D, where registers are short
+  constexpr int kU = D == 2 ? 2 : 1;
+#pragma unroll kU
+  for (int i = 0; i < cnt; ++i) {
+    const double* r = fb + i * (L * W);
     const double2 sc = rot[i * kFusedBlock + threadIdx.x];
     const double cw = load_uniform(r + D + 2), sw = load_uniform(r + D + 3);
     double wgt = sc.x;
     if (gb != 0.0) wgt = ga * sc.x + gb * (sc.x * cw - sc.y * sw);
 #pragma unroll
     for (int q = 0; q < D * D; ++q) kap[q] += wgt * load_uniform(r + D + 4 + q);
-    double sn, cn;
-    if (reseed) {
-      double th = 0.0;
-#pragma unroll
-      for (int j = 0; j < D; ++j) th += x[j] * load_uniform(r + j);
-      th = th + load_uniform(r + D) + load_uniform(r + D + 1) * t_next;
-      sincos(th, &sn, &cn);
-    } else {
-      sn = sc.x * cw + sc.y * sw;
-      cn = sc.y * cw - sc.x * sw;
-    }
-    rot[i * kFusedBlock + threadIdx.x] = make_double2(sn, cn);
+    rot[i * kFusedBlock + threadIdx.x] = make_double2(sc.x * cw + sc.y * sw, sc.y * cw - sc.x * sw);
   }
 #pragma unroll
   for (int q = 0; q < D * D; ++q) kap[q] = lanes_sum<L>(kap[q]);
@@ -230,8 +222,8 @@ __global__ __launch_bounds__(kFusedBlock) void fused_exp_kernel(const FusedArgs<
 #pragma unroll
       for (int q = 0; q < D * D; ++q) k[q] = first ? ks[q] : a.fa * ks[q] + a.fb * ks[q];
     } else if (rotate) {
-      rot_kappa<D, L>(a.field, a.nterms, h, x, (double)(n + 1) * a.dt, (j + 1) % kReseed == 0, a.fa,
-                      first ? 0.0 : a.fb, rot, k);
+      rot_kappa<D, L>(a.field, a.nterms, h, a.fa, first ? 0.0 : a.fb, rot, k);
+      if ((j + 1) % kReseed == 0) rot_seed<D, L>(a.field, a.nterms, h, x, (double)(n + 1) * a.dt, rot);
     } else if (first) {
       field_kappa<D, L>(a.field, a.nterms, h, x, 0.0, 1.0, 0.0, k);
     } else {
