@@ -269,29 +269,34 @@ def _mfp_2d(stream, steps):
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X
 
 
-def fused_flops_per_point_step(dim, m, nterms):
+def fused_flops_per_point_step(dim, m, nterms, scheme="exp"):
     """Floating-point operations of one fused step per point: the mode update (7 per
-    mode-component: e y + f X, (1 - e) y into H, lambda dt Y into G), the field (per term:
-    rotation 6, half-step weight 6, the d x d accumulation 2 d^2) and the local system
-    (assembly, elimination 2c^3/3, A(H), tau: taken as 2c^3/3 + 8c^2)."""
+    mode-component: e y + f X, (1 - e) y into H, lambda dt Y into G for the exponential
+    scheme; 2 Y^n - Y^{n-1}/2, d h + dc P, eta h into G for BDF2), the field (per term:
+    rotation 6, extrapolation weight 6, the d x d accumulation 2 d^2) and the local system
+    (assembly, elimination 2c^3/3, A(.), tau: taken as 2c^3/3 + 8c^2)."""
     c = dim * (dim + 1) // 2
     return 7 * m * c + nterms * (12 + 2 * dim * dim) + (2 * c ** 3) // 3 + 8 * c * c
 
 
 def _fused(stream, K=50):
-    """Temporally fused steps (tfs_run_fused): the exponential scheme advanced K = 50 levels
-    per launch with kappa evaluated in the kernel from the analytic field, next to the
-    step-by-step path (one step kernel per level plus the synthesis of that level's kappa on
-    the device), for a time-varying and a steady field: 128^3, m = 32, FP32 modes with the
-    384^3 configuration's field; 1024^2, m = 32, FP64 with the 1024^2 workload's field."""
+    """Temporally fused steps (tfs_run_fused): K = 50 levels per launch with kappa evaluated
+    in the kernel from the analytic field, next to the step-by-step path (one step kernel per
+    level plus the synthesis of that level's kappa on the device), for the exponential scheme
+    and the paper's BDF2 scheme (after its SDIRK2 start), time-varying and steady fields:
+    128^3, m = 32, FP32 modes with the 384^3 configuration's field; 1024^2, m = 32, FP64 with
+    the 1024^2 workload's field."""
     import numpy as np
     import torch
     from paper_2411_17294_amd import inputs as I
     from paper_2411_17294_amd import tfs
     from paper_2411_17294_amd.device_inputs import DeviceKappa
     res = {}
-    for name, d, g, wl_id, ff_id, prec in (("3d_128cube_m32_fp32modes", 3, 128, 4, 5, "fp32_modes"),
-                                           ("2d_1024sq_m32_fp64", 2, 1024, 2, 2, "fp64")):
+    for name, d, g, wl_id, ff_id, prec, scheme in (
+            ("exp_3d_128cube_m32_fp32modes", 3, 128, 4, 5, "fp32_modes", "exp"),
+            ("bdf2_3d_128cube_m32_fp32modes", 3, 128, 4, 5, "fp32_modes", "bdf2"),
+            ("exp_2d_1024sq_m32_fp64", 2, 1024, 2, 2, "fp64", "exp"),
+            ("bdf2_2d_1024sq_m32_fp64", 2, 1024, 2, 2, "fp64", "bdf2")):
         wl = I.WORKLOADS[wl_id]
         P, m, dt = g ** d, 32, wl.dt
         w, lam, _, _, _ = tfs.soe_fit(wl.alphas[0], m, dt, dt * wl.nsteps)
@@ -300,13 +305,18 @@ def _fused(stream, K=50):
             if steady:
                 ff.omega = np.zeros_like(ff.omega)
             p = tfs.Plan(d, P, w, lam, wl.alphas[0], wl.De, wl.eta_p, dt, 3 * K + 16, precision=prec,
-                         scheme="exp")
+                         scheme=scheme)
             p.set_field(ff.k, ff.phase, ff.omega, ff.coef(), g, 0)
             X, Y, tau, _ = p.alloc()
-            p.run_fused(0, K, X, Y, tau)
-            ms = _timed(stream, lambda n: p.run_fused(K + n * K, K, X, Y, tau), 0, 2) / K
             ka, kb = p.kappa_tensor(), p.kappa_tensor()
             dk = DeviceKappa(ff, g, P)
+            first = 0
+            if scheme == "bdf2":       # level 0 -> 1 is the SDIRK2 start (tfs_step)
+                dk.fill(ka, 0.0)
+                p.step(0, ka, None, X, Y, tau)
+                first = 1
+            p.run_fused(first, K, X, Y, tau)
+            ms = _timed(stream, lambda n: p.run_fused(first + K + n * K, K, X, Y, tau), 0, 2) / K
             n0 = 3 * K
             for n in range(n0, n0 + 3):
                 p.step(n, ka, kb, X, Y, tau)
@@ -314,7 +324,7 @@ def _fused(stream, K=50):
             dk.fill(ka, 0.0)
             # a steady field is synthesised once, not per step
             ms_fill = 0.0 if steady else _timed(stream, lambda n: dk.fill(ka, n * dt), 1, 5)
-            flops = fused_flops_per_point_step(d, m, 0 if steady else len(ff.amp)) * P
+            flops = fused_flops_per_point_step(d, m, 0 if steady else len(ff.amp), scheme) * P
             tf = flops / (ms * 1e-3) / 1e12
             res[name + ("_steady" if steady else "_time_varying")] = {
                 "ms_per_step": ms, "point_mode_updates_per_s": P * m / (ms * 1e-3), "steps_per_launch": K,
@@ -340,8 +350,12 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
     P = wl.npoints if npoints is None else npoints
     alpha = wl.alphas[0]
     w, lam, _, _, _ = tfs.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * wl.nsteps)
+    # mode-ring tile measured best per configuration: 4096 points for the 128^3, m = 32 grid
+    # (its BDF2 forward and recompute run 5-7% faster than with the 3-D default), the
+    # default 8192 for the 384^3 slab (its adjoint runs 8% slower with 4096)
+    tile = 4096 if workload == 4 else None
     p = tfs.Plan(wl.dim, P, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=wl.precision,
-                 scheme=scheme)
+                 scheme=scheme, tile=tile)
     exp = scheme == "exp"
     ka, kb = p.kappa_tensor(), p.kappa_tensor()
     dk = DeviceKappa(I.fourier_field(wl), wl.grid, P)

@@ -174,22 +174,26 @@ typedef struct tfs_field {
 tfs_status tfs_plan_set_field(tfs_plan plan, const tfs_field* field);
 
 /*
- * Temporally fused steps (exponential-mode scheme, Sec. 2.2 modes integrated exactly for X
- * linear on each step): advance every point from level n0 to n0 + nsteps in ONE launch,
- * with kappa evaluated from the plan's field inside the kernel at t_n = n dt and the
- * half-step gradient kappa~ = 3/2 kappa(t_n) - 1/2 kappa(t_{n-1}) (kappa(t_0) at n = 0), as
- * tfs_step would with those kappa levels.  Each point's mode level, X and kappa stay in
- * registers for all nsteps steps: HBM is read once and written once per launch.
+ * Temporally fused steps: advance every point from level n0 to n0 + nsteps in ONE launch,
+ * with kappa evaluated from the plan's field inside the kernel at t_n = n dt, as tfs_step
+ * would advance them with those kappa levels:
+ *   TFS_SCHEME_EXP   kappa~ = 3/2 kappa(t_n) - 1/2 kappa(t_{n-1}) (kappa(t_0) at n = 0);
+ *   TFS_SCHEME_BDF2  kappa~ = 2 kappa(t_n) - kappa(t_{n-1}) (eq. BDF_and_extrapolation), from
+ *                    n0 >= 1: level 0 -> 1 is the SDIRK2 start, taken with tfs_step.
+ * Each point's mode levels, X and kappa stay in registers for all nsteps steps: HBM is read
+ * once and written once per launch.
  *
- * X    device [2][c][stride] ring: level n0 in slot n0 % 2 on entry; on return level
- *      n0 + nsteps in slot (n0 + nsteps) % 2 and level n0 + nsteps - 1 in the other slot.
- * Y    device, one mode level in the plan's layout (Y_k = X_k - q_k X), updated in place;
- *      ignored on entry when n0 = 0.
+ * X    device [2][c][stride] ring: levels n0 (slot n0 % 2) and, for BDF2, n0 - 1 on entry; on
+ *      return level n0 + nsteps in slot (n0 + nsteps) % 2 and level n0 + nsteps - 1 in the
+ *      other slot.
+ * Y    device modes in the plan's layout (Y_k = X_k - c_k X): for BDF2 the two-slot ring of
+ *      tfs_step, for EXP its one level, updated in place (ignored on entry when n0 = 0).
  * tau  device [c][stride] or NULL: tau at level n0 + nsteps.
- * Asynchronous on the plan's stream; no allocation.  Requires a TFS_SCHEME_EXP plan with
- * m = 16 or 32 (FP32 modes in 3-D; either precision in 2-D), no spatial form, and a field.
- * Errors: TFS_EINVAL (null plan, no field, 0 <= n0 <= n0 + nsteps <= max_steps violated,
- * null X or Y), TFS_EUNSUPPORTED (other scheme, m, precision or a spatial form), TFS_EHIP.
+ * Asynchronous on the plan's stream; no allocation.  Requires m = 16 or 32 (FP32 modes in
+ * 3-D; either precision in 2-D), no spatial form, and a field.
+ * Errors: TFS_EINVAL (null plan, no field, 0 <= n0 <= n0 + nsteps <= max_steps violated, a
+ * BDF2 launch from n0 = 0, null X or Y), TFS_EUNSUPPORTED (other m or precision, or a
+ * spatial form), TFS_EHIP.
  */
 tfs_status tfs_run_fused(tfs_plan plan, int64_t n0, int64_t nsteps, double* X, void* Y, double* tau);
 

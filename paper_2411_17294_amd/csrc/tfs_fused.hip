@@ -40,20 +40,25 @@ struct FusedArgs {
   int64_t npoints, stride, tile, n0, nsteps, grid, point0;
   int nterms, steady;
   double dt, a_diag, q, s_h, inv_De, tau_scale, eta_e, fa, fb;
+  double eta, s_ec;       // BDF2: eta = sum_k b0 c_k, s_ec = sum_k eta_k c_k
 };
 
-// The other lane's value within a pair of lanes (2i, 2i + 1): DPP quad permutation [1, 0, 3, 2].
-__device__ __forceinline__ double pair_other(double v) {
+// v moved within each quad of lanes by the DPP quad permutation CTRL.
+template <int CTRL>
+__device__ __forceinline__ double quad_mov(double v) {
   const uint64_t b = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0xB1, 0xf, 0xf, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0xB1, 0xf, 0xf, false);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// Sum over the L lanes of a point (L = 1 or 2); both lanes get the same value.
+// Sum over the L lanes of a point (L = 1, 2 or 4 consecutive lanes); every lane gets the
+// same value: pairs exchange by quad_perm [1, 0, 3, 2], then halves of the quad by
+// [2, 3, 0, 1].
 template <int L>
 __device__ __forceinline__ double lanes_sum(double v) {
-  if constexpr (L == 2) return v + pair_other(v);
+  if constexpr (L >= 2) v = v + quad_mov<0xB1>(v);
+  if constexpr (L == 4) v = v + quad_mov<0x4E>(v);
   return v;
 }
 
@@ -270,7 +275,154 @@ __global__ __launch_bounds__(kFusedBlock) void fused_exp_kernel(const FusedArgs<
     for (int s = 0; s < C; ++s) a.Y[ym + (int64_t)((k0 + k) * C + s) * T] = y[k][s];
 }
 
+// One BDF2 step of the lane's modes (Sec. 4.1 in the representation Y_k = X_k - c_k X):
+// h_k = 2 Y_k^n - Y_k^{n-1}/2, Y_k^{n+1} = d_k h_k + d_k c_k P written over Y_k^{n-1}, and
+// the lane's part of G = sum eta_k h_k (compensated).
+template <int C, typename MT, int M, int MH>
+__device__ __forceinline__ void bdf2_mode_pass(const double* coef, int k0, const double (&P)[C],
+                                               const MT (&yn)[MH][C], MT (&ym)[MH][C], double (&Gs)[C],
+                                               double (&Ge)[C]) {
+#pragma unroll
+  for (int s = 0; s < C; ++s) { Gs[s] = 0.0; Ge[s] = 0.0; }
+  const double* cf = opaque_ptr(coef) + k0;
+#pragma unroll
+  for (int kk = 0; kk < MH; ++kk) {
+    const double dk = load_uniform(cf + kRowD * M + kk);
+    const double dck = load_uniform(cf + kRowDC * M + kk);
+    const double ek = load_uniform(cf + kRowEta * M + kk);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      const double h = 2.0 * (double)yn[kk][s] - 0.5 * (double)ym[kk][s];
+      ym[kk][s] = (MT)(dk * h + dck * P[s]);
+      two_sum_acc(Gs[s], Ge[s], mul_rn(ek, h));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// One fused BDF2 time level n -> n+1 of a point: kappa~ = 2 kappa(t_n) - kappa(t_{n-1}) from
+// the field, the modes (yn = level n, ym = level n-1, overwritten with n+1), the c x c solve.
 template <int D, typename MT, int M, int L>
+__device__ __forceinline__ void bdf2_fused_step(const FusedArgs<MT>& a, int h, int64_t n, int64_t j, bool rotate,
+                                                const double (&x)[D], const double (&ks)[D * D], double2* rot,
+                                                double (&Xn)[Sym<D>::C], double (&Xm)[Sym<D>::C],
+                                                const MT (&yn)[M / L][Sym<D>::C], MT (&ym)[M / L][Sym<D>::C],
+                                                double (&tout)[Sym<D>::C]) {
+  constexpr int C = Sym<D>::C;
+  double k[D * D];
+  if (a.steady) {
+#pragma unroll
+    for (int q = 0; q < D * D; ++q) k[q] = 2.0 * ks[q] - ks[q];
+  } else if (rotate) {
+    rot_kappa<D, L>(a.field, a.nterms, h, 2.0, -1.0, rot, k);
+    if ((j + 1) % kReseed == 0) rot_seed<D, L>(a.field, a.nterms, h, x, (double)(n + 1) * a.dt, rot);
+  } else {
+    field_kappa<D, L>(a.field, a.nterms, h, x, (double)n * a.dt, 2.0, -1.0, k);
+  }
+  double P[C], Gs[C], Ge[C], G[C], AG[C], R[C];
+#pragma unroll
+  for (int s = 0; s < C; ++s) P[s] = 2.0 * Xn[s] - 0.5 * Xm[s];
+  bdf2_mode_pass<C, MT, M, M / L>(a.coef, h * (M / L), P, yn, ym, Gs, Ge);
+#pragma unroll
+  for (int s = 0; s < C; ++s) G[s] = lanes_sum<L>(Gs[s] + Ge[s]) + a.s_ec * P[s];
+  apply_K<D>(k, G, AG);
+  const double zeta = a.zeta[n + 1];
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    const int i = Sym<D>::i(s), jj = Sym<D>::j(s);
+    const double S = k[i * D + jj] + k[jj * D + i];
+    R[s] = P[s] - (AG[s] - a.inv_De * G[s]) + zeta * S;
+  }
+  double Mx[C][C];
+  build_M<D>(k, a.a_diag, a.eta, Mx);
+  solve_pivot<C>(Mx, R);
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    tout[s] = a.tau_scale * (a.eta * R[s] - G[s]);
+    Xm[s] = Xn[s];
+    Xn[s] = R[s];
+  }
+}
+
+// Fused BDF2 levels n0 -> n0 + nsteps (n0 >= 1): L lanes per point, each with its share of
+// both mode levels in registers; level j returns to ring slot j % 2.
+template <int D, typename MT, int M, int L>
+__global__ __launch_bounds__(kFusedBlock) void fused_bdf2_kernel(const FusedArgs<MT> a) {
+  constexpr int C = Sym<D>::C;
+  constexpr int MH = M / L;
+  const int64_t g = (int64_t)blockIdx.x * kFusedBlock + threadIdx.x;
+  const int64_t p = g / L;
+  const int h = (int)(g % L);
+  if (p >= a.npoints) return;
+  const int64_t st = a.stride, T = a.tile;
+  const int64_t ys = (int64_t)M * C * st;                     // one ring slot
+  const int64_t ym0 = (p / T) * (int64_t)M * C * T + p % T;
+  const int k0 = h * MH;
+  double x[D];
+  {
+    int64_t r = a.point0 + p;
+    const double hx = 2.0 * 3.14159265358979323846 / (double)a.grid;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      x[j] = hx * (double)(r % a.grid);
+      r /= a.grid;
+    }
+  }
+  const int64_t sa = a.n0 % 2, sb = 1 - sa;
+  double Xn[C], Xm[C], tout[C];
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    Xn[s] = a.X[(sa * C + s) * st + p];
+    Xm[s] = a.X[(sb * C + s) * st + p];
+    tout[s] = 0.0;
+  }
+  MT ya[MH][C], yb[MH][C];
+#pragma unroll
+  for (int k = 0; k < MH; ++k)
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      ya[k][s] = a.Y[sa * ys + ym0 + (int64_t)((k0 + k) * C + s) * T];
+      yb[k][s] = a.Y[sb * ys + ym0 + (int64_t)((k0 + k) * C + s) * T];
+    }
+  extern __shared__ double2 rot[];
+  const bool rotate = !a.steady && (a.nterms + L - 1) / L <= kRotTerms;
+  double ks[D * D];
+  if (a.steady) field_kappa<D, L>(a.field, a.nterms, h, x, 0.0, 1.0, 0.0, ks);
+  if (rotate) rot_seed<D, L>(a.field, a.nterms, h, x, (double)a.n0 * a.dt, rot);
+  // ya holds level n and yb level n - 1; the step overwrites yb with n + 1, then the two swap
+  // (register moves: calling the step with the roles exchanged every other step holds more
+  // registers)
+  for (int64_t j = 0; j < a.nsteps; ++j) {
+    bdf2_fused_step<D, MT, M, L>(a, h, a.n0 + j, j, rotate, x, ks, rot, Xn, Xm, ya, yb, tout);
+#pragma unroll
+    for (int k = 0; k < MH; ++k)
+#pragma unroll
+      for (int s = 0; s < C; ++s) {
+        const MT t = ya[k][s];
+        ya[k][s] = yb[k][s];
+        yb[k][s] = t;
+      }
+  }
+  // after the loop ya holds level n0 + nsteps and yb level n0 + nsteps - 1
+  const int64_t sn = (a.n0 + a.nsteps) % 2;
+  if (h == 0) {
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      a.X[(sn * C + s) * st + p] = Xn[s];
+      a.X[((1 - sn) * C + s) * st + p] = Xm[s];
+      if (a.tau) a.tau[s * st + p] = tout[s];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < MH; ++k)
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      a.Y[sn * ys + ym0 + (int64_t)((k0 + k) * C + s) * T] = ya[k][s];
+      a.Y[(1 - sn) * ys + ym0 + (int64_t)((k0 + k) * C + s) * T] = yb[k][s];
+    }
+}
+
+template <int D, typename MT, int M, int L, bool BDF2>
 hipError_t fused_go(const tfs_plan_s* p, int64_t n0, int64_t nsteps, double* X, void* Y, double* tau) {
   FusedArgs<MT> a;
   a.X = X;
@@ -297,23 +449,31 @@ hipError_t fused_go(const tfs_plan_s* p, int64_t n0, int64_t nsteps, double* X, 
   a.eta_e = p->eta_e;
   a.fa = 1.5;
   a.fb = -0.5;
+  a.eta = p->eta;
+  a.s_ec = p->s_ec;
+  if constexpr (BDF2) a.a_diag = p->a_diag;
+  const void* fn;
+  if constexpr (BDF2) fn = reinterpret_cast<const void*>(&fused_bdf2_kernel<D, MT, M, L>);
+  else fn = reinterpret_cast<const void*>(&fused_exp_kernel<D, MT, M, L>);
   const int64_t blocks = (p->npoints * L + kFusedBlock - 1) / kFusedBlock;
   const int per_lane = (p->field_terms + L - 1) / L;
   const size_t lds = (!p->field_steady && per_lane <= kRotTerms) ? sizeof(double2) * per_lane * kFusedBlock : 0;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_exp_kernel<D, MT, M, L>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((fused_exp_kernel<D, MT, M, L>), dim3((unsigned)blocks), dim3(kFusedBlock), lds, p->stream,
-                     a);
+  if constexpr (BDF2)
+    hipLaunchKernelGGL((fused_bdf2_kernel<D, MT, M, L>), dim3((unsigned)blocks), dim3(kFusedBlock), lds, p->stream,
+                       a);
+  else
+    hipLaunchKernelGGL((fused_exp_kernel<D, MT, M, L>), dim3((unsigned)blocks), dim3(kFusedBlock), lds, p->stream,
+                       a);
   return hipGetLastError();
 }
 
 }  // namespace
 
 bool fused_supported(const tfs_plan_s* p) {
-  if (p->scheme != TFS_SCHEME_EXP) return false;
   if (p->m != 16 && p->m != 32) return false;
   return p->d == 2 || p->precision == TFS_FP32_MODES;
 }
@@ -321,15 +481,26 @@ bool fused_supported(const tfs_plan_s* p) {
 hipError_t launch_fused(const tfs_plan_s* p, int64_t n0, int64_t nsteps, double* X, void* Y, double* tau) {
   if (p->npoints == 0 || nsteps == 0) return hipSuccess;
   const bool f32 = p->precision == TFS_FP32_MODES;
-  // two lanes per point: each holds half of the modes and of the field's terms
-  if (p->d == 2) {
-    if (f32) return p->m == 16 ? fused_go<2, float, 16, 2>(p, n0, nsteps, X, Y, tau)
-                               : fused_go<2, float, 32, 2>(p, n0, nsteps, X, Y, tau);
-    return p->m == 16 ? fused_go<2, double, 16, 2>(p, n0, nsteps, X, Y, tau)
-                      : fused_go<2, double, 32, 2>(p, n0, nsteps, X, Y, tau);
+  // the exponential scheme: two lanes per point, each with half of the one mode level and of
+  // the field's terms; BDF2 (two levels): four lanes per point
+  if (p->scheme == TFS_SCHEME_BDF2) {
+    if (p->d == 2) {
+      if (f32) return p->m == 16 ? fused_go<2, float, 16, 4, true>(p, n0, nsteps, X, Y, tau)
+                                 : fused_go<2, float, 32, 4, true>(p, n0, nsteps, X, Y, tau);
+      return p->m == 16 ? fused_go<2, double, 16, 4, true>(p, n0, nsteps, X, Y, tau)
+                        : fused_go<2, double, 32, 4, true>(p, n0, nsteps, X, Y, tau);
+    }
+    return p->m == 16 ? fused_go<3, float, 16, 4, true>(p, n0, nsteps, X, Y, tau)
+                      : fused_go<3, float, 32, 4, true>(p, n0, nsteps, X, Y, tau);
   }
-  return p->m == 16 ? fused_go<3, float, 16, 2>(p, n0, nsteps, X, Y, tau)
-                    : fused_go<3, float, 32, 2>(p, n0, nsteps, X, Y, tau);
+  if (p->d == 2) {
+    if (f32) return p->m == 16 ? fused_go<2, float, 16, 2, false>(p, n0, nsteps, X, Y, tau)
+                               : fused_go<2, float, 32, 2, false>(p, n0, nsteps, X, Y, tau);
+    return p->m == 16 ? fused_go<2, double, 16, 2, false>(p, n0, nsteps, X, Y, tau)
+                      : fused_go<2, double, 32, 2, false>(p, n0, nsteps, X, Y, tau);
+  }
+  return p->m == 16 ? fused_go<3, float, 16, 2, false>(p, n0, nsteps, X, Y, tau)
+                    : fused_go<3, float, 32, 2, false>(p, n0, nsteps, X, Y, tau);
 }
 
 }  // namespace tfs

@@ -543,7 +543,9 @@ tfs_status tfs_plan_set_field(tfs_plan p, const tfs_field* f) {
 tfs_status tfs_run_fused(tfs_plan p, int64_t n0, int64_t nsteps, double* X, void* Y, double* tau) {
   if (!p) return fail(TFS_EINVAL, "null plan");
   if (!tfs::fused_supported(p))
-    return fail(TFS_EUNSUPPORTED, "fused steps need the exponential scheme, m = 16 or 32, and FP32 modes in 3-D");
+    return fail(TFS_EUNSUPPORTED, "fused steps need m = 16 or 32, and FP32 modes in 3-D");
+  if (p->scheme == TFS_SCHEME_BDF2 && n0 < 1 && nsteps > 0)
+    return fail(TFS_EINVAL, "fused BDF2 steps start at level 1 or later (level 0 -> 1 is tfs_step's SDIRK2 start)");
   if (spatial(p)) return fail(TFS_EUNSUPPORTED, "no fused steps in the spatial form");
   if (!p->d_field) return fail(TFS_EINVAL, "no field set (tfs_plan_set_field)");
   if (n0 < 0 || nsteps < 0 || n0 > p->max_steps - nsteps)

@@ -1,7 +1,8 @@
 """Temporally fused exponential-mode steps (tfs_run_fused): K time levels per launch with
 kappa evaluated from the analytic Fourier field inside the kernel, against the oracle
 (kappa levels from the same field definition in numpy) and against the step-by-step GPU
-path fed with those levels.  Launches of 70 and 33 steps pass the points where the kernel
+path fed with those levels, for the exponential scheme and for the paper's BDF2 scheme
+(after its SDIRK2 start).  Launches of 69 and more steps pass the points where the kernel
 re-evaluates the rotated field terms with a fresh sincos."""
 import numpy as np
 import pytest
@@ -23,9 +24,9 @@ def field_of(wl_id, steady):
     return ff
 
 
-def make_plan(d, P, m, prec, dt, N, alpha=0.5, De=1.0, eta_p=0.1):
+def make_plan(d, P, m, prec, dt, N, alpha=0.5, De=1.0, eta_p=0.1, scheme="exp"):
     w, lam, _ = osoe.soe_fit(alpha, m, dt, dt * N * 10)
-    plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, N, precision=prec, scheme="exp")
+    plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, N, precision=prec, scheme=scheme)
     return plan, w, lam
 
 
@@ -34,13 +35,19 @@ def levels(ff, grid, points, dt, N):
     return np.stack([ff.kappa_at(idx, grid, n * dt) for n in range(N + 1)])      # [N+1][d*d][P]
 
 
-def fused_run(plan, ff, grid, point0, X0, chunks):
-    """Fused launches of the given step counts from level 0; returns X ring, Y, tau."""
+def fused_run(plan, ff, grid, point0, X0, chunks, kap0=None):
+    """Fused launches of the given step counts from level 0; returns X ring, Y, tau.  For
+    BDF2 plans the first level comes from tfs_step (the SDIRK2 start) with kappa level kap0."""
     d, c, st, P = plan.dim, plan.c, plan.stride, plan.npoints
     plan.set_field(ff.k, ff.phase, ff.omega, ff.coef(), grid, point0)
     X, Y, tau, _ = plan.alloc()
     X[0, :, :P] = torch.from_numpy(X0).cuda()
     n0 = 0
+    if kap0 is not None:
+        k0 = torch.zeros((d * d, st), dtype=torch.float64, device="cuda")
+        k0[:, :P] = torch.from_numpy(kap0).cuda()
+        plan.step(0, k0, None, X, Y, tau)
+        n0 = 1
     for K in chunks:
         plan.run_fused(n0, K, X, Y, tau)
         n0 += K
@@ -147,5 +154,48 @@ def test_fused_errors_and_noop():
     w, lam, _ = osoe.soe_fit(0.5, 16, 1e-3, 1e-2)
     bdf = tfs.Plan(2, 100, w, lam, 0.5, 1.0, 0.1, 1e-3, 10)
     bdf.set_field(ff.k, ff.phase, ff.omega, ff.coef(), 32, 0)
-    with pytest.raises(tfs.TfsError):              # the paper's BDF2 scheme keeps two mode levels
+    with pytest.raises(tfs.TfsError):              # BDF2 fused launches start after the SDIRK2 step
         bdf.run_fused(0, 1, *bdf.alloc()[:3])
+
+
+BDF2_CASES = [(2, "fp64", 32, 32, False), (2, "fp32_modes", 16, 32, True), (2, "fp64", 16, 32, True),
+              (3, "fp32_modes", 32, 12, False), (3, "fp32_modes", 16, 12, True)]
+
+
+@pytest.mark.parametrize("d,prec,m,grid,steady", BDF2_CASES)
+@pytest.mark.parametrize("chunks", [(1,), (12,), (4, 1, 7), (69,)])
+def test_fused_bdf2_matches_oracle_and_stepwise_path(d, prec, m, grid, steady, chunks):
+    """The paper's scheme fused: the SDIRK2 start by tfs_step, then levels 1 -> N in fused
+    launches, against the oracle (SDIRK2 + BDF2 with the extrapolated kappa levels) and the
+    step-by-step GPU path."""
+    ff = field_of(2 if d == 2 else 5, steady)
+    P = grid ** d - 7
+    point0 = 5
+    N = 1 + sum(chunks)
+    dt = 2e-3
+    plan, w, lam = make_plan(d, P, m, prec, dt, N, scheme="bdf2")
+    X0 = I.random_symmetric_case(d, P, 43, kscale=0.6, xscale=2e-2)[1]
+    kl = levels(ff, grid, np.arange(point0, point0 + P), dt, N)
+    X, Y, tau, _ = fused_run(plan, ff, grid, point0, X0, chunks, kap0=kl[0])
+    Xs, Ys, taus = stepwise_run(plan, kl, X0, N)
+    o = O.run(d, w, lam, 1.0, 0.1, dt, N, kl, X0, startup="sdirk2", want_modes=True)
+    bar = 1e-12 if prec == "fp64" else 1e-5
+    got = {"X": np.stack([X[N % 2, :, :P].cpu().numpy(), X[(N - 1) % 2, :, :P].cpu().numpy()]),
+           "tau": tau[:, :P].cpu().numpy(),
+           "modes": np.stack([plain_modes(plan, X, Y, N % 2), plain_modes(plan, X, Y, (N - 1) % 2)])}
+    step = {"X": np.stack([Xs[N % 2, :, :P].cpu().numpy(), Xs[(N - 1) % 2, :, :P].cpu().numpy()]),
+            "tau": taus[:, :P].cpu().numpy(),
+            "modes": np.stack([plain_modes(plan, Xs, Ys, N % 2), plain_modes(plan, Xs, Ys, (N - 1) % 2)])}
+    errs = {k: relerr(got[k], o[k]) for k in got}
+    errs_step = {k: relerr(got[k], step[k]) for k in got}
+    print("bdf2", d, prec, m, steady, chunks, "oracle", errs, "stepwise", errs_step, flush=True)
+    assert all(e < bar for e in errs.values()), errs
+    assert all(e < bar for e in errs_step.values()), errs_step
+
+
+def test_fused_bdf2_needs_the_start_step():
+    ff = field_of(2, False)
+    plan, _, _ = make_plan(2, 100, 16, "fp64", 1e-3, 10, scheme="bdf2")
+    plan.set_field(ff.k, ff.phase, ff.omega, ff.coef(), 32, 0)
+    with pytest.raises(tfs.TfsError):
+        plan.run_fused(0, 3, *plan.alloc()[:3])
