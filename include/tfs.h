@@ -140,11 +140,13 @@ tfs_status tfs_plan_set_stream(tfs_plan plan, void* stream);
  * source_point  the point that holds the constant basis function's coefficient (it alone
  *               gets the mass-mode source), or -1: every point gets it (the plain
  *               pointwise form).
- * Applies to tfs_step and tfs_step_levels of both schemes until it is called again;
- * rate = NULL with source_point = -1 restores the pointwise form.  tfs_step_adjoint
- * returns TFS_EUNSUPPORTED while a spatial form is set.  The diagnostics' minors do not
- * describe a conformation tensor in this form; TFS_FLAG_CHECK_SYNC then checks only the
- * non-finite count.
+ * Applies to tfs_step, tfs_step_levels and, for TFS_SCHEME_BDF2 plans, tfs_step_adjoint
+ * until it is called again; rate = NULL with source_point = -1 restores the pointwise form.
+ * The adjoint of an exponential-scheme plan returns TFS_EUNSUPPORTED while a spatial form
+ * is set.  With a rate field the adjoint also accumulates sum_p rate_p dL/drate_p
+ * (tfs_pbar_rate_gradient): for rate = eps |xi|^2 that is eps dL/deps.  The diagnostics'
+ * minors do not describe a conformation tensor in this form; TFS_FLAG_CHECK_SYNC then
+ * checks only the non-finite count.
  * Errors: TFS_EINVAL (null plan, source_point < -1 or >= npoints).
  */
 tfs_status tfs_plan_set_spatial(tfs_plan plan, const double* rate, int64_t source_point);
@@ -295,6 +297,14 @@ int64_t tfs_pbar_size(tfs_plan plan);
  */
 tfs_status tfs_pbar_to_params(tfs_plan plan, const double* pbar_host, double* dL_dw, double* dL_dlambda,
                               double* dL_dDe, double* dL_deta_p);
+
+/*
+ * Spatial form: sum_p rate_p dL/drate_p from a host copy of the accumulated pbar of a
+ * backward pass (eps dL/deps when rate = eps |xi|^2: the gradient with respect to the
+ * diffusion coefficient, scaled).  Zero without a rate field.
+ * Errors: TFS_EINVAL (null plan, pbar or out).
+ */
+tfs_status tfs_pbar_rate_gradient(tfs_plan plan, const double* pbar_host, double* out);
 
 /*
  * Convert the mode ring slot `slot` (0 or 1) to plain fractional modes

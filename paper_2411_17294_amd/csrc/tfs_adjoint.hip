@@ -193,6 +193,27 @@ __device__ __forceinline__ void add_kbar(double* kb, double f, int64_t st, const
   for (int t = 0; t < D * D; ++t) store_v<FULL, double, V>(at(kb + t * st + w.pw, w.ox), nv, x[t]);
 }
 
+// Spatial form (tfs_plan_set_spatial): each point's extra relaxation rate and whether it is
+// the one point that carries the mass-mode source.
+struct AdjSpatial {
+  const double* rate;   // [stride] or null
+  int64_t src;          // the source point, or -1 (every point)
+};
+
+// rate and source weight (1 or 0) of the points p0 .. p0 + V - 1 at base + byte offset
+template <bool FULL, int V>
+__device__ __forceinline__ void adj_spatial(const AdjSpatial& sp, const double* rate_base, int64_t p0, int nv,
+                                            double (&rate)[V], double (&srcw)[V]) {
+  if (sp.rate) {
+    load_v<FULL, double, V>(rate_base, nv, rate);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) rate[v] = 0.0;
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) srcw[v] = (sp.src < 0 || p0 + v == sp.src) ? 1.0 : 0.0;
+}
+
 // ------------------------------------------------------------------ BDF2 step adjoint
 template <typename MT>
 struct AdjArgs {
@@ -218,6 +239,7 @@ struct AdjArgs {
   int64_t stride, tile;
   int m, part0;
   Bdf2Scalars s;
+  AdjSpatial sp;
 };
 
 // Per-lane values kept in LDS across the mode stream (they are needed again after it):
@@ -227,7 +249,7 @@ struct AdjSlots {
   static constexpr int N = Sym<D>::C + D * D;
 };
 
-template <int D, typename MT, int V, bool FULL>
+template <int D, typename MT, int V, bool FULL, bool SP>
 __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& w, int nv, double* smode,
                                           double* slot, double (&sc)[kNumAdjScalars]) {
   constexpr int C = Sym<D>::C;
@@ -265,9 +287,15 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
 #pragma unroll
         for (int v = 0; v < V; ++v) tb[s][v] = 0.0;
     }
+    double rate[V], srcw[V];
+    if constexpr (SP) adj_spatial<FULL, V>(a.sp, at(a.sp.rate + w.pw, w.ox), w.pw + (int64_t)(w.ox / 8), nv, rate, srcw);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       double k[D * D], xp[C], rb[C], tv[C], S[C];
+      // spatial form: 1/De + rate, the diagonal a + eta rate, the source weight
+      const double idv = SP ? a.s.inv_De + rate[v] : a.s.inv_De;
+      const double adg = SP ? a.s.a_diag + eta * rate[v] : a.s.a_diag;
+      const double zw = SP ? a.s.zeta * srcw[v] : a.s.zeta;
 #pragma unroll
       for (int t = 0; t < D * D; ++t) k[t] = kt[t][v];
 #pragma unroll
@@ -282,25 +310,32 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
       sc[4] += eta * dot<C>(tv, xp);                // d tau / d q (X+ part; the G part follows the modes)
       {
         double M[C][C];
-        build_M<D>(k, a.s.a_diag, eta, M);
+        build_M<D>(k, adg, eta, M);
         solve_transposed<C>(M, rb);                 // Rbar = M^{-T} Xbar
       }
       double Kx[C];
       apply_K<D>(k, xp, Kx);
-      sc[0] += -dot<C>(rb, xp);                     // a
+      const double ra = -dot<C>(rb, xp);
+      sc[0] += ra;                                  // a
       sc[1] += dot<C>(rb, Kx);                      // eta (matrix)
-      sc[5] += dot<C>(rb, S);                       // zeta
+      if constexpr (SP) {
+        sc[5] += srcw[v] * dot<C>(rb, S);           // zeta (the source point only)
+        sc[6] += rate[v] * ra;                      // eta through a + eta rate
+        sc[7] += rate[v] * eta * ra;                // rate through a + eta rate
+      } else {
+        sc[5] += dot<C>(rb, S);                     // zeta
+      }
       double kb_[D * D];
 #pragma unroll
       for (int t = 0; t < D * D; ++t) kb_[t] = 0.0;
       kgrad_VZ<D>(kb_, eta, rb, xp);                // M = a I - eta K(kappa)
-      kgrad_V<D>(kb_, a.s.zeta, rb);                // R = ... + zeta S
+      kgrad_V<D>(kb_, zw, rb);                      // R = ... + zeta S
       // A(G) = K G - G/De with AGbar = -Rbar:  Gbar = K^T AGbar - AGbar/De - q taubar
       double u[C];
       apply_KT<D>(k, rb, u);
 #pragma unroll
       for (int t = 0; t < C; ++t) {
-        Gb[t][v] = -u[t] + a.s.inv_De * rb[t] - q * tv[t];
+        Gb[t][v] = -u[t] + idv * rb[t] - q * tv[t];
         Pb[t][v] = rb[t] + a.s.s_ec * Gb[t][v];     // P enters R directly and through G = G^ + s P
       }
 #pragma unroll
@@ -395,6 +430,8 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
 #pragma unroll
         for (int v = 0; v < V; ++v) tb[s][v] = 0.0;
     }
+    double rate[V], srcw[V];
+    if constexpr (SP) adj_spatial<FULL, V>(a.sp, at(a.sp.rate + w.pw, w.ox), w.pw + (int64_t)(w.ox / 8), nv, rate, srcw);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       double G[C], rb[C], tv[C], kb_[D * D];
@@ -406,7 +443,9 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
       }
 #pragma unroll
       for (int t = 0; t < D * D; ++t) kb_[t] = lds(v, C + t);
-      sc[3] += dot<C>(rb, G);                       // 1/De (AGbar = -Rbar)
+      const double rg = dot<C>(rb, G);
+      sc[3] += rg;                                  // 1/De (AGbar = -Rbar)
+      if constexpr (SP) sc[7] += rate[v] * rg;      // rate through 1/De + rate
       sc[4] += -dot<C>(tv, G);                      // q (G part)
       kgrad_VZ<D>(kb_, -1.0, rb, G);                // A(G) = K(kappa) G - G/De
 #pragma unroll
@@ -435,7 +474,7 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
 // FULL: whole waves of V-point groups (ngroups a multiple of 64).  !FULL (V = 1): the
 // points after the last whole wave; lanes past the end run an empty group, since the wave
 // reductions need all 64 lanes.
-template <int D, typename MT, int V, bool FULL>
+template <int D, typename MT, int V, bool FULL, bool SP>
 __global__ __launch_bounds__(kBlock) void adj_kernel(const AdjArgs<MT> a) {
   constexpr int C = Sym<D>::C;
   extern __shared__ double smem[];    // [kBlock/64][3][m] mode sums, then the lane slots
@@ -453,7 +492,7 @@ __global__ __launch_bounds__(kBlock) void adj_kernel(const AdjArgs<MT> a) {
        wv += wstride) {
     const WaveAddr w = wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m);
     const int nv = (FULL || wv * 64 + lane < a.ngroups) ? V : 0;
-    adj_group<D, MT, V, FULL>(a, w, nv, smode, slot, sc);
+    adj_group<D, MT, V, FULL, SP>(a, w, nv, smode, slot, sc);
   }
   __syncthreads();
   write_block_partial(a.part + (size_t)a.part0 * (3 * a.m + kNumAdjScalars), a.m, smode, sc);
@@ -763,9 +802,10 @@ struct StartAdjArgs {
   int64_t npts, stride, tile;
   int m;
   StartScalars s;
+  AdjSpatial sp;
 };
 
-template <int D, typename MT, int V, bool FULL>
+template <int D, typename MT, int V, bool FULL, bool SP>
 __device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64_t p0, int nv, double* smode,
                                                 double (&sc)[kNumAdjScalars]) {
   constexpr int C = Sym<D>::C;
@@ -777,26 +817,32 @@ __device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64
   for (int s = 0; s < C; ++s) load_v<FULL, double, V>(a.X0 + s * st + p0, nv, X0[s]);
 #pragma unroll
   for (int q = 0; q < D * D; ++q) load_v<FULL, double, V>(a.ka + q * st + p0, nv, kt[q]);
+  // spatial form: 1/De + rate per point and the source weight of the mass-mode terms
+  double rate[V], srcw[V];
+  if constexpr (SP) adj_spatial<FULL, V>(a.sp, a.sp.rate + p0, p0, nv, rate, srcw);
   // forward recomputation of the two stages
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     double k[D * D], S[C], r[C], M[C][C], AX[C], x1[C];
+    const double idv = SP ? a.s.inv_De + rate[v] : a.s.inv_De;
+    const double s1 = SP ? a.s.src1 * srcw[v] : a.s.src1;
+    const double s2 = SP ? a.s.sigma2 * srcw[v] : a.s.sigma2;
 #pragma unroll
     for (int t = 0; t < D * D; ++t) k[t] = kt[t][v];
 #pragma unroll
     for (int s = 0; s < C; ++s) {
       const int i = Sym<D>::i(s), j = Sym<D>::j(s);
       S[s] = k[i * D + j] + k[j * D + i];
-      r[s] = X0[s][v] + a.s.src1 * S[s];
+      r[s] = X0[s][v] + s1 * S[s];
     }
-    build_M<D>(k, 1.0 + a.s.hgt * a.s.inv_De, a.s.hgt, M);
+    build_M<D>(k, 1.0 + a.s.hgt * idv, a.s.hgt, M);
     solve_pivot<C>(M, r);
 #pragma unroll
     for (int s = 0; s < C; ++s) { x1[s] = r[s]; X1[s][v] = r[s]; }
     apply_K<D>(k, x1, AX);
 #pragma unroll
-    for (int s = 0; s < C; ++s) r[s] = X0[s][v] + a.s.sigma1 * (AX[s] - a.s.inv_De * x1[s]) + a.s.sigma2 * S[s];
-    build_M<D>(k, 1.0 + a.s.hgt * a.s.inv_De, a.s.hgt, M);
+    for (int s = 0; s < C; ++s) r[s] = X0[s][v] + a.s.sigma1 * (AX[s] - idv * x1[s]) + s2 * S[s];
+    build_M<D>(k, 1.0 + a.s.hgt * idv, a.s.hgt, M);
     solve_pivot<C>(M, r);
 #pragma unroll
     for (int s = 0; s < C; ++s) X2[s][v] = r[s];
@@ -880,7 +926,11 @@ __device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64
     double M[C][C], rb[C], Kx[C], kb_[D * D];
 #pragma unroll
     for (int t = 0; t < D * D; ++t) kb_[t] = 0.0;
-    const double diag1 = 1.0 + a.s.hgt * a.s.inv_De;
+    const double idv = SP ? a.s.inv_De + rate[v] : a.s.inv_De;
+    const double s1 = SP ? a.s.src1 * srcw[v] : a.s.src1;
+    const double s2 = SP ? a.s.sigma2 * srcw[v] : a.s.sigma2;
+    double didv = 0.0;                              // dL/d(1/De + rate) of this point
+    const double diag1 = 1.0 + a.s.hgt * idv;
     // stage 2: M X^(2) = X^0 + sigma1 A(X^(1)) + sigma2 S
     build_M<D>(k, diag1, a.s.hgt, M);
 #pragma unroll
@@ -888,16 +938,17 @@ __device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64
     solve_transposed<C>(M, rb);
     apply_K<D>(k, x2, Kx);
     const double rx2 = dot<C>(rb, x2);
-    sc[1] += -rx2 * a.s.inv_De + dot<C>(rb, Kx);   // hgt (matrix)
+    sc[1] += -rx2 * idv + dot<C>(rb, Kx);          // hgt (matrix)
     sc[0] += -rx2 * a.s.hgt;                        // 1/De (matrix)
+    didv += -rx2 * a.s.hgt;
     kgrad_VZ<D>(kb_, a.s.hgt, rb, x2);
     double AX[C];
     apply_K<D>(k, x1, AX);
 #pragma unroll
-    for (int s = 0; s < C; ++s) AX[s] -= a.s.inv_De * x1[s];
+    for (int s = 0; s < C; ++s) AX[s] -= idv * x1[s];
     sc[3] += dot<C>(rb, AX);                        // sigma1
-    sc[4] += dot<C>(rb, S);                         // sigma2
-    kgrad_V<D>(kb_, a.s.sigma2, rb);
+    sc[4] += (SP ? srcw[v] : 1.0) * dot<C>(rb, S);  // sigma2
+    kgrad_V<D>(kb_, s2, rb);
     double x0b[C];
 #pragma unroll
     for (int s = 0; s < C; ++s) x0b[s] = X0b[s][v] + rb[s];
@@ -911,9 +962,10 @@ __device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64
       double acc = 0.0;
 #pragma unroll
       for (int s = 0; s < C; ++s) acc += Km[s][t] * axb[s];
-      x1b[t] += acc - a.s.inv_De * axb[t];
+      x1b[t] += acc - idv * axb[t];
     }
     sc[0] += -dot<C>(axb, x1);                      // 1/De
+    didv += -dot<C>(axb, x1);
     kgrad_VZ<D>(kb_, 1.0, axb, x1);
     // stage 1: M X^(1) = X^0 + src1 S
     build_M<D>(k, diag1, a.s.hgt, M);
@@ -922,11 +974,13 @@ __device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64
     solve_transposed<C>(M, rb);
     apply_K<D>(k, x1, Kx);
     const double rx1 = dot<C>(rb, x1);
-    sc[1] += -rx1 * a.s.inv_De + dot<C>(rb, Kx);
+    sc[1] += -rx1 * idv + dot<C>(rb, Kx);
     sc[0] += -rx1 * a.s.hgt;
+    didv += -rx1 * a.s.hgt;
+    if constexpr (SP) sc[8] += rate[v] * didv;     // rate through 1/De + rate
     kgrad_VZ<D>(kb_, a.s.hgt, rb, x1);
-    sc[2] += dot<C>(rb, S);                         // src1
-    kgrad_V<D>(kb_, a.s.src1, rb);
+    sc[2] += (SP ? srcw[v] : 1.0) * dot<C>(rb, S);  // src1
+    kgrad_V<D>(kb_, s1, rb);
 #pragma unroll
     for (int s = 0; s < C; ++s) X0b[s][v] = Xb0in[s][v] + x0b[s] + rb[s];
 #pragma unroll
@@ -946,7 +1000,7 @@ __device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64
   }
 }
 
-template <int D, typename MT, int V>
+template <int D, typename MT, int V, bool SP>
 __global__ __launch_bounds__(kBlock) void start_adj_kernel(const StartAdjArgs<MT> a) {
   extern __shared__ double smode[];
   for (int j = threadIdx.x; j < (kBlock / 64) * 3 * a.m; j += kBlock) smode[j] = 0.0;
@@ -961,8 +1015,8 @@ __global__ __launch_bounds__(kBlock) void start_adj_kernel(const StartAdjArgs<MT
     const int64_t p0 = mine * V;
     int nv = (int)((a.npts - p0) < V ? (a.npts - p0) : V);
     if (mine >= ngroups) nv = 0;
-    if (nv == V) start_adj_group<D, MT, V, true>(a, p0, nv, smode, sc);
-    else start_adj_group<D, MT, V, false>(a, nv > 0 ? p0 : 0, nv, smode, sc);
+    if (nv == V) start_adj_group<D, MT, V, true, SP>(a, p0, nv, smode, sc);
+    else start_adj_group<D, MT, V, false, SP>(a, nv > 0 ? p0 : 0, nv, smode, sc);
   }
   __syncthreads();
   write_block_partial(a.part, a.m, smode, sc);
@@ -1004,8 +1058,8 @@ size_t adj_shared_bytes(const tfs_plan_s* p, int V) {
 
 // Whole waves of V-point groups with the V-wide kernel, the remaining points (fewer than
 // 64 V) with the masked V = 1 kernel; one finisher folds the block partials of both.
-template <int D, typename MT, int V>
-hipError_t adj_go(const tfs_plan_s* p, AdjArgs<MT> a, int64_t zeta_dest, double* pbar) {
+template <int D, typename MT, int V, bool SP>
+hipError_t adj_go_(const tfs_plan_s* p, AdjArgs<MT> a, int64_t zeta_dest, double* pbar) {
   const int64_t nwaves = p->npoints / (64 * V);
   const int64_t p_tail = nwaves * 64 * V, rest = p->npoints - p_tail;
   int nb = 0, nt = 0;
@@ -1016,19 +1070,19 @@ hipError_t adj_go(const tfs_plan_s* p, AdjArgs<MT> a, int64_t zeta_dest, double*
     nb = grid_adj(p, a.ngroups);
     const size_t shm = adj_shared_bytes(p, V);
     if (shm > 65536) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&adj_kernel<D, MT, V, true>),
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&adj_kernel<D, MT, V, true, SP>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((adj_kernel<D, MT, V, true>), dim3(nb), dim3(kBlock), shm, p->stream, a);
+    hipLaunchKernelGGL((adj_kernel<D, MT, V, true, SP>), dim3(nb), dim3(kBlock), shm, p->stream, a);
   }
   if (rest > 0) {
     a.p_begin = p_tail;
     a.ngroups = rest;
     a.part0 = nb;
     nt = grid_adj(p, rest);
-    hipLaunchKernelGGL((adj_kernel<D, MT, 1, false>), dim3(nt), dim3(kBlock), adj_shared_bytes(p, 1), p->stream,
-                       a);
+    hipLaunchKernelGGL((adj_kernel<D, MT, 1, false, SP>), dim3(nt), dim3(kBlock), adj_shared_bytes(p, 1),
+                       p->stream, a);
   }
   const int np = 3 * p->m + kNumAdjScalars;
   hipLaunchKernelGGL(adj_finish_kernel, dim3(np), dim3(kBlock), 0, p->stream, a.part, nb + nt, np,
@@ -1037,11 +1091,20 @@ hipError_t adj_go(const tfs_plan_s* p, AdjArgs<MT> a, int64_t zeta_dest, double*
 }
 
 template <int D, typename MT, int V>
+hipError_t adj_go(const tfs_plan_s* p, const AdjArgs<MT>& a, int64_t zeta_dest, double* pbar) {
+  if (a.sp.rate || a.sp.src >= 0) return adj_go_<D, MT, V, true>(p, a, zeta_dest, pbar);
+  return adj_go_<D, MT, V, false>(p, a, zeta_dest, pbar);
+}
+
+template <int D, typename MT, int V>
 hipError_t start_adj_go(const tfs_plan_s* p, const StartAdjArgs<MT>& a, double* pbar) {
   const int64_t ngroups = (a.npts + V - 1) / V;
   const int grid = grid_adj(p, ngroups);
   const size_t shm = sizeof(double) * (kBlock / 64) * 3 * p->m;
-  hipLaunchKernelGGL((start_adj_kernel<D, MT, V>), dim3(grid), dim3(kBlock), shm, p->stream, a);
+  if (a.sp.rate || a.sp.src >= 0)
+    hipLaunchKernelGGL((start_adj_kernel<D, MT, V, true>), dim3(grid), dim3(kBlock), shm, p->stream, a);
+  else
+    hipLaunchKernelGGL((start_adj_kernel<D, MT, V, false>), dim3(grid), dim3(kBlock), shm, p->stream, a);
   const int np = 3 * p->m + kNumAdjScalars;
   hipLaunchKernelGGL(adj_finish_kernel, dim3(np), dim3(kBlock), 0, p->stream, a.part, grid, np,
                      p->d_dest_start, (int64_t)-1, pbar);
@@ -1183,6 +1246,8 @@ hipError_t adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, doub
     a.s.gamma = p->gamma;
     a.s.theta = p->theta;
     a.s.hr = p->hr;
+    a.sp.rate = p->sp_rate;
+    a.sp.src = p->sp_source;
     return start_adj_go<D, MT, 1>(p, a, pbar);
   }
   AdjArgs<MT> a;
@@ -1212,6 +1277,8 @@ hipError_t adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, doub
   a.s.inv_De = 1.0 / p->De;
   a.s.zeta = p->zeta[n + 1];
   a.s.tau_scale = p->tau_scale;
+  a.sp.rate = p->sp_rate;
+  a.sp.src = p->sp_source;
   // the zeta gradient of this step goes to pbar[zeta offset + n + 1]
   const int64_t zd = (int64_t)kPbarScalars + 6 * p->m + n + 1;
   if (adj_vec<MT>(p, L) == 2) return adj_go<D, MT, 2>(p, a, zd, pbar);

@@ -427,6 +427,8 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   dest_b[3 * m + 3] = sb + tfs::kPbInvDe;
   dest_b[3 * m + 4] = sb + tfs::kPbQ;
   dest_b[3 * m + 5] = -2;  // zeta of this step
+  dest_b[3 * m + 6] = sb + tfs::kPbEtaRate;
+  dest_b[3 * m + 7] = sb + tfs::kPbRate;
   dest_s[3 * m + 0] = sb + tfs::kPbInvDe;
   dest_s[3 * m + 1] = sb + tfs::kPbHgt;
   dest_s[3 * m + 2] = sb + tfs::kPbSrc1;
@@ -435,6 +437,7 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   dest_s[3 * m + 5] = sb + tfs::kPbGamma;
   dest_s[3 * m + 6] = sb + tfs::kPbTheta;
   dest_s[3 * m + 7] = sb + tfs::kPbHr;
+  dest_s[3 * m + 8] = sb + tfs::kPbRate;
   // exponential-mode scheme: rows [0, m) dL/dw_k, [m, 2m) dL/dlambda_k, [2m, 3m) unused
   std::vector<int> dest_e(np, -1);
   for (int j = 0; j < 2 * m; ++j) dest_e[j] = j;
@@ -762,6 +765,12 @@ int64_t tfs_pbar_size(tfs_plan p) {
   return p ? 6 * (int64_t)p->m + tfs::kPbarScalars + p->max_steps + 1 : -1;
 }
 
+tfs_status tfs_pbar_rate_gradient(tfs_plan p, const double* pbar_host, double* out) {
+  if (!p || !pbar_host || !out) return fail(TFS_EINVAL, "null plan, pbar or out");
+  *out = pbar_host[6 * (int64_t)p->m + tfs::kPbRate];
+  return TFS_OK;
+}
+
 tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, const double* X_n,
                             const double* X_nm1, const double* X_np1, const void* Y_n, const void* Y_nm1,
                             double* Xbar, void* Hbar, const double* taubar, double* kappabar_a,
@@ -770,7 +779,8 @@ tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const 
   if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
                                               (long long)n, (long long)p->max_steps);
   if (!pbar) return fail(TFS_EINVAL, "null pbar");
-  if (spatial(p)) return fail(TFS_EUNSUPPORTED, "no adjoint of the spatial form");
+  if (spatial(p) && p->scheme == TFS_SCHEME_EXP)
+    return fail(TFS_EUNSUPPORTED, "no adjoint of the exponential scheme's spatial form");
   if (p->npoints > 0) {
     if (!kappa_a || !X_n || !Xbar || !Hbar) return fail(TFS_EINVAL, "null kappa_a, X_n, Xbar or Hbar");
     if (p->scheme == TFS_SCHEME_EXP) {
@@ -812,7 +822,7 @@ tfs_status tfs_pbar_to_params(tfs_plan p, const double* pb, double* dw, double* 
     cb[k] = pb[3 * m + k];                // start-up Y^0 = -c X^0
   }
   // scalar chain: a = b0 + eta/De, q = gamma/dt, gamma = eta_p/De
-  double etab = sc[tfs::kPbEta] + sc[tfs::kPbA] * iD;
+  double etab = sc[tfs::kPbEta] + sc[tfs::kPbA] * iD + sc[tfs::kPbEtaRate];
   double iDb = sc[tfs::kPbInvDe] + sc[tfs::kPbA] * p->eta;
   const double gammab = sc[tfs::kPbGamma] + sc[tfs::kPbQ] / h;
   const double eta_pb = gammab * iD;

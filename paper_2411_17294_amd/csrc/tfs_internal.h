@@ -57,12 +57,14 @@ constexpr int kBlock = 256;
 // diagnostic scratch).
 constexpr int kMaxBlocksPerCU = 64;
 // Scalar sums per block of one adjoint launch, and the scalar block of pbar.
-constexpr int kNumAdjScalars = 8;
+constexpr int kNumAdjScalars = 9;
 constexpr int kPbarScalars = 16;
 // Scalar positions in pbar (after the 6 m per-mode entries).
 enum PbarScalar : int {
   kPbA = 0, kPbEta = 1, kPbS = 2, kPbInvDe = 3, kPbQ = 4, kPbHgt = 5, kPbSrc1 = 6, kPbSigma1 = 7,
-  kPbSigma2 = 8, kPbGamma = 9, kPbTheta = 10, kPbHr = 11
+  kPbSigma2 = 8, kPbGamma = 9, kPbTheta = 10, kPbHr = 11,
+  // spatial form: sum_p rate_p dL/da_p (adds to dL/deta) and sum_p rate_p dL/drate_p
+  kPbEtaRate = 12, kPbRate = 13
 };
 
 // Per-step scalars of the BDF2 update, all FP64.

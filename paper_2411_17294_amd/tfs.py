@@ -22,7 +22,8 @@ TFS_SCHEME_BDF2, TFS_SCHEME_EXP = 0, 1
 TFS_FLAG_CHECK_SYNC = 1
 
 EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
-           "tfs_step_levels", "tfs_step_adjoint", "tfs_plan_set_field", "tfs_run_fused", "tfs_pbar_size", "tfs_pbar_to_params", "tfs_modes_to_plain",
+           "tfs_step_levels", "tfs_step_adjoint", "tfs_plan_set_field", "tfs_run_fused", "tfs_pbar_size", "tfs_pbar_to_params", "tfs_pbar_rate_gradient",
+           "tfs_modes_to_plain",
            "tfs_plan_tables", "tfs_plan_stride", "tfs_plan_tile", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
            "tfs_status_string", "tfs_last_error")
 
@@ -78,6 +79,7 @@ def lib():
     L.tfs_pbar_size.argtypes = [vp]
     L.tfs_pbar_size.restype = i64
     L.tfs_pbar_to_params.argtypes = [vp, dp, dp, dp, dp, dp]
+    L.tfs_pbar_rate_gradient.argtypes = [vp, dp, dp]
     L.tfs_modes_to_plain.argtypes = [vp, i32, vp, vp, vp]
     L.tfs_plan_tables.argtypes = [vp, dp, dp, dp]
     L.tfs_plan_stride.argtypes = [vp]
@@ -92,7 +94,7 @@ def lib():
     L.tfs_last_error.restype = C.c_char_p
     for name in ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
                  "tfs_step_levels", "tfs_plan_set_field", "tfs_run_fused",
-                 "tfs_step_adjoint", "tfs_pbar_to_params", "tfs_modes_to_plain",
+                 "tfs_step_adjoint", "tfs_pbar_to_params", "tfs_pbar_rate_gradient", "tfs_modes_to_plain",
                  "tfs_plan_tables", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -302,6 +304,15 @@ class Plan:
         dDe, dep = C.c_double(0.0), C.c_double(0.0)
         check(lib().tfs_pbar_to_params(self._h, _dptr(pb), _dptr(dw), _dptr(dl), C.pointer(dDe), C.pointer(dep)))
         return dw, dl, dDe.value, dep.value
+
+    def pbar_rate_gradient(self, pbar_host):
+        """sum_p rate_p dL/drate_p of the spatial form (eps dL/deps for rate = eps |xi|^2)."""
+        pb = np.ascontiguousarray(pbar_host, dtype=np.float64)
+        if pb.size < self.pbar_size:
+            raise ValueError("pbar too short")
+        out = C.c_double(0.0)
+        check(lib().tfs_pbar_rate_gradient(self._h, _dptr(pb), C.pointer(out)))
+        return out.value
 
     def modes_to_plain(self, slot, X, Y, out):
         import torch

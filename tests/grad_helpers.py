@@ -77,10 +77,73 @@ def oracle_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, dw_da=None,
     return out
 
 
+def oracle_spatial_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, rate, source, per_mode=False,
+                             extrap=True):
+    """Complex-step gradients of the spatial form in the Fourier layout, from the pointwise
+    oracle: a point of rate r follows the pointwise scheme with 1/De -> 1/De + r at the same
+    eta_p/De, without the mass-mode source (a run from X0 minus a run from 0) unless it is the
+    source point or no source point is set (source < 0).  Points of equal rate and source
+    flag run together.  Returns the keys of oracle_gradients (no alpha) plus "rate" =
+    sum_p rate_p dL/drate_p."""
+    wts = pack_weights(d)[:, None]
+    P = X0.shape[1]
+    m = len(w)
+    groups = {}
+    for p in range(P):
+        groups.setdefault((float(rate[p]), source < 0 or p == source), []).append(p)
+    out = {"kappa": np.zeros((d * d, P)), "X0": np.zeros_like(X0), "De": 0.0, "eta_p": 0.0, "rate": 0.0,
+           "loss": 0.0}
+    if per_mode:
+        out["w"], out["lam"] = np.zeros(m), np.zeros(m)
+    for (r, src), idx in groups.items():
+        idx = np.asarray(idx)
+        kap, x0, tg = kappa[..., idx], X0[:, idx], target[:, idx]
+
+        def tau(dk=None, dX0=None, dwv=None, dlv=None, dDe=0.0, dep=0.0, drate=0.0):
+            Dc = De + 1j * H_CS * dDe
+            ec = eta_p + 1j * H_CS * dep
+            rc = r + 1j * H_CS * drate
+            Dx = 1.0 / (1.0 / Dc + rc)
+            ex = ec * Dx / Dc
+            kc = kap.astype(complex) + (1j * H_CS * dk if dk is not None else 0)
+            xc = x0.astype(complex) + (1j * H_CS * dX0 if dX0 is not None else 0)
+            wc = np.asarray(w, complex) + (1j * H_CS * dwv if dwv is not None else 0)
+            lc = np.asarray(lam, complex) + (1j * H_CS * dlv if dlv is not None else 0)
+            t = O.run_complex(d, wc, lc, Dx, ex, dt, N, kc, xc, extrap=extrap)["tau"]
+            if not src:
+                t = t - O.run_complex(d, wc, lc, Dx, ex, dt, N, kc, np.zeros_like(xc), extrap=extrap)["tau"]
+            return t
+
+        base = tau().real
+        resid = base - tg
+        out["loss"] += loss(base, tg, d)
+        dirv = lambda **kw: np.sum(wts * resid * tau(**kw).imag / H_CS, axis=0)
+        for q in range(d * d):
+            dk = np.zeros_like(kap)
+            dk[..., q, :] = 1.0
+            out["kappa"][q, idx] = dirv(dk=dk)
+        for s in range(x0.shape[0]):
+            dX = np.zeros_like(x0)
+            dX[s] = 1.0
+            out["X0"][s, idx] = dirv(dX0=dX)
+        out["De"] += float(np.sum(dirv(dDe=1.0)))
+        out["eta_p"] += float(np.sum(dirv(dep=1.0)))
+        out["rate"] += float(np.sum(dirv(drate=r)))
+        if per_mode:
+            for k in range(m):
+                e = np.zeros(m)
+                e[k] = 1.0
+                out["w"][k] += float(np.sum(dirv(dwv=e)))
+                out["lam"][k] += float(np.sum(dirv(dlv=e)))
+    return out
+
+
 def gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precision="fp64", tile=None,
-                  dw_da=None, dl_da=None, extrap=True, tune=None, scheme="bdf2"):
+                  dw_da=None, dl_da=None, extrap=True, tune=None, scheme="bdf2", spatial=None):
     """Forward + adjoint on the GPU; kappa steady [d*d][P] or levels [nlev][d*d][P].
-    tune: {key: value} passed to tfs_plan_tune (e.g. points per lane)."""
+    tune: {key: value} passed to tfs_plan_tune (e.g. points per lane).
+    spatial: (rate [P], source point) of the spatial form (tfs_plan_set_spatial); the result
+    then carries "rate" = sum_p rate_p dL/drate_p."""
     P = X0.shape[1]
     c = d * (d + 1) // 2
     plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, max(N, 1), precision=precision, tile=tile, scheme=scheme)
@@ -89,6 +152,10 @@ def gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precisi
         plan.tune(key, value)
     st, m = plan.stride, plan.m
     dev = "cuda"
+    if spatial is not None:
+        rate_t = torch.zeros(st, dtype=torch.float64, device=dev)
+        rate_t[:P] = torch.from_numpy(np.ascontiguousarray(spatial[0], dtype=np.float64)).to(dev)
+        plan.set_spatial(rate_t, int(spatial[1]))
     mt = plan.mode_dtype
     Xs = [torch.zeros((c, st), dtype=torch.float64, device=dev) for _ in range(N + 1)]
     Ys = [torch.zeros((m * c * st,), dtype=mt, device=dev) for _ in range(N + 1)]
@@ -127,9 +194,12 @@ def gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precisi
                           Ys[n - 1] if n >= 1 else None, Xbar, Hbar, pbar,
                           taubar=taubar if n == N - 1 else None, kappabar_a=kbar, kappabar_b=kbar)
     torch.cuda.synchronize()
-    gw, gl, gDe, gep = plan.pbar_to_params(pbar.cpu().numpy())
+    pb = pbar.cpu().numpy()
+    gw, gl, gDe, gep = plan.pbar_to_params(pb)
     out = {"loss": loss(tau_h, target, d), "tau": tau_h, "kappa": kbar[:, :P].cpu().numpy(),
            "X0": Xbar[0, :, :P].cpu().numpy(), "De": gDe, "eta_p": gep, "w": gw, "lam": gl}
+    if spatial is not None:
+        out["rate"] = plan.pbar_rate_gradient(pb)
     if dw_da is not None:
         out["alpha"] = float(np.dot(gw, dw_da) + np.dot(gl, dl_da))
     return out

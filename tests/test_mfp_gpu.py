@@ -204,8 +204,8 @@ def test_paper_convergence_experiment_on_gpu():
     assert all(1.3 < o < 1.7 for o in orders), (norms, orders)
 
 
-def test_set_spatial_validation_and_adjoint_refused():
-    plan = tfs.Plan(2, 100, [1.0], [0.0], 0.5, 1.0, 0.1, 1e-3, 4)
+def test_set_spatial_validation_and_exp_adjoint_refused():
+    plan = tfs.Plan(2, 100, [1.0], [0.0], 0.5, 1.0, 0.1, 1e-3, 4, scheme="exp")
     with pytest.raises(tfs.TfsError):
         plan.set_spatial(None, 100)
     with pytest.raises(tfs.TfsError):
@@ -214,7 +214,112 @@ def test_set_spatial_validation_and_adjoint_refused():
     Xb = torch.zeros((2, 3, plan.stride), dtype=torch.float64, device="cuda")
     with pytest.raises(tfs.TfsError) as e:
         plan.step_adjoint(0, Xb[0, :1].expand(4, plan.stride).contiguous(), None, Xb[0], None, Xb[1], None, None,
-                          Xb, torch.zeros(2 * plan.m * 3 * plan.stride, dtype=torch.float64, device="cuda"),
+                          Xb, torch.zeros(plan.mode_levels * plan.m * 3 * plan.stride, dtype=torch.float64,
+                                          device="cuda"),
                           torch.zeros(plan.pbar_size, dtype=torch.float64, device="cuda"))
     assert "spatial" in str(e.value) or "UNSUPPORTED" in str(e.value).upper()
     plan.set_spatial(None, -1)      # back to the pointwise form
+
+
+# ---- adjoint of the spatial form (BDF2 after the SDIRK2 start) ---------------------------
+
+ADJ_BAR = {"fp64": 1e-9, "fp32_modes": 1e-5}
+
+
+def spatial_case(d, P, m, seed, source, dt=2e-3, T=0.05):
+    """Per-point kappa and X0, rates from a few eps |xi|^2-like values (zero included), a
+    random target; source: "one" (the point P // 2 carries the mass-mode source) or "all"."""
+    from paper_2411_17294_amd import inputs as I
+    kappa, X0 = I.random_symmetric_case(d, P, seed, kscale=0.7, xscale=0.2)
+    w, lam, _ = osoe.soe_fit(0.45, m, dt, T)
+    rng = np.random.default_rng(seed + 1)
+    rate = rng.choice([0.0, 0.79, 7.9, 49.3], size=P)
+    rate[0] = 7.9                   # a single point still carries a rate
+    target = rng.standard_normal((d * (d + 1) // 2, P)) * 1e-2
+    return kappa, X0, w, lam, rate, (P // 2 if source == "one" else -1), target
+
+
+def compare_spatial(g, o, prec, label):
+    errs = {"kappa": relerr(g["kappa"], o["kappa"]), "X0": relerr(g["X0"], o["X0"])}
+    for k in ("De", "eta_p", "rate"):
+        errs[k] = abs(g[k] - o[k]) / abs(o[k]) if o[k] != 0.0 else abs(g[k])
+    for k in ("w", "lam"):
+        if k in o:
+            errs[k] = relerr(g[k], o[k])
+    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= ADJ_BAR[prec]}
+    assert not bad, f"{label}: {bad}"
+
+
+@pytest.mark.parametrize("source", ["one", "all"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("P,N", [(1, 1), (37, 12)])
+def test_spatial_adjoint_matches_pointwise_complex_step(d, prec, P, N, source):
+    """Every gradient of the spatial form's adjoint (kappa and X0 fields, De, eta_p, the rate
+    scale, per-mode w and lambda) against complex-step derivatives of the pointwise oracle,
+    coefficient class by coefficient class."""
+    from tests.grad_helpers import gpu_gradients, oracle_spatial_gradients
+    m = 5
+    kappa, X0, w, lam, rate, src, target = spatial_case(d, P, m, 700 + 10 * d + P, source)
+    print(f"spatial adjoint d={d} {prec} P={P} N={N} source={src}", flush=True)
+    o = oracle_spatial_gradients(d, w, lam, 1.1, 0.1, 2e-3, N, kappa, X0, target, rate, src, per_mode=True)
+    g = gpu_gradients(d, w, lam, 0.45, 1.1, 0.1, 2e-3, N, kappa, X0, target, precision=prec,
+                      spatial=(rate, src))
+    assert abs(g["loss"] - o["loss"]) <= ADJ_BAR[prec] * o["loss"]
+    compare_spatial(g, o, prec, f"sp adj d={d} {prec} P={P} N={N} src={src}")
+
+
+@pytest.mark.parametrize("adj_vec", [1, 2])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_spatial_adjoint_whole_waves_and_tail(d, prec, adj_vec):
+    """389 points: whole waves of V = 1 or 2 points per lane and a masked tail, the source
+    point inside the tail's wave."""
+    from tests.grad_helpers import gpu_gradients, oracle_spatial_gradients
+    P, N, m = 389, 6, 6
+    kappa, X0, w, lam, rate, _, target = spatial_case(d, P, m, 800 + d, "one")
+    src = 385
+    print(f"spatial adjoint waves d={d} {prec} V={adj_vec}", flush=True)
+    o = oracle_spatial_gradients(d, w, lam, 1.1, 0.1, 2e-3, N, kappa, X0, target, rate, src)
+    g = gpu_gradients(d, w, lam, 0.45, 1.1, 0.1, 2e-3, N, kappa, X0, target, precision=prec,
+                      spatial=(rate, src), tune={"adj_vec": adj_vec})
+    compare_spatial(g, o, prec, f"sp adj waves d={d} {prec} V={adj_vec}")
+
+
+@pytest.mark.parametrize("extrap", [True, False])
+def test_spatial_adjoint_time_varying_kappa(extrap):
+    from tests.grad_helpers import gpu_gradients, oracle_spatial_gradients
+    d, P, N, m, dt = 2, 29, 14, 6, 2e-3
+    _, X0, w, lam, rate, src, target = spatial_case(d, P, m, 91, "one")
+    rng = np.random.default_rng(92)
+    a, b, om = (rng.standard_normal((d * d, P)) * 0.6 for _ in range(3))
+    t = np.arange(N + 1)[:, None, None] * dt
+    kap = np.ascontiguousarray(a[None] + b[None] * np.sin(3.0 * t + om[None]))
+    o = oracle_spatial_gradients(d, w, lam, 0.9, 0.2, dt, N, kap, X0, target, rate, src, extrap=extrap)
+    g = gpu_gradients(d, w, lam, 0.45, 0.9, 0.2, dt, N, kap, X0, target, spatial=(rate, src), extrap=extrap)
+    compare_spatial(g, o, "fp64", f"sp adj tv extrap={extrap}")
+
+
+def test_spatial_adjoint_eps_against_gpu_finite_differences():
+    """A spectral grid (rate = eps |xi|^2, mass-mode source at the zero wave vector): the
+    adjoint's eps dL/deps against central differences of the GPU forward in eps."""
+    from tests.grad_helpers import gpu_gradients
+    d, N, m, dt = 2, 20, 8, 2e-3
+    grid = PeriodicGrid((16, 12), (1.0, 1.5))
+    P = grid.npoints
+    k2 = grid.wavenumber_squared().numpy()
+    rng = np.random.default_rng(19)
+    kd = rng.standard_normal((d, d)) * 0.5
+    kappa = np.repeat(kd.reshape(d * d, 1), P, axis=1)
+    X0 = rng.standard_normal((3, P)) * 0.05
+    target = rng.standard_normal((3, P)) * 1e-3
+    w, lam, _ = osoe.soe_fit(0.5, m, dt, dt * N)
+    eps = 0.02
+    L = lambda e: gpu_gradients(d, w, lam, 0.5, 1.0, 0.1, dt, N, kappa, X0, target,
+                                spatial=(e * k2, grid.source_point))
+    g = L(eps)
+    h = 1e-4 * eps
+    fd = (L(eps + h)["loss"] - L(eps - h)["loss"]) / (2 * h)
+    print("eps dL/deps", g["rate"], "FD", eps * fd, flush=True)
+    assert abs(g["rate"] - eps * fd) <= 1e-6 * abs(eps * fd)
