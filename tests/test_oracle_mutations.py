@@ -109,3 +109,39 @@ def test_planted_mistake_in_spatial_oracle_fails_a_pin(name, tmp_path):
                         os.path.join(ROOT, "tests", "test_oracle_mfp_pins.py"), sel],
                        cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"no pin caught '{name}':\n{r.stdout[-2000:]}{r.stderr[-2000:]}"
+
+
+# Mistakes planted in the coupled-step oracle (oracle/ns.py; pins in test_oracle_ns_pins.py).
+NS_SRC = os.path.join(ROOT, "oracle", "ns.py")
+NS_MUTATIONS = {
+    "gradient_transposed": ("self.ifft(1j * self.xi[j] * uh[i]) for i in range(d) for j in range(d)",
+                            "self.ifft(1j * self.xi[i] * uh[j]) for i in range(d) for j in range(d)",
+                            "derivatives"),
+    "stress_divergence_sign": ("F = -box.fft(adv) + box.div_tensor(box.fft(tau_grid))",
+                               "F = -box.fft(adv) - box.div_tensor(box.fft(tau_grid))", "shear_wave"),
+    "first_order_extrapolation": ("2: ((1.5, -2.0, 0.5), (2.0, -1.0))", "2: ((1.5, -2.0, 0.5), (1.0, 0.0))",
+                                  "shear_wave"),
+    "pressure_dropped": ("ph = np.where(box.xi2 > 0, divXi / safe, 0.0)", "ph = 0.0 * divXi",
+                         "exact_solutions or divergence"),
+    "viscosity_sign": ("return rhs / (b[0] / dt + nu * box.xi2), ph", "return rhs / (b[0] / dt - nu * box.xi2), ph",
+                       "exact_solutions"),
+    "band_not_applied": ("    return F * box.band", "    return F", "exact_product"),
+    "advection_index": ("adv = np.stack([sum(u[j] * kap[i * d + j] for j in range(d)) for i in range(d)])",
+                        "adv = np.stack([sum(u[j] * kap[j * d + i] for j in range(d)) for i in range(d)])",
+                        "exact_product or taylor_green"),
+}
+
+_RUN_NS_MUTANT = _RUN_MUTANT.replace("oracle.mfp", "oracle.ns")
+
+
+@pytest.mark.parametrize("name", sorted(NS_MUTATIONS))
+def test_planted_mistake_in_coupled_oracle_fails_a_pin(name, tmp_path):
+    orig, bad, sel = NS_MUTATIONS[name]
+    src = open(NS_SRC).read()
+    assert src.count(orig) == 1, "mutation anchor drifted from the coupled-step oracle source"
+    mut = tmp_path / "ns_mutant.py"
+    mut.write_text(src.replace(orig, bad))
+    r = subprocess.run([sys.executable, "-c", _RUN_NS_MUTANT, str(mut),
+                        os.path.join(ROOT, "tests", "test_oracle_ns_pins.py"), sel],
+                       cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"no pin caught '{name}':\n{r.stdout[-2000:]}{r.stderr[-2000:]}"
