@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtfs.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("tfs_kernels.hip", "tfs_adjoint.hip", "tfs_fused.hip", "tfs_host.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("tfs_kernels.hip", "tfs_adjoint.hip", "tfs_fused.hip", "tfs_ns.hip", "tfs_host.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -55,7 +55,9 @@ def build(verbose: bool = False, extra=None) -> str:
             print(out)
     if failed:
         raise RuntimeError("hipcc failed:\n" + "\n".join(failed))
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    # the coupled step's transforms: hipFFT (resolved against the copy already loaded by
+    # torch when there is one, since the sonames agree)
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-L/opt/rocm/lib", "-lhipfft", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     out = _filtered(r.stdout + r.stderr)
     if r.returncode != 0:

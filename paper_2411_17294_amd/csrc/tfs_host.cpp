@@ -176,6 +176,11 @@ bool spatial(const tfs_plan_s* p) { return p->sp_rate != nullptr || p->sp_source
 
 }  // namespace
 
+namespace tfs {
+// Error reporting for the other translation units of the library (the coupled step).
+tfs_status set_error(tfs_status s, const char* msg) { return fail(s, "%s", msg); }
+}  // namespace tfs
+
 extern "C" {
 
 const char* tfs_last_error(void) { return g_last_error.c_str(); }

@@ -25,7 +25,8 @@ EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_pl
            "tfs_step_levels", "tfs_step_adjoint", "tfs_plan_set_field", "tfs_run_fused", "tfs_pbar_size", "tfs_pbar_to_params", "tfs_pbar_rate_gradient",
            "tfs_modes_to_plain",
            "tfs_plan_tables", "tfs_plan_stride", "tfs_plan_tile", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
-           "tfs_status_string", "tfs_last_error")
+           "tfs_status_string", "tfs_last_error",
+           "tfs_ns_create", "tfs_ns_destroy", "tfs_ns_spectral_size", "tfs_ns_init", "tfs_ns_step")
 
 
 # Mode-ring tile (points) used when the caller does not choose one; measured best on
@@ -92,10 +93,17 @@ def lib():
     L.tfs_status_string.argtypes = [C.c_int]
     L.tfs_status_string.restype = C.c_char_p
     L.tfs_last_error.restype = C.c_char_p
+    L.tfs_ns_create.argtypes = [C.c_int, C.POINTER(i64), dp, C.c_double, C.c_double, i64, C.POINTER(C.c_void_p)]
+    L.tfs_ns_destroy.argtypes = [vp]
+    L.tfs_ns_spectral_size.argtypes = [vp]
+    L.tfs_ns_spectral_size.restype = i64
+    L.tfs_ns_init.argtypes = [vp, vp, vp, vp, vp]
+    L.tfs_ns_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     for name in ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
                  "tfs_step_levels", "tfs_plan_set_field", "tfs_run_fused",
                  "tfs_step_adjoint", "tfs_pbar_to_params", "tfs_pbar_rate_gradient", "tfs_modes_to_plain",
-                 "tfs_plan_tables", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log"):
+                 "tfs_plan_tables", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
+                 "tfs_ns_create", "tfs_ns_destroy", "tfs_ns_init", "tfs_ns_step"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -14,18 +14,20 @@ from paper_2411_17294_amd import tfs
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    text = open(os.path.join(ROOT, "include", "tfs.h")).read()
+def header_functions(name="tfs.h"):
+    text = open(os.path.join(ROOT, "include", name)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(tfs_\w+)\s*\(", text, flags=re.M)))
 
 
 def test_library_exports_every_declared_function():
-    names = header_functions()
-    assert len(names) >= 10
+    headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    assert headers == ["tfs.h", "tfs_ns.h"]
+    names = sorted(set(n for h in headers for n in header_functions(h)))
+    assert len(names) >= 15
     L = tfs.lib()
     for n in names:
-        assert hasattr(L, n), f"{n} declared in tfs.h but not exported"
+        assert hasattr(L, n), f"{n} declared in include/ but not exported"
     assert set(names) == set(tfs.EXPORTS)
 
 

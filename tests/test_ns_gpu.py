@@ -1,0 +1,183 @@
+"""Coupled step on the GPU (tfs_ns_step: pseudo-spectral projection method for the
+Navier-Stokes equations on a periodic box + the stress update), against the coupled-step
+oracle (oracle/ns.py: numpy full-spectrum transforms, the paper's pressure Poisson and
+velocity Helmholtz solves, the pointwise oracle for the stress) on small grids, and on full
+-size grids against properties that hold at any size: the shear-wave scalar reduction, the
+decay of the Taylor-Green vortex, a zero divergence."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ns as ons
+from oracle import oracle as O
+from oracle import soe as osoe
+from paper_2411_17294_amd import ns, tfs
+from tests.gpu_helpers import relerr
+
+pytestmark = pytest.mark.gpu
+
+BAR = {"fp64": 1e-12, "fp32_modes": 1e-5}
+
+
+def gpu_run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, prec="fp64", scheme="bdf2", alpha=0.6):
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, max(N, 1), precision=prec, scheme=scheme)
+    sol = ns.Solver(plan, shape, extent, nu, dt)
+    u, kappa, uh, fh = sol.alloc()
+    X, Y, tau, _ = plan.alloc()
+    u[:, :P] = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+    X[0, :, :P] = torch.from_numpy(np.ascontiguousarray(X0)).cuda()
+    sol.init(u, uh, kappa)
+    for n in range(N):
+        sol.step(n, u, uh, fh, kappa, X, Y, tau)
+    torch.cuda.synchronize()
+    out = {"u": u[:, :P].cpu().numpy(), "kappa": kappa[:, :P].cpu().numpy(), "tau": tau[:, :P].cpu().numpy(),
+           "X": np.stack([X[N % 2, :, :P].cpu().numpy(), X[(N - 1) % 2, :, :P].cpu().numpy()]) if N else None,
+           "uh": uh[N % 2].cpu().numpy(), "plan": plan, "solver": sol}
+    return out
+
+
+def random_case(d, shape, seed, amp=0.6):
+    """A random grid velocity (with a gradient part and content outside the 2/3 band, which
+    the first level removes) and a random initial X."""
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((d, P)) * amp, rng.standard_normal((c, P)) * 0.05
+
+
+CASES = [(2, (16, 12), (1.0, 1.5)), (2, (9, 14), (2 * math.pi, 1.0)), (3, (8, 6, 10), (1.0, 0.8, 1.3))]
+
+
+@pytest.mark.parametrize("N", [0, 1, 2, 9])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d,shape,extent", CASES)
+def test_coupled_steps_match_oracle(d, shape, extent, prec, N):
+    m, alpha, De, eta_p, nu, dt = 6, 0.6, 0.7, 0.3, 0.05, 1e-2
+    w, lam, _ = osoe.soe_fit(alpha, m, dt, dt * max(N, 2))
+    u0, X0 = random_case(d, shape, 100 + d + N)
+    print(f"coupled d={d} shape={shape} {prec} N={N}", flush=True)
+    g = gpu_run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, prec=prec, alpha=alpha)
+    o = ons.run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0)
+    half = o["uh"][..., :shape[-1] // 2 + 1].reshape(d, -1)
+    errs = {"u": relerr(g["u"], o["u"]), "kappa": relerr(g["kappa"], o["kappa"]),
+            "uh": float(np.max(np.abs(g["uh"] - half)) / np.max(np.abs(half)))}
+    if N:
+        errs["tau"] = relerr(g["tau"], o["tau"])
+        errs["X"] = relerr(g["X"], o["X"])
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert all(v < BAR[prec] for v in errs.values()), errs
+
+
+def test_coupled_exponential_scheme_matches_oracle():
+    d, shape, extent = 2, (12, 10), (1.0, 1.0)
+    w, lam, _ = osoe.soe_fit(0.5, 5, 1e-2, 0.1)
+    u0, X0 = random_case(d, shape, 7)
+    g = gpu_run(d, shape, extent, 0.05, w, lam, 0.8, 0.3, 1e-2, 7, u0, X0, scheme="exp", alpha=0.5)
+    o = ons.run(d, shape, extent, 0.05, w, lam, 0.8, 0.3, 1e-2, 7, u0, X0, startup="exp")
+    errs = {"u": relerr(g["u"], o["u"]), "tau": relerr(g["tau"], o["tau"])}
+    assert all(v < 1e-12 for v in errs.values()), errs
+
+
+def shear_reference(d, k, U0, nu, w, lam, De, eta_p, dt, N):
+    """U^n, T^n of the shear wave from the scalar recurrence and the one-point oracle."""
+    c = d * (d + 1) // 2
+    xy = 2 if d == 2 else 3
+    U, T = [U0], [0.0]
+    for n in range(N):
+        b, a = ((1.0, -1.0), (1.0,)) if n == 0 else ((1.5, -2.0, 0.5), (2.0, -1.0))
+        g = len(a)
+        rhs = -sum(b[j] / dt * U[n + 1 - j] for j in range(1, g + 1)) + sum(
+            a[j - 1] * (-k * T[n + 1 - j]) for j in range(1, g + 1))
+        U.append(rhs / (b[0] / dt + nu * k * k))
+        lev = np.zeros((n + 2, d * d, 1))
+        lev[:, 1, 0] = k * np.array(U)
+        T.append(O.run(d, w, lam, De, eta_p, dt, n + 1, lev, np.zeros((c, 1)), extrap=False)["tau"][xy, 0])
+    return U[-1], T[-1]
+
+
+@pytest.mark.parametrize("d,shape,prec", [(2, (1024, 1024), "fp64"), (3, (64, 128, 64), "fp32_modes")])
+def test_shear_wave_full_size(d, shape, prec):
+    """The benchmark's 1024^2, m = 32 configuration (and a 3-D FP32-mode grid): the shear
+    wave u = (U sin(k y), 0[, 0]) against the scalar recurrence at every grid point."""
+    extent = (1.0,) * d
+    P = int(np.prod(shape))
+    # beta = 0.9 (nu = beta/Re, eta_p = (1-beta)/Re at Re = 18): with the stress extrapolated,
+    # the viscous term must dominate it at the grid scale, or the high wave numbers grow
+    # from rounding
+    m, De, eta_p, nu, dt, N = 32, 0.5, 0.0055, 0.05, 2e-3, 8
+    w, lam, _ = osoe.soe_fit(0.5, m, dt, 1.0)
+    k = 2 * math.pi * 3
+    axes = [np.arange(n) / n for n in shape]
+    y = np.meshgrid(*axes, indexing="ij")[1].reshape(P)
+    u0 = np.zeros((d, P))
+    u0[0] = 0.9 * np.sin(k * y)
+    c = d * (d + 1) // 2
+    g = gpu_run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, np.zeros((c, P)), prec=prec, alpha=0.5)
+    U, T = shear_reference(d, k, 0.9, nu, w, lam, De, eta_p, dt, N)
+    xy = 2 if d == 2 else 3
+    eu = np.max(np.abs(g["u"][0] - U * np.sin(k * y))) / abs(U)
+    et = np.max(np.abs(g["tau"][xy] - T * np.cos(k * y))) / abs(T)
+    print(f"shear wave d={d} {shape}: u {eu:.2e} tau_xy {et:.2e} |u_other| {np.max(np.abs(g['u'][1:])):.1e}", flush=True)
+    bar = BAR[prec]
+    assert eu < bar and et < bar
+    assert np.max(np.abs(g["u"][1:])) < 1e-13
+
+
+def test_taylor_green_second_order_on_gpu():
+    """eta_p = 0: the 2-D Taylor-Green vortex on a 64^2 grid decays like exp(-2 nu t) with
+    errors shrinking like dt^2."""
+    shape, extent, nu, T = (64, 64), (2 * math.pi,) * 2, 0.1, 0.5
+    P = 64 * 64
+    x, y = np.meshgrid(*[np.arange(64) * (2 * math.pi / 64)] * 2, indexing="ij")
+    u0 = np.stack([np.sin(x) * np.cos(y), -np.cos(x) * np.sin(y)]).reshape(2, P)
+    errs = []
+    for N in (8, 16, 32):
+        w, lam, _ = osoe.soe_fit(0.5, 3, T / N, T)
+        g = gpu_run(2, shape, extent, nu, w, lam, 1.0, 0.0, T / N, N, u0, np.zeros((3, P)), alpha=0.5)
+        errs.append(np.max(np.abs(g["u"] - u0 * math.exp(-2 * nu * T))))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    print("Taylor-Green errors", errs, orders, flush=True)
+    assert all(1.85 < o < 2.15 for o in orders), (errs, orders)
+
+
+def test_divergence_free_at_128_cubed():
+    """A random velocity on 128^3 with the stress coupled in (FP32 modes, m = 16): after the
+    first level and four steps, i xi . u-hat vanishes to rounding."""
+    d, shape = 3, (128, 128, 128)
+    P = 128 ** 3
+    extent = (1.0, 1.0, 1.0)
+    w, lam, _ = osoe.soe_fit(0.5, 16, 1e-3, 1.0)
+    u0, X0 = random_case(d, shape, 3, amp=0.3)
+    g = gpu_run(d, shape, extent, 0.05, w, lam, 0.5, 0.0055, 1e-3, 4, u0, X0, prec="fp32_modes", alpha=0.5)
+    uh = torch.from_numpy(g["uh"]).reshape(d, 128, 128, 65)
+    k = [torch.fft.fftfreq(128, 1 / 128.0), torch.fft.fftfreq(128, 1 / 128.0), torch.fft.rfftfreq(128, 1 / 128.0)]
+    K = torch.meshgrid(*k, indexing="ij")
+    div = sum(2 * math.pi * K[j].to(torch.float64) * uh[j] for j in range(3))
+    rel = (div.abs().max() / (uh.abs().max() * 2 * math.pi * 64)).item()
+    print("relative divergence", rel, flush=True)
+    assert rel < 1e-14
+    assert np.max(np.abs(g["tau"])) > 1e-6
+
+
+def test_solver_errors():
+    w, lam, _ = osoe.soe_fit(0.5, 4, 1e-3, 1e-2)
+    plan = tfs.Plan(2, 16 * 16, w, lam, 0.5, 1.0, 0.1, 1e-3, 4)
+    with pytest.raises(tfs.TfsError):
+        ns.Solver(plan, (16, 1), (1.0, 1.0), 0.1, 1e-3)          # an axis of one point
+    with pytest.raises(tfs.TfsError):
+        ns.Solver(plan, (16, 16), (1.0, -1.0), 0.1, 1e-3)        # negative extent
+    sol = ns.Solver(plan, (16, 16), (1.0, 1.0), 0.1, 1e-3)
+    u, kappa, uh, fh = sol.alloc()
+    X, Y, tau, _ = plan.alloc()
+    other = tfs.Plan(3, 16 * 16, w, lam, 0.5, 1.0, 0.1, 1e-3, 4)      # a 3-D stress plan
+    rc = tfs.lib().tfs_ns_init(sol.handle, other.handle, u.data_ptr(), uh.data_ptr(), kappa.data_ptr())
+    assert rc == tfs.TFS_EINVAL
+    sol.init(u, uh, kappa)
+    with pytest.raises(tfs.TfsError):
+        sol.step(4, u, uh, fh, kappa, X, Y, tau)                 # past max_steps
+    sol.step(0, u, uh, fh, kappa, X, Y, tau)
+    torch.cuda.synchronize()
