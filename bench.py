@@ -143,6 +143,8 @@ def measure_forms(stream, steps=20, which="all"):
         out["mfp_spectral_2d"] = _mfp_2d(stream, steps)
     if which in ("all", "fused"):
         out["fused_exp"] = _fused(stream)
+    if which in ("all", "ns"):
+        out["ns_coupled"] = _ns_coupled(stream, steps)
     return out
 
 
@@ -264,6 +266,57 @@ def _mfp_2d(stream, steps):
     return {"workload": name, "grid": [n, n], "coefficients": P, "ms_per_step": ms,
             "point_mode_updates_per_s": P * m / (ms * 1e-3), "bytes_per_launch": nbytes, "achieved_GBs": gbs,
             "frac": gbs / HBM_PEAK_GBS, "traffic": profiled_traffic("bdf2_kernel_" + name)}
+
+
+def synthetic_velocity(d, n, seed, k0=4.0):
+    """A seeded random grid velocity on [0, 2 pi)^d with the isotropic spectrum shape
+    E(k) ~ k^4 exp(-2 (k/k0)^2) of synthetic decaying-turbulence initial data, rms 1 per
+    component ([d][n^d], C order; the solver keeps its solenoidal part)."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    f = torch.randn((d,) + (n,) * d, dtype=torch.float64, device="cuda", generator=g)
+    F = torch.fft.rfftn(f, dim=tuple(range(1, d + 1)))
+    ks = [torch.fft.fftfreq(n, 1.0 / n, dtype=torch.float64, device="cuda")] * (d - 1) + \
+        [torch.fft.rfftfreq(n, 1.0 / n, dtype=torch.float64, device="cuda")]
+    K2 = sum(k * k for k in torch.meshgrid(*ks, indexing="ij"))
+    F = F * (K2 * torch.exp(-K2 / (k0 * k0)))
+    u = torch.fft.irfftn(F, s=(n,) * d, dim=tuple(range(1, d + 1)))
+    u = u / u.pow(2).mean(dim=tuple(range(1, d + 1)), keepdim=True).sqrt()
+    return u.reshape(d, n ** d)
+
+
+def _ns_coupled(stream, steps):
+    """The coupled step (tfs_ns_step: the velocity by the projection method, then the stress
+    update with the new gradient) on [0, 2 pi)^d from synthetic_velocity, beta = 0.9 at
+    Re = 1000 (nu = 9e-4, eta_p = 1e-4), De = 1, alpha = 0.5, dt = 1e-3: 1024^2 with m = 32
+    FP64 modes and 128^3 with m = 32 FP32 modes.  Per configuration the ms of a coupled step,
+    of the stress update alone (tfs_step with the same kappa, timed after the coupled steps)
+    and of the velocity part (the difference)."""
+    import math
+    import torch
+    from paper_2411_17294_amd import ns, tfs
+    res = {}
+    for name, d, n, prec in (("ns_coupled_2d_1024sq_m32_fp64", 2, 1024, "fp64"),
+                             ("ns_coupled_3d_128cube_m32_fp32modes", 3, 128, "fp32_modes")):
+        P, m, alpha, De, beta, Re, dt = n ** d, 32, 0.5, 1.0, 0.9, 1000.0, 1e-3
+        w, lam, _, _, _ = tfs.soe_fit(alpha, m, dt, 1.0)
+        p = tfs.Plan(d, P, w, lam, alpha, De, (1 - beta) / Re, dt, 2 * steps + 16, precision=prec)
+        sol = ns.Solver(p, (n,) * d, (2 * math.pi,) * d, beta / Re, dt)
+        u, kappa, uh, fh = sol.alloc()
+        X, Y, tau, _ = p.alloc()
+        u[:, :P] = synthetic_velocity(d, n, 11 + d)
+        sol.init(u, uh, kappa)
+        for k in range(4):
+            sol.step(k, u, uh, fh, kappa, X, Y, tau)
+        ms = _timed(stream, lambda k: sol.step(k, u, uh, fh, kappa, X, Y, tau), 4, steps)
+        ms_stress = _timed(stream, lambda k: p.step(k, kappa, None, X, Y, tau), 4 + steps, steps)
+        if not bool(torch.isfinite(u[:, :P]).all()) or not bool(torch.isfinite(tau[:, :P]).all()):
+            raise SystemExit("non-finite field in the coupled-step benchmark")
+        res[name] = {"grid": [n] * d, "modes": m, "precision": prec, "ms_per_coupled_step": ms,
+                     "ms_stress_update": ms_stress, "ms_velocity_part": ms - ms_stress,
+                     "point_mode_updates_per_s": P * m / (ms * 1e-3), "u_rms": float(u[:, :P].pow(2).mean().sqrt())}
+        del sol, p
+    return res
 
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X
@@ -514,7 +567,7 @@ def main():
                     help="run the 384^3 differentiation workload end to end with STEPS time levels")
     ap.add_argument("--job-slabs", type=int, default=64, help="slabs of the --job run (64 = whole grid)")
     ap.add_argument("--only-forms", choices=["all", "fp32_vs_fp64", "fwd_adjoint", "slab384", "exp_vs_bdf2",
-                                             "fwd_adjoint_exp", "mfp_2d", "fused"],
+                                             "fwd_adjoint_exp", "mfp_2d", "fused", "ns"],
                     default=None,
                     help="only the 3-D form measurements (for profiling)")
     args = ap.parse_args()

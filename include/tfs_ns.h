@@ -65,6 +65,21 @@ tfs_status tfs_ns_destroy(tfs_ns ns);
 int64_t tfs_ns_spectral_size(tfs_ns ns);
 
 /*
+ * 1 when the solver transforms whole fields in batched hipFFT plans, 0 when it transforms
+ * one plane at a time (hipFFT refuses the batched layout, planes `stride` apart, for some
+ * sizes; the results are the same).
+ */
+int tfs_ns_batched(tfs_ns ns);
+
+/*
+ * Choose the transform form: on = 0 transforms one plane at a time, on = 1 asks for the
+ * batched plans (the form tfs_ns_create tries first).  Synchronises the device and remakes
+ * the plans.  Errors: TFS_EINVAL (null solver), TFS_EUNSUPPORTED (on = 1 and hipFFT
+ * refuses the batched layout; the solver then transforms one plane at a time), TFS_EHIP.
+ */
+tfs_status tfs_ns_set_batched(tfs_ns ns, int on);
+
+/*
  * Level 0: from the grid velocity u [d][stride] (overwritten), keep its divergence-free
  * part in the 2/3 band (Sec. 4.1 asks for a solenoidal velocity), store its coefficients
  * in slot 0 of uh, and write u^0 and kappa^0 = grad u^0 back on the grid.  Runs on the

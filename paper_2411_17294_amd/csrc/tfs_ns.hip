@@ -32,8 +32,11 @@ struct tfs_ns_s {
   double k0[3] = {0, 0, 0};        // 2 pi / L per axis
   double nu = 0.0, dt = 0.0;
   int64_t npoints = 0, nc = 0, stride = 0;
-  hipfftHandle fwd = 0, inv = 0;     // one real-to-complex and one complex-to-real transform
-  bool have_fwd = false, have_inv = false;
+  // Batched transforms of whole fields (d and c planes forward, d and d*d planes back), or,
+  // where hipFFT refuses such a layout, one plane at a time.
+  bool batched = false;
+  hipfftHandle plan[4] = {0, 0, 0, 0};   // batched: fwd d, fwd c, inv d, inv d*d; else fwd, inv
+  bool have[4] = {false, false, false, false};
   double* adv = nullptr;            // [d][stride] grid advection
   double2* spec_f = nullptr;        // [d + c][nc] forward transforms (advection, then tau)
   double2* spec_i = nullptr;        // [d + d*d][nc] inverse-transform inputs (u, then grad u)
@@ -252,34 +255,80 @@ tfs_status check_plan(const tfs_ns_s* s, const tfs_plan_s* p) {
 }
 
 tfs_status set_streams(tfs_ns_s* s, hipStream_t st) {
-  hipfftResult r = hipfftSetStream(s->fwd, st);
-  if (r == HIPFFT_SUCCESS) r = hipfftSetStream(s->inv, st);
-  return r == HIPFFT_SUCCESS ? TFS_OK : hipfft_fail(r, "hipfftSetStream");
+  for (int i = 0; i < 4; ++i) {
+    if (!s->have[i]) continue;
+    const hipfftResult r = hipfftSetStream(s->plan[i], st);
+    if (r != HIPFFT_SUCCESS) return hipfft_fail(r, "hipfftSetStream");
+  }
+  return TFS_OK;
 }
 
-// One transform of one contiguous plane (the planes of a field are transformed one by one:
-// batched plans with a plane distance above the plane size are refused for some sizes).
-tfs_status make_plan(tfs_ns_s* s, hipfftHandle* h, bool forward) {
-  int nn[3];
-  for (int j = 0; j < s->dim; ++j) nn[j] = (int)s->n[j];
-  const hipfftResult r = hipfftPlanMany(h, s->dim, nn, nullptr, 1, 0, nullptr, 1, 0,
-                                        forward ? HIPFFT_D2Z : HIPFFT_Z2D, 1);
-  return r == HIPFFT_SUCCESS ? TFS_OK : hipfft_fail(r, forward ? "hipfftPlanMany (D2Z)" : "hipfftPlanMany (Z2D)");
+void destroy_plans(tfs_ns_s* s) {
+  for (int i = 0; i < 4; ++i)
+    if (s->have[i]) hipfftDestroy(s->plan[i]);
+  for (int i = 0; i < 4; ++i) s->have[i] = false;
 }
 
-// Grid planes [count][stride] -> coefficient planes [count][nc].
-tfs_status forward_planes(tfs_ns_s* s, double* grid, double2* spec, int count) {
+// batch planes of distance `stride` on the grid side and nc on the coefficient side; with
+// batch = 0 one contiguous plane.
+hipfftResult make_plan(tfs_ns_s* s, hipfftHandle* h, bool forward, int batch) {
+  int nn[3], eg[3], es[3];
+  for (int j = 0; j < s->dim; ++j) nn[j] = eg[j] = es[j] = (int)s->n[j];
+  es[s->dim - 1] = (int)(s->n[s->dim - 1] / 2 + 1);
+  const hipfftType t = forward ? HIPFFT_D2Z : HIPFFT_Z2D;
+  if (batch == 0) return hipfftPlanMany(h, s->dim, nn, nullptr, 1, 0, nullptr, 1, 0, t, 1);
+  const int gd = (int)s->stride, sd = (int)s->nc;
+  return forward ? hipfftPlanMany(h, s->dim, nn, eg, 1, gd, es, 1, sd, t, batch)
+                 : hipfftPlanMany(h, s->dim, nn, es, 1, sd, eg, 1, gd, t, batch);
+}
+
+tfs_status make_plans(tfs_ns_s* s, bool try_batched) {
+  const int d = s->dim, c = d * (d + 1) / 2;
+  const int batch[4] = {d, c, d, d * d};
+  hipfftResult r = HIPFFT_SUCCESS;
+  for (int i = 0; i < 4 && r == HIPFFT_SUCCESS && try_batched; ++i) {
+    r = make_plan(s, &s->plan[i], i < 2, batch[i]);
+    s->have[i] = r == HIPFFT_SUCCESS;
+  }
+  if (try_batched && r == HIPFFT_SUCCESS) {
+    s->batched = true;
+    return TFS_OK;
+  }
+  destroy_plans(s);                 // not asked for, or the batched layout was refused
+  s->batched = false;
+  for (int i = 0; i < 2; ++i) {
+    r = make_plan(s, &s->plan[i], i == 0, 0);
+    if (r != HIPFFT_SUCCESS) return hipfft_fail(r, i == 0 ? "hipfftPlanMany (D2Z)" : "hipfftPlanMany (Z2D)");
+    s->have[i] = true;
+  }
+  return TFS_OK;
+}
+
+// Grid planes [count][stride] -> coefficient planes [count][nc]; `which` is the batched
+// plan for count planes (0: d, 1: c).
+tfs_status forward_planes(tfs_ns_s* s, double* grid, double2* spec, int count, int which) {
+  if (s->batched) {
+    const hipfftResult r = hipfftExecD2Z(s->plan[which], grid, (hipfftDoubleComplex*)spec);
+    return r == HIPFFT_SUCCESS ? TFS_OK : hipfft_fail(r, "hipfftExecD2Z");
+  }
   for (int i = 0; i < count; ++i) {
-    const hipfftResult r = hipfftExecD2Z(s->fwd, grid + (int64_t)i * s->stride, (hipfftDoubleComplex*)(spec + (int64_t)i * s->nc));
+    const hipfftResult r = hipfftExecD2Z(s->plan[0], grid + (int64_t)i * s->stride,
+                                         (hipfftDoubleComplex*)(spec + (int64_t)i * s->nc));
     if (r != HIPFFT_SUCCESS) return hipfft_fail(r, "hipfftExecD2Z");
   }
   return TFS_OK;
 }
 
-// Coefficient planes [count][nc] (overwritten) -> grid planes [count][stride].
-tfs_status inverse_planes(tfs_ns_s* s, double2* spec, double* grid, int count) {
+// Coefficient planes [count][nc] (overwritten) -> grid planes [count][stride]; `which` is
+// the batched plan for count planes (2: d, 3: d*d).
+tfs_status inverse_planes(tfs_ns_s* s, double2* spec, double* grid, int count, int which) {
+  if (s->batched) {
+    const hipfftResult r = hipfftExecZ2D(s->plan[which], (hipfftDoubleComplex*)spec, grid);
+    return r == HIPFFT_SUCCESS ? TFS_OK : hipfft_fail(r, "hipfftExecZ2D");
+  }
   for (int i = 0; i < count; ++i) {
-    const hipfftResult r = hipfftExecZ2D(s->inv, (hipfftDoubleComplex*)(spec + (int64_t)i * s->nc), grid + (int64_t)i * s->stride);
+    const hipfftResult r = hipfftExecZ2D(s->plan[1], (hipfftDoubleComplex*)(spec + (int64_t)i * s->nc),
+                                         grid + (int64_t)i * s->stride);
     if (r != HIPFFT_SUCCESS) return hipfft_fail(r, "hipfftExecZ2D");
   }
   return TFS_OK;
@@ -358,9 +407,7 @@ tfs_status tfs_ns_create(int dim, const int64_t* shape, const double* extent, do
   if (e == hipSuccess) e = hipMalloc((void**)&s->spec_f, sizeof(double2) * (dim + c) * s->nc);
   if (e == hipSuccess) e = hipMalloc((void**)&s->spec_i, sizeof(double2) * (dim + dim * dim) * s->nc);
   if (e != hipSuccess) st = set_error(TFS_ENOMEM, "device allocation of the solver's buffers failed");
-  if (st == TFS_OK) st = make_plan(s, &s->fwd, true);
-  if (st == TFS_OK) { s->have_fwd = true; st = make_plan(s, &s->inv, false); }
-  if (st == TFS_OK) s->have_inv = true;
+  if (st == TFS_OK) st = make_plans(s, true);
   if (st != TFS_OK) {
     const std::string keep = tfs_last_error();
     tfs_ns_destroy(s);
@@ -373,8 +420,7 @@ tfs_status tfs_ns_create(int dim, const int64_t* shape, const double* extent, do
 tfs_status tfs_ns_destroy(tfs_ns s) {
   if (!s) return TFS_OK;
   (void)hipDeviceSynchronize();
-  if (s->have_fwd) hipfftDestroy(s->fwd);
-  if (s->have_inv) hipfftDestroy(s->inv);
+  destroy_plans(s);
   if (s->adv) (void)hipFree(s->adv);
   if (s->spec_f) (void)hipFree(s->spec_f);
   if (s->spec_i) (void)hipFree(s->spec_i);
@@ -384,6 +430,17 @@ tfs_status tfs_ns_destroy(tfs_ns s) {
 
 int64_t tfs_ns_spectral_size(tfs_ns s) { return s ? s->nc : -1; }
 
+int tfs_ns_batched(tfs_ns s) { return s && s->batched ? 1 : 0; }
+
+tfs_status tfs_ns_set_batched(tfs_ns s, int on) {
+  if (!s) return set_error(TFS_EINVAL, "null solver");
+  (void)hipDeviceSynchronize();                 // plans of earlier launches may still run
+  const tfs_status st = make_plans(s, on != 0);
+  if (st != TFS_OK) return st;
+  if (on && !s->batched) return set_error(TFS_EUNSUPPORTED, "hipFFT refuses the batched layout for this size");
+  return TFS_OK;
+}
+
 tfs_status tfs_ns_init(tfs_ns s, tfs_plan p, double* u, void* uh, double* kappa) {
   if (!s) return set_error(TFS_EINVAL, "null solver");
   if (!u || !uh || !kappa) return set_error(TFS_EINVAL, "null u, uh or kappa");
@@ -391,7 +448,7 @@ tfs_status tfs_ns_init(tfs_ns s, tfs_plan p, double* u, void* uh, double* kappa)
   if (st != TFS_OK) return st;
   hipStream_t stream = p->stream;
   if ((st = set_streams(s, stream)) != TFS_OK) return st;
-  if ((st = forward_planes(s, u, s->spec_f, s->dim)) != TFS_OK) return st;
+  if ((st = forward_planes(s, u, s->spec_f, s->dim, 0)) != TFS_OK) return st;
   double2* uh0 = (double2*)uh;                  // slot 0
   const int blocks = grid_blocks(s->nc);
   if (s->dim == 2)
@@ -403,8 +460,8 @@ tfs_status tfs_ns_init(tfs_ns s, tfs_plan p, double* u, void* uh, double* kappa)
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "ns_init_kernel launch");
   const int d = s->dim;
-  if ((st = inverse_planes(s, s->spec_i, u, d)) != TFS_OK) return st;
-  return inverse_planes(s, s->spec_i + (int64_t)d * s->nc, kappa, d * d);
+  if ((st = inverse_planes(s, s->spec_i, u, d, 2)) != TFS_OK) return st;
+  return inverse_planes(s, s->spec_i + (int64_t)d * s->nc, kappa, d * d, 3);
 }
 
 tfs_status tfs_ns_step(tfs_ns s, tfs_plan p, int64_t n, double* u, void* uh, void* fh, double* kappa, double* X,
@@ -433,13 +490,13 @@ tfs_status tfs_ns_step(tfs_ns s, tfs_plan p, int64_t n, double* u, void* uh, voi
                        s->adv, s->npoints, s->stride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "ns_advect_kernel launch");
-  if ((st = forward_planes(s, s->adv, s->spec_f, d)) != TFS_OK) return st;
-  if ((st = forward_planes(s, tau, s->spec_f + lvl, d * (d + 1) / 2)) != TFS_OK) return st;
+  if ((st = forward_planes(s, s->adv, s->spec_f, d, 0)) != TFS_OK) return st;
+  if ((st = forward_planes(s, tau, s->spec_f + lvl, d * (d + 1) / 2, 1)) != TFS_OK) return st;
   st = d == 2 ? launch_update<2>(s, stream, n, uh_n, uh_o, fh_m, fh_n, uh_o)
               : launch_update<3>(s, stream, n, uh_n, uh_o, fh_m, fh_n, uh_o);
   if (st != TFS_OK) return st;
-  if ((st = inverse_planes(s, s->spec_i, u, d)) != TFS_OK) return st;
-  if ((st = inverse_planes(s, s->spec_i + lvl, kappa, d * d)) != TFS_OK) return st;
+  if ((st = inverse_planes(s, s->spec_i, u, d, 2)) != TFS_OK) return st;
+  if ((st = inverse_planes(s, s->spec_i + lvl, kappa, d * d, 3)) != TFS_OK) return st;
   // the stress of level n+1 from kappa^{n+1}
   return tfs_step(p, n, kappa, nullptr, X, Y, tau, diag);
 }

@@ -25,6 +25,12 @@ class Solver:
         tfs.check(tfs.lib().tfs_ns_create(self.dim, sh, ex, float(nu), float(dt), int(plan.stride), C.byref(h)))
         self._h = h
         self.nc = int(tfs.lib().tfs_ns_spectral_size(h))
+        self.batched = bool(tfs.lib().tfs_ns_batched(h))
+
+    def set_batched(self, on: bool):
+        """Transform whole fields in batched plans (True) or one plane at a time (False)."""
+        tfs.check(tfs.lib().tfs_ns_set_batched(self._h, int(bool(on))))
+        self.batched = bool(tfs.lib().tfs_ns_batched(self._h))
 
     @property
     def handle(self):

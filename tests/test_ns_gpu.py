@@ -21,11 +21,15 @@ pytestmark = pytest.mark.gpu
 BAR = {"fp64": 1e-12, "fp32_modes": 1e-5}
 
 
-def gpu_run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, prec="fp64", scheme="bdf2", alpha=0.6):
+def gpu_run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, prec="fp64", scheme="bdf2", alpha=0.6,
+            batched=True):
     P = int(np.prod(shape))
     c = d * (d + 1) // 2
     plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, max(N, 1), precision=prec, scheme=scheme)
     sol = ns.Solver(plan, shape, extent, nu, dt)
+    if not batched:
+        sol.set_batched(False)
+    print(f"  transforms batched: {sol.batched}", flush=True)
     u, kappa, uh, fh = sol.alloc()
     X, Y, tau, _ = plan.alloc()
     u[:, :P] = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
@@ -52,15 +56,17 @@ def random_case(d, shape, seed, amp=0.6):
 CASES = [(2, (16, 12), (1.0, 1.5)), (2, (9, 14), (2 * math.pi, 1.0)), (3, (8, 6, 10), (1.0, 0.8, 1.3))]
 
 
+@pytest.mark.parametrize("batched", [True, False])
 @pytest.mark.parametrize("N", [0, 1, 2, 9])
 @pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
 @pytest.mark.parametrize("d,shape,extent", CASES)
-def test_coupled_steps_match_oracle(d, shape, extent, prec, N):
+def test_coupled_steps_match_oracle(d, shape, extent, prec, N, batched):
+    """Both transform forms (batched plans where hipFFT takes them, one plane at a time)."""
     m, alpha, De, eta_p, nu, dt = 6, 0.6, 0.7, 0.3, 0.05, 1e-2
     w, lam, _ = osoe.soe_fit(alpha, m, dt, dt * max(N, 2))
     u0, X0 = random_case(d, shape, 100 + d + N)
-    print(f"coupled d={d} shape={shape} {prec} N={N}", flush=True)
-    g = gpu_run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, prec=prec, alpha=alpha)
+    print(f"coupled d={d} shape={shape} {prec} N={N} batched={batched}", flush=True)
+    g = gpu_run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, prec=prec, alpha=alpha, batched=batched)
     o = ons.run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0)
     half = o["uh"][..., :shape[-1] // 2 + 1].reshape(d, -1)
     errs = {"u": relerr(g["u"], o["u"]), "kappa": relerr(g["kappa"], o["kappa"]),
@@ -171,6 +177,12 @@ def test_solver_errors():
     with pytest.raises(tfs.TfsError):
         ns.Solver(plan, (16, 16), (1.0, -1.0), 0.1, 1e-3)        # negative extent
     sol = ns.Solver(plan, (16, 16), (1.0, 1.0), 0.1, 1e-3)
+    sol.set_batched(False)
+    assert not sol.batched
+    try:
+        sol.set_batched(True)
+    except tfs.TfsError as e:          # hipFFT may refuse the batched layout at this size
+        assert e.status == tfs.TFS_EUNSUPPORTED and not sol.batched
     u, kappa, uh, fh = sol.alloc()
     X, Y, tau, _ = plan.alloc()
     other = tfs.Plan(3, 16 * 16, w, lam, 0.5, 1.0, 0.1, 1e-3, 4)      # a 3-D stress plan
