@@ -83,8 +83,9 @@ tfs_status tfs_ns_set_batched(tfs_ns ns, int on);
  * Level 0: from the grid velocity u [d][stride] (overwritten), keep its divergence-free
  * part in the 2/3 band (Sec. 4.1 asks for a solenoidal velocity), store its coefficients
  * in slot 0 of uh, and write u^0 and kappa^0 = grad u^0 back on the grid.  Runs on the
- * plan's stream; the plan (dim, npoints, stride) must match the solver.
- * Errors: TFS_EINVAL (null pointers, mismatched plan), TFS_EHIP.
+ * plan's stream; the plan (dim, npoints, stride) must match the solver and must not have
+ * a spatial form set (tfs_plan_set_spatial: its points are Fourier coefficients).
+ * Errors: TFS_EINVAL (null pointers, mismatched or spatial-form plan), TFS_EHIP.
  */
 tfs_status tfs_ns_init(tfs_ns ns, tfs_plan plan, double* u, void* uh, double* kappa);
 
@@ -94,7 +95,8 @@ tfs_status tfs_ns_init(tfs_ns ns, tfs_plan plan, double* u, void* uh, double* ka
  * unused at n = 0) and fh slot (n-1) % 2 holds F^{n-1} (unused at n = 0).  The step writes
  * F^n to fh slot n % 2, u^{n+1} to uh slot (n+1) % 2, u and kappa of level n+1 on the grid,
  * and then calls tfs_step(plan, n, kappa, NULL, X, Y, tau, diag).
- * Errors: those of tfs_step, TFS_EINVAL (null pointers, mismatched plan), TFS_EHIP.
+ * Errors: those of tfs_step, TFS_EINVAL (null pointers, mismatched or spatial-form plan),
+ * TFS_EHIP.
  */
 tfs_status tfs_ns_step(tfs_ns ns, tfs_plan plan, int64_t n, double* u, void* uh, void* fh, double* kappa,
                        double* X, void* Y, double* tau, double* diag);

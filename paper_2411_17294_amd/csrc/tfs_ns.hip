@@ -28,6 +28,7 @@ tfs_status set_error(tfs_status s, const char* msg);   // tfs_host.cpp
 
 struct tfs_ns_s {
   int dim = 0;
+  int device = 0;                   // the device its buffers and plans live on
   int64_t n[3] = {1, 1, 1};
   double k0[3] = {0, 0, 0};        // 2 pi / L per axis
   double nu = 0.0, dt = 0.0;
@@ -251,6 +252,11 @@ tfs_status check_plan(const tfs_ns_s* s, const tfs_plan_s* p) {
   if (!p) return set_error(TFS_EINVAL, "null stress plan");
   if (p->d != s->dim || p->npoints != s->npoints || p->stride != s->stride)
     return set_error(TFS_EINVAL, "stress plan does not match the solver (dim, npoints, stride)");
+  if (p->sp_rate || p->sp_source >= 0)
+    return set_error(TFS_EINVAL, "the coupled step needs a pointwise stress plan (no spatial form set)");
+  if (p->device != s->device) return set_error(TFS_EINVAL, "stress plan and solver live on different devices");
+  if (!s->have[0] || !s->have[1])
+    return set_error(TFS_EHIP, "the solver has no transform plans (an earlier tfs_ns_set_batched failed)");
   return TFS_OK;
 }
 
@@ -392,6 +398,7 @@ tfs_status tfs_ns_create(int dim, const int64_t* shape, const double* extent, do
   tfs_ns_s* s = new (std::nothrow) tfs_ns_s;
   if (!s) return set_error(TFS_ENOMEM, "host allocation failed");
   s->dim = dim;
+  (void)hipGetDevice(&s->device);
   for (int j = 0; j < dim; ++j) {
     s->n[j] = shape[j];
     s->k0[j] = 2.0 * M_PI / extent[j];

@@ -188,6 +188,10 @@ def test_solver_errors():
     other = tfs.Plan(3, 16 * 16, w, lam, 0.5, 1.0, 0.1, 1e-3, 4)      # a 3-D stress plan
     rc = tfs.lib().tfs_ns_init(sol.handle, other.handle, u.data_ptr(), uh.data_ptr(), kappa.data_ptr())
     assert rc == tfs.TFS_EINVAL
+    plan.set_spatial(None, 0)                                     # a spatial-form plan is refused
+    with pytest.raises(tfs.TfsError):
+        sol.init(u, uh, kappa)
+    plan.set_spatial(None, -1)
     sol.init(u, uh, kappa)
     with pytest.raises(tfs.TfsError):
         sol.step(4, u, uh, fh, kappa, X, Y, tau)                 # past max_steps
