@@ -2,9 +2,10 @@
 benchmark's CPU-baseline leg may use it; the product path never does).
 
 What it computes: the macroscopic Fokker-Planck (MFP) equation of Sec. 4.1 with
-centre-of-mass diffusion and no advection (u = 0), on a periodic grid,
+centre-of-mass diffusion and, optionally, advection by a given velocity field u(x, t), on a
+periodic grid,
 
-    d/dt Phi + L( sum_k (w_k Phi - lam_k Phi_k) ) = 0,   L = -eps Laplace - A(kappa),
+    d/dt Phi + L( sum_k (w_k Phi - lam_k Phi_k) ) = 0,   L = u.grad - eps Laplace - A(kappa),
     d/dt Phi_k = -lam_k Phi_k + w_k Phi                  (Sec. 2.2, kernel compression),
 
 in the paper's own variables: at every grid point the vector Phi of Hermite coefficients
@@ -20,8 +21,12 @@ operator taken from the pinned pointwise oracle.  The time scheme is the paper's
 Everything is assembled in physical space as dense matrices over (grid point, Hermite
 component) and solved directly (numpy.linalg.solve), so only small grids are meant.  The
 Laplacian is the spectral one on the periodic grid: its symbol is -|xi|^2 on the discrete
-Fourier modes (numpy.fft), the Nyquist mode included.  kappa may vary in space and time;
-the extrapolation kappa~ = 2 kappa^n - kappa^{n-1} is the one of eq. BDF_and_extrapolation.
+Fourier modes (numpy.fft), the Nyquist mode included.  The advection u.grad acts on every
+Hermite coefficient: at each point u_j(x) times the spectral derivative d/dx_j, whose
+symbol is i xi_j with the Nyquist wave number taken as zero (an odd derivative of a real
+grid field has no Nyquist component).  kappa and u may vary in space and time; both use the
+level rule of eq. BDF_and_extrapolation (kappa~ = 2 kappa^n - kappa^{n-1}, likewise u~) or,
+without extrapolation, the level n+1.
 
 The stress is tau = (eta_p / De) D^{1-alpha}(C - I) with D^{1-alpha} Phi taken from the
 modes of the new level (eq. fractional_modes_fractional_derivative), summed with Neumaier
@@ -59,6 +64,23 @@ def laplacian_matrix(shape, extent):
     return lap
 
 
+def derivative_matrix(shape, extent, axis):
+    """Dense matrix of the spectral first derivative along `axis` on the flattened grid."""
+    P = int(np.prod(shape))
+    n, L = shape[axis], extent[axis]
+    k = 2.0 * math.pi * np.fft.fftfreq(n, d=L / n)
+    if n % 2 == 0:
+        k[n // 2] = 0.0
+    sym = k.reshape([n if j == axis else 1 for j in range(len(shape))])
+    D = np.empty((P, P))
+    for j in range(P):
+        e = np.zeros(P)
+        e[j] = 1.0
+        col = np.fft.ifftn(1j * sym * np.fft.fftn(e.reshape(shape)))
+        D[:, j] = col.real.reshape(P)
+    return D
+
+
 def hermite_map(d):
     """B with Phi = B [1, X_packed] (mass mode one), from the pointwise oracle's map."""
     c = d * (d + 1) // 2
@@ -79,11 +101,20 @@ def _kappa_at(kappa, d, P, lev):
     return np.asarray(k, dtype=np.float64).reshape(d, d, P).transpose(2, 0, 1)
 
 
-def _operator(d, De, eps, lap, kap_pts):
-    """Dense A(kappa) + eps Laplace over [point][component] (= -L)."""
+def _u_at(u, d, P, lev):
+    """u of level lev as [d][P] (steady [d][P] or levels [nlev][d][P])."""
+    uu = np.asarray(u, dtype=np.float64)
+    return uu if uu.ndim == 2 else uu[lev]
+
+
+def _operator(d, De, eps, lap, kap_pts, adv=None):
+    """Dense A(kappa) + eps Laplace - u.grad over [point][component] (= -L); adv is the
+    dense u.grad of one scalar field (or None)."""
     P = kap_pts.shape[0]
     n = d * (d + 1) // 2 + 1
     A = eps * np.kron(lap, np.eye(n))
+    if adv is not None:
+        A -= np.kron(adv, np.eye(n))
     for p in range(P):
         A[p * n:(p + 1) * n, p * n:(p + 1) * n] += _pointwise.coupling_matrix(d, De, kap_pts[p])
     return A
@@ -102,12 +133,12 @@ def _neumaier(terms):
 
 
 def run(d, shape, extent, eps, w, lam, De, eta_p, dt, nsteps, kappa, X0, extrap=True,
-        want_modes=False, want_traj=False):
+        want_modes=False, want_traj=False, u=None):
     """Run the spatial oracle.
 
     shape, extent: grid points and box length per axis (len d); points in C order.
     kappa: [d*d][P] (steady) or [nlev][d*d][P], nlev >= nsteps + 1; X0: [c][P] (packed,
-    X = C - I).  Returns X [2][c][P] (levels N, N-1), tau [c][P], modes [2][m][c][P] (plain,
+    X = C - I); u: None (no advection), [d][P] (steady) or [nlev][d][P].  Returns X [2][c][P] (levels N, N-1), tau [c][P], modes [2][m][c][P] (plain,
     levels N and N-1) or None, traj [N+1][c][P] or None."""
     w = np.asarray(w, dtype=np.float64)
     lam = np.asarray(lam, dtype=np.float64)
@@ -119,6 +150,7 @@ def run(d, shape, extent, eps, w, lam, De, eta_p, dt, nsteps, kappa, X0, extrap=
     kappa = np.asarray(kappa, dtype=np.float64)
     assert X0.shape == (c, P) and len(shape) == d
     lap = laplacian_matrix(shape, extent)
+    Dm = [derivative_matrix(shape, extent, j) for j in range(d)] if u is not None else None
     B = hermite_map(d)
     Binv = np.linalg.inv(B)
     gamma = eta_p / De
@@ -137,16 +169,25 @@ def run(d, shape, extent, eps, w, lam, De, eta_p, dt, nsteps, kappa, X0, extrap=
     etak = lam * dt / (B0 + lam * dt)
 
     I = np.eye(P * n)
-    kt_prev, A = None, None
+    kt_prev, ut_prev, A = None, None, None
     for step in range(nsteps):
+        ut = None
         if extrap:
             ka = _kappa_at(kappa, d, P, step)
             kt = ka if step == 0 else 2.0 * ka - _kappa_at(kappa, d, P, step - 1)
+            if u is not None:
+                ua = _u_at(u, d, P, step)
+                ut = ua if step == 0 else 2.0 * ua - _u_at(u, d, P, step - 1)
         else:
             kt = _kappa_at(kappa, d, P, step + 1)
-        if kt_prev is None or not np.array_equal(kt, kt_prev):
-            A = _operator(d, De, eps, lap, kt)
-            kt_prev = kt
+            if u is not None:
+                ut = _u_at(u, d, P, step + 1)
+        same_u = (ut is None and ut_prev is None) or (
+            ut is not None and ut_prev is not None and np.array_equal(ut, ut_prev))
+        if kt_prev is None or not np.array_equal(kt, kt_prev) or not same_u:
+            adv = None if ut is None else sum(ut[j][:, None] * Dm[j] for j in range(d))
+            A = _operator(d, De, eps, lap, kt, adv)
+            kt_prev, ut_prev = kt, ut
         if step == 0:
             hg = dt * GS
             theta = np.sum(w / (1.0 + hg * lam))

@@ -132,3 +132,63 @@ def test_paper_convergence_experiment_sec_5_1():
         norms.append(math.sqrt(np.sum(dt * l2 * ts ** (2 * (1 - alpha)))))
     orders = [math.log2(norms[i] / norms[i + 1]) for i in range(len(norms) - 1)]
     assert all(1.3 < o < 1.7 for o in orders), (norms, orders)
+
+
+@pytest.mark.parametrize("shape,extent", [((6, 8), (1.0, 2.0)), ((4, 6, 8), (1.0, 2.0 * math.pi, 3.0))])
+def test_spectral_derivatives_of_trigonometric_polynomials(shape, extent):
+    """d/dx_j of sin(2 pi k.x/L) and cos(...) below the Nyquist mode in closed form; the
+    Nyquist cosine (the only Nyquist mode a real grid field carries) has derivative zero."""
+    d = len(shape)
+    xs = grid_points(shape, extent)
+    rng = np.random.default_rng(21)
+    for axis in range(d):
+        Dm = mfp.derivative_matrix(shape, extent, axis)
+        for trial in range(4):
+            ks = [int(rng.integers(-(n // 2 - 1), n // 2)) for n in shape]
+            arg = sum(2 * math.pi * ks[j] * xs[j] / extent[j] for j in range(d))
+            dk = 2 * math.pi * ks[axis] / extent[axis]
+            np.testing.assert_allclose(Dm @ np.sin(arg), dk * np.cos(arg), rtol=0, atol=1e-10 * max(1.0, abs(dk)))
+            np.testing.assert_allclose(Dm @ np.cos(arg), -dk * np.sin(arg), rtol=0, atol=1e-10 * max(1.0, abs(dk)))
+        nyq = np.cos(math.pi * shape[axis] * xs[axis] / extent[axis])
+        assert np.max(np.abs(Dm @ nyq)) < 1e-10
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("N", [1, 2, 12])
+def test_uniform_advection_of_one_fourier_mode_is_a_complex_rate(d, N):
+    """u uniform, kappa constant, X0 = F + E cos(xi.x): the mean follows the pointwise scheme
+    from F, and since u.grad acts on exp(i xi.x) as i xi.u, the cos(xi.x) part is the real
+    part of exp(i xi.x) times the source-free pointwise scheme from E with the complex rate
+    1/De + eps |xi|^2 + i xi.u in place of 1/De (complex runs of the pointwise oracle, from E
+    minus from 0), at the same eta_p/De."""
+    shape, extent = ((6, 8), (1.0, 2.0)) if d == 2 else ((4, 4, 6), (1.0, 2.0, 3.0))
+    ks = (1, 3) if d == 2 else (1, -1, 2)
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    xs = grid_points(shape, extent)
+    xi = [2 * math.pi * ks[j] / extent[j] for j in range(d)]
+    phase = sum(xi[j] * xs[j] for j in range(d))
+    rng = np.random.default_rng(31 + d)
+    kd = rng.standard_normal((d, d)) * 0.4
+    u0 = rng.standard_normal(d) * 0.7
+    E = rng.standard_normal(c) * 0.05
+    F = rng.standard_normal(c) * 0.05
+    X0 = F[:, None] + E[:, None] * np.cos(phase)[None, :]
+    De, eta_p, eps, dt = 0.8, 0.1, 0.02, 2e-3
+    w, lam, _ = soe.soe_fit(0.6, 8, dt, dt * max(N, 2))
+    kap = np.repeat(kd.reshape(d * d, 1), P, axis=1)
+    u = np.repeat(u0.reshape(d, 1), P, axis=1)
+    r = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, want_modes=True, u=u)
+    one = kd.reshape(d * d, 1)
+    rate = 1.0 / De + eps * sum(x * x for x in xi) + 1j * sum(xi[j] * u0[j] for j in range(d))
+    De_x = 1.0 / rate
+    mean = O.run(d, w, lam, De, eta_p, dt, N, one, F[:, None], want_modes=True)
+    zE = O.run_complex(d, w, lam, De_x, eta_p * De_x / De, dt, N, one.astype(complex), E[:, None].astype(complex),
+                       want_modes=True)
+    z0 = O.run_complex(d, w, lam, De_x, eta_p * De_x / De, dt, N, one.astype(complex), np.zeros((c, 1), complex),
+                       want_modes=True)
+    wave = np.exp(1j * phase)
+    for k in ("X", "tau", "modes"):
+        pred = mean[k] + np.real((zE[k] - z0[k]) * wave)
+        err = np.max(np.abs(r[k] - pred)) / np.max(np.abs(pred))
+        assert err < 1e-12, (k, err)

@@ -83,6 +83,12 @@ MFP_MUTATIONS = {
     "nyquist_dropped": ("return sum(g * g for g in grids)",
                         "return sum(np.where(np.abs(g) >= np.max(np.abs(g)) - 1e-9, 0.0, g * g) for g in grids)",
                         "trigonometric"),
+    "advection_sign": ("A -= np.kron(adv, np.eye(n))", "A += np.kron(adv, np.eye(n))", "complex_rate"),
+    "derivative_on_the_wrong_axis": ("sym = k.reshape([n if j == axis else 1 for j in range(len(shape))])",
+                                     "sym = k.reshape([n if j == len(shape) - 1 - axis else 1 "
+                                     "for j in range(len(shape))]) if len(set(shape)) == 1 else "
+                                     "np.resize(k, shape[-1]).reshape([1] * (len(shape) - 1) + [shape[-1]])",
+                                     "spectral_derivatives"),
 }
 
 _RUN_MUTANT = """
