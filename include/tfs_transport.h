@@ -1,0 +1,72 @@
+/*
+ * tfs_transport.h -- C ABI of the stress update with the transport terms of the MFP
+ * equation on a periodic grid (Sec. 4.1, eq. FP_discrete with L = u.grad - eps Laplace -
+ * A(kappa~)): advection by a velocity field u(x) and centre-of-mass diffusion, both inside
+ * the implicit operator (b_0 + eta L) of the BDF2 scheme and of its SDIRK2 start, with u and
+ * kappa varying in space and time.
+ *
+ * The operator couples the points, so a step is no longer pointwise.  Per step:
+ *   1. the modes advance pointwise (in the Y-form of tfs.h they do not depend on X^{n+1});
+ *      each point's right-hand side R and history combination G come out of the same pass;
+ *   2. the right-hand side gains L's transport part applied to G (the history terms
+ *      sum_k eta_k L Phi_k of eq. FP_discrete);
+ *   3. the coupled system (a I - b K(kappa~(x)) + b T) X = rhs, T = u~.grad - eps Laplace, is
+ *      solved by a fixed number of splitting iterations preconditioned by its
+ *      constant-coefficient part: with the spatial means kappa_bar and u_bar,
+ *          P(xi) = (a + b eps |xi|^2 + i b xi.u_bar) I - b K(kappa_bar),
+ *          X_hat <- P^{-1} (rhs_hat - F[ -b K(kappa~ - kappa_bar) X + b (u~ - u_bar).grad X ]),
+ *      which converges when the variable part is small next to P (small dt, eps > 0 or a
+ *      nearly uniform u);
+ *   4. tau from X^{n+1} and G, pointwise.
+ * The SDIRK2 start solves the same kind of system once per stage.  Derivatives are spectral
+ * (first derivatives with the Nyquist wave number taken as zero); transforms are hipFFT
+ * plans made at creation.
+ *
+ * Layouts: as tfs.h (grid fields [comp][stride], point index = C-order grid index); the
+ * velocity u is [d][stride] FP64.  The object owns its FFT plans and work buffers (about
+ * (6c + 2cd) planes of the stride plus spectral planes), allocated at creation.
+ */
+#ifndef TFS_TRANSPORT_H
+#define TFS_TRANSPORT_H
+
+#include <stdint.h>
+
+#include "tfs.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tfs_transport_s* tfs_transport;
+
+/*
+ * A periodic box of shape[0..dim-1] points (each >= 2) and extent[0..dim-1] lengths (> 0),
+ * centre-of-mass diffusion eps >= 0, grid fields of plane stride `stride` (the stress plan's
+ * stride), and `iters` >= 0 splitting iterations per solve (0: the preconditioner alone,
+ * exact when kappa and u are uniform).
+ * Errors: TFS_EINVAL, TFS_ENOMEM, TFS_EHIP.  *out is NULL on error.
+ */
+tfs_status tfs_transport_create(int dim, const int64_t* shape, const double* extent, double eps, int64_t stride,
+                                int iters, tfs_transport* out);
+
+/* Release (NULL is accepted); synchronises the device first. */
+tfs_status tfs_transport_destroy(tfs_transport tr);
+
+/*
+ * One step n -> n+1 of a TFS_SCHEME_BDF2 plan with the transport terms: as tfs_step (the
+ * same X and Y rings, SDIRK2 at n = 0, BDF2 after), with the velocity levels u_a, u_b
+ * [d][stride] following kappa's rule (extrapolated 2 u_a - u_b when kappa_b is given and
+ * n >= 1, else u_a).  The plan must match the object (dim, npoints, stride), be pointwise
+ * (no tfs_plan_set_spatial) and use the BDF2 scheme.  No diagnostics.
+ * Errors: TFS_EINVAL (null or mismatched arguments, u_b missing while kappa_b is given),
+ * TFS_EUNSUPPORTED (exponential scheme, spatial form), TFS_EHIP.
+ */
+tfs_status tfs_transport_step(tfs_transport tr, tfs_plan plan, int64_t n, const double* kappa_a,
+                              const double* kappa_b, const double* u_a, const double* u_b, double* X, void* Y,
+                              double* tau);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

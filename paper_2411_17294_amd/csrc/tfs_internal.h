@@ -184,6 +184,10 @@ hipError_t launch_fused(const tfs_plan_s* p, int64_t n0, int64_t nsteps, double*
 hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
                        double* tau, double* diag);
 hipError_t launch_startup(const tfs_plan_s* p, const double* ka, const Levels& L, double* tau, double* diag);
+// BDF2 step n >= 1 without the local solve: writes Y^{n+1} (L.Yo), the right-hand side R of
+// each point (L.Xo) and the history combination G ([c][stride]); no diagnostics.
+hipError_t launch_bdf2_split(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+                             double* G);
 // Exponential-mode step n -> n+1 (TFS_SCHEME_EXP): reads L.Xn and L.Yn (not at n = 0),
 // writes L.Xo and L.Yo (which may be L.Yn).
 hipError_t launch_exp(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,

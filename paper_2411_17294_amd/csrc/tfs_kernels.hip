@@ -95,7 +95,10 @@ struct Bdf2Args {
   SpatialArgs sp;
 };
 
-template <int D, typename MT, int V, bool DIAG, bool SP>
+// SPLIT: the step without its local solve, for a caller that solves a spatially coupled
+// system for X^{n+1}: the modes advance as usual (in the Y-form they do not depend on
+// X^{n+1}), the point's right-hand side R goes to Xo and the history combination G to tau.
+template <int D, typename MT, int V, bool DIAG, bool SP, bool SPLIT = false>
 __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr& w, DiagAcc& acc) {
   constexpr int C = Sym<D>::C;
   const int64_t st = a.stride;
@@ -202,6 +205,14 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr
       const double S = k[i * D + j] + k[j * D + i];
       R[s] = P[s][v] - (AG[s] - idv * G[s]) + zw * S;
     }
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int s = 0; s < C; ++s) {
+        Xout[s][v] = R[s];
+        Tout[s][v] = G[s];
+      }
+      continue;
+    }
     double M[C][C];
     build_M<D>(k, ad, a.s.eta, M);
     solve_pivot<C>(M, R);
@@ -226,7 +237,7 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr
 
 // Groups [0, ngroups) of V points from p_begin, 64 consecutive groups per wave; the
 // caller launches a V = 1 pass for the points after the last whole group.
-template <int D, typename MT, int V, bool DIAG, bool SP>
+template <int D, typename MT, int V, bool DIAG, bool SP, bool SPLIT = false>
 __global__ __launch_bounds__(kBlock) void bdf2_kernel(const Bdf2Args<MT> a) {
   constexpr int C = Sym<D>::C;
   DiagAcc acc;
@@ -236,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void bdf2_kernel(const Bdf2Args<MT> a) {
   for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
        wv += wstride) {
     if (wv * 64 + lane < a.ngroups)
-      bdf2_group<D, MT, V, DIAG, SP>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
+      bdf2_group<D, MT, V, DIAG, SP, SPLIT>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
   }
   if constexpr (DIAG) {
     const DiagAcc r = block_reduce(acc);
@@ -701,6 +712,61 @@ hipError_t start_go(const tfs_plan_s* p, const StartArgs<MT>& a, bool diag, doub
   return diag ? start_go_<D, MT, V, true, false>(p, a, diag_out) : start_go_<D, MT, V, false, false>(p, a, diag_out);
 }
 
+// The split step (no local solve): a V-wide pass and a V = 1 tail pass, no diagnostics.
+template <int D, typename MT, int V>
+hipError_t bdf2_split_go(const tfs_plan_s* p, Bdf2Args<MT> a) {
+  const int64_t full = p->npoints / V, rest = p->npoints - full * V;
+  if (full > 0) {
+    a.p_begin = 0;
+    a.ngroups = full;
+    a.part0 = 0;
+    hipLaunchKernelGGL((bdf2_kernel<D, MT, V, false, false, true>), dim3(grid_for(p, full)), dim3(kBlock), 0,
+                       p->stream, a);
+  }
+  if (rest > 0) {
+    a.p_begin = full * V;
+    a.ngroups = rest;
+    a.part0 = 0;
+    hipLaunchKernelGGL((bdf2_kernel<D, MT, 1, false, false, true>), dim3(grid_for(p, rest)), dim3(kBlock), 0,
+                       p->stream, a);
+  }
+  return hipGetLastError();
+}
+
+template <int D, typename MT>
+hipError_t bdf2_split_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+                               double* G) {
+  Bdf2Args<MT> a;
+  a.ka = ka;
+  a.kb = kb;
+  a.Xn = L.Xn;
+  a.Xm = L.Xm;
+  a.Xo = L.Xo;
+  a.Yn = static_cast<const MT*>(L.Yn);
+  a.Ym = static_cast<const MT*>(L.Ym);
+  a.Yo = static_cast<MT*>(L.Yo);
+  a.tau = G;
+  a.coef = p->d_coef;
+  a.part = p->d_part;
+  a.stride = p->stride;
+  a.tile = p->tile;
+  a.m = p->m;
+  a.s.a_diag = p->a_diag;
+  a.sp.rate = nullptr;
+  a.sp.src = -1;
+  a.s.eta = p->eta;
+  a.s.s_ec = p->s_ec;
+  a.s.inv_De = 1.0 / p->De;
+  a.s.zeta = p->zeta[n + 1];
+  a.s.tau_scale = p->tau_scale;
+  const int V = pick_vec<D, MT>(p, ka, kb, L, G);
+  if constexpr (sizeof(MT) == 4) {
+    if (V == 4) return bdf2_split_go<D, MT, 4>(p, a);
+  }
+  if (V == 2) return bdf2_split_go<D, MT, 2>(p, a);
+  return bdf2_split_go<D, MT, 1>(p, a);
+}
+
 template <int D, typename MT>
 hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, const Levels& L, double* tau, double* diag) {
   StartArgs<MT> a;
@@ -820,6 +886,16 @@ hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const d
                      : bdf2_dispatch<3, double>(p, n, ka, kb, L, tau, diag);
   return p->d == 2 ? bdf2_dispatch<2, float>(p, n, ka, kb, L, tau, diag)
                    : bdf2_dispatch<3, float>(p, n, ka, kb, L, tau, diag);
+}
+
+hipError_t launch_bdf2_split(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+                             double* G) {
+  if (p->npoints == 0) return hipSuccess;
+  if (p->precision == TFS_FP64)
+    return p->d == 2 ? bdf2_split_dispatch<2, double>(p, n, ka, kb, L, G)
+                     : bdf2_split_dispatch<3, double>(p, n, ka, kb, L, G);
+  return p->d == 2 ? bdf2_split_dispatch<2, float>(p, n, ka, kb, L, G)
+                   : bdf2_split_dispatch<3, float>(p, n, ka, kb, L, G);
 }
 
 hipError_t launch_startup(const tfs_plan_s* p, const double* ka, const Levels& L, double* tau, double* diag) {

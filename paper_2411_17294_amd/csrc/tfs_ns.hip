@@ -21,6 +21,7 @@
 #include "tfs_device.h"
 #include "tfs_internal.h"
 #include "tfs_ns.h"
+#include "tfs_spectral.h"
 
 namespace tfs {
 tfs_status set_error(tfs_status s, const char* msg);   // tfs_host.cpp
@@ -61,30 +62,19 @@ tfs_status hip_fail(hipError_t e, const char* what) {
   return set_error(TFS_EHIP, buf);
 }
 
-// Spectral coordinates of coefficient q of the half spectrum: wave vector xi and whether
-// every integer wave number lies in the 2/3 band.
-struct SpecGeom {
-  int64_t n0, n1, n2, h;            // grid sizes (unused axes 1) and the half length of the last
-  double k0, k1, k2;                // 2 pi / L
-};
+using tfs::SpecGeom;
 
+// Wave vector xi of coefficient q and whether every integer wave number lies in the 2/3
+// band |k_j| < n_j / 3.
 template <int D>
 __device__ __forceinline__ bool wave_vector(const SpecGeom& g, int64_t q, double xi[D]) {
-  const int64_t nn[3] = {g.n0, g.n1, g.n2};
-  const double kk[3] = {g.k0, g.k1, g.k2};
-  int64_t idx[D];
-  idx[D - 1] = q % g.h;                                 // last axis: 0 .. n/2, never negative
-  int64_t rest = q / g.h;
-  for (int j = D - 2; j >= 0; --j) {
-    idx[j] = rest % nn[j];
-    rest /= nn[j];
-  }
+  int64_t k[D];
+  tfs::wave_numbers<D>(g, q, k);
   bool band = true;
   for (int j = 0; j < D; ++j) {
-    const int64_t k = (j == D - 1 || idx[j] < (nn[j] + 1) / 2) ? idx[j] : idx[j] - nn[j];
-    const int64_t a = k < 0 ? -k : k;
-    band = band && 3 * a < nn[j];
-    xi[j] = kk[j] * (double)k;
+    const int64_t a = k[j] < 0 ? -k[j] : k[j];
+    band = band && 3 * a < tfs::axis_n(g, j);
+    xi[j] = tfs::axis_k0(g, j) * (double)k[j];
   }
   return band;
 }

@@ -1,0 +1,661 @@
+// Stress update with the MFP equation's transport terms (advection u.grad and centre-of-mass
+// diffusion eps Laplace) inside the implicit operator of the BDF2 scheme and its SDIRK2 start
+// (Sec. 4.1, eq. FP_discrete), on a periodic grid with u and kappa varying in space.
+//
+// A step: the modes advance pointwise with the split BDF2 kernel (which also leaves each
+// point's right-hand side R and history combination G), L's transport part acts on G, and
+// the coupled system (a I - b K(kappa~(x)) + b T) X = rhs is solved by splitting iterations
+// preconditioned by its constant-coefficient part, which is diagonal per Fourier
+// coefficient.  The kernels here are single passes over the grid or the spectrum; the
+// transforms are hipFFT.
+#include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
+
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <string>
+
+#include "tfs_device.h"
+#include "tfs_internal.h"
+#include "tfs_spectral.h"
+#include "tfs_transport.h"
+
+namespace tfs {
+tfs_status set_error(tfs_status s, const char* msg);   // tfs_host.cpp
+}
+
+struct tfs_transport_s {
+  int dim = 0, device = 0, iters = 0;
+  int64_t n[3] = {1, 1, 1};
+  double k0[3] = {0, 0, 0};
+  double eps = 0.0;
+  int64_t npoints = 0, nc = 0, stride = 0;
+  hipfftHandle fwd = 0, inv = 0;
+  bool have_fwd = false, have_inv = false;
+  // grid planes: right-hand side, SDIRK2 stage-1 value, fluctuation, iterate, gradients (c d)
+  double *rg = nullptr, *x1g = nullptr, *fg = nullptr, *xg = nullptr, *dg = nullptr;
+  // spectral planes: right-hand side, iterate, fluctuation, extra term, inverse inputs (c + c d)
+  double2 *rh = nullptr, *xh = nullptr, *fh = nullptr, *eh = nullptr, *iv = nullptr;
+  double *part = nullptr, *mean = nullptr;   // spatial means of kappa~ (d*d) and u~ (d)
+};
+
+namespace {
+
+using tfs::SpecGeom;
+using tfs::set_error;
+using namespace tfs::dev;
+
+constexpr int kTBlock = 256;
+constexpr int kMeanBlocks = 256;
+
+tfs_status hipfft_fail(hipfftResult r, const char* what) {
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "%s failed (hipfftResult %d)", what, (int)r);
+  return set_error(TFS_EHIP, buf);
+}
+
+tfs_status hip_fail(hipError_t e, const char* what) {
+  char buf[200];
+  std::snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+  return set_error(TFS_EHIP, buf);
+}
+
+// The field levels of a step: kappa~ = fa ka + fb kb, u~ = fa ua + fb ub (kb, ub may be null).
+struct Lev {
+  const double *ka, *kb, *ua, *ub;
+  double fa, fb;
+};
+
+template <int D>
+__device__ __forceinline__ void level_at(const Lev& L, int64_t st, int64_t p, double (&k)[D * D], double (&u)[D]) {
+#pragma unroll
+  for (int q = 0; q < D * D; ++q) k[q] = L.fa * L.ka[q * st + p] + (L.kb ? L.fb * L.kb[q * st + p] : 0.0);
+#pragma unroll
+  for (int j = 0; j < D; ++j) u[j] = L.fa * L.ua[j * st + p] + (L.ub ? L.fb * L.ub[j * st + p] : 0.0);
+}
+
+// Block sums of kappa~ and u~ (d*d + d quantities) over a grid-stride range of points.
+template <int D>
+__global__ __launch_bounds__(kTBlock) void mean_partial_kernel(Lev L, int64_t npoints, int64_t st, double* part) {
+  constexpr int NQ = D * D + D;
+  __shared__ double red[kTBlock];
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * kTBlock + threadIdx.x; p < npoints; p += (int64_t)gridDim.x * kTBlock) {
+    double k[D * D], u[D];
+    level_at<D>(L, st, p, k, u);
+#pragma unroll
+    for (int q = 0; q < D * D; ++q) acc[q] += k[q];
+#pragma unroll
+    for (int j = 0; j < D; ++j) acc[D * D + j] += u[j];
+  }
+  for (int q = 0; q < NQ; ++q) {
+    red[threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = kTBlock / 2; h > 0; h /= 2) {
+      if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x * NQ + q] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void mean_finish_kernel(const double* part, int nblocks, int nq, double inv_P, double* mean) {
+  const int q = threadIdx.x;
+  if (q >= nq) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += part[b * nq + q];
+  mean[q] = s * inv_P;
+}
+
+// SDIRK2 stage 1: R = X^0 + src1 (kappa + kappa^T).
+template <int D>
+__global__ __launch_bounds__(kTBlock) void start_rhs1_kernel(const double* X0, const double* ka, double src1,
+                                                             int64_t npoints, int64_t st, double* R) {
+  constexpr int C = Sym<D>::C;
+  for (int64_t p = (int64_t)blockIdx.x * kTBlock + threadIdx.x; p < npoints; p += (int64_t)gridDim.x * kTBlock) {
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+      R[s * st + p] = X0[s * st + p] + src1 * (ka[(i * D + j) * st + p] + ka[(j * D + i) * st + p]);
+    }
+  }
+}
+
+// SDIRK2 stage 2, pointwise part: R = X^0 + sigma1 (K(kappa) X1 - X1/De) + sigma2 (kappa + kappa^T).
+template <int D>
+__global__ __launch_bounds__(kTBlock) void start_rhs2_kernel(const double* X0, const double* X1, const double* ka,
+                                                             double sigma1, double sigma2, double inv_De,
+                                                             int64_t npoints, int64_t st, double* R) {
+  constexpr int C = Sym<D>::C;
+  for (int64_t p = (int64_t)blockIdx.x * kTBlock + threadIdx.x; p < npoints; p += (int64_t)gridDim.x * kTBlock) {
+    double k[D * D], x1[C], kx[C];
+#pragma unroll
+    for (int q = 0; q < D * D; ++q) k[q] = ka[q * st + p];
+#pragma unroll
+    for (int s = 0; s < C; ++s) x1[s] = X1[s * st + p];
+    apply_K<D>(k, x1, kx);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      const int i = Sym<D>::i(s), j = Sym<D>::j(s);
+      R[s * st + p] = X0[s * st + p] + sigma1 * (kx[s] - inv_De * x1[s]) + sigma2 * (k[i * D + j] + k[j * D + i]);
+    }
+  }
+}
+
+// out = base + coef u~ . grad E (the gradient planes dg[(s d + j)] of the c fields E).
+template <int D>
+__global__ __launch_bounds__(kTBlock) void advect_add_kernel(const double* base, const double* dg, Lev L, double coef,
+                                                             int64_t npoints, int64_t st, double* out) {
+  constexpr int C = Sym<D>::C;
+  for (int64_t p = (int64_t)blockIdx.x * kTBlock + threadIdx.x; p < npoints; p += (int64_t)gridDim.x * kTBlock) {
+    double k[D * D], u[D];
+    level_at<D>(L, st, p, k, u);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) a = fma(u[j], dg[(s * D + j) * st + p], a);
+      out[s * st + p] = base[s * st + p] + coef * a;
+    }
+  }
+}
+
+// The variable part of the operator on the iterate: f = -b K(kappa~ - kappa_bar) X +
+// b (u~ - u_bar) . grad X.
+template <int D>
+__global__ __launch_bounds__(kTBlock) void fluct_kernel(const double* X, const double* dg, Lev L, const double* mean,
+                                                        double b, int64_t npoints, int64_t st, double* f) {
+  constexpr int C = Sym<D>::C;
+  for (int64_t p = (int64_t)blockIdx.x * kTBlock + threadIdx.x; p < npoints; p += (int64_t)gridDim.x * kTBlock) {
+    double k[D * D], u[D], x[C], kx[C];
+    level_at<D>(L, st, p, k, u);
+#pragma unroll
+    for (int q = 0; q < D * D; ++q) k[q] -= mean[q];
+#pragma unroll
+    for (int j = 0; j < D; ++j) u[j] -= mean[D * D + j];
+#pragma unroll
+    for (int s = 0; s < C; ++s) x[s] = X[s * st + p];
+    apply_K<D>(k, x, kx);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) a = fma(u[j], dg[(s * D + j) * st + p], a);
+      f[s * st + p] = b * (a - kx[s]);
+    }
+  }
+}
+
+// xi (for |xi|^2, the Nyquist wave number kept) and xd (first derivatives, Nyquist zero).
+template <int D>
+__device__ __forceinline__ void spec_xi(const SpecGeom& g, int64_t q, double (&xi)[D], double (&xd)[D]) {
+  int64_t k[D];
+  tfs::wave_numbers<D>(g, q, k);
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const int64_t n = tfs::axis_n(g, j);
+    const bool nyq = (n % 2 == 0) && (k[j] == n / 2 || k[j] == -n / 2);
+    xi[j] = tfs::axis_k0(g, j) * (double)k[j];
+    xd[j] = nyq ? 0.0 : xi[j];
+  }
+}
+
+__device__ __forceinline__ double2 c_i(double s, double2 z) { return make_double2(-s * z.y, s * z.x); }
+
+// Derivative planes i xd_j E_s at iv[(C + s D + j)] (and E itself at iv[s] when self), with
+// E an unnormalised forward transform (scaled by inv_P = 1/points, so that the inverse
+// transforms give grid values).
+template <int D>
+__global__ __launch_bounds__(kTBlock) void deriv_kernel(SpecGeom g, int64_t nc, double inv_P, const double2* E,
+                                                        bool self, double2* iv) {
+  constexpr int C = Sym<D>::C;
+  for (int64_t q = (int64_t)blockIdx.x * kTBlock + threadIdx.x; q < nc; q += (int64_t)gridDim.x * kTBlock) {
+    double xi[D], xd[D];
+    spec_xi<D>(g, q, xi, xd);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      double2 e = E[s * nc + q];
+      e.x *= inv_P;
+      e.y *= inv_P;
+      if (self) iv[s * nc + q] = e;
+#pragma unroll
+      for (int j = 0; j < D; ++j) iv[(C + s * D + j) * nc + q] = c_i(xd[j], e);
+    }
+  }
+}
+
+// rh += ae |xi|^2 E  (ae = alpha eps: the diffusion part of T applied to E, in the spectrum).
+template <int D>
+__global__ __launch_bounds__(kTBlock) void diffuse_add_kernel(SpecGeom g, int64_t nc, const double2* E, double ae,
+                                                              double2* rh) {
+  constexpr int C = Sym<D>::C;
+  for (int64_t q = (int64_t)blockIdx.x * kTBlock + threadIdx.x; q < nc; q += (int64_t)gridDim.x * kTBlock) {
+    double xi[D], xd[D];
+    spec_xi<D>(g, q, xi, xd);
+    double x2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) x2 = fma(xi[j], xi[j], x2);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      const double2 e = E[s * nc + q];
+      double2 r = rh[s * nc + q];
+      r.x = fma(ae * x2, e.x, r.x);
+      r.y = fma(ae * x2, e.y, r.y);
+      rh[s * nc + q] = r;
+    }
+  }
+}
+
+// Solve (Mr + i w I) z = r for complex z (Gaussian elimination, partial pivoting by modulus).
+template <int N>
+__device__ __forceinline__ void solve_shifted(double (&Mr)[N][N], double w, double2 (&r)[N]) {
+  double2 A[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) A[i][j] = make_double2(Mr[i][j], i == j ? w : 0.0);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    int piv = j;
+    double best = A[j][j].x * A[j][j].x + A[j][j].y * A[j][j].y;
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      const double v = A[i][j].x * A[i][j].x + A[i][j].y * A[i][j].y;
+      if (v > best) { best = v; piv = i; }
+    }
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      if (i == piv) {
+#pragma unroll
+        for (int t = 0; t < N; ++t) { const double2 h = A[j][t]; A[j][t] = A[i][t]; A[i][t] = h; }
+        const double2 h = r[j]; r[j] = r[i]; r[i] = h;
+      }
+    }
+    const double2 d = A[j][j];
+    const double dn = 1.0 / (d.x * d.x + d.y * d.y);
+    const double2 inv = make_double2(d.x * dn, -d.y * dn);
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      const double2 a = A[i][j];
+      const double2 l = make_double2(a.x * inv.x - a.y * inv.y, a.x * inv.y + a.y * inv.x);
+#pragma unroll
+      for (int t = j + 1; t < N; ++t) {
+        const double2 u = A[j][t];
+        A[i][t].x -= l.x * u.x - l.y * u.y;
+        A[i][t].y -= l.x * u.y + l.y * u.x;
+      }
+      r[i].x -= l.x * r[j].x - l.y * r[j].y;
+      r[i].y -= l.x * r[j].y + l.y * r[j].x;
+    }
+  }
+#pragma unroll
+  for (int j = N - 1; j >= 0; --j) {
+    double2 acc = r[j];
+#pragma unroll
+    for (int t = j + 1; t < N; ++t) {
+      acc.x -= A[j][t].x * r[t].x - A[j][t].y * r[t].y;
+      acc.y -= A[j][t].x * r[t].y + A[j][t].y * r[t].x;
+    }
+    const double2 d = A[j][j];
+    const double dn = 1.0 / (d.x * d.x + d.y * d.y);
+    r[j] = make_double2((acc.x * d.x + acc.y * d.y) * dn, (acc.y * d.x - acc.x * d.y) * dn);
+  }
+}
+
+struct PrecondArgs {
+  SpecGeom g;
+  int64_t nc;
+  double inv_P;             // rh and fh are unnormalised forward transforms
+  const double2* rh;        // right-hand side coefficients [C][nc]
+  const double2* fh;        // variable part's coefficients, or null
+  const double* mean;       // kappa_bar (d*d), u_bar (d)
+  double a, b, eps;
+  double2* xh;              // new iterate [C][nc]
+  double2* iv;              // inverse-transform inputs: X (C planes), i xd_j X (C D planes)
+};
+
+// X_hat = P(xi)^{-1} (rh - fh) / points, P(xi) = (a + b eps |xi|^2 + i b xd.u_bar) I - b K(kappa_bar).
+template <int D>
+__global__ __launch_bounds__(kTBlock) void precond_kernel(const PrecondArgs A) {
+  constexpr int C = Sym<D>::C;
+  double kb[D * D], ub[D];
+#pragma unroll
+  for (int q = 0; q < D * D; ++q) kb[q] = A.mean[q];
+#pragma unroll
+  for (int j = 0; j < D; ++j) ub[j] = A.mean[D * D + j];
+  for (int64_t q = (int64_t)blockIdx.x * kTBlock + threadIdx.x; q < A.nc; q += (int64_t)gridDim.x * kTBlock) {
+    double xi[D], xd[D];
+    spec_xi<D>(A.g, q, xi, xd);
+    double x2 = 0.0, xu = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      x2 = fma(xi[j], xi[j], x2);
+      xu = fma(xd[j], ub[j], xu);
+    }
+    double2 r[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      r[s] = A.rh[s * A.nc + q];
+      if (A.fh) {
+        const double2 f = A.fh[s * A.nc + q];
+        r[s].x -= f.x;
+        r[s].y -= f.y;
+      }
+      r[s].x *= A.inv_P;
+      r[s].y *= A.inv_P;
+    }
+    double M[C][C];
+    build_M<D>(kb, A.a + A.b * A.eps * x2, A.b, M);
+    solve_shifted<C>(M, A.b * xu, r);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      A.xh[s * A.nc + q] = r[s];
+      A.iv[s * A.nc + q] = r[s];
+#pragma unroll
+      for (int j = 0; j < D; ++j) A.iv[(C + s * D + j) * A.nc + q] = c_i(xd[j], r[s]);
+    }
+  }
+}
+
+// tau = (gamma/dt) (eta X - G), G read from tau.
+template <int D>
+__global__ __launch_bounds__(kTBlock) void bdf2_finish_kernel(const double* X, double* tau, double eta, double ts,
+                                                              int64_t npoints, int64_t st) {
+  constexpr int C = Sym<D>::C;
+  for (int64_t p = (int64_t)blockIdx.x * kTBlock + threadIdx.x; p < npoints; p += (int64_t)gridDim.x * kTBlock) {
+#pragma unroll
+    for (int s = 0; s < C; ++s) tau[s * st + p] = ts * (eta * X[s * st + p] - tau[s * st + p]);
+  }
+}
+
+// SDIRK2 start, pointwise end: tau^1 = gamma (theta X2 - hr X1); modes Y_k^0 = -c_k X^0 and
+// Y_k^1 = u_k X1 + v_k X2 in the plan's tiled layout.
+template <int D, typename MT>
+__global__ __launch_bounds__(kTBlock) void start_finish_kernel(const double* X0, const double* X1, const double* X2,
+                                                               const double* coef, int m, double gamma,
+                                                               double theta, double hr, double* tau, MT* Y0, MT* Y1,
+                                                               int64_t npoints, int64_t st, int64_t T) {
+  constexpr int C = Sym<D>::C;
+  for (int64_t p = (int64_t)blockIdx.x * kTBlock + threadIdx.x; p < npoints; p += (int64_t)gridDim.x * kTBlock) {
+    double x0[C], x1[C], x2[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      x0[s] = X0[s * st + p];
+      x1[s] = X1[s * st + p];
+      x2[s] = X2[s * st + p];
+      if (tau) tau[s * st + p] = gamma * (theta * x2[s] - hr * x1[s]);
+    }
+    const int64_t base = (p / T) * m * C * T + p % T;
+    for (int k = 0; k < m; ++k) {
+      const double ck = coef[tfs::kRowC * m + k], uk = coef[tfs::kRowU * m + k], vk = coef[tfs::kRowV * m + k];
+#pragma unroll
+      for (int s = 0; s < C; ++s) {
+        const int64_t e = base + ((int64_t)k * C + s) * T;
+        Y0[e] = (MT)(-ck * x0[s]);
+        Y1[e] = (MT)(uk * x1[s] + vk * x2[s]);
+      }
+    }
+  }
+}
+
+int blocks_for(int64_t work) {
+  const int64_t b = (work + kTBlock - 1) / kTBlock;
+  const int64_t cap = 256 * 16;
+  return (int)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+SpecGeom geom(const tfs_transport_s* s) {
+  SpecGeom g;
+  g.n0 = s->n[0];
+  g.n1 = s->n[1];
+  g.n2 = s->n[2];
+  g.h = s->n[s->dim - 1] / 2 + 1;
+  g.k0 = s->k0[0];
+  g.k1 = s->k0[1];
+  g.k2 = s->k0[2];
+  return g;
+}
+
+tfs_status forward_planes(tfs_transport_s* s, const double* grid, double2* spec, int count) {
+  for (int i = 0; i < count; ++i) {
+    const hipfftResult r = hipfftExecD2Z(s->fwd, const_cast<double*>(grid) + (int64_t)i * s->stride,
+                                         (hipfftDoubleComplex*)(spec + (int64_t)i * s->nc));
+    if (r != HIPFFT_SUCCESS) return hipfft_fail(r, "hipfftExecD2Z");
+  }
+  return TFS_OK;
+}
+
+tfs_status inverse_planes(tfs_transport_s* s, double2* spec, double* grid, int count) {
+  for (int i = 0; i < count; ++i) {
+    const hipfftResult r = hipfftExecZ2D(s->inv, (hipfftDoubleComplex*)(spec + (int64_t)i * s->nc),
+                                         grid + (int64_t)i * s->stride);
+    if (r != HIPFFT_SUCCESS) return hipfft_fail(r, "hipfftExecZ2D");
+  }
+  return TFS_OK;
+}
+
+// Solve (a I - b K(kappa~) + b T) X = rhs with rhs = F^{-1}[F(rg) + alpha eps |xi|^2 E_hat]
+// (E_hat = s->eh when extra), X into out.
+template <int D>
+tfs_status solve(tfs_transport_s* s, hipStream_t st, const Lev& L, double a, double b, bool extra, double alpha,
+                 double* out) {
+  constexpr int C = Sym<D>::C;
+  const SpecGeom g = geom(s);
+  const int bs = blocks_for(s->nc), bp = blocks_for(s->npoints);
+  tfs_status r = forward_planes(s, s->rg, s->rh, C);
+  if (r != TFS_OK) return r;
+  if (extra) hipLaunchKernelGGL(diffuse_add_kernel<D>, dim3(bs), dim3(kTBlock), 0, st, g, s->nc, s->eh, alpha * s->eps, s->rh);
+  PrecondArgs A;
+  A.g = g;
+  A.nc = s->nc;
+  A.inv_P = 1.0 / (double)s->npoints;
+  A.rh = s->rh;
+  A.fh = nullptr;
+  A.mean = s->mean;
+  A.a = a;
+  A.b = b;
+  A.eps = s->eps;
+  A.xh = s->xh;
+  A.iv = s->iv;
+  hipLaunchKernelGGL(precond_kernel<D>, dim3(bs), dim3(kTBlock), 0, st, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "precond_kernel launch");
+  A.fh = s->fh;
+  for (int it = 0; it < s->iters; ++it) {
+    if ((r = inverse_planes(s, s->iv, s->xg, C)) != TFS_OK) return r;
+    if ((r = inverse_planes(s, s->iv + (int64_t)C * s->nc, s->dg, C * D)) != TFS_OK) return r;
+    hipLaunchKernelGGL(fluct_kernel<D>, dim3(bp), dim3(kTBlock), 0, st, s->xg, s->dg, L, s->mean, b, s->npoints,
+                       s->stride, s->fg);
+    if ((r = forward_planes(s, s->fg, s->fh, C)) != TFS_OK) return r;
+    hipLaunchKernelGGL(precond_kernel<D>, dim3(bs), dim3(kTBlock), 0, st, A);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "solver iteration launch");
+  }
+  return inverse_planes(s, s->iv, out, C);
+}
+
+// grad of the c fields whose coefficients are in s->eh, into s->dg.
+template <int D>
+tfs_status gradient_of_extra(tfs_transport_s* s, hipStream_t st) {
+  constexpr int C = Sym<D>::C;
+  hipLaunchKernelGGL(deriv_kernel<D>, dim3(blocks_for(s->nc)), dim3(kTBlock), 0, st, geom(s), s->nc,
+                     1.0 / (double)s->npoints, s->eh, false, s->iv);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "deriv_kernel launch");
+  return inverse_planes(s, s->iv + (int64_t)C * s->nc, s->dg, C * D);
+}
+
+template <int D, typename MT>
+tfs_status step_d(tfs_transport_s* s, const tfs_plan_s* p, int64_t n, const Lev& L, const tfs::Levels& lv,
+                  double* tau) {
+  constexpr int C = Sym<D>::C;
+  hipStream_t st = p->stream;
+  const int bp = blocks_for(s->npoints);
+  const int64_t P = s->npoints, sd = s->stride;
+  hipLaunchKernelGGL(mean_partial_kernel<D>, dim3(kMeanBlocks), dim3(kTBlock), 0, st, L, P, sd, s->part);
+  hipLaunchKernelGGL(mean_finish_kernel, dim3(1), dim3(64), 0, st, s->part, kMeanBlocks, D * D + D, 1.0 / (double)P,
+                     s->mean);
+  tfs_status r;
+  if (n == 0) {
+    const double hgt = p->hg * p->theta, inv_De = 1.0 / p->De;
+    hipLaunchKernelGGL(start_rhs1_kernel<D>, dim3(bp), dim3(kTBlock), 0, st, lv.Xn, L.ka, hgt, P, sd, s->rg);
+    if ((r = solve<D>(s, st, L, 1.0 + hgt * inv_De, hgt, false, 0.0, s->x1g)) != TFS_OK) return r;
+    // stage 2: X^0 + sigma1 (K X1 - X1/De - T X1) + sigma2 S
+    if ((r = forward_planes(s, s->x1g, s->eh, C)) != TFS_OK) return r;
+    if ((r = gradient_of_extra<D>(s, st)) != TFS_OK) return r;
+    hipLaunchKernelGGL(start_rhs2_kernel<D>, dim3(bp), dim3(kTBlock), 0, st, lv.Xn, s->x1g, L.ka, p->sigma1,
+                       p->sigma2, inv_De, P, sd, s->rg);
+    hipLaunchKernelGGL(advect_add_kernel<D>, dim3(bp), dim3(kTBlock), 0, st, s->rg, s->dg, L, -p->sigma1, P, sd,
+                       s->rg);
+    if ((r = solve<D>(s, st, L, 1.0 + hgt * inv_De, hgt, true, -p->sigma1, lv.Xo)) != TFS_OK) return r;
+    hipLaunchKernelGGL((start_finish_kernel<D, MT>), dim3(bp), dim3(kTBlock), 0, st, lv.Xn, s->x1g, lv.Xo, p->d_coef,
+                       p->m, p->gamma, p->theta, p->hr, tau, static_cast<MT*>(lv.Ym0), static_cast<MT*>(lv.Yo), P, sd,
+                       p->tile);
+  } else {
+    // modes, each point's R (into X^{n+1}) and G (into tau)
+    hipError_t e = tfs::launch_bdf2_split(p, n, L.ka, L.kb, lv, tau);
+    if (e != hipSuccess) return hip_fail(e, "split step launch");
+    // rhs = R + T G
+    if ((r = forward_planes(s, tau, s->eh, C)) != TFS_OK) return r;
+    if ((r = gradient_of_extra<D>(s, st)) != TFS_OK) return r;
+    hipLaunchKernelGGL(advect_add_kernel<D>, dim3(bp), dim3(kTBlock), 0, st, lv.Xo, s->dg, L, 1.0, P, sd, s->rg);
+    if ((r = solve<D>(s, st, L, p->a_diag, p->eta, true, 1.0, lv.Xo)) != TFS_OK) return r;
+    hipLaunchKernelGGL(bdf2_finish_kernel<D>, dim3(bp), dim3(kTBlock), 0, st, lv.Xo, tau, p->eta, p->tau_scale, P,
+                       sd);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? TFS_OK : hip_fail(e, "transport step launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+tfs_status tfs_transport_create(int dim, const int64_t* shape, const double* extent, double eps, int64_t stride,
+                                int iters, tfs_transport* out) {
+  if (!out) return set_error(TFS_EINVAL, "null output handle");
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return set_error(TFS_EINVAL, "dim must be 2 or 3");
+  if (!shape || !extent) return set_error(TFS_EINVAL, "null shape or extent");
+  if (!(std::isfinite(eps) && eps >= 0.0)) return set_error(TFS_EINVAL, "eps must be finite and >= 0");
+  if (iters < 0 || iters > 10000) return set_error(TFS_EINVAL, "iters must be in [0, 10000]");
+  int64_t P = 1;
+  for (int j = 0; j < dim; ++j) {
+    if (shape[j] < 2 || shape[j] > (1 << 20)) return set_error(TFS_EINVAL, "every axis needs 2 .. 2^20 points");
+    if (!(std::isfinite(extent[j]) && extent[j] > 0.0)) return set_error(TFS_EINVAL, "extent must be finite and > 0");
+    P *= shape[j];
+  }
+  if (P > (int64_t)1 << 30) return set_error(TFS_EINVAL, "more than 2^30 grid points");
+  if (stride < P || stride > INT32_MAX) return set_error(TFS_EINVAL, "stride must be >= the number of points and < 2^31");
+  tfs_transport_s* s = new (std::nothrow) tfs_transport_s;
+  if (!s) return set_error(TFS_ENOMEM, "host allocation failed");
+  s->dim = dim;
+  s->iters = iters;
+  s->eps = eps;
+  (void)hipGetDevice(&s->device);
+  for (int j = 0; j < dim; ++j) {
+    s->n[j] = shape[j];
+    s->k0[j] = 2.0 * M_PI / extent[j];
+  }
+  s->npoints = P;
+  s->stride = stride;
+  s->nc = P / shape[dim - 1] * (shape[dim - 1] / 2 + 1);
+  const int c = dim * (dim + 1) / 2, cd = c * dim;
+  const size_t gp = sizeof(double) * stride, sp = sizeof(double2) * s->nc;
+  hipError_t e = hipMalloc((void**)&s->rg, gp * c);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->x1g, gp * c);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->fg, gp * c);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->xg, gp * c);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->dg, gp * cd);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->rh, sp * c);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->xh, sp * c);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->fh, sp * c);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->eh, sp * c);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->iv, sp * (c + cd));
+  if (e == hipSuccess) e = hipMalloc((void**)&s->part, sizeof(double) * kMeanBlocks * (dim * dim + dim));
+  if (e == hipSuccess) e = hipMalloc((void**)&s->mean, sizeof(double) * (dim * dim + dim));
+  tfs_status st = TFS_OK;
+  if (e != hipSuccess) st = set_error(TFS_ENOMEM, "device allocation of the transport buffers failed");
+  int nn[3];
+  for (int j = 0; j < dim; ++j) nn[j] = (int)shape[j];
+  if (st == TFS_OK) {
+    hipfftResult r = hipfftPlanMany(&s->fwd, dim, nn, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_D2Z, 1);
+    s->have_fwd = r == HIPFFT_SUCCESS;
+    if (r == HIPFFT_SUCCESS) {
+      r = hipfftPlanMany(&s->inv, dim, nn, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_Z2D, 1);
+      s->have_inv = r == HIPFFT_SUCCESS;
+    }
+    if (r != HIPFFT_SUCCESS) st = hipfft_fail(r, "hipfftPlanMany");
+  }
+  if (st != TFS_OK) {
+    const std::string keep = tfs_last_error();
+    tfs_transport_destroy(s);
+    return set_error(st, keep.c_str());
+  }
+  *out = s;
+  return TFS_OK;
+}
+
+tfs_status tfs_transport_destroy(tfs_transport s) {
+  if (!s) return TFS_OK;
+  (void)hipDeviceSynchronize();
+  if (s->have_fwd) hipfftDestroy(s->fwd);
+  if (s->have_inv) hipfftDestroy(s->inv);
+  for (double* b : {s->rg, s->x1g, s->fg, s->xg, s->dg, s->part, s->mean})
+    if (b) (void)hipFree(b);
+  for (double2* b : {s->rh, s->xh, s->fh, s->eh, s->iv})
+    if (b) (void)hipFree(b);
+  delete s;
+  return TFS_OK;
+}
+
+tfs_status tfs_transport_step(tfs_transport s, tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b,
+                              const double* u_a, const double* u_b, double* X, void* Y, double* tau) {
+  if (!s || !p) return set_error(TFS_EINVAL, "null transport object or plan");
+  if (p->d != s->dim || p->npoints != s->npoints || p->stride != s->stride)
+    return set_error(TFS_EINVAL, "plan does not match the transport object (dim, npoints, stride)");
+  if (p->device != s->device) return set_error(TFS_EINVAL, "plan and transport object live on different devices");
+  if (p->scheme != TFS_SCHEME_BDF2) return set_error(TFS_EUNSUPPORTED, "transport steps need a BDF2 plan");
+  if (p->sp_rate || p->sp_source >= 0) return set_error(TFS_EUNSUPPORTED, "transport steps need a pointwise plan");
+  if (n < 0 || n >= p->max_steps) return set_error(TFS_EINVAL, "step index out of range");
+  if (!kappa_a || !u_a || !X || !Y || !tau) return set_error(TFS_EINVAL, "null kappa_a, u_a, X, Y or tau");
+  if (kappa_b && !u_b) return set_error(TFS_EINVAL, "u_b is needed with kappa_b");
+  const hipfftResult fr = hipfftSetStream(s->fwd, p->stream);
+  const hipfftResult ir = hipfftSetStream(s->inv, p->stream);
+  if (fr != HIPFFT_SUCCESS || ir != HIPFFT_SUCCESS) return hipfft_fail(fr != HIPFFT_SUCCESS ? fr : ir, "hipfftSetStream");
+  Lev L;
+  L.ka = kappa_a;
+  L.ua = u_a;
+  const bool ex = kappa_b && n >= 1;
+  L.kb = ex ? kappa_b : nullptr;
+  L.ub = ex ? u_b : nullptr;
+  L.fa = ex ? 2.0 : 1.0;
+  L.fb = ex ? -1.0 : 0.0;
+  // the rings as tfs_step reads them
+  const int64_t xs = (int64_t)p->c * p->stride, ys = (int64_t)p->m * p->c * p->stride;
+  const size_t eb = p->precision == TFS_FP64 ? 8 : 4;
+  char* Yb = static_cast<char*>(Y);
+  tfs::Levels lv;
+  const int sn = (int)(n % 2), sm = 1 - sn;
+  if (n == 0) {
+    lv.Xn = X;
+    lv.Xo = X + xs;
+    lv.Ym0 = Yb;
+    lv.Yo = Yb + ys * eb;
+  } else {
+    lv.Xn = X + sn * xs;
+    lv.Xm = X + sm * xs;
+    lv.Xo = X + sm * xs;
+    lv.Yn = Yb + sn * ys * eb;
+    lv.Ym = Yb + sm * ys * eb;
+    lv.Yo = Yb + sm * ys * eb;
+  }
+  if (p->precision == TFS_FP64)
+    return s->dim == 2 ? step_d<2, double>(s, p, n, L, lv, tau) : step_d<3, double>(s, p, n, L, lv, tau);
+  return s->dim == 2 ? step_d<2, float>(s, p, n, L, lv, tau) : step_d<3, float>(s, p, n, L, lv, tau);
+}
+
+}  // extern "C"

@@ -22,7 +22,7 @@ def header_functions(name="tfs.h"):
 
 def test_library_exports_every_declared_function():
     headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
-    assert headers == ["tfs.h", "tfs_ns.h"]
+    assert headers == ["tfs.h", "tfs_ns.h", "tfs_transport.h"]
     names = sorted(set(n for h in headers for n in header_functions(h)))
     assert len(names) >= 15
     L = tfs.lib()

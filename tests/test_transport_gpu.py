@@ -1,0 +1,129 @@
+"""Stress update with the MFP equation's transport terms on the GPU (tfs_transport_step:
+advection by a velocity field and centre-of-mass diffusion inside the implicit operator,
+u and kappa varying in space), against the spatial oracle (oracle/mfp.py: dense operators
+over the grid, direct solves)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mfp
+from oracle import soe as osoe
+from paper_2411_17294_amd import tfs
+from paper_2411_17294_amd.transport import Transport
+from tests.gpu_helpers import relerr
+
+pytestmark = pytest.mark.gpu
+
+BAR = {"fp64": 1e-12, "fp32_modes": 1e-5}
+
+
+def fields(d, shape, extent, nlev, seed, u_amp=0.3, k_amp=0.3, uniform=False):
+    """Smooth periodic u [nlev][d][P] and kappa [nlev][d*d][P] (a mean plus one travelling
+    Fourier term per component), or uniform ones."""
+    P = int(np.prod(shape))
+    rng = np.random.default_rng(seed)
+    axes = [np.arange(n) * (L / n) for n, L in zip(shape, extent)]
+    xs = [g.reshape(P) for g in np.meshgrid(*axes, indexing="ij")]
+    u0, k0 = rng.standard_normal(d) * 0.5, rng.standard_normal(d * d) * 0.4
+    u = np.empty((nlev, d, P))
+    k = np.empty((nlev, d * d, P))
+    terms = []
+    for _ in range(d + d * d):
+        kv = [2 * math.pi * int(rng.integers(-2, 3)) / L for L in extent]
+        terms.append((kv, rng.uniform(0, 2 * math.pi), rng.uniform(0.5, 1.0)))
+    for lv in range(nlev):
+        t = 0.01 * lv
+        for q in range(d + d * d):
+            kv, ph, a = terms[q]
+            wave = 0.0 if uniform else a * np.sin(sum(kv[j] * xs[j] for j in range(d)) + ph + 3.0 * t)
+            if q < d:
+                u[lv, q] = u0[q] + u_amp * wave
+            else:
+                k[lv, q - d] = k0[q - d] + k_amp * wave
+    return u, k
+
+
+def gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, extrap, iters):
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec)
+    tr = Transport(plan, shape, extent, eps, iters)
+    st = plan.stride
+    X, Y, tau, _ = plan.alloc()
+    X[0, :, :P] = torch.from_numpy(X0).cuda()
+    dev = lambda a, rows: torch.nn.functional.pad(torch.from_numpy(np.ascontiguousarray(a)), (0, st - P)).cuda() \
+        .reshape(rows, st).contiguous()
+    kl = [dev(kap[i], d * d) for i in range(kap.shape[0])]
+    ul = [dev(u[i], d) for i in range(u.shape[0])]
+    for n in range(N):
+        if extrap:
+            tr.step(n, kl[n], kl[n - 1] if n >= 1 else None, ul[n], ul[n - 1] if n >= 1 else None, X, Y, tau)
+        else:
+            tr.step(n, kl[n + 1], None, ul[n + 1], None, X, Y, tau)
+    torch.cuda.synchronize()
+    o = torch.zeros((plan.m, c, st), dtype=torch.float64, device="cuda")
+    plan.modes_to_plain(N % 2, X, Y, o)
+    torch.cuda.synchronize()
+    return {"X": np.stack([X[N % 2, :, :P].cpu().numpy(), X[(N - 1) % 2, :, :P].cpu().numpy()]),
+            "tau": tau[:, :P].cpu().numpy(), "modes": o[:, :, :P].cpu().numpy()}
+
+
+CASES = [(2, (6, 8), (1.0, 2.0)), (2, (7, 6), (1.5, 1.0)), (3, (4, 4, 6), (1.0, 2.0, 3.0))]
+
+
+@pytest.mark.parametrize("extrap", [True, False])
+@pytest.mark.parametrize("N", [1, 2, 9])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d,shape,extent", CASES)
+def test_transport_step_matches_spatial_oracle(d, shape, extent, prec, N, extrap):
+    """u and kappa varying in space and time; 40 splitting iterations per solve."""
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    De, eta_p, eps, dt = 0.8, 0.1, 0.05, 2e-3
+    w, lam, _ = osoe.soe_fit(0.5, 6, dt, dt * max(N, 2))
+    u, kap = fields(d, shape, extent, N + 1, 50 + d + N)
+    X0 = np.random.default_rng(60 + d).standard_normal((c, P)) * 0.05
+    print(f"transport d={d} shape={shape} {prec} N={N} extrap={extrap}", flush=True)
+    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, extrap, 40)
+    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, extrap=extrap, want_modes=True, u=u)
+    errs = {"X": relerr(g["X"], o["X"]), "tau": relerr(g["tau"], o["tau"]), "modes": relerr(g["modes"], o["modes"][0])}
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert all(v < BAR[prec] for v in errs.values()), errs
+
+
+@pytest.mark.parametrize("d,shape,extent", CASES)
+def test_uniform_fields_need_no_iteration(d, shape, extent):
+    """Uniform u and kappa: the preconditioner is the whole operator, so the solve is exact
+    with no splitting iteration."""
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    N, De, eta_p, eps, dt = 6, 0.8, 0.1, 0.05, 2e-3
+    w, lam, _ = osoe.soe_fit(0.5, 6, dt, dt * N)
+    u, kap = fields(d, shape, extent, N + 1, 70 + d, uniform=True)
+    X0 = np.random.default_rng(71).standard_normal((c, P)) * 0.05
+    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, "fp64", True, 0)
+    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, want_modes=True, u=u)
+    errs = {"X": relerr(g["X"], o["X"]), "tau": relerr(g["tau"], o["tau"])}
+    assert all(v < 1e-12 for v in errs.values()), errs
+
+
+def test_transport_errors():
+    w, lam, _ = osoe.soe_fit(0.5, 4, 1e-3, 1e-2)
+    plan = tfs.Plan(2, 64, w, lam, 0.5, 1.0, 0.1, 1e-3, 4)
+    with pytest.raises(tfs.TfsError):
+        Transport(plan, (8, 8), (1.0, 1.0), -1.0)                   # negative eps
+    tr = Transport(plan, (8, 8), (1.0, 1.0), 0.1, 3)
+    X, Y, tau, _ = plan.alloc()
+    k = torch.zeros((4, plan.stride), dtype=torch.float64, device="cuda")
+    u = torch.zeros((2, plan.stride), dtype=torch.float64, device="cuda")
+    with pytest.raises(tfs.TfsError):
+        tr.step(1, k, k, u, None, X, Y, tau)                          # u_b missing with kappa_b
+    exp_plan = tfs.Plan(2, 64, w, lam, 0.5, 1.0, 0.1, 1e-3, 4, scheme="exp")
+    tr2 = Transport(exp_plan, (8, 8), (1.0, 1.0), 0.1, 3)
+    Xe, Ye, te, _ = exp_plan.alloc()
+    with pytest.raises(tfs.TfsError):
+        tr2.step(0, k, None, u, None, Xe, Ye, te)                    # exponential scheme
+    tr.step(0, k, None, u, None, X, Y, tau)
+    torch.cuda.synchronize()
