@@ -20,7 +20,8 @@
  * 2/3 band |k_j| < n_j/3 of integer wave numbers, so the quadratic term is alias-free and
  * the Nyquist modes stay empty.  Transforms are hipFFT (rocFFT) plans made at creation.
  * g = 1 (BDF1, E f = f^n) at the first step, g = 2 (b = (3/2, -2, 1/2), E f = 2 f^n - f^{n-1})
- * after.  The stress update has no transport terms (tfs.h's pointwise model).
+ * after.  The stress update is tfs.h's pointwise model, or with tfs_ns_set_transport the MFP
+ * equation with its advection and diffusion terms (tfs_transport.h).
  *
  * Layouts (all device memory, caller-owned, FP64):
  *   grid fields    structure-of-arrays, point index = C-order index of the grid point
@@ -41,6 +42,7 @@
 #include <stdint.h>
 
 #include "tfs.h"
+#include "tfs_transport.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -80,6 +82,15 @@ int tfs_ns_batched(tfs_ns ns);
 tfs_status tfs_ns_set_batched(tfs_ns ns, int on);
 
 /*
+ * Stress update of the coupled step: tr = NULL (the default) uses tfs_step, the pointwise
+ * update; otherwise tfs_transport_step(tr, plan, n, kappa^{n+1}, NULL, u^{n+1}, NULL, ...),
+ * which adds the MFP equation's advection by u and centre-of-mass diffusion (eq. FP_discrete
+ * in full).  The solver keeps the handle; tr must outlive its use.  Errors: TFS_EINVAL (null
+ * solver).
+ */
+tfs_status tfs_ns_set_transport(tfs_ns ns, tfs_transport tr);
+
+/*
  * Level 0: from the grid velocity u [d][stride] (overwritten), keep its divergence-free
  * part in the 2/3 band (Sec. 4.1 asks for a solenoidal velocity), store its coefficients
  * in slot 0 of uh, and write u^0 and kappa^0 = grad u^0 back on the grid.  Runs on the
@@ -94,7 +105,8 @@ tfs_status tfs_ns_init(tfs_ns ns, tfs_plan plan, double* u, void* uh, double* ka
  * hold level n (tau = 0 at n = 0: the stress of level 0), uh holds levels n and n-1 (n-1
  * unused at n = 0) and fh slot (n-1) % 2 holds F^{n-1} (unused at n = 0).  The step writes
  * F^n to fh slot n % 2, u^{n+1} to uh slot (n+1) % 2, u and kappa of level n+1 on the grid,
- * and then calls tfs_step(plan, n, kappa, NULL, X, Y, tau, diag).
+ * and then calls tfs_step(plan, n, kappa, NULL, X, Y, tau, diag), or the transport step set
+ * by tfs_ns_set_transport (diag must then be NULL: TFS_EUNSUPPORTED otherwise).
  * Errors: those of tfs_step, TFS_EINVAL (null pointers, mismatched or spatial-form plan),
  * TFS_EHIP.
  */

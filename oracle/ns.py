@@ -30,12 +30,13 @@ the velocity free of aliasing in the quadratic term and of the Nyquist modes.  T
 velocity is also made divergence-free (its gradient part removed).  tau^0 = 0, the
 pointwise scheme's stress at level 0.
 
-The stress update is the pointwise scheme without transport terms (no u.grad or eps
-Laplace acting on the Hermite coefficients): the pinned pointwise oracle run with the
-gradients of the velocity levels as given velocity-gradient levels (extrap = 0: step
-n -> n+1 uses kappa^{n+1}), re-run from level 0 at every step so that each of its steps
-sees exactly the levels the coupled scheme has produced by then.  Its cost is quadratic in
-the number of steps: small cases only.
+The stress update is either the pointwise scheme without transport terms (the pinned
+pointwise oracle) or, with eps given, the MFP equation of eq. FP_discrete in full, advection
+by u and centre-of-mass diffusion eps Laplace included (the pinned spatial oracle,
+oracle/mfp.py).  Either runs with the velocity levels and their gradients as given levels
+(no extrapolation: step n -> n+1 uses u^{n+1} and kappa^{n+1}), re-run from level 0 at every
+step so that each of its steps sees exactly the levels the coupled scheme has produced by
+then.  Its cost is quadratic in the number of steps: small cases only.
 """
 from __future__ import annotations
 
@@ -43,6 +44,7 @@ import math
 
 import numpy as np
 
+from . import mfp as _spatial
 from . import oracle as _pointwise
 
 # packed symmetric components, the order of the pointwise path: (xx, yy, xy) and
@@ -139,8 +141,10 @@ def initial_velocity(box, u0_grid):
     return box.project(box.fft(u0_grid)) * box.band
 
 
-def run(d, shape, extent, nu, w, lam, De, eta_p, dt, nsteps, u0, X0, startup="sdirk2", want_levels=False):
-    """Coupled run.  u0: [d][P] grid velocity (C-order points), X0: [c][P].
+def run(d, shape, extent, nu, w, lam, De, eta_p, dt, nsteps, u0, X0, startup="sdirk2", want_levels=False,
+        eps=None):
+    """Coupled run.  u0: [d][P] grid velocity (C-order points), X0: [c][P]; eps: None for
+    the pointwise stress update, else the MFP equation with advection and diffusion eps.
     Returns dict: u [d][P] and kappa [d*d][P] of level N, uh (coefficients [d][*shape]),
     p (pressure coefficients of the last step, None if N = 0), tau [c][P], X [2][c][P]
     (levels N, N-1 of the pointwise scheme), modes [2][m][c][P], div (max |div u^N|), and
@@ -149,6 +153,7 @@ def run(d, shape, extent, nu, w, lam, De, eta_p, dt, nsteps, u0, X0, startup="sd
     assert box.d == d
     uh = initial_velocity(box, box.grid(np.asarray(u0, dtype=np.float64)))
     kappas = [box.flat(box.gradient(uh))]
+    vels = [np.stack([box.flat(box.ifft(uh[i])) for i in range(d)])]
     tau = np.zeros((d * (d + 1) // 2, box.P))
     uh_hist, F_hist, C_hist = [uh], [], []
     levels = [uh] if want_levels else None
@@ -162,8 +167,13 @@ def run(d, shape, extent, nu, w, lam, De, eta_p, dt, nsteps, u0, X0, startup="sd
         uh_hist = [uh_new] + uh_hist[:1]
         F_hist, C_hist = F_hist[:1], C_hist[:1]
         kappas.append(box.flat(box.gradient(uh_new)))
-        res = _pointwise.run(d, w, lam, De, eta_p, dt, n + 1, np.stack(kappas), X0, extrap=False, startup=startup,
-                             want_modes=True)
+        vels.append(np.stack([box.flat(box.ifft(uh_new[i])) for i in range(d)]))
+        if eps is None:
+            res = _pointwise.run(d, w, lam, De, eta_p, dt, n + 1, np.stack(kappas), X0, extrap=False,
+                                 startup=startup, want_modes=True)
+        else:
+            res = _spatial.run(d, shape, extent, eps, w, lam, De, eta_p, dt, n + 1, np.stack(kappas), X0,
+                               extrap=False, want_modes=True, u=np.stack(vels))
         tau = res["tau"]
         if want_levels:
             levels.append(uh_new)

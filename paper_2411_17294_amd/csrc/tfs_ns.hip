@@ -22,6 +22,7 @@
 #include "tfs_internal.h"
 #include "tfs_ns.h"
 #include "tfs_spectral.h"
+#include "tfs_transport.h"
 
 namespace tfs {
 tfs_status set_error(tfs_status s, const char* msg);   // tfs_host.cpp
@@ -42,6 +43,7 @@ struct tfs_ns_s {
   double* adv = nullptr;            // [d][stride] grid advection
   double2* spec_f = nullptr;        // [d + c][nc] forward transforms (advection, then tau)
   double2* spec_i = nullptr;        // [d + d*d][nc] inverse-transform inputs (u, then grad u)
+  tfs_transport transport = nullptr;  // stress update with the transport terms, or null (pointwise)
 };
 
 namespace {
@@ -429,6 +431,12 @@ int64_t tfs_ns_spectral_size(tfs_ns s) { return s ? s->nc : -1; }
 
 int tfs_ns_batched(tfs_ns s) { return s && s->batched ? 1 : 0; }
 
+tfs_status tfs_ns_set_transport(tfs_ns s, tfs_transport tr) {
+  if (!s) return set_error(TFS_EINVAL, "null solver");
+  s->transport = tr;
+  return TFS_OK;
+}
+
 tfs_status tfs_ns_set_batched(tfs_ns s, int on) {
   if (!s) return set_error(TFS_EINVAL, "null solver");
   (void)hipDeviceSynchronize();                 // plans of earlier launches may still run
@@ -494,7 +502,11 @@ tfs_status tfs_ns_step(tfs_ns s, tfs_plan p, int64_t n, double* u, void* uh, voi
   if (st != TFS_OK) return st;
   if ((st = inverse_planes(s, s->spec_i, u, d, 2)) != TFS_OK) return st;
   if ((st = inverse_planes(s, s->spec_i + lvl, kappa, d * d, 3)) != TFS_OK) return st;
-  // the stress of level n+1 from kappa^{n+1}
+  // the stress of level n+1 from kappa^{n+1} (and u^{n+1} when the transport terms are on)
+  if (s->transport) {
+    if (diag) return set_error(TFS_EUNSUPPORTED, "no diagnostics with the transport terms");
+    return tfs_transport_step(s->transport, p, n, kappa, nullptr, u, nullptr, X, Y, tau);
+  }
   return tfs_step(p, n, kappa, nullptr, X, Y, tau, diag);
 }
 

@@ -32,6 +32,12 @@ class Solver:
         tfs.check(tfs.lib().tfs_ns_set_batched(self._h, int(bool(on))))
         self.batched = bool(tfs.lib().tfs_ns_batched(self._h))
 
+    def set_transport(self, tr):
+        """Stress update with the MFP transport terms (a transport.Transport), or None for the
+        pointwise update."""
+        self._transport = tr                     # kept alive while the solver uses it
+        tfs.check(tfs.lib().tfs_ns_set_transport(self._h, None if tr is None else tr.handle))
+
     @property
     def handle(self):
         return self._h

@@ -197,3 +197,62 @@ def test_solver_errors():
         sol.step(4, u, uh, fh, kappa, X, Y, tau)                 # past max_steps
     sol.step(0, u, uh, fh, kappa, X, Y, tau)
     torch.cuda.synchronize()
+
+
+def gpu_run_transport(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, eps, iters=40, prec="fp64"):
+    from paper_2411_17294_amd.transport import Transport
+    P = int(np.prod(shape))
+    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec)
+    sol = ns.Solver(plan, shape, extent, nu, dt)
+    tr = Transport(plan, shape, extent, eps, iters)
+    sol.set_transport(tr)
+    u, kappa, uh, fh = sol.alloc()
+    X, Y, tau, _ = plan.alloc()
+    u[:, :P] = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+    X[0, :, :P] = torch.from_numpy(np.ascontiguousarray(X0)).cuda()
+    sol.init(u, uh, kappa)
+    for n in range(N):
+        sol.step(n, u, uh, fh, kappa, X, Y, tau)
+    torch.cuda.synchronize()
+    return {"u": u[:, :P].cpu().numpy(), "tau": tau[:, :P].cpu().numpy(),
+            "X": np.stack([X[N % 2, :, :P].cpu().numpy(), X[(N - 1) % 2, :, :P].cpu().numpy()])}
+
+
+@pytest.mark.parametrize("N", [1, 2, 5])
+@pytest.mark.parametrize("d,shape,extent", [(2, (8, 8), (1.0, 1.0)), (2, (6, 9), (1.0, 1.5)), (3, (4, 6, 4), (1.0, 1.0, 0.8))])
+def test_coupled_with_transport_matches_oracle(d, shape, extent, N):
+    """The coupled step with the MFP equation in full (advection of the stress by u and
+    centre-of-mass diffusion inside the implicit operator) against the coupled oracle run
+    with the spatial oracle for the stress."""
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    nu, De, eta_p, dt, eps = 0.05, 0.7, 0.01, 2e-3, 0.1
+    w, lam, _ = osoe.soe_fit(0.5, 5, dt, dt * max(N, 2))
+    u0, X0 = random_case(d, shape, 200 + d + N, amp=0.3)
+    print(f"coupled+transport d={d} shape={shape} N={N}", flush=True)
+    g = gpu_run_transport(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, eps)
+    o = ons.run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, eps=eps)
+    errs = {"u": relerr(g["u"], o["u"]), "tau": relerr(g["tau"], o["tau"]), "X": relerr(g["X"], o["X"])}
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert all(v < 1e-12 for v in errs.values()), errs
+
+
+def test_shear_wave_with_transport_full_size():
+    """1024^2, m = 32, FP64: the shear wave with the transport terms on against the scalar
+    recurrence whose stress relaxes at 1/De + eps k^2 (advection of the stress vanishes)."""
+    d, shape = 2, (1024, 1024)
+    P = 1024 * 1024
+    m, De, eta_p, nu, dt, N, eps = 32, 0.5, 0.0055, 0.05, 2e-3, 6, 0.02
+    w, lam, _ = osoe.soe_fit(0.5, m, dt, 1.0)
+    k = 2 * math.pi * 3
+    y = np.meshgrid(np.arange(1024) / 1024, np.arange(1024) / 1024, indexing="ij")[1].reshape(P)
+    U0 = 0.1
+    u0 = np.zeros((d, P))
+    u0[0] = U0 * np.sin(k * y)
+    g = gpu_run_transport(d, shape, (1.0, 1.0), nu, w, lam, De, eta_p, dt, N, u0, np.zeros((3, P)), eps, iters=30)
+    Dx = 1.0 / (1.0 / De + eps * k * k)
+    U, T = shear_reference(d, k, U0, nu, w, lam, Dx, eta_p * Dx / De, dt, N)
+    eu = np.max(np.abs(g["u"][0] - U * np.sin(k * y))) / abs(U)
+    et = np.max(np.abs(g["tau"][2] - T * np.cos(k * y))) / abs(T)
+    print(f"shear wave with transport 1024^2: u {eu:.2e} tau_xy {et:.2e}", flush=True)
+    assert eu < 1e-12 and et < 1e-12

@@ -10,7 +10,8 @@ Each pin ties the oracle to something other than itself:
     advection is a pure gradient: errors of order dt^2 for the BDF2 scheme;
   * a zero divergence at every level from a velocity that starts with a gradient part;
   * a shear wave u = (U(t) sin(k y), 0[, 0]), for which the coupled system reduces exactly
-    to a scalar recurrence for U driven by the pointwise stress of one point."""
+    to a scalar recurrence for U driven by the pointwise stress of one point; with the MFP
+    transport terms on, by the pointwise stress at the shifted rate 1/De + eps k^2."""
 import math
 
 import numpy as np
@@ -205,3 +206,36 @@ def test_shear_wave_reduces_to_a_scalar_recurrence(d):
     np.testing.assert_allclose(r["u"][0], ux, rtol=0, atol=1e-12 * abs(U[-1]))
     assert np.max(np.abs(r["u"][1:])) < 1e-14
     np.testing.assert_allclose(r["tau"][xy], txy, rtol=0, atol=1e-12 * abs(T[-1]))
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_shear_wave_with_diffusion_reduces_to_a_scalar_recurrence(d):
+    """With the MFP transport terms on: advection of the stress vanishes for the shear wave
+    (u depends on y only, X too), and eps Laplace acts on tau_xy = T cos(k y) as the extra
+    rate eps k^2, so T^n is the pointwise stress at 1/De + eps k^2 (same eta_p/De)."""
+    shape = (4, 12) if d == 2 else (4, 12, 4)
+    extent = (1.0, 1.5) if d == 2 else (1.0, 1.5, 0.7)
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    x = coords(shape, extent)
+    k = 2 * math.pi * 2 / extent[1]
+    U0, nu, De, eta_p, dt, N, eps = 0.8, 0.05, 0.6, 0.02, 0.01, 6, 0.03
+    w, lam, _ = soe.soe_fit(0.6, 5, dt, dt * N)
+    u0 = np.zeros((d,) + shape)
+    u0[0] = U0 * np.sin(k * x[1])
+    r = ns.run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0.reshape(d, P), np.zeros((c, P)), eps=eps)
+    xy = 2 if d == 2 else 3
+    Dx = 1.0 / (1.0 / De + eps * k * k)
+    U, T = [U0], [0.0]
+    for n in range(N):
+        b, a = ((1.0, -1.0), (1.0,)) if n == 0 else ((1.5, -2.0, 0.5), (2.0, -1.0))
+        g = len(a)
+        rhs = -sum(b[j] / dt * U[n + 1 - j] for j in range(1, g + 1)) + sum(
+            a[j - 1] * (-k * T[n + 1 - j]) for j in range(1, g + 1))
+        U.append(rhs / (b[0] / dt + nu * k * k))
+        lev = np.zeros((n + 2, d * d, 1))
+        lev[:, 1, 0] = k * np.array(U)
+        T.append(O.run(d, w, lam, Dx, eta_p * Dx / De, dt, n + 1, lev, np.zeros((c, 1)), extrap=False)["tau"][xy, 0])
+    assert abs(T[-1]) > 1e-4
+    np.testing.assert_allclose(r["u"][0], U[-1] * np.sin(k * x[1]).reshape(P), rtol=0, atol=1e-12 * abs(U[-1]))
+    np.testing.assert_allclose(r["tau"][xy], T[-1] * np.cos(k * x[1]).reshape(P), rtol=0, atol=1e-12 * abs(T[-1]))
