@@ -145,6 +145,8 @@ def measure_forms(stream, steps=20, which="all"):
         out["fused_exp"] = _fused(stream)
     if which in ("all", "ns"):
         out["ns_coupled"] = _ns_coupled(stream, steps)
+    if which in ("all", "transport"):
+        out["transport_2d"] = _transport(stream, 10)
     return out
 
 
@@ -300,7 +302,7 @@ def _ns_coupled(stream, steps):
                              ("ns_coupled_3d_128cube_m32_fp32modes", 3, 128, "fp32_modes")):
         P, m, alpha, De, beta, Re, dt = n ** d, 32, 0.5, 1.0, 0.9, 1000.0, 1e-3
         w, lam, _, _, _ = tfs.soe_fit(alpha, m, dt, 1.0)
-        p = tfs.Plan(d, P, w, lam, alpha, De, (1 - beta) / Re, dt, 2 * steps + 16, precision=prec)
+        p = tfs.Plan(d, P, w, lam, alpha, De, (1 - beta) / Re, dt, 3 * steps + 16, precision=prec)
         sol = ns.Solver(p, (n,) * d, (2 * math.pi,) * d, beta / Re, dt)
         u, kappa, uh, fh = sol.alloc()
         X, Y, tau, _ = p.alloc()
@@ -315,8 +317,57 @@ def _ns_coupled(stream, steps):
         res[name] = {"grid": [n] * d, "modes": m, "precision": prec, "ms_per_coupled_step": ms,
                      "ms_stress_update": ms_stress, "ms_velocity_part": ms - ms_stress,
                      "point_mode_updates_per_s": P * m / (ms * 1e-3), "u_rms": float(u[:, :P].pow(2).mean().sqrt())}
+        if d == 2:
+            # the same with the MFP transport terms (eps = 0.1, 20 splitting iterations)
+            from paper_2411_17294_amd.transport import Transport
+            tr = Transport(p, (n,) * d, (2 * math.pi,) * d, 0.1, 20)
+            sol.set_transport(tr)
+            base = 4 + 2 * steps if 4 + 2 * steps + steps < p.max_steps else 0
+            ms_t = _timed(stream, lambda k: sol.step(k, u, uh, fh, kappa, X, Y, tau), base, min(steps, 4))
+            res[name]["ms_per_coupled_step_with_transport"] = ms_t
+            sol.set_transport(None)
+            del tr
         del sol, p
     return res
+
+
+def _transport(stream, steps):
+    """The stress update with the MFP transport terms (tfs_transport_step: advection by u and
+    centre-of-mass diffusion eps = 0.1 inside the implicit operator) on [0, 2 pi)^2, 1024^2,
+    m = 32 FP64 modes, with u from synthetic_velocity and kappa = grad u (steady levels),
+    De = 1, alpha = 0.5, eta_p = 1e-4, dt = 1e-3: ms per step with 10 and 20 splitting
+    iterations per solve, the relative change of X between them after the same steps (the
+    iteration's convergence), and the pointwise step on the same fields for comparison."""
+    import math
+    import torch
+    from paper_2411_17294_amd import ns, tfs
+    from paper_2411_17294_amd.transport import Transport
+    n, m, alpha, De, dt, eps = 1024, 32, 0.5, 1.0, 1e-3, 0.1
+    P = n * n
+    w, lam, _, _, _ = tfs.soe_fit(alpha, m, dt, 1.0)
+    out = {"grid": [n, n], "modes": m, "eps": eps}
+    Xs = {}
+    for iters in (10, 20):
+        p = tfs.Plan(2, P, w, lam, alpha, De, 1e-4, dt, 2 * steps + 16, precision="fp64")
+        sol = ns.Solver(p, (n, n), (2 * math.pi,) * 2, 9e-4, dt)
+        u, kappa, uh, fh = sol.alloc()
+        u[:, :P] = synthetic_velocity(2, n, 13)
+        sol.init(u, uh, kappa)
+        tr = Transport(p, (n, n), (2 * math.pi,) * 2, eps, iters)
+        X, Y, tau, _ = p.alloc()
+        for k in range(4):
+            tr.step(k, kappa, kappa, u, u, X, Y, tau)
+        ms = _timed(stream, lambda k: tr.step(k, kappa, kappa, u, u, X, Y, tau), 4, steps)
+        torch.cuda.synchronize()
+        Xs[iters] = X[(4 + steps) % 2, :, :P].clone()
+        out[f"ms_per_step_{iters}_iterations"] = ms
+        if iters == 10:
+            ms_pt = _timed(stream, lambda k: p.step(k, kappa, kappa, X, Y, tau), 4 + steps, steps)
+            out["ms_pointwise_step_same_fields"] = ms_pt
+        del tr, sol, p
+    out["x_rel_change_10_to_20_iterations"] = float((Xs[10] - Xs[20]).abs().max() / Xs[20].abs().max())
+    out["point_mode_updates_per_s_20_iterations"] = P * m / (out["ms_per_step_20_iterations"] * 1e-3)
+    return out
 
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X
@@ -567,7 +618,7 @@ def main():
                     help="run the 384^3 differentiation workload end to end with STEPS time levels")
     ap.add_argument("--job-slabs", type=int, default=64, help="slabs of the --job run (64 = whole grid)")
     ap.add_argument("--only-forms", choices=["all", "fp32_vs_fp64", "fwd_adjoint", "slab384", "exp_vs_bdf2",
-                                             "fwd_adjoint_exp", "mfp_2d", "fused", "ns"],
+                                             "fwd_adjoint_exp", "mfp_2d", "fused", "ns", "transport"],
                     default=None,
                     help="only the 3-D form measurements (for profiling)")
     args = ap.parse_args()

@@ -53,6 +53,15 @@ tfs_status tfs_transport_create(int dim, const int64_t* shape, const double* ext
 tfs_status tfs_transport_destroy(tfs_transport tr);
 
 /*
+ * Transform form, as tfs_ns_batched / tfs_ns_set_batched: 1 when whole fields go through
+ * batched hipFFT plans (tried at creation), 0 when planes go one at a time; set_batched(0)
+ * forces planes one at a time, set_batched(1) asks for the batched plans (TFS_EUNSUPPORTED
+ * if hipFFT refuses the layout).  Results agree to rounding.
+ */
+int tfs_transport_batched(tfs_transport tr);
+tfs_status tfs_transport_set_batched(tfs_transport tr, int on);
+
+/*
  * One step n -> n+1 of a TFS_SCHEME_BDF2 plan with the transport terms: as tfs_step (the
  * same X and Y rings, SDIRK2 at n = 0, BDF2 after), with the velocity levels u_a, u_b
  * [d][stride] following kappa's rule (extrapolated 2 u_a - u_b when kappa_b is given and

@@ -31,8 +31,12 @@ struct tfs_transport_s {
   double k0[3] = {0, 0, 0};
   double eps = 0.0;
   int64_t npoints = 0, nc = 0, stride = 0;
-  hipfftHandle fwd = 0, inv = 0;
+  hipfftHandle fwd = 0, inv = 0;     // one plane
   bool have_fwd = false, have_inv = false;
+  // batched plans over c planes (forward and back) and c d planes (back), planes `stride`
+  // apart on the grid; used where hipFFT takes that layout
+  hipfftHandle bf = 0, bi = 0, bid = 0;
+  bool batched = false;
   // grid planes: right-hand side, SDIRK2 stage-1 value, fluctuation, iterate, gradients (c d)
   double *rg = nullptr, *x1g = nullptr, *fg = nullptr, *xg = nullptr, *dg = nullptr;
   // spectral planes: right-hand side, iterate, fluctuation, extra term, inverse inputs (c + c d)
@@ -402,6 +406,32 @@ __global__ __launch_bounds__(kTBlock) void start_finish_kernel(const double* X0,
   }
 }
 
+// Batched plans over c planes (forward and back) and c d planes (back), planes `stride`
+// apart on the grid; s->batched tells whether hipFFT made all three.
+void make_batched(tfs_transport_s* s) {
+  const int dim = s->dim, c = dim * (dim + 1) / 2;
+  int nn[3], eg[3], es[3];
+  for (int j = 0; j < dim; ++j) nn[j] = eg[j] = es[j] = (int)s->n[j];
+  es[dim - 1] = (int)(s->n[dim - 1] / 2 + 1);
+  const int gd = (int)s->stride, sd = (int)s->nc;
+  const bool okf = hipfftPlanMany(&s->bf, dim, nn, eg, 1, gd, es, 1, sd, HIPFFT_D2Z, c) == HIPFFT_SUCCESS;
+  const bool oki = okf && hipfftPlanMany(&s->bi, dim, nn, es, 1, sd, eg, 1, gd, HIPFFT_Z2D, c) == HIPFFT_SUCCESS;
+  const bool okd = oki && hipfftPlanMany(&s->bid, dim, nn, es, 1, sd, eg, 1, gd, HIPFFT_Z2D, c * dim) == HIPFFT_SUCCESS;
+  s->batched = okd;
+  if (!okd) {
+    if (okf) hipfftDestroy(s->bf);
+    if (oki) hipfftDestroy(s->bi);
+  }
+}
+
+void drop_batched(tfs_transport_s* s) {
+  if (!s->batched) return;
+  hipfftDestroy(s->bf);
+  hipfftDestroy(s->bi);
+  hipfftDestroy(s->bid);
+  s->batched = false;
+}
+
 int blocks_for(int64_t work) {
   const int64_t b = (work + kTBlock - 1) / kTBlock;
   const int64_t cap = 256 * 16;
@@ -421,6 +451,10 @@ SpecGeom geom(const tfs_transport_s* s) {
 }
 
 tfs_status forward_planes(tfs_transport_s* s, const double* grid, double2* spec, int count) {
+  if (s->batched && count == s->dim * (s->dim + 1) / 2) {
+    const hipfftResult r = hipfftExecD2Z(s->bf, const_cast<double*>(grid), (hipfftDoubleComplex*)spec);
+    return r == HIPFFT_SUCCESS ? TFS_OK : hipfft_fail(r, "hipfftExecD2Z");
+  }
   for (int i = 0; i < count; ++i) {
     const hipfftResult r = hipfftExecD2Z(s->fwd, const_cast<double*>(grid) + (int64_t)i * s->stride,
                                          (hipfftDoubleComplex*)(spec + (int64_t)i * s->nc));
@@ -430,6 +464,11 @@ tfs_status forward_planes(tfs_transport_s* s, const double* grid, double2* spec,
 }
 
 tfs_status inverse_planes(tfs_transport_s* s, double2* spec, double* grid, int count) {
+  const int c = s->dim * (s->dim + 1) / 2;
+  if (s->batched && (count == c || count == c * s->dim)) {
+    const hipfftResult r = hipfftExecZ2D(count == c ? s->bi : s->bid, (hipfftDoubleComplex*)spec, grid);
+    return r == HIPFFT_SUCCESS ? TFS_OK : hipfft_fail(r, "hipfftExecZ2D");
+  }
   for (int i = 0; i < count; ++i) {
     const hipfftResult r = hipfftExecZ2D(s->inv, (hipfftDoubleComplex*)(spec + (int64_t)i * s->nc),
                                          grid + (int64_t)i * s->stride);
@@ -590,6 +629,7 @@ tfs_status tfs_transport_create(int dim, const int64_t* shape, const double* ext
     }
     if (r != HIPFFT_SUCCESS) st = hipfft_fail(r, "hipfftPlanMany");
   }
+  if (st == TFS_OK) make_batched(s);   // if hipFFT refuses the layout, single planes serve alone
   if (st != TFS_OK) {
     const std::string keep = tfs_last_error();
     tfs_transport_destroy(s);
@@ -604,12 +644,26 @@ tfs_status tfs_transport_destroy(tfs_transport s) {
   (void)hipDeviceSynchronize();
   if (s->have_fwd) hipfftDestroy(s->fwd);
   if (s->have_inv) hipfftDestroy(s->inv);
+  drop_batched(s);
   for (double* b : {s->rg, s->x1g, s->fg, s->xg, s->dg, s->part, s->mean})
     if (b) (void)hipFree(b);
   for (double2* b : {s->rh, s->xh, s->fh, s->eh, s->iv})
     if (b) (void)hipFree(b);
   delete s;
   return TFS_OK;
+}
+
+int tfs_transport_batched(tfs_transport s) { return s && s->batched ? 1 : 0; }
+
+tfs_status tfs_transport_set_batched(tfs_transport s, int on) {
+  if (!s) return set_error(TFS_EINVAL, "null transport object");
+  (void)hipDeviceSynchronize();
+  if (!on) {
+    drop_batched(s);
+    return TFS_OK;
+  }
+  if (!s->batched) make_batched(s);
+  return s->batched ? TFS_OK : set_error(TFS_EUNSUPPORTED, "hipFFT refuses the batched layout for this size");
 }
 
 tfs_status tfs_transport_step(tfs_transport s, tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b,
@@ -623,9 +677,12 @@ tfs_status tfs_transport_step(tfs_transport s, tfs_plan p, int64_t n, const doub
   if (n < 0 || n >= p->max_steps) return set_error(TFS_EINVAL, "step index out of range");
   if (!kappa_a || !u_a || !X || !Y || !tau) return set_error(TFS_EINVAL, "null kappa_a, u_a, X, Y or tau");
   if (kappa_b && !u_b) return set_error(TFS_EINVAL, "u_b is needed with kappa_b");
-  const hipfftResult fr = hipfftSetStream(s->fwd, p->stream);
-  const hipfftResult ir = hipfftSetStream(s->inv, p->stream);
-  if (fr != HIPFFT_SUCCESS || ir != HIPFFT_SUCCESS) return hipfft_fail(fr != HIPFFT_SUCCESS ? fr : ir, "hipfftSetStream");
+  hipfftResult fr = hipfftSetStream(s->fwd, p->stream);
+  if (fr == HIPFFT_SUCCESS) fr = hipfftSetStream(s->inv, p->stream);
+  if (fr == HIPFFT_SUCCESS && s->batched) fr = hipfftSetStream(s->bf, p->stream);
+  if (fr == HIPFFT_SUCCESS && s->batched) fr = hipfftSetStream(s->bi, p->stream);
+  if (fr == HIPFFT_SUCCESS && s->batched) fr = hipfftSetStream(s->bid, p->stream);
+  if (fr != HIPFFT_SUCCESS) return hipfft_fail(fr, "hipfftSetStream");
   Lev L;
   L.ka = kappa_a;
   L.ua = u_a;

@@ -27,7 +27,8 @@ EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_pl
            "tfs_plan_tables", "tfs_plan_stride", "tfs_plan_tile", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
            "tfs_status_string", "tfs_last_error",
            "tfs_ns_create", "tfs_ns_destroy", "tfs_ns_spectral_size", "tfs_ns_batched", "tfs_ns_set_batched", "tfs_ns_set_transport", "tfs_ns_init",
-           "tfs_ns_step", "tfs_transport_create", "tfs_transport_destroy", "tfs_transport_step")
+           "tfs_ns_step", "tfs_transport_create", "tfs_transport_destroy", "tfs_transport_step",
+           "tfs_transport_batched", "tfs_transport_set_batched")
 
 
 # Mode-ring tile (points) used when the caller does not choose one; measured best on
@@ -105,6 +106,9 @@ def lib():
     L.tfs_transport_create.argtypes = [C.c_int, C.POINTER(i64), dp, C.c_double, i64, C.c_int, C.POINTER(C.c_void_p)]
     L.tfs_transport_destroy.argtypes = [vp]
     L.tfs_transport_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.tfs_transport_batched.argtypes = [vp]
+    L.tfs_transport_batched.restype = C.c_int
+    L.tfs_transport_set_batched.argtypes = [vp, C.c_int]
     L.tfs_ns_init.argtypes = [vp, vp, vp, vp, vp]
     L.tfs_ns_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     for name in ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
@@ -112,7 +116,8 @@ def lib():
                  "tfs_step_adjoint", "tfs_pbar_to_params", "tfs_pbar_rate_gradient", "tfs_modes_to_plain",
                  "tfs_plan_tables", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
                  "tfs_ns_create", "tfs_ns_destroy", "tfs_ns_set_batched", "tfs_ns_set_transport", "tfs_ns_init", "tfs_ns_step",
-                 "tfs_transport_create", "tfs_transport_destroy", "tfs_transport_step"):
+                 "tfs_transport_create", "tfs_transport_destroy", "tfs_transport_step",
+           "tfs_transport_batched", "tfs_transport_set_batched"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -27,6 +27,14 @@ class Transport:
         self._h = h
 
     @property
+    def batched(self):
+        return bool(tfs.lib().tfs_transport_batched(self._h))
+
+    def set_batched(self, on: bool):
+        """Transform whole fields in batched plans (True) or one plane at a time (False)."""
+        tfs.check(tfs.lib().tfs_transport_set_batched(self._h, int(bool(on))))
+
+    @property
     def handle(self):
         return self._h
 

@@ -45,11 +45,14 @@ def fields(d, shape, extent, nlev, seed, u_amp=0.3, k_amp=0.3, uniform=False):
     return u, k
 
 
-def gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, extrap, iters):
+def gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, extrap, iters, batched=True):
     P = int(np.prod(shape))
     c = d * (d + 1) // 2
     plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec)
     tr = Transport(plan, shape, extent, eps, iters)
+    if not batched:
+        tr.set_batched(False)
+    print(f"  transforms batched: {tr.batched}", flush=True)
     st = plan.stride
     X, Y, tau, _ = plan.alloc()
     X[0, :, :P] = torch.from_numpy(X0).cuda()
@@ -73,12 +76,14 @@ def gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, e
 CASES = [(2, (6, 8), (1.0, 2.0)), (2, (7, 6), (1.5, 1.0)), (3, (4, 4, 6), (1.0, 2.0, 3.0))]
 
 
+@pytest.mark.parametrize("batched", [True, False])
 @pytest.mark.parametrize("extrap", [True, False])
 @pytest.mark.parametrize("N", [1, 2, 9])
 @pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
 @pytest.mark.parametrize("d,shape,extent", CASES)
-def test_transport_step_matches_spatial_oracle(d, shape, extent, prec, N, extrap):
-    """u and kappa varying in space and time; 40 splitting iterations per solve."""
+def test_transport_step_matches_spatial_oracle(d, shape, extent, prec, N, extrap, batched):
+    """u and kappa varying in space and time; 40 splitting iterations per solve; both
+    transform forms."""
     P = int(np.prod(shape))
     c = d * (d + 1) // 2
     De, eta_p, eps, dt = 0.8, 0.1, 0.05, 2e-3
@@ -86,7 +91,7 @@ def test_transport_step_matches_spatial_oracle(d, shape, extent, prec, N, extrap
     u, kap = fields(d, shape, extent, N + 1, 50 + d + N)
     X0 = np.random.default_rng(60 + d).standard_normal((c, P)) * 0.05
     print(f"transport d={d} shape={shape} {prec} N={N} extrap={extrap}", flush=True)
-    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, extrap, 40)
+    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, extrap, 40, batched)
     o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, extrap=extrap, want_modes=True, u=u)
     errs = {"X": relerr(g["X"], o["X"]), "tau": relerr(g["tau"], o["tau"]), "modes": relerr(g["modes"], o["modes"][0])}
     print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
