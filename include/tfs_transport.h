@@ -11,8 +11,9 @@
  *   2. the right-hand side gains L's transport part applied to G (the history terms
  *      sum_k eta_k L Phi_k of eq. FP_discrete);
  *   3. the coupled system (a I - b K(kappa~(x)) + b T) X = rhs, T = u~.grad - eps Laplace, is
- *      solved by a fixed number of splitting iterations preconditioned by its
- *      constant-coefficient part: with the spatial means kappa_bar and u_bar,
+ *      solved by a fixed number of splitting iterations (or GMRES steps,
+ *      tfs_transport_set_method) preconditioned by its constant-coefficient part: with the
+ *      spatial means kappa_bar and u_bar,
  *          P(xi) = (a + b eps |xi|^2 + i b xi.u_bar) I - b K(kappa_bar),
  *          X_hat <- P^{-1} (rhs_hat - F[ -b K(kappa~ - kappa_bar) X + b (u~ - u_bar).grad X ]),
  *      which converges when the variable part is small next to P (small dt, eps > 0 or a
@@ -60,6 +61,18 @@ tfs_status tfs_transport_destroy(tfs_transport tr);
  */
 int tfs_transport_batched(tfs_transport tr);
 tfs_status tfs_transport_set_batched(tfs_transport tr, int on);
+
+/*
+ * The solver of step 3: method 0 (the default) runs `iters` splitting iterations; method 1
+ * runs GMRES on the same preconditioned system (the splitting's fixed-point equation, real
+ * inner product over the coefficients) with at most `iters` Arnoldi steps (classical
+ * Gram-Schmidt twice) from zero, stopping early at a relative residual of 1e-15.  GMRES
+ * converges where the splitting contracts slowly or not at all (strong advection, small
+ * eps); it synchronises the stream once per Arnoldi step for the small least-squares
+ * problem and keeps iters + 1 basis vectors of 2 c nc doubles (allocated here).
+ * Errors: TFS_EINVAL (null object, unknown method, iters > 256 for GMRES), TFS_ENOMEM.
+ */
+tfs_status tfs_transport_set_method(tfs_transport tr, int method);
 
 /*
  * One step n -> n+1 of a TFS_SCHEME_BDF2 plan with the transport terms: as tfs_step (the

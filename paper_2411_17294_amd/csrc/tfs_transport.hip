@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "tfs_device.h"
 #include "tfs_internal.h"
@@ -42,6 +43,9 @@ struct tfs_transport_s {
   // spectral planes: right-hand side, iterate, fluctuation, extra term, inverse inputs (c + c d)
   double2 *rh = nullptr, *xh = nullptr, *fh = nullptr, *eh = nullptr, *iv = nullptr;
   double *part = nullptr, *mean = nullptr;   // spatial means of kappa~ (d*d) and u~ (d)
+  // GMRES (method 1): Krylov basis [iters + 1][2 c nc] doubles, dot partials, coefficients
+  int method = 0;
+  double *basis = nullptr, *dpart = nullptr, *coef = nullptr;
 };
 
 namespace {
@@ -406,6 +410,90 @@ __global__ __launch_bounds__(kTBlock) void start_finish_kernel(const double* X0,
   }
 }
 
+// ---------------------------------------------------------------- GMRES on the spectrum
+// Vectors are the c coefficient planes as 2 c nc doubles (re, im) with the real inner
+// product: the operator is linear over the reals (the inverse transform keeps only the
+// Hermitian part of a half spectrum), not over the complex numbers.
+constexpr int kDotBlocks = 512;
+
+// part[k * kDotBlocks + b] = block b's share of <w, V_k>, k < nvec (blockIdx.y = k).
+__global__ __launch_bounds__(kTBlock) void multi_dot_kernel(const double* V, int64_t nv, const double* w,
+                                                            double* part) {
+  __shared__ double red[kTBlock];
+  const double* v = V + (int64_t)blockIdx.y * nv;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kTBlock + threadIdx.x; i < nv; i += (int64_t)gridDim.x * kTBlock)
+    acc = fma(w[i], v[i], acc);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = kTBlock / 2; h > 0; h /= 2) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.y * kDotBlocks + blockIdx.x] = red[0];
+}
+
+__global__ void dot_finish_kernel(const double* part, int nvec, double* out) {
+  const int k = threadIdx.x;
+  if (k >= nvec) return;
+  double s = 0.0;
+  for (int b = 0; b < kDotBlocks; ++b) s += part[k * kDotBlocks + b];
+  out[k] = s;
+}
+
+// w -= sum_k coef[k] V_k (k < nvec), or with set: w = sum_k coef[k] V_k.
+__global__ __launch_bounds__(kTBlock) void multi_axpy_kernel(const double* V, int64_t nv, int nvec,
+                                                             const double* coef, bool set, double* w) {
+  for (int64_t i = (int64_t)blockIdx.x * kTBlock + threadIdx.x; i < nv; i += (int64_t)gridDim.x * kTBlock) {
+    double a = 0.0;
+    for (int k = 0; k < nvec; ++k) a = fma(coef[k], V[(int64_t)k * nv + i], a);
+    w[i] = set ? a : w[i] - a;
+  }
+}
+
+// out = w / sqrt(nrm2[0]).
+__global__ __launch_bounds__(kTBlock) void normalize_kernel(const double* w, int64_t nv, const double* nrm2,
+                                                            double* out) {
+  const double f = 1.0 / sqrt(nrm2[0]);
+  for (int64_t i = (int64_t)blockIdx.x * kTBlock + threadIdx.x; i < nv; i += (int64_t)gridDim.x * kTBlock)
+    out[i] = w[i] * f;
+}
+
+// w = v + P(xi)^{-1} fh / points (the preconditioned operator applied to v).
+template <int D>
+__global__ __launch_bounds__(kTBlock) void gm_apply_kernel(const PrecondArgs A, const double2* v, double2* w) {
+  constexpr int C = Sym<D>::C;
+  double kb[D * D], ub[D];
+#pragma unroll
+  for (int q = 0; q < D * D; ++q) kb[q] = A.mean[q];
+#pragma unroll
+  for (int j = 0; j < D; ++j) ub[j] = A.mean[D * D + j];
+  for (int64_t q = (int64_t)blockIdx.x * kTBlock + threadIdx.x; q < A.nc; q += (int64_t)gridDim.x * kTBlock) {
+    double xi[D], xd[D];
+    spec_xi<D>(A.g, q, xi, xd);
+    double x2 = 0.0, xu = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      x2 = fma(xi[j], xi[j], x2);
+      xu = fma(xd[j], ub[j], xu);
+    }
+    double2 r[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      const double2 f = A.fh[s * A.nc + q];
+      r[s] = make_double2(f.x * A.inv_P, f.y * A.inv_P);
+    }
+    double M[C][C];
+    build_M<D>(kb, A.a + A.b * A.eps * x2, A.b, M);
+    solve_shifted<C>(M, A.b * xu, r);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      const double2 x = v[s * A.nc + q];
+      w[s * A.nc + q] = make_double2(x.x + r[s].x, x.y + r[s].y);
+    }
+  }
+}
+
 // Batched plans over c planes (forward and back) and c d planes (back), planes `stride`
 // apart on the grid; s->batched tells whether hipFFT made all three.
 void make_batched(tfs_transport_s* s) {
@@ -503,6 +591,10 @@ tfs_status solve(tfs_transport_s* s, hipStream_t st, const Lev& L, double a, dou
   hipLaunchKernelGGL(precond_kernel<D>, dim3(bs), dim3(kTBlock), 0, st, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "precond_kernel launch");
+  if (s->method == 1 && s->iters > 0) {
+    if ((r = gmres<D>(s, st, L, A)) != TFS_OK) return r;
+    return inverse_planes(s, s->iv, out, C);
+  }
   A.fh = s->fh;
   for (int it = 0; it < s->iters; ++it) {
     if ((r = inverse_planes(s, s->iv, s->xg, C)) != TFS_OK) return r;
@@ -514,6 +606,111 @@ tfs_status solve(tfs_transport_s* s, hipStream_t st, const Lev& L, double a, dou
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "solver iteration launch");
   }
   return inverse_planes(s, s->iv, out, C);
+}
+
+// The variable part of the operator on coefficient vector v (normalised coefficients),
+// transformed: s->fh = F[fluct(F^{-1} v)] (unnormalised).
+template <int D>
+tfs_status apply_fluct(tfs_transport_s* s, hipStream_t st, const Lev& L, double b, const double2* v) {
+  constexpr int C = Sym<D>::C;
+  hipLaunchKernelGGL(deriv_kernel<D>, dim3(blocks_for(s->nc)), dim3(kTBlock), 0, st, geom(s), s->nc, 1.0, v, true,
+                     s->iv);
+  tfs_status r = inverse_planes(s, s->iv, s->xg, C);
+  if (r == TFS_OK) r = inverse_planes(s, s->iv + (int64_t)C * s->nc, s->dg, C * D);
+  if (r != TFS_OK) return r;
+  hipLaunchKernelGGL(fluct_kernel<D>, dim3(blocks_for(s->npoints)), dim3(kTBlock), 0, st, s->xg, s->dg, L, s->mean,
+                     b, s->npoints, s->stride, s->fg);
+  return forward_planes(s, s->fg, s->fh, C);
+}
+
+// GMRES on the preconditioned system (I + P^{-1} F fluct F^{-1}) x = P^{-1} rhs_hat (the
+// splitting iteration's fixed-point equation) from x = 0, s->iters Arnoldi steps (classical
+// Gram-Schmidt, twice), early exit at a relative residual of 1e-15; x into s->xh.
+template <int D>
+tfs_status gmres(tfs_transport_s* s, hipStream_t st, const Lev& L, const PrecondArgs& A0) {
+  constexpr int C = Sym<D>::C;
+  const int64_t nv = (int64_t)2 * C * s->nc;
+  const int m = s->iters, bs = blocks_for(s->nc), bv = blocks_for(nv);
+  double* V = s->basis;
+  double* w = reinterpret_cast<double*>(s->fh);    // work vector: fh is free between applications
+  double* h = s->coef;                               // device: [m + 2] projections, then y
+  // b' = P^{-1} rhs_hat is in s->xh (precond_kernel); v_0 = b' / |b'|
+  const double* bp = reinterpret_cast<const double*>(s->xh);
+  hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, 1), dim3(kTBlock), 0, st, bp, nv, bp, s->dpart);
+  hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(kTBlock), 0, st, s->dpart, 1, h);
+  double beta2 = 0.0;
+  hipError_t e = hipMemcpyAsync(&beta2, h, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "GMRES start");
+  const double beta = std::sqrt(beta2);
+  if (!(beta > 0.0)) return TFS_OK;                  // zero right-hand side: x = 0 = b'
+  hipLaunchKernelGGL(normalize_kernel, dim3(bv), dim3(kTBlock), 0, st, bp, nv, h, V);
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), hc1(m + 1), hc2(m + 1);
+  g[0] = beta;
+  int k = 0;
+  for (int j = 0; j < m; ++j) {
+    const double2* vj = reinterpret_cast<const double2*>(V + (int64_t)j * nv);
+    tfs_status r = apply_fluct<D>(s, st, L, A0.b, vj);
+    if (r != TFS_OK) return r;
+    PrecondArgs A = A0;
+    A.fh = s->fh;
+    hipLaunchKernelGGL(gm_apply_kernel<D>, dim3(bs), dim3(kTBlock), 0, st, A, vj, reinterpret_cast<double2*>(w));
+    // two passes of classical Gram-Schmidt against v_0 .. v_j
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, j + 1), dim3(kTBlock), 0, st, V, nv, w, s->dpart);
+      hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(kTBlock), 0, st, s->dpart, j + 1, h);
+      hipLaunchKernelGGL(multi_axpy_kernel, dim3(bv), dim3(kTBlock), 0, st, V, nv, j + 1, h, false, w);
+      e = hipMemcpyAsync(pass ? hc2.data() : hc1.data(), h, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) return hip_fail(e, "GMRES projections");
+      if (pass == 0) {                               // h is reused by the second pass
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "GMRES projections");
+      }
+    }
+    hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, 1), dim3(kTBlock), 0, st, w, nv, w, s->dpart);
+    hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(kTBlock), 0, st, s->dpart, 1, h + m + 1);
+    double nrm2 = 0.0;
+    e = hipMemcpyAsync(&nrm2, h + m + 1, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "GMRES norm");
+    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc1[i] + hc2[i];
+    const double hn = std::sqrt(nrm2);
+    H[(size_t)(j + 1) * m + j] = hn;
+    if (j + 1 < m + 1 && hn > 0.0)
+      hipLaunchKernelGGL(normalize_kernel, dim3(bv), dim3(kTBlock), 0, st, w, nv, h + m + 1, V + (int64_t)(j + 1) * nv);
+    // Givens rotations of column j
+    for (int i = 0; i < j; ++i) {
+      const double a = H[(size_t)i * m + j], bq = H[(size_t)(i + 1) * m + j];
+      H[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
+      H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bq;
+    }
+    const double a = H[(size_t)j * m + j], bq = H[(size_t)(j + 1) * m + j];
+    const double rr = std::hypot(a, bq);
+    cs[j] = rr > 0.0 ? a / rr : 1.0;
+    sn[j] = rr > 0.0 ? bq / rr : 0.0;
+    H[(size_t)j * m + j] = rr;
+    H[(size_t)(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    k = j + 1;
+    if (std::fabs(g[j + 1]) <= 1e-15 * beta || hn == 0.0) break;
+  }
+  // y from the k x k triangle, x = V y
+  std::vector<double> y(k, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int t = i + 1; t < k; ++t) acc -= H[(size_t)i * m + t] * y[t];
+    y[i] = acc / H[(size_t)i * m + i];
+  }
+  e = hipMemcpyAsync(h, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "GMRES solution");
+  hipLaunchKernelGGL(multi_axpy_kernel, dim3(bv), dim3(kTBlock), 0, st, V, nv, k, h, true,
+                     reinterpret_cast<double*>(s->xh));
+  e = hipStreamSynchronize(st);                      // y (host memory) stays alive until the copy ran
+  if (e != hipSuccess) return hip_fail(e, "GMRES solution");
+  hipLaunchKernelGGL(deriv_kernel<D>, dim3(bs), dim3(kTBlock), 0, st, geom(s), s->nc, 1.0, s->xh, true, s->iv);
+  e = hipGetLastError();
+  return e == hipSuccess ? TFS_OK : hip_fail(e, "GMRES launch");
 }
 
 // grad of the c fields whose coefficients are in s->eh, into s->dg.
@@ -645,7 +842,7 @@ tfs_status tfs_transport_destroy(tfs_transport s) {
   if (s->have_fwd) hipfftDestroy(s->fwd);
   if (s->have_inv) hipfftDestroy(s->inv);
   drop_batched(s);
-  for (double* b : {s->rg, s->x1g, s->fg, s->xg, s->dg, s->part, s->mean})
+  for (double* b : {s->rg, s->x1g, s->fg, s->xg, s->dg, s->part, s->mean, s->basis, s->dpart, s->coef})
     if (b) (void)hipFree(b);
   for (double2* b : {s->rh, s->xh, s->fh, s->eh, s->iv})
     if (b) (void)hipFree(b);
@@ -654,6 +851,26 @@ tfs_status tfs_transport_destroy(tfs_transport s) {
 }
 
 int tfs_transport_batched(tfs_transport s) { return s && s->batched ? 1 : 0; }
+
+tfs_status tfs_transport_set_method(tfs_transport s, int method) {
+  if (!s) return set_error(TFS_EINVAL, "null transport object");
+  if (method != 0 && method != 1) return set_error(TFS_EINVAL, "method must be 0 (splitting) or 1 (GMRES)");
+  if (method == 1 && s->iters > kTBlock) return set_error(TFS_EINVAL, "GMRES takes at most 256 iterations");
+  if (method == 1 && !s->basis && s->iters > 0) {
+    const int c = s->dim * (s->dim + 1) / 2;
+    const int64_t nv = (int64_t)2 * c * s->nc;
+    hipError_t e = hipMalloc((void**)&s->basis, sizeof(double) * nv * (s->iters + 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->dpart, sizeof(double) * kDotBlocks * (s->iters + 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->coef, sizeof(double) * (s->iters + 2));
+    if (e != hipSuccess) {
+      for (double** b : {&s->basis, &s->dpart, &s->coef})
+        if (*b) { (void)hipFree(*b); *b = nullptr; }
+      return set_error(TFS_ENOMEM, "device allocation of the Krylov basis failed");
+    }
+  }
+  s->method = method;
+  return TFS_OK;
+}
 
 tfs_status tfs_transport_set_batched(tfs_transport s, int on) {
   if (!s) return set_error(TFS_EINVAL, "null transport object");

@@ -34,6 +34,10 @@ class Transport:
         """Transform whole fields in batched plans (True) or one plane at a time (False)."""
         tfs.check(tfs.lib().tfs_transport_set_batched(self._h, int(bool(on))))
 
+    def set_method(self, method: str):
+        """"splitting" (the default) or "gmres" for the implicit solve."""
+        tfs.check(tfs.lib().tfs_transport_set_method(self._h, {"splitting": 0, "gmres": 1}[method]))
+
     @property
     def handle(self):
         return self._h

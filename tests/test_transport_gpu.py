@@ -45,11 +45,13 @@ def fields(d, shape, extent, nlev, seed, u_amp=0.3, k_amp=0.3, uniform=False):
     return u, k
 
 
-def gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, extrap, iters, batched=True):
+def gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, extrap, iters, batched=True,
+            method="splitting"):
     P = int(np.prod(shape))
     c = d * (d + 1) // 2
     plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec)
     tr = Transport(plan, shape, extent, eps, iters)
+    tr.set_method(method)
     if not batched:
         tr.set_batched(False)
     print(f"  transforms batched: {tr.batched}", flush=True)
@@ -132,3 +134,39 @@ def test_transport_errors():
         tr2.step(0, k, None, u, None, Xe, Ye, te)                    # exponential scheme
     tr.step(0, k, None, u, None, X, Y, tau)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("N", [1, 2, 9])
+@pytest.mark.parametrize("d,shape,extent", CASES)
+def test_transport_gmres_matches_spatial_oracle(d, shape, extent, N):
+    """The GMRES solver on the same cases (at most 30 Arnoldi steps per solve)."""
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    De, eta_p, eps, dt = 0.8, 0.1, 0.05, 2e-3
+    w, lam, _ = osoe.soe_fit(0.5, 6, dt, dt * max(N, 2))
+    u, kap = fields(d, shape, extent, N + 1, 50 + d + N)
+    X0 = np.random.default_rng(60 + d).standard_normal((c, P)) * 0.05
+    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, "fp64", True, 30, method="gmres")
+    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, want_modes=True, u=u)
+    errs = {"X": relerr(g["X"], o["X"]), "tau": relerr(g["tau"], o["tau"]), "modes": relerr(g["modes"], o["modes"][0])}
+    print("gmres", d, shape, N, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert all(v < 1e-12 for v in errs.values()), errs
+
+
+def test_gmres_converges_under_strong_advection():
+    """u deviating by 1.5 from its mean and eps = 0.01 on a 16 x 16 grid: the splitting's
+    contraction estimate |du| sqrt(b / (a eps)) / 2 is about 1.7, so it diverges; GMRES with
+    90 Arnoldi steps still meets the FP64 bar."""
+    d, shape, extent = 2, (16, 16), (1.0, 1.0)
+    P, c, N = 256, 3, 4
+    De, eta_p, eps, dt = 0.8, 0.1, 0.01, 5e-3
+    w, lam, _ = osoe.soe_fit(0.5, 6, dt, dt * N)
+    u, kap = fields(d, shape, extent, N + 1, 81, u_amp=1.5, k_amp=0.5)
+    X0 = np.random.default_rng(82).standard_normal((c, P)) * 0.05
+    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, want_modes=True, u=u)
+    gm = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, "fp64", True, 90, method="gmres")
+    sp = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, "fp64", True, 40)
+    e_gm = relerr(gm["X"], o["X"])
+    e_sp = relerr(sp["X"], o["X"]) if np.all(np.isfinite(sp["X"])) else float("inf")
+    print(f"strong advection: GMRES {e_gm:.2e}, splitting {e_sp:.2e}", flush=True)
+    assert e_gm < 1e-11
