@@ -170,3 +170,56 @@ def test_gmres_converges_under_strong_advection():
     e_sp = relerr(sp["X"], o["X"]) if np.all(np.isfinite(sp["X"])) else float("inf")
     print(f"strong advection: GMRES {e_gm:.2e}, splitting {e_sp:.2e}", flush=True)
     assert e_gm < 1e-11
+
+
+@pytest.mark.parametrize("d,n,prec", [(2, 1024, "fp64"), (3, 64, "fp32_modes")])
+def test_uniform_fields_full_size_sampled_coefficients(d, n, prec):
+    """1024^2 FP64 and 64^3 FP32 modes, m = 32, u and kappa uniform (u != 0), no splitting
+    iteration: every
+    Fourier coefficient of X evolves on its own with the complex rate 1/De + eps |xi|^2 +
+    i xi.u in place of 1/De (the mass-mode source only at xi = 0).  24 sampled coefficients
+    of the GPU result (transformed with torch.fft) against complex runs of the pointwise
+    oracle from the same initial coefficients."""
+    from oracle import oracle as O
+    shape, extent = (n,) * d, (1.0,) * d
+    P, c, N = n ** d, d * (d + 1) // 2, 6
+    De, eta_p, eps, dt = 0.5, 0.1, 0.02, 1e-3
+    w, lam, _ = osoe.soe_fit(0.5, 32, dt, 1.0)
+    u0 = np.array([0.7, -0.4, 0.3][:d])
+    kd = np.array([[0.3, 0.5, 0.1], [-0.2, -0.3, 0.2], [0.1, 0.0, 0.0]])[:d, :d]
+    u = np.repeat(u0.reshape(1, d, 1), N + 1, axis=0) * np.ones((1, 1, P))
+    kap = np.repeat(kd.reshape(1, d * d, 1), N + 1, axis=0) * np.ones((1, 1, P))
+    rng = np.random.default_rng(90)
+    # a smooth random initial field (a few hundred low modes) plus a mean
+    axes = tuple(range(1, d + 1))
+    Xh0 = np.zeros((c,) + shape, complex)
+    filled = []
+    kmax = 20 if d == 2 else 8
+    for _ in range(300):
+        idx = tuple(int(v) for v in rng.integers(-kmax, kmax + 1, size=d))
+        Xh0[(slice(None),) + tuple(v % n for v in idx)] += (rng.standard_normal(c) + 1j * rng.standard_normal(c)) * 0.01
+        filled.append(idx)
+    X0 = np.real(np.fft.ifftn(Xh0, axes=axes) * P).reshape(c, P) + rng.standard_normal((c, 1)) * 0.05
+    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, True, 0)
+    Gh = torch.fft.fftn(torch.from_numpy(g["X"][0].reshape((c,) + shape)), dim=axes).numpy() / P
+    Ih = np.fft.fftn(X0.reshape((c,) + shape), axes=axes) / P
+    picks = [(0,) * d] + [filled[k] for k in rng.choice(len(filled), 23, replace=False)]
+    one = kd.reshape(d * d, 1)
+    worst = 0.0
+    for idx in picks:
+        xi = 2 * math.pi * np.array(idx, dtype=float)
+        rate = 1.0 / De + eps * xi @ xi + 1j * (xi @ u0)
+        Dx = 1.0 / rate
+        at = (slice(None),) + tuple(v % n for v in idx)
+        x0 = Ih[at].reshape(c, 1)
+        if idx == (0,) * d:
+            want = O.run(d, w, lam, De, eta_p, dt, N, one, x0.real)["X"][0][:, 0]
+        else:
+            z = O.run_complex(d, w, lam, Dx, eta_p * Dx / De, dt, N, one.astype(complex), x0)["X"][0][:, 0]
+            z0 = O.run_complex(d, w, lam, Dx, eta_p * Dx / De, dt, N, one.astype(complex),
+                               np.zeros((c, 1), complex))["X"][0][:, 0]
+            want = z - z0
+        got = Gh[at]
+        worst = max(worst, float(np.max(np.abs(got - want)) / np.max(np.abs(want))))
+    print(f"full-size uniform transport d={d} n={n} {prec}: worst sampled coefficient {worst:.2e}", flush=True)
+    assert worst < (1e-10 if prec == "fp64" else 1e-5)
