@@ -106,7 +106,7 @@ tfs_status tfs_ns_init(tfs_ns ns, tfs_plan plan, double* u, void* uh, double* ka
  * unused at n = 0) and fh slot (n-1) % 2 holds F^{n-1} (unused at n = 0).  The step writes
  * F^n to fh slot n % 2, u^{n+1} to uh slot (n+1) % 2, u and kappa of level n+1 on the grid,
  * and then calls tfs_step(plan, n, kappa, NULL, X, Y, tau, diag), or the transport step set
- * by tfs_ns_set_transport (diag must then be NULL: TFS_EUNSUPPORTED otherwise).
+ * by tfs_ns_set_transport.
  * Errors: those of tfs_step, TFS_EINVAL (null pointers, mismatched or spatial-form plan),
  * TFS_EHIP.
  */

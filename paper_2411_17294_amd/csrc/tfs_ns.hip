@@ -503,10 +503,7 @@ tfs_status tfs_ns_step(tfs_ns s, tfs_plan p, int64_t n, double* u, void* uh, voi
   if ((st = inverse_planes(s, s->spec_i, u, d, 2)) != TFS_OK) return st;
   if ((st = inverse_planes(s, s->spec_i + lvl, kappa, d * d, 3)) != TFS_OK) return st;
   // the stress of level n+1 from kappa^{n+1} (and u^{n+1} when the transport terms are on)
-  if (s->transport) {
-    if (diag) return set_error(TFS_EUNSUPPORTED, "no diagnostics with the transport terms");
-    return tfs_transport_step(s->transport, p, n, kappa, nullptr, u, nullptr, X, Y, tau);
-  }
+  if (s->transport) return tfs_transport_step(s->transport, p, n, kappa, nullptr, u, nullptr, X, Y, tau, diag);
   return tfs_step(p, n, kappa, nullptr, X, Y, tau, diag);
 }
 

@@ -520,6 +520,40 @@ void drop_batched(tfs_transport_s* s) {
   s->batched = false;
 }
 
+// Diagnostics of tfs.h (minors of C = I + X, max and sum of ||tau||_F^2, non-finite count):
+// block partials over a grid-stride range of points, then one block folds them in order.
+template <int D>
+__global__ __launch_bounds__(kTBlock) void diag_partial_kernel(const double* X, const double* tau, int64_t npoints,
+                                                               int64_t st, double* part) {
+  constexpr int C = Sym<D>::C;
+  DiagAcc acc;
+  for (int64_t p = (int64_t)blockIdx.x * kTBlock + threadIdx.x; p < npoints; p += (int64_t)gridDim.x * kTBlock) {
+    double x[C], t[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      x[s] = X[s * st + p];
+      t[s] = tau[s * st + p];
+    }
+    diag_point<D>(acc, x, t);
+  }
+  const DiagAcc r = block_reduce(acc);
+  if (threadIdx.x == 0) write_partial(part, blockIdx.x, r);
+}
+
+__global__ __launch_bounds__(kTBlock) void diag_fold_kernel(const double* part, int nparts, double* diag) {
+  DiagAcc a;
+  for (int i = threadIdx.x; i < nparts; i += kTBlock) {
+    const double* q = part + (size_t)i * tfs::kNumDiag;
+    DiagAcc b;
+    b.mn1 = q[0]; b.mn2 = q[1]; b.mn3 = q[2]; b.mx = q[3]; b.sum = q[4]; b.cnt = q[5];
+    diag_combine(a, b);
+  }
+  const DiagAcc r = block_reduce(a);
+  if (threadIdx.x == 0) {
+    diag[0] = r.mn1; diag[1] = r.mn2; diag[2] = r.mn3; diag[3] = r.mx; diag[4] = r.sum; diag[5] = r.cnt;
+  }
+}
+
 int blocks_for(int64_t work) {
   const int64_t b = (work + kTBlock - 1) / kTBlock;
   const int64_t cap = 256 * 16;
@@ -726,7 +760,7 @@ tfs_status gradient_of_extra(tfs_transport_s* s, hipStream_t st) {
 
 template <int D, typename MT>
 tfs_status step_d(tfs_transport_s* s, const tfs_plan_s* p, int64_t n, const Lev& L, const tfs::Levels& lv,
-                  double* tau) {
+                  double* tau, double* diag) {
   constexpr int C = Sym<D>::C;
   hipStream_t st = p->stream;
   const int bp = blocks_for(s->npoints);
@@ -761,6 +795,10 @@ tfs_status step_d(tfs_transport_s* s, const tfs_plan_s* p, int64_t n, const Lev&
     if ((r = solve<D>(s, st, L, p->a_diag, p->eta, true, 1.0, lv.Xo)) != TFS_OK) return r;
     hipLaunchKernelGGL(bdf2_finish_kernel<D>, dim3(bp), dim3(kTBlock), 0, st, lv.Xo, tau, p->eta, p->tau_scale, P,
                        sd);
+  }
+  if (diag) {   // s->part (kMeanBlocks x (d*d + d) >= kMeanBlocks x 6 doubles) is free again
+    hipLaunchKernelGGL(diag_partial_kernel<D>, dim3(kMeanBlocks), dim3(kTBlock), 0, st, lv.Xo, tau, P, sd, s->part);
+    hipLaunchKernelGGL(diag_fold_kernel, dim3(1), dim3(kTBlock), 0, st, s->part, kMeanBlocks, diag);
   }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? TFS_OK : hip_fail(e, "transport step launch");
@@ -884,7 +922,7 @@ tfs_status tfs_transport_set_batched(tfs_transport s, int on) {
 }
 
 tfs_status tfs_transport_step(tfs_transport s, tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b,
-                              const double* u_a, const double* u_b, double* X, void* Y, double* tau) {
+                              const double* u_a, const double* u_b, double* X, void* Y, double* tau, double* diag) {
   if (!s || !p) return set_error(TFS_EINVAL, "null transport object or plan");
   if (p->d != s->dim || p->npoints != s->npoints || p->stride != s->stride)
     return set_error(TFS_EINVAL, "plan does not match the transport object (dim, npoints, stride)");
@@ -928,8 +966,8 @@ tfs_status tfs_transport_step(tfs_transport s, tfs_plan p, int64_t n, const doub
     lv.Yo = Yb + sm * ys * eb;
   }
   if (p->precision == TFS_FP64)
-    return s->dim == 2 ? step_d<2, double>(s, p, n, L, lv, tau) : step_d<3, double>(s, p, n, L, lv, tau);
-  return s->dim == 2 ? step_d<2, float>(s, p, n, L, lv, tau) : step_d<3, float>(s, p, n, L, lv, tau);
+    return s->dim == 2 ? step_d<2, double>(s, p, n, L, lv, tau, diag) : step_d<3, double>(s, p, n, L, lv, tau, diag);
+  return s->dim == 2 ? step_d<2, float>(s, p, n, L, lv, tau, diag) : step_d<3, float>(s, p, n, L, lv, tau, diag);
 }
 
 }  // extern "C"

@@ -105,7 +105,7 @@ def lib():
     L.tfs_ns_set_transport.argtypes = [vp, vp]
     L.tfs_transport_create.argtypes = [C.c_int, C.POINTER(i64), dp, C.c_double, i64, C.c_int, C.POINTER(C.c_void_p)]
     L.tfs_transport_destroy.argtypes = [vp]
-    L.tfs_transport_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.tfs_transport_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     L.tfs_transport_batched.argtypes = [vp]
     L.tfs_transport_batched.restype = C.c_int
     L.tfs_transport_set_batched.argtypes = [vp, C.c_int]

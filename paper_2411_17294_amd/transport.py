@@ -53,8 +53,9 @@ class Transport:
         except Exception:
             pass
 
-    def step(self, n, kappa_a, kappa_b, u_a, u_b, X, Y, tau):
-        """Step n -> n+1 (tfs_transport_step); kappa_b / u_b None for given levels."""
+    def step(self, n, kappa_a, kappa_b, u_a, u_b, X, Y, tau, diag=None):
+        """Step n -> n+1 (tfs_transport_step); kappa_b / u_b None for given levels; diag an
+        optional device [6] FP64 tensor for the diagnostics of level n+1."""
         import torch
         p, st = self.plan, self.plan.stride
         for t, nm, k in ((kappa_a, "kappa_a", p.dim * p.dim), (kappa_b, "kappa_b", p.dim * p.dim),
@@ -62,6 +63,7 @@ class Transport:
             p._need(t, nm, k * st, torch.float64)
         p._need(X, "X", 2 * p.c * st, torch.float64)
         p._need(Y, "Y", p.mode_levels * p.m * p.c * st, p.mode_dtype)
+        p._need(diag, "diag", 6, torch.float64)
         ptr = lambda t: None if t is None else t.data_ptr()
         tfs.check(tfs.lib().tfs_transport_step(self._h, p.handle, int(n), ptr(kappa_a), ptr(kappa_b), ptr(u_a),
-                                               ptr(u_b), X.data_ptr(), Y.data_ptr(), tau.data_ptr()))
+                                               ptr(u_b), X.data_ptr(), Y.data_ptr(), tau.data_ptr(), ptr(diag)))

@@ -46,7 +46,7 @@ def fields(d, shape, extent, nlev, seed, u_amp=0.3, k_amp=0.3, uniform=False):
 
 
 def gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, extrap, iters, batched=True,
-            method="splitting"):
+            method="splitting", want_diag=False):
     P = int(np.prod(shape))
     c = d * (d + 1) // 2
     plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec)
@@ -62,17 +62,20 @@ def gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, e
         .reshape(rows, st).contiguous()
     kl = [dev(kap[i], d * d) for i in range(kap.shape[0])]
     ul = [dev(u[i], d) for i in range(u.shape[0])]
+    diag = torch.zeros(6, dtype=torch.float64, device="cuda") if want_diag else None
     for n in range(N):
+        dg = diag if n == N - 1 else None
         if extrap:
-            tr.step(n, kl[n], kl[n - 1] if n >= 1 else None, ul[n], ul[n - 1] if n >= 1 else None, X, Y, tau)
+            tr.step(n, kl[n], kl[n - 1] if n >= 1 else None, ul[n], ul[n - 1] if n >= 1 else None, X, Y, tau, dg)
         else:
-            tr.step(n, kl[n + 1], None, ul[n + 1], None, X, Y, tau)
+            tr.step(n, kl[n + 1], None, ul[n + 1], None, X, Y, tau, dg)
     torch.cuda.synchronize()
     o = torch.zeros((plan.m, c, st), dtype=torch.float64, device="cuda")
     plan.modes_to_plain(N % 2, X, Y, o)
     torch.cuda.synchronize()
     return {"X": np.stack([X[N % 2, :, :P].cpu().numpy(), X[(N - 1) % 2, :, :P].cpu().numpy()]),
-            "tau": tau[:, :P].cpu().numpy(), "modes": o[:, :, :P].cpu().numpy()}
+            "tau": tau[:, :P].cpu().numpy(), "modes": o[:, :, :P].cpu().numpy(),
+            "diag": diag.cpu().numpy() if want_diag else None}
 
 
 CASES = [(2, (6, 8), (1.0, 2.0)), (2, (7, 6), (1.5, 1.0)), (3, (4, 4, 6), (1.0, 2.0, 3.0))]
@@ -223,3 +226,38 @@ def test_uniform_fields_full_size_sampled_coefficients(d, n, prec):
         worst = max(worst, float(np.max(np.abs(got - want)) / np.max(np.abs(want))))
     print(f"full-size uniform transport d={d} n={n} {prec}: worst sampled coefficient {worst:.2e}", flush=True)
     assert worst < (1e-10 if prec == "fp64" else 1e-5)
+
+
+def host_diag(d, X, tau):
+    """The diagnostics' definitions: leading principal minors of C = I + X (min over points),
+    max and sum over points of ||tau||_F^2 (full tensor), non-finite count."""
+    c = d * (d + 1) // 2
+    pairs = {2: ((0, 0), (1, 1), (0, 1)), 3: ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))}[d]
+    P = X.shape[1]
+    Cm = np.zeros((P, d, d))
+    Tm = np.zeros((P, d, d))
+    for s, (i, j) in enumerate(pairs):
+        Cm[:, i, j] = Cm[:, j, i] = X[s]
+        Tm[:, i, j] = Tm[:, j, i] = tau[s]
+    Cm += np.eye(d)
+    m1 = np.min(Cm[:, 0, 0])
+    m2 = np.min(np.linalg.det(Cm[:, :2, :2]))
+    m3 = np.min(np.linalg.det(Cm)) if d == 3 else m2
+    f2 = np.sum(Tm * Tm, axis=(1, 2))
+    return np.array([m1, m2, m3, np.sqrt(np.max(f2)), np.sum(f2), 0.0])
+
+
+@pytest.mark.parametrize("d,shape,extent", CASES)
+def test_transport_diagnostics(d, shape, extent):
+    """The diagnostics of the last step against their definitions on the oracle's X and tau."""
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    N, De, eta_p, eps, dt = 5, 0.8, 0.1, 0.05, 2e-3
+    w, lam, _ = osoe.soe_fit(0.5, 6, dt, dt * N)
+    u, kap = fields(d, shape, extent, N + 1, 95 + d)
+    X0 = np.random.default_rng(96).standard_normal((c, P)) * 0.05
+    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, "fp64", True, 40, want_diag=True)
+    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, u=u)
+    want = host_diag(d, o["X"][0], o["tau"])
+    print("diag", g["diag"], want, flush=True)
+    np.testing.assert_allclose(g["diag"], want, rtol=1e-11, atol=1e-14)
