@@ -270,26 +270,9 @@ def _mfp_2d(stream, steps):
             "frac": gbs / HBM_PEAK_GBS, "traffic": profiled_traffic("bdf2_kernel_" + name)}
 
 
-def synthetic_velocity(d, n, seed, k0=4.0):
-    """A seeded random grid velocity on [0, 2 pi)^d with the isotropic spectrum shape
-    E(k) ~ k^4 exp(-2 (k/k0)^2) of synthetic decaying-turbulence initial data, rms 1 per
-    component ([d][n^d], C order; the solver keeps its solenoidal part)."""
-    import torch
-    g = torch.Generator(device="cuda").manual_seed(seed)
-    f = torch.randn((d,) + (n,) * d, dtype=torch.float64, device="cuda", generator=g)
-    F = torch.fft.rfftn(f, dim=tuple(range(1, d + 1)))
-    ks = [torch.fft.fftfreq(n, 1.0 / n, dtype=torch.float64, device="cuda")] * (d - 1) + \
-        [torch.fft.rfftfreq(n, 1.0 / n, dtype=torch.float64, device="cuda")]
-    K2 = sum(k * k for k in torch.meshgrid(*ks, indexing="ij"))
-    F = F * (K2 * torch.exp(-K2 / (k0 * k0)))
-    u = torch.fft.irfftn(F, s=(n,) * d, dim=tuple(range(1, d + 1)))
-    u = u / u.pow(2).mean(dim=tuple(range(1, d + 1)), keepdim=True).sqrt()
-    return u.reshape(d, n ** d)
-
-
 def _ns_coupled(stream, steps):
     """The coupled step (tfs_ns_step: the velocity by the projection method, then the stress
-    update with the new gradient) on [0, 2 pi)^d from synthetic_velocity, beta = 0.9 at
+    update with the new gradient) on [0, 2 pi)^d from device_inputs.synthetic_velocity, beta = 0.9 at
     Re = 1000 (nu = 9e-4, eta_p = 1e-4), De = 1, alpha = 0.5, dt = 1e-3: 1024^2 with m = 32
     FP64 modes and 128^3 with m = 32 FP32 modes.  Per configuration the ms of a coupled step,
     of the stress update alone (tfs_step with the same kappa, timed after the coupled steps)
@@ -297,6 +280,7 @@ def _ns_coupled(stream, steps):
     import math
     import torch
     from paper_2411_17294_amd import ns, tfs
+    from paper_2411_17294_amd.device_inputs import synthetic_velocity
     res = {}
     for name, d, n, prec in (("ns_coupled_2d_1024sq_m32_fp64", 2, 1024, "fp64"),
                              ("ns_coupled_3d_128cube_m32_fp32modes", 3, 128, "fp32_modes")):
@@ -334,7 +318,7 @@ def _ns_coupled(stream, steps):
 def _transport(stream, steps):
     """The stress update with the MFP transport terms (tfs_transport_step: advection by u and
     centre-of-mass diffusion eps = 0.1 inside the implicit operator) on [0, 2 pi)^2, 1024^2,
-    m = 32 FP64 modes, with u from synthetic_velocity and kappa = grad u (steady levels),
+    m = 32 FP64 modes, with u from device_inputs.synthetic_velocity and kappa = grad u (steady levels),
     De = 1, alpha = 0.5, eta_p = 1e-4, dt = 1e-3: ms per step with 10 and 20 splitting
     iterations and 10 and 20 GMRES steps per solve, the relative difference of X from the
     20-step GMRES result after the same steps (the solvers' convergence), and the pointwise
@@ -342,6 +326,7 @@ def _transport(stream, steps):
     import math
     import torch
     from paper_2411_17294_amd import ns, tfs
+    from paper_2411_17294_amd.device_inputs import synthetic_velocity
     from paper_2411_17294_amd.transport import Transport
     n, m, alpha, De, dt, eps = 1024, 32, 0.5, 1.0, 1e-3, 0.1
     P = n * n

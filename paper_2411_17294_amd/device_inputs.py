@@ -62,3 +62,19 @@ def x0_ring(wl: I.Workload, stride: int, device="cuda", points=None):
     X = torch.zeros((2, wl.c, stride), dtype=torch.float64, device=device)
     X[0, :, :P] = torch.from_numpy(X0).to(device)
     return X
+
+
+def synthetic_velocity(d, n, seed, k0=4.0):
+    """A seeded random grid velocity on [0, 2 pi)^d with the isotropic spectrum shape
+    E(k) ~ k^4 exp(-2 (k/k0)^2) of synthetic decaying-turbulence initial data, rms 1 per
+    component ([d][n^d], C order; the solver keeps its solenoidal part)."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    f = torch.randn((d,) + (n,) * d, dtype=torch.float64, device="cuda", generator=g)
+    F = torch.fft.rfftn(f, dim=tuple(range(1, d + 1)))
+    ks = [torch.fft.fftfreq(n, 1.0 / n, dtype=torch.float64, device="cuda")] * (d - 1) + \
+        [torch.fft.rfftfreq(n, 1.0 / n, dtype=torch.float64, device="cuda")]
+    K2 = sum(k * k for k in torch.meshgrid(*ks, indexing="ij"))
+    F = F * (K2 * torch.exp(-K2 / (k0 * k0)))
+    u = torch.fft.irfftn(F, s=(n,) * d, dim=tuple(range(1, d + 1)))
+    u = u / u.pow(2).mean(dim=tuple(range(1, d + 1)), keepdim=True).sqrt()
+    return u.reshape(d, n ** d)
