@@ -80,9 +80,10 @@ tfs_status tfs_transport_set_method(tfs_transport tr, int method);
  * [d][stride] following kappa's rule (extrapolated 2 u_a - u_b when kappa_b is given and
  * n >= 1, else u_a).  The plan must match the object (dim, npoints, stride), be pointwise
  * (no tfs_plan_set_spatial) and use the BDF2 scheme.  diag (device [6] FP64, or NULL)
- * receives tfs_step's diagnostics of level n+1 (TFS_FLAG_CHECK_SYNC is not applied here).
+ * receives tfs_step's diagnostics of level n+1; TFS_FLAG_CHECK_SYNC acts as in tfs_step.
  * Errors: TFS_EINVAL (null or mismatched arguments, u_b missing while kappa_b is given),
- * TFS_EUNSUPPORTED (exponential scheme, spatial form), TFS_EHIP.
+ * TFS_EUNSUPPORTED (exponential scheme, spatial form), TFS_EHIP, TFS_ENUMERIC (only with
+ * TFS_FLAG_CHECK_SYNC).
  */
 tfs_status tfs_transport_step(tfs_transport tr, tfs_plan plan, int64_t n, const double* kappa_a,
                               const double* kappa_b, const double* u_a, const double* u_b, double* X, void* Y,

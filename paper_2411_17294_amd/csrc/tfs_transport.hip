@@ -965,9 +965,24 @@ tfs_status tfs_transport_step(tfs_transport s, tfs_plan p, int64_t n, const doub
     lv.Ym = Yb + sm * ys * eb;
     lv.Yo = Yb + sm * ys * eb;
   }
+  tfs_status r;
   if (p->precision == TFS_FP64)
-    return s->dim == 2 ? step_d<2, double>(s, p, n, L, lv, tau, diag) : step_d<3, double>(s, p, n, L, lv, tau, diag);
-  return s->dim == 2 ? step_d<2, float>(s, p, n, L, lv, tau, diag) : step_d<3, float>(s, p, n, L, lv, tau, diag);
+    r = s->dim == 2 ? step_d<2, double>(s, p, n, L, lv, tau, diag) : step_d<3, double>(s, p, n, L, lv, tau, diag);
+  else
+    r = s->dim == 2 ? step_d<2, float>(s, p, n, L, lv, tau, diag) : step_d<3, float>(s, p, n, L, lv, tau, diag);
+  if (r != TFS_OK || !(p->flags & TFS_FLAG_CHECK_SYNC)) return r;
+  // as tfs_step: synchronise, and with diagnostics refuse non-finite or non-positive-definite levels
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (diag) {
+    double h[tfs::kNumDiag];
+    e = hipMemcpy(h, diag, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "diagnostic read-back");
+    if (h[5] != 0.0) return set_error(TFS_ENUMERIC, "non-finite entries in the new level");
+    if (!(h[0] > 0.0 && h[1] > 0.0 && h[2] > 0.0))
+      return set_error(TFS_ENUMERIC, "conformation not positive definite in the new level");
+  }
+  return TFS_OK;
 }
 
 }  // extern "C"

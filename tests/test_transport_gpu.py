@@ -261,3 +261,23 @@ def test_transport_diagnostics(d, shape, extent):
     want = host_diag(d, o["X"][0], o["tau"])
     print("diag", g["diag"], want, flush=True)
     np.testing.assert_allclose(g["diag"], want, rtol=1e-11, atol=1e-14)
+
+
+def test_transport_check_sync_flags_a_non_positive_conformation():
+    """With TFS_FLAG_CHECK_SYNC the step synchronises and refuses a level whose C = I + X is
+    not positive definite (X^0 = -2 I, a finite input the kernels process normally)."""
+    d, shape, extent = 2, (8, 8), (1.0, 1.0)
+    P = 64
+    w, lam, _ = osoe.soe_fit(0.5, 4, 1e-3, 1e-2)
+    plan = tfs.Plan(d, P, w, lam, 0.5, 1.0, 0.1, 1e-3, 4, flags=tfs.TFS_FLAG_CHECK_SYNC)
+    tr = Transport(plan, shape, extent, 0.05, 5)
+    X, Y, tau, diag = plan.alloc()
+    k = torch.zeros((4, plan.stride), dtype=torch.float64, device="cuda")
+    u = torch.zeros((2, plan.stride), dtype=torch.float64, device="cuda")
+    tr.step(0, k, None, u, None, X, Y, tau, diag)                    # identity conformation: fine
+    X[0, 0, :P] = -2.0
+    X[0, 1, :P] = -2.0
+    X[0, 2, :P] = 0.0
+    with pytest.raises(tfs.TfsError) as e:
+        tr.step(0, k, None, u, None, X, Y, tau, diag)
+    assert e.value.status == tfs.TFS_ENUMERIC
