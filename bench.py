@@ -586,9 +586,15 @@ def cpu_baseline(wl, alpha, w, lam, nthreads):
     O.run(wl.dim, w, lam, wl.De, wl.eta_p, wl.dt, wl.nsteps, kap, X0, nthreads=nthreads)
     el = time.perf_counter() - t0
     rate = len(pts) * len(w) * wl.nsteps / el
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": rate, "unit": "point-mode updates/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{len(pts)} points (every 2nd of {wl.grid}^{wl.dim}), {wl.nsteps} steps, alpha={alpha}, "
-                      f"m={len(w)}, FP64, {el:.1f} s"}
+                      f"m={len(w)}, FP64, {el:.1f} s", "cpu_model": model}
 
 
 def main():
