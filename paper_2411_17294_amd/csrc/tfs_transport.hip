@@ -36,9 +36,10 @@ struct tfs_transport_s {
   bool have_fwd = false, have_inv = false;
   // batched plans over c planes (forward and back) and c d planes (back), planes `stride`
   // apart on the grid; used where hipFFT takes that layout
-  hipfftHandle bf = 0, bi = 0, bid = 0;
+  hipfftHandle bf = 0, bi = 0, bid = 0, bia = 0;   // bia: c (1 + d) planes (X, then grad X)
   bool batched = false;
-  // grid planes: right-hand side, SDIRK2 stage-1 value, fluctuation, iterate, gradients (c d)
+  // grid planes: right-hand side, SDIRK2 stage-1 value, fluctuation, iterate and, right after
+  // it in the same allocation, its gradients (c d planes: dg = xg + c stride)
   double *rg = nullptr, *x1g = nullptr, *fg = nullptr, *xg = nullptr, *dg = nullptr;
   // spectral planes: right-hand side, iterate, fluctuation, extra term, inverse inputs (c + c d)
   double2 *rh = nullptr, *xh = nullptr, *fh = nullptr, *eh = nullptr, *iv = nullptr;
@@ -505,10 +506,13 @@ void make_batched(tfs_transport_s* s) {
   const bool okf = hipfftPlanMany(&s->bf, dim, nn, eg, 1, gd, es, 1, sd, HIPFFT_D2Z, c) == HIPFFT_SUCCESS;
   const bool oki = okf && hipfftPlanMany(&s->bi, dim, nn, es, 1, sd, eg, 1, gd, HIPFFT_Z2D, c) == HIPFFT_SUCCESS;
   const bool okd = oki && hipfftPlanMany(&s->bid, dim, nn, es, 1, sd, eg, 1, gd, HIPFFT_Z2D, c * dim) == HIPFFT_SUCCESS;
-  s->batched = okd;
-  if (!okd) {
+  const bool oka = okd && hipfftPlanMany(&s->bia, dim, nn, es, 1, sd, eg, 1, gd, HIPFFT_Z2D, c + c * dim) ==
+                              HIPFFT_SUCCESS;
+  s->batched = oka;
+  if (!oka) {
     if (okf) hipfftDestroy(s->bf);
     if (oki) hipfftDestroy(s->bi);
+    if (okd) hipfftDestroy(s->bid);
   }
 }
 
@@ -517,6 +521,7 @@ void drop_batched(tfs_transport_s* s) {
   hipfftDestroy(s->bf);
   hipfftDestroy(s->bi);
   hipfftDestroy(s->bid);
+  hipfftDestroy(s->bia);
   s->batched = false;
 }
 
@@ -587,8 +592,9 @@ tfs_status forward_planes(tfs_transport_s* s, const double* grid, double2* spec,
 
 tfs_status inverse_planes(tfs_transport_s* s, double2* spec, double* grid, int count) {
   const int c = s->dim * (s->dim + 1) / 2;
-  if (s->batched && (count == c || count == c * s->dim)) {
-    const hipfftResult r = hipfftExecZ2D(count == c ? s->bi : s->bid, (hipfftDoubleComplex*)spec, grid);
+  if (s->batched && (count == c || count == c * s->dim || count == c + c * s->dim)) {
+    const hipfftHandle h = count == c ? s->bi : (count == c * s->dim ? s->bid : s->bia);
+    const hipfftResult r = hipfftExecZ2D(h, (hipfftDoubleComplex*)spec, grid);
     return r == HIPFFT_SUCCESS ? TFS_OK : hipfft_fail(r, "hipfftExecZ2D");
   }
   for (int i = 0; i < count; ++i) {
@@ -631,8 +637,7 @@ tfs_status solve(tfs_transport_s* s, hipStream_t st, const Lev& L, double a, dou
   }
   A.fh = s->fh;
   for (int it = 0; it < s->iters; ++it) {
-    if ((r = inverse_planes(s, s->iv, s->xg, C)) != TFS_OK) return r;
-    if ((r = inverse_planes(s, s->iv + (int64_t)C * s->nc, s->dg, C * D)) != TFS_OK) return r;
+    if ((r = inverse_planes(s, s->iv, s->xg, C + C * D)) != TFS_OK) return r;    // X and grad X
     hipLaunchKernelGGL(fluct_kernel<D>, dim3(bp), dim3(kTBlock), 0, st, s->xg, s->dg, L, s->mean, b, s->npoints,
                        s->stride, s->fg);
     if ((r = forward_planes(s, s->fg, s->fh, C)) != TFS_OK) return r;
@@ -649,8 +654,7 @@ tfs_status apply_fluct(tfs_transport_s* s, hipStream_t st, const Lev& L, double 
   constexpr int C = Sym<D>::C;
   hipLaunchKernelGGL(deriv_kernel<D>, dim3(blocks_for(s->nc)), dim3(kTBlock), 0, st, geom(s), s->nc, 1.0, v, true,
                      s->iv);
-  tfs_status r = inverse_planes(s, s->iv, s->xg, C);
-  if (r == TFS_OK) r = inverse_planes(s, s->iv + (int64_t)C * s->nc, s->dg, C * D);
+  tfs_status r = inverse_planes(s, s->iv, s->xg, C + C * D);                     // X and grad X
   if (r != TFS_OK) return r;
   hipLaunchKernelGGL(fluct_kernel<D>, dim3(blocks_for(s->npoints)), dim3(kTBlock), 0, st, s->xg, s->dg, L, s->mean,
                      b, s->npoints, s->stride, s->fg);
@@ -842,8 +846,8 @@ tfs_status tfs_transport_create(int dim, const int64_t* shape, const double* ext
   hipError_t e = hipMalloc((void**)&s->rg, gp * c);
   if (e == hipSuccess) e = hipMalloc((void**)&s->x1g, gp * c);
   if (e == hipSuccess) e = hipMalloc((void**)&s->fg, gp * c);
-  if (e == hipSuccess) e = hipMalloc((void**)&s->xg, gp * c);
-  if (e == hipSuccess) e = hipMalloc((void**)&s->dg, gp * cd);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->xg, gp * (c + cd));
+  if (e == hipSuccess) s->dg = s->xg + (int64_t)c * stride;
   if (e == hipSuccess) e = hipMalloc((void**)&s->rh, sp * c);
   if (e == hipSuccess) e = hipMalloc((void**)&s->xh, sp * c);
   if (e == hipSuccess) e = hipMalloc((void**)&s->fh, sp * c);
@@ -880,7 +884,7 @@ tfs_status tfs_transport_destroy(tfs_transport s) {
   if (s->have_fwd) hipfftDestroy(s->fwd);
   if (s->have_inv) hipfftDestroy(s->inv);
   drop_batched(s);
-  for (double* b : {s->rg, s->x1g, s->fg, s->xg, s->dg, s->part, s->mean, s->basis, s->dpart, s->coef})
+  for (double* b : {s->rg, s->x1g, s->fg, s->xg, s->part, s->mean, s->basis, s->dpart, s->coef})
     if (b) (void)hipFree(b);
   for (double2* b : {s->rh, s->xh, s->fh, s->eh, s->iv})
     if (b) (void)hipFree(b);
@@ -937,6 +941,7 @@ tfs_status tfs_transport_step(tfs_transport s, tfs_plan p, int64_t n, const doub
   if (fr == HIPFFT_SUCCESS && s->batched) fr = hipfftSetStream(s->bf, p->stream);
   if (fr == HIPFFT_SUCCESS && s->batched) fr = hipfftSetStream(s->bi, p->stream);
   if (fr == HIPFFT_SUCCESS && s->batched) fr = hipfftSetStream(s->bid, p->stream);
+  if (fr == HIPFFT_SUCCESS && s->batched) fr = hipfftSetStream(s->bia, p->stream);
   if (fr != HIPFFT_SUCCESS) return hipfft_fail(fr, "hipfftSetStream");
   Lev L;
   L.ka = kappa_a;
