@@ -75,6 +75,19 @@ tfs_status tfs_transport_set_batched(tfs_transport tr, int on);
 tfs_status tfs_transport_set_method(tfs_transport tr, int method);
 
 /*
+ * Early exit of the solves: with tol > 0 the splitting stops once an iteration changes the
+ * coefficients by at most tol relative to their norm, tested every `every` iterations (one
+ * stream synchronisation per test), and GMRES once its relative residual is at most tol;
+ * `iters` stays the cap.  tol = 0 (the default) restores the fixed counts (GMRES still stops
+ * at 1e-15).  Errors: TFS_EINVAL (null object, tol < 0 or not finite, every < 1).
+ */
+tfs_status tfs_transport_set_tolerance(tfs_transport tr, double tol, int every);
+
+/* Iterations (or Arnoldi steps) the longest solve of the last tfs_transport_step took; -1
+ * for a null object. */
+int tfs_transport_last_iterations(tfs_transport tr);
+
+/*
  * One step n -> n+1 of a TFS_SCHEME_BDF2 plan with the transport terms: as tfs_step (the
  * same X and Y rings, SDIRK2 at n = 0, BDF2 after), with the velocity levels u_a, u_b
  * [d][stride] following kappa's rule (extrapolated 2 u_a - u_b when kappa_b is given and

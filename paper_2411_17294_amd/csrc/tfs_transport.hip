@@ -47,6 +47,13 @@ struct tfs_transport_s {
   // GMRES (method 1): Krylov basis [iters + 1][2 c nc] doubles, dot partials, coefficients
   int method = 0;
   double *basis = nullptr, *dpart = nullptr, *coef = nullptr;
+  // early exit: relative update (splitting) or residual (GMRES) below tol, tested every
+  // `every` iterations (tol = 0: fixed counts; GMRES then stops at 1e-15); last_iters: the
+  // most iterations one solve of the last step took
+  double tol = 0.0;
+  int every = 5;
+  int last_iters = 0;
+  double* part2 = nullptr;   // [2 kDotBlocks + 2] partials and results of the convergence test
 };
 
 namespace {
@@ -460,6 +467,32 @@ __global__ __launch_bounds__(kTBlock) void normalize_kernel(const double* w, int
     out[i] = w[i] * f;
 }
 
+// part[b] = block b's share of |x - y|^2, part[kDotBlocks + b] of |x|^2.
+__global__ __launch_bounds__(kTBlock) void diff_norm_kernel(const double* x, const double* y, int64_t nv,
+                                                            double* part) {
+  __shared__ double r1[kTBlock], r2[kTBlock];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kTBlock + threadIdx.x; i < nv; i += (int64_t)gridDim.x * kTBlock) {
+    const double d = x[i] - y[i];
+    a = fma(d, d, a);
+    b = fma(x[i], x[i], b);
+  }
+  r1[threadIdx.x] = a;
+  r2[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = kTBlock / 2; h > 0; h /= 2) {
+    if ((int)threadIdx.x < h) {
+      r1[threadIdx.x] += r1[threadIdx.x + h];
+      r2[threadIdx.x] += r2[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = r1[0];
+    part[kDotBlocks + blockIdx.x] = r2[0];
+  }
+}
+
 // w = v + P(xi)^{-1} fh / points (the preconditioned operator applied to v).
 template <int D>
 __global__ __launch_bounds__(kTBlock) void gm_apply_kernel(const PrecondArgs A, const double2* v, double2* w) {
@@ -605,6 +638,18 @@ tfs_status inverse_planes(tfs_transport_s* s, double2* spec, double* grid, int c
   return TFS_OK;
 }
 
+// |x - y| <= tol |x| (real inner product over nv doubles)?  Synchronises the stream.
+tfs_status converged(tfs_transport_s* s, hipStream_t st, const double* x, const double* y, int64_t nv, bool* done) {
+  hipLaunchKernelGGL(diff_norm_kernel, dim3(kDotBlocks), dim3(kTBlock), 0, st, x, y, nv, s->part2);
+  hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(kTBlock), 0, st, s->part2, 2, s->part2 + 2 * kDotBlocks);
+  double h[2];
+  hipError_t e = hipMemcpyAsync(h, s->part2 + 2 * kDotBlocks, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "convergence test");
+  *done = std::sqrt(h[0]) <= s->tol * std::sqrt(h[1]);
+  return TFS_OK;
+}
+
 // Solve (a I - b K(kappa~) + b T) X = rhs with rhs = F^{-1}[F(rg) + alpha eps |xi|^2 E_hat]
 // (E_hat = s->eh when extra), X into out.
 template <int D>
@@ -636,14 +681,33 @@ tfs_status solve(tfs_transport_s* s, hipStream_t st, const Lev& L, double a, dou
     return inverse_planes(s, s->iv, out, C);
   }
   A.fh = s->fh;
-  for (int it = 0; it < s->iters; ++it) {
+  const int64_t nv = (int64_t)2 * C * s->nc;
+  int it = 0;
+  for (; it < s->iters; ++it) {
+    // the update is measured on checked iterations (s->eh is free during the iterations)
+    const bool check = s->tol > 0.0 && (it + 1) % s->every == 0;
     if ((r = inverse_planes(s, s->iv, s->xg, C + C * D)) != TFS_OK) return r;    // X and grad X
     hipLaunchKernelGGL(fluct_kernel<D>, dim3(bp), dim3(kTBlock), 0, st, s->xg, s->dg, L, s->mean, b, s->npoints,
                        s->stride, s->fg);
     if ((r = forward_planes(s, s->fg, s->fh, C)) != TFS_OK) return r;
+    if (check) {
+      e = hipMemcpyAsync(s->eh, s->xh, sizeof(double2) * C * s->nc, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "iterate copy");
+    }
     hipLaunchKernelGGL(precond_kernel<D>, dim3(bs), dim3(kTBlock), 0, st, A);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "solver iteration launch");
+    if (check) {
+      bool done = false;
+      if ((r = converged(s, st, reinterpret_cast<const double*>(s->xh), reinterpret_cast<const double*>(s->eh), nv,
+                         &done)) != TFS_OK)
+        return r;
+      if (done) {
+        ++it;
+        break;
+      }
+    }
   }
+  if (it > s->last_iters) s->last_iters = it;
   return inverse_planes(s, s->iv, out, C);
 }
 
@@ -731,8 +795,9 @@ tfs_status gmres(tfs_transport_s* s, hipStream_t st, const Lev& L, const Precond
     g[j + 1] = -sn[j] * g[j];
     g[j] = cs[j] * g[j];
     k = j + 1;
-    if (std::fabs(g[j + 1]) <= 1e-15 * beta || hn == 0.0) break;
+    if (std::fabs(g[j + 1]) <= (s->tol > 0.0 ? s->tol : 1e-15) * beta || hn == 0.0) break;
   }
+  if (k > s->last_iters) s->last_iters = k;
   // y from the k x k triangle, x = V y
   std::vector<double> y(k, 0.0);
   for (int i = k - 1; i >= 0; --i) {
@@ -855,6 +920,7 @@ tfs_status tfs_transport_create(int dim, const int64_t* shape, const double* ext
   if (e == hipSuccess) e = hipMalloc((void**)&s->iv, sp * (c + cd));
   if (e == hipSuccess) e = hipMalloc((void**)&s->part, sizeof(double) * kMeanBlocks * (dim * dim + dim));
   if (e == hipSuccess) e = hipMalloc((void**)&s->mean, sizeof(double) * (dim * dim + dim));
+  if (e == hipSuccess) e = hipMalloc((void**)&s->part2, sizeof(double) * (2 * kDotBlocks + 2));
   tfs_status st = TFS_OK;
   if (e != hipSuccess) st = set_error(TFS_ENOMEM, "device allocation of the transport buffers failed");
   int nn[3];
@@ -884,7 +950,7 @@ tfs_status tfs_transport_destroy(tfs_transport s) {
   if (s->have_fwd) hipfftDestroy(s->fwd);
   if (s->have_inv) hipfftDestroy(s->inv);
   drop_batched(s);
-  for (double* b : {s->rg, s->x1g, s->fg, s->xg, s->part, s->mean, s->basis, s->dpart, s->coef})
+  for (double* b : {s->rg, s->x1g, s->fg, s->xg, s->part, s->mean, s->basis, s->dpart, s->coef, s->part2})
     if (b) (void)hipFree(b);
   for (double2* b : {s->rh, s->xh, s->fh, s->eh, s->iv})
     if (b) (void)hipFree(b);
@@ -893,6 +959,16 @@ tfs_status tfs_transport_destroy(tfs_transport s) {
 }
 
 int tfs_transport_batched(tfs_transport s) { return s && s->batched ? 1 : 0; }
+
+tfs_status tfs_transport_set_tolerance(tfs_transport s, double tol, int every) {
+  if (!s) return set_error(TFS_EINVAL, "null transport object");
+  if (!(std::isfinite(tol) && tol >= 0.0) || every < 1) return set_error(TFS_EINVAL, "need tol >= 0 and every >= 1");
+  s->tol = tol;
+  s->every = every;
+  return TFS_OK;
+}
+
+int tfs_transport_last_iterations(tfs_transport s) { return s ? s->last_iters : -1; }
 
 tfs_status tfs_transport_set_method(tfs_transport s, int method) {
   if (!s) return set_error(TFS_EINVAL, "null transport object");
@@ -970,6 +1046,7 @@ tfs_status tfs_transport_step(tfs_transport s, tfs_plan p, int64_t n, const doub
     lv.Ym = Yb + sm * ys * eb;
     lv.Yo = Yb + sm * ys * eb;
   }
+  s->last_iters = 0;
   tfs_status r;
   if (p->precision == TFS_FP64)
     r = s->dim == 2 ? step_d<2, double>(s, p, n, L, lv, tau, diag) : step_d<3, double>(s, p, n, L, lv, tau, diag);

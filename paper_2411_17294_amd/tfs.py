@@ -28,7 +28,8 @@ EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_pl
            "tfs_status_string", "tfs_last_error",
            "tfs_ns_create", "tfs_ns_destroy", "tfs_ns_spectral_size", "tfs_ns_batched", "tfs_ns_set_batched", "tfs_ns_set_transport", "tfs_ns_init",
            "tfs_ns_step", "tfs_transport_create", "tfs_transport_destroy", "tfs_transport_step",
-           "tfs_transport_batched", "tfs_transport_set_batched", "tfs_transport_set_method")
+           "tfs_transport_batched", "tfs_transport_set_batched", "tfs_transport_set_method",
+           "tfs_transport_set_tolerance", "tfs_transport_last_iterations")
 
 
 # Mode-ring tile (points) used when the caller does not choose one; measured best on
@@ -110,6 +111,9 @@ def lib():
     L.tfs_transport_batched.restype = C.c_int
     L.tfs_transport_set_batched.argtypes = [vp, C.c_int]
     L.tfs_transport_set_method.argtypes = [vp, C.c_int]
+    L.tfs_transport_set_tolerance.argtypes = [vp, C.c_double, C.c_int]
+    L.tfs_transport_last_iterations.argtypes = [vp]
+    L.tfs_transport_last_iterations.restype = C.c_int
     L.tfs_ns_init.argtypes = [vp, vp, vp, vp, vp]
     L.tfs_ns_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     for name in ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
@@ -118,7 +122,8 @@ def lib():
                  "tfs_plan_tables", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
                  "tfs_ns_create", "tfs_ns_destroy", "tfs_ns_set_batched", "tfs_ns_set_transport", "tfs_ns_init", "tfs_ns_step",
                  "tfs_transport_create", "tfs_transport_destroy", "tfs_transport_step",
-           "tfs_transport_batched", "tfs_transport_set_batched", "tfs_transport_set_method"):
+           "tfs_transport_batched", "tfs_transport_set_batched", "tfs_transport_set_method",
+           "tfs_transport_set_tolerance", "tfs_transport_last_iterations"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -38,6 +38,14 @@ class Transport:
         """"splitting" (the default) or "gmres" for the implicit solve."""
         tfs.check(tfs.lib().tfs_transport_set_method(self._h, {"splitting": 0, "gmres": 1}[method]))
 
+    def set_tolerance(self, tol: float, every: int = 5):
+        """Early exit of the solves at relative tolerance tol (0: fixed iteration counts)."""
+        tfs.check(tfs.lib().tfs_transport_set_tolerance(self._h, float(tol), int(every)))
+
+    @property
+    def last_iterations(self) -> int:
+        return int(tfs.lib().tfs_transport_last_iterations(self._h))
+
     @property
     def handle(self):
         return self._h

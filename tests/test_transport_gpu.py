@@ -281,3 +281,34 @@ def test_transport_check_sync_flags_a_non_positive_conformation():
     with pytest.raises(tfs.TfsError) as e:
         tr.step(0, k, None, u, None, X, Y, tau, diag)
     assert e.value.status == tfs.TFS_ENUMERIC
+
+
+@pytest.mark.parametrize("method", ["splitting", "gmres"])
+def test_transport_tolerance_stops_early(method):
+    """With a tolerance the solves stop before the cap and still meet the oracle to about
+    that tolerance; the iteration count is reported."""
+    d, shape, extent = 2, (6, 8), (1.0, 2.0)
+    P, c, N = 48, 3, 4
+    De, eta_p, eps, dt = 0.8, 0.1, 0.05, 2e-3
+    w, lam, _ = osoe.soe_fit(0.5, 6, dt, dt * N)
+    u, kap = fields(d, shape, extent, N + 1, 57)
+    X0 = np.random.default_rng(58).standard_normal((c, P)) * 0.05
+    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, N)
+    tr = Transport(plan, shape, extent, eps, 200)
+    tr.set_method(method)
+    tr.set_tolerance(1e-13, 2)
+    st = plan.stride
+    X, Y, tau, _ = plan.alloc()
+    X[0, :, :P] = torch.from_numpy(X0).cuda()
+    dev = lambda a, rows: torch.nn.functional.pad(torch.from_numpy(np.ascontiguousarray(a)), (0, st - P)).cuda() \
+        .reshape(rows, st).contiguous()
+    iters = []
+    for n in range(N):
+        tr.step(n, dev(kap[n], 4), dev(kap[n - 1], 4) if n else None, dev(u[n], 2), dev(u[n - 1], 2) if n else None,
+                X, Y, tau)
+        torch.cuda.synchronize()
+        iters.append(tr.last_iterations)
+    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, u=u)
+    err = relerr(X[N % 2, :, :P].cpu().numpy(), o["X"][0])
+    print(method, "iterations per step", iters, "error", err, flush=True)
+    assert all(0 < i < 200 for i in iters) and err < 1e-11
