@@ -78,7 +78,8 @@ def gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, e
             "diag": diag.cpu().numpy() if want_diag else None}
 
 
-CASES = [(2, (6, 8), (1.0, 2.0)), (2, (7, 6), (1.5, 1.0)), (3, (4, 4, 6), (1.0, 2.0, 3.0))]
+# (5, 7): an odd number of points (the split kernel's one-point tail pass) and odd axes
+CASES = [(2, (6, 8), (1.0, 2.0)), (2, (7, 6), (1.5, 1.0)), (2, (5, 7), (1.0, 1.3)), (3, (4, 4, 6), (1.0, 2.0, 3.0))]
 
 
 @pytest.mark.parametrize("batched", [True, False])
