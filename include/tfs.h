@@ -140,10 +140,9 @@ tfs_status tfs_plan_set_stream(tfs_plan plan, void* stream);
  * source_point  the point that holds the constant basis function's coefficient (it alone
  *               gets the mass-mode source), or -1: every point gets it (the plain
  *               pointwise form).
- * Applies to tfs_step, tfs_step_levels and, for TFS_SCHEME_BDF2 plans, tfs_step_adjoint
- * until it is called again; rate = NULL with source_point = -1 restores the pointwise form.
- * The adjoint of an exponential-scheme plan returns TFS_EUNSUPPORTED while a spatial form
- * is set.  With a rate field the adjoint also accumulates sum_p rate_p dL/drate_p
+ * Applies to tfs_step, tfs_step_levels and tfs_step_adjoint (either scheme) until it is
+ * called again; rate = NULL with source_point = -1 restores the pointwise form.
+ * With a rate field the adjoint also accumulates sum_p rate_p dL/drate_p
  * (tfs_pbar_rate_gradient): for rate = eps |xi|^2 that is eps dL/deps.  The diagnostics'
  * minors do not describe a conformation tensor in this form; TFS_FLAG_CHECK_SYNC then
  * checks only the non-finite count.
@@ -278,8 +277,12 @@ tfs_status tfs_step_levels(tfs_plan plan, int64_t n, const double* kappa_a, cons
  *   pbar                device [tfs_pbar_size] FP64, accumulated: gradients of the per-mode
  *                       factors, the scalar factors and zeta^{n+1}; convert with
  *                       tfs_pbar_to_params.
+ * TFS_SCHEME_EXP plans: X_nm1 and Y_nm1 are unused (X_np1 is read at every n, Y_n for
+ * n >= 1); Xbar is the same ring (slot (n+1)%2 holds dL/dX^{n+1} complete, slot n%2
+ * receives dL/dX^n), and Hbar is a single mode level holding dL/dY^{n+1} before the call and
+ * dL/dY^n after it.
  * Asynchronous on the plan's stream.  Errors: TFS_EINVAL (null required pointer, n out of
- * range), TFS_EHIP, TFS_EUNSUPPORTED (TFS_SCHEME_EXP plans: no adjoint in this build).
+ * range), TFS_EHIP.
  */
 tfs_status tfs_step_adjoint(tfs_plan plan, int64_t n, const double* kappa_a, const double* kappa_b,
                             const double* X_n, const double* X_nm1, const double* X_np1,

@@ -527,6 +527,7 @@ struct ExpAdjArgs {
   int m, part0;
   ExpScalars s;
   double dt;
+  AdjSpatial sp;
 };
 
 // TAU: this step's stress is in the loss (taubar given: the last step of a misfit).  Without
@@ -537,7 +538,10 @@ struct ExpAdjArgs {
 // modes whose forward and adjoint loads are in flight ahead of the one being updated
 constexpr int kExpAdjAhead = TFS_EXP_ADJ_AHEAD;
 
-template <int D, typename MT, int V, bool FULL, bool TAU>
+// SP: the spatial form (1/De + rate per point, a + q rate on the diagonal, the mass-mode
+// source at the source point only); sc[7] collects sum rate dL/da (a part of dL/dq) and sc[8]
+// sum rate dL/drate.
+template <int D, typename MT, int V, bool FULL, bool TAU, bool SP>
 __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const WaveAddr& w, int nv, double* smode,
                                               double* slot, double (&sc)[kNumAdjScalars]) {
   constexpr int C = Sym<D>::C;
@@ -550,8 +554,12 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
 
   // ---- local part, point by point
   double Gb[TAU ? C : 1][V], Hb[C][V], Xc[C][V], Xacc[C][V];
+  double rate[V], srcw[V];
+  if constexpr (SP) adj_spatial<FULL, V>(a.sp, at(a.sp.rate + w.pw, w.ox), w.pw + (int64_t)(w.ox / 8), nv, rate, srcw);
 #pragma unroll
   for (int v = 0; v < V; ++v) {
+    const double idv = SP ? a.s.inv_De + rate[v] : a.s.inv_De;
+    const double adg = SP ? a.s.a_diag + q * rate[v] : a.s.a_diag;
     const uint32_t ox = w.ox + v * 8;
     const int nv1 = v < nv ? 1 : 0;
     double k[D * D], xp[C], rb[C], tv[C], S[C];
@@ -595,18 +603,25 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
     }
     {
       double M[C][C];
-      build_M<D>(k, a.s.a_diag, q, M);
+      build_M<D>(k, adg, q, M);
       solve_transposed<C>(M, rb);                  // Rbar = M^{-T} Xbar
     }
     double Kx[C], u[C];
     apply_K<D>(k, xp, Kx);
-    sc[0] += -dot<C>(rb, xp);                      // a
+    const double ra = -dot<C>(rb, xp);
+    sc[0] += ra;                                   // a
     sc[1] += dot<C>(rb, Kx);                       // q (matrix)
-    sc[5] += dot<C>(rb, S);                        // zeta
+    if constexpr (SP) {
+      sc[5] += srcw[v] * dot<C>(rb, S);            // zeta (the source point only)
+      sc[7] += rate[v] * ra;                       // q through a + q rate
+      sc[8] += rate[v] * q * ra;                   // rate through a + q rate
+    } else {
+      sc[5] += dot<C>(rb, S);                      // zeta
+    }
     apply_KT<D>(k, rb, u);
 #pragma unroll
     for (int t = 0; t < C; ++t) {
-      Hb[t][v] = -u[t] + a.s.inv_De * rb[t];       // R = X^n - K H + H/De
+      Hb[t][v] = -u[t] + idv * rb[t];              // R = X^n - K H + H (1/De + rate)
       if constexpr (TAU) Gb[t][v] = -ts * tv[t];
       Xacc[t][v] = rb[t] + a.s.s_h * Hb[t][v];
       lds(v, t) = rb[t];
@@ -730,6 +745,7 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
     double Xp[C][V];
 #pragma unroll
     for (int s = 0; s < C; ++s) load_v<FULL, double, V>(at(a.Xp + s * st + w.pw, w.ox), nv, Xp[s]);
+    if constexpr (SP) adj_spatial<FULL, V>(a.sp, at(a.sp.rate + w.pw, w.ox), w.pw + (int64_t)(w.ox / 8), nv, rate, srcw);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       double Hv[C], Z[C], rb[C], kb_[D * D];
@@ -746,11 +762,13 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
         for (int s = 0; s < C; ++s) gv += Gb[s][v] * Gs[s][v];
         sc[6] += gv / ts;                          // ts (G part): -taubar . G
       }
-      sc[3] += dot<C>(rb, Hv);                     // 1/De
+      const double rh = dot<C>(rb, Hv);
+      sc[3] += rh;                                 // 1/De
+      if constexpr (SP) sc[8] += rate[v] * rh;     // rate through 1/De + rate
 #pragma unroll
       for (int t = 0; t < D * D; ++t) kb_[t] = 0.0;
       kgrad_VZ<D>(kb_, 1.0, rb, Z);
-      kgrad_V<D>(kb_, a.s.zeta, rb);
+      kgrad_V<D>(kb_, SP ? a.s.zeta * srcw[v] : a.s.zeta, rb);
 #pragma unroll
       for (int t = 0; t < D * D; ++t) kbar[t][v] = kb_[t];
     }
@@ -762,7 +780,7 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
   if (a.kbb && fb != 0.0) add_kbar<D, V, FULL>(a.kbb, fb, st, w, nv, kbar);
 }
 
-template <int D, typename MT, int V, bool FULL, bool TAU>
+template <int D, typename MT, int V, bool FULL, bool TAU, bool SP>
 __global__ __launch_bounds__(kBlock) void exp_adj_kernel(const ExpAdjArgs<MT> a) {
   constexpr int C = Sym<D>::C;
   extern __shared__ double smem[];    // [kBlock/64][3][m] mode sums, then Rbar per lane
@@ -780,7 +798,7 @@ __global__ __launch_bounds__(kBlock) void exp_adj_kernel(const ExpAdjArgs<MT> a)
        wv += wstride) {
     const WaveAddr w = wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m);
     const int nv = (FULL || wv * 64 + lane < a.ngroups) ? V : 0;
-    exp_adj_group<D, MT, V, FULL, TAU>(a, w, nv, smode, slot, sc);
+    exp_adj_group<D, MT, V, FULL, TAU, SP>(a, w, nv, smode, slot, sc);
   }
   __syncthreads();
   write_block_partial(a.part + (size_t)a.part0 * (3 * a.m + kNumAdjScalars), a.m, smode, sc);
@@ -1132,7 +1150,7 @@ size_t exp_adj_shared_bytes(const tfs_plan_s* p, int V) {
   return sizeof(double) * ((size_t)(kBlock / 64) * 3 * p->m + (size_t)p->c * V * kBlock);
 }
 
-template <int D, typename MT, int V, bool TAU>
+template <int D, typename MT, int V, bool TAU, bool SP>
 hipError_t exp_adj_go_(const tfs_plan_s* p, ExpAdjArgs<MT> a, int64_t zeta_dest, double* pbar) {
   const int64_t nwaves = p->npoints / (64 * V);
   const int64_t p_tail = nwaves * 64 * V, rest = p->npoints - p_tail;
@@ -1144,18 +1162,18 @@ hipError_t exp_adj_go_(const tfs_plan_s* p, ExpAdjArgs<MT> a, int64_t zeta_dest,
     nb = grid_adj(p, a.ngroups);
     const size_t shm = exp_adj_shared_bytes(p, V);
     if (shm > 65536) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&exp_adj_kernel<D, MT, V, true, TAU>),
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&exp_adj_kernel<D, MT, V, true, TAU, SP>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((exp_adj_kernel<D, MT, V, true, TAU>), dim3(nb), dim3(kBlock), shm, p->stream, a);
+    hipLaunchKernelGGL((exp_adj_kernel<D, MT, V, true, TAU, SP>), dim3(nb), dim3(kBlock), shm, p->stream, a);
   }
   if (rest > 0) {
     a.p_begin = p_tail;
     a.ngroups = rest;
     a.part0 = nb;
     nt = grid_adj(p, rest);
-    hipLaunchKernelGGL((exp_adj_kernel<D, MT, 1, false, TAU>), dim3(nt), dim3(kBlock), exp_adj_shared_bytes(p, 1),
+    hipLaunchKernelGGL((exp_adj_kernel<D, MT, 1, false, TAU, SP>), dim3(nt), dim3(kBlock), exp_adj_shared_bytes(p, 1),
                        p->stream, a);
   }
   const int np = 3 * p->m + kNumAdjScalars;
@@ -1166,8 +1184,11 @@ hipError_t exp_adj_go_(const tfs_plan_s* p, ExpAdjArgs<MT> a, int64_t zeta_dest,
 
 template <int D, typename MT, int V>
 hipError_t exp_adj_go(const tfs_plan_s* p, const ExpAdjArgs<MT>& a, int64_t zeta_dest, double* pbar) {
-  return a.taubar ? exp_adj_go_<D, MT, V, true>(p, a, zeta_dest, pbar)
-                  : exp_adj_go_<D, MT, V, false>(p, a, zeta_dest, pbar);
+  if (a.sp.rate || a.sp.src >= 0)
+    return a.taubar ? exp_adj_go_<D, MT, V, true, true>(p, a, zeta_dest, pbar)
+                    : exp_adj_go_<D, MT, V, false, true>(p, a, zeta_dest, pbar);
+  return a.taubar ? exp_adj_go_<D, MT, V, true, false>(p, a, zeta_dest, pbar)
+                  : exp_adj_go_<D, MT, V, false, false>(p, a, zeta_dest, pbar);
 }
 
 template <int D, typename MT>
@@ -1204,6 +1225,8 @@ hipError_t exp_adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, 
   a.s.fb = -0.5;
   a.s.first = n == 0 ? 1 : 0;
   a.dt = p->dt;
+  a.sp.rate = p->sp_rate;
+  a.sp.src = p->sp_source;
   const int64_t zd = (int64_t)kPbarScalars + 6 * p->m + n + 1;
   // one point per lane unless tuned: measured faster than two for this kernel
   const int want = p->adj_vec_override ? p->adj_vec_override : 1;

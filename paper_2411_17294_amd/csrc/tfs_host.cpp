@@ -453,6 +453,8 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   dest_e[3 * m + 4] = sb + tfs::kPeEtaE;
   dest_e[3 * m + 5] = -2;  // zeta of this step
   dest_e[3 * m + 6] = sb + tfs::kPeTs;
+  dest_e[3 * m + 7] = sb + tfs::kPeQRate;
+  dest_e[3 * m + 8] = sb + tfs::kPbRate;    // the rate gradient sits where the BDF2 scheme keeps it
   bool ok = hipMalloc(&p->d_adj_part, sizeof(double) * np * (size_t)std::max(1, p->part_cap)) == hipSuccess;
   ok = ok && hipMalloc(&p->d_dest_bdf2, sizeof(int) * np) == hipSuccess;
   ok = ok && hipMalloc(&p->d_dest_start, sizeof(int) * np) == hipSuccess;
@@ -632,7 +634,7 @@ tfs_status exp_pbar_to_params(tfs_plan p, const double* pb, double* dw, double* 
   const double* zb = pb + 6 * m + tfs::kPbarScalars;
   std::vector<double> wb(m), lb(m);
   for (int k = 0; k < m; ++k) { wb[k] = pb[k]; lb[k] = pb[m + k]; }
-  const double qb = sc[tfs::kPeQ] + sc[tfs::kPeA] * iD;
+  const double qb = sc[tfs::kPeQ] + sc[tfs::kPeA] * iD + sc[tfs::kPeQRate];
   double iDb = sc[tfs::kPeInvDe] + sc[tfs::kPeA] * p->q_e;
   const double shb = sc[tfs::kPeSh], eeb = sc[tfs::kPeEtaE], tsb = sc[tfs::kPeTs];
   const int64_t N = p->max_steps;
@@ -784,8 +786,6 @@ tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const 
   if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
                                               (long long)n, (long long)p->max_steps);
   if (!pbar) return fail(TFS_EINVAL, "null pbar");
-  if (spatial(p) && p->scheme == TFS_SCHEME_EXP)
-    return fail(TFS_EUNSUPPORTED, "no adjoint of the exponential scheme's spatial form");
   if (p->npoints > 0) {
     if (!kappa_a || !X_n || !Xbar || !Hbar) return fail(TFS_EINVAL, "null kappa_a, X_n, Xbar or Hbar");
     if (p->scheme == TFS_SCHEME_EXP) {

@@ -45,7 +45,8 @@ constexpr int kNumCoefAll = 10;   // rows of the table (BDF2 plans use the first
 
 // Scalar positions in pbar for TFS_SCHEME_EXP plans (after the 6 m per-mode entries, of
 // which [0, m) hold dL/dw_k and [m, 2m) dL/dlambda_k from the device).
-enum PbarExpScalar : int { kPeA = 0, kPeQ = 1, kPeSh = 2, kPeInvDe = 3, kPeEtaE = 4, kPeTs = 5 };
+enum PbarExpScalar : int { kPeA = 0, kPeQ = 1, kPeSh = 2, kPeInvDe = 3, kPeEtaE = 4, kPeTs = 5,
+                           kPeQRate = 6 };   // spatial form: sum_p rate_p dL/da_p (adds to dL/dq)
 
 // Number of diagnostics written per step.
 constexpr int kNumDiag = 6;

@@ -78,14 +78,15 @@ def oracle_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, dw_da=None,
 
 
 def oracle_spatial_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, rate, source, per_mode=False,
-                             extrap=True):
+                             extrap=True, scheme="bdf2"):
     """Complex-step gradients of the spatial form in the Fourier layout, from the pointwise
     oracle: a point of rate r follows the pointwise scheme with 1/De -> 1/De + r at the same
     eta_p/De, without the mass-mode source (a run from X0 minus a run from 0) unless it is the
     source point or no source point is set (source < 0).  Points of equal rate and source
     flag run together.  Returns the keys of oracle_gradients (no alpha) plus "rate" =
-    sum_p rate_p dL/drate_p."""
+    sum_p rate_p dL/drate_p.  scheme: "bdf2" (SDIRK2 start) or "exp"."""
     wts = pack_weights(d)[:, None]
+    startup = "exp" if scheme == "exp" else "sdirk2"
     P = X0.shape[1]
     m = len(w)
     groups = {}
@@ -109,9 +110,10 @@ def oracle_spatial_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, rat
             xc = x0.astype(complex) + (1j * H_CS * dX0 if dX0 is not None else 0)
             wc = np.asarray(w, complex) + (1j * H_CS * dwv if dwv is not None else 0)
             lc = np.asarray(lam, complex) + (1j * H_CS * dlv if dlv is not None else 0)
-            t = O.run_complex(d, wc, lc, Dx, ex, dt, N, kc, xc, extrap=extrap)["tau"]
+            t = O.run_complex(d, wc, lc, Dx, ex, dt, N, kc, xc, extrap=extrap, startup=startup)["tau"]
             if not src:
-                t = t - O.run_complex(d, wc, lc, Dx, ex, dt, N, kc, np.zeros_like(xc), extrap=extrap)["tau"]
+                t = t - O.run_complex(d, wc, lc, Dx, ex, dt, N, kc, np.zeros_like(xc), extrap=extrap,
+                                      startup=startup)["tau"]
             return t
 
         base = tau().real

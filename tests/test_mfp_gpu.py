@@ -204,20 +204,13 @@ def test_paper_convergence_experiment_on_gpu():
     assert all(1.3 < o < 1.7 for o in orders), (norms, orders)
 
 
-def test_set_spatial_validation_and_exp_adjoint_refused():
+def test_set_spatial_validation():
     plan = tfs.Plan(2, 100, [1.0], [0.0], 0.5, 1.0, 0.1, 1e-3, 4, scheme="exp")
     with pytest.raises(tfs.TfsError):
         plan.set_spatial(None, 100)
     with pytest.raises(tfs.TfsError):
         plan.set_spatial(None, -2)
     plan.set_spatial(None, 3)
-    Xb = torch.zeros((2, 3, plan.stride), dtype=torch.float64, device="cuda")
-    with pytest.raises(tfs.TfsError) as e:
-        plan.step_adjoint(0, Xb[0, :1].expand(4, plan.stride).contiguous(), None, Xb[0], None, Xb[1], None, None,
-                          Xb, torch.zeros(plan.mode_levels * plan.m * 3 * plan.stride, dtype=torch.float64,
-                                          device="cuda"),
-                          torch.zeros(plan.pbar_size, dtype=torch.float64, device="cuda"))
-    assert "spatial" in str(e.value) or "UNSUPPORTED" in str(e.value).upper()
     plan.set_spatial(None, -1)      # back to the pointwise form
 
 
@@ -299,6 +292,25 @@ def test_spatial_adjoint_time_varying_kappa(extrap):
     o = oracle_spatial_gradients(d, w, lam, 0.9, 0.2, dt, N, kap, X0, target, rate, src, extrap=extrap)
     g = gpu_gradients(d, w, lam, 0.45, 0.9, 0.2, dt, N, kap, X0, target, spatial=(rate, src), extrap=extrap)
     compare_spatial(g, o, "fp64", f"sp adj tv extrap={extrap}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("P,N,adj_vec", [(1, 1, 1), (37, 9, 1), (389, 5, 2)])
+def test_spatial_adjoint_exponential_scheme(d, prec, P, N, adj_vec):
+    """The exponential scheme's adjoint in the spatial form: every gradient against
+    complex-step derivatives of the pointwise oracle run with that scheme (one point per
+    lane with a masked tail, and two points per lane over whole waves)."""
+    from tests.grad_helpers import gpu_gradients, oracle_spatial_gradients
+    m = 5
+    kappa, X0, w, lam, rate, src, target = spatial_case(d, P, m, 900 + 10 * d + P, "one")
+    print(f"spatial adjoint exp d={d} {prec} P={P} N={N} V={adj_vec}", flush=True)
+    o = oracle_spatial_gradients(d, w, lam, 1.1, 0.1, 2e-3, N, kappa, X0, target, rate, src, per_mode=True,
+                                 scheme="exp")
+    g = gpu_gradients(d, w, lam, 0.45, 1.1, 0.1, 2e-3, N, kappa, X0, target, precision=prec,
+                      spatial=(rate, src), scheme="exp", tune={"adj_vec": adj_vec})
+    assert abs(g["loss"] - o["loss"]) <= ADJ_BAR[prec] * o["loss"]
+    compare_spatial(g, o, prec, f"sp adj exp d={d} {prec} P={P} N={N} V={adj_vec}")
 
 
 def test_spatial_adjoint_eps_against_gpu_finite_differences():
