@@ -18,6 +18,15 @@ operator taken from the pinned pointwise oracle.  The time scheme is the paper's
         (b0 + eta L) Phi^{n+1} = -sum_{j=1,2} b_j (Phi^{n+1-j} + sum_k eta_k L Phi_k^{n+1-j}),
     and the mode push-forward, eq. BDF_Phi_k_n+1.
 
+With scheme="exp" it runs instead the exponential-mode scheme of the pointwise oracle (an
+extension, not the paper's scheme) with L in place of -A(kappa): each mode integrates
+Phi_k' = -lam_k Phi_k + w_k Phi exactly with Phi linear over the step,
+    Phi_k^{n+1} = e_k Phi_k^n + w_k dt (a0_k Phi^n + a1_k Phi^{n+1}),
+and since the compressed derivative is sum_k Phi_k', the state takes the increment form
+    Phi^{n+1} - Phi^n = -L sum_k (Phi_k^{n+1} - Phi_k^n),
+one step from n = 0 with zero modes (no start-up), kappa and u taken at the half step
+(3/2 level n - 1/2 level n-1).
+
 Everything is assembled in physical space as dense matrices over (grid point, Hermite
 component) and solved directly (numpy.linalg.solve), so only small grids are meant.  The
 Laplacian is the spectral one on the periodic grid: its symbol is -|xi|^2 on the discrete
@@ -133,13 +142,15 @@ def _neumaier(terms):
 
 
 def run(d, shape, extent, eps, w, lam, De, eta_p, dt, nsteps, kappa, X0, extrap=True,
-        want_modes=False, want_traj=False, u=None):
+        want_modes=False, want_traj=False, u=None, scheme="bdf2"):
     """Run the spatial oracle.
 
     shape, extent: grid points and box length per axis (len d); points in C order.
     kappa: [d*d][P] (steady) or [nlev][d*d][P], nlev >= nsteps + 1; X0: [c][P] (packed,
-    X = C - I); u: None (no advection), [d][P] (steady) or [nlev][d][P].  Returns X [2][c][P] (levels N, N-1), tau [c][P], modes [2][m][c][P] (plain,
-    levels N and N-1) or None, traj [N+1][c][P] or None."""
+    X = C - I); u: None (no advection), [d][P] (steady) or [nlev][d][P]; scheme: "bdf2"
+    (SDIRK2 start, then BDF2) or "exp".  Returns X [2][c][P] (levels N, N-1), tau [c][P],
+    modes [2][m][c][P] (plain, levels N and N-1) or None, traj [N+1][c][P] or None."""
+    assert scheme in ("bdf2", "exp")
     w = np.asarray(w, dtype=np.float64)
     lam = np.asarray(lam, dtype=np.float64)
     m = w.size
@@ -169,15 +180,20 @@ def run(d, shape, extent, eps, w, lam, De, eta_p, dt, nsteps, kappa, X0, extrap=
     etak = lam * dt / (B0 + lam * dt)
 
     I = np.eye(P * n)
+    # extrapolation to t_{n+1} (BDF2) or to the half step (exponential scheme)
+    fa, fb = (2.0, -1.0) if scheme == "bdf2" else (1.5, -0.5)
+    if scheme == "exp":
+        ew = np.array([_pointwise.exp_weights(lam[k] * dt) for k in range(m)])     # (e, a0, a1) per mode
+        q_exp = float(np.sum(w * dt * ew[:, 2]))
     kt_prev, ut_prev, A = None, None, None
     for step in range(nsteps):
         ut = None
         if extrap:
             ka = _kappa_at(kappa, d, P, step)
-            kt = ka if step == 0 else 2.0 * ka - _kappa_at(kappa, d, P, step - 1)
+            kt = ka if step == 0 else fa * ka + fb * _kappa_at(kappa, d, P, step - 1)
             if u is not None:
                 ua = _u_at(u, d, P, step)
-                ut = ua if step == 0 else 2.0 * ua - _u_at(u, d, P, step - 1)
+                ut = ua if step == 0 else fa * ua + fb * _u_at(u, d, P, step - 1)
         else:
             kt = _kappa_at(kappa, d, P, step + 1)
             if u is not None:
@@ -188,7 +204,14 @@ def run(d, shape, extent, eps, w, lam, De, eta_p, dt, nsteps, kappa, X0, extrap=
             adv = None if ut is None else sum(ut[j][:, None] * Dm[j] for j in range(d))
             A = _operator(d, De, eps, lap, kt, adv)
             kt_prev, ut_prev = kt, ut
-        if step == 0:
+        if scheme == "exp":
+            # (I - q A) Phi^{n+1} = Phi^n + A sum_k ((e_k - 1) Phi_k^n + w_k dt a0_k Phi^n)
+            v = np.sum((ew[:, 0] - 1.0)[:, None] * modes[0] + (w * dt * ew[:, 1])[:, None] * phi[0][None, :],
+                       axis=0)
+            new_phi = np.linalg.solve(I - q_exp * A, phi[0] + A @ v)
+            new_modes = ew[:, 0][:, None] * modes[0] + (w * dt)[:, None] * (
+                ew[:, 1][:, None] * phi[0][None, :] + ew[:, 2][:, None] * new_phi[None, :])
+        elif step == 0:
             hg = dt * GS
             theta = np.sum(w / (1.0 + hg * lam))
             M = I - hg * theta * A

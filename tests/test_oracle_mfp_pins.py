@@ -12,7 +12,10 @@ Each pin ties the oracle to something other than itself:
     cos(2 pi x1) cos(4 pi x2) E_alpha(-(r + 20 eps pi^2) t^alpha) on the unit square,
     eps = 1e-2, De = 0.5, T = 1, alpha = 0.5, with an error decaying like dt^{1+alpha} in
     the weighted norm of eq. weighted_Bochner_space_norm (Fig. 2a).  r = 1/De under the
-    tested operator (the paper prints 1/(2De) with its block matrix)."""
+    tested operator (the paper prints 1/(2De) with its block matrix).
+The first three (and the uniform-advection pin) run for both time schemes: the paper's
+BDF2 and the exponential-mode extension, each against the pointwise oracle's own run of
+that scheme."""
 import math
 
 import numpy as np
@@ -22,6 +25,9 @@ from oracle import mfp
 from oracle import oracle as O
 from oracle import soe
 from tests.mlf import mittag_leffler
+
+
+STARTUP = {"bdf2": "sdirk2", "exp": "exp"}     # the pointwise oracle's name of each scheme
 
 
 def grid_points(shape, extent):
@@ -51,11 +57,12 @@ def test_spectral_laplacian_of_trigonometric_polynomials(shape, extent):
     assert np.max(np.abs(lap @ np.ones(lap.shape[0]))) < 1e-12
 
 
+@pytest.mark.parametrize("scheme", ["bdf2", "exp"])
 @pytest.mark.parametrize("d", [2, 3])
 @pytest.mark.parametrize("levels", [False, True])
-def test_eps_zero_is_the_pointwise_oracle(d, levels):
+def test_eps_zero_is_the_pointwise_oracle(d, levels, scheme):
     """Without diffusion the grid points decouple: every output equals the pointwise
-    oracle's, for kappa varying in space (and in time)."""
+    oracle's, for kappa varying in space (and in time), with either time scheme."""
     shape = (3, 4) if d == 2 else (2, 2, 3)
     P = int(np.prod(shape))
     c = d * (d + 1) // 2
@@ -64,16 +71,17 @@ def test_eps_zero_is_the_pointwise_oracle(d, levels):
     kap = rng.standard_normal((N + 1, d * d, P)) * 0.3 if levels else rng.standard_normal((d * d, P)) * 0.3
     X0 = rng.standard_normal((c, P)) * 0.05
     w, lam, _ = soe.soe_fit(0.5, 6, 2e-3, 2e-3 * N)
-    r = mfp.run(d, shape, (1.0,) * d, 0.0, w, lam, 1.2, 0.1, 2e-3, N, kap, X0, want_modes=True)
-    o = O.run(d, w, lam, 1.2, 0.1, 2e-3, N, kap, X0, want_modes=True)
+    r = mfp.run(d, shape, (1.0,) * d, 0.0, w, lam, 1.2, 0.1, 2e-3, N, kap, X0, want_modes=True, scheme=scheme)
+    o = O.run(d, w, lam, 1.2, 0.1, 2e-3, N, kap, X0, want_modes=True, startup=STARTUP[scheme])
     for k in ("X", "tau", "modes"):
         err = np.max(np.abs(r[k] - o[k])) / np.max(np.abs(o[k]))
         assert err < 1e-13, (k, err)
 
 
+@pytest.mark.parametrize("scheme", ["bdf2", "exp"])
 @pytest.mark.parametrize("d", [2, 3])
 @pytest.mark.parametrize("N", [1, 2, 12])
-def test_one_fourier_mode_is_a_shifted_relaxation_rate(d, N):
+def test_one_fourier_mode_is_a_shifted_relaxation_rate(d, N, scheme):
     """X0 = F + E cos(xi.x), kappa constant: the mean follows the pointwise scheme from F
     (with the mass-mode source), and the cos(xi.x) part follows the source-free pointwise
     scheme from E with 1/De replaced by 1/De + eps |xi|^2 (a pointwise run from E minus one
@@ -94,12 +102,13 @@ def test_one_fourier_mode_is_a_shifted_relaxation_rate(d, N):
     X0 = F[:, None] + E[:, None] * np.cos(phase)[None, :]
     De, eta_p, eps, dt = 0.8, 0.1, 0.02, 2e-3
     w, lam, _ = soe.soe_fit(0.6, 8, dt, dt * max(N, 2))
-    r = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, want_modes=True)
+    r = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, want_modes=True, scheme=scheme)
     one = kd.reshape(d * d, 1)
     De_x = 1.0 / (1.0 / De + eps * xi2)
-    mean = O.run(d, w, lam, De, eta_p, dt, N, one, F[:, None], want_modes=True)
-    withE = O.run(d, w, lam, De_x, eta_p * De_x / De, dt, N, one, E[:, None], want_modes=True)
-    zero = O.run(d, w, lam, De_x, eta_p * De_x / De, dt, N, one, np.zeros((c, 1)), want_modes=True)
+    st = STARTUP[scheme]
+    mean = O.run(d, w, lam, De, eta_p, dt, N, one, F[:, None], want_modes=True, startup=st)
+    withE = O.run(d, w, lam, De_x, eta_p * De_x / De, dt, N, one, E[:, None], want_modes=True, startup=st)
+    zero = O.run(d, w, lam, De_x, eta_p * De_x / De, dt, N, one, np.zeros((c, 1)), want_modes=True, startup=st)
     for k in ("X", "tau", "modes"):
         pred = mean[k] + (withE[k] - zero[k]) * np.cos(phase)
         err = np.max(np.abs(r[k] - pred)) / np.max(np.abs(pred))
@@ -153,9 +162,10 @@ def test_spectral_derivatives_of_trigonometric_polynomials(shape, extent):
         assert np.max(np.abs(Dm @ nyq)) < 1e-10
 
 
+@pytest.mark.parametrize("scheme", ["bdf2", "exp"])
 @pytest.mark.parametrize("d", [2, 3])
 @pytest.mark.parametrize("N", [1, 2, 12])
-def test_uniform_advection_of_one_fourier_mode_is_a_complex_rate(d, N):
+def test_uniform_advection_of_one_fourier_mode_is_a_complex_rate(d, N, scheme):
     """u uniform, kappa constant, X0 = F + E cos(xi.x): the mean follows the pointwise scheme
     from F, and since u.grad acts on exp(i xi.x) as i xi.u, the cos(xi.x) part is the real
     part of exp(i xi.x) times the source-free pointwise scheme from E with the complex rate
@@ -178,15 +188,16 @@ def test_uniform_advection_of_one_fourier_mode_is_a_complex_rate(d, N):
     w, lam, _ = soe.soe_fit(0.6, 8, dt, dt * max(N, 2))
     kap = np.repeat(kd.reshape(d * d, 1), P, axis=1)
     u = np.repeat(u0.reshape(d, 1), P, axis=1)
-    r = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, want_modes=True, u=u)
+    r = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, want_modes=True, u=u, scheme=scheme)
     one = kd.reshape(d * d, 1)
     rate = 1.0 / De + eps * sum(x * x for x in xi) + 1j * sum(xi[j] * u0[j] for j in range(d))
     De_x = 1.0 / rate
-    mean = O.run(d, w, lam, De, eta_p, dt, N, one, F[:, None], want_modes=True)
+    st = STARTUP[scheme]
+    mean = O.run(d, w, lam, De, eta_p, dt, N, one, F[:, None], want_modes=True, startup=st)
     zE = O.run_complex(d, w, lam, De_x, eta_p * De_x / De, dt, N, one.astype(complex), E[:, None].astype(complex),
-                       want_modes=True)
+                       want_modes=True, startup=st)
     z0 = O.run_complex(d, w, lam, De_x, eta_p * De_x / De, dt, N, one.astype(complex), np.zeros((c, 1), complex),
-                       want_modes=True)
+                       want_modes=True, startup=st)
     wave = np.exp(1j * phase)
     for k in ("X", "tau", "modes"):
         pred = mean[k] + np.real((zE[k] - z0[k]) * wave)

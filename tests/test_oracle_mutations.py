@@ -84,6 +84,11 @@ MFP_MUTATIONS = {
                         "return sum(np.where(np.abs(g) >= np.max(np.abs(g)) - 1e-9, 0.0, g * g) for g in grids)",
                         "trigonometric"),
     "advection_sign": ("A -= np.kron(adv, np.eye(n))", "A += np.kron(adv, np.eye(n))", "complex_rate"),
+    "exp_history_without_laplacian": ("new_phi = np.linalg.solve(I - q_exp * A, phi[0] + A @ v)",
+                                      "new_phi = np.linalg.solve(I - q_exp * A, phi[0] + "
+                                      "(A - eps * np.kron(lap, np.eye(n))) @ v)", "fourier_mode and exp"),
+    "exp_half_step_as_bdf2": ("fa, fb = (2.0, -1.0) if scheme == \"bdf2\" else (1.5, -0.5)",
+                              "fa, fb = (2.0, -1.0)", "pointwise_oracle and exp"),
     "derivative_on_the_wrong_axis": ("sym = k.reshape([n if j == axis else 1 for j in range(len(shape))])",
                                      "sym = k.reshape([n if j == len(shape) - 1 - axis else 1 "
                                      "for j in range(len(shape))]) if len(set(shape)) == 1 else "
