@@ -19,7 +19,11 @@
  *      which converges when the variable part is small next to P (small dt, eps > 0 or a
  *      nearly uniform u);
  *   4. tau from X^{n+1} and G, pointwise.
- * The SDIRK2 start solves the same kind of system once per stage.  Derivatives are spectral
+ * The SDIRK2 start solves the same kind of system once per stage.  With a TFS_SCHEME_EXP plan
+ * (the exponential-mode extension) the state takes the increment form
+ * X^{n+1} - X^n = -L sum_k (X_k^{n+1} - X_k^n) of that scheme: step 1 gives R and H
+ * (sum_k (X_k^{n+1} - X_k^n) = q X^{n+1} - H), the right-hand side gains T H, and step 3 solves
+ * ((1 + q/De) I - q K(kappa~) + q T) X = rhs; there is no start-up step.  Derivatives are spectral
  * (first derivatives with the Nyquist wave number taken as zero); transforms are hipFFT
  * plans made at creation.
  *
@@ -88,15 +92,16 @@ tfs_status tfs_transport_set_tolerance(tfs_transport tr, double tol, int every);
 int tfs_transport_last_iterations(tfs_transport tr);
 
 /*
- * One step n -> n+1 of a TFS_SCHEME_BDF2 plan with the transport terms: as tfs_step (the
- * same X and Y rings, SDIRK2 at n = 0, BDF2 after), with the velocity levels u_a, u_b
- * [d][stride] following kappa's rule (extrapolated 2 u_a - u_b when kappa_b is given and
- * n >= 1, else u_a).  The plan must match the object (dim, npoints, stride), be pointwise
- * (no tfs_plan_set_spatial) and use the BDF2 scheme.  diag (device [6] FP64, or NULL)
- * receives tfs_step's diagnostics of level n+1; TFS_FLAG_CHECK_SYNC acts as in tfs_step.
+ * One step n -> n+1 with the transport terms: as tfs_step (the same X and Y rings and
+ * levels; for TFS_SCHEME_BDF2 plans SDIRK2 at n = 0 and BDF2 after, for TFS_SCHEME_EXP plans
+ * the exponential-mode step at every n), with the velocity levels u_a, u_b [d][stride]
+ * following kappa's rule (extrapolated 2 u_a - u_b, or 3/2 u_a - 1/2 u_b for the exponential
+ * scheme, when kappa_b is given and n >= 1, else u_a).  The plan must match the object (dim,
+ * npoints, stride) and be pointwise (no tfs_plan_set_spatial).  diag (device [6] FP64, or
+ * NULL) receives tfs_step's diagnostics of level n+1; TFS_FLAG_CHECK_SYNC acts as in
+ * tfs_step.
  * Errors: TFS_EINVAL (null or mismatched arguments, u_b missing while kappa_b is given),
- * TFS_EUNSUPPORTED (exponential scheme, spatial form), TFS_EHIP, TFS_ENUMERIC (only with
- * TFS_FLAG_CHECK_SYNC).
+ * TFS_EUNSUPPORTED (spatial form), TFS_EHIP, TFS_ENUMERIC (only with TFS_FLAG_CHECK_SYNC).
  */
 tfs_status tfs_transport_step(tfs_transport tr, tfs_plan plan, int64_t n, const double* kappa_a,
                               const double* kappa_b, const double* u_a, const double* u_b, double* X, void* Y,

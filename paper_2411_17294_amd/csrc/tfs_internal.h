@@ -193,6 +193,10 @@ hipError_t launch_bdf2_split(const tfs_plan_s* p, int64_t n, const double* ka, c
 // writes L.Xo and L.Yo (which may be L.Yn).
 hipError_t launch_exp(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
                       double* tau, double* diag);
+// Exponential-mode step without the local solve: writes Y^{n+1} (L.Yo, may be L.Yn), the
+// right-hand side R of each point (L.Xo), G and H ([c][stride] each); no diagnostics.
+hipError_t launch_exp_split(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+                            double* G, double* H);
 hipError_t launch_modes_to_plain(const tfs_plan_s* p, int slot, const double* X, const void* Y,
                                  double* Xk);
 // Upper bound of blocks the launchers use for a plan (sizes d_part).

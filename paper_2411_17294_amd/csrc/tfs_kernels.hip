@@ -393,6 +393,7 @@ struct ExpArgs {
   const MT* Yn;         // Y^n (m * c * stride elements, tiled); not read at n = 0
   MT* Yo;               // Y^{n+1} (may be Yn: each lane reads a mode before writing it)
   double* tau;          // [c][stride] or null
+  double* Hout;         // SPLIT: H [c][stride]
   const double* coef;   // [kNumCoef][m], ExpRow order
   double* part;         // block partials or null (this launch writes part[part0 + block])
   int64_t p_begin, ngroups;
@@ -402,7 +403,10 @@ struct ExpArgs {
   SpatialArgs sp;
 };
 
-template <int D, typename MT, int V, bool DIAG, bool SP>
+// SPLIT: the step without its local solve, for a caller that solves a spatially coupled
+// system: X^{n+1} receives each point's right-hand side R, tau the compensated G and Hout the
+// H of the local system (the modes are written as usual: they do not depend on X^{n+1}).
+template <int D, typename MT, int V, bool DIAG, bool SP, bool SPLIT = false>
 __device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& w, DiagAcc& acc) {
   constexpr int C = Sym<D>::C;
   const int64_t st = a.stride;
@@ -476,9 +480,9 @@ __device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& 
   // the local solve point by point (kappa loaded per point): one c x c system live at a time.
   // X^{n+1} and tau are stored V-wide at the end; in 3-D the finished points wait in LDS
   // instead of registers.
-  constexpr bool kLds = (D == 3);
+  constexpr bool kLds = (D == 3) && !SPLIT;
   __shared__ double stage[(kLds && V > 1) ? 2 * C * (V - 1) : 1][kBlock];
-  double Xout[C][V], Tout[C][V];
+  double Xout[C][V], Tout[C][V], Hsp[SPLIT ? C : 1][V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const uint32_t ox = w.ox + v * 8;
@@ -514,6 +518,15 @@ __device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& 
       const double S = k[i * D + j] + k[j * D + i];
       R[s] = Xc[s][v] - (AH[s] - idv * Hv[s]) + zw * S;
     }
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int s = 0; s < C; ++s) {
+        Xout[s][v] = R[s];
+        Tout[s][v] = Gs[s][v] + Ge[s][v];
+        Hsp[s][v] = Hv[s];
+      }
+      continue;
+    }
     double M[C][C];
     build_M<D>(k, ad, a.s.q, M);
     solve_pivot<C>(M, R);
@@ -542,10 +555,11 @@ __device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& 
     }
     store_v<true, double, V>(at(a.Xo + s * st + w.pw, w.ox), V, Xout[s]);
     if (a.tau) store_v<true, double, V>(at(a.tau + s * st + w.pw, w.ox), V, Tout[s]);
+    if constexpr (SPLIT) store_v<true, double, V>(at(a.Hout + s * st + w.pw, w.ox), V, Hsp[s]);
   }
 }
 
-template <int D, typename MT, int V, bool DIAG, bool SP>
+template <int D, typename MT, int V, bool DIAG, bool SP, bool SPLIT = false>
 __global__ __launch_bounds__(kBlock) void exp_kernel(const ExpArgs<MT> a) {
   constexpr int C = Sym<D>::C;
   DiagAcc acc;
@@ -555,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void exp_kernel(const ExpArgs<MT> a) {
   for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
        wv += wstride) {
     if (wv * 64 + lane < a.ngroups)
-      exp_group<D, MT, V, DIAG, SP>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
+      exp_group<D, MT, V, DIAG, SP, SPLIT>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
   }
   if constexpr (DIAG) {
     const DiagAcc r = block_reduce(acc);
@@ -844,6 +858,7 @@ hipError_t exp_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const 
   a.Yn = static_cast<const MT*>(L.Yn);
   a.Yo = static_cast<MT*>(L.Yo);
   a.tau = tau;
+  a.Hout = nullptr;
   a.coef = p->d_coef;
   a.part = p->d_part;
   a.stride = p->stride;
@@ -868,6 +883,66 @@ hipError_t exp_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const 
   const int V = pick_vec<D, MT>(p, ka, a.kb, A, tau, D == 3 ? 2 : 4);
   if (a.sp.rate || a.sp.src >= 0) return exp_go<D, MT, true>(p, a, V, diag);
   return exp_go<D, MT, false>(p, a, V, diag);
+}
+
+// The split exponential step (no local solve): a V-wide pass and a V = 1 tail pass.
+template <int D, typename MT, int V>
+hipError_t exp_split_go(const tfs_plan_s* p, ExpArgs<MT> a) {
+  const int64_t full = p->npoints / V, rest = p->npoints - full * V;
+  a.part0 = 0;
+  if (full > 0) {
+    a.p_begin = 0;
+    a.ngroups = full;
+    hipLaunchKernelGGL((exp_kernel<D, MT, V, false, false, true>), dim3(grid_for(p, full)), dim3(kBlock), 0,
+                       p->stream, a);
+  }
+  if (rest > 0) {
+    a.p_begin = full * V;
+    a.ngroups = rest;
+    hipLaunchKernelGGL((exp_kernel<D, MT, 1, false, false, true>), dim3(grid_for(p, rest)), dim3(kBlock), 0,
+                       p->stream, a);
+  }
+  return hipGetLastError();
+}
+
+template <int D, typename MT>
+hipError_t exp_split_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+                              double* G, double* H) {
+  ExpArgs<MT> a;
+  a.ka = ka;
+  a.kb = (n >= 1) ? kb : nullptr;
+  a.Xn = L.Xn;
+  a.Xo = L.Xo;
+  a.Yn = static_cast<const MT*>(L.Yn);
+  a.Yo = static_cast<MT*>(L.Yo);
+  a.tau = G;
+  a.Hout = H;
+  a.coef = p->d_coef;
+  a.part = nullptr;
+  a.stride = p->stride;
+  a.tile = p->tile;
+  a.m = p->m;
+  a.s.a_diag = 1.0 + p->q_e / p->De;
+  a.sp.rate = nullptr;
+  a.sp.src = -1;
+  a.s.q = p->q_e;
+  a.s.s_h = p->s_h;
+  a.s.inv_De = 1.0 / p->De;
+  a.s.zeta = p->zeta[n + 1];
+  a.s.tau_scale = p->tau_scale;
+  a.s.eta_e = p->eta_e;
+  a.s.fa = 1.5;
+  a.s.fb = -0.5;
+  a.s.first = n == 0 ? 1 : 0;
+  Levels A = L;
+  A.Ym = nullptr;
+  int V = pick_vec<D, MT>(p, ka, a.kb, A, G, D == 3 ? 2 : 4);
+  if (!aligned(H, (size_t)V * 8)) V = 1;
+  if constexpr (sizeof(MT) == 4 && D == 2) {
+    if (V == 4) return exp_split_go<D, MT, 4>(p, a);
+  }
+  if (V == 2) return exp_split_go<D, MT, 2>(p, a);
+  return exp_split_go<D, MT, 1>(p, a);
 }
 
 }  // namespace
@@ -921,6 +996,16 @@ hipError_t launch_exp(const tfs_plan_s* p, int64_t n, const double* ka, const do
                      : exp_dispatch<3, double>(p, n, ka, kb, L, tau, diag);
   return p->d == 2 ? exp_dispatch<2, float>(p, n, ka, kb, L, tau, diag)
                    : exp_dispatch<3, float>(p, n, ka, kb, L, tau, diag);
+}
+
+hipError_t launch_exp_split(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+                            double* G, double* H) {
+  if (p->npoints == 0) return hipSuccess;
+  if (p->precision == TFS_FP64)
+    return p->d == 2 ? exp_split_dispatch<2, double>(p, n, ka, kb, L, G, H)
+                     : exp_split_dispatch<3, double>(p, n, ka, kb, L, G, H);
+  return p->d == 2 ? exp_split_dispatch<2, float>(p, n, ka, kb, L, G, H)
+                   : exp_split_dispatch<3, float>(p, n, ka, kb, L, G, H);
 }
 
 hipError_t launch_modes_to_plain(const tfs_plan_s* p, int slot, const double* X, const void* Y, double* Xk) {

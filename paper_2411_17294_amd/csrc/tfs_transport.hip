@@ -838,7 +838,18 @@ tfs_status step_d(tfs_transport_s* s, const tfs_plan_s* p, int64_t n, const Lev&
   hipLaunchKernelGGL(mean_finish_kernel, dim3(1), dim3(64), 0, st, s->part, kMeanBlocks, D * D + D, 1.0 / (double)P,
                      s->mean);
   tfs_status r;
-  if (n == 0) {
+  if (p->scheme == TFS_SCHEME_EXP) {
+    // modes, each point's R (into X^{n+1}), G (into tau) and H (into s->rg)
+    hipError_t e = tfs::launch_exp_split(p, n, L.ka, L.kb, lv, tau, s->rg);
+    if (e != hipSuccess) return hip_fail(e, "split step launch");
+    // rhs = R + T H, then (a I - q K + q T) X = rhs with a = 1 + q/De
+    if ((r = forward_planes(s, s->rg, s->eh, C)) != TFS_OK) return r;
+    if ((r = gradient_of_extra<D>(s, st)) != TFS_OK) return r;
+    hipLaunchKernelGGL(advect_add_kernel<D>, dim3(bp), dim3(kTBlock), 0, st, lv.Xo, s->dg, L, 1.0, P, sd, s->rg);
+    if ((r = solve<D>(s, st, L, 1.0 + p->q_e / p->De, p->q_e, true, 1.0, lv.Xo)) != TFS_OK) return r;
+    hipLaunchKernelGGL(bdf2_finish_kernel<D>, dim3(bp), dim3(kTBlock), 0, st, lv.Xo, tau, p->eta_e, p->tau_scale, P,
+                       sd);
+  } else if (n == 0) {
     const double hgt = p->hg * p->theta, inv_De = 1.0 / p->De;
     hipLaunchKernelGGL(start_rhs1_kernel<D>, dim3(bp), dim3(kTBlock), 0, st, lv.Xn, L.ka, hgt, P, sd, s->rg);
     if ((r = solve<D>(s, st, L, 1.0 + hgt * inv_De, hgt, false, 0.0, s->x1g)) != TFS_OK) return r;
@@ -1007,7 +1018,6 @@ tfs_status tfs_transport_step(tfs_transport s, tfs_plan p, int64_t n, const doub
   if (p->d != s->dim || p->npoints != s->npoints || p->stride != s->stride)
     return set_error(TFS_EINVAL, "plan does not match the transport object (dim, npoints, stride)");
   if (p->device != s->device) return set_error(TFS_EINVAL, "plan and transport object live on different devices");
-  if (p->scheme != TFS_SCHEME_BDF2) return set_error(TFS_EUNSUPPORTED, "transport steps need a BDF2 plan");
   if (p->sp_rate || p->sp_source >= 0) return set_error(TFS_EUNSUPPORTED, "transport steps need a pointwise plan");
   if (n < 0 || n >= p->max_steps) return set_error(TFS_EINVAL, "step index out of range");
   if (!kappa_a || !u_a || !X || !Y || !tau) return set_error(TFS_EINVAL, "null kappa_a, u_a, X, Y or tau");
@@ -1023,17 +1033,23 @@ tfs_status tfs_transport_step(tfs_transport s, tfs_plan p, int64_t n, const doub
   L.ka = kappa_a;
   L.ua = u_a;
   const bool ex = kappa_b && n >= 1;
+  const bool expo = p->scheme == TFS_SCHEME_EXP;
   L.kb = ex ? kappa_b : nullptr;
   L.ub = ex ? u_b : nullptr;
-  L.fa = ex ? 2.0 : 1.0;
-  L.fb = ex ? -1.0 : 0.0;
+  L.fa = ex ? (expo ? 1.5 : 2.0) : 1.0;      // to t_{n+1} (BDF2) or to the half step (exponential)
+  L.fb = ex ? (expo ? -0.5 : -1.0) : 0.0;
   // the rings as tfs_step reads them
   const int64_t xs = (int64_t)p->c * p->stride, ys = (int64_t)p->m * p->c * p->stride;
   const size_t eb = p->precision == TFS_FP64 ? 8 : 4;
   char* Yb = static_cast<char*>(Y);
   tfs::Levels lv;
   const int sn = (int)(n % 2), sm = 1 - sn;
-  if (n == 0) {
+  if (expo) {                 // one mode level, updated in place
+    lv.Xn = X + sn * xs;
+    lv.Xo = X + sm * xs;
+    lv.Yn = Yb;
+    lv.Yo = Yb;
+  } else if (n == 0) {
     lv.Xn = X;
     lv.Xo = X + xs;
     lv.Ym0 = Yb;

@@ -46,10 +46,10 @@ def fields(d, shape, extent, nlev, seed, u_amp=0.3, k_amp=0.3, uniform=False):
 
 
 def gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, extrap, iters, batched=True,
-            method="splitting", want_diag=False):
+            method="splitting", want_diag=False, scheme="bdf2"):
     P = int(np.prod(shape))
     c = d * (d + 1) // 2
-    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec)
+    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec, scheme=scheme)
     tr = Transport(plan, shape, extent, eps, iters)
     tr.set_method(method)
     if not batched:
@@ -131,13 +131,56 @@ def test_transport_errors():
     u = torch.zeros((2, plan.stride), dtype=torch.float64, device="cuda")
     with pytest.raises(tfs.TfsError):
         tr.step(1, k, k, u, None, X, Y, tau)                          # u_b missing with kappa_b
-    exp_plan = tfs.Plan(2, 64, w, lam, 0.5, 1.0, 0.1, 1e-3, 4, scheme="exp")
-    tr2 = Transport(exp_plan, (8, 8), (1.0, 1.0), 0.1, 3)
-    Xe, Ye, te, _ = exp_plan.alloc()
+    sp_plan = tfs.Plan(2, 64, w, lam, 0.5, 1.0, 0.1, 1e-3, 4, scheme="exp")
+    sp_plan.set_spatial(None, 3)
+    tr2 = Transport(sp_plan, (8, 8), (1.0, 1.0), 0.1, 3)
+    Xe, Ye, te, _ = sp_plan.alloc()
     with pytest.raises(tfs.TfsError):
-        tr2.step(0, k, None, u, None, Xe, Ye, te)                    # exponential scheme
+        tr2.step(0, k, None, u, None, Xe, Ye, te)                    # a plan in the diagonal spatial form
     tr.step(0, k, None, u, None, X, Y, tau)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("extrap", [True, False])
+@pytest.mark.parametrize("N", [1, 2, 9])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d,shape,extent", CASES)
+def test_transport_exponential_scheme_matches_spatial_oracle(d, shape, extent, prec, N, extrap):
+    """The exponential-mode scheme with the transport terms (u and kappa varying in space and
+    time, taken at the half step), 40 splitting iterations per solve, against the spatial
+    oracle's run of that scheme."""
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    De, eta_p, eps, dt = 0.8, 0.1, 0.05, 2e-3
+    w, lam, _ = osoe.soe_fit(0.5, 6, dt, dt * max(N, 2))
+    u, kap = fields(d, shape, extent, N + 1, 80 + d + N)
+    X0 = np.random.default_rng(90 + d).standard_normal((c, P)) * 0.05
+    print(f"transport exp d={d} shape={shape} {prec} N={N} extrap={extrap}", flush=True)
+    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, extrap, 40, scheme="exp")
+    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, extrap=extrap, want_modes=True, u=u,
+                scheme="exp")
+    errs = {"X": relerr(g["X"], o["X"]), "tau": relerr(g["tau"], o["tau"]), "modes": relerr(g["modes"], o["modes"][0])}
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert all(v < BAR[prec] for v in errs.values()), errs
+
+
+@pytest.mark.parametrize("method,iters", [("splitting", 0), ("gmres", 30)])
+@pytest.mark.parametrize("d,shape,extent", [CASES[0], CASES[3]])
+def test_transport_exponential_scheme_uniform_fields_and_gmres(d, shape, extent, method, iters):
+    """Exponential scheme: uniform u and kappa are solved exactly by the preconditioner alone;
+    varying ones by GMRES."""
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    N, De, eta_p, eps, dt = 6, 0.8, 0.1, 0.05, 2e-3
+    w, lam, _ = osoe.soe_fit(0.5, 6, dt, dt * N)
+    u, kap = fields(d, shape, extent, N + 1, 95 + d, uniform=method == "splitting")
+    X0 = np.random.default_rng(96).standard_normal((c, P)) * 0.05
+    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, "fp64", True, iters, method=method,
+                scheme="exp")
+    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, want_modes=True, u=u, scheme="exp")
+    errs = {"X": relerr(g["X"], o["X"]), "tau": relerr(g["tau"], o["tau"]), "modes": relerr(g["modes"], o["modes"][0])}
+    print("exp", method, d, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert all(v < 1e-12 for v in errs.values()), errs
 
 
 @pytest.mark.parametrize("N", [1, 2, 9])
