@@ -322,7 +322,8 @@ def _transport(stream, steps):
     De = 1, alpha = 0.5, eta_p = 1e-4, dt = 1e-3: ms per step with 10 and 20 splitting
     iterations and 10 and 20 GMRES steps per solve, the relative difference of X from the
     20-step GMRES result after the same steps (the solvers' convergence), and the pointwise
-    step on the same fields for comparison."""
+    step on the same fields for comparison; then the exponential-mode scheme with 10
+    splitting iterations and its pointwise step."""
     import math
     import torch
     from paper_2411_17294_amd import ns, tfs
@@ -333,8 +334,9 @@ def _transport(stream, steps):
     w, lam, _, _, _ = tfs.soe_fit(alpha, m, dt, 1.0)
     out = {"grid": [n, n], "modes": m, "eps": eps}
     Xs = {}
-    for method, iters in (("splitting", 10), ("splitting", 20), ("gmres", 10), ("gmres", 20)):
-        p = tfs.Plan(2, P, w, lam, alpha, De, 1e-4, dt, 2 * steps + 16, precision="fp64")
+    for method, iters, scheme in (("splitting", 10, "bdf2"), ("splitting", 20, "bdf2"), ("gmres", 10, "bdf2"),
+                                  ("gmres", 20, "bdf2"), ("splitting", 10, "exp")):
+        p = tfs.Plan(2, P, w, lam, alpha, De, 1e-4, dt, 2 * steps + 16, precision="fp64", scheme=scheme)
         sol = ns.Solver(p, (n, n), (2 * math.pi,) * 2, 9e-4, dt)
         u, kappa, uh, fh = sol.alloc()
         u[:, :P] = synthetic_velocity(2, n, 13)
@@ -346,6 +348,12 @@ def _transport(stream, steps):
             tr.step(k, kappa, kappa, u, u, X, Y, tau)
         ms = _timed(stream, lambda k: tr.step(k, kappa, kappa, u, u, X, Y, tau), 4, steps)
         torch.cuda.synchronize()
+        if scheme == "exp":
+            out["ms_per_step_exp_splitting_10"] = ms
+            ms_pt = _timed(stream, lambda k: p.step(k, kappa, kappa, X, Y, tau), 4 + steps, steps)
+            out["ms_pointwise_exp_step_same_fields"] = ms_pt
+            del tr, sol, p
+            continue
         Xs[(method, iters)] = X[(4 + steps) % 2, :, :P].clone()
         out[f"ms_per_step_{method}_{iters}"] = ms
         if (method, iters) == ("splitting", 10):
