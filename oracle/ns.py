@@ -33,7 +33,8 @@ pointwise scheme's stress at level 0.
 The stress update is either the pointwise scheme without transport terms (the pinned
 pointwise oracle) or, with eps given, the MFP equation of eq. FP_discrete in full, advection
 by u and centre-of-mass diffusion eps Laplace included (the pinned spatial oracle,
-oracle/mfp.py).  Either runs with the velocity levels and their gradients as given levels
+oracle/mfp.py; with startup="exp" both run the exponential-mode scheme).  Either runs with
+the velocity levels and their gradients as given levels
 (no extrapolation: step n -> n+1 uses u^{n+1} and kappa^{n+1}), re-run from level 0 at every
 step so that each of its steps sees exactly the levels the coupled scheme has produced by
 then.  Its cost is quadratic in the number of steps: small cases only.
@@ -173,7 +174,8 @@ def run(d, shape, extent, nu, w, lam, De, eta_p, dt, nsteps, u0, X0, startup="sd
                                  startup=startup, want_modes=True)
         else:
             res = _spatial.run(d, shape, extent, eps, w, lam, De, eta_p, dt, n + 1, np.stack(kappas), X0,
-                               extrap=False, want_modes=True, u=np.stack(vels))
+                               extrap=False, want_modes=True, u=np.stack(vels),
+                               scheme="exp" if startup == "exp" else "bdf2")
         tau = res["tau"]
         if want_levels:
             levels.append(uh_new)

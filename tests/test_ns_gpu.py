@@ -199,10 +199,11 @@ def test_solver_errors():
     torch.cuda.synchronize()
 
 
-def gpu_run_transport(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, eps, iters=40, prec="fp64"):
+def gpu_run_transport(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, eps, iters=40, prec="fp64",
+                      scheme="bdf2"):
     from paper_2411_17294_amd.transport import Transport
     P = int(np.prod(shape))
-    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec)
+    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec, scheme=scheme)
     sol = ns.Solver(plan, shape, extent, nu, dt)
     tr = Transport(plan, shape, extent, eps, iters)
     sol.set_transport(tr)
@@ -218,20 +219,22 @@ def gpu_run_transport(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, ep
             "X": np.stack([X[N % 2, :, :P].cpu().numpy(), X[(N - 1) % 2, :, :P].cpu().numpy()])}
 
 
+@pytest.mark.parametrize("scheme", ["bdf2", "exp"])
 @pytest.mark.parametrize("N", [1, 2, 5])
 @pytest.mark.parametrize("d,shape,extent", [(2, (8, 8), (1.0, 1.0)), (2, (6, 9), (1.0, 1.5)), (3, (4, 6, 4), (1.0, 1.0, 0.8))])
-def test_coupled_with_transport_matches_oracle(d, shape, extent, N):
+def test_coupled_with_transport_matches_oracle(d, shape, extent, N, scheme):
     """The coupled step with the MFP equation in full (advection of the stress by u and
     centre-of-mass diffusion inside the implicit operator) against the coupled oracle run
-    with the spatial oracle for the stress."""
+    with the spatial oracle for the stress, for the paper's scheme and the exponential one."""
     P = int(np.prod(shape))
     c = d * (d + 1) // 2
     nu, De, eta_p, dt, eps = 0.05, 0.7, 0.01, 2e-3, 0.1
     w, lam, _ = osoe.soe_fit(0.5, 5, dt, dt * max(N, 2))
     u0, X0 = random_case(d, shape, 200 + d + N, amp=0.3)
-    print(f"coupled+transport d={d} shape={shape} N={N}", flush=True)
-    g = gpu_run_transport(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, eps)
-    o = ons.run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, eps=eps)
+    print(f"coupled+transport d={d} shape={shape} N={N} {scheme}", flush=True)
+    g = gpu_run_transport(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, eps, scheme=scheme)
+    o = ons.run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, eps=eps,
+                startup="exp" if scheme == "exp" else "sdirk2")
     errs = {"u": relerr(g["u"], o["u"]), "tau": relerr(g["tau"], o["tau"]), "X": relerr(g["X"], o["X"])}
     print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     assert all(v < 1e-12 for v in errs.values()), errs
