@@ -219,10 +219,11 @@ def test_gmres_converges_under_strong_advection():
     assert e_gm < 1e-11
 
 
+@pytest.mark.parametrize("scheme", ["bdf2", "exp"])
 @pytest.mark.parametrize("d,n,prec", [(2, 1024, "fp64"), (3, 64, "fp32_modes")])
-def test_uniform_fields_full_size_sampled_coefficients(d, n, prec):
+def test_uniform_fields_full_size_sampled_coefficients(d, n, prec, scheme):
     """1024^2 FP64 and 64^3 FP32 modes, m = 32, u and kappa uniform (u != 0), no splitting
-    iteration: every
+    iteration, either time scheme: every
     Fourier coefficient of X evolves on its own with the complex rate 1/De + eps |xi|^2 +
     i xi.u in place of 1/De (the mass-mode source only at xi = 0).  24 sampled coefficients
     of the GPU result (transformed with torch.fft) against complex runs of the pointwise
@@ -247,7 +248,8 @@ def test_uniform_fields_full_size_sampled_coefficients(d, n, prec):
         Xh0[(slice(None),) + tuple(v % n for v in idx)] += (rng.standard_normal(c) + 1j * rng.standard_normal(c)) * 0.01
         filled.append(idx)
     X0 = np.real(np.fft.ifftn(Xh0, axes=axes) * P).reshape(c, P) + rng.standard_normal((c, 1)) * 0.05
-    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, True, 0)
+    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, True, 0, scheme=scheme)
+    st = "exp" if scheme == "exp" else "sdirk2"
     Gh = torch.fft.fftn(torch.from_numpy(g["X"][0].reshape((c,) + shape)), dim=axes).numpy() / P
     Ih = np.fft.fftn(X0.reshape((c,) + shape), axes=axes) / P
     picks = [(0,) * d] + [filled[k] for k in rng.choice(len(filled), 23, replace=False)]
@@ -260,15 +262,16 @@ def test_uniform_fields_full_size_sampled_coefficients(d, n, prec):
         at = (slice(None),) + tuple(v % n for v in idx)
         x0 = Ih[at].reshape(c, 1)
         if idx == (0,) * d:
-            want = O.run(d, w, lam, De, eta_p, dt, N, one, x0.real)["X"][0][:, 0]
+            want = O.run(d, w, lam, De, eta_p, dt, N, one, x0.real, startup=st)["X"][0][:, 0]
         else:
-            z = O.run_complex(d, w, lam, Dx, eta_p * Dx / De, dt, N, one.astype(complex), x0)["X"][0][:, 0]
+            z = O.run_complex(d, w, lam, Dx, eta_p * Dx / De, dt, N, one.astype(complex), x0, startup=st)["X"][0][:, 0]
             z0 = O.run_complex(d, w, lam, Dx, eta_p * Dx / De, dt, N, one.astype(complex),
-                               np.zeros((c, 1), complex))["X"][0][:, 0]
+                               np.zeros((c, 1), complex), startup=st)["X"][0][:, 0]
             want = z - z0
         got = Gh[at]
         worst = max(worst, float(np.max(np.abs(got - want)) / np.max(np.abs(want))))
-    print(f"full-size uniform transport d={d} n={n} {prec}: worst sampled coefficient {worst:.2e}", flush=True)
+    print(f"full-size uniform transport d={d} n={n} {prec} {scheme}: worst sampled coefficient {worst:.2e}",
+          flush=True)
     assert worst < (1e-10 if prec == "fp64" else 1e-5)
 
 
