@@ -295,7 +295,8 @@ def host_diag(d, X, tau):
 
 
 @pytest.mark.parametrize("d,shape,extent", CASES)
-def test_transport_diagnostics(d, shape, extent):
+@pytest.mark.parametrize("scheme", ["bdf2", "exp"])
+def test_transport_diagnostics(d, shape, extent, scheme):
     """The diagnostics of the last step against their definitions on the oracle's X and tau."""
     P = int(np.prod(shape))
     c = d * (d + 1) // 2
@@ -303,8 +304,9 @@ def test_transport_diagnostics(d, shape, extent):
     w, lam, _ = osoe.soe_fit(0.5, 6, dt, dt * N)
     u, kap = fields(d, shape, extent, N + 1, 95 + d)
     X0 = np.random.default_rng(96).standard_normal((c, P)) * 0.05
-    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, "fp64", True, 40, want_diag=True)
-    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, u=u)
+    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, "fp64", True, 40, want_diag=True,
+                scheme=scheme)
+    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, u=u, scheme=scheme)
     want = host_diag(d, o["X"][0], o["tau"])
     print("diag", g["diag"], want, flush=True)
     np.testing.assert_allclose(g["diag"], want, rtol=1e-11, atol=1e-14)
