@@ -32,9 +32,10 @@ EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_pl
            "tfs_transport_set_tolerance", "tfs_transport_last_iterations")
 
 
-# Mode-ring tile (points) used when the caller does not choose one; measured best on
-# MI355X for the 2-D (c = 3) and 3-D (c = 6) update.
-DEFAULT_TILE = {2: 4096, 3: 8192}
+# Mode-ring tile (points) used when the caller does not choose one, measured best on
+# MI355X: 4096 points, except 8192 for 3-D FP32 modes (both give 32 KB mode planes in 3-D).
+def default_tile(dim, precision):
+    return 8192 if dim == 3 and precision == TFS_FP32_MODES else 4096
 
 
 class TfsError(RuntimeError):
@@ -189,7 +190,7 @@ class Plan:
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         if tile is None:
-            tile = DEFAULT_TILE[self.dim]
+            tile = default_tile(self.dim, self.precision)
         d = PlanDesc(self.dim, self.m, self.npoints, int(stride), int(tile), self.alpha, self.De, self.eta_p, self.dt,
                      self.max_steps, _dptr(self.w), _dptr(self.lam), self.precision, int(flags),
                      C.c_void_p(stream), self.scheme)
