@@ -32,10 +32,10 @@ EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_pl
            "tfs_transport_set_tolerance", "tfs_transport_last_iterations")
 
 
-# Mode-ring tile (points) used when the caller does not choose one, measured best on
-# MI355X: 4096 points, except 8192 for 3-D FP32 modes (both give 32 KB mode planes in 3-D).
+# Mode-ring tile (points) used when the caller does not choose one: 32 KB mode planes
+# (4096 FP64 or 8192 FP32 points), measured best on MI355X in 2-D and 3-D for both precisions.
 def default_tile(dim, precision):
-    return 8192 if dim == 3 and precision == TFS_FP32_MODES else 4096
+    return 8192 if precision == TFS_FP32_MODES else 4096
 
 
 class TfsError(RuntimeError):
