@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the time-fractional extra-stress update on one MI355X.
 
-Default workload: the 2-D FP64 configuration, 1024x1024 points, m = 32 exponential
-modes, alpha in {0.3, 0.7} (two independent fields), dt = 5e-4, 1000 time levels of a
-time-varying seeded divergence-free velocity gradient with second-order extrapolation.
-All kappa levels, the state rings and the mode rings are resident in HBM before the
-timed region; one benchmark step advances both fields by one time level (two launches
-of the fused BDF2 kernel).
+Default workload (the headline): the 384^3 differentiation configuration -- alpha = 0.2,
+m = 48 exponential modes, dt = 1e-4, FP32 mode storage with FP64 recombination and local
+solve, FP32 velocity gradients of the time-varying seeded field -- on one point slab of the
+grid (884736 consecutive points; the whole grid is 64 such slabs, which is how the
+checkpointed job fits one device).  One benchmark step is one time level of that job: a
+forward step with the fused diagnostics, the recomputed step of the backward sweep and the
+adjoint step.  All kappa levels, the state and mode rings and the adjoint buffers are
+resident in HBM before the timed region.
 
-Prints one JSON line: point-mode updates/s, the roofline of the fused step kernel
-(algorithmic bytes per launch / average launch duration from HIP events on the plan's
-stream), and the CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line: point-mode updates/s (points x modes per time level / time), the
+roofline of the dominant kernel (its algorithmic bytes per launch / its average launch
+duration from HIP events on the plan's stream inside the timed loop), and the CPU oracle
+timed on the same slab's kappa and X0.  --workload 2 or 3 times the forward step of the 2-D
+FP64 or the 256^3 configuration instead.
 """
 import argparse
 import json
@@ -25,11 +29,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def algorithmic_bytes_per_point(dim, m, mode_bytes, kappa_reads):
+def algorithmic_bytes_per_point(dim, m, mode_bytes, kappa_reads, kappa_bytes=8):
     """Minimum HBM traffic of one step per point: two mode levels read and one written,
     X at two levels read and one written, tau written, kappa read (1 or 2 levels)."""
     c = dim * (dim + 1) // 2
-    return 3 * m * c * mode_bytes + 3 * c * 8 + c * 8 + kappa_reads * dim * dim * 8
+    return 3 * m * c * mode_bytes + 3 * c * 8 + c * 8 + kappa_reads * dim * dim * kappa_bytes
 
 
 def log(*a):
@@ -58,28 +62,28 @@ def profiled_traffic(profile_name):
         return None
 
 
-def exp_bytes_per_point(dim, m, mode_bytes, kappa_reads):
+def exp_bytes_per_point(dim, m, mode_bytes, kappa_reads, kappa_bytes=8):
     """Minimum HBM traffic of one exponential-mode step per point: the single mode level read
     and written in place, X^n read and X^{n+1} written, tau written, kappa read."""
     c = dim * (dim + 1) // 2
-    return 2 * m * c * mode_bytes + 2 * c * 8 + c * 8 + kappa_reads * dim * dim * 8
+    return 2 * m * c * mode_bytes + 2 * c * 8 + c * 8 + kappa_reads * dim * dim * kappa_bytes
 
 
-def exp_adjoint_bytes_per_point(dim, m, mode_bytes):
+def exp_adjoint_bytes_per_point(dim, m, mode_bytes, kappa_bytes=8):
     """Minimum HBM traffic of one adjoint step of the exponential-mode scheme per point: the
     forward mode level read, the adjoint mode level read and written in place; X^n and
-    X^{n+1} read, Xbar^{n+1} read and Xbar^n written; kappa at two levels read and its
+    X^{n+1} read, Xbar^{n+1} read and Xbar^n written; kappa at two levels read and its FP64
     adjoint read and written."""
     c = dim * (dim + 1) // 2
-    return 3 * m * c * mode_bytes + 2 * c * 8 + 2 * c * 8 + 4 * dim * dim * 8
+    return 3 * m * c * mode_bytes + 2 * c * 8 + 2 * c * 8 + 2 * dim * dim * kappa_bytes + 2 * dim * dim * 8
 
 
-def adjoint_bytes_per_point(dim, m, mode_bytes):
+def adjoint_bytes_per_point(dim, m, mode_bytes, kappa_bytes=8):
     """Minimum HBM traffic of one adjoint step per point: four mode streams read (H^(n+1),
     H^(n+2), Y^n, Y^(n-1)) and one written (H^(n)); X at three levels read, the two adjoint
-    X slots read and written; kappa at two levels read and its adjoint read and written."""
+    X slots read and written; kappa at two levels read and its FP64 adjoint read and written."""
     c = dim * (dim + 1) // 2
-    return 5 * m * c * mode_bytes + 3 * c * 8 + 4 * c * 8 + 4 * dim * dim * 8
+    return 5 * m * c * mode_bytes + 3 * c * 8 + 4 * c * 8 + 2 * dim * dim * kappa_bytes + 2 * dim * dim * 8
 
 
 def _timed(stream, fn, first, count):
@@ -166,19 +170,21 @@ def _fp32_vs_fp64(stream, steps):
     res = {}
     taus = {}
     for form in ("fp64", "fp32_modes"):
-        p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=form)
+        # the FP32-mode form reads FP32 velocity gradients
+        p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=form,
+                     kappa="fp64" if form == "fp64" else "fp32")
         # the steady field at two levels in two buffers, as a time-varying one would be read
         ka, kb = p.kappa_tensor(), p.kappa_tensor()
         DeviceKappa(I.fourier_field(wl), wl.grid, wl.npoints).fill(ka, 0.0)
         kb.copy_(ka)
-        X = x0_ring(wl, p.stride)
+        X = x0_ring(wl, p.stride, levels=p.x_levels)
         _, Y, tau, _ = p.alloc()
         p.step(0, ka, None, X, Y, tau)
         for n in range(1, 4):
             p.step(n, ka, kb, X, Y, tau)
         ms = _timed(stream, lambda n: p.step(n, ka, kb, X, Y, tau), 4, steps)
         mb = 8 if form == "fp64" else 4
-        nbytes = algorithmic_bytes_per_point(wl.dim, wl.nmodes, mb, 2) * wl.npoints
+        nbytes = algorithmic_bytes_per_point(wl.dim, wl.nmodes, mb, 2, mb) * wl.npoints
         gbs = nbytes / (ms * 1e-3) / 1e9
         prof = "bdf2_kernel_" + ("fp64_3d_256cube_m40" if form == "fp64" else wl.name)
         res[form] = {"ms_per_step": ms, "point_mode_updates_per_s": wl.npoints * wl.nmodes / (ms * 1e-3),
@@ -210,17 +216,17 @@ def _exp_vs_bdf2(stream, steps):
     res, taus = {}, {}
     for scheme in ("bdf2", "exp"):
         p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps,
-                     precision=wl.precision, scheme=scheme)
+                     precision=wl.precision, scheme=scheme, kappa="fp32")
         ka, kb = p.kappa_tensor(), p.kappa_tensor()
         DeviceKappa(I.fourier_field(wl), wl.grid, wl.npoints).fill(ka, 0.0)
         kb.copy_(ka)
-        X = x0_ring(wl, p.stride)
+        X = x0_ring(wl, p.stride, levels=p.x_levels)
         _, Y, tau, _ = p.alloc()
         p.step(0, ka, None, X, Y, tau)
         for n in range(1, 4):
             p.step(n, ka, kb, X, Y, tau)
         ms = _timed(stream, lambda n: p.step(n, ka, kb, X, Y, tau), 4, steps)
-        bpp = (exp_bytes_per_point if scheme == "exp" else algorithmic_bytes_per_point)(wl.dim, wl.nmodes, 4, 2)
+        bpp = (exp_bytes_per_point if scheme == "exp" else algorithmic_bytes_per_point)(wl.dim, wl.nmodes, 4, 2, 4)
         nbytes = bpp * wl.npoints
         gbs = nbytes / (ms * 1e-3) / 1e9
         kern = "exp_kernel_" if scheme == "exp" else "bdf2_kernel_"
@@ -406,7 +412,7 @@ def _fused(stream, K=50):
             if steady:
                 ff.omega = np.zeros_like(ff.omega)
             p = tfs.Plan(d, P, w, lam, wl.alphas[0], wl.De, wl.eta_p, dt, 3 * K + 16, precision=prec,
-                         scheme=scheme)
+                         scheme=scheme, mode_form="y")
             p.set_field(ff.k, ff.phase, ff.omega, ff.coef(), g, 0)
             X, Y, tau, _ = p.alloc()
             ka, kb = p.kappa_tensor(), p.kappa_tensor()
@@ -456,30 +462,31 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
     # default 8192 for the 384^3 slab (its adjoint runs 8% slower with 4096)
     tile = 4096 if workload == 4 else None
     p = tfs.Plan(wl.dim, P, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=wl.precision,
-                 scheme=scheme, tile=tile)
+                 scheme=scheme, tile=tile, kappa="fp32")
     exp = scheme == "exp"
     ka, kb = p.kappa_tensor(), p.kappa_tensor()
     dk = DeviceKappa(I.fourier_field(wl), wl.grid, P)
     dk.fill(ka, wl.dt if wl.time_varying else 0.0)
     dk.fill(kb, 0.0)
     st, c, m = p.stride, p.c, p.m
-    X = torch.zeros((2, c, st), dtype=torch.float64, device="cuda")
+    X, Y, tau, _ = p.alloc()
     X[0, :, :P] = torch.from_numpy(I.initial_state(wl, np.arange(P))).cuda()
-    _, Y, tau, _ = p.alloc()
-    Xs = [torch.zeros((c, st), dtype=torch.float64, device="cuda") for _ in range(3)]
+    # levels n-1, n, n+1 and (read by the shifted mode form) n-2 of the recomputed steps
+    Xs = [torch.zeros((c, st), dtype=torch.float64, device="cuda") for _ in range(4)]
     Ys = [torch.zeros((m * c * st,), dtype=p.mode_dtype, device="cuda") for _ in range(3)]
     Xs[0].copy_(X[0])
+    Xs[3].copy_(X[0])
     if exp:
         p.step_levels(0, ka, None, Xs[0], None, Xs[1], None, None, Ys[1], tau)
         p.step_levels(1, ka, kb, Xs[1], None, Xs[2], Ys[1], None, Ys[2], tau)
     else:
         p.step_levels(0, ka, None, Xs[0], None, Xs[1], None, Ys[0], Ys[1], tau)
         p.step_levels(1, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Ys[2], tau)
-    Xbar = torch.zeros((2, c, st), dtype=torch.float64, device="cuda")
+    Xbar = torch.zeros((p.x_levels, c, st), dtype=torch.float64, device="cuda")
     Xbar[0, :, :P].normal_()
     Hbar = torch.zeros((p.mode_levels * m * c * st,), dtype=p.mode_dtype, device="cuda")
     pbar = torch.zeros(p.pbar_size, dtype=torch.float64, device="cuda")
-    kbar = torch.zeros_like(ka)
+    kbar = torch.zeros(ka.shape, dtype=torch.float64, device="cuda")
     p.step(0, ka, None, X, Y, tau)
 
     def fwd(n):
@@ -489,7 +496,7 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
         if exp:
             p.step_levels(n, ka, kb, Xs[1], None, Xs[2], Ys[1], None, Ys[2], tau)
         else:
-            p.step_levels(n, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Ys[2], tau)
+            p.step_levels(n, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Ys[2], None, X_nm2=Xs[3])
 
     def adj(n):
         if exp:
@@ -497,18 +504,20 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
                            kappabar_b=kbar)
         else:
             p.step_adjoint(n, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Xbar, Hbar, pbar, kappabar_a=kbar,
-                           kappabar_b=kbar)
+                           kappabar_b=kbar, X_nm2=Xs[3])
     if exp:
-        fb = exp_bytes_per_point(wl.dim, m, 4, 2) * P
-        ab = exp_adjoint_bytes_per_point(wl.dim, m, 4) * P
+        fb = exp_bytes_per_point(wl.dim, m, 4, 2, 4) * P
+        rb = fb - c * 8 * P
+        ab = exp_adjoint_bytes_per_point(wl.dim, m, 4, 4) * P
     else:
-        fb = algorithmic_bytes_per_point(wl.dim, m, 4, 2) * P
-        ab = adjoint_bytes_per_point(wl.dim, m, 4) * P
+        fb = algorithmic_bytes_per_point(wl.dim, m, 4, 2, 4) * P
+        rb = fb - c * 8 * P            # the recomputation writes no stress
+        ab = adjoint_bytes_per_point(wl.dim, m, 4, 4) * P
     tag = "fp32modes_3d_128cube_m32" if workload == 4 else "fp32modes_3d_384cube_m48_slab"
     kf, ka_ = ("exp_kernel_", "exp_adj_kernel_") if exp else ("bdf2_kernel_", "adj_kernel_")
     parts = {}
     for name, fn, nbytes, prof in (("forward", fwd, fb, kf + tag),
-                                   ("recompute", rec, fb, kf + tag),
+                                   ("recompute", rec, rb, kf + tag),
                                    ("adjoint", adj, ab, ka_ + tag)):
         for n in range(1, 4):
             fn(n)
@@ -520,7 +529,8 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
     out = {"workload": wl.name, "form": wl.precision, "scheme": scheme, "points": P, **parts,
            "ms_per_time_level": total,
            "point_mode_updates_per_s": P * m / (total * 1e-3),
-           "frac_all": (2 * fb + ab) / (total * 1e-3) / 1e9 / HBM_PEAK_GBS}
+           "mode_form": "shifted (Z)" if p.x_levels == 3 else "Y",
+           "frac_all": (fb + rb + ab) / (total * 1e-3) / 1e9 / HBM_PEAK_GBS}
     if P != wl.npoints:
         # kernels only: every slab runs the same three kernels per time level
         out["kernel_seconds_whole_grid_all_steps"] = total * 1e-3 * (wl.npoints / P) * wl.nsteps
@@ -530,7 +540,8 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
 def differentiation_job(steps, slabs_to_run):
     """The 384^3 differentiation workload end to end: 64 slabs of 884736 points, each a
     checkpointed forward (checkpoints every 100 steps) and backward through
-    autograd.run_slabs, with the time-varying field evaluated per level on the slab's points.
+    autograd.run_slabs, with the time-varying field evaluated per level on the slab's points
+    by the library (FP32 levels).
     Loss: 1/2 sum ||tau^N||_F^2.  Wall time includes the field synthesis and the checkpoint
     copies; the kernels alone are measured by the slab384 form."""
     import numpy as np
@@ -543,7 +554,7 @@ def differentiation_job(steps, slabs_to_run):
     alpha, m, dt = wl.alphas[0], wl.nmodes, wl.dt
     _, _, _, _, info = tfs.soe_fit(alpha, m, dt, dt * wl.nsteps)
     spec = Spec(dim=3, nmodes=m, dt=dt, nsteps=steps, y_lo=info["y_lo"], y_hi=info["y_hi"],
-                ckpt_every=wl.ckpt_every, precision=wl.precision)
+                ckpt_every=wl.ckpt_every, precision=wl.precision, kappa="fp32")
     S, nslab = SLAB_384, wl.npoints // SLAB_384
     X0_all = I.initial_state(wl)
     ff = I.fourier_field(wl)
@@ -555,9 +566,8 @@ def differentiation_job(steps, slabs_to_run):
         def make():
             t_slab.append(time.perf_counter())
             log(f"slab {j}/{slabs_to_run}: points [{j * S}, {(j + 1) * S})")
-            dk = DeviceKappa(ff, wl.grid, S, offset=j * S)
             X0 = torch.from_numpy(np.ascontiguousarray(X0_all[:, j * S:(j + 1) * S])).cuda()
-            return zero_k, X0, (lambda n, out: dk.fill(out, n * dt))
+            return zero_k, X0, ff.table(wl.grid, j * S)      # the slab's levels from tfs_field_eval
         return make
 
     def loss_grad(tau, j):
@@ -579,8 +589,24 @@ def differentiation_job(steps, slabs_to_run):
             "note": "forward + checkpointed backward per time level and point, wall clock incl. field synthesis"}
 
 
+def host_threads():
+    """Threads for the CPU baseline: the process's CPU share (OMP_NUM_THREADS when the
+    environment sets it, as the GPU hosts do), else the CPUs it may run on."""
+    vis = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return (int(env) if env.isdigit() and int(env) > 0 else vis), vis
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "unknown")
+    except OSError:
+        return "unknown"
+
+
 def cpu_baseline(wl, alpha, w, lam, nthreads):
-    """Oracle on a bounded sample of the workload: every 2nd point of the grid for all
+    """Oracle on a bounded sample of a forward workload: every 2nd point of the grid for all
     time levels, kappa frozen at t = 0 (the oracle's per-step work does not depend on it)."""
     import numpy as np
     from oracle import oracle as O
@@ -594,23 +620,291 @@ def cpu_baseline(wl, alpha, w, lam, nthreads):
     O.run(wl.dim, w, lam, wl.De, wl.eta_p, wl.dt, wl.nsteps, kap, X0, nthreads=nthreads)
     el = time.perf_counter() - t0
     rate = len(pts) * len(w) * wl.nsteps / el
-    model = "unknown"
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
-    except OSError:
-        pass
     return {"value": rate, "unit": "point-mode updates/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{len(pts)} points (every 2nd of {wl.grid}^{wl.dim}), {wl.nsteps} steps, alpha={alpha}, "
-                      f"m={len(w)}, FP64, {el:.1f} s", "cpu_model": model}
+                      f"m={len(w)}, FP64, {el:.1f} s", "cpu_model": cpu_model()}
+
+
+def cpu_baseline_slab(wl, w, lam, kap_dev, X0, nsteps=24, single_points=65536):
+    """The FP64 oracle on the benchmark's own slab inputs: the kappa levels 0..nsteps the GPU
+    read (FP32 values, copied to the host) and the same X0, forward from level 0 (the SDIRK2
+    start, then BDF2): all points with the process's CPU share of threads, and the first
+    single_points points with one thread.  The oracle has no reverse mode, so its rate is that
+    of the forward sweep; the GPU's rate counts a forward, a recomputed and an adjoint step per
+    time level."""
+    import numpy as np
+    from oracle import oracle as O
+    P = X0.shape[1]
+    kap = kap_dev[:nsteps + 1, :, :P].double().cpu().numpy()
+    nth, vis = host_threads()
+    m = len(w)
+    O.run(3, w, lam, wl.De, wl.eta_p, wl.dt, 1, kap[:2, :, :1024], X0[:, :1024], nthreads=nth)  # load + warm
+    t0 = time.perf_counter()
+    O.run(3, w, lam, wl.De, wl.eta_p, wl.dt, nsteps, kap, X0, nthreads=nth)
+    el = time.perf_counter() - t0
+    Ps = min(single_points, P)
+    t0 = time.perf_counter()
+    O.run(3, w, lam, wl.De, wl.eta_p, wl.dt, nsteps, np.ascontiguousarray(kap[:, :, :Ps]),
+          np.ascontiguousarray(X0[:, :Ps]), nthreads=1)
+    el1 = time.perf_counter() - t0
+    return {"value": P * m * nsteps / el, "unit": "point-mode updates/s", "cores": nth, "kind": "oracle",
+            "sample": f"forward only (the oracle has no reverse mode): the benchmark slab's {P} points, "
+                      f"levels 0..{nsteps} of its kappa (the GPU's FP32 values) and X0, alpha={wl.alphas[0]}, "
+                      f"m={m}, FP64, {el:.1f} s with {nth} threads",
+            "single_thread": {"value": Ps * m * nsteps / el1, "points": Ps, "steps": nsteps, "seconds": el1},
+            "host_cpus_visible": vis, "cpu_model": cpu_model()}
+
+
+def headline_differentiation(args, stream, wl_id=5):
+    """One time level of the checkpointed differentiation job, timed: the forward step (with
+    the fused diagnostics), the recomputed step and the adjoint step of the 384^3
+    configuration on its first point slab (wl_id 5), or of the 128^3 configuration on the
+    whole grid (wl_id 4).  FP32 modes, FP32 velocity gradients of the seeded field."""
+    import numpy as np
+    import torch
+    from paper_2411_17294_amd import inputs as I
+    from paper_2411_17294_amd import tfs
+    wl = I.WORKLOADS[wl_id]
+    P = SLAB_384 if wl_id == 5 else wl.npoints
+    point0 = 0
+    alpha, m = wl.alphas[0], wl.nmodes
+    W, K = args.warmup, args.steps
+    if W < 1:
+        raise SystemExit("warmup must include the start-up step (>= 1)")
+    if W + K + 1 > wl.nsteps:
+        raise SystemExit(f"warmup + steps must stay below the workload's {wl.nsteps} time levels")
+    w, lam, _, _, info = tfs.soe_fit(alpha, m, wl.dt, wl.dt * wl.nsteps)
+    log(f"{wl.name}: SOE symbol rel err {info['symbol_relerr']:.2e}, kernel rel err {info['kernel_relerr']:.2e}")
+    tile = 4096 if wl_id == 4 else (None if args.tile < 0 else args.tile)
+    p = tfs.Plan(3, P, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision="fp32_modes", kappa="fp32",
+                 tile=tile)
+    p.tune("grid_per_cu", args.grid_per_cu)
+    ff = I.fourier_field(wl)
+    p.set_field(*ff.table(wl.grid, point0))
+    st, c = p.stride, p.c
+    nlev = max(W + K + 1, 25)
+    t0 = time.perf_counter()
+    kap = torch.zeros((nlev, 9, st), dtype=torch.float32, device="cuda")
+    for n in range(nlev):
+        p.field_eval(n * wl.dt, kap[n])
+    X0 = I.initial_state(wl, point0 + np.arange(P))
+    X, Y, tau, diag = p.alloc()
+    X[0, :, :P] = torch.from_numpy(X0).cuda()
+    # levels n-1, n, n+1 and (read by the shifted mode form) n-2 of the recomputed steps
+    Xs = [torch.zeros((c, st), dtype=torch.float64, device="cuda") for _ in range(4)]
+    Ys = [torch.zeros((m * c * st,), dtype=torch.float32, device="cuda") for _ in range(3)]
+    Xs[0].copy_(X[0])
+    Xs[3].copy_(X[0])
+    Xbar = torch.zeros((p.x_levels, c, st), dtype=torch.float64, device="cuda")
+    Xbar[0, :, :P].normal_()
+    Hbar = torch.zeros((2 * m * c * st,), dtype=torch.float32, device="cuda")
+    pbar = torch.zeros(p.pbar_size, dtype=torch.float64, device="cuda")
+    kbar = torch.zeros((9, st), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s ({P} points, stride {st}, tile {p.tile})")
+    level = lambda n: (kap[n], kap[n - 1] if n >= 1 else None)
+
+    def fwd(n):
+        p.step(n, *level(n), X, Y, tau, diag)
+
+    def rec(n):
+        # the backward sweep recomputes the state and the modes; it needs no stress
+        p.step_levels(n, *level(n), Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Ys[2], None, X_nm2=Xs[3])
+
+    def adj(n):
+        p.step_adjoint(n, *level(n), Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Xbar, Hbar, pbar,
+                       kappabar_a=kbar, kappabar_b=kbar, X_nm2=Xs[3])
+    p.step_levels(0, kap[0], None, Xs[0], None, Xs[1], None, Ys[0], Ys[1], None)
+    for n in range(W):
+        fwd(n)
+        rec(max(n, 1))
+        adj(max(n, 1))
+    torch.cuda.synchronize()
+    E = lambda: torch.cuda.Event(enable_timing=True)
+    evs = {"forward": [], "recompute": [], "adjoint": []}
+    e0, e1 = E(), E()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for n in range(W, W + K):
+        for name, fn in (("forward", fwd), ("recompute", rec), ("adjoint", adj)):
+            a, b = E(), E()
+            a.record(stream)
+            fn(n)
+            b.record(stream)
+            evs[name].append((a, b))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    d = diag.cpu().numpy()
+    if not bool(torch.isfinite(tau[:, :P]).all()) or d[5] != 0 or not d[2] > 0:
+        raise SystemExit(f"non-finite or non-positive-definite state in the benchmark run (diag {d})")
+    kb = 4
+    nbytes = {"forward": algorithmic_bytes_per_point(3, m, 4, 2, kb) * P,
+              # no stress written by the recomputation
+              "recompute": (algorithmic_bytes_per_point(3, m, 4, 2, kb) - c * 8) * P,
+              "adjoint": adjoint_bytes_per_point(3, m, 4, kb) * P}
+    kern = {"forward": "bdf2_kernel", "recompute": "bdf2_kernel", "adjoint": "adj_kernel"}
+    parts = {}
+    for name, lst in evs.items():
+        t = sum(a.elapsed_time(b) for a, b in lst) / K
+        gbs = nbytes[name] / (t * 1e-3) / 1e9
+        parts[name] = {"ms_per_launch": t, "bytes_per_launch": nbytes[name], "achieved_GBs": gbs,
+                       "frac": gbs / HBM_PEAK_GBS, "kernel": kern[name]}
+    dom = max(parts, key=lambda k: parts[k]["ms_per_launch"])
+    tag = "fp32modes_3d_384cube_m48_slab" if wl_id == 5 else "fp32modes_3d_128cube_m32"
+    prof = {"forward": "bdf2_kernel_diag_", "recompute": "bdf2_kernel_", "adjoint": "adj_kernel_"}[dom] + tag
+    ms_level = ms / K
+    total_bytes = sum(nbytes.values())
+    out = {
+        "metric": "point-mode updates/s + % HBM roofline, FP64 vs FP32-mode fwd+adjoint",
+        "value": P * m / (ms_level * 1e-3),
+        "unit": "point-mode updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_level,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 modes / f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name + ("_slab" if wl_id == 5 else ""), "grid": f"{wl.grid}^3",
+                   "points": P, "point0": point0, "alpha": alpha, "modes": m, "dt": wl.dt,
+                   "time_levels": wl.nsteps, "checkpoint_every": wl.ckpt_every,
+                   "form": "fp32 modes, fp32 kappa; fp64 recombination, solve, X, tau",
+                   "kappa": "time-varying, extrapolated" if wl.time_varying else "steady",
+                   "step": "forward (with diagnostics) + recomputed forward + adjoint, per time level",
+                   "mode_form": "shifted (Z)" if p.x_levels == 3 else "Y",
+                   "mode_tile": p.tile},
+        "roofline": {"bound": "hbm", "achieved": parts[dom]["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": parts[dom]["frac"], "traffic": profiled_traffic(prof),
+                     "kernel": parts[dom]["kernel"] + f" ({dom})", "bytes_per_launch": nbytes[dom],
+                     "avg_launch_us": parts[dom]["ms_per_launch"] * 1e3},
+        "parts": parts,
+        "frac_all": total_bytes / (ms_level * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "wall_s": wall,
+        "diag_last_step": d.tolist(),
+    }
+    state = {"wl": wl, "w": w, "lam": lam, "kap": kap, "X0": X0}
+    del X, Y, tau, Xs, Ys, Xbar, Hbar, pbar, kbar
+    return out, state
+
+
+def forward_line(stream, wl_id, steps, warmup, form="default", tile=-1, vec=0, grid_per_cu=16, keep_plans=False):
+    """The forward step of a forward workload (1024^2 FP64 with both alphas, or 256^3) timed on
+    its whole grid: all kappa levels resident, one benchmark step advances every field by one
+    time level.  The FP32-mode form reads FP32 velocity gradients."""
+    import torch
+    from paper_2411_17294_amd import inputs as I
+    from paper_2411_17294_amd import tfs
+    from paper_2411_17294_amd.device_inputs import DeviceKappa, x0_ring
+    wl = I.WORKLOADS[wl_id]
+    form = wl.precision if form == "default" else form
+    kp = "fp64" if form == "fp64" else "fp32"
+    N = wl.nsteps
+    if warmup < 1:
+        raise SystemExit("warmup must include the start-up step (>= 1)")
+    if warmup + steps > N:
+        raise SystemExit(f"warmup + steps must not exceed the workload's {N} time levels")
+    dev = "cuda"
+    ff = I.fourier_field(wl)
+    dk = DeviceKappa(ff, wl.grid, wl.npoints)
+    plans, states = [], []
+    for alpha in wl.alphas:
+        w, lam, _, _, info = tfs.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * N)
+        log(f"alpha={alpha}: SOE symbol rel err {info['symbol_relerr']:.2e}")
+        p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, N, precision=form,
+                     tile=None if tile < 0 else tile, kappa=kp)
+        if vec:
+            p.tune("vec", vec)
+        p.tune("grid_per_cu", grid_per_cu)
+        X = x0_ring(wl, p.stride, levels=p.x_levels)
+        _, Y, tau, _ = p.alloc()
+        plans.append((alpha, w, lam, p))
+        states.append((X, Y, tau))
+    st = plans[0][3].stride
+    kdt = plans[0][3].kappa_dtype
+    t0 = time.perf_counter()
+    if wl.time_varying:
+        nlev = warmup + steps
+        kap = torch.zeros((nlev, wl.dim * wl.dim, st), dtype=kdt, device=dev)
+        for n in range(nlev):
+            dk.fill(kap[n], n * wl.dt)
+        level = lambda n: (kap[n], kap[n - 1] if n >= 1 else None)
+    else:
+        k0 = torch.zeros((wl.dim * wl.dim, st), dtype=kdt, device=dev)
+        dk.fill(k0, 0.0)
+        level = lambda n: (k0, k0)
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
+
+    def step(n):
+        ka, kb = level(n)
+        for (_, _, _, p), (X, Y, tau) in zip(plans, states):
+            p.step(n, ka, kb, X, Y, tau)
+
+    for n in range(warmup):
+        step(n)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for n in range(warmup, warmup + steps):
+        step(n)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    for (X, Y, tau) in states:
+        if not bool(torch.isfinite(tau[:, :wl.npoints]).all()):
+            raise SystemExit("non-finite stress in the benchmark run")
+    nfields = len(wl.alphas)
+    mode_bytes = 8 if form == "fp64" else 4
+    bytes_per_launch = algorithmic_bytes_per_point(wl.dim, wl.nmodes, mode_bytes, 2, 8 if kp == "fp64" else 4) * \
+        wl.npoints
+    avg_launch_s = ms * 1e-3 / (nfields * steps)
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    profile = "bdf2_kernel_" + wl.name + ("" if form == wl.precision else "_" + form)
+    out = {
+        "metric": "point-mode updates/s + % HBM roofline, FP64 vs FP32-mode fwd+adjoint",
+        "value": nfields * wl.npoints * wl.nmodes * steps / (ms * 1e-3),
+        "unit": "point-mode updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": ms / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if form == "fp64" else "f32 modes / f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": f"{wl.grid}^{wl.dim}", "alphas": list(wl.alphas),
+                   "modes": wl.nmodes, "dt": wl.dt, "time_levels": N, "form": form, "kappa_storage": kp,
+                   "kappa": "time-varying, extrapolated" if wl.time_varying else "steady",
+                   "fields_per_step": nfields, "mode_tile": plans[0][3].tile},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(profile),
+                     "kernel": "bdf2_kernel", "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": avg_launch_s * 1e6},
+        "wall_s": wall,
+    }
+    keep = [(a, w, lam) for (a, w, lam, _) in plans]
+    del states, plans
+    if wl.time_varying:
+        del kap
+    torch.cuda.empty_cache()
+    return (out, keep) if keep_plans else out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=990)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", type=int, default=2, help="workload id (2 = default 2-D FP64)")
+    ap.add_argument("--workload", type=int, default=5,
+                    help="5 (default): one time level of the 384^3 differentiation job on a slab; 4: the same "
+                         "on the 128^3 grid; 2, 3: the forward step of the 2-D FP64 / 256^3 configuration")
     ap.add_argument("--form", choices=["default", "fp64", "fp32_modes"], default="default")
     ap.add_argument("--vec", type=int, default=0)
     ap.add_argument("--tile", type=int, default=-1, help="mode-ring tile (points); -1 = library default")
@@ -651,120 +945,38 @@ def main():
         print(json.dumps({"forms": forms, "measured_copy_GBs": copy_rate_gbs(stream)}), flush=True)
         return
 
-    wl = I.WORKLOADS[args.workload]
-    form = wl.precision if args.form == "default" else args.form
-    N = wl.nsteps
-    if args.warmup < 1:
-        raise SystemExit("warmup must include the start-up step (>= 1)")
-    if args.warmup + args.steps > N:
-        raise SystemExit(f"warmup + steps must not exceed the workload's {N} time levels")
+    if args.workload in (4, 5):
+        torch.cuda.set_device(0)
+        stream = torch.cuda.current_stream()
+        out, st = headline_differentiation(args, stream, args.workload)
+        out["roofline"]["measured_copy_GBs"] = copy_rate_gbs(stream)
+        if not args.no_cpu_baseline and args.workload == 5:
+            t0 = time.perf_counter()
+            out["cpu_baseline"] = cpu_baseline_slab(st["wl"], st["w"], st["lam"], st["kap"], st["X0"])
+            log(f"CPU baseline in {time.perf_counter() - t0:.1f} s")
+        del st
+        torch.cuda.empty_cache()
+        if not args.no_forms:
+            t0 = time.perf_counter()
+            out["forms"] = {"forward_2d_1024sq_fp64": forward_line(stream, 2, 20, 5)}
+            out["forms"].update(measure_forms(stream))
+            log(f"form measurements in {time.perf_counter() - t0:.1f} s")
+        print(json.dumps(out), flush=True)
+        return
     torch.cuda.set_device(0)
-    dev = "cuda"
     stream = torch.cuda.current_stream()
-
-    # inputs resident in HBM
-    ff = I.fourier_field(wl)
-    dk = DeviceKappa(ff, wl.grid, wl.npoints)
-    plans, states = [], []
-    for alpha in wl.alphas:
-        w, lam, _, _, info = tfs.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * N)
-        log(f"alpha={alpha}: SOE symbol rel err {info['symbol_relerr']:.2e}")
-        p = tfs.Plan(wl.dim, wl.npoints, w, lam, alpha, wl.De, wl.eta_p, wl.dt, N, precision=form,
-                     tile=None if args.tile < 0 else args.tile)
-        if args.vec:
-            p.tune("vec", args.vec)
-        p.tune("grid_per_cu", args.grid_per_cu)
-        X = x0_ring(wl, p.stride)
-        _, Y, tau, _ = p.alloc()
-        plans.append((alpha, w, lam, p))
-        states.append((X, Y, tau))
-    st = plans[0][3].stride
-    t0 = time.perf_counter()
-    if wl.time_varying:
-        nlev = args.warmup + args.steps
-        kap = torch.empty((nlev, wl.dim * wl.dim, st), dtype=torch.float64, device=dev)
-        for n in range(nlev):
-            dk.fill(kap[n], n * wl.dt)
-        level = lambda n: (kap[n], kap[n - 1] if n >= 1 else None)
-    else:
-        k0 = torch.empty((wl.dim * wl.dim, st), dtype=torch.float64, device=dev)
-        dk.fill(k0, 0.0)
-        level = lambda n: (k0, k0)
-    torch.cuda.synchronize()
-    log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
-
-    def step(n):
-        ka, kb = level(n)
-        for (_, _, _, p), (X, Y, tau) in zip(plans, states):
-            p.step(n, ka, kb, X, Y, tau)
-
-    for n in range(args.warmup):
-        step(n)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    for n in range(args.warmup, args.warmup + args.steps):
-        step(n)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = ev0.elapsed_time(ev1)
-    ms_per_step = ms / args.steps
-    for (X, Y, tau) in states:
-        if not bool(torch.isfinite(tau[:, :wl.npoints]).all()):
-            raise SystemExit("non-finite stress in the benchmark run")
-
-    copy_gbs = copy_rate_gbs(stream)
-
-    nfields = len(wl.alphas)
-    updates = nfields * wl.npoints * wl.nmodes * args.steps
-    value = updates / (ms * 1e-3)
-    mode_bytes = 8 if form == "fp64" else 4
-    bpp = algorithmic_bytes_per_point(wl.dim, wl.nmodes, mode_bytes, 2)
-    bytes_per_launch = bpp * wl.npoints
-    launches = nfields * args.steps
-    avg_launch_s = ms * 1e-3 / launches
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    profile = "bdf2_kernel_" + wl.name + ("" if form == wl.precision else "_" + form)
-    traffic = profiled_traffic(profile)
-
-    out = {
-        "metric": "point-mode updates/s + % HBM roofline, FP64 vs FP32-mode fwd+adjoint",
-        "value": value,
-        "unit": "point-mode updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if form == "fp64" else "f32 modes / f64",
-        "data": "synthetic",
-        "config": {"workload": wl.name, "grid": f"{wl.grid}^{wl.dim}", "alphas": list(wl.alphas),
-                   "modes": wl.nmodes, "dt": wl.dt, "time_levels": N, "form": form,
-                   "kappa": "time-varying, extrapolated" if wl.time_varying else "steady",
-                   "fields_per_step": nfields, "mode_tile": plans[0][3].tile},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "bdf2_kernel", "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": avg_launch_s * 1e6, "measured_copy_GBs": copy_gbs},
-        "wall_s": wall,
-    }
+    out, plans = forward_line(stream, args.workload, args.steps, args.warmup, form=args.form, tile=args.tile,
+                              vec=args.vec, grid_per_cu=args.grid_per_cu, keep_plans=True)
+    out["roofline"]["measured_copy_GBs"] = copy_rate_gbs(stream)
     if not args.no_forms:
-        del states, plans[1:]
-        if wl.time_varying:
-            del kap
         torch.cuda.empty_cache()
         t0 = time.perf_counter()
         out["forms"] = measure_forms(stream)
         log(f"3-D form measurements in {time.perf_counter() - t0:.1f} s")
     if not args.no_cpu_baseline:
-        nthreads = min(16, os.cpu_count() or 1)
-        alpha, w, lam, _ = plans[0]
-        out["cpu_baseline"] = cpu_baseline(wl, alpha, w, lam, nthreads)
+        nthreads, _ = host_threads()
+        alpha, w, lam = plans[0]
+        out["cpu_baseline"] = cpu_baseline(I.WORKLOADS[args.workload], alpha, w, lam, nthreads)
     print(json.dumps(out), flush=True)
 
 

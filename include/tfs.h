@@ -73,6 +73,38 @@ typedef enum {
     TFS_SCHEME_EXP = 1
 } tfs_scheme;
 
+/*
+ * Storage precision of the velocity-gradient fields kappa_a, kappa_b a plan's steps read.
+ * The extrapolation kappa~ = 2 kappa^n - kappa^{n-1} (eq. BDF_and_extrapolation) and all
+ * arithmetic with it are FP64 either way; FP32 storage halves the gradient's share of the
+ * memory traffic of the FP32-mode form.  Gradient adjoints (kappabar) stay FP64.
+ */
+typedef enum {
+    TFS_KAPPA_FP64 = 0,
+    TFS_KAPPA_FP32 = 1    /* FP32-mode plans only; no spatial form, coupled or transport step */
+} tfs_kappa_precision;
+
+/*
+ * How a TFS_SCHEME_BDF2 plan stores its fractional modes (the arithmetic of the scheme is the
+ * same; only what is stored, and so what FP32 storage rounds, differs):
+ *   TFS_MODE_FORM_Y  Y_k^j = X_k^j - c_k X^j.  The new level Y_k^{n+1} = d_k h_k + d_k c_k P is
+ *                    known before the local solve, so the modes stream once.  X ring: 2 slots.
+ *   TFS_MODE_FORM_Z  Z_k^j = Y_k^j - beta_k X^{j-1} with beta_k = w_k/lambda_k - c_k (0 for
+ *                    lambda_k = 0) and X^{-1} = 0: also the quasi-static part (w_k/lambda_k) X of
+ *                    a mode that follows X is taken out, so the stored value is small.  Its
+ *                    new level Y_k^{n+1} - beta_k X^n is still known before the solve; reading
+ *                    level n-1 back needs X^{n-2}, so the X ring holds 3 levels.  The stress is a
+ *                    near-cancelling sum over the modes: with FP32 storage this form rounds it
+ *                    about ten times less (measured at alpha = 0.2, m = 48, 2000 steps).
+ *   TFS_MODE_FORM_AUTO  Z for FP32-mode BDF2 plans, Y otherwise.
+ * TFS_SCHEME_EXP plans have their own one-level form (tfs_scheme).
+ */
+typedef enum {
+    TFS_MODE_FORM_AUTO = 0,
+    TFS_MODE_FORM_Y = 1,
+    TFS_MODE_FORM_Z = 2
+} tfs_mode_form;
+
 enum {
     TFS_FLAG_CHECK_SYNC = 1u << 0  /* tfs_step synchronises and returns TFS_ENUMERIC on non-finite/non-PD diagnostics */
 };
@@ -98,6 +130,8 @@ typedef struct {
     uint32_t flags;       /* TFS_FLAG_* */
     void* stream;         /* hipStream_t the plan launches on (NULL = default stream) */
     int32_t scheme;       /* tfs_scheme */
+    int32_t kappa_precision;  /* tfs_kappa_precision (0 = FP64) */
+    int32_t mode_form;        /* tfs_mode_form (0 = AUTO) */
 } tfs_plan_desc;
 
 /*
@@ -111,7 +145,9 @@ typedef struct {
  * Errors: TFS_EINVAL (dim not 2/3, m < 1, npoints < 0, stride < npoints, alpha not in
  * (0,1], De <= 0, eta_p < 0, dt <= 0, max_steps < 1, null or negative/non-finite w or
  * lambda, unknown precision or scheme, tile negative or not a multiple of 4, stride not
- * a multiple of a positive tile), TFS_ENOMEM, TFS_EHIP.  *out is NULL on error.
+ * a multiple of a positive tile, an unknown kappa precision or FP32 velocity gradients with
+ * FP64 modes, an unknown mode form or TFS_MODE_FORM_Z with TFS_SCHEME_EXP), TFS_ENOMEM,
+ * TFS_EHIP.  *out is NULL on error.
  * With TFS_SCHEME_EXP the per-mode factors are e_k, a0_k and a1_k of tfs_scheme and the
  * mass-mode table holds the increments sum_k (mu_k^{n+1} - mu_k^n).
  */
@@ -146,7 +182,8 @@ tfs_status tfs_plan_set_stream(tfs_plan plan, void* stream);
  * (tfs_pbar_rate_gradient): for rate = eps |xi|^2 that is eps dL/deps.  The diagnostics'
  * minors do not describe a conformation tensor in this form; TFS_FLAG_CHECK_SYNC then
  * checks only the non-finite count.
- * Errors: TFS_EINVAL (null plan, source_point < -1 or >= npoints).
+ * Errors: TFS_EINVAL (null plan, source_point < -1 or >= npoints), TFS_EUNSUPPORTED (a rate
+ * or a source point on a plan with FP32 velocity gradients).
  */
 tfs_status tfs_plan_set_spatial(tfs_plan plan, const double* rate, int64_t source_point);
 
@@ -173,6 +210,19 @@ typedef struct tfs_field {
 /* Errors: TFS_EINVAL (null plan or field, nterms out of range, grid < 1, the points outside
  * the grid, a null or non-finite table), TFS_ENOMEM, TFS_EHIP. */
 tfs_status tfs_plan_set_field(tfs_plan plan, const tfs_field* field);
+
+/*
+ * The plan's analytic velocity gradient (tfs_plan_set_field) at time t on the plan's points,
+ * written for the step calls: kappa_out[q][p] = kappa_q(x_p, t) + add[q][p], each Fourier term's
+ * phase and sine and the sums in FP64, rounded once to the plan's kappa precision.  This is
+ * input synthesis for callers whose gradient is that field (the benchmark workloads); the
+ * update itself never calls it.
+ * add        device [d*d][stride] FP64 (a steady perturbation of the field), or NULL.
+ * kappa_out  device [d*d][stride] in the plan's kappa precision; columns >= npoints untouched.
+ * Asynchronous on the plan's stream; no allocation.
+ * Errors: TFS_EINVAL (null plan, no field set, non-finite t, null kappa_out), TFS_EHIP.
+ */
+tfs_status tfs_field_eval(tfs_plan plan, double t, const double* add, void* kappa_out);
 
 /*
  * Temporally fused steps: advance every point from level n0 to n0 + nsteps in ONE launch,
@@ -203,17 +253,19 @@ tfs_status tfs_run_fused(tfs_plan plan, int64_t n0, int64_t nsteps, double* X, v
  * on the plan's stream; no allocation, no host synchronisation (unless
  * TFS_FLAG_CHECK_SYNC).
  *
- * kappa_a, kappa_b  device [d*d][stride], FP64.  The step is driven by
+ * kappa_a, kappa_b  device [d*d][stride] in the plan's kappa precision (FP64, or FP32 with
+ *                   TFS_KAPPA_FP32).  The step is driven by
  *                   kappa~ = 2 kappa_a - kappa_b  (second-order extrapolation
  *                   E^{n+1} kappa = 2 kappa^n - kappa^{n-1}, eq. BDF_and_extrapolation:
  *                   pass kappa^n, kappa^{n-1}), or kappa~ = kappa_a when kappa_b is NULL
  *                   (pass the gradient of the already updated velocity kappa^{n+1}, as in
  *                   eq. FP_discrete).  At n = 0 kappa_b is ignored.
- * X                 device [2][c][stride] FP64 ring: slot j%2 holds level j.  The caller
- *                   stores X^0 in slot 0 before n = 0.  Level n+1 overwrites slot (n+1)%2.
+ * X                 device [L][c][stride] FP64 ring, L = tfs_plan_x_levels (2, or 3 for the
+ *                   shifted mode form): slot j%L holds level j.  The caller stores X^0 in
+ *                   slot 0 before n = 0.  Level n+1 overwrites slot (n+1)%L.
  * Y                 device ring of the fractional modes, 2 * m * c * stride elements in the
- *                   plan's (possibly tiled) layout, in the representation Y_k = X_k - c_k X
- *                   (FP64, or FP32 for TFS_FP32_MODES): slot j%2 holds level j.  Written
+ *                   plan's (possibly tiled) layout, in the plan's mode form (tfs_mode_form;
+ *                   FP64, or FP32 for TFS_FP32_MODES): slot j%2 holds level j.  Written
  *                   entirely at n = 0 (levels 0 and 1); its input contents are ignored then.
  * tau               device [c][stride] FP64 or NULL: tau^{n+1} = gamma D^{1-alpha} X^{n+1}.
  * diag              device [6] FP64 or NULL: over the points at level n+1, the minimum of the
@@ -230,7 +282,7 @@ tfs_status tfs_run_fused(tfs_plan plan, int64_t n0, int64_t nsteps, double* X, v
  * layout, in the representation Y_k = X_k - q_k X with q_k = w_k dt a1_k, updated in place
  * from level n to n+1; at n = 0 its input contents are ignored (the modes start at zero).
  */
-tfs_status tfs_step(tfs_plan plan, int64_t n, const double* kappa_a, const double* kappa_b,
+tfs_status tfs_step(tfs_plan plan, int64_t n, const void* kappa_a, const void* kappa_b,
                     double* X, void* Y, double* tau, double* diag);
 
 /*
@@ -239,6 +291,8 @@ tfs_status tfs_step(tfs_plan plan, int64_t n, const double* kappa_a, const doubl
  * layouts per level:
  *   X_n, X_nm1, X_out    [c][stride] FP64: levels n, n-1 (unused at n = 0) and n+1;
  *                        X_out must not alias X_n (it may alias X_nm1).
+ *   X_nm2                [c][stride] FP64 level n-2: read by shifted-mode-form plans at n >= 2
+ *                        (X_out may alias it); ignored otherwise.
  *   Y_n, Y_nm1, Y_out    m * c * stride mode elements each (plan precision and tiling):
  *                        levels n, n-1 and n+1; Y_out may alias Y_nm1 but not Y_n.
  *                        At n = 0 the start-up writes level 0 into Y_nm1 and level 1 into
@@ -247,8 +301,8 @@ tfs_status tfs_step(tfs_plan plan, int64_t n, const double* kappa_a, const doubl
  * TFS_SCHEME_EXP plans read X_n and Y_n (ignored at n = 0) and write X_out and Y_out,
  * which may alias Y_n; X_nm1 and Y_nm1 are unused.
  */
-tfs_status tfs_step_levels(tfs_plan plan, int64_t n, const double* kappa_a, const double* kappa_b,
-                           const double* X_n, const double* X_nm1, double* X_out,
+tfs_status tfs_step_levels(tfs_plan plan, int64_t n, const void* kappa_a, const void* kappa_b,
+                           const double* X_n, const double* X_nm1, const double* X_nm2, double* X_out,
                            const void* Y_n, void* Y_nm1, void* Y_out, double* tau, double* diag);
 
 /*
@@ -261,13 +315,19 @@ tfs_status tfs_step_levels(tfs_plan plan, int64_t n, const double* kappa_a, cons
  * the same run (recomputed from checkpoints by the caller):
  *   X_n, X_nm1, X_np1   [c][stride] FP64 forward levels n, n-1, n+1 (X_n = X^0 at n = 0;
  *                       X_nm1, X_np1 unused at n = 0)
+ *   X_nm2               forward level n-2: read by shifted-mode-form plans at n >= 2 only
  *   Y_n, Y_nm1          forward mode levels n, n-1 (tiled layout; unused at n = 0)
- *   kappa_a, kappa_b    as passed to the forward step n
- *   Xbar                device [2][c][stride] FP64 adjoint ring.  Before step n, slot (n+1)%2
- *                       holds dL/dX^{n+1} from the later steps and slot n%2 the part of dL/dX^n
- *                       from step n+1; after it, slot n%2 holds dL/dX^n complete and slot
- *                       (n+1)%2 the part of dL/dX^{n-1} from step n.  After n = 0, slot 0 is
- *                       dL/dX^0.
+ *   kappa_a, kappa_b    as passed to the forward step n (the plan's kappa precision)
+ *   Xbar                device [L][c][stride] FP64 adjoint ring (L = tfs_plan_x_levels).  With
+ *                       L = 2: before step n, slot (n+1)%2 holds dL/dX^{n+1} from the later
+ *                       steps and slot n%2 the part of dL/dX^n from step n+1; after it, slot n%2
+ *                       holds dL/dX^n complete and slot (n+1)%2 the part of dL/dX^{n-1} from
+ *                       step n.  With L = 3 (the shifted mode form, where step n also reads
+ *                       X^{n-2}): before step n, slot (n+1)%3 holds dL/dX^{n+1} complete, slot
+ *                       n%3 and slot (n-1)%3 the parts of dL/dX^n and dL/dX^{n-1} from the later
+ *                       steps (zero before the last step); after it, slot n%3 holds dL/dX^n
+ *                       complete, slot (n-1)%3 the part of dL/dX^{n-1} so far and slot (n+1)%3
+ *                       the part of dL/dX^{n-2} from step n.  After n = 0, slot 0 is dL/dX^0.
  *   Hbar                device mode-adjoint ring (2 slots, plan precision and tiling) holding
  *                       H_k^(j) = dL/d(2 Y_k^j - Y_k^{j-1}/2); slot j%2 holds H^(j).
  *   taubar              device [c][stride] FP64 dL/dtau^{n+1} (or NULL: no direct loss on it)
@@ -284,8 +344,8 @@ tfs_status tfs_step_levels(tfs_plan plan, int64_t n, const double* kappa_a, cons
  * Asynchronous on the plan's stream.  Errors: TFS_EINVAL (null required pointer, n out of
  * range), TFS_EHIP.
  */
-tfs_status tfs_step_adjoint(tfs_plan plan, int64_t n, const double* kappa_a, const double* kappa_b,
-                            const double* X_n, const double* X_nm1, const double* X_np1,
+tfs_status tfs_step_adjoint(tfs_plan plan, int64_t n, const void* kappa_a, const void* kappa_b,
+                            const double* X_n, const double* X_nm1, const double* X_nm2, const double* X_np1,
                             const void* Y_n, const void* Y_nm1, double* Xbar, void* Hbar,
                             const double* taubar, double* kappabar_a, double* kappabar_b, double* pbar);
 
@@ -296,10 +356,17 @@ int64_t tfs_pbar_size(tfs_plan plan);
  * Host chain rule from an accumulated pbar (host copy) to the gradients with respect to the
  * weights and poles (dL_dw, dL_dlambda: host [m]), the relaxation time De and eta_p (host
  * scalars), through every coefficient the plan derived from them: the BDF2 factors, the
- * SDIRK2 start-up factors and the mass-mode memory table.  Any output may be NULL.
+ * SDIRK2 start-up factors and the mass-mode memory table (of the exponential-mode factors and
+ * its mass-mode increments for TFS_SCHEME_EXP plans), and on to the fractional order:
+ *   dL_dalpha = sum_k (dL/dw_k dw_k/dalpha + dL/dlambda_k dlambda_k/dalpha)   (compensated),
+ * with dw_dalpha, dlambda_dalpha (host [m]) the derivatives of the plan's sum-of-exponentials
+ * rule, for example those tfs_soe_gl_log returns for a window held fixed (Sec. 2.2).
+ * Any output may be NULL; dw_dalpha and dlambda_dalpha are read only for dL_dalpha.
+ * Errors: TFS_EINVAL (null plan or pbar, dL_dalpha without both derivative tables).
  */
-tfs_status tfs_pbar_to_params(tfs_plan plan, const double* pbar_host, double* dL_dw, double* dL_dlambda,
-                              double* dL_dDe, double* dL_deta_p);
+tfs_status tfs_pbar_to_params(tfs_plan plan, const double* pbar_host, const double* dw_dalpha,
+                              const double* dlambda_dalpha, double* dL_dw, double* dL_dlambda,
+                              double* dL_dDe, double* dL_deta_p, double* dL_dalpha);
 
 /*
  * Spatial form: sum_p rate_p dL/drate_p from a host copy of the accumulated pbar of a
@@ -310,13 +377,17 @@ tfs_status tfs_pbar_to_params(tfs_plan plan, const double* pbar_host, double* dL
 tfs_status tfs_pbar_rate_gradient(tfs_plan plan, const double* pbar_host, double* out);
 
 /*
- * Convert the mode ring slot `slot` (0 or 1) to plain fractional modes
- * X_k = Y_k + c_k X, with X taken from the same slot of the X ring.
+ * Plain fractional modes X_k of time level `level` from the rings of tfs_step: the mode
+ * ring's slot level%2 and the X ring's levels `level` and `level`-1 (X_k = Y_k + c_k X^level,
+ * plus beta_k X^{level-1} in the shifted form, X^{-1} = 0), the latter two still in the X ring.
  * Xk_out: device [m][c][stride] FP64, untiled.  Asynchronous on the plan's stream.
- * TFS_SCHEME_EXP plans: Y is the single mode level, X_k = Y_k + q_k X with X from slot
- * `slot` of the X ring (the slot of the level Y holds).
+ * TFS_SCHEME_EXP plans: Y is the single mode level, holding level `level`; X_k = Y_k + q_k X.
+ * Errors: TFS_EINVAL (null plan, level < 0).
  */
-tfs_status tfs_modes_to_plain(tfs_plan plan, int32_t slot, const double* X, const void* Y, double* Xk_out);
+tfs_status tfs_modes_to_plain(tfs_plan plan, int64_t level, const double* X, const void* Y, double* Xk_out);
+
+/* Slots of the plan's X ring (and of the adjoint's Xbar ring): 2, or 3 for the shifted mode form. */
+int32_t tfs_plan_x_levels(tfs_plan plan);
 
 /*
  * Host copies of the plan's coefficient tables, FP64:

@@ -1,7 +1,7 @@
 """Build the CPU oracle library (test infrastructure only).
 
-Compiles tfs_oracle.c twice (real and complex-step scalar types) with gcc and
-links both into oracle/liboracle.so.  -ffp-contract=off keeps every product and
+Compiles tfs_oracle.c three times (real, complex-step and x87 extended-precision
+scalar types) with gcc and links them into oracle/liboracle.so.  -ffp-contract=off keeps every product and
 sum rounded separately, as written.
 """
 import os
@@ -16,7 +16,7 @@ def build(verbose: bool = False, src: str = None, lib: str = None) -> str:
     src = src or os.path.join(HERE, "tfs_oracle.c")
     lib = lib or LIB
     objs = []
-    for tag, defs in (("real", []), ("cplx", ["-DORC_COMPLEX"])):
+    for tag, defs in (("real", []), ("cplx", ["-DORC_COMPLEX"]), ("long", ["-DORC_LONG"])):
         obj = lib + f".{tag}.o"
         cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-fopenmp", "-ffp-contract=off",
                "-Wall", "-Wno-unused-function", *defs, "-c", src, "-o", obj]

@@ -37,10 +37,12 @@
  * Phi^{n+1} - Phi^n = A(kappa~) sum_k (Phi_k^{n+1} - Phi_k^n), exact for constant
  * kappa, with kappa~ at the half step (one-step scheme, no start-up step).
  *
- * The same source is compiled twice: once with real doubles (orc_*), once with
- * C99 complex doubles (orcz_*) for complex-step derivatives (the imaginary part
- * of every output is the directional derivative along the imaginary part of
- * the inputs, exact to rounding).  Branches compare real parts only.
+ * The same source is compiled three times: with real doubles (orc_*), with C99
+ * complex doubles (orcz_*) for complex-step derivatives (the imaginary part of
+ * every output is the directional derivative along the imaginary part of the
+ * inputs, exact to rounding), and with x87 extended-precision long doubles
+ * (orcl_*, 64-bit significand) as a reference for the rounding error of FP64
+ * evaluations of the same discrete scheme.  Branches compare real parts only.
  */
 #include <complex.h>
 #include <math.h>
@@ -50,21 +52,38 @@
 #include <omp.h>
 #endif
 
-#ifdef ORC_COMPLEX
+#if defined(ORC_COMPLEX)
 typedef double complex sc;
+typedef double rl;       /* real scalar of the build */
 #define ORC(name) orcz_##name
 #define RE(x) creal(x)
+#elif defined(ORC_LONG)
+typedef long double sc;
+typedef long double rl;
+#define ORC(name) orcl_##name
+#define RE(x) (x)
 #else
 typedef double sc;
+typedef double rl;
 #define ORC(name) orc_##name
 #define RE(x) (x)
+#endif
+
+#ifdef ORC_LONG
+#define SQRTR(x) sqrtl(x)
+#define FABSR(x) fabsl(x)
+#else
+#define SQRTR(x) sqrt(x)
+#define FABSR(x) fabs(x)
 #endif
 
 #define MAXD 3
 #define MAXN 7 /* c + 1 in 3-D */
 
-#ifdef ORC_COMPLEX
+#if defined(ORC_COMPLEX)
 #define EXPS(x) cexp(x)
+#elif defined(ORC_LONG)
+#define EXPS(x) expl(x)
 #else
 #define EXPS(x) exp(x)
 #endif
@@ -131,7 +150,7 @@ static int hset_find(const hset* h, const int* zz) {
  * kap[i*d+j] = kappa_ij = d u_i / d x_j, so (grad u)_{ml} = kap[m*d+l]. */
 static void build_A(const hset* h, sc De, const sc* kap, sc* A) {
     const int d = h->d, n = h->n;
-    const double a = 1.0 / sqrt(2.0);
+    const rl a = 1 / SQRTR((rl)2);
     for (int i = 0; i < n * n; ++i) A[i] = 0.0;
     for (int r = 0; r < n; ++r) {
         const int* z = h->z[r];
@@ -173,9 +192,9 @@ static void build_A(const hset* h, sc De, const sc* kap, sc* A) {
 static int gauss_solve(int n, sc* M, sc* b) {
     for (int j = 0; j < n; ++j) {
         int p = j;
-        double best = fabs(RE(M[j * n + j]));
+        rl best = FABSR(RE(M[j * n + j]));
         for (int i = j + 1; i < n; ++i) {
-            double v = fabs(RE(M[i * n + j]));
+            rl v = FABSR(RE(M[i * n + j]));
             if (v > best) { best = v; p = i; }
         }
         if (best == 0.0) return 0;
@@ -218,7 +237,7 @@ static void tensor_to_hermite(const hset* h, const sc* Xfull /* d*d */, sc mass,
             for (int t = 0; t < z[l]; ++t) { if (i1 < 0) i1 = l; else i2 = l; }
         }
         if (deg == 0) Phi[r] = mass;
-        else if (i1 == i2) Phi[r] = Xfull[i1 * d + i1] / sqrt(2.0);
+        else if (i1 == i2) Phi[r] = Xfull[i1 * d + i1] / SQRTR((rl)2);
         else Phi[r] = Xfull[i1 * d + i2];
     }
 }
@@ -233,7 +252,7 @@ static void hermite_to_tensor(const hset* h, const sc* Phi, sc* Xfull /* d*d */)
             for (int t = 0; t < z[l]; ++t) { if (i1 < 0) i1 = l; else i2 = l; }
         }
         if (deg == 0) continue;
-        if (i1 == i2) Xfull[i1 * d + i1] = sqrt(2.0) * Phi[r];
+        if (i1 == i2) Xfull[i1 * d + i1] = SQRTR((rl)2) * Phi[r];
         else { Xfull[i1 * d + i2] = Phi[r]; Xfull[i2 * d + i1] = Phi[r]; }
     }
 }
@@ -251,7 +270,7 @@ static sc neumaier(int n, const sc* x) {
     sc s = 0.0, comp = 0.0;
     for (int i = 0; i < n; ++i) {
         sc t = s + x[i];
-        if (fabs(RE(s)) >= fabs(RE(x[i]))) comp += (s - t) + x[i];
+        if (FABSR(RE(s)) >= FABSR(RE(x[i]))) comp += (s - t) + x[i];
         else comp += (x[i] - t) + s;
         s = t;
     }
@@ -281,6 +300,11 @@ static void kappa_level(const sc* kappa, long nlev, long npts, int d, long p, lo
  *                2: the exponential-mode scheme (see the header); kappa~ is then
  *                3/2 kappa^n - 1/2 kappa^{n-1} (kappa^0 at n = 0) with extrap, else kappa^{n+1}
  *   X0           [c][npts] packed initial X = C - I
+ *   mass         [npts] the mass mode Phi_000 of each point, or NULL: 1 everywhere (a
+ *                normalised density, Sec. 3.4).  0 gives a point without the mass mode and
+ *                so without its source term: the scheme is linear in the whole vector Phi
+ *                and Phi_000 is constant in time, and a coefficient of a non-constant
+ *                basis function of the spatial form has no mass-mode part.
  * Outputs (any may be NULL)
  *   X_out        [2][c][npts] levels N and N-1 (N = nsteps)
  *   tau_out      [c][npts] tau^N (zero when nsteps == 0)
@@ -293,7 +317,8 @@ static void kappa_level(const sc* kappa, long nlev, long npts, int d, long p, lo
  */
 int ORC(run)(int d, long npts, int m, const sc* w, const sc* lam, sc De, sc eta_p, double dt,
              long nsteps, const sc* kappa, long nlev, int extrap, int startup, const sc* X0,
-             sc* X_out, sc* tau_out, sc* modes_out, sc* traj_out, double* diag_out, int nthreads)
+             const double* mass, sc* X_out, sc* tau_out, sc* modes_out, sc* traj_out, double* diag_out,
+             int nthreads)
 {
     if ((d != 2 && d != 3) || npts < 0 || m < 1 || nsteps < 0 || startup < 0 || startup > 2) return 1;
     if (nlev != 1 && nlev < nsteps + 1) return 1;
@@ -302,7 +327,7 @@ int ORC(run)(int d, long npts, int m, const sc* w, const sc* lam, sc De, sc eta_
     hset_init(&h, d);
     const int n = h.n;
     const double b0 = 1.5, b1 = -2.0, b2 = 0.5;
-    const double gs = 1.0 - 1.0 / sqrt(2.0);   /* SDIRK2 diagonal */
+    const rl gs = 1 - 1 / SQRTR((rl)2);   /* SDIRK2 diagonal */
     const sc gamma = eta_p / De;
     int status = 0;
 
@@ -354,7 +379,7 @@ int ORC(run)(int d, long npts, int m, const sc* w, const sc* lam, sc De, sc eta_
                 Xf[j * d + i] = X0[(size_t)s * npts + p];
             }
             sc* P0 = Phi;          /* slot of level 0 */
-            tensor_to_hermite(&h, Xf, 1.0, P0);
+            tensor_to_hermite(&h, Xf, mass ? (sc)mass[p] : (sc)1.0, P0);
             for (int q = 0; q < 2 * m * n; ++q) Phik[q] = 0.0;
             if (startup == 1) for (int q = 0; q < n; ++q) Phi[n + q] = P0[q]; /* ghost Phi^{-1} in slot 1 */
             if (traj_out)
@@ -412,7 +437,7 @@ int ORC(run)(int d, long npts, int m, const sc* w, const sc* lam, sc De, sc eta_
                      * Each stage solves Y = E + h*gs*F(Y); the modes are eliminated:
                      *   Y_k = (E_k + h gs w_k Y) / (1 + h gs lam_k),
                      *   (I - h gs theta A) Y = E - h gs A sum_k lam_k E_k / (1 + h gs lam_k). */
-                    const double hg = dt * gs;
+                    const rl hg = dt * gs;
                     sc theta = 0.0;
                     for (int k = 0; k < m; ++k) theta += w[k] / (1.0 + hg * lam[k]);
                     sc Y1[MAXN], Y2[MAXN], E[MAXN], F1[MAXN];

@@ -16,8 +16,8 @@ schedules them and keeps checkpoints:
   steps into per-level buffers (tfs_step_levels), then run the adjoint steps back
   through the segment (tfs_step_adjoint).
 
-Memory: N/K checkpoints of two mode levels (one with the exponential-mode scheme) plus K+2
-mode levels of one segment.
+Memory: N/K checkpoints of two mode levels (one with the exponential-mode scheme) and two or
+three X levels, plus K+2 mode levels of one segment.
 Points are independent, so `run_slabs` processes a grid in point slabs with the same
 code and sums the parameter gradients.
 """
@@ -26,7 +26,6 @@ from __future__ import annotations
 import dataclasses
 from typing import Callable, Optional
 
-import numpy as np
 import torch
 
 from . import tfs
@@ -49,6 +48,12 @@ class Spec:
     kappa_levels: Optional[Callable] = None
     # "bdf2" (the paper's scheme) or "exp" (exponential mode update, one mode level)
     scheme: str = "bdf2"
+    # storage precision of the velocity-gradient levels the steps read: "fp64", or "fp32"
+    # (FP32-mode plans); the differentiable input and its gradient stay FP64
+    kappa: str = "fp64"
+    # analytic time-varying base field evaluated by the library (tfs_field_eval) in place of
+    # kappa_levels: (k [NF][d], phase [NF], omega [NF], coef [NF][d][d], grid, point0)
+    field: Optional[tuple] = None
 
 
 class Checkpointed:
@@ -61,7 +66,10 @@ class Checkpointed:
         w, lam, dw, dl = tfs.soe_gl_log(alpha, spec.nmodes, spec.y_lo, spec.y_hi)
         self.w, self.lam, self.dw, self.dl = w, lam, dw, dl
         self.plan = tfs.Plan(spec.dim, self.P, w, lam, alpha, De, eta_p, spec.dt, spec.nsteps,
-                             precision=spec.precision, tile=spec.tile, scheme=spec.scheme)
+                             precision=spec.precision, tile=spec.tile, scheme=spec.scheme, kappa=spec.kappa)
+        if spec.field is not None:
+            self.plan.set_field(*spec.field)
+        self.kdt = self.plan.kappa_dtype
         self.exp = spec.scheme == "exp"
         self.dev = device
         self.c = spec.dim * (spec.dim + 1) // 2
@@ -70,27 +78,37 @@ class Checkpointed:
         self.ys = self.plan.m * self.c * self.st
 
     # -- velocity gradient of level n ---------------------------------------------------------
+    def _time_varying(self):
+        return self.spec.kappa_levels is not None or self.spec.field is not None
+
     def _level_cache(self, nslots):
         """Level buffers of a time-varying base field: slot n % nslots holds level n (+ the
         perturbation) once filled, so consecutive steps and the adjoint sweep over a
         recomputed segment evaluate each level once."""
         st, d2 = self.st, self.spec.dim * self.spec.dim
-        return {"buf": [torch.zeros((d2, st), dtype=torch.float64, device=self.dev) for _ in range(nslots)],
+        return {"buf": [torch.zeros((d2, st), dtype=self.kdt, device=self.dev) for _ in range(nslots)],
                 "held": [None] * nslots}
 
     def _kappa(self, pert, n, cache):
         i = n % len(cache["buf"])
         buf = cache["buf"][i]
         if cache["held"][i] != n:
-            self.spec.kappa_levels(n, buf)
-            buf[:, :self.P] += pert[:, :self.P]
+            if self.spec.field is not None:
+                self.plan.field_eval(n * self.spec.dt, buf, add=pert)
+            else:
+                lev = buf if self.kdt == torch.float64 else self._lev64
+                self.spec.kappa_levels(n, lev)
+                lev[:, :self.P] += pert[:, :self.P]
+                if lev is not buf:
+                    buf.copy_(lev)
             cache["held"][i] = n
         return buf
 
     def _levels(self, pert, n, cache):
         """(kappa_a, kappa_b) of step n."""
-        if self.spec.kappa_levels is None:
-            return pert, (pert if self.spec.extrap else None)
+        if not self._time_varying():
+            k = self.kappa_steady
+            return k, (k if self.spec.extrap else None)
         if self.spec.extrap:
             ka = self._kappa(pert, n, cache)
             kb = self._kappa(pert, n - 1, cache) if n >= 1 else None
@@ -101,25 +119,35 @@ class Checkpointed:
         """kappa: [d*d][P] FP64 device (steady field, or perturbation); X0: [c][P]. Returns tau^N."""
         sp, P, st = self.spec, self.P, self.st
         d2 = sp.dim * sp.dim
+        # FP64 perturbation of a time-varying field, or the steady field itself
         self.kappa_pad = torch.zeros((d2, st), dtype=torch.float64, device=self.dev)
         self.kappa_pad[:, :P] = kappa
-        cache = self._level_cache(2) if sp.kappa_levels is not None else None
-        X = torch.zeros((2, self.c, st), dtype=torch.float64, device=self.dev)
+        if self._time_varying():
+            if sp.field is None and self.kdt != torch.float64:
+                self._lev64 = torch.zeros((d2, st), dtype=torch.float64, device=self.dev)
+        else:
+            self.kappa_steady = self.kappa_pad if self.kdt == torch.float64 else self.kappa_pad.to(self.kdt)
+        cache = self._level_cache(2) if self._time_varying() else None
+        XL = self.plan.x_levels
+        X = torch.zeros((XL, self.c, st), dtype=torch.float64, device=self.dev)
         X[0, :, :P] = X0
         Y = torch.zeros((self.plan.mode_levels * self.ys,), dtype=self.mt, device=self.dev)
         tau = torch.zeros((self.c, st), dtype=torch.float64, device=self.dev)
-        self.ckpt = {0: (X[0].clone(), None, None, None)}
+        # a checkpoint of level n: X at levels n, n-1 (and n-2 in the shifted mode form; a level
+        # below 0 is not kept) and the mode levels n, n-1 (level n only, exponential scheme)
+        self.ckpt = {0: ((X[0].clone(),), ())}
         K, N = sp.ckpt_every, sp.nsteps
         for n in range(N):
             if n > 0 and n % K == 0:
-                sn, sm = n % 2, (n - 1) % 2
-                if self.exp:   # one-step scheme: level n of X and of the modes
-                    self.ckpt[n] = (X[sn].clone(), None, Y.clone(), None)
+                if self.exp:
+                    self.ckpt[n] = ((X[n % XL].clone(),), (Y.clone(),))
                 else:
-                    self.ckpt[n] = (X[sn].clone(), X[sm].clone(), Y[sn * self.ys:(sn + 1) * self.ys].clone(),
-                                    Y[sm * self.ys:(sm + 1) * self.ys].clone())
+                    xs = tuple(X[(n - j) % XL].clone() for j in range(min(XL, n + 1)))
+                    ys = tuple(Y[(l % 2) * self.ys:(l % 2 + 1) * self.ys].clone() for l in (n, n - 1))
+                    self.ckpt[n] = (xs, ys)
             ka, kb = self._levels(self.kappa_pad, n, cache)
             self.plan.step(n, ka, kb, X, Y, tau)
+        self.X_last = X[N % XL, :, :P].clone()      # the final state, for callers that check it
         return tau[:, :P].clone()
 
     def backward(self, tau_bar):
@@ -129,41 +157,40 @@ class Checkpointed:
         K, N = sp.ckpt_every, sp.nsteps
         taubar = torch.zeros((c, st), dtype=torch.float64, device=self.dev)
         taubar[:, :P] = tau_bar
-        Xbar = torch.zeros((2, c, st), dtype=torch.float64, device=self.dev)
+        Xbar = torch.zeros((self.plan.x_levels, c, st), dtype=torch.float64, device=self.dev)
         Hbar = torch.zeros((self.plan.mode_levels * self.ys,), dtype=self.mt, device=self.dev)
         pbar = torch.zeros(self.plan.pbar_size, dtype=torch.float64, device=self.dev)
         kbar = torch.zeros((d2, st), dtype=torch.float64, device=self.dev)
         starts = sorted(self.ckpt)
-        seg_len = K + 1
-        Xseg = [torch.zeros((c, st), dtype=torch.float64, device=self.dev) for _ in range(seg_len + 1)]
-        Yseg = [torch.zeros((self.ys,), dtype=self.mt, device=self.dev) for _ in range(seg_len + 1)]
+        # local index i <-> level s0 - 2 + i: slot 0 = level s0-2 (shifted mode form only),
+        # slot 1 = level s0-1, slot 2 = level s0, ..., slot K + 2 = level s0 + K
+        Xseg = [torch.zeros((c, st), dtype=torch.float64, device=self.dev) for _ in range(K + 3)]
+        Yseg = [torch.zeros((self.ys,), dtype=self.mt, device=self.dev) for _ in range(K + 3)]
         # the levels a segment needs (s0 - 1 .. s1) fit without eviction; the recompute fills
         # them and the adjoint sweep of the same segment reuses them
-        cache = self._level_cache(K + 2) if sp.kappa_levels is not None else None
-        tau_tmp = torch.zeros((c, st), dtype=torch.float64, device=self.dev)
+        cache = self._level_cache(K + 2) if self._time_varying() else None
+        lv = lambda n: n - s0 + 2
         for s0 in reversed(starts):
             s1 = min(s0 + K, N)
-            # local index i <-> level s0 - 1 + i: slot 0 = level s0-1, slot 1 = level s0, ...
-            Xc, Xp, Yc, Yp = self.ckpt[s0]
-            Xseg[1].copy_(Xc)
-            if s0 > 0:
-                Yseg[1].copy_(Yc)
-                if not self.exp:
-                    Xseg[0].copy_(Xp)
-                    Yseg[0].copy_(Yp)
+            xs, ys = self.ckpt[s0]
+            for j, x in enumerate(xs):           # levels s0, s0-1, s0-2
+                Xseg[lv(s0 - j)].copy_(x)
+            for j, y in enumerate(ys):
+                Yseg[lv(s0 - j)].copy_(y)
+            X2 = lambda n: Xseg[lv(n - 2)] if n >= 2 else None
             for n in range(s0, s1):
-                i = n - s0 + 1
+                i = lv(n)
                 ka, kb = self._levels(self.kappa_pad, n, cache)
                 if self.exp:
                     self.plan.step_levels(n, ka, kb, Xseg[i], None, Xseg[i + 1], Yseg[i] if n > 0 else None, None,
-                                          Yseg[i + 1], tau_tmp)
+                                          Yseg[i + 1], None)
                 elif n == 0:
-                    self.plan.step_levels(0, ka, kb, Xseg[i], None, Xseg[i + 1], None, Yseg[i], Yseg[i + 1], tau_tmp)
+                    self.plan.step_levels(0, ka, kb, Xseg[i], None, Xseg[i + 1], None, Yseg[i], Yseg[i + 1], None)
                 else:
                     self.plan.step_levels(n, ka, kb, Xseg[i], Xseg[i - 1], Xseg[i + 1], Yseg[i], Yseg[i - 1],
-                                          Yseg[i + 1], tau_tmp)
+                                          Yseg[i + 1], None, X_nm2=X2(n))
             for n in range(s1 - 1, s0 - 1, -1):
-                i = n - s0 + 1
+                i = lv(n)
                 ka, kb = self._levels(self.kappa_pad, n, cache)
                 tb = taubar if n == N - 1 else None
                 if self.exp:
@@ -175,9 +202,9 @@ class Checkpointed:
                                            taubar=tb, kappabar_a=kbar, kappabar_b=kbar)
                 else:
                     self.plan.step_adjoint(n, ka, kb, Xseg[i], Xseg[i - 1], Xseg[i + 1], Yseg[i], Yseg[i - 1],
-                                           Xbar, Hbar, pbar, taubar=tb, kappabar_a=kbar, kappabar_b=kbar)
-        gw, gl, gDe, gep = self.plan.pbar_to_params(pbar.cpu().numpy())
-        galpha = float(np.dot(gw, self.dw) + np.dot(gl, self.dl))
+                                           Xbar, Hbar, pbar, taubar=tb, kappabar_a=kbar, kappabar_b=kbar,
+                                           X_nm2=X2(n))
+        gw, gl, gDe, gep, galpha = self.plan.pbar_to_params(pbar.cpu().numpy(), self.dw, self.dl)
         return kbar[:, :P].clone(), Xbar[0, :, :P].clone(), galpha, gDe, gep
 
     def release(self):
@@ -215,9 +242,11 @@ def run_slabs(spec: Spec, slabs, alpha, De, eta_p, loss_grad, device="cuda", kee
     """Forward + backward slab by slab (points are independent, so the parameter gradients
     are sums over slabs and the field gradients are slab-local).
 
-    slabs: iterable of (kappa [d*d][P], X0 [c][P]) or (kappa, X0, kappa_levels) device
-    tensors, or callables returning them; kappa_levels(n, out) replaces spec.kappa_levels
-    for that slab (a time-varying base field evaluated on the slab's points).
+    slabs: iterable of (kappa [d*d][P], X0 [c][P]) or (kappa, X0, levels) device
+    tensors, or callables returning them; levels is kappa_levels(n, out), which replaces
+    spec.kappa_levels for that slab, or a field tuple as Spec.field (with the slab's first
+    grid point as point0), which replaces spec.field: a time-varying base field evaluated on
+    the slab's points.
     loss_grad(tau [c][P], slab_index) -> (loss_value, dL/dtau).
     Returns dict: loss, alpha, De, eta_p (summed over slabs) and, with keep_fields, the
     per-slab (dL/dkappa, dL/dX0) on the host."""
@@ -228,7 +257,10 @@ def run_slabs(spec: Spec, slabs, alpha, De, eta_p, loss_grad, device="cuda", kee
         kappa, X0 = item[0], item[1]
         sp = spec
         if len(item) > 2 and item[2] is not None:
-            sp = dataclasses.replace(spec, kappa_levels=item[2])
+            if isinstance(item[2], tuple):      # the slab's analytic field (tfs_field_eval)
+                sp = dataclasses.replace(spec, field=item[2], kappa_levels=None)
+            else:
+                sp = dataclasses.replace(spec, kappa_levels=item[2])
         run = Checkpointed(sp, X0.shape[1], alpha, De, eta_p, device=device)
         tau = run.forward(kappa, X0)
         lv, tb = loss_grad(tau, j)

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtfs.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("tfs_kernels.hip", "tfs_adjoint.hip", "tfs_fused.hip", "tfs_ns.hip", "tfs_transport.hip",
-                                                          "tfs_host.cpp")]
+                                                          "tfs_field.hip", "tfs_host.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -215,17 +215,21 @@ __device__ __forceinline__ void adj_spatial(const AdjSpatial& sp, const double* 
 }
 
 // ------------------------------------------------------------------ BDF2 step adjoint
-template <typename MT>
+template <typename MT, typename KT>
 struct AdjArgs {
-  const double* ka;
-  const double* kb;      // null: kappa~ = kappa_a
+  const KT* ka;          // the plan's kappa precision
+  const KT* kb;          // null: kappa~ = kappa_a
   const double* Xn;      // forward X^n
   const double* Xm;      // forward X^{n-1}
+  const double* Xmm;     // forward X^{n-2} (shifted mode form; null: zero)
   const double* Xp;      // forward X^{n+1}
-  const MT* Yn;          // forward Y^n (tiled)
+  const MT* Yn;          // forward Y^n (tiled; Z^n in the shifted form)
   const MT* Ym;          // forward Y^{n-1}
-  double* Xb_new;        // adjoint slot (n+1)%2: in Xbar^{n+1}, out partial Xbar^{n-1}
-  double* Xb_cur;        // adjoint slot n%2: in partial Xbar^n, out complete Xbar^n
+  double* Xb_new;        // adjoint slot (n+1)%L: in Xbar^{n+1}; out partial Xbar^{n-1} (L = 2) or
+                         // the part of Xbar^{n-2} from this step (L = 3; at n = 1 the part of the
+                         // zero level X^{-1}, which nothing reads)
+  double* Xb_cur;        // adjoint slot n%L: in partial Xbar^n, out complete Xbar^n
+  double* Xb_old;        // L = 3: slot (n-1)%3, in and out partial Xbar^{n-1}
   const MT* H1;          // H^(n+1) slot (n+1)%2
   MT* H2;                // H^(n+2) in, H^(n) out: slot n%2
   const double* taubar;  // [c][stride] or null
@@ -242,6 +246,12 @@ struct AdjArgs {
   AdjSpatial sp;
 };
 
+// Modes of the BDF2 adjoint's four streams loaded ahead of the one being updated (0 or 1).
+#ifndef TFS_ADJ_AHEAD
+#define TFS_ADJ_AHEAD 1
+#endif
+constexpr int kAdjAhead = TFS_ADJ_AHEAD;
+
 // Per-lane values kept in LDS across the mode stream (they are needed again after it):
 // Rbar (c values) and the kappa~ adjoint of the local part (d*d values), per point.
 template <int D>
@@ -249,10 +259,17 @@ struct AdjSlots {
   static constexpr int N = Sym<D>::C + D * D;
 };
 
-template <int D, typename MT, int V, bool FULL, bool SP>
-__device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& w, int nv, double* smode,
+// ZF: the shifted mode form (Z_k^j = Y_k^j - beta_k X^{j-1}).  Its history reads back as
+// h^_k = 2 Z_k^n - Z_k^{n-1}/2 + beta_k B, B = 2 X^{n-1} - X^{n-2}/2, and its new level is
+// Z_k^{n+1} = d_k h^_k + d_k c_k P - beta_k X^n; so with H_k = dL/dh^_k (the same recurrence),
+// Bbar = sum_k beta_k H_k reaches X^{n-1} (x 2) and X^{n-2} (x -1/2), and X^n gets
+// -sum_k beta_k Zbar_k^{n+1}.  beta_k is a change of representation, not a coefficient of
+// the scheme: it has no gradient.
+template <int D, typename MT, typename KT, int V, bool FULL, bool SP, bool ZF = false>
+__device__ __forceinline__ void adj_group(const AdjArgs<MT, KT>& a, const WaveAddr& w, int nv, double* smode,
                                           double* slot, double (&sc)[kNumAdjScalars]) {
   constexpr int C = Sym<D>::C;
+  constexpr int CZ = ZF ? C : 1;
   constexpr int NS = AdjSlots<D>::N;
   const int64_t st = a.stride;
   const int m = a.m;
@@ -264,18 +281,19 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
   double Gb[C][V], Pb[C][V];
   {
     double kt[D * D][V], Xp[C][V], Xbn[C][V], tb[C][V];
+    const uint32_t kx = field_off<KT>(w.ox);
 #pragma unroll
     for (int t = 0; t < D * D; ++t) {
-      double x[V];
-      load_v<FULL, double, V>(at(a.ka + t * st + w.pw, w.ox), nv, x);
+      KT x[V];
+      load_v<FULL, KT, V>(at(a.ka + t * st + w.pw, kx), nv, x);
       if (a.kb) {
-        double y[V];
-        load_v<FULL, double, V>(at(a.kb + t * st + w.pw, w.ox), nv, y);
+        KT y[V];
+        load_v<FULL, KT, V>(at(a.kb + t * st + w.pw, kx), nv, y);
 #pragma unroll
-        for (int v = 0; v < V; ++v) kt[t][v] = 2.0 * x[v] - y[v];
+        for (int v = 0; v < V; ++v) kt[t][v] = 2.0 * (double)x[v] - (double)y[v];
       } else {
 #pragma unroll
-        for (int v = 0; v < V; ++v) kt[t][v] = x[v];
+        for (int v = 0; v < V; ++v) kt[t][v] = (double)x[v];
       }
     }
 #pragma unroll
@@ -345,7 +363,7 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
     }
   }
 
-  double P[C][V];
+  double P[C][V], B[CZ][V];
 #pragma unroll
   for (int s = 0; s < C; ++s) {
     double xn[V], xm[V];
@@ -353,6 +371,17 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
     load_v<FULL, double, V>(at(a.Xm + s * st + w.pw, w.ox), nv, xm);
 #pragma unroll
     for (int v = 0; v < V; ++v) P[s][v] = 2.0 * xn[v] - 0.5 * xm[v];
+    if constexpr (ZF) {
+      double xmm[V];
+      if (a.Xmm) {
+        load_v<FULL, double, V>(at(a.Xmm + s * st + w.pw, w.ox), nv, xmm);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) xmm[v] = 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) B[s][v] = 2.0 * xm[v] - 0.5 * xmm[v];
+    }
   }
   {
     double g = 0.0;
@@ -369,29 +398,50 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
   MT* h2p = a.H2 + w.tw;
   const MT* ynp = a.Yn + w.tw;
   const MT* ymp = a.Ym + w.tw;
-  double Gh[C][V];
+  double Gh[C][V], Bb[CZ][V], Zx[CZ][V];   // Bbar and -sum_k beta_k Zbar_k^{n+1} (shifted form)
 #pragma unroll
   for (int s = 0; s < C; ++s)
 #pragma unroll
-    for (int v = 0; v < V; ++v) Gh[s][v] = 0.0;
-  for (int k = 0; k < m; ++k) {
-    const double dk = load_uniform(a.coef + kRowD * m + k);
-    const double ek = load_uniform(a.coef + kRowDC * m + k);
-    const double hk = load_uniform(a.coef + kRowEta * m + k);
-    MT c1[C][V], c2[C][V], cn[C][V], cm[C][V];
+    for (int v = 0; v < V; ++v) {
+      Gh[s][v] = 0.0;
+      if constexpr (ZF) {
+        Bb[s][v] = 0.0;
+        Zx[s][v] = 0.0;
+      }
+    }
+  // the four streams of mode k + 1 are loaded before mode k's arithmetic, reductions and
+  // store, so a wave keeps its next loads in flight while it works (H^(n+2) of mode k + 1 is
+  // read before H^(n) of mode k is written into the same slot: different addresses)
+  MT c1[C][V], c2[C][V], cn[C][V], cm[C][V];
+  auto load_mode = [&](int k, MT (&x1)[C][V], MT (&x2)[C][V], MT (&xn)[C][V], MT (&xm)[C][V]) {
     const int64_t o = (int64_t)k * C * T;
     const uint32_t om = opaque(w.om);
     const MT* b1 = opaque_ptr(h1p + o);
-    MT* b2 = opaque_ptr(h2p + o);
+    const MT* b2 = opaque_ptr(h2p + o);
     const MT* bn = opaque_ptr(ynp + o);
     const MT* bm = opaque_ptr(ymp + o);
 #pragma unroll
     for (int s = 0; s < C; ++s) {
-      load_v<FULL, MT, V, true>(at(b1 + s * T, om), nv, c1[s]);
-      load_v<FULL, MT, V, true>(at(b2 + s * T, om), nv, c2[s]);
-      load_v<FULL, MT, V, true>(at(bn + s * T, om), nv, cn[s]);
-      load_v<FULL, MT, V, true>(at(bm + s * T, om), nv, cm[s]);
+      load_v<FULL, MT, V, true>(at(b1 + s * T, om), nv, x1[s]);
+      load_v<FULL, MT, V, true>(at(b2 + s * T, om), nv, x2[s]);
+      load_v<FULL, MT, V, true>(at(bn + s * T, om), nv, xn[s]);
+      load_v<FULL, MT, V, true>(at(bm + s * T, om), nv, xm[s]);
     }
+  };
+  if constexpr (kAdjAhead) load_mode(0, c1, c2, cn, cm);
+  for (int k = 0; k < m; ++k) {
+    const double dk = load_uniform(a.coef + kRowD * m + k);
+    const double ek = load_uniform(a.coef + kRowDC * m + k);
+    const double hk = load_uniform(a.coef + kRowEta * m + k);
+    const double bk = ZF ? load_uniform(a.coef + kRowBeta * m + k) : 0.0;
+    MT n1[C][V], n2[C][V], nn[C][V], nm[C][V];
+    if constexpr (kAdjAhead) {
+      if (k + 1 < m) load_mode(k + 1, n1, n2, nn, nm);
+    } else {
+      load_mode(k, c1, c2, cn, cm);
+    }
+    const uint32_t om = opaque(w.om);
+    MT* b2 = opaque_ptr(h2p + (int64_t)k * C * T);
     double ad = 0.0, ae = 0.0, ah = 0.0;
 #pragma unroll
     for (int s = 0; s < C; ++s) {
@@ -399,9 +449,15 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const double yb = 2.0 * (double)c1[s][v] - 0.5 * (double)c2[s][v];
-        const double hh = 2.0 * (double)cn[s][v] - 0.5 * (double)cm[s][v];
+        double hh = 2.0 * (double)cn[s][v] - 0.5 * (double)cm[s][v];
+        if constexpr (ZF) hh += bk * B[s][v];
         Gh[s][v] += hk * hh;
-        hv[v] = (MT)(dk * yb + hk * Gb[s][v]);
+        const double hn = dk * yb + hk * Gb[s][v];
+        hv[v] = (MT)hn;
+        if constexpr (ZF) {
+          Bb[s][v] += bk * hn;
+          Zx[s][v] -= bk * yb;
+        }
         Pb[s][v] += ek * yb;
         ad += yb * hh;
         ae += yb * P[s][v];
@@ -416,6 +472,17 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
       smode[wave * 3 * m + k] += ad;
       smode[wave * 3 * m + m + k] += ae;
       smode[wave * 3 * m + 2 * m + k] += ah;
+    }
+    if (kAdjAhead && k + 1 < m) {
+#pragma unroll
+      for (int s = 0; s < C; ++s)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          c1[s][v] = n1[s][v];
+          c2[s][v] = n2[s][v];
+          cn[s][v] = nn[s][v];
+          cm[s][v] = nm[s][v];
+        }
     }
   }
 
@@ -456,13 +523,27 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
   for (int s = 0; s < C; ++s) {
     double xc[V], xw[V];
     load_v<FULL, double, V>(at(a.Xb_cur + s * st + w.pw, w.ox), nv, xc);
+    if constexpr (ZF) {
+      // three slots: Xbar^n complete, Xbar^{n-1} accumulated, Xbar^{n-2} started
+      double xo[V];
+      load_v<FULL, double, V>(at(a.Xb_old + s * st + w.pw, w.ox), nv, xo);
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      xc[v] += 2.0 * Pb[s][v];                      // P = 2 X^n - X^{n-1}/2
-      xw[v] = -0.5 * Pb[s][v];
+      for (int v = 0; v < V; ++v) {
+        xc[v] += 2.0 * Pb[s][v] + Zx[s][v];         // P = 2 X^n - X^{n-1}/2; Z^{n+1} = ... - beta X^n
+        xo[v] += -0.5 * Pb[s][v] + 2.0 * Bb[s][v];  // B = 2 X^{n-1} - X^{n-2}/2
+        xw[v] = -0.5 * Bb[s][v];
+      }
+      store_v<FULL, double, V>(at(a.Xb_old + s * st + w.pw, w.ox), nv, xo);
+      store_v<FULL, double, V>(at(a.Xb_new + s * st + w.pw, w.ox), nv, xw);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        xc[v] += 2.0 * Pb[s][v];                      // P = 2 X^n - X^{n-1}/2
+        xw[v] = -0.5 * Pb[s][v];
+      }
+      store_v<FULL, double, V>(at(a.Xb_new + s * st + w.pw, w.ox), nv, xw);
     }
     store_v<FULL, double, V>(at(a.Xb_cur + s * st + w.pw, w.ox), nv, xc);
-    store_v<FULL, double, V>(at(a.Xb_new + s * st + w.pw, w.ox), nv, xw);
   }
   // kappa adjoints: kappa~ = 2 kappa_a - kappa_b, or kappa_a
   double fa = 1.0, fb = 0.0;
@@ -474,8 +555,19 @@ __device__ __forceinline__ void adj_group(const AdjArgs<MT>& a, const WaveAddr& 
 // FULL: whole waves of V-point groups (ngroups a multiple of 64).  !FULL (V = 1): the
 // points after the last whole wave; lanes past the end run an empty group, since the wave
 // reductions need all 64 lanes.
-template <int D, typename MT, int V, bool FULL, bool SP>
-__global__ __launch_bounds__(kBlock) void adj_kernel(const AdjArgs<MT> a) {
+// Optional lower bound on the waves per SIMD the BDF2 adjoint is compiled for (0: the
+// compiler's choice); it caps the registers a lane may hold.
+#ifndef TFS_ADJ_WAVES
+#define TFS_ADJ_WAVES 0
+#endif
+#if TFS_ADJ_WAVES > 0
+#define TFS_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(TFS_ADJ_WAVES)))
+#else
+#define TFS_ADJ_ATTR
+#endif
+
+template <int D, typename MT, typename KT, int V, bool FULL, bool SP, bool ZF>
+__global__ __launch_bounds__(kBlock) TFS_ADJ_ATTR void adj_kernel(const AdjArgs<MT, KT> a) {
   constexpr int C = Sym<D>::C;
   extern __shared__ double smem[];    // [kBlock/64][3][m] mode sums, then the lane slots
   double* smode = smem;
@@ -492,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void adj_kernel(const AdjArgs<MT> a) {
        wv += wstride) {
     const WaveAddr w = wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m);
     const int nv = (FULL || wv * 64 + lane < a.ngroups) ? V : 0;
-    adj_group<D, MT, V, FULL, SP>(a, w, nv, smode, slot, sc);
+    adj_group<D, MT, KT, V, FULL, SP, ZF>(a, w, nv, smode, slot, sc);
   }
   __syncthreads();
   write_block_partial(a.part + (size_t)a.part0 * (3 * a.m + kNumAdjScalars), a.m, smode, sc);
@@ -506,10 +598,10 @@ __global__ __launch_bounds__(kBlock) void adj_kernel(const AdjArgs<MT> a) {
 //   Yhat_k = Ybar_k^{n+1} + l_k Gbar,   Ybar_k^n = e_k Yhat_k + om_k Hbar   (one level, in place)
 //   Xbar^n = Rbar + s_h Hbar + sum_k f_k Yhat_k   (at n = 0 also - sum_k q_k Ybar_k^0)
 // and per mode dL/dw_k, dL/dlambda_k through e_k, f_k, om_k, l_k (and q_k at n = 0).
-template <typename MT>
+template <typename MT, typename KT>
 struct ExpAdjArgs {
-  const double* ka;
-  const double* kb;      // null: kappa~ = kappa_a
+  const KT* ka;          // the plan's kappa precision
+  const KT* kb;          // null: kappa~ = kappa_a
   const double* Xn;      // forward X^n
   const double* Xp;      // forward X^{n+1}
   const MT* Yn;          // forward Y^n (one level, tiled); not read at n = 0
@@ -541,8 +633,8 @@ constexpr int kExpAdjAhead = TFS_EXP_ADJ_AHEAD;
 // SP: the spatial form (1/De + rate per point, a + q rate on the diagonal, the mass-mode
 // source at the source point only); sc[7] collects sum rate dL/da (a part of dL/dq) and sc[8]
 // sum rate dL/drate.
-template <int D, typename MT, int V, bool FULL, bool TAU, bool SP>
-__device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const WaveAddr& w, int nv, double* smode,
+template <int D, typename MT, typename KT, int V, bool FULL, bool TAU, bool SP>
+__device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT, KT>& a, const WaveAddr& w, int nv, double* smode,
                                               double* slot, double (&sc)[kNumAdjScalars]) {
   constexpr int C = Sym<D>::C;
   const int64_t st = a.stride;
@@ -565,17 +657,17 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
     double k[D * D], xp[C], rb[C], tv[C], S[C];
 #pragma unroll
     for (int t = 0; t < D * D; ++t) {
-      double x[1];
-      load_v<FULL, double, 1>(at(a.ka + t * st + w.pw, ox), nv1, x);
-      k[t] = x[0];
+      KT x[1];
+      load_v<FULL, KT, 1>(at(a.ka + t * st + w.pw, field_off<KT>(ox)), nv1, x);
+      k[t] = (double)x[0];
     }
     if (a.kb) {
       double kb[D * D];
 #pragma unroll
       for (int t = 0; t < D * D; ++t) {
-        double x[1];
-        load_v<FULL, double, 1>(at(a.kb + t * st + w.pw, ox), nv1, x);
-        kb[t] = x[0];
+        KT x[1];
+        load_v<FULL, KT, 1>(at(a.kb + t * st + w.pw, field_off<KT>(ox)), nv1, x);
+        kb[t] = (double)x[0];
       }
 #pragma unroll
       for (int t = 0; t < D * D; ++t) k[t] = a.s.fa * k[t] + a.s.fb * kb[t];
@@ -780,8 +872,8 @@ __device__ __forceinline__ void exp_adj_group(const ExpAdjArgs<MT>& a, const Wav
   if (a.kbb && fb != 0.0) add_kbar<D, V, FULL>(a.kbb, fb, st, w, nv, kbar);
 }
 
-template <int D, typename MT, int V, bool FULL, bool TAU, bool SP>
-__global__ __launch_bounds__(kBlock) void exp_adj_kernel(const ExpAdjArgs<MT> a) {
+template <int D, typename MT, typename KT, int V, bool FULL, bool TAU, bool SP>
+__global__ __launch_bounds__(kBlock) void exp_adj_kernel(const ExpAdjArgs<MT, KT> a) {
   constexpr int C = Sym<D>::C;
   extern __shared__ double smem[];    // [kBlock/64][3][m] mode sums, then Rbar per lane
   double* smode = smem;
@@ -798,16 +890,16 @@ __global__ __launch_bounds__(kBlock) void exp_adj_kernel(const ExpAdjArgs<MT> a)
        wv += wstride) {
     const WaveAddr w = wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m);
     const int nv = (FULL || wv * 64 + lane < a.ngroups) ? V : 0;
-    exp_adj_group<D, MT, V, FULL, TAU, SP>(a, w, nv, smode, slot, sc);
+    exp_adj_group<D, MT, KT, V, FULL, TAU, SP>(a, w, nv, smode, slot, sc);
   }
   __syncthreads();
   write_block_partial(a.part + (size_t)a.part0 * (3 * a.m + kNumAdjScalars), a.m, smode, sc);
 }
 
 // ------------------------------------------------------------------ start-up adjoint
-template <typename MT>
+template <typename MT, typename KT>
 struct StartAdjArgs {
-  const double* ka;
+  const KT* ka;          // the plan's kappa precision
   const double* X0;      // forward X^0
   double* Xb0;           // adjoint slot 0: in partial Xbar^0, out complete Xbar^0
   const double* Xb1;     // adjoint slot 1: Xbar^1 from later steps
@@ -819,12 +911,13 @@ struct StartAdjArgs {
   double* part;
   int64_t npts, stride, tile;
   int m;
+  int zform;             // shifted mode form: Z^1 = Y^1 - beta_k X^0
   StartScalars s;
   AdjSpatial sp;
 };
 
-template <int D, typename MT, int V, bool FULL, bool SP>
-__device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64_t p0, int nv, double* smode,
+template <int D, typename MT, typename KT, int V, bool FULL, bool SP>
+__device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT, KT>& a, int64_t p0, int nv, double* smode,
                                                 double (&sc)[kNumAdjScalars]) {
   constexpr int C = Sym<D>::C;
   const int64_t st = a.stride;
@@ -834,7 +927,12 @@ __device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64
 #pragma unroll
   for (int s = 0; s < C; ++s) load_v<FULL, double, V>(a.X0 + s * st + p0, nv, X0[s]);
 #pragma unroll
-  for (int q = 0; q < D * D; ++q) load_v<FULL, double, V>(a.ka + q * st + p0, nv, kt[q]);
+  for (int q = 0; q < D * D; ++q) {
+    KT x[V];
+    load_v<FULL, KT, V>(a.ka + q * st + p0, nv, x);
+#pragma unroll
+    for (int v = 0; v < V; ++v) kt[q][v] = (double)x[v];
+  }
   // spatial form: 1/De + rate per point and the source weight of the mass-mode terms
   double rate[V], srcw[V];
   if constexpr (SP) adj_spatial<FULL, V>(a.sp, a.sp.rate + p0, p0, nv, rate, srcw);
@@ -879,6 +977,7 @@ __device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64
     const double ck = load_uniform(a.coef + kRowC * m + k);
     const double uk = load_uniform(a.coef + kRowU * m + k);
     const double vk = load_uniform(a.coef + kRowV * m + k);
+    const double bk = a.zform ? load_uniform(a.coef + kRowBeta * m + k) : 0.0;
     double ac = 0.0, au = 0.0, av = 0.0;
 #pragma unroll
     for (int s = 0; s < C; ++s) {
@@ -889,7 +988,7 @@ __device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64
       for (int v = 0; v < V; ++v) {
         const double y0 = -0.5 * (double)h1[v];
         const double y1 = 2.0 * (double)h1[v] - 0.5 * (double)h2[v];
-        X0b[s][v] += -ck * y0;
+        X0b[s][v] += -ck * y0 - bk * y1;
         X1b[s][v] += uk * y1;
         X2b[s][v] += vk * y1;
         ac += -y0 * X0[s][v];
@@ -1018,8 +1117,8 @@ __device__ __forceinline__ void start_adj_group(const StartAdjArgs<MT>& a, int64
   }
 }
 
-template <int D, typename MT, int V, bool SP>
-__global__ __launch_bounds__(kBlock) void start_adj_kernel(const StartAdjArgs<MT> a) {
+template <int D, typename MT, typename KT, int V, bool SP>
+__global__ __launch_bounds__(kBlock) void start_adj_kernel(const StartAdjArgs<MT, KT> a) {
   extern __shared__ double smode[];
   for (int j = threadIdx.x; j < (kBlock / 64) * 3 * a.m; j += kBlock) smode[j] = 0.0;
   __syncthreads();
@@ -1033,8 +1132,8 @@ __global__ __launch_bounds__(kBlock) void start_adj_kernel(const StartAdjArgs<MT
     const int64_t p0 = mine * V;
     int nv = (int)((a.npts - p0) < V ? (a.npts - p0) : V);
     if (mine >= ngroups) nv = 0;
-    if (nv == V) start_adj_group<D, MT, V, true, SP>(a, p0, nv, smode, sc);
-    else start_adj_group<D, MT, V, false, SP>(a, nv > 0 ? p0 : 0, nv, smode, sc);
+    if (nv == V) start_adj_group<D, MT, KT, V, true, SP>(a, p0, nv, smode, sc);
+    else start_adj_group<D, MT, KT, V, false, SP>(a, nv > 0 ? p0 : 0, nv, smode, sc);
   }
   __syncthreads();
   write_block_partial(a.part, a.m, smode, sc);
@@ -1076,8 +1175,8 @@ size_t adj_shared_bytes(const tfs_plan_s* p, int V) {
 
 // Whole waves of V-point groups with the V-wide kernel, the remaining points (fewer than
 // 64 V) with the masked V = 1 kernel; one finisher folds the block partials of both.
-template <int D, typename MT, int V, bool SP>
-hipError_t adj_go_(const tfs_plan_s* p, AdjArgs<MT> a, int64_t zeta_dest, double* pbar) {
+template <int D, typename MT, typename KT, int V, bool SP, bool ZF>
+hipError_t adj_go_(const tfs_plan_s* p, AdjArgs<MT, KT> a, int64_t zeta_dest, double* pbar) {
   const int64_t nwaves = p->npoints / (64 * V);
   const int64_t p_tail = nwaves * 64 * V, rest = p->npoints - p_tail;
   int nb = 0, nt = 0;
@@ -1088,18 +1187,18 @@ hipError_t adj_go_(const tfs_plan_s* p, AdjArgs<MT> a, int64_t zeta_dest, double
     nb = grid_adj(p, a.ngroups);
     const size_t shm = adj_shared_bytes(p, V);
     if (shm > 65536) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&adj_kernel<D, MT, V, true, SP>),
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&adj_kernel<D, MT, KT, V, true, SP, ZF>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((adj_kernel<D, MT, V, true, SP>), dim3(nb), dim3(kBlock), shm, p->stream, a);
+    hipLaunchKernelGGL((adj_kernel<D, MT, KT, V, true, SP, ZF>), dim3(nb), dim3(kBlock), shm, p->stream, a);
   }
   if (rest > 0) {
     a.p_begin = p_tail;
     a.ngroups = rest;
     a.part0 = nb;
     nt = grid_adj(p, rest);
-    hipLaunchKernelGGL((adj_kernel<D, MT, 1, false, SP>), dim3(nt), dim3(kBlock), adj_shared_bytes(p, 1),
+    hipLaunchKernelGGL((adj_kernel<D, MT, KT, 1, false, SP, ZF>), dim3(nt), dim3(kBlock), adj_shared_bytes(p, 1),
                        p->stream, a);
   }
   const int np = 3 * p->m + kNumAdjScalars;
@@ -1108,21 +1207,34 @@ hipError_t adj_go_(const tfs_plan_s* p, AdjArgs<MT> a, int64_t zeta_dest, double
   return hipGetLastError();
 }
 
-template <int D, typename MT, int V>
-hipError_t adj_go(const tfs_plan_s* p, const AdjArgs<MT>& a, int64_t zeta_dest, double* pbar) {
-  if (a.sp.rate || a.sp.src >= 0) return adj_go_<D, MT, V, true>(p, a, zeta_dest, pbar);
-  return adj_go_<D, MT, V, false>(p, a, zeta_dest, pbar);
+// The spatial form reads FP64 velocity gradients only (an FP32-kappa plan refuses it).
+template <int D, typename MT, typename KT, int V, bool ZF>
+hipError_t adj_go_z(const tfs_plan_s* p, const AdjArgs<MT, KT>& a, int64_t zeta_dest, double* pbar) {
+  if constexpr (sizeof(KT) == 8) {
+    if (a.sp.rate || a.sp.src >= 0) return adj_go_<D, MT, KT, V, true, ZF>(p, a, zeta_dest, pbar);
+  }
+  return adj_go_<D, MT, KT, V, false, ZF>(p, a, zeta_dest, pbar);
 }
 
-template <int D, typename MT, int V>
-hipError_t start_adj_go(const tfs_plan_s* p, const StartAdjArgs<MT>& a, double* pbar) {
+template <int D, typename MT, typename KT, int V>
+hipError_t adj_go(const tfs_plan_s* p, const AdjArgs<MT, KT>& a, int64_t zeta_dest, double* pbar) {
+  return p->zform ? adj_go_z<D, MT, KT, V, true>(p, a, zeta_dest, pbar)
+                  : adj_go_z<D, MT, KT, V, false>(p, a, zeta_dest, pbar);
+}
+
+template <int D, typename MT, typename KT, int V>
+hipError_t start_adj_go(const tfs_plan_s* p, const StartAdjArgs<MT, KT>& a, double* pbar) {
   const int64_t ngroups = (a.npts + V - 1) / V;
   const int grid = grid_adj(p, ngroups);
   const size_t shm = sizeof(double) * (kBlock / 64) * 3 * p->m;
-  if (a.sp.rate || a.sp.src >= 0)
-    hipLaunchKernelGGL((start_adj_kernel<D, MT, V, true>), dim3(grid), dim3(kBlock), shm, p->stream, a);
-  else
-    hipLaunchKernelGGL((start_adj_kernel<D, MT, V, false>), dim3(grid), dim3(kBlock), shm, p->stream, a);
+  bool sp = false;
+  if constexpr (sizeof(KT) == 8) sp = a.sp.rate || a.sp.src >= 0;
+  if (sp) {
+    if constexpr (sizeof(KT) == 8)
+      hipLaunchKernelGGL((start_adj_kernel<D, MT, KT, V, true>), dim3(grid), dim3(kBlock), shm, p->stream, a);
+  } else {
+    hipLaunchKernelGGL((start_adj_kernel<D, MT, KT, V, false>), dim3(grid), dim3(kBlock), shm, p->stream, a);
+  }
   const int np = 3 * p->m + kNumAdjScalars;
   hipLaunchKernelGGL(adj_finish_kernel, dim3(np), dim3(kBlock), 0, p->stream, a.part, grid, np,
                      p->d_dest_start, (int64_t)-1, pbar);
@@ -1133,14 +1245,14 @@ bool al(const void* ptr, size_t b) { return ptr == nullptr || ((uintptr_t)ptr % 
 
 // Points per lane of the BDF2 adjoint: the "adj_vec" tuning (0 = default 1), if every field
 // is aligned for it and its LDS slots fit in 64 KB per block.
-template <typename MT>
+template <typename MT, typename KT>
 int adj_vec(const tfs_plan_s* p, const AdjLevels& L) {
   const int want = p->adj_vec_override ? p->adj_vec_override : (sizeof(MT) == 4 ? 2 : 1);
   const int V = want == 2 ? 2 : 1;
   if (V == 1) return 1;
   if (p->stride % V || p->tile % V || adj_shared_bytes(p, V) > (size_t)p->lds_max) return 1;
-  const size_t bm = (size_t)V * sizeof(MT), bd = (size_t)V * 8;
-  if (al(L.ka, bd) && al(L.kb, bd) && al(L.Xn, bd) && al(L.Xm, bd) && al(L.Xp, bd) && al(L.Xbar, bd) &&
+  const size_t bm = (size_t)V * sizeof(MT), bd = (size_t)V * 8, bk = (size_t)V * sizeof(KT);
+  if (al(L.ka, bk) && al(L.kb, bk) && al(L.Xn, bd) && al(L.Xm, bd) && al(L.Xmm, bd) && al(L.Xp, bd) && al(L.Xbar, bd) &&
       al(L.taubar, bd) && al(L.kba, bd) && al(L.kbb, bd) && al(L.Yn, bm) && al(L.Ym, bm) && al(L.Hbar, bm))
     return V;
   return 1;
@@ -1150,8 +1262,8 @@ size_t exp_adj_shared_bytes(const tfs_plan_s* p, int V) {
   return sizeof(double) * ((size_t)(kBlock / 64) * 3 * p->m + (size_t)p->c * V * kBlock);
 }
 
-template <int D, typename MT, int V, bool TAU, bool SP>
-hipError_t exp_adj_go_(const tfs_plan_s* p, ExpAdjArgs<MT> a, int64_t zeta_dest, double* pbar) {
+template <int D, typename MT, typename KT, int V, bool TAU, bool SP>
+hipError_t exp_adj_go_(const tfs_plan_s* p, ExpAdjArgs<MT, KT> a, int64_t zeta_dest, double* pbar) {
   const int64_t nwaves = p->npoints / (64 * V);
   const int64_t p_tail = nwaves * 64 * V, rest = p->npoints - p_tail;
   int nb = 0, nt = 0;
@@ -1162,18 +1274,18 @@ hipError_t exp_adj_go_(const tfs_plan_s* p, ExpAdjArgs<MT> a, int64_t zeta_dest,
     nb = grid_adj(p, a.ngroups);
     const size_t shm = exp_adj_shared_bytes(p, V);
     if (shm > 65536) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&exp_adj_kernel<D, MT, V, true, TAU, SP>),
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&exp_adj_kernel<D, MT, KT, V, true, TAU, SP>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((exp_adj_kernel<D, MT, V, true, TAU, SP>), dim3(nb), dim3(kBlock), shm, p->stream, a);
+    hipLaunchKernelGGL((exp_adj_kernel<D, MT, KT, V, true, TAU, SP>), dim3(nb), dim3(kBlock), shm, p->stream, a);
   }
   if (rest > 0) {
     a.p_begin = p_tail;
     a.ngroups = rest;
     a.part0 = nb;
     nt = grid_adj(p, rest);
-    hipLaunchKernelGGL((exp_adj_kernel<D, MT, 1, false, TAU, SP>), dim3(nt), dim3(kBlock), exp_adj_shared_bytes(p, 1),
+    hipLaunchKernelGGL((exp_adj_kernel<D, MT, KT, 1, false, TAU, SP>), dim3(nt), dim3(kBlock), exp_adj_shared_bytes(p, 1),
                        p->stream, a);
   }
   const int np = 3 * p->m + kNumAdjScalars;
@@ -1182,23 +1294,25 @@ hipError_t exp_adj_go_(const tfs_plan_s* p, ExpAdjArgs<MT> a, int64_t zeta_dest,
   return hipGetLastError();
 }
 
-template <int D, typename MT, int V>
-hipError_t exp_adj_go(const tfs_plan_s* p, const ExpAdjArgs<MT>& a, int64_t zeta_dest, double* pbar) {
-  if (a.sp.rate || a.sp.src >= 0)
-    return a.taubar ? exp_adj_go_<D, MT, V, true, true>(p, a, zeta_dest, pbar)
-                    : exp_adj_go_<D, MT, V, false, true>(p, a, zeta_dest, pbar);
-  return a.taubar ? exp_adj_go_<D, MT, V, true, false>(p, a, zeta_dest, pbar)
-                  : exp_adj_go_<D, MT, V, false, false>(p, a, zeta_dest, pbar);
+template <int D, typename MT, typename KT, int V>
+hipError_t exp_adj_go(const tfs_plan_s* p, const ExpAdjArgs<MT, KT>& a, int64_t zeta_dest, double* pbar) {
+  if constexpr (sizeof(KT) == 8) {
+    if (a.sp.rate || a.sp.src >= 0)
+      return a.taubar ? exp_adj_go_<D, MT, KT, V, true, true>(p, a, zeta_dest, pbar)
+                      : exp_adj_go_<D, MT, KT, V, false, true>(p, a, zeta_dest, pbar);
+  }
+  return a.taubar ? exp_adj_go_<D, MT, KT, V, true, false>(p, a, zeta_dest, pbar)
+                  : exp_adj_go_<D, MT, KT, V, false, false>(p, a, zeta_dest, pbar);
 }
 
-template <int D, typename MT>
+template <int D, typename MT, typename KT>
 hipError_t exp_adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, double* pbar) {
   const int64_t st = p->stride;
   const int64_t xs = (int64_t)Sym<D>::C * st;
   const int sn = (int)(n % 2), sp = 1 - sn;
-  ExpAdjArgs<MT> a;
-  a.ka = L.ka;
-  a.kb = n >= 1 ? L.kb : nullptr;
+  ExpAdjArgs<MT, KT> a;
+  a.ka = static_cast<const KT*>(L.ka);
+  a.kb = n >= 1 ? static_cast<const KT*>(L.kb) : nullptr;
   a.Xn = L.Xn;
   a.Xp = L.Xp;
   a.Yn = static_cast<const MT*>(L.Yn);
@@ -1231,14 +1345,14 @@ hipError_t exp_adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, 
   // one point per lane unless tuned: measured faster than two for this kernel
   const int want = p->adj_vec_override ? p->adj_vec_override : 1;
   bool two = want == 2 && p->stride % 2 == 0 && p->tile % 2 == 0 && exp_adj_shared_bytes(p, 2) <= (size_t)p->lds_max;
-  const size_t bm = 2 * sizeof(MT), bd = 16;
-  two = two && al(L.ka, bd) && al(L.kb, bd) && al(L.Xn, bd) && al(L.Xp, bd) && al(L.Xbar, bd) &&
+  const size_t bm = 2 * sizeof(MT), bd = 16, bk = 2 * sizeof(KT);
+  two = two && al(L.ka, bk) && al(L.kb, bk) && al(L.Xn, bd) && al(L.Xp, bd) && al(L.Xbar, bd) &&
         al(L.taubar, bd) && al(L.kba, bd) && al(L.kbb, bd) && al(L.Yn, bm) && al(L.Hbar, bm);
-  if (two) return exp_adj_go<D, MT, 2>(p, a, zd, pbar);
-  return exp_adj_go<D, MT, 1>(p, a, zd, pbar);
+  if (two) return exp_adj_go<D, MT, KT, 2>(p, a, zd, pbar);
+  return exp_adj_go<D, MT, KT, 1>(p, a, zd, pbar);
 }
 
-template <int D, typename MT>
+template <int D, typename MT, typename KT>
 hipError_t adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, double* pbar) {
   const int64_t st = p->stride;
   const int64_t ys = (int64_t)p->m * Sym<D>::C * st;
@@ -1246,8 +1360,8 @@ hipError_t adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, doub
   const int sn = (int)(n % 2), sp = 1 - sn;
   MT* Hb = static_cast<MT*>(L.Hbar);
   if (n == 0) {
-    StartAdjArgs<MT> a;
-    a.ka = L.ka;
+    StartAdjArgs<MT, KT> a;
+    a.ka = static_cast<const KT*>(L.ka);
     a.X0 = L.Xn;
     a.Xb0 = L.Xbar;
     a.Xb1 = L.Xbar + xs;
@@ -1261,6 +1375,7 @@ hipError_t adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, doub
     a.stride = st;
     a.tile = p->tile;
     a.m = p->m;
+    a.zform = p->zform ? 1 : 0;
     a.s.hgt = p->hg * p->theta;
     a.s.inv_De = 1.0 / p->De;
     a.s.src1 = p->hg * p->theta;
@@ -1271,18 +1386,26 @@ hipError_t adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, doub
     a.s.hr = p->hr;
     a.sp.rate = p->sp_rate;
     a.sp.src = p->sp_source;
-    return start_adj_go<D, MT, 1>(p, a, pbar);
+    return start_adj_go<D, MT, KT, 1>(p, a, pbar);
   }
-  AdjArgs<MT> a;
-  a.ka = L.ka;
-  a.kb = L.kb;
+  AdjArgs<MT, KT> a;
+  a.ka = static_cast<const KT*>(L.ka);
+  a.kb = static_cast<const KT*>(L.kb);
   a.Xn = L.Xn;
   a.Xm = L.Xm;
+  a.Xmm = p->zform ? L.Xmm : nullptr;
   a.Xp = L.Xp;
   a.Yn = static_cast<const MT*>(L.Yn);
   a.Ym = static_cast<const MT*>(L.Ym);
-  a.Xb_new = L.Xbar + sp * xs;
-  a.Xb_cur = L.Xbar + sn * xs;
+  if (p->zform) {
+    a.Xb_new = L.Xbar + ((n + 1) % 3) * xs;
+    a.Xb_cur = L.Xbar + (n % 3) * xs;
+    a.Xb_old = L.Xbar + ((n - 1) % 3) * xs;
+  } else {
+    a.Xb_new = L.Xbar + sp * xs;
+    a.Xb_cur = L.Xbar + sn * xs;
+    a.Xb_old = nullptr;
+  }
   a.H1 = Hb + sp * ys;
   a.H2 = Hb + sn * ys;
   a.taubar = L.taubar;
@@ -1304,22 +1427,25 @@ hipError_t adj_dispatch(const tfs_plan_s* p, int64_t n, const AdjLevels& L, doub
   a.sp.src = p->sp_source;
   // the zeta gradient of this step goes to pbar[zeta offset + n + 1]
   const int64_t zd = (int64_t)kPbarScalars + 6 * p->m + n + 1;
-  if (adj_vec<MT>(p, L) == 2) return adj_go<D, MT, 2>(p, a, zd, pbar);
-  return adj_go<D, MT, 1>(p, a, zd, pbar);
+  if (adj_vec<MT, KT>(p, L) == 2) return adj_go<D, MT, KT, 2>(p, a, zd, pbar);
+  return adj_go<D, MT, KT, 1>(p, a, zd, pbar);
 }
 
 }  // namespace
 
+// The plan's (dim, mode precision, kappa precision) instance of a dispatcher; FP32 velocity
+// gradients exist only with FP32 modes.
+#define TFS_ADJ_DISPATCH(fn)                                                                        \
+  (p->precision == TFS_FP64                                                                         \
+       ? (p->d == 2 ? fn<2, double, double>(p, n, L, pbar) : fn<3, double, double>(p, n, L, pbar)) \
+       : p->kappa_f32                                                                               \
+             ? (p->d == 2 ? fn<2, float, float>(p, n, L, pbar) : fn<3, float, float>(p, n, L, pbar))  \
+             : (p->d == 2 ? fn<2, float, double>(p, n, L, pbar) : fn<3, float, double>(p, n, L, pbar)))
+
 hipError_t launch_adjoint(const tfs_plan_s* p, int64_t n, const AdjLevels& L, double* pbar) {
   if (p->npoints == 0) return hipSuccess;
-  if (p->scheme == TFS_SCHEME_EXP) {
-    if (p->precision == TFS_FP64)
-      return p->d == 2 ? exp_adj_dispatch<2, double>(p, n, L, pbar) : exp_adj_dispatch<3, double>(p, n, L, pbar);
-    return p->d == 2 ? exp_adj_dispatch<2, float>(p, n, L, pbar) : exp_adj_dispatch<3, float>(p, n, L, pbar);
-  }
-  if (p->precision == TFS_FP64)
-    return p->d == 2 ? adj_dispatch<2, double>(p, n, L, pbar) : adj_dispatch<3, double>(p, n, L, pbar);
-  return p->d == 2 ? adj_dispatch<2, float>(p, n, L, pbar) : adj_dispatch<3, float>(p, n, L, pbar);
+  if (p->scheme == TFS_SCHEME_EXP) return TFS_ADJ_DISPATCH(exp_adj_dispatch);
+  return TFS_ADJ_DISPATCH(adj_dispatch);
 }
 
 }  // namespace tfs

@@ -184,6 +184,13 @@ __device__ __forceinline__ T load_uniform(const T* p) {
   return *(const __attribute__((address_space(4))) T*)p;
 }
 
+// Byte offset in a plain field of element type T of the lane whose offset in an FP64 field
+// is ox (the velocity gradient may be stored in FP32).
+template <typename T>
+__device__ __forceinline__ uint32_t field_off(uint32_t ox) {
+  return sizeof(T) == 8 ? ox : ox / (uint32_t)(8 / sizeof(T));
+}
+
 // Tiled mode layout: [tile][m][c][T], point p at element (p / T) m c T + p % T of (0, 0).
 template <typename MT, int C, int V>
 __device__ __forceinline__ WaveAddr wave_addr(int64_t pw, int lane, int64_t T, int m) {

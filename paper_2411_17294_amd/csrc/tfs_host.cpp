@@ -278,6 +278,14 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   if (!D.w || !D.lambda) return fail(TFS_EINVAL, "null w or lambda");
   if (D.precision != TFS_FP64 && D.precision != TFS_FP32_MODES) return fail(TFS_EINVAL, "unknown precision");
   if (D.scheme != TFS_SCHEME_BDF2 && D.scheme != TFS_SCHEME_EXP) return fail(TFS_EINVAL, "unknown scheme");
+  if (D.kappa_precision != TFS_KAPPA_FP64 && D.kappa_precision != TFS_KAPPA_FP32)
+    return fail(TFS_EINVAL, "unknown kappa precision");
+  if (D.kappa_precision == TFS_KAPPA_FP32 && D.precision != TFS_FP32_MODES)
+    return fail(TFS_EINVAL, "FP32 velocity gradients need an FP32-mode plan");
+  if (D.mode_form != TFS_MODE_FORM_AUTO && D.mode_form != TFS_MODE_FORM_Y && D.mode_form != TFS_MODE_FORM_Z)
+    return fail(TFS_EINVAL, "unknown mode form");
+  if (D.mode_form == TFS_MODE_FORM_Z && D.scheme != TFS_SCHEME_BDF2)
+    return fail(TFS_EINVAL, "the shifted mode form is a form of the BDF2 scheme");
   for (int k = 0; k < D.nmodes; ++k)
     if (!finite_nonneg(D.w[k]) || !finite_nonneg(D.lambda[k]))
       return fail(TFS_EINVAL, "w and lambda must be finite and >= 0 (mode %d)", k);
@@ -297,7 +305,11 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   p->dt = D.dt;
   p->gamma = D.eta_p / D.De;
   p->precision = D.precision;
+  p->kappa_f32 = D.kappa_precision == TFS_KAPPA_FP32;
   p->scheme = D.scheme;
+  p->zform = D.scheme == TFS_SCHEME_BDF2 &&
+             (D.mode_form == TFS_MODE_FORM_Z || (D.mode_form == TFS_MODE_FORM_AUTO && D.precision == TFS_FP32_MODES));
+  p->xlev = p->zform ? 3 : 2;
   p->flags = D.flags;
   p->stream = static_cast<hipStream_t>(D.stream);
   p->w.assign(D.w, D.w + D.nmodes);
@@ -323,6 +335,9 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
     // start-up modes: X_k^1 = [h(1-gs) w_k r X^(1) + h gs w_k X^(2)] r;  Y_k^1 = X_k^1 - c_k X^1
     p->coef[tfs::kRowU * m + k] = dt * (1.0 - gs) * wk * r * r;
     p->coef[tfs::kRowV * m + k] = hg * wk * r - ck;
+    // shifted form: the quasi-static value of a mode that follows X is (w_k/lambda_k) X, of
+    // which Y_k keeps (w_k/lambda_k - c_k) X
+    if (p->zform && lk > 0.0) p->coef[tfs::kRowBeta * m + k] = wk / lk - ck;
     eta.add(b0 * ck);
     s_ec.add(ek * ck);
     theta.add(wk * r);
@@ -554,6 +569,7 @@ tfs_status tfs_run_fused(tfs_plan p, int64_t n0, int64_t nsteps, double* X, void
   if (!p) return fail(TFS_EINVAL, "null plan");
   if (!tfs::fused_supported(p))
     return fail(TFS_EUNSUPPORTED, "fused steps need m = 16 or 32, and FP32 modes in 3-D");
+  if (p->zform) return fail(TFS_EUNSUPPORTED, "fused steps keep the modes in the Y form (TFS_MODE_FORM_Y)");
   if (p->scheme == TFS_SCHEME_BDF2 && n0 < 1 && nsteps > 0)
     return fail(TFS_EINVAL, "fused BDF2 steps start at level 1 or later (level 0 -> 1 is tfs_step's SDIRK2 start)");
   if (spatial(p)) return fail(TFS_EUNSUPPORTED, "no fused steps in the spatial form");
@@ -567,10 +583,22 @@ tfs_status tfs_run_fused(tfs_plan p, int64_t n0, int64_t nsteps, double* X, void
   return TFS_OK;
 }
 
+tfs_status tfs_field_eval(tfs_plan p, double t, const double* add, void* kappa_out) {
+  if (!p) return fail(TFS_EINVAL, "null plan");
+  if (!p->d_field) return fail(TFS_EINVAL, "no field set (tfs_plan_set_field)");
+  if (!std::isfinite(t)) return fail(TFS_EINVAL, "non-finite time");
+  if (p->npoints > 0 && !kappa_out) return fail(TFS_EINVAL, "null kappa_out");
+  hipError_t e = tfs::launch_field_eval(p, t, add, kappa_out);
+  if (e != hipSuccess) return hip_fail(e, "field evaluation launch");
+  return TFS_OK;
+}
+
 tfs_status tfs_plan_set_spatial(tfs_plan p, const double* rate, int64_t source_point) {
   if (!p) return fail(TFS_EINVAL, "null plan");
   if (source_point < -1 || source_point >= p->npoints)
     return fail(TFS_EINVAL, "source_point %lld outside [-1, npoints)", (long long)source_point);
+  if (p->kappa_f32 && (rate || source_point >= 0))
+    return fail(TFS_EUNSUPPORTED, "the spatial form takes FP64 velocity gradients");
   p->sp_rate = rate;
   p->sp_source = source_point;
   return TFS_OK;
@@ -626,8 +654,24 @@ namespace {
 // dL/dlambda_k through e_k, f_k, om_k, l_k (and q_k at level 0); what remains goes through
 // the plan's scalars a = 1 + q/De, q = sum q_k, s_h = sum (om_k q_k - r_k),
 // eta_e = dt sum (w_k - lambda_k q_k), ts = eta_p/(De dt), and the mass increments zeta.
-tfs_status exp_pbar_to_params(tfs_plan p, const double* pb, double* dw, double* dlam, double* dDe,
-                              double* deta_p) {
+// dL/dalpha = sum_k (dL/dw_k dw_k/dalpha + dL/dlambda_k dlambda_k/dalpha), Neumaier-compensated.
+double alpha_chain(const std::vector<double>& wb, const std::vector<double>& lb, const double* dwa,
+                   const double* dla) {
+  double s = 0.0, comp = 0.0;
+  auto add = [&](double x) {
+    const double t = s + x;
+    comp += std::fabs(s) >= std::fabs(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+  };
+  for (size_t k = 0; k < wb.size(); ++k) {
+    add(wb[k] * dwa[k]);
+    add(lb[k] * dla[k]);
+  }
+  return s + comp;
+}
+
+tfs_status exp_pbar_to_params(tfs_plan p, const double* pb, const double* dwa, const double* dla, double* dw,
+                              double* dlam, double* dDe, double* deta_p, double* dalpha) {
   const int m = p->m;
   const double h = p->dt, iD = 1.0 / p->De;
   const double* sc = pb + 6 * m;
@@ -668,10 +712,11 @@ tfs_status exp_pbar_to_params(tfs_plan p, const double* pb, double* dw, double* 
   if (dlam) for (int k = 0; k < m; ++k) dlam[k] = lb[k];
   if (dDe) *dDe = -iDb * iD * iD;
   if (deta_p) *deta_p = eta_pb;
+  if (dalpha) *dalpha = alpha_chain(wb, lb, dwa, dla);
   return TFS_OK;
 }
 
-tfs_status run_step(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, const tfs::Levels& L,
+tfs_status run_step(tfs_plan p, int64_t n, const void* kappa_a, const void* kappa_b, const tfs::Levels& L,
                     double* tau, double* diag) {
   hipError_t e = p->scheme == TFS_SCHEME_EXP ? tfs::launch_exp(p, n, kappa_a, kappa_b, L, tau, diag)
                  : (n == 0) ? tfs::launch_startup(p, kappa_a, L, tau, diag)
@@ -694,7 +739,7 @@ tfs_status run_step(tfs_plan p, int64_t n, const double* kappa_a, const double* 
 
 }  // namespace
 
-tfs_status tfs_step(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, double* X, void* Y,
+tfs_status tfs_step(tfs_plan p, int64_t n, const void* kappa_a, const void* kappa_b, double* X, void* Y,
                     double* tau, double* diag) {
   if (!p) return fail(TFS_EINVAL, "null plan");
   if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
@@ -705,6 +750,25 @@ tfs_status tfs_step(tfs_plan p, int64_t n, const double* kappa_a, const double* 
   char* Yb = static_cast<char*>(Y);
   tfs::Levels L;
   const int sn = (int)(n % 2), sm = 1 - sn;
+  if (p->zform) {
+    // three X levels; the mode ring as in the plain form
+    const int64_t XL = p->xlev;
+    if (n == 0) {
+      L.Xn = X;
+      L.Xo = X + xs;
+      L.Ym0 = Yb;
+      L.Yo = Yb + ys * eb;
+    } else {
+      L.Xn = X + (n % XL) * xs;
+      L.Xm = X + ((n - 1) % XL) * xs;
+      L.Xmm = n >= 2 ? X + ((n - 2) % XL) * xs : nullptr;
+      L.Xo = X + ((n + 1) % XL) * xs;
+      L.Yn = Yb + sn * ys * eb;
+      L.Ym = Yb + sm * ys * eb;
+      L.Yo = Yb + sm * ys * eb;
+    }
+    return run_step(p, n, kappa_a, kappa_b, L, tau, diag);
+  }
   if (p->scheme == TFS_SCHEME_EXP) {
     L.Xn = X + sn * xs;
     L.Xo = X + sm * xs;
@@ -728,9 +792,9 @@ tfs_status tfs_step(tfs_plan p, int64_t n, const double* kappa_a, const double* 
   return run_step(p, n, kappa_a, kappa_b, L, tau, diag);
 }
 
-tfs_status tfs_step_levels(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, const double* X_n,
-                           const double* X_nm1, double* X_out, const void* Y_n, void* Y_nm1, void* Y_out,
-                           double* tau, double* diag) {
+tfs_status tfs_step_levels(tfs_plan p, int64_t n, const void* kappa_a, const void* kappa_b, const double* X_n,
+                           const double* X_nm1, const double* X_nm2, double* X_out, const void* Y_n, void* Y_nm1,
+                           void* Y_out, double* tau, double* diag) {
   if (!p) return fail(TFS_EINVAL, "null plan");
   if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
                                               (long long)n, (long long)p->max_steps);
@@ -750,6 +814,7 @@ tfs_status tfs_step_levels(tfs_plan p, int64_t n, const double* kappa_a, const d
   if (p->npoints > 0) {
     if (!kappa_a || !X_n || !X_out || !Y_nm1 || !Y_out) return fail(TFS_EINVAL, "null kappa_a, X or Y level");
     if (n > 0 && (!X_nm1 || !Y_n)) return fail(TFS_EINVAL, "null level n or n-1");
+    if (p->zform && n > 1 && !X_nm2) return fail(TFS_EINVAL, "null level n-2 (shifted mode form)");
     if (X_out == X_n) return fail(TFS_EINVAL, "X_out must not alias X_n");
     if (n > 0 && Y_out == Y_n) return fail(TFS_EINVAL, "Y_out must not alias Y_n");
   }
@@ -761,6 +826,7 @@ tfs_status tfs_step_levels(tfs_plan p, int64_t n, const double* kappa_a, const d
     L.Yo = Y_out;
   } else {
     L.Xm = X_nm1;
+    L.Xmm = (p->zform && n > 1) ? X_nm2 : nullptr;
     L.Yn = Y_n;
     L.Ym = Y_nm1;
     L.Yo = Y_out;
@@ -778,8 +844,9 @@ tfs_status tfs_pbar_rate_gradient(tfs_plan p, const double* pbar_host, double* o
   return TFS_OK;
 }
 
-tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const double* kappa_b, const double* X_n,
-                            const double* X_nm1, const double* X_np1, const void* Y_n, const void* Y_nm1,
+tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const void* kappa_a, const void* kappa_b, const double* X_n,
+                            const double* X_nm1, const double* X_nm2, const double* X_np1, const void* Y_n,
+                            const void* Y_nm1,
                             double* Xbar, void* Hbar, const double* taubar, double* kappabar_a,
                             double* kappabar_b, double* pbar) {
   if (!p) return fail(TFS_EINVAL, "null plan");
@@ -792,6 +859,8 @@ tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const 
       if (!X_np1 || (n > 0 && !Y_n)) return fail(TFS_EINVAL, "null forward level");
     } else if (n > 0 && (!X_nm1 || !X_np1 || !Y_n || !Y_nm1)) {
       return fail(TFS_EINVAL, "null forward level");
+    } else if (p->zform && n > 1 && !X_nm2) {
+      return fail(TFS_EINVAL, "null forward level n-2 (shifted mode form)");
     }
   }
   tfs::AdjLevels L;
@@ -799,6 +868,7 @@ tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const 
   L.kb = n > 0 ? kappa_b : nullptr;
   L.Xn = X_n;
   L.Xm = X_nm1;
+  L.Xmm = (p->zform && n > 1) ? X_nm2 : nullptr;
   L.Xp = X_np1;
   L.Yn = Y_n;
   L.Ym = Y_nm1;
@@ -812,9 +882,11 @@ tfs_status tfs_step_adjoint(tfs_plan p, int64_t n, const double* kappa_a, const 
   return TFS_OK;
 }
 
-tfs_status tfs_pbar_to_params(tfs_plan p, const double* pb, double* dw, double* dlam, double* dDe, double* deta_p) {
+tfs_status tfs_pbar_to_params(tfs_plan p, const double* pb, const double* dwa, const double* dla, double* dw,
+                              double* dlam, double* dDe, double* deta_p, double* dalpha) {
   if (!p || !pb) return fail(TFS_EINVAL, "null plan or pbar");
-  if (p->scheme == TFS_SCHEME_EXP) return exp_pbar_to_params(p, pb, dw, dlam, dDe, deta_p);
+  if (dalpha && (!dwa || !dla)) return fail(TFS_EINVAL, "dL/dalpha needs dw/dalpha and dlambda/dalpha");
+  if (p->scheme == TFS_SCHEME_EXP) return exp_pbar_to_params(p, pb, dwa, dla, dw, dlam, dDe, deta_p, dalpha);
   const int m = p->m;
   const double h = p->dt, b0 = tfs::kB0, gs = 1.0 - 1.0 / std::sqrt(2.0), hg = h * gs, hs = h * (1.0 - gs);
   const double iD = 1.0 / p->De;
@@ -907,16 +979,19 @@ tfs_status tfs_pbar_to_params(tfs_plan p, const double* pb, double* dw, double* 
   if (dlam) for (int k = 0; k < m; ++k) dlam[k] = lb[k];
   if (dDe) *dDe = -iDb * iD * iD;
   if (deta_p) *deta_p = eta_pb;
+  if (dalpha) *dalpha = alpha_chain(wb, lb, dwa, dla);
   return TFS_OK;
 }
 
-tfs_status tfs_modes_to_plain(tfs_plan p, int32_t slot, const double* X, const void* Y, double* Xk_out) {
+tfs_status tfs_modes_to_plain(tfs_plan p, int64_t level, const double* X, const void* Y, double* Xk_out) {
   if (!p) return fail(TFS_EINVAL, "null plan");
-  if (slot != 0 && slot != 1) return fail(TFS_EINVAL, "slot must be 0 or 1");
+  if (level < 0) return fail(TFS_EINVAL, "level must be >= 0");
   if (p->npoints > 0 && (!X || !Y || !Xk_out)) return fail(TFS_EINVAL, "null pointer");
-  hipError_t e = tfs::launch_modes_to_plain(p, slot, X, Y, Xk_out);
+  hipError_t e = tfs::launch_modes_to_plain(p, level, X, Y, Xk_out);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return TFS_OK;
 }
+
+int32_t tfs_plan_x_levels(tfs_plan p) { return p ? p->xlev : -1; }
 
 }  // extern "C"

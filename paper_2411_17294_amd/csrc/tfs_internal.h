@@ -24,7 +24,8 @@ enum CoefRow : int {
   kRowC = 3,    // c_k = w_k dt d_k
   kRowU = 4,    // start-up: coefficient of the first stage value in Y_k^1
   kRowV = 5,    // start-up: coefficient of the second stage value in Y_k^1
-  kNumCoef = 6
+  kRowBeta = 6, // shifted mode form: beta_k = w_k/lambda_k - c_k (0 for lambda_k = 0 or the plain form)
+  kNumCoef = 7
 };
 
 // Rows of the same table for TFS_SCHEME_EXP plans (exponential mode update).
@@ -111,6 +112,11 @@ struct tfs_plan_s {
   int64_t tile = 0;           // mode-ring tile (points); equals stride when untiled
   double alpha = 0, De = 0, eta_p = 0, dt = 0, gamma = 0;
   int precision = 0;
+  bool kappa_f32 = false;     // velocity gradients stored in FP32 (FP32-mode plans only)
+  // BDF2 mode representation: Y-form Y_k^j = X_k^j - c_k X^j, or the shifted form
+  // Z_k^j = Y_k^j - beta_k X^{j-1} (X^{-1} = 0), which needs X at three levels
+  bool zform = false;
+  int xlev = 2;               // slots of the X ring (3 with the shifted form)
   int scheme = TFS_SCHEME_BDF2;
   uint32_t flags = 0;
   hipStream_t stream = nullptr;
@@ -154,6 +160,7 @@ namespace tfs {
 struct Levels {
   const double* Xn = nullptr;
   const double* Xm = nullptr;
+  const double* Xmm = nullptr;  // X^{n-2} (shifted mode form, n >= 2; null: zero)
   double* Xo = nullptr;
   const void* Yn = nullptr;
   const void* Ym = nullptr;
@@ -163,14 +170,15 @@ struct Levels {
 
 // Pointers of one adjoint step.
 struct AdjLevels {
-  const double* ka = nullptr;
-  const double* kb = nullptr;
+  const void* ka = nullptr;     // plan's kappa precision
+  const void* kb = nullptr;
   const double* Xn = nullptr;   // forward X^n (X^0 at n = 0)
   const double* Xm = nullptr;   // forward X^{n-1}
+  const double* Xmm = nullptr;  // forward X^{n-2} (shifted mode form, n >= 2; null: zero)
   const double* Xp = nullptr;   // forward X^{n+1}
   const void* Yn = nullptr;     // forward Y^n
   const void* Ym = nullptr;     // forward Y^{n-1}
-  double* Xbar = nullptr;       // adjoint ring [2][c][stride]
+  double* Xbar = nullptr;       // adjoint ring [xlev][c][stride]
   void* Hbar = nullptr;         // mode-adjoint ring, 2 slots
   const double* taubar = nullptr;
   double* kba = nullptr;
@@ -182,23 +190,27 @@ hipError_t launch_adjoint(const tfs_plan_s* p, int64_t n, const AdjLevels& L, do
 // Fused exponential-mode steps with kappa from the plan's analytic field (tfs_fused.hip).
 bool fused_supported(const tfs_plan_s* p);
 hipError_t launch_fused(const tfs_plan_s* p, int64_t n0, int64_t nsteps, double* X, void* Y, double* tau);
-hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+// ka, kb: velocity gradients in the plan's kappa precision (FP64, or FP32 when kappa_f32).
+hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const void* ka, const void* kb, const Levels& L,
                        double* tau, double* diag);
-hipError_t launch_startup(const tfs_plan_s* p, const double* ka, const Levels& L, double* tau, double* diag);
+hipError_t launch_startup(const tfs_plan_s* p, const void* ka, const Levels& L, double* tau, double* diag);
 // BDF2 step n >= 1 without the local solve: writes Y^{n+1} (L.Yo), the right-hand side R of
 // each point (L.Xo) and the history combination G ([c][stride]); no diagnostics.
 hipError_t launch_bdf2_split(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
                              double* G);
 // Exponential-mode step n -> n+1 (TFS_SCHEME_EXP): reads L.Xn and L.Yn (not at n = 0),
 // writes L.Xo and L.Yo (which may be L.Yn).
-hipError_t launch_exp(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+hipError_t launch_exp(const tfs_plan_s* p, int64_t n, const void* ka, const void* kb, const Levels& L,
                       double* tau, double* diag);
 // Exponential-mode step without the local solve: writes Y^{n+1} (L.Yo, may be L.Yn), the
 // right-hand side R of each point (L.Xo), G and H ([c][stride] each); no diagnostics.
 hipError_t launch_exp_split(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
                             double* G, double* H);
-hipError_t launch_modes_to_plain(const tfs_plan_s* p, int slot, const double* X, const void* Y,
+hipError_t launch_modes_to_plain(const tfs_plan_s* p, int64_t level, const double* X, const void* Y,
                                  double* Xk);
+// kappa_out [d*d][stride] (plan's kappa precision) = the plan's analytic field at time t, plus
+// add [d*d][stride] FP64 when add is not null (tfs_field.hip).
+hipError_t launch_field_eval(const tfs_plan_s* p, double t, const double* add, void* out);
 // Upper bound of blocks the launchers use for a plan (sizes d_part).
 int max_blocks(const tfs_plan_s* p);
 

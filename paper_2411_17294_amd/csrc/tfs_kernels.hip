@@ -74,14 +74,15 @@ __device__ __forceinline__ void load_spatial(const SpatialArgs& sp, const WaveAd
   for (int v = 0; v < V; ++v) srcw[v] = (sp.src < 0 || p0 + v == sp.src) ? 1.0 : 0.0;
 }
 
-template <typename MT>
+template <typename MT, typename KT>
 struct Bdf2Args {
-  const double* ka;     // kappa_a [d*d][stride]
-  const double* kb;     // kappa_b or null
+  const KT* ka;         // kappa_a [d*d][stride] (FP64, or FP32 for an FP32-kappa plan)
+  const KT* kb;         // kappa_b or null
   const double* Xn;     // X^n      [c][stride]
   const double* Xm;     // X^{n-1}  [c][stride]
-  double* Xo;           // X^{n+1}  [c][stride] (may be Xm: then each lane reads before it writes)
-  const MT* Yn;         // Y^n      (m * c * stride elements, tiled)
+  const double* Xmm;    // X^{n-2}  [c][stride] (shifted mode form; null: zero)
+  double* Xo;           // X^{n+1}  [c][stride] (may be Xm or Xmm: each lane reads before it writes)
+  const MT* Yn;         // Y^n      (m * c * stride elements, tiled; Z^n in the shifted form)
   const MT* Ym;         // Y^{n-1}
   MT* Yo;               // Y^{n+1}  (may be Ym, same rule)
   double* tau;          // [c][stride] or null
@@ -98,15 +99,19 @@ struct Bdf2Args {
 // SPLIT: the step without its local solve, for a caller that solves a spatially coupled
 // system for X^{n+1}: the modes advance as usual (in the Y-form they do not depend on
 // X^{n+1}), the point's right-hand side R goes to Xo and the history combination G to tau.
-template <int D, typename MT, int V, bool DIAG, bool SP, bool SPLIT = false>
-__device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr& w, DiagAcc& acc) {
+// ZF: the shifted mode form Z_k^j = Y_k^j - beta_k X^{j-1}: the history is read back as
+// h^_k = 2 Z_k^n - Z_k^{n-1}/2 + beta_k B with B = 2 X^{n-1} - X^{n-2}/2, and the new level is
+// stored as Z_k^{n+1} = d_k h^_k + d_k c_k P - beta_k X^n (still independent of X^{n+1}).
+template <int D, typename MT, typename KT, int V, bool DIAG, bool SP, bool SPLIT = false, bool ZF = false>
+__device__ __forceinline__ void bdf2_group(const Bdf2Args<MT, KT>& a, const WaveAddr& w, DiagAcc& acc) {
   constexpr int C = Sym<D>::C;
+  constexpr int CZ = ZF ? C : 1;
   const int64_t st = a.stride;
   const int m = a.m;
   const int64_t T = a.tile;
 
-  // P = 2 X^n - X^{n-1}/2
-  double P[C][V];
+  // P = 2 X^n - X^{n-1}/2 (and B = 2 X^{n-1} - X^{n-2}/2 and X^n in the shifted form)
+  double P[C][V], B[CZ][V], Xc[CZ][V];
 #pragma unroll
   for (int s = 0; s < C; ++s) {
     double xn[V], xm[V];
@@ -114,6 +119,20 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr
     load_v<true, double, V>(at(a.Xm + s * st + w.pw, w.ox), V, xm);
 #pragma unroll
     for (int v = 0; v < V; ++v) P[s][v] = 2.0 * xn[v] - 0.5 * xm[v];
+    if constexpr (ZF) {
+      double xmm[V];
+      if (a.Xmm) {
+        load_v<true, double, V>(at(a.Xmm + s * st + w.pw, w.ox), V, xmm);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) xmm[v] = 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        B[s][v] = 2.0 * xm[v] - 0.5 * xmm[v];
+        Xc[s][v] = xn[v];
+      }
+    }
   }
 
   // mode stream: the loads of mode k+1 are issued before the stores of mode k
@@ -136,6 +155,7 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr
     const double dk = load_uniform(a.coef + kRowD * m + k);
     const double dck = load_uniform(a.coef + kRowDC * m + k);
     const double ek = load_uniform(a.coef + kRowEta * m + k);
+    const double bk = ZF ? load_uniform(a.coef + kRowBeta * m + k) : 0.0;
     MT nn[C][V], nm[C][V];
     if (k + 1 < m) {
       const int64_t o = (int64_t)(k + 1) * C * T;
@@ -153,8 +173,13 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr
       MT out[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        const double h = 2.0 * (double)cn[s][v] - 0.5 * (double)cm[s][v];
-        out[v] = (MT)(dk * h + dck * P[s][v]);
+        double h = 2.0 * (double)cn[s][v] - 0.5 * (double)cm[s][v];
+        if constexpr (ZF) {
+          h += bk * B[s][v];
+          out[v] = (MT)(dk * h + (dck * P[s][v] - bk * Xc[s][v]));
+        } else {
+          out[v] = (MT)(dk * h + dck * P[s][v]);
+        }
         two_sum_acc(Gs[s][v], Ge[s][v], mul_rn(ek, h));
       }
       store_v<true, MT, V, true>(at(yo + s * T, om), V, out);
@@ -167,20 +192,21 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr
     }
   }
 
-  // velocity gradient driving the step
+  // velocity gradient driving the step (read in its storage precision, extrapolated in FP64)
   double kt[D * D][V];
+  const uint32_t kx = field_off<KT>(w.ox);
 #pragma unroll
   for (int q = 0; q < D * D; ++q) {
-    double ka[V];
-    load_v<true, double, V>(at(a.ka + q * st + w.pw, w.ox), V, ka);
+    KT ka[V];
+    load_v<true, KT, V>(at(a.ka + q * st + w.pw, kx), V, ka);
     if (a.kb) {
-      double kb[V];
-      load_v<true, double, V>(at(a.kb + q * st + w.pw, w.ox), V, kb);
+      KT kb[V];
+      load_v<true, KT, V>(at(a.kb + q * st + w.pw, kx), V, kb);
 #pragma unroll
-      for (int v = 0; v < V; ++v) kt[q][v] = 2.0 * ka[v] - kb[v];
+      for (int v = 0; v < V; ++v) kt[q][v] = 2.0 * (double)ka[v] - (double)kb[v];
     } else {
 #pragma unroll
-      for (int v = 0; v < V; ++v) kt[q][v] = ka[v];
+      for (int v = 0; v < V; ++v) kt[q][v] = (double)ka[v];
     }
   }
 
@@ -237,8 +263,8 @@ __device__ __forceinline__ void bdf2_group(const Bdf2Args<MT>& a, const WaveAddr
 
 // Groups [0, ngroups) of V points from p_begin, 64 consecutive groups per wave; the
 // caller launches a V = 1 pass for the points after the last whole group.
-template <int D, typename MT, int V, bool DIAG, bool SP, bool SPLIT = false>
-__global__ __launch_bounds__(kBlock) void bdf2_kernel(const Bdf2Args<MT> a) {
+template <int D, typename MT, typename KT, int V, bool DIAG, bool SP, bool SPLIT = false, bool ZF = false>
+__global__ __launch_bounds__(kBlock) void bdf2_kernel(const Bdf2Args<MT, KT> a) {
   constexpr int C = Sym<D>::C;
   DiagAcc acc;
   const int lane = threadIdx.x % 64;
@@ -247,7 +273,8 @@ __global__ __launch_bounds__(kBlock) void bdf2_kernel(const Bdf2Args<MT> a) {
   for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
        wv += wstride) {
     if (wv * 64 + lane < a.ngroups)
-      bdf2_group<D, MT, V, DIAG, SP, SPLIT>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
+      bdf2_group<D, MT, KT, V, DIAG, SP, SPLIT, ZF>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m),
+                                                    acc);
   }
   if constexpr (DIAG) {
     const DiagAcc r = block_reduce(acc);
@@ -256,9 +283,9 @@ __global__ __launch_bounds__(kBlock) void bdf2_kernel(const Bdf2Args<MT> a) {
 }
 
 // ------------------------------------------------------------------ SDIRK2 start-up
-template <typename MT>
+template <typename MT, typename KT>
 struct StartArgs {
-  const double* ka;  // kappa^0
+  const KT* ka;      // kappa^0
   const double* X0;  // X^0 [c][stride]
   double* X1;        // X^1 [c][stride] (out)
   MT* Y0;            // Y^0 (m * c * stride elements, tiled; out)
@@ -269,12 +296,13 @@ struct StartArgs {
   int64_t p_begin, ngroups;
   int64_t stride, tile;
   int m, part0;
+  int zform;         // shifted mode form: Z^1 = Y^1 - beta_k X^0 (Z^0 = Y^0: X^{-1} = 0)
   StartScalars s;
   SpatialArgs sp;
 };
 
-template <int D, typename MT, int V, bool DIAG, bool SP>
-__device__ __forceinline__ void start_group(const StartArgs<MT>& a, const WaveAddr& w, DiagAcc& acc) {
+template <int D, typename MT, typename KT, int V, bool DIAG, bool SP>
+__device__ __forceinline__ void start_group(const StartArgs<MT, KT>& a, const WaveAddr& w, DiagAcc& acc) {
   constexpr int C = Sym<D>::C;
   const int64_t st = a.stride;
   const int m = a.m;
@@ -283,7 +311,12 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, const WaveAd
   for (int s = 0; s < C; ++s) load_v<true, double, V>(at(a.X0 + s * st + w.pw, w.ox), V, X0[s]);
   double kt[D * D][V];
 #pragma unroll
-  for (int q = 0; q < D * D; ++q) load_v<true, double, V>(at(a.ka + q * st + w.pw, w.ox), V, kt[q]);
+  for (int q = 0; q < D * D; ++q) {
+    KT x[V];
+    load_v<true, KT, V>(at(a.ka + q * st + w.pw, field_off<KT>(w.ox)), V, x);
+#pragma unroll
+    for (int v = 0; v < V; ++v) kt[q][v] = (double)x[v];
+  }
 
   double rate[V], srcw[V];
   if constexpr (SP) load_spatial<V>(a.sp, w, rate, srcw);
@@ -333,7 +366,8 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, const WaveAd
     store_v<true, double, V>(at(a.X1 + s * st + w.pw, w.ox), V, X2[s]);
     if (a.tau) store_v<true, double, V>(at(a.tau + s * st + w.pw, w.ox), V, Tout[s]);
   }
-  // modes: Y_k^0 = -c_k X^0 (slot 0), Y_k^1 = u_k X^(1) + v_k X^(2) (slot 1)
+  // modes: Y_k^0 = -c_k X^0 (slot 0), Y_k^1 = u_k X^(1) + v_k X^(2) (slot 1); in the
+  // shifted form level 1 is stored less beta_k X^0
   const int64_t T = a.tile;
   MT* Y0 = a.Y0 + w.tw;
   MT* Y1 = a.Y1 + w.tw;
@@ -341,13 +375,14 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, const WaveAd
     const double ck = load_uniform(a.coef + kRowC * m + k);
     const double uk = load_uniform(a.coef + kRowU * m + k);
     const double vk = load_uniform(a.coef + kRowV * m + k);
+    const double bk = a.zform ? load_uniform(a.coef + kRowBeta * m + k) : 0.0;
 #pragma unroll
     for (int s = 0; s < C; ++s) {
       MT o0[V], o1[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         o0[v] = (MT)(-ck * X0[s][v]);
-        o1[v] = (MT)(uk * X1[s][v] + vk * X2[s][v]);
+        o1[v] = (MT)((uk * X1[s][v] + vk * X2[s][v]) - bk * X0[s][v]);
       }
       store_v<true, MT, V, true>(at(Y0 + ((int64_t)k * C + s) * T, w.om), V, o0);
       store_v<true, MT, V, true>(at(Y1 + ((int64_t)k * C + s) * T, w.om), V, o1);
@@ -355,8 +390,8 @@ __device__ __forceinline__ void start_group(const StartArgs<MT>& a, const WaveAd
   }
 }
 
-template <int D, typename MT, int V, bool DIAG, bool SP>
-__global__ __launch_bounds__(kBlock) void start_kernel(const StartArgs<MT> a) {
+template <int D, typename MT, typename KT, int V, bool DIAG, bool SP>
+__global__ __launch_bounds__(kBlock) void start_kernel(const StartArgs<MT, KT> a) {
   constexpr int C = Sym<D>::C;
   DiagAcc acc;
   const int lane = threadIdx.x % 64;
@@ -365,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void start_kernel(const StartArgs<MT> a) {
   for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
        wv += wstride) {
     if (wv * 64 + lane < a.ngroups)
-      start_group<D, MT, V, DIAG, SP>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
+      start_group<D, MT, KT, V, DIAG, SP>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
   }
   if constexpr (DIAG) {
     const DiagAcc r = block_reduce(acc);
@@ -384,10 +419,10 @@ __global__ __launch_bounds__(kBlock) void start_kernel(const StartArgs<MT> a) {
 // Mode loads issued ahead of the arithmetic in the exponential-mode step.
 constexpr int kExpAhead = 2;
 
-template <typename MT>
+template <typename MT, typename KT>
 struct ExpArgs {
-  const double* ka;     // kappa_a [d*d][stride]
-  const double* kb;     // kappa_b or null
+  const KT* ka;         // kappa_a [d*d][stride]
+  const KT* kb;         // kappa_b or null
   const double* Xn;     // X^n     [c][stride]
   double* Xo;           // X^{n+1} [c][stride]
   const MT* Yn;         // Y^n (m * c * stride elements, tiled); not read at n = 0
@@ -406,8 +441,8 @@ struct ExpArgs {
 // SPLIT: the step without its local solve, for a caller that solves a spatially coupled
 // system: X^{n+1} receives each point's right-hand side R, tau the compensated G and Hout the
 // H of the local system (the modes are written as usual: they do not depend on X^{n+1}).
-template <int D, typename MT, int V, bool DIAG, bool SP, bool SPLIT = false>
-__device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& w, DiagAcc& acc) {
+template <int D, typename MT, typename KT, int V, bool DIAG, bool SP, bool SPLIT = false>
+__device__ __forceinline__ void exp_group(const ExpArgs<MT, KT>& a, const WaveAddr& w, DiagAcc& acc) {
   constexpr int C = Sym<D>::C;
   const int64_t st = a.stride;
   const int m = a.m;
@@ -489,12 +524,12 @@ __device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& 
     double k[D * D], Hv[C], AH[C], R[C];
 #pragma unroll
     for (int q = 0; q < D * D; ++q) {
-      double x[1];
-      load_v<true, double, 1>(at(a.ka + q * st + w.pw, ox), 1, x);
-      k[q] = x[0];
+      KT x[1];
+      load_v<true, KT, 1>(at(a.ka + q * st + w.pw, field_off<KT>(ox)), 1, x);
+      k[q] = (double)x[0];
       if (a.kb) {
-        load_v<true, double, 1>(at(a.kb + q * st + w.pw, ox), 1, x);
-        k[q] = a.s.fa * k[q] + a.s.fb * x[0];
+        load_v<true, KT, 1>(at(a.kb + q * st + w.pw, field_off<KT>(ox)), 1, x);
+        k[q] = a.s.fa * k[q] + a.s.fb * (double)x[0];
       }
     }
     double rate = 0.0, srcw = 1.0;                 // spatial form: extra rate, source weight
@@ -559,8 +594,8 @@ __device__ __forceinline__ void exp_group(const ExpArgs<MT>& a, const WaveAddr& 
   }
 }
 
-template <int D, typename MT, int V, bool DIAG, bool SP, bool SPLIT = false>
-__global__ __launch_bounds__(kBlock) void exp_kernel(const ExpArgs<MT> a) {
+template <int D, typename MT, typename KT, int V, bool DIAG, bool SP, bool SPLIT = false>
+__global__ __launch_bounds__(kBlock) void exp_kernel(const ExpArgs<MT, KT> a) {
   constexpr int C = Sym<D>::C;
   DiagAcc acc;
   const int lane = threadIdx.x % 64;
@@ -569,7 +604,8 @@ __global__ __launch_bounds__(kBlock) void exp_kernel(const ExpArgs<MT> a) {
   for (int64_t wv = wave_uniform((int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64); wv < nwaves;
        wv += wstride) {
     if (wv * 64 + lane < a.ngroups)
-      exp_group<D, MT, V, DIAG, SP, SPLIT>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m), acc);
+      exp_group<D, MT, KT, V, DIAG, SP, SPLIT>(a, wave_addr<MT, C, V>(a.p_begin + wv * 64 * V, lane, a.tile, a.m),
+                                               acc);
   }
   if constexpr (DIAG) {
     const DiagAcc r = block_reduce(acc);
@@ -578,10 +614,12 @@ __global__ __launch_bounds__(kBlock) void exp_kernel(const ExpArgs<MT> a) {
 }
 
 // ------------------------------------------------------------------ plain modes
+// X_k = Y_k + c_k X^j (+ beta_k X^{j-1} in the shifted form, Xm null: zero).
 template <typename MT>
-__global__ __launch_bounds__(kBlock) void plain_kernel(const double* __restrict__ X, const MT* __restrict__ Y,
-                                                       const double* __restrict__ coef, double* __restrict__ out,
-                                                       int64_t npts, int64_t stride, int64_t tile, int m, int c) {
+__global__ __launch_bounds__(kBlock) void plain_kernel(const double* __restrict__ X, const double* __restrict__ Xm,
+                                                       const MT* __restrict__ Y, const double* __restrict__ coef,
+                                                       double* __restrict__ out, int64_t npts, int64_t stride,
+                                                       int64_t tile, int m, int c, int zform) {
   const int64_t total = (int64_t)m * c * npts;
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += (int64_t)gridDim.x * kBlock) {
     const int64_t p = t % npts;
@@ -589,7 +627,9 @@ __global__ __launch_bounds__(kBlock) void plain_kernel(const double* __restrict_
     const int s = (int)(ks % c);
     const int k = (int)(ks / c);
     const int64_t yi = ((p / tile) * m * c + ks) * tile + p % tile;
-    out[ks * stride + p] = (double)Y[yi] + coef[kRowC * m + k] * X[s * stride + p];
+    double x = (double)Y[yi] + coef[kRowC * m + k] * X[s * stride + p];
+    if (zform && Xm) x += coef[kRowBeta * m + k] * Xm[s * stride + p];
+    out[ks * stride + p] = x;
   }
 }
 
@@ -606,9 +646,9 @@ bool aligned(const void* ptr, size_t bytes) { return ptr == nullptr || ((uintptr
 
 // Points per lane: the requested width, else the widest one (4 for FP32 modes, 2 for
 // FP64: 16-byte mode accesses, fastest on MI355X) for which every plane start and every
-// group start is aligned to the vector size of each field (modes: V * sizeof(MT); FP64
-// fields: V * 8).
-template <int D, typename MT>
+// group start is aligned to the vector size of each field (modes: V * sizeof(MT); the
+// velocity gradient: V * sizeof(KT); the other fields, FP64: V * 8).
+template <int D, typename MT, typename KT>
 int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const Levels& L, const void* tau,
              int max_v = 4) {
   const int widest = std::min(max_v, sizeof(MT) == 4 ? 4 : 2);
@@ -617,8 +657,8 @@ int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const Levels& 
     if (V > widest) continue;
     if (p->vec_override && V != p->vec_override) continue;
     if (p->stride % V || p->tile % V) continue;
-    const size_t bm = (size_t)V * sizeof(MT), bd = (size_t)V * 8;
-    if (aligned(k0, bd) && aligned(k1, bd) && aligned(L.Xn, bd) && aligned(L.Xm, bd) && aligned(L.Xo, bd) &&
+    const size_t bm = (size_t)V * sizeof(MT), bd = (size_t)V * 8, bk = (size_t)V * sizeof(KT);
+    if (aligned(k0, bk) && aligned(k1, bk) && aligned(L.Xn, bd) && aligned(L.Xm, bd) && aligned(L.Xo, bd) &&
         aligned(L.Yn, bm) && aligned(L.Ym, bm) && aligned(L.Ym0, bm) && aligned(L.Yo, bm) && aligned(tau, bd) &&
         aligned(p->sp_rate, bd))
       return V;
@@ -628,46 +668,58 @@ int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const Levels& 
 
 // Whole groups of V points with the V-wide kernel, the remaining npoints % V points with
 // the V = 1 kernel; the diagnostics fold the block partials of both launches.
-template <int D, typename MT, int V, bool DIAG, bool SP>
-hipError_t bdf2_launch(const tfs_plan_s* p, Bdf2Args<MT> a, int64_t p_begin, int64_t ngroups, int part0,
+template <int D, typename MT, typename KT, int V, bool DIAG, bool SP, bool ZF>
+hipError_t bdf2_launch(const tfs_plan_s* p, Bdf2Args<MT, KT> a, int64_t p_begin, int64_t ngroups, int part0,
                        int* nblocks) {
   a.p_begin = p_begin;
   a.ngroups = ngroups;
   a.part0 = part0;
   const int grid = grid_for(p, ngroups);
-  hipLaunchKernelGGL((bdf2_kernel<D, MT, V, DIAG, SP>), dim3(grid), dim3(kBlock), 0, p->stream, a);
+  hipLaunchKernelGGL((bdf2_kernel<D, MT, KT, V, DIAG, SP, false, ZF>), dim3(grid), dim3(kBlock), 0, p->stream, a);
   *nblocks = grid;
   return hipGetLastError();
 }
 
-template <int D, typename MT, int V, bool DIAG, bool SP>
-hipError_t bdf2_go_(const tfs_plan_s* p, const Bdf2Args<MT>& a, double* diag_out) {
+template <int D, typename MT, typename KT, int V, bool DIAG, bool SP, bool ZF>
+hipError_t bdf2_go_(const tfs_plan_s* p, const Bdf2Args<MT, KT>& a, double* diag_out) {
   const int64_t full = p->npoints / V, rest = p->npoints - full * V;
   int nb = 0, nt = 0;
   hipError_t e = hipSuccess;
-  if (full > 0) e = bdf2_launch<D, MT, V, DIAG, SP>(p, a, 0, full, 0, &nb);
-  if (e == hipSuccess && rest > 0) e = bdf2_launch<D, MT, 1, DIAG, SP>(p, a, full * V, rest, nb, &nt);
+  if (full > 0) e = bdf2_launch<D, MT, KT, V, DIAG, SP, ZF>(p, a, 0, full, 0, &nb);
+  if (e == hipSuccess && rest > 0) e = bdf2_launch<D, MT, KT, 1, DIAG, SP, ZF>(p, a, full * V, rest, nb, &nt);
   if (e == hipSuccess && DIAG)
     hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, a.part, nb + nt, diag_out);
   return e == hipSuccess ? hipGetLastError() : e;
 }
 
-template <int D, typename MT, int V>
-hipError_t bdf2_go(const tfs_plan_s* p, const Bdf2Args<MT>& a, bool diag, double* diag_out) {
-  if (a.sp.rate || a.sp.src >= 0)
-    return diag ? bdf2_go_<D, MT, V, true, true>(p, a, diag_out) : bdf2_go_<D, MT, V, false, true>(p, a, diag_out);
-  return diag ? bdf2_go_<D, MT, V, true, false>(p, a, diag_out) : bdf2_go_<D, MT, V, false, false>(p, a, diag_out);
+// The spatial form reads FP64 velocity gradients only (an FP32-kappa plan refuses it).
+template <int D, typename MT, typename KT, int V, bool ZF>
+hipError_t bdf2_go_z(const tfs_plan_s* p, const Bdf2Args<MT, KT>& a, bool diag, double* diag_out) {
+  if constexpr (sizeof(KT) == 8) {
+    if (a.sp.rate || a.sp.src >= 0)
+      return diag ? bdf2_go_<D, MT, KT, V, true, true, ZF>(p, a, diag_out)
+                  : bdf2_go_<D, MT, KT, V, false, true, ZF>(p, a, diag_out);
+  }
+  return diag ? bdf2_go_<D, MT, KT, V, true, false, ZF>(p, a, diag_out)
+              : bdf2_go_<D, MT, KT, V, false, false, ZF>(p, a, diag_out);
 }
 
-template <int D, typename MT>
-hipError_t bdf2_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+template <int D, typename MT, typename KT, int V>
+hipError_t bdf2_go(const tfs_plan_s* p, const Bdf2Args<MT, KT>& a, bool diag, double* diag_out) {
+  return p->zform ? bdf2_go_z<D, MT, KT, V, true>(p, a, diag, diag_out)
+                  : bdf2_go_z<D, MT, KT, V, false>(p, a, diag, diag_out);
+}
+
+template <int D, typename MT, typename KT>
+hipError_t bdf2_dispatch(const tfs_plan_s* p, int64_t n, const void* ka, const void* kb, const Levels& L,
                          double* tau, double* diag) {
   const int64_t st = p->stride;
-  Bdf2Args<MT> a;
-  a.ka = ka;
-  a.kb = kb;
+  Bdf2Args<MT, KT> a;
+  a.ka = static_cast<const KT*>(ka);
+  a.kb = static_cast<const KT*>(kb);
   a.Xn = L.Xn;
   a.Xm = L.Xm;
+  a.Xmm = p->zform ? L.Xmm : nullptr;
   a.Xo = L.Xo;
   a.Yn = static_cast<const MT*>(L.Yn);
   a.Ym = static_cast<const MT*>(L.Ym);
@@ -686,62 +738,67 @@ hipError_t bdf2_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const
   a.s.inv_De = 1.0 / p->De;
   a.s.zeta = p->zeta[n + 1];
   a.s.tau_scale = p->tau_scale;
-  const int V = pick_vec<D, MT>(p, ka, kb, L, tau);
+  int V = pick_vec<D, MT, KT>(p, ka, kb, L, tau);
+  if (V > 1 && !aligned(a.Xmm, (size_t)V * 8)) V = 1;
   const bool dg = diag != nullptr;
   if constexpr (sizeof(MT) == 4) {
-    if (V == 4) return bdf2_go<D, MT, 4>(p, a, dg, diag);
+    if (V == 4) return bdf2_go<D, MT, KT, 4>(p, a, dg, diag);
   }
-  if (V == 2) return bdf2_go<D, MT, 2>(p, a, dg, diag);
-  return bdf2_go<D, MT, 1>(p, a, dg, diag);
+  if (V == 2) return bdf2_go<D, MT, KT, 2>(p, a, dg, diag);
+  return bdf2_go<D, MT, KT, 1>(p, a, dg, diag);
 }
 
-template <int D, typename MT, int V, bool DIAG, bool SP>
-hipError_t start_launch(const tfs_plan_s* p, StartArgs<MT> a, int64_t p_begin, int64_t ngroups, int part0,
-                       int* nblocks) {
+template <int D, typename MT, typename KT, int V, bool DIAG, bool SP>
+hipError_t start_launch(const tfs_plan_s* p, StartArgs<MT, KT> a, int64_t p_begin, int64_t ngroups, int part0,
+                        int* nblocks) {
   a.p_begin = p_begin;
   a.ngroups = ngroups;
   a.part0 = part0;
   const int grid = grid_for(p, ngroups);
-  hipLaunchKernelGGL((start_kernel<D, MT, V, DIAG, SP>), dim3(grid), dim3(kBlock), 0, p->stream, a);
+  hipLaunchKernelGGL((start_kernel<D, MT, KT, V, DIAG, SP>), dim3(grid), dim3(kBlock), 0, p->stream, a);
   *nblocks = grid;
   return hipGetLastError();
 }
 
-template <int D, typename MT, int V, bool DIAG, bool SP>
-hipError_t start_go_(const tfs_plan_s* p, const StartArgs<MT>& a, double* diag_out) {
+template <int D, typename MT, typename KT, int V, bool DIAG, bool SP>
+hipError_t start_go_(const tfs_plan_s* p, const StartArgs<MT, KT>& a, double* diag_out) {
   const int64_t full = p->npoints / V, rest = p->npoints - full * V;
   int nb = 0, nt = 0;
   hipError_t e = hipSuccess;
-  if (full > 0) e = start_launch<D, MT, V, DIAG, SP>(p, a, 0, full, 0, &nb);
-  if (e == hipSuccess && rest > 0) e = start_launch<D, MT, 1, DIAG, SP>(p, a, full * V, rest, nb, &nt);
+  if (full > 0) e = start_launch<D, MT, KT, V, DIAG, SP>(p, a, 0, full, 0, &nb);
+  if (e == hipSuccess && rest > 0) e = start_launch<D, MT, KT, 1, DIAG, SP>(p, a, full * V, rest, nb, &nt);
   if (e == hipSuccess && DIAG)
     hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, a.part, nb + nt, diag_out);
   return e == hipSuccess ? hipGetLastError() : e;
 }
 
-template <int D, typename MT, int V>
-hipError_t start_go(const tfs_plan_s* p, const StartArgs<MT>& a, bool diag, double* diag_out) {
-  if (a.sp.rate || a.sp.src >= 0)
-    return diag ? start_go_<D, MT, V, true, true>(p, a, diag_out) : start_go_<D, MT, V, false, true>(p, a, diag_out);
-  return diag ? start_go_<D, MT, V, true, false>(p, a, diag_out) : start_go_<D, MT, V, false, false>(p, a, diag_out);
+template <int D, typename MT, typename KT, int V>
+hipError_t start_go(const tfs_plan_s* p, const StartArgs<MT, KT>& a, bool diag, double* diag_out) {
+  if constexpr (sizeof(KT) == 8) {
+    if (a.sp.rate || a.sp.src >= 0)
+      return diag ? start_go_<D, MT, KT, V, true, true>(p, a, diag_out)
+                  : start_go_<D, MT, KT, V, false, true>(p, a, diag_out);
+  }
+  return diag ? start_go_<D, MT, KT, V, true, false>(p, a, diag_out)
+              : start_go_<D, MT, KT, V, false, false>(p, a, diag_out);
 }
 
 // The split step (no local solve): a V-wide pass and a V = 1 tail pass, no diagnostics.
 template <int D, typename MT, int V>
-hipError_t bdf2_split_go(const tfs_plan_s* p, Bdf2Args<MT> a) {
+hipError_t bdf2_split_go(const tfs_plan_s* p, Bdf2Args<MT, double> a) {
   const int64_t full = p->npoints / V, rest = p->npoints - full * V;
   if (full > 0) {
     a.p_begin = 0;
     a.ngroups = full;
     a.part0 = 0;
-    hipLaunchKernelGGL((bdf2_kernel<D, MT, V, false, false, true>), dim3(grid_for(p, full)), dim3(kBlock), 0,
+    hipLaunchKernelGGL((bdf2_kernel<D, MT, double, V, false, false, true>), dim3(grid_for(p, full)), dim3(kBlock), 0,
                        p->stream, a);
   }
   if (rest > 0) {
     a.p_begin = full * V;
     a.ngroups = rest;
     a.part0 = 0;
-    hipLaunchKernelGGL((bdf2_kernel<D, MT, 1, false, false, true>), dim3(grid_for(p, rest)), dim3(kBlock), 0,
+    hipLaunchKernelGGL((bdf2_kernel<D, MT, double, 1, false, false, true>), dim3(grid_for(p, rest)), dim3(kBlock), 0,
                        p->stream, a);
   }
   return hipGetLastError();
@@ -750,11 +807,12 @@ hipError_t bdf2_split_go(const tfs_plan_s* p, Bdf2Args<MT> a) {
 template <int D, typename MT>
 hipError_t bdf2_split_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
                                double* G) {
-  Bdf2Args<MT> a;
+  Bdf2Args<MT, double> a;
   a.ka = ka;
   a.kb = kb;
   a.Xn = L.Xn;
   a.Xm = L.Xm;
+  a.Xmm = nullptr;
   a.Xo = L.Xo;
   a.Yn = static_cast<const MT*>(L.Yn);
   a.Ym = static_cast<const MT*>(L.Ym);
@@ -773,7 +831,7 @@ hipError_t bdf2_split_dispatch(const tfs_plan_s* p, int64_t n, const double* ka,
   a.s.inv_De = 1.0 / p->De;
   a.s.zeta = p->zeta[n + 1];
   a.s.tau_scale = p->tau_scale;
-  const int V = pick_vec<D, MT>(p, ka, kb, L, G);
+  const int V = pick_vec<D, MT, double>(p, ka, kb, L, G);
   if constexpr (sizeof(MT) == 4) {
     if (V == 4) return bdf2_split_go<D, MT, 4>(p, a);
   }
@@ -781,10 +839,10 @@ hipError_t bdf2_split_dispatch(const tfs_plan_s* p, int64_t n, const double* ka,
   return bdf2_split_go<D, MT, 1>(p, a);
 }
 
-template <int D, typename MT>
-hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, const Levels& L, double* tau, double* diag) {
-  StartArgs<MT> a;
-  a.ka = ka;
+template <int D, typename MT, typename KT>
+hipError_t start_dispatch(const tfs_plan_s* p, const void* ka, const Levels& L, double* tau, double* diag) {
+  StartArgs<MT, KT> a;
+  a.ka = static_cast<const KT*>(ka);
   a.X0 = L.Xn;
   a.X1 = L.Xo;
   a.Y0 = static_cast<MT*>(L.Ym0);
@@ -795,6 +853,7 @@ hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, const Levels& L
   a.stride = p->stride;
   a.tile = p->tile;
   a.m = p->m;
+  a.zform = p->zform ? 1 : 0;
   a.s.hgt = p->hg * p->theta;
   a.sp.rate = p->sp_rate;
   a.sp.src = p->sp_source;
@@ -805,54 +864,55 @@ hipError_t start_dispatch(const tfs_plan_s* p, const double* ka, const Levels& L
   a.s.gamma = p->gamma;
   a.s.theta = p->theta;
   a.s.hr = p->hr;
-  const int V = pick_vec<D, MT>(p, ka, nullptr, L, tau);
+  const int V = pick_vec<D, MT, KT>(p, ka, nullptr, L, tau);
   const bool dg = diag != nullptr;
   if constexpr (sizeof(MT) == 4) {
-    if (V == 4) return start_go<D, MT, 4>(p, a, dg, diag);
+    if (V == 4) return start_go<D, MT, KT, 4>(p, a, dg, diag);
   }
-  if (V == 2) return start_go<D, MT, 2>(p, a, dg, diag);
-  return start_go<D, MT, 1>(p, a, dg, diag);
+  if (V == 2) return start_go<D, MT, KT, 2>(p, a, dg, diag);
+  return start_go<D, MT, KT, 1>(p, a, dg, diag);
 }
 
-template <int D, typename MT, int V, bool DIAG, bool SP>
-hipError_t exp_launch(const tfs_plan_s* p, ExpArgs<MT> a, int64_t p_begin, int64_t ngroups, int part0,
+template <int D, typename MT, typename KT, int V, bool DIAG, bool SP>
+hipError_t exp_launch(const tfs_plan_s* p, ExpArgs<MT, KT> a, int64_t p_begin, int64_t ngroups, int part0,
                       int* nblocks) {
   a.p_begin = p_begin;
   a.ngroups = ngroups;
   a.part0 = part0;
   const int grid = grid_for(p, ngroups);
-  hipLaunchKernelGGL((exp_kernel<D, MT, V, DIAG, SP>), dim3(grid), dim3(kBlock), 0, p->stream, a);
+  hipLaunchKernelGGL((exp_kernel<D, MT, KT, V, DIAG, SP>), dim3(grid), dim3(kBlock), 0, p->stream, a);
   *nblocks = grid;
   return hipGetLastError();
 }
 
-template <int D, typename MT, int V, bool DIAG, bool SP>
-hipError_t exp_go_(const tfs_plan_s* p, const ExpArgs<MT>& a, double* diag_out) {
+template <int D, typename MT, typename KT, int V, bool DIAG, bool SP>
+hipError_t exp_go_(const tfs_plan_s* p, const ExpArgs<MT, KT>& a, double* diag_out) {
   const int64_t full = p->npoints / V, rest = p->npoints - full * V;
   int nb = 0, nt = 0;
   hipError_t e = hipSuccess;
-  if (full > 0) e = exp_launch<D, MT, V, DIAG, SP>(p, a, 0, full, 0, &nb);
-  if (e == hipSuccess && rest > 0) e = exp_launch<D, MT, 1, DIAG, SP>(p, a, full * V, rest, nb, &nt);
+  if (full > 0) e = exp_launch<D, MT, KT, V, DIAG, SP>(p, a, 0, full, 0, &nb);
+  if (e == hipSuccess && rest > 0) e = exp_launch<D, MT, KT, 1, DIAG, SP>(p, a, full * V, rest, nb, &nt);
   if (e == hipSuccess && DIAG)
     hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, a.part, nb + nt, diag_out);
   return e == hipSuccess ? hipGetLastError() : e;
 }
 
-template <int D, typename MT, bool SP>
-hipError_t exp_go(const tfs_plan_s* p, const ExpArgs<MT>& a, int V, double* diag) {
+template <int D, typename MT, typename KT, bool SP>
+hipError_t exp_go(const tfs_plan_s* p, const ExpArgs<MT, KT>& a, int V, double* diag) {
   if constexpr (sizeof(MT) == 4 && D == 2) {
-    if (V == 4) return diag ? exp_go_<D, MT, 4, true, SP>(p, a, diag) : exp_go_<D, MT, 4, false, SP>(p, a, diag);
+    if (V == 4)
+      return diag ? exp_go_<D, MT, KT, 4, true, SP>(p, a, diag) : exp_go_<D, MT, KT, 4, false, SP>(p, a, diag);
   }
-  if (V == 2) return diag ? exp_go_<D, MT, 2, true, SP>(p, a, diag) : exp_go_<D, MT, 2, false, SP>(p, a, diag);
-  return diag ? exp_go_<D, MT, 1, true, SP>(p, a, diag) : exp_go_<D, MT, 1, false, SP>(p, a, diag);
+  if (V == 2) return diag ? exp_go_<D, MT, KT, 2, true, SP>(p, a, diag) : exp_go_<D, MT, KT, 2, false, SP>(p, a, diag);
+  return diag ? exp_go_<D, MT, KT, 1, true, SP>(p, a, diag) : exp_go_<D, MT, KT, 1, false, SP>(p, a, diag);
 }
 
-template <int D, typename MT>
-hipError_t exp_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+template <int D, typename MT, typename KT>
+hipError_t exp_dispatch(const tfs_plan_s* p, int64_t n, const void* ka, const void* kb, const Levels& L,
                         double* tau, double* diag) {
-  ExpArgs<MT> a;
-  a.ka = ka;
-  a.kb = (n >= 1) ? kb : nullptr;
+  ExpArgs<MT, KT> a;
+  a.ka = static_cast<const KT*>(ka);
+  a.kb = (n >= 1) ? static_cast<const KT*>(kb) : nullptr;
   a.Xn = L.Xn;
   a.Xo = L.Xo;
   a.Yn = static_cast<const MT*>(L.Yn);
@@ -880,26 +940,28 @@ hipError_t exp_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const 
   Levels A = L;
   A.Ym = nullptr;
   // two compensated sums per component: in 3-D four points per lane would spill
-  const int V = pick_vec<D, MT>(p, ka, a.kb, A, tau, D == 3 ? 2 : 4);
-  if (a.sp.rate || a.sp.src >= 0) return exp_go<D, MT, true>(p, a, V, diag);
-  return exp_go<D, MT, false>(p, a, V, diag);
+  const int V = pick_vec<D, MT, KT>(p, ka, a.kb, A, tau, D == 3 ? 2 : 4);
+  if constexpr (sizeof(KT) == 8) {
+    if (a.sp.rate || a.sp.src >= 0) return exp_go<D, MT, KT, true>(p, a, V, diag);
+  }
+  return exp_go<D, MT, KT, false>(p, a, V, diag);
 }
 
 // The split exponential step (no local solve): a V-wide pass and a V = 1 tail pass.
 template <int D, typename MT, int V>
-hipError_t exp_split_go(const tfs_plan_s* p, ExpArgs<MT> a) {
+hipError_t exp_split_go(const tfs_plan_s* p, ExpArgs<MT, double> a) {
   const int64_t full = p->npoints / V, rest = p->npoints - full * V;
   a.part0 = 0;
   if (full > 0) {
     a.p_begin = 0;
     a.ngroups = full;
-    hipLaunchKernelGGL((exp_kernel<D, MT, V, false, false, true>), dim3(grid_for(p, full)), dim3(kBlock), 0,
+    hipLaunchKernelGGL((exp_kernel<D, MT, double, V, false, false, true>), dim3(grid_for(p, full)), dim3(kBlock), 0,
                        p->stream, a);
   }
   if (rest > 0) {
     a.p_begin = full * V;
     a.ngroups = rest;
-    hipLaunchKernelGGL((exp_kernel<D, MT, 1, false, false, true>), dim3(grid_for(p, rest)), dim3(kBlock), 0,
+    hipLaunchKernelGGL((exp_kernel<D, MT, double, 1, false, false, true>), dim3(grid_for(p, rest)), dim3(kBlock), 0,
                        p->stream, a);
   }
   return hipGetLastError();
@@ -908,7 +970,7 @@ hipError_t exp_split_go(const tfs_plan_s* p, ExpArgs<MT> a) {
 template <int D, typename MT>
 hipError_t exp_split_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
                               double* G, double* H) {
-  ExpArgs<MT> a;
+  ExpArgs<MT, double> a;
   a.ka = ka;
   a.kb = (n >= 1) ? kb : nullptr;
   a.Xn = L.Xn;
@@ -936,7 +998,7 @@ hipError_t exp_split_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, 
   a.s.first = n == 0 ? 1 : 0;
   Levels A = L;
   A.Ym = nullptr;
-  int V = pick_vec<D, MT>(p, ka, a.kb, A, G, D == 3 ? 2 : 4);
+  int V = pick_vec<D, MT, double>(p, ka, a.kb, A, G, D == 3 ? 2 : 4);
   if (!aligned(H, (size_t)V * 8)) V = 1;
   if constexpr (sizeof(MT) == 4 && D == 2) {
     if (V == 4) return exp_split_go<D, MT, 4>(p, a);
@@ -950,17 +1012,22 @@ hipError_t exp_split_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, 
 // a V-wide pass and a V = 1 tail pass
 int max_blocks(const tfs_plan_s* p) { return 2 * p->num_cus * kMaxBlocksPerCU; }
 
-hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+// The plan's (dim, mode precision, kappa precision) instance of a dispatcher; FP32 velocity
+// gradients exist only with FP32 modes.
+#define TFS_DISPATCH(fn, ...)                                                                      \
+  (p->precision == TFS_FP64                                                                        \
+       ? (p->d == 2 ? fn<2, double, double>(__VA_ARGS__) : fn<3, double, double>(__VA_ARGS__))    \
+       : p->kappa_f32                                                                              \
+             ? (p->d == 2 ? fn<2, float, float>(__VA_ARGS__) : fn<3, float, float>(__VA_ARGS__))  \
+             : (p->d == 2 ? fn<2, float, double>(__VA_ARGS__) : fn<3, float, double>(__VA_ARGS__)))
+
+hipError_t launch_bdf2(const tfs_plan_s* p, int64_t n, const void* ka, const void* kb, const Levels& L,
                        double* tau, double* diag) {
   if (p->npoints == 0) {
     if (diag) hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, p->d_part, 0, diag);
     return hipGetLastError();
   }
-  if (p->precision == TFS_FP64)
-    return p->d == 2 ? bdf2_dispatch<2, double>(p, n, ka, kb, L, tau, diag)
-                     : bdf2_dispatch<3, double>(p, n, ka, kb, L, tau, diag);
-  return p->d == 2 ? bdf2_dispatch<2, float>(p, n, ka, kb, L, tau, diag)
-                   : bdf2_dispatch<3, float>(p, n, ka, kb, L, tau, diag);
+  return TFS_DISPATCH(bdf2_dispatch, p, n, ka, kb, L, tau, diag);
 }
 
 hipError_t launch_bdf2_split(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
@@ -973,29 +1040,21 @@ hipError_t launch_bdf2_split(const tfs_plan_s* p, int64_t n, const double* ka, c
                    : bdf2_split_dispatch<3, float>(p, n, ka, kb, L, G);
 }
 
-hipError_t launch_startup(const tfs_plan_s* p, const double* ka, const Levels& L, double* tau, double* diag) {
+hipError_t launch_startup(const tfs_plan_s* p, const void* ka, const Levels& L, double* tau, double* diag) {
   if (p->npoints == 0) {
     if (diag) hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, p->d_part, 0, diag);
     return hipGetLastError();
   }
-  if (p->precision == TFS_FP64)
-    return p->d == 2 ? start_dispatch<2, double>(p, ka, L, tau, diag)
-                     : start_dispatch<3, double>(p, ka, L, tau, diag);
-  return p->d == 2 ? start_dispatch<2, float>(p, ka, L, tau, diag)
-                   : start_dispatch<3, float>(p, ka, L, tau, diag);
+  return TFS_DISPATCH(start_dispatch, p, ka, L, tau, diag);
 }
 
-hipError_t launch_exp(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
+hipError_t launch_exp(const tfs_plan_s* p, int64_t n, const void* ka, const void* kb, const Levels& L,
                       double* tau, double* diag) {
   if (p->npoints == 0) {
     if (diag) hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(kBlock), 0, p->stream, p->d_part, 0, diag);
     return hipGetLastError();
   }
-  if (p->precision == TFS_FP64)
-    return p->d == 2 ? exp_dispatch<2, double>(p, n, ka, kb, L, tau, diag)
-                     : exp_dispatch<3, double>(p, n, ka, kb, L, tau, diag);
-  return p->d == 2 ? exp_dispatch<2, float>(p, n, ka, kb, L, tau, diag)
-                   : exp_dispatch<3, float>(p, n, ka, kb, L, tau, diag);
+  return TFS_DISPATCH(exp_dispatch, p, n, ka, kb, L, tau, diag);
 }
 
 hipError_t launch_exp_split(const tfs_plan_s* p, int64_t n, const double* ka, const double* kb, const Levels& L,
@@ -1008,22 +1067,24 @@ hipError_t launch_exp_split(const tfs_plan_s* p, int64_t n, const double* ka, co
                    : exp_split_dispatch<3, float>(p, n, ka, kb, L, G, H);
 }
 
-hipError_t launch_modes_to_plain(const tfs_plan_s* p, int slot, const double* X, const void* Y, double* Xk) {
+hipError_t launch_modes_to_plain(const tfs_plan_s* p, int64_t level, const double* X, const void* Y, double* Xk) {
   if (p->npoints == 0) return hipSuccess;
-  const int64_t st = p->stride;
-  const double* Xs = X + (int64_t)slot * p->c * st;
-  if (p->scheme == TFS_SCHEME_EXP) slot = 0;   // one mode level, paired with X slot `slot`
+  const int64_t st = p->stride, xs = (int64_t)p->c * st;
+  const double* Xs = X + (level % p->xlev) * xs;
+  const double* Xm = (p->zform && level >= 1) ? X + ((level - 1) % p->xlev) * xs : nullptr;
+  const int slot = p->scheme == TFS_SCHEME_EXP ? 0 : (int)(level % 2);   // the exponential scheme keeps one level
   const int64_t total = (int64_t)p->m * p->c * p->npoints;
   int grid = (int)((total + kBlock - 1) / kBlock);
   if (grid > 65536) grid = 65536;
+  const int zf = p->zform ? 1 : 0;
   if (p->precision == TFS_FP64) {
     const double* Ys = static_cast<const double*>(Y) + (int64_t)slot * p->m * p->c * st;
-    hipLaunchKernelGGL(plain_kernel<double>, dim3(grid), dim3(kBlock), 0, p->stream, Xs, Ys, p->d_coef, Xk,
-                       p->npoints, st, p->tile, p->m, p->c);
+    hipLaunchKernelGGL(plain_kernel<double>, dim3(grid), dim3(kBlock), 0, p->stream, Xs, Xm, Ys, p->d_coef, Xk,
+                       p->npoints, st, p->tile, p->m, p->c, zf);
   } else {
     const float* Ys = static_cast<const float*>(Y) + (int64_t)slot * p->m * p->c * st;
-    hipLaunchKernelGGL(plain_kernel<float>, dim3(grid), dim3(kBlock), 0, p->stream, Xs, Ys, p->d_coef, Xk,
-                       p->npoints, st, p->tile, p->m, p->c);
+    hipLaunchKernelGGL(plain_kernel<float>, dim3(grid), dim3(kBlock), 0, p->stream, Xs, Xm, Ys, p->d_coef, Xk,
+                       p->npoints, st, p->tile, p->m, p->c, zf);
   }
   return hipGetLastError();
 }

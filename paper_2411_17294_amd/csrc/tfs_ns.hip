@@ -475,6 +475,7 @@ tfs_status tfs_ns_step(tfs_ns s, tfs_plan p, int64_t n, double* u, void* uh, voi
   if (!u || !uh || !fh || !kappa || !X || !Y || !tau) return set_error(TFS_EINVAL, "null field pointer");
   tfs_status st = check_plan(s, p);
   if (st != TFS_OK) return st;
+  if (p->kappa_f32) return set_error(TFS_EUNSUPPORTED, "the coupled step writes FP64 velocity gradients");
   if (n < 0 || n >= p->max_steps) return set_error(TFS_EINVAL, "step index out of range");
   hipStream_t stream = p->stream;
   if ((st = set_streams(s, stream)) != TFS_OK) return st;

@@ -1019,6 +1019,8 @@ tfs_status tfs_transport_step(tfs_transport s, tfs_plan p, int64_t n, const doub
     return set_error(TFS_EINVAL, "plan does not match the transport object (dim, npoints, stride)");
   if (p->device != s->device) return set_error(TFS_EINVAL, "plan and transport object live on different devices");
   if (p->sp_rate || p->sp_source >= 0) return set_error(TFS_EUNSUPPORTED, "transport steps need a pointwise plan");
+  if (p->kappa_f32) return set_error(TFS_EUNSUPPORTED, "transport steps take FP64 velocity gradients");
+  if (p->zform) return set_error(TFS_EUNSUPPORTED, "transport steps keep the modes in the Y form (TFS_MODE_FORM_Y)");
   if (n < 0 || n >= p->max_steps) return set_error(TFS_EINVAL, "step index out of range");
   if (!kappa_a || !u_a || !X || !Y || !tau) return set_error(TFS_EINVAL, "null kappa_a, u_a, X, Y or tau");
   if (kappa_b && !u_b) return set_error(TFS_EINVAL, "u_b is needed with kappa_b");

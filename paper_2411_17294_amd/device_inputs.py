@@ -1,9 +1,8 @@
 """Device-side synthesis of the seeded inputs (plumbing, not the method).
 
 Evaluates the same divergence-free Fourier velocity-gradient field as
-``inputs.FourierField.kappa_at`` on the whole grid with torch FP64 operations,
-chunked over points, and lays out X0 in the X ring.  No part of the update runs
-here.
+``inputs.FourierField.kappa_at`` on the whole grid with the library's field kernel
+(tfs_field_eval), and lays out X0 in the X ring.  No part of the update runs here.
 """
 from __future__ import annotations
 
@@ -13,53 +12,50 @@ import numpy as np
 import torch
 
 from . import inputs as I
+from . import tfs
 
 
 class DeviceKappa:
-    """kappa(x, t) of a FourierField on a full periodic grid, written into [d*d][stride] tensors."""
+    """kappa(x, t) of a FourierField on a periodic grid (or a slab of consecutive grid points
+    from flat index `offset`), written into [d*d][stride] device tensors by the library's field
+    evaluation (tfs_field_eval: every term's phase and sine and the sums in FP64, rounded once
+    to the tensor's precision, FP64 or FP32).  The evaluation runs through a one-mode plan per
+    (stride, precision) that serves only this purpose."""
 
-    def __init__(self, ff: I.FourierField, grid: int, npoints: int, device="cuda", chunk=1 << 22, offset=0):
+    def __init__(self, ff: I.FourierField, grid: int, npoints: int, device="cuda", offset=0):
         self.ff = ff
         self.grid = grid
         self.dim = ff.dim
         self.npoints = npoints
         self.offset = int(offset)   # first flat grid index (a slab of the grid)
         self.device = device
-        self.chunk = chunk
-        self.k = torch.tensor(ff.k.T.astype(np.float64), device=device)                    # [d, NF]
-        self.B = torch.tensor(ff.coef().reshape(len(ff.amp), ff.dim * ff.dim), device=device)  # [NF, d*d]
-        self.phase = torch.tensor(ff.phase, device=device)
-        self.omega = torch.tensor(ff.omega, device=device)
-        # k . x + phase of every point, kept when it fits one chunk (slabs evaluated at many t)
-        self.theta0 = self._theta0(0, npoints) if npoints <= chunk else None
+        self._plans = {}
 
-    def _theta0(self, p0, p1):
-        d, g = self.dim, self.grid
-        flat = torch.arange(self.offset + p0, self.offset + p1, device=self.device, dtype=torch.int64)
-        idx = torch.empty((p1 - p0, d), device=self.device, dtype=torch.float64)
-        r = flat.clone()
-        for a in range(d):
-            idx[:, a] = (r % g).to(torch.float64)
-            r = r // g
-        return (idx * (2.0 * math.pi / g)) @ self.k + self.phase[None, :]
+    def _plan(self, stride, dtype):
+        key = (stride, dtype)
+        if key not in self._plans:
+            f32 = dtype == torch.float32
+            p = tfs.Plan(self.dim, self.npoints, [1.0], [0.0], 1.0, 1.0, 0.0, 1.0, 1,
+                         precision="fp32_modes" if f32 else "fp64", stride=stride, tile=0,
+                         kappa="fp32" if f32 else "fp64")
+            p.set_field(*self.ff.table(self.grid, self.offset))
+            self._plans[key] = p
+        return self._plans[key]
 
     def fill(self, out: torch.Tensor, t: float):
-        """out: [d*d][stride] FP64; column j gets grid point offset + j, j < npoints."""
-        if self.theta0 is not None:
-            out[:, :self.npoints] = (torch.sin(self.theta0 + self.omega[None, :] * t) @ self.B).T
-            return out
-        for p0 in range(0, self.npoints, self.chunk):
-            p1 = min(self.npoints, p0 + self.chunk)
-            theta = self._theta0(p0, p1) + self.omega[None, :] * t
-            out[:, p0:p1] = (torch.sin(theta) @ self.B).T
+        """out: [d*d][stride] FP64 or FP32; column j gets grid point offset + j, j < npoints."""
+        if out.dim() != 2 or out.shape[0] != self.dim * self.dim or out.shape[1] < self.npoints:
+            raise ValueError("out must be [d*d][stride >= npoints]")
+        self._plan(int(out.shape[1]), out.dtype).field_eval(t, out)
         return out
 
 
-def x0_ring(wl: I.Workload, stride: int, device="cuda", points=None):
-    """X ring [2][c][stride] with X0 of workload wl in slot 0 (all points, or the given subset)."""
+def x0_ring(wl: I.Workload, stride: int, device="cuda", points=None, levels=2):
+    """X ring [levels][c][stride] with X0 of workload wl in slot 0 (all points, or the given
+    subset); levels is the plan's x_levels."""
     X0 = I.initial_state(wl, points)
     P = X0.shape[1]
-    X = torch.zeros((2, wl.c, stride), dtype=torch.float64, device=device)
+    X = torch.zeros((levels, wl.c, stride), dtype=torch.float64, device=device)
     X[0, :, :P] = torch.from_numpy(X0).to(device)
     return X
 

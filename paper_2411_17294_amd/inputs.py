@@ -101,6 +101,11 @@ class FourierField:
         """[NF, d, d] coefficient B_n,ij = -A_n e_n,i k_n,j of sin(theta_n) in kappa_ij."""
         return -(self.amp[:, None, None] * self.e[:, :, None] * self.k[:, None, :])
 
+    def table(self, grid: int, point0: int = 0) -> tuple:
+        """(k, phase, omega, coef, grid, point0): the field as tfs_plan_set_field takes it,
+        on the grid of `grid` points per axis with the plan's point 0 at flat index point0."""
+        return (self.k.astype(np.float64), self.phase, self.omega, self.coef(), int(grid), int(point0))
+
     def kappa_at(self, idx: np.ndarray, grid: int, t: float) -> np.ndarray:
         """kappa at the grid points with multi-indices idx [P, d] and time t -> [d*d, P] fp64."""
         d = self.dim

@@ -19,11 +19,13 @@ LIB_PATH = os.path.join(_HERE, "libtfs.so")
 TFS_OK, TFS_EINVAL, TFS_ENOMEM, TFS_EHIP, TFS_ENUMERIC, TFS_EUNSUPPORTED = range(6)
 TFS_FP64, TFS_FP32_MODES = 0, 1
 TFS_SCHEME_BDF2, TFS_SCHEME_EXP = 0, 1
+TFS_KAPPA_FP64, TFS_KAPPA_FP32 = 0, 1
+TFS_MODE_FORM_AUTO, TFS_MODE_FORM_Y, TFS_MODE_FORM_Z = 0, 1, 2
 TFS_FLAG_CHECK_SYNC = 1
 
 EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
-           "tfs_step_levels", "tfs_step_adjoint", "tfs_plan_set_field", "tfs_run_fused", "tfs_pbar_size", "tfs_pbar_to_params", "tfs_pbar_rate_gradient",
-           "tfs_modes_to_plain",
+           "tfs_step_levels", "tfs_step_adjoint", "tfs_plan_set_field", "tfs_field_eval", "tfs_run_fused", "tfs_pbar_size", "tfs_pbar_to_params", "tfs_pbar_rate_gradient",
+           "tfs_modes_to_plain", "tfs_plan_x_levels",
            "tfs_plan_tables", "tfs_plan_stride", "tfs_plan_tile", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
            "tfs_status_string", "tfs_last_error",
            "tfs_ns_create", "tfs_ns_destroy", "tfs_ns_spectral_size", "tfs_ns_batched", "tfs_ns_set_batched", "tfs_ns_set_transport", "tfs_ns_init",
@@ -50,7 +52,7 @@ class PlanDesc(C.Structure):
                 ("alpha", C.c_double), ("De", C.c_double), ("eta_p", C.c_double), ("dt", C.c_double),
                 ("max_steps", C.c_int64), ("w", C.POINTER(C.c_double)), ("lam", C.POINTER(C.c_double)),
                 ("precision", C.c_int32), ("flags", C.c_uint32), ("stream", C.c_void_p),
-                ("scheme", C.c_int32)]
+                ("scheme", C.c_int32), ("kappa_precision", C.c_int32), ("mode_form", C.c_int32)]
 
 
 class FieldDesc(C.Structure):
@@ -78,14 +80,17 @@ def lib():
     L.tfs_plan_set_spatial.argtypes = [vp, vp, i64]
     L.tfs_plan_set_field.argtypes = [vp, C.POINTER(FieldDesc)]
     L.tfs_run_fused.argtypes = [vp, i64, i64, vp, vp, vp]
+    L.tfs_field_eval.argtypes = [vp, C.c_double, vp, vp]
     L.tfs_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
-    L.tfs_step_levels.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
-    L.tfs_step_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.tfs_step_levels.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.tfs_step_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.tfs_pbar_size.argtypes = [vp]
     L.tfs_pbar_size.restype = i64
-    L.tfs_pbar_to_params.argtypes = [vp, dp, dp, dp, dp, dp]
+    L.tfs_pbar_to_params.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp]
     L.tfs_pbar_rate_gradient.argtypes = [vp, dp, dp]
-    L.tfs_modes_to_plain.argtypes = [vp, i32, vp, vp, vp]
+    L.tfs_modes_to_plain.argtypes = [vp, i64, vp, vp, vp]
+    L.tfs_plan_x_levels.argtypes = [vp]
+    L.tfs_plan_x_levels.restype = i32
     L.tfs_plan_tables.argtypes = [vp, dp, dp, dp]
     L.tfs_plan_stride.argtypes = [vp]
     L.tfs_plan_stride.restype = i64
@@ -118,7 +123,7 @@ def lib():
     L.tfs_ns_init.argtypes = [vp, vp, vp, vp, vp]
     L.tfs_ns_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     for name in ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
-                 "tfs_step_levels", "tfs_plan_set_field", "tfs_run_fused",
+                 "tfs_step_levels", "tfs_plan_set_field", "tfs_field_eval", "tfs_run_fused",
                  "tfs_step_adjoint", "tfs_pbar_to_params", "tfs_pbar_rate_gradient", "tfs_modes_to_plain",
                  "tfs_plan_tables", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
                  "tfs_ns_create", "tfs_ns_destroy", "tfs_ns_set_batched", "tfs_ns_set_transport", "tfs_ns_init", "tfs_ns_step",
@@ -170,7 +175,7 @@ class Plan:
     """One tfs_plan: dim, m, npoints, parameters and the (w, lambda) table."""
 
     def __init__(self, dim, npoints, w, lam, alpha, De, eta_p, dt, max_steps, precision="fp64",
-                 stride=0, tile=None, flags=0, stream=None, scheme="bdf2"):
+                 stride=0, tile=None, flags=0, stream=None, scheme="bdf2", kappa="fp64", mode_form="auto"):
         import torch
         self.dim = int(dim)
         self.c = self.dim * (self.dim + 1) // 2
@@ -183,6 +188,10 @@ class Plan:
         self.precision = {"fp64": TFS_FP64, "fp32_modes": TFS_FP32_MODES}[precision] \
             if isinstance(precision, str) else int(precision)
         self.mode_dtype = torch.float64 if self.precision == TFS_FP64 else torch.float32
+        # storage precision of the velocity gradients the steps read (kappabar stays FP64)
+        self.kappa_precision = {"fp64": TFS_KAPPA_FP64, "fp32": TFS_KAPPA_FP32}[kappa] \
+            if isinstance(kappa, str) else int(kappa)
+        self.kappa_dtype = torch.float32 if self.kappa_precision == TFS_KAPPA_FP32 else torch.float64
         self.scheme = {"bdf2": TFS_SCHEME_BDF2, "exp": TFS_SCHEME_EXP}[scheme] \
             if isinstance(scheme, str) else int(scheme)
         # mode levels the caller keeps: a two-slot ring (BDF2) or one level updated in place
@@ -193,12 +202,16 @@ class Plan:
             tile = default_tile(self.dim, self.precision)
         d = PlanDesc(self.dim, self.m, self.npoints, int(stride), int(tile), self.alpha, self.De, self.eta_p, self.dt,
                      self.max_steps, _dptr(self.w), _dptr(self.lam), self.precision, int(flags),
-                     C.c_void_p(stream), self.scheme)
+                     C.c_void_p(stream), self.scheme, self.kappa_precision,
+                     {"auto": TFS_MODE_FORM_AUTO, "y": TFS_MODE_FORM_Y, "z": TFS_MODE_FORM_Z}[mode_form]
+                     if isinstance(mode_form, str) else int(mode_form))
         h = C.c_void_p()
         check(lib().tfs_plan_create(C.byref(d), C.byref(h)))
         self._h = h
         self.stride = int(lib().tfs_plan_stride(h))
         self.tile = int(lib().tfs_plan_tile(h))
+        # slots of the X ring and of the adjoint's Xbar ring (3 for the shifted mode form)
+        self.x_levels = int(lib().tfs_plan_x_levels(h))
 
     @property
     def handle(self):
@@ -240,12 +253,21 @@ class Plan:
         desc = FieldDesc(nf, int(grid), int(point0), _dptr(k), _dptr(ph), _dptr(om), _dptr(cf))
         check(lib().tfs_plan_set_field(self._h, C.byref(desc)))
 
+    def field_eval(self, t, out, add=None):
+        """out [d*d][stride] (kappa_dtype) = the plan's field at time t (+ add, FP64) (tfs_field_eval)."""
+        import torch
+        n = self.dim * self.dim * self.stride
+        self._need(out, "kappa_out", n, self.kappa_dtype)
+        self._need(add, "add", n, torch.float64)
+        check(lib().tfs_field_eval(self._h, float(t), _tptr(add), _tptr(out)))
+        return out
+
     def run_fused(self, n0, nsteps, X, Y, tau=None):
         """Levels n0 -> n0 + nsteps in one launch, kappa from the plan's field (tfs_run_fused)."""
         import torch
         if self.npoints > 0:
             st, c = self.stride, self.c
-            self._need(X, "X", 2 * c * st, torch.float64)
+            self._need(X, "X", self.x_levels * c * st, torch.float64)
             self._need(Y, "Y", self.mode_levels * self.m * c * st, self.mode_dtype)
             self._need(tau, "tau", c * st, torch.float64)
         check(lib().tfs_run_fused(self._h, int(n0), int(nsteps), _tptr(X), _tptr(Y), _tptr(tau)))
@@ -255,10 +277,11 @@ class Plan:
 
     # -- buffers -------------------------------------------------------------------------
     def alloc(self, device="cuda"):
-        """Zeroed X ring, Y ring (flat, in the plan's tiled layout), tau and diag tensors."""
+        """Zeroed X ring ([x_levels][c][stride]), Y ring (flat, in the plan's tiled layout), tau and
+        diag tensors."""
         import torch
         st = self.stride
-        X = torch.zeros((2, self.c, st), dtype=torch.float64, device=device)
+        X = torch.zeros((self.x_levels, self.c, st), dtype=torch.float64, device=device)
         Y = torch.zeros((self.mode_levels * self.m * self.c * st,), dtype=self.mode_dtype, device=device)
         tau = torch.zeros((self.c, st), dtype=torch.float64, device=device)
         diag = torch.zeros(6, dtype=torch.float64, device=device)
@@ -278,61 +301,75 @@ class Plan:
         import torch
         if self.npoints > 0:
             st, c, d = self.stride, self.c, self.dim
-            self._need(kappa_a, "kappa_a", d * d * st, torch.float64)
-            self._need(kappa_b, "kappa_b", d * d * st, torch.float64)
-            self._need(X, "X", 2 * c * st, torch.float64)
+            self._need(kappa_a, "kappa_a", d * d * st, self.kappa_dtype)
+            self._need(kappa_b, "kappa_b", d * d * st, self.kappa_dtype)
+            self._need(X, "X", self.x_levels * c * st, torch.float64)
             self._need(Y, "Y", self.mode_levels * self.m * c * st, self.mode_dtype)
             self._need(tau, "tau", c * st, torch.float64)
         self._need(diag, "diag", 6, torch.float64)
         check(lib().tfs_step(self._h, int(n), _tptr(kappa_a), _tptr(kappa_b), _tptr(X), _tptr(Y), _tptr(tau),
                              _tptr(diag)))
 
-    def step_levels(self, n, kappa_a, kappa_b, X_n, X_nm1, X_out, Y_n, Y_nm1, Y_out, tau=None, diag=None):
+    def step_levels(self, n, kappa_a, kappa_b, X_n, X_nm1, X_out, Y_n, Y_nm1, Y_out, tau=None, diag=None,
+                    X_nm2=None):
+        """tfs_step_levels; X_nm2 (level n-2) is read by shifted-mode-form plans at n >= 2."""
         import torch
         if self.npoints > 0:
             st, c, d = self.stride, self.c, self.dim
             for t, nm in ((kappa_a, "kappa_a"), (kappa_b, "kappa_b")):
-                self._need(t, nm, d * d * st, torch.float64)
-            for t, nm in ((X_n, "X_n"), (X_nm1, "X_nm1"), (X_out, "X_out"), (tau, "tau")):
+                self._need(t, nm, d * d * st, self.kappa_dtype)
+            for t, nm in ((X_n, "X_n"), (X_nm1, "X_nm1"), (X_nm2, "X_nm2"), (X_out, "X_out"), (tau, "tau")):
                 self._need(t, nm, c * st, torch.float64)
             for t, nm in ((Y_n, "Y_n"), (Y_nm1, "Y_nm1"), (Y_out, "Y_out")):
                 self._need(t, nm, self.m * c * st, self.mode_dtype)
         self._need(diag, "diag", 6, torch.float64)
         check(lib().tfs_step_levels(self._h, int(n), _tptr(kappa_a), _tptr(kappa_b), _tptr(X_n), _tptr(X_nm1),
-                                    _tptr(X_out), _tptr(Y_n), _tptr(Y_nm1), _tptr(Y_out), _tptr(tau), _tptr(diag)))
+                                    _tptr(X_nm2), _tptr(X_out), _tptr(Y_n), _tptr(Y_nm1), _tptr(Y_out), _tptr(tau),
+                                    _tptr(diag)))
 
     @property
     def pbar_size(self):
         return int(lib().tfs_pbar_size(self._h))
 
     def step_adjoint(self, n, kappa_a, kappa_b, X_n, X_nm1, X_np1, Y_n, Y_nm1, Xbar, Hbar, pbar,
-                     taubar=None, kappabar_a=None, kappabar_b=None):
+                     taubar=None, kappabar_a=None, kappabar_b=None, X_nm2=None):
+        """tfs_step_adjoint; X_nm2 (forward level n-2) is read by shifted-mode-form plans at n >= 2,
+        whose Xbar ring has x_levels = 3 slots."""
         import torch
         if self.npoints > 0:
             st, c, d = self.stride, self.c, self.dim
-            for t, nm in ((kappa_a, "kappa_a"), (kappa_b, "kappa_b"), (kappabar_a, "kappabar_a"),
-                          (kappabar_b, "kappabar_b")):
+            for t, nm in ((kappa_a, "kappa_a"), (kappa_b, "kappa_b")):
+                self._need(t, nm, d * d * st, self.kappa_dtype)
+            for t, nm in ((kappabar_a, "kappabar_a"), (kappabar_b, "kappabar_b")):
                 self._need(t, nm, d * d * st, torch.float64)
-            for t, nm in ((X_n, "X_n"), (X_nm1, "X_nm1"), (X_np1, "X_np1"), (taubar, "taubar")):
+            for t, nm in ((X_n, "X_n"), (X_nm1, "X_nm1"), (X_nm2, "X_nm2"), (X_np1, "X_np1"), (taubar, "taubar")):
                 self._need(t, nm, c * st, torch.float64)
             for t, nm in ((Y_n, "Y_n"), (Y_nm1, "Y_nm1")):
                 self._need(t, nm, self.m * c * st, self.mode_dtype)
-            self._need(Xbar, "Xbar", 2 * c * st, torch.float64)
+            self._need(Xbar, "Xbar", self.x_levels * c * st, torch.float64)
             self._need(Hbar, "Hbar", self.mode_levels * self.m * c * st, self.mode_dtype)
         self._need(pbar, "pbar", self.pbar_size, torch.float64)
         check(lib().tfs_step_adjoint(self._h, int(n), _tptr(kappa_a), _tptr(kappa_b), _tptr(X_n), _tptr(X_nm1),
-                                     _tptr(X_np1), _tptr(Y_n), _tptr(Y_nm1), _tptr(Xbar), _tptr(Hbar),
+                                     _tptr(X_nm2), _tptr(X_np1), _tptr(Y_n), _tptr(Y_nm1), _tptr(Xbar), _tptr(Hbar),
                                      _tptr(taubar), _tptr(kappabar_a), _tptr(kappabar_b), _tptr(pbar)))
 
-    def pbar_to_params(self, pbar_host):
-        """(dL/dw [m], dL/dlambda [m], dL/dDe, dL/deta_p) from a host copy of pbar."""
+    def pbar_to_params(self, pbar_host, dw_dalpha=None, dlambda_dalpha=None):
+        """(dL/dw [m], dL/dlambda [m], dL/dDe, dL/deta_p, dL/dalpha) from a host copy of pbar;
+        dL/dalpha (chained in the library) is None unless the rule's derivatives are given."""
         pb = np.ascontiguousarray(pbar_host, dtype=np.float64)
         if pb.size < self.pbar_size:
             raise ValueError("pbar too short")
         dw, dl = np.zeros(self.m), np.zeros(self.m)
-        dDe, dep = C.c_double(0.0), C.c_double(0.0)
-        check(lib().tfs_pbar_to_params(self._h, _dptr(pb), _dptr(dw), _dptr(dl), C.pointer(dDe), C.pointer(dep)))
-        return dw, dl, dDe.value, dep.value
+        dDe, dep, da = C.c_double(0.0), C.c_double(0.0), C.c_double(0.0)
+        want_a = dw_dalpha is not None and dlambda_dalpha is not None
+        dwa = np.ascontiguousarray(dw_dalpha, dtype=np.float64) if want_a else None
+        dla = np.ascontiguousarray(dlambda_dalpha, dtype=np.float64) if want_a else None
+        if want_a and (dwa.size != self.m or dla.size != self.m):
+            raise ValueError("dw/dalpha and dlambda/dalpha need m entries")
+        check(lib().tfs_pbar_to_params(self._h, _dptr(pb), _dptr(dwa) if want_a else None,
+                                       _dptr(dla) if want_a else None, _dptr(dw), _dptr(dl), C.pointer(dDe),
+                                       C.pointer(dep), C.pointer(da) if want_a else None))
+        return dw, dl, dDe.value, dep.value, (da.value if want_a else None)
 
     def pbar_rate_gradient(self, pbar_host):
         """sum_p rate_p dL/drate_p of the spatial form (eps dL/deps for rate = eps |xi|^2)."""
@@ -343,20 +380,22 @@ class Plan:
         check(lib().tfs_pbar_rate_gradient(self._h, _dptr(pb), C.pointer(out)))
         return out.value
 
-    def modes_to_plain(self, slot, X, Y, out):
+    def modes_to_plain(self, level, X, Y, out):
+        """Plain modes of time level `level` from the X and mode rings (tfs_modes_to_plain)."""
         import torch
         st, c = self.stride, self.c
-        self._need(X, "X", 2 * c * st, torch.float64)
+        self._need(X, "X", self.x_levels * c * st, torch.float64)
         self._need(Y, "Y", self.mode_levels * self.m * c * st, self.mode_dtype)
         self._need(out, "out", self.m * c * st, torch.float64)
-        check(lib().tfs_modes_to_plain(self._h, int(slot), _tptr(X), _tptr(Y), _tptr(out)))
+        check(lib().tfs_modes_to_plain(self._h, int(level), _tptr(X), _tptr(Y), _tptr(out)))
 
     def kappa_tensor(self, kappa=None, device="cuda"):
-        """[d*d][stride] FP64 device tensor, optionally filled from a host [d*d][npoints] array."""
+        """[d*d][stride] device tensor in the plan's kappa precision, optionally filled from a
+        host [d*d][npoints] array (rounded to that precision)."""
         import torch
-        t = torch.zeros((self.dim * self.dim, self.stride), dtype=torch.float64, device=device)
+        t = torch.zeros((self.dim * self.dim, self.stride), dtype=self.kappa_dtype, device=device)
         if kappa is not None:
-            t[:, :self.npoints] = torch.as_tensor(np.ascontiguousarray(kappa)).to(device)
+            t[:, :self.npoints] = torch.as_tensor(np.ascontiguousarray(kappa)).to(device).to(self.kappa_dtype)
         return t
 
     def tables(self):

@@ -26,3 +26,15 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _release_device_memory():
+    """Return cached device memory after each test: the full-size runs need most of the
+    device, and a test's tensors are garbage once it ends."""
+    yield
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_available() and torch.cuda.is_initialized():
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()

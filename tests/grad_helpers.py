@@ -81,10 +81,10 @@ def oracle_spatial_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, rat
                              extrap=True, scheme="bdf2"):
     """Complex-step gradients of the spatial form in the Fourier layout, from the pointwise
     oracle: a point of rate r follows the pointwise scheme with 1/De -> 1/De + r at the same
-    eta_p/De, without the mass-mode source (a run from X0 minus a run from 0) unless it is the
-    source point or no source point is set (source < 0).  Points of equal rate and source
-    flag run together.  Returns the keys of oracle_gradients (no alpha) plus "rate" =
-    sum_p rate_p dL/drate_p.  scheme: "bdf2" (SDIRK2 start) or "exp"."""
+    eta_p/De, without the mass mode and its source (mass 0) unless it is the source point or
+    no source point is set (source < 0).  Points of equal rate and source flag run together.
+    Returns the keys of oracle_gradients (no alpha) plus "rate" = sum_p rate_p dL/drate_p.
+    scheme: "bdf2" (SDIRK2 start) or "exp"."""
     wts = pack_weights(d)[:, None]
     startup = "exp" if scheme == "exp" else "sdirk2"
     P = X0.shape[1]
@@ -110,11 +110,8 @@ def oracle_spatial_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, rat
             xc = x0.astype(complex) + (1j * H_CS * dX0 if dX0 is not None else 0)
             wc = np.asarray(w, complex) + (1j * H_CS * dwv if dwv is not None else 0)
             lc = np.asarray(lam, complex) + (1j * H_CS * dlv if dlv is not None else 0)
-            t = O.run_complex(d, wc, lc, Dx, ex, dt, N, kc, xc, extrap=extrap, startup=startup)["tau"]
-            if not src:
-                t = t - O.run_complex(d, wc, lc, Dx, ex, dt, N, kc, np.zeros_like(xc), extrap=extrap,
-                                      startup=startup)["tau"]
-            return t
+            return O.run_complex(d, wc, lc, Dx, ex, dt, N, kc, xc, extrap=extrap, startup=startup,
+                                 mass=1.0 if src else 0.0)["tau"]
 
         base = tau().real
         resid = base - tg
@@ -141,14 +138,17 @@ def oracle_spatial_gradients(d, w, lam, De, eta_p, dt, N, kappa, X0, target, rat
 
 
 def gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precision="fp64", tile=None,
-                  dw_da=None, dl_da=None, extrap=True, tune=None, scheme="bdf2", spatial=None):
+                  dw_da=None, dl_da=None, extrap=True, tune=None, scheme="bdf2", spatial=None, kappa_prec="fp64",
+                  mode_form="auto"):
     """Forward + adjoint on the GPU; kappa steady [d*d][P] or levels [nlev][d*d][P].
     tune: {key: value} passed to tfs_plan_tune (e.g. points per lane).
     spatial: (rate [P], source point) of the spatial form (tfs_plan_set_spatial); the result
-    then carries "rate" = sum_p rate_p dL/drate_p."""
+    then carries "rate" = sum_p rate_p dL/drate_p.
+    kappa_prec: "fp32" stores the velocity gradients in FP32 (FP32-mode plans)."""
     P = X0.shape[1]
     c = d * (d + 1) // 2
-    plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, max(N, 1), precision=precision, tile=tile, scheme=scheme)
+    plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, max(N, 1), precision=precision, tile=tile, scheme=scheme,
+                    kappa=kappa_prec, mode_form=mode_form)
     exp = scheme == "exp"
     for key, value in (tune or {}).items():
         plan.tune(key, value)
@@ -176,13 +176,13 @@ def gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precisi
             plan.step_levels(n, ka, kb, Xs[n], None, Xs[n + 1], Ys[n] if n >= 1 else None, None, Ys[n + 1], tau)
             continue
         plan.step_levels(n, ka, kb, Xs[n], Xs[n - 1] if n >= 1 else None, Xs[n + 1], Ys[n] if n >= 1 else None,
-                         Ys[n - 1] if n >= 1 else Ys[0], Ys[n + 1], tau)
+                         Ys[n - 1] if n >= 1 else Ys[0], Ys[n + 1], tau, X_nm2=Xs[n - 2] if n >= 2 else None)
     torch.cuda.synchronize()
     tau_h = tau[:, :P].cpu().numpy()
     wts = pack_weights(d)[:, None]
     taubar = torch.zeros((c, st), dtype=torch.float64, device=dev)
     taubar[:, :P] = torch.from_numpy(wts * (tau_h - target)).to(dev)
-    Xbar = torch.zeros((2, c, st), dtype=torch.float64, device=dev)
+    Xbar = torch.zeros((plan.x_levels, c, st), dtype=torch.float64, device=dev)
     Hbar = torch.zeros((plan.mode_levels * m * c * st,), dtype=mt, device=dev)
     pbar = torch.zeros(plan.pbar_size, dtype=torch.float64, device=dev)
     kbar = torch.zeros((d * d, st), dtype=torch.float64, device=dev)
@@ -194,14 +194,15 @@ def gpu_gradients(d, w, lam, alpha, De, eta_p, dt, N, kappa, X0, target, precisi
             continue
         plan.step_adjoint(n, ka, kb, Xs[n], Xs[n - 1] if n >= 1 else None, Xs[n + 1], Ys[n] if n >= 1 else None,
                           Ys[n - 1] if n >= 1 else None, Xbar, Hbar, pbar,
-                          taubar=taubar if n == N - 1 else None, kappabar_a=kbar, kappabar_b=kbar)
+                          taubar=taubar if n == N - 1 else None, kappabar_a=kbar, kappabar_b=kbar,
+                          X_nm2=Xs[n - 2] if n >= 2 else None)
     torch.cuda.synchronize()
     pb = pbar.cpu().numpy()
-    gw, gl, gDe, gep = plan.pbar_to_params(pb)
+    gw, gl, gDe, gep, ga = plan.pbar_to_params(pb, dw_da, dl_da)
     out = {"loss": loss(tau_h, target, d), "tau": tau_h, "kappa": kbar[:, :P].cpu().numpy(),
            "X0": Xbar[0, :, :P].cpu().numpy(), "De": gDe, "eta_p": gep, "w": gw, "lam": gl}
     if spatial is not None:
         out["rate"] = plan.pbar_rate_gradient(pb)
     if dw_da is not None:
-        out["alpha"] = float(np.dot(gw, dw_da) + np.dot(gl, dl_da))
+        out["alpha"] = ga
     return out

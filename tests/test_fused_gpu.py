@@ -26,7 +26,8 @@ def field_of(wl_id, steady):
 
 def make_plan(d, P, m, prec, dt, N, alpha=0.5, De=1.0, eta_p=0.1, scheme="exp"):
     w, lam, _ = osoe.soe_fit(alpha, m, dt, dt * N * 10)
-    plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, N, precision=prec, scheme=scheme)
+    # fused launches keep the modes in the Y form
+    plan = tfs.Plan(d, P, w, lam, alpha, De, eta_p, dt, N, precision=prec, scheme=scheme, mode_form="y")
     return plan, w, lam
 
 
@@ -70,9 +71,9 @@ def stepwise_run(plan, kap_levels, X0, N):
     return X, Y, tau
 
 
-def plain_modes(plan, X, Y, slot):
+def plain_modes(plan, X, Y, level):
     o = torch.zeros((plan.m, plan.c, plan.stride), dtype=torch.float64, device="cuda")
-    plan.modes_to_plain(slot, X, Y, o)
+    plan.modes_to_plain(level, X, Y, o)
     torch.cuda.synchronize()
     return o[:, :, :plan.npoints].cpu().numpy()
 
@@ -99,9 +100,9 @@ def test_fused_matches_oracle_and_stepwise_path(d, prec, m, grid, steady, chunks
     o = O.run(d, w, lam, 1.0, 0.1, dt, N, kl, X0, startup="exp", want_modes=True)
     bar = 1e-12 if prec == "fp64" else 1e-5
     got = {"X": np.stack([X[N % 2, :, :P].cpu().numpy(), X[(N - 1) % 2, :, :P].cpu().numpy()]),
-           "tau": tau[:, :P].cpu().numpy(), "modes": plain_modes(plan, X, Y, N % 2)}
+           "tau": tau[:, :P].cpu().numpy(), "modes": plain_modes(plan, X, Y, N)}
     step = {"X": np.stack([Xs[N % 2, :, :P].cpu().numpy(), Xs[(N - 1) % 2, :, :P].cpu().numpy()]),
-            "tau": taus[:, :P].cpu().numpy(), "modes": plain_modes(plan, Xs, Ys, N % 2)}
+            "tau": taus[:, :P].cpu().numpy(), "modes": plain_modes(plan, Xs, Ys, N)}
     errs = {k: relerr(got[k], o[k][0] if k == "modes" else o[k]) for k in got}
     errs_step = {k: relerr(got[k], step[k]) for k in got}
     print(d, prec, m, steady, chunks, "oracle", errs, "stepwise", errs_step, flush=True)
@@ -126,7 +127,7 @@ def test_fused_full_size_128cube_sampled():
     sel = torch.from_numpy(sample).cuda()
     ex = relerr(X[N % 2][:, sel].cpu().numpy(), o["X"][0])
     et = relerr(tau[:, sel].cpu().numpy(), o["tau"])
-    em = relerr(plain_modes(plan, X, Y, N % 2)[:, :, sample], o["modes"][0])
+    em = relerr(plain_modes(plan, X, Y, N)[:, :, sample], o["modes"][0])
     print("128^3 fused sample", ex, et, em, flush=True)
     assert ex < 1e-5 and et < 1e-5 and em < 1e-5
 
@@ -182,10 +183,10 @@ def test_fused_bdf2_matches_oracle_and_stepwise_path(d, prec, m, grid, steady, c
     bar = 1e-12 if prec == "fp64" else 1e-5
     got = {"X": np.stack([X[N % 2, :, :P].cpu().numpy(), X[(N - 1) % 2, :, :P].cpu().numpy()]),
            "tau": tau[:, :P].cpu().numpy(),
-           "modes": np.stack([plain_modes(plan, X, Y, N % 2), plain_modes(plan, X, Y, (N - 1) % 2)])}
+           "modes": np.stack([plain_modes(plan, X, Y, N), plain_modes(plan, X, Y, N - 1)])}
     step = {"X": np.stack([Xs[N % 2, :, :P].cpu().numpy(), Xs[(N - 1) % 2, :, :P].cpu().numpy()]),
             "tau": taus[:, :P].cpu().numpy(),
-            "modes": np.stack([plain_modes(plan, Xs, Ys, N % 2), plain_modes(plan, Xs, Ys, (N - 1) % 2)])}
+            "modes": np.stack([plain_modes(plan, Xs, Ys, N), plain_modes(plan, Xs, Ys, N - 1)])}
     errs = {k: relerr(got[k], o[k]) for k in got}
     errs_step = {k: relerr(got[k], step[k]) for k in got}
     print("bdf2", d, prec, m, steady, chunks, "oracle", errs, "stepwise", errs_step, flush=True)

@@ -28,7 +28,8 @@ def run_spectral(grid, eps, d, w, lam, De, eta_p, dt, N, kap_levels, X0_grid, pr
     plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=precision, scheme=scheme)
     st = plan.stride
     plan.set_spatial(grid.rate(eps, st), grid.source_point)
-    X = torch.zeros((2, c, st), dtype=torch.float64, device="cuda")
+    XL = plan.x_levels
+    X = torch.zeros((XL, c, st), dtype=torch.float64, device="cuda")
     Y = torch.zeros((plan.mode_levels * plan.m * c * st,), dtype=plan.mode_dtype, device="cuda")
     tau = torch.zeros((c, st), dtype=torch.float64, device="cuda")
     X[0, :, :P] = grid.to_points(torch.from_numpy(X0_grid).cuda())
@@ -47,15 +48,15 @@ def run_spectral(grid, eps, d, w, lam, De, eta_p, dt, N, kap_levels, X0_grid, pr
             ka, kb = kl[n + 1], None
         plan.step(n, ka, kb, X, Y, tau)
         if traj:
-            path.append(grid.to_grid(X[(n + 1) % 2, :, :P]).cpu().numpy())
+            path.append(grid.to_grid(X[(n + 1) % XL, :, :P]).cpu().numpy())
     torch.cuda.synchronize()
-    out = {"X": np.stack([grid.to_grid(X[N % 2, :, :P]).cpu().numpy(),
-                          grid.to_grid(X[(N - 1) % 2, :, :P]).cpu().numpy()]),
+    out = {"X": np.stack([grid.to_grid(X[N % XL, :, :P]).cpu().numpy(),
+                          grid.to_grid(X[(N - 1) % XL, :, :P]).cpu().numpy()]),
            "tau": grid.to_grid(tau[:, :P]).cpu().numpy(), "plan": plan}
     if want_modes:
         m = plan.m
         o = torch.zeros((m, c, st), dtype=torch.float64, device="cuda")
-        plan.modes_to_plain(N % 2, X, Y, o)
+        plan.modes_to_plain(N, X, Y, o)
         out["modes"] = grid.to_grid(o[:, :, :P]).cpu().numpy()
     if traj:
         out["traj"] = np.stack(path)
@@ -112,21 +113,15 @@ def test_spectral_step_time_varying_kappa(extrap):
 
 def pointwise_coefficient(d, w, lam, De, eta_p, dt, N, kd, x0, rate, source, scheme):
     """One coefficient of the layout by the pointwise oracle: 1/De -> 1/De + rate at the same
-    eta_p/De; without the mass-mode source (a run from x0 minus a run from 0) unless the
-    coefficient is the constant function's.  Returns (X, tau) and the scale of each (the
-    largest magnitude among the runs combined: the difference of two runs is only known to
-    the rounding of the larger one)."""
+    eta_p/De, with the mass mode (and so its source term) only for the constant function's
+    coefficient (source), and without it (mass 0) for every other one.  Returns (X, tau) and
+    the scale of each."""
     Dx = 1.0 / (1.0 / De + rate)
     one = kd.reshape(d * d, 1)
     st = {"bdf2": "sdirk2", "exp": "exp"}[scheme]
-    r = O.run(d, w, lam, Dx, eta_p * Dx / De, dt, N, one, x0[:, None], startup=st)
+    r = O.run(d, w, lam, Dx, eta_p * Dx / De, dt, N, one, x0[:, None], startup=st, mass=1.0 if source else 0.0)
     rx, rt = r["X"][0][:, 0], r["tau"][:, 0]
-    if source:
-        return rx, rt, np.max(np.abs(rx)), np.max(np.abs(rt))
-    z = O.run(d, w, lam, Dx, eta_p * Dx / De, dt, N, one, np.zeros((x0.size, 1)), startup=st)
-    zx, zt = z["X"][0][:, 0], z["tau"][:, 0]
-    return (rx - zx, rt - zt, max(np.max(np.abs(rx)), np.max(np.abs(zx))),
-            max(np.max(np.abs(rt)), np.max(np.abs(zt))))
+    return rx, rt, np.max(np.abs(rx)), np.max(np.abs(rt))
 
 
 @pytest.mark.parametrize("scheme,d,shape,prec", [("bdf2", 2, (1024, 1024), "fp64"), ("exp", 2, (256, 256), "fp64"),
@@ -146,7 +141,7 @@ def test_large_grid_sampled_coefficients(scheme, d, shape, prec):
     rate = grid.rate(eps, st)
     plan.set_spatial(rate, grid.source_point)
     g = torch.Generator(device="cuda").manual_seed(9)
-    X = torch.zeros((2, c, st), dtype=torch.float64, device="cuda")
+    X = torch.zeros((plan.x_levels, c, st), dtype=torch.float64, device="cuda")
     X[0, :, :P] = torch.randn((c, P), generator=g, device="cuda", dtype=torch.float64) * 0.05
     Y = torch.zeros((plan.mode_levels * plan.m * c * st,), dtype=plan.mode_dtype, device="cuda")
     tau = torch.zeros((c, st), dtype=torch.float64, device="cuda")
@@ -156,7 +151,7 @@ def test_large_grid_sampled_coefficients(scheme, d, shape, prec):
     for n in range(N):
         plan.step(n, kt, kt, X, Y, tau)
     torch.cuda.synchronize()
-    Xg, tg = X[N % 2, :, :P].cpu().numpy(), tau[:, :P].cpu().numpy()
+    Xg, tg = X[N % plan.x_levels, :, :P].cpu().numpy(), tau[:, :P].cpu().numpy()
     rng = np.random.default_rng(1)
     sample = np.unique(np.concatenate([[0, 1, P - 2, P - 1], rng.choice(P, 36, replace=False)]))
     rt = rate.cpu().numpy()
@@ -164,7 +159,7 @@ def test_large_grid_sampled_coefficients(scheme, d, shape, prec):
     for j in sample:
         xo, to, sx, stau = pointwise_coefficient(d, w, lam, De, eta_p, dt, N, kd, X0[:, j], rt[j], j == 0, scheme)
         worst = max(worst, np.max(np.abs(Xg[:, j] - xo)) / sx, np.max(np.abs(tg[:, j] - to)) / stau)
-    bar = 1e-11 if prec == "fp64" else 1e-5
+    bar = 1e-12 if prec == "fp64" else 1e-5
     print(scheme, shape, prec, "worst sampled relative error", worst, flush=True)
     assert worst < bar
 
@@ -216,7 +211,7 @@ def test_set_spatial_validation():
 
 # ---- adjoint of the spatial form (BDF2 after the SDIRK2 start) ---------------------------
 
-ADJ_BAR = {"fp64": 1e-9, "fp32_modes": 1e-5}
+ADJ_BAR = {"fp64": 1e-12, "fp32_modes": 1e-5}
 
 
 def spatial_case(d, P, m, seed, source, dt=2e-3, T=0.05):

@@ -39,7 +39,8 @@ def gpu_run(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, prec="fp64",
         sol.step(n, u, uh, fh, kappa, X, Y, tau)
     torch.cuda.synchronize()
     out = {"u": u[:, :P].cpu().numpy(), "kappa": kappa[:, :P].cpu().numpy(), "tau": tau[:, :P].cpu().numpy(),
-           "X": np.stack([X[N % 2, :, :P].cpu().numpy(), X[(N - 1) % 2, :, :P].cpu().numpy()]) if N else None,
+           "X": np.stack([X[N % plan.x_levels, :, :P].cpu().numpy(),
+                          X[(N - 1) % plan.x_levels, :, :P].cpu().numpy()]) if N else None,
            "uh": uh[N % 2].cpu().numpy(), "plan": plan, "solver": sol}
     return out
 
@@ -203,7 +204,8 @@ def gpu_run_transport(d, shape, extent, nu, w, lam, De, eta_p, dt, N, u0, X0, ep
                       scheme="bdf2"):
     from paper_2411_17294_amd.transport import Transport
     P = int(np.prod(shape))
-    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec, scheme=scheme)
+    # transport steps keep the modes in the Y form
+    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec, scheme=scheme, mode_form="y")
     sol = ns.Solver(plan, shape, extent, nu, dt)
     tr = Transport(plan, shape, extent, eps, iters)
     sol.set_transport(tr)

@@ -27,17 +27,19 @@ MUTATIONS = {
                               "const double b0 = 1.5, b1 = -2.0, b2 = -0.5;", "alpha_one"),
     "eta_k_with_weight": ("const sc etak = lam[k] * dt / (b0 + lam[k] * dt);",
                           "const sc etak = w[k] * dt / (b0 + lam[k] * dt);", "brute_force"),
-    "sdirk_diagonal": ("const double gs = 1.0 - 1.0 / sqrt(2.0);", "const double gs = 0.5;", "sdirk2 or alpha_one"),
+    "sdirk_diagonal": ("const rl gs = 1 - 1 / SQRTR((rl)2);", "const rl gs = 0.5;", "sdirk2 or alpha_one"),
     "recombination_sign": ("terms[k] = w[k] * Pnew[q] - lam[k] * Knew[k * n + q];",
                            "terms[k] = w[k] * Pnew[q] + lam[k] * Knew[k * n + q];", "brute_force or sdirk2"),
     "stage_two_explicit_part": ("E[q] = Pn[q] + dt * (1.0 - gs) * F1[q];", "E[q] = Pn[q];", "sdirk2"),
-    "hermite_map_scale": ("else if (i1 == i2) Phi[r] = Xfull[i1 * d + i1] / sqrt(2.0);",
+    "hermite_map_scale": ("else if (i1 == i2) Phi[r] = Xfull[i1 * d + i1] / SQRTR((rl)2);",
                           "else if (i1 == i2) Phi[r] = Xfull[i1 * d + i1] / 2.0;", "hermite_map or operator"),
     "mode_push_dropped_level": ("Km[k * n + q] = (-(b1 * Kn[k * n + q] + b2 * Km[k * n + q]) + w[k] * dt * rhs[q]) /",
                                 "Km[k * n + q] = (-(b1 * Kn[k * n + q]) + w[k] * dt * rhs[q]) /", "brute_force"),
     "eta_without_b0": ("eta += b0 * w[k] * dt / (b0 + lam[k] * dt);", "eta += w[k] * dt / (b0 + lam[k] * dt);",
                        "alpha_one or brute_force"),
     "no_extrapolation": ("kt[q] = fa * ka[q] + fb * kb[q];", "kt[q] = ka[q];", "time_varying"),
+    "mass_switch_ignored": ("tensor_to_hermite(&h, Xf, mass ? (sc)mass[p] : (sc)1.0, P0);",
+                            "tensor_to_hermite(&h, Xf, (sc)1.0, P0);", "mass_free"),
     # exponential-mode scheme (pins in test_oracle_exp_pins.py)
     "exp_weights_swapped": ("Km[k * n + i] = e * Kn[k * n + i] + w[k] * dt * (a0 * Pn[i] + a1 * rhs[i]);",
                             "Km[k * n + i] = e * Kn[k * n + i] + w[k] * dt * (a1 * Pn[i] + a0 * rhs[i]);",

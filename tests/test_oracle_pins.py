@@ -160,9 +160,12 @@ def test_chi_constants_and_stress_factors():
 
 
 # ---------------------------------------------------------------- alpha = 1: Oldroyd-B
-def _textbook_oldroyd(d, k, De, X0, dt, N):
-    """Textbook SDIRK2 (Alexander) first step + BDF2 for X' = L X + S (packed)."""
+def _textbook_oldroyd(d, k, De, X0, dt, N, source=True):
+    """Textbook SDIRK2 (Alexander) first step + BDF2 for X' = L X + S (packed); without the
+    source S when source is False."""
     L, S = packed_operator(d, k, De)
+    if not source:
+        S = np.zeros_like(S)
     c = I.ncomp(d)
     Id = np.eye(c)
     gs = 1 - 1 / math.sqrt(2)
@@ -189,6 +192,21 @@ def test_alpha_one_is_textbook_bdf2_oldroyd_b(d):
     xt, _ = _textbook_oldroyd(d, k, De, X0, dt, N)
     assert np.max(np.abs(r["X"][0][:, 0] - xt)) < 1e-13 * max(1, np.max(np.abs(xt)))
     assert np.max(np.abs(r["tau"][:, 0] - eta_p / De * xt)) < 1e-13
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_mass_free_point_is_textbook_without_source(d):
+    """A point without the mass mode (mass 0: a non-constant coefficient of the spatial form)
+    follows the same integrator with no source term S = kappa + kappa^T; at alpha = 1 that is
+    textbook SDIRK2 + BDF2 for X' = kappa X + X kappa^T - X/De."""
+    rng = np.random.default_rng(30 + d)
+    k = rng.standard_normal((d, d)) * 0.8
+    De, eta_p, dt, N = 0.7, 0.1, 2e-3, 120
+    X0 = rng.standard_normal(I.ncomp(d)) * 1e-2
+    r = O.run(d, [1.0], [0.0], De, eta_p, dt, N, one_point(k), X0.reshape(-1, 1), mass=0.0)
+    xt, _ = _textbook_oldroyd(d, k, De, X0, dt, N, source=False)
+    assert np.max(np.abs(r["X"][0][:, 0] - xt)) < 1e-13 * max(1, np.max(np.abs(xt)))
+    assert np.max(np.abs(r["tau"][:, 0] - eta_p / De * xt)) < 1e-13 * max(1e-30, np.max(np.abs(eta_p / De * xt)))
 
 
 def test_alpha_one_simple_shear_startup_closed_form():

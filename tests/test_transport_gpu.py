@@ -49,7 +49,8 @@ def gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, e
             method="splitting", want_diag=False, scheme="bdf2"):
     P = int(np.prod(shape))
     c = d * (d + 1) // 2
-    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec, scheme=scheme)
+    # transport steps keep the modes in the Y form
+    plan = tfs.Plan(d, P, w, lam, 0.5, De, eta_p, dt, max(N, 1), precision=prec, scheme=scheme, mode_form="y")
     tr = Transport(plan, shape, extent, eps, iters)
     tr.set_method(method)
     if not batched:
@@ -71,7 +72,7 @@ def gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, prec, e
             tr.step(n, kl[n + 1], None, ul[n + 1], None, X, Y, tau, dg)
     torch.cuda.synchronize()
     o = torch.zeros((plan.m, c, st), dtype=torch.float64, device="cuda")
-    plan.modes_to_plain(N % 2, X, Y, o)
+    plan.modes_to_plain(N, X, Y, o)
     torch.cuda.synchronize()
     return {"X": np.stack([X[N % 2, :, :P].cpu().numpy(), X[(N - 1) % 2, :, :P].cpu().numpy()]),
             "tau": tau[:, :P].cpu().numpy(), "modes": o[:, :, :P].cpu().numpy(),
