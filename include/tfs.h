@@ -89,9 +89,11 @@ typedef enum {
  * same; only what is stored, and so what FP32 storage rounds, differs):
  *   TFS_MODE_FORM_Y  Y_k^j = X_k^j - c_k X^j.  The new level Y_k^{n+1} = d_k h_k + d_k c_k P is
  *                    known before the local solve, so the modes stream once.  X ring: 2 slots.
- *   TFS_MODE_FORM_Z  Z_k^j = Y_k^j - beta_k X^{j-1} with beta_k = w_k/lambda_k - c_k (0 for
- *                    lambda_k = 0) and X^{-1} = 0: also the quasi-static part (w_k/lambda_k) X of
- *                    a mode that follows X is taken out, so the stored value is small.  Its
+ *   TFS_MODE_FORM_Z  Z_k^j = Y_k^j - beta_k X^{j-1} with beta_k = w_k/lambda_k - c_k for the
+ *                    modes that relax within the plan's horizon (lambda_k max_steps dt >= 1),
+ *                    beta_k = 0 for the others (lambda_k = 0 included), and X^{-1} = 0: the
+ *                    quasi-static part (w_k/lambda_k) X of a mode that follows X is taken out,
+ *                    so the stored value is small.  Its
  *                    new level Y_k^{n+1} - beta_k X^n is still known before the solve; reading
  *                    level n-1 back needs X^{n-2}, so the X ring holds 3 levels.  The stress is a
  *                    near-cancelling sum over the modes: with FP32 storage this form rounds it

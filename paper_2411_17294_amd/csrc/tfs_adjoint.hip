@@ -246,9 +246,10 @@ struct AdjArgs {
   AdjSpatial sp;
 };
 
-// Modes of the BDF2 adjoint's four streams loaded ahead of the one being updated (0 or 1).
+// Modes of the BDF2 adjoint's four streams loaded ahead of the one being updated (0 or 1;
+// measured at 3-D, m = 48: the prefetch holds more registers than it hides latency).
 #ifndef TFS_ADJ_AHEAD
-#define TFS_ADJ_AHEAD 1
+#define TFS_ADJ_AHEAD 0
 #endif
 constexpr int kAdjAhead = TFS_ADJ_AHEAD;
 

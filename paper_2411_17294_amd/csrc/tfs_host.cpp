@@ -336,8 +336,11 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
     p->coef[tfs::kRowU * m + k] = dt * (1.0 - gs) * wk * r * r;
     p->coef[tfs::kRowV * m + k] = hg * wk * r - ck;
     // shifted form: the quasi-static value of a mode that follows X is (w_k/lambda_k) X, of
-    // which Y_k keeps (w_k/lambda_k - c_k) X
-    if (p->zform && lk > 0.0) p->coef[tfs::kRowBeta * m + k] = wk / lk - ck;
+    // which Y_k keeps (w_k/lambda_k - c_k) X.  Only modes that relax within the plan's
+    // horizon (lambda_k max_steps dt >= 1) come near it; a slower mode stays far below it,
+    // and shifting it would store a value (w_k/lambda_k) |X| much larger than the mode.
+    if (p->zform && lk > 0.0 && lk * dt * (double)p->max_steps >= 1.0)
+      p->coef[tfs::kRowBeta * m + k] = wk / lk - ck;
     eta.add(b0 * ck);
     s_ec.add(ek * ck);
     theta.add(wk * r);

@@ -111,16 +111,17 @@ def test_spectral_step_time_varying_kappa(extrap):
     assert ex < 1e-12 and et < 1e-12, (ex, et)
 
 
-def pointwise_coefficient(d, w, lam, De, eta_p, dt, N, kd, x0, rate, source, scheme):
+def pointwise_coefficient(d, w, lam, De, eta_p, dt, N, kd, x0, rate, source, scheme, extended=False):
     """One coefficient of the layout by the pointwise oracle: 1/De -> 1/De + rate at the same
     eta_p/De, with the mass mode (and so its source term) only for the constant function's
     coefficient (source), and without it (mass 0) for every other one.  Returns (X, tau) and
-    the scale of each."""
+    the scale of each; extended: the oracle's extended-precision build (results in FP64)."""
     Dx = 1.0 / (1.0 / De + rate)
     one = kd.reshape(d * d, 1)
     st = {"bdf2": "sdirk2", "exp": "exp"}[scheme]
-    r = O.run(d, w, lam, Dx, eta_p * Dx / De, dt, N, one, x0[:, None], startup=st, mass=1.0 if source else 0.0)
-    rx, rt = r["X"][0][:, 0], r["tau"][:, 0]
+    run = O.run_long if extended else O.run
+    r = run(d, w, lam, Dx, eta_p * Dx / De, dt, N, one, x0[:, None], startup=st, mass=1.0 if source else 0.0)
+    rx, rt = r["X"][0][:, 0].astype(np.float64), r["tau"][:, 0].astype(np.float64)
     return rx, rt, np.max(np.abs(rx)), np.max(np.abs(rt))
 
 
@@ -130,7 +131,14 @@ def pointwise_coefficient(d, w, lam, De, eta_p, dt, N, kd, x0, rate, source, sch
 def test_large_grid_sampled_coefficients(scheme, d, shape, prec):
     """A full-size grid in the launch configuration of the benchmark form: 40 sampled
     coefficients (the constant one, the Nyquist corner, random others) against the
-    pointwise oracle run with the coefficient's rate."""
+    pointwise oracle run with the coefficient's rate, each relative to its own scale.
+
+    FP64 bar per coefficient: the extended-precision oracle is the reference and the bar is
+    max(1e-12, 4 e_o), e_o the FP64 oracle's own error there.  A coefficient of rate
+    eps |xi|^2 up to 1.5e5 carries no mass-mode source (Sec. 4.1: L = -eps Laplace - A(kappa)
+    acts on it alone), so its stress is the near-cancelling sum over the modes of a state
+    damped by exp(-rate t): relative to its own scale the FP64 oracle's stress is off by up to
+    2e-10 there, while its X is good to 1e-15."""
     c = d * (d + 1) // 2
     grid = PeriodicGrid(shape, (1.0,) * d)
     P = grid.npoints
@@ -155,13 +163,23 @@ def test_large_grid_sampled_coefficients(scheme, d, shape, prec):
     rng = np.random.default_rng(1)
     sample = np.unique(np.concatenate([[0, 1, P - 2, P - 1], rng.choice(P, 36, replace=False)]))
     rt = rate.cpu().numpy()
-    worst = 0.0
+    worst, worst_ratio = 0.0, 0.0
     for j in sample:
-        xo, to, sx, stau = pointwise_coefficient(d, w, lam, De, eta_p, dt, N, kd, X0[:, j], rt[j], j == 0, scheme)
-        worst = max(worst, np.max(np.abs(Xg[:, j] - xo)) / sx, np.max(np.abs(tg[:, j] - to)) / stau)
-    bar = 1e-12 if prec == "fp64" else 1e-5
-    print(scheme, shape, prec, "worst sampled relative error", worst, flush=True)
-    assert worst < bar
+        args = (d, w, lam, De, eta_p, dt, N, kd, X0[:, j], rt[j], j == 0, scheme)
+        xo, to, sx, stau = pointwise_coefficient(*args)
+        if prec == "fp64":
+            xl, tl, sxl, stl = pointwise_coefficient(*args, extended=True)
+            for gv, ov, lv, sc in ((Xg[:, j], xo, xl, sxl), (tg[:, j], to, tl, stl)):
+                eg = np.max(np.abs(gv - lv)) / sc
+                bar = max(1e-12, 4.0 * np.max(np.abs(ov - lv)) / sc)
+                worst = max(worst, eg)
+                worst_ratio = max(worst_ratio, eg / bar)
+        else:
+            e = max(np.max(np.abs(Xg[:, j] - xo)) / sx, np.max(np.abs(tg[:, j] - to)) / stau)
+            worst = max(worst, e)
+            worst_ratio = max(worst_ratio, e / 1e-5)
+    print(scheme, shape, prec, "worst sampled relative error", worst, "worst error / bar", worst_ratio, flush=True)
+    assert worst_ratio <= 1.0
 
 
 def test_paper_convergence_experiment_on_gpu():
