@@ -288,6 +288,24 @@ tfs_status tfs_step(tfs_plan plan, int64_t n, const void* kappa_a, const void* k
                     double* X, void* Y, double* tau, double* diag);
 
 /*
+ * tfs_step for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same arguments, kernels and results, but
+ * the diagnostics' block partials (the step's only scratch) live in a static device array of the
+ * library, 8192 partials (384 KiB) per device, held until the process ends, instead of the
+ * plan's buffer.  The call allocates and frees nothing.  The array's address on the device is
+ * looked up once per device at tfs_plan_create.
+ * Limit: with diag, the step's launches write up to 2 x CUs x grid_per_cu partials; a plan above
+ * 8192 (more than 16 blocks per CU on a 256-CU device, see tfs_plan_tune) is refused with
+ * TFS_EINVAL before anything is launched.  Without diag it is tfs_step.
+ * Every call on a device shares that device's array (each launch writes the partials it reads
+ * before reading them, so nothing carries over between calls); calls that overlap in time on
+ * one device, on different streams or from different threads, race on it.
+ * Errors: those of tfs_step, and TFS_EHIP if the array's address could not be looked up.
+ */
+tfs_status tfs_step_noalloc(tfs_plan plan, int64_t n, const void* kappa_a, const void* kappa_b,
+                            double* X, void* Y, double* tau, double* diag);
+
+/*
  * tfs_step with explicit time levels instead of the two-slot rings, so that a caller can
  * keep every level (checkpointed recomputation for the adjoint).  Same update, same
  * layouts per level:

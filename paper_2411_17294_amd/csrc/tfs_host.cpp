@@ -432,6 +432,10 @@ tfs_status tfs_plan_create(const tfs_plan_desc* desc, tfs_plan* out) {
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) == hipSuccess && lds > 0)
     p->lds_max = lds;
+  // the static scratch of tfs_step_noalloc on this device; a failed lookup only disables that
+  // entry point
+  p->scratch_err = (int)tfs::scratch_address(p->device, &p->d_scratch);
+  if (p->scratch_err != (int)hipSuccess) p->d_scratch = nullptr;
   e = hipMalloc(&p->d_coef, sizeof(double) * p->coef.size());
   if (e != hipSuccess) { delete p; return fail(TFS_ENOMEM, "coefficient table: %s", hipGetErrorString(e)); }
   e = hipMemcpy(p->d_coef, p->coef.data(), sizeof(double) * p->coef.size(), hipMemcpyHostToDevice);
@@ -742,8 +746,11 @@ tfs_status run_step(tfs_plan p, int64_t n, const void* kappa_a, const void* kapp
 
 }  // namespace
 
-tfs_status tfs_step(tfs_plan p, int64_t n, const void* kappa_a, const void* kappa_b, double* X, void* Y,
-                    double* tau, double* diag) {
+namespace {
+
+// tfs_step with the diagnostics block partials in `part` (null: the plan's buffer).
+tfs_status step_ring(tfs_plan p, int64_t n, const void* kappa_a, const void* kappa_b, double* X, void* Y,
+                     double* tau, double* diag, double* part) {
   if (!p) return fail(TFS_EINVAL, "null plan");
   if (n < 0 || n >= p->max_steps) return fail(TFS_EINVAL, "time level n=%lld outside [0, %lld)",
                                               (long long)n, (long long)p->max_steps);
@@ -752,6 +759,7 @@ tfs_status tfs_step(tfs_plan p, int64_t n, const void* kappa_a, const void* kapp
   const size_t eb = p->precision == TFS_FP64 ? 8 : 4;
   char* Yb = static_cast<char*>(Y);
   tfs::Levels L;
+  L.part = part;
   const int sn = (int)(n % 2), sm = 1 - sn;
   if (p->zform) {
     // three X levels; the mode ring as in the plain form
@@ -793,6 +801,30 @@ tfs_status tfs_step(tfs_plan p, int64_t n, const void* kappa_a, const void* kapp
     L.Yo = Yb + sm * ys * eb;
   }
   return run_step(p, n, kappa_a, kappa_b, L, tau, diag);
+}
+
+}  // namespace
+
+tfs_status tfs_step(tfs_plan p, int64_t n, const void* kappa_a, const void* kappa_b, double* X, void* Y,
+                    double* tau, double* diag) {
+  return step_ring(p, n, kappa_a, kappa_b, X, Y, tau, diag, nullptr);
+}
+
+tfs_status tfs_step_noalloc(tfs_plan p, int64_t n, const void* kappa_a, const void* kappa_b, double* X, void* Y,
+                            double* tau, double* diag) {
+  if (!p) return fail(TFS_EINVAL, "null plan");
+  if (!diag) return step_ring(p, n, kappa_a, kappa_b, X, Y, tau, nullptr, nullptr);
+  if (!p->d_scratch)
+    return fail(TFS_EHIP, "static scratch unavailable on device %d: %s", p->device,
+                hipGetErrorString((hipError_t)p->scratch_err));
+  // a V-wide pass and a tail pass, each of at most num_cus * grid_per_cu blocks
+  const int64_t need = 2 * (int64_t)p->num_cus * p->grid_per_cu;
+  if (need > tfs::kScratchPartials)
+    return fail(TFS_EINVAL,
+                "the step's launches write up to %lld diagnostics partials (2 x %d CUs x grid_per_cu %d); the "
+                "static scratch holds %d: lower grid_per_cu (tfs_plan_tune)",
+                (long long)need, p->num_cus, p->grid_per_cu, tfs::kScratchPartials);
+  return step_ring(p, n, kappa_a, kappa_b, X, Y, tau, diag, p->d_scratch);
 }
 
 tfs_status tfs_step_levels(tfs_plan p, int64_t n, const void* kappa_a, const void* kappa_b, const double* X_n,

@@ -136,6 +136,9 @@ struct tfs_plan_s {
   int* d_dest_bdf2 = nullptr;    // device [3 m + kNumAdjScalars]: pbar index of each partial entry
   int* d_dest_start = nullptr;
   int* d_dest_exp = nullptr;
+  // the calling device's static scratch (tfs_step_noalloc), looked up at plan creation
+  double* d_scratch = nullptr;
+  int scratch_err = 0;        // hipError_t of that lookup
 
   // tuning (tfs_plan_tune): points per lane (0 = widest aligned), blocks per CU cap
   int vec_override = 0;
@@ -166,6 +169,7 @@ struct Levels {
   const void* Ym = nullptr;
   void* Ym0 = nullptr;
   void* Yo = nullptr;
+  double* part = nullptr;       // block partials of the diagnostics (null: the plan's d_part)
 };
 
 // Pointers of one adjoint step.
@@ -213,5 +217,10 @@ hipError_t launch_modes_to_plain(const tfs_plan_s* p, int64_t level, const doubl
 hipError_t launch_field_eval(const tfs_plan_s* p, double t, const double* add, void* out);
 // Upper bound of blocks the launchers use for a plan (sizes d_part).
 int max_blocks(const tfs_plan_s* p);
+// Block partials the static scratch holds (tfs_step_noalloc).
+constexpr int kScratchPartials = 2 * 256 * 16;
+// Device address of the static scratch on the current device, looked up once per device
+// (tfs_kernels.hip).
+hipError_t scratch_address(int device, double** out);
 
 }  // namespace tfs

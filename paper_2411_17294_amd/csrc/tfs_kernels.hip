@@ -25,6 +25,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
+#include <vector>
 
 #include "tfs_device.h"
 #include "tfs_internal.h"
@@ -726,7 +728,7 @@ hipError_t bdf2_dispatch(const tfs_plan_s* p, int64_t n, const void* ka, const v
   a.Yo = static_cast<MT*>(L.Yo);
   a.tau = tau;
   a.coef = p->d_coef;
-  a.part = p->d_part;
+  a.part = L.part ? L.part : p->d_part;
   a.stride = st;
   a.tile = p->tile;
   a.m = p->m;
@@ -849,7 +851,7 @@ hipError_t start_dispatch(const tfs_plan_s* p, const void* ka, const Levels& L, 
   a.Y1 = static_cast<MT*>(L.Yo);
   a.tau = tau;
   a.coef = p->d_coef;
-  a.part = p->d_part;
+  a.part = L.part ? L.part : p->d_part;
   a.stride = p->stride;
   a.tile = p->tile;
   a.m = p->m;
@@ -920,7 +922,7 @@ hipError_t exp_dispatch(const tfs_plan_s* p, int64_t n, const void* ka, const vo
   a.tau = tau;
   a.Hout = nullptr;
   a.coef = p->d_coef;
-  a.part = p->d_part;
+  a.part = L.part ? L.part : p->d_part;
   a.stride = p->stride;
   a.tile = p->tile;
   a.m = p->m;
@@ -1011,6 +1013,30 @@ hipError_t exp_split_dispatch(const tfs_plan_s* p, int64_t n, const double* ka, 
 
 // a V-wide pass and a V = 1 tail pass
 int max_blocks(const tfs_plan_s* p) { return 2 * p->num_cus * kMaxBlocksPerCU; }
+
+// Static scratch of tfs_step_noalloc: the diagnostics block partials of one step (the V-wide
+// pass and the tail pass of a 256-CU device at the default 16 blocks per CU), 384 KiB.  Every
+// device holds its own copy until the process ends.  Host code never passes the symbol itself
+// to a kernel or a copy: only the address scratch_address returns for the device.
+static __device__ __align__(256) double scratch[(size_t)kScratchPartials * kNumDiag];
+
+hipError_t scratch_address(int device, double** out) {
+  static std::mutex mu;
+  static std::vector<double*> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((size_t)device < cache.size() && cache[device]) {
+    *out = cache[device];
+    return hipSuccess;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if ((size_t)device >= cache.size()) cache.resize((size_t)device + 1, nullptr);
+  cache[device] = static_cast<double*>(ptr);
+  *out = cache[device];
+  return hipSuccess;
+}
 
 // The plan's (dim, mode precision, kappa precision) instance of a dispatcher; FP32 velocity
 // gradients exist only with FP32 modes.

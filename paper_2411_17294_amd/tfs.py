@@ -24,7 +24,7 @@ TFS_MODE_FORM_AUTO, TFS_MODE_FORM_Y, TFS_MODE_FORM_Z = 0, 1, 2
 TFS_FLAG_CHECK_SYNC = 1
 
 EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
-           "tfs_step_levels", "tfs_step_adjoint", "tfs_plan_set_field", "tfs_field_eval", "tfs_run_fused", "tfs_pbar_size", "tfs_pbar_to_params", "tfs_pbar_rate_gradient",
+           "tfs_step_noalloc", "tfs_step_levels", "tfs_step_adjoint", "tfs_plan_set_field", "tfs_field_eval", "tfs_run_fused", "tfs_pbar_size", "tfs_pbar_to_params", "tfs_pbar_rate_gradient",
            "tfs_modes_to_plain", "tfs_plan_x_levels",
            "tfs_plan_tables", "tfs_plan_stride", "tfs_plan_tile", "tfs_plan_tune", "tfs_soe_fit", "tfs_soe_gl_log",
            "tfs_status_string", "tfs_last_error",
@@ -82,6 +82,7 @@ def lib():
     L.tfs_run_fused.argtypes = [vp, i64, i64, vp, vp, vp]
     L.tfs_field_eval.argtypes = [vp, C.c_double, vp, vp]
     L.tfs_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+    L.tfs_step_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
     L.tfs_step_levels.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.tfs_step_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.tfs_pbar_size.argtypes = [vp]
@@ -298,6 +299,14 @@ class Plan:
             raise ValueError(f"{name}: {t.numel()} elements, the plan's layout needs {numel}")
 
     def step(self, n, kappa_a, kappa_b, X, Y, tau=None, diag=None):
+        self._step(lib().tfs_step, n, kappa_a, kappa_b, X, Y, tau, diag)
+
+    def step_noalloc(self, n, kappa_a, kappa_b, X, Y, tau=None, diag=None):
+        """tfs_step_noalloc: tfs_step with the diagnostics partials in the library's static
+        device scratch (no device allocation by the call)."""
+        self._step(lib().tfs_step_noalloc, n, kappa_a, kappa_b, X, Y, tau, diag)
+
+    def _step(self, fn, n, kappa_a, kappa_b, X, Y, tau, diag):
         import torch
         if self.npoints > 0:
             st, c, d = self.stride, self.c, self.dim
@@ -307,8 +316,7 @@ class Plan:
             self._need(Y, "Y", self.mode_levels * self.m * c * st, self.mode_dtype)
             self._need(tau, "tau", c * st, torch.float64)
         self._need(diag, "diag", 6, torch.float64)
-        check(lib().tfs_step(self._h, int(n), _tptr(kappa_a), _tptr(kappa_b), _tptr(X), _tptr(Y), _tptr(tau),
-                             _tptr(diag)))
+        check(fn(self._h, int(n), _tptr(kappa_a), _tptr(kappa_b), _tptr(X), _tptr(Y), _tptr(tau), _tptr(diag)))
 
     def step_levels(self, n, kappa_a, kappa_b, X_n, X_nm1, X_out, Y_n, Y_nm1, Y_out, tau=None, diag=None,
                     X_nm2=None):

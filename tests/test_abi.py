@@ -67,6 +67,7 @@ def test_null_arguments_are_rejected():
     h = C.c_void_p()
     assert L.tfs_plan_create(None, C.byref(h)) == tfs.TFS_EINVAL
     assert L.tfs_step(None, 0, None, None, None, None, None, None) == tfs.TFS_EINVAL
+    assert L.tfs_step_noalloc(None, 0, None, None, None, None, None, None) == tfs.TFS_EINVAL
     assert L.tfs_plan_destroy(None) == tfs.TFS_OK
     assert L.tfs_status_string(tfs.TFS_ENUMERIC).decode().startswith("non-finite")
 
