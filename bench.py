@@ -678,7 +678,8 @@ def headline_differentiation(args, stream, wl_id=5):
     tile = 4096 if wl_id == 4 else (None if args.tile < 0 else args.tile)
     p = tfs.Plan(3, P, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision="fp32_modes", kappa="fp32",
                  tile=tile)
-    p.tune("grid_per_cu", args.grid_per_cu)
+    if args.grid_per_cu:
+        p.tune("grid_per_cu", args.grid_per_cu)
     ff = I.fourier_field(wl)
     p.set_field(*ff.table(wl.grid, point0))
     st, c = p.stride, p.c
@@ -791,7 +792,7 @@ def headline_differentiation(args, stream, wl_id=5):
     return out, state
 
 
-def forward_line(stream, wl_id, steps, warmup, form="default", tile=-1, vec=0, grid_per_cu=16, keep_plans=False):
+def forward_line(stream, wl_id, steps, warmup, form="default", tile=-1, vec=0, grid_per_cu=0, keep_plans=False):
     """The forward step of a forward workload (1024^2 FP64 with both alphas, or 256^3) timed on
     its whole grid: all kappa levels resident, one benchmark step advances every field by one
     time level.  The FP32-mode form reads FP32 velocity gradients."""
@@ -818,7 +819,8 @@ def forward_line(stream, wl_id, steps, warmup, form="default", tile=-1, vec=0, g
                      tile=None if tile < 0 else tile, kappa=kp)
         if vec:
             p.tune("vec", vec)
-        p.tune("grid_per_cu", grid_per_cu)
+        if grid_per_cu:
+            p.tune("grid_per_cu", grid_per_cu)
         X = x0_ring(wl, p.stride, levels=p.x_levels)
         _, Y, tau, _ = p.alloc()
         plans.append((alpha, w, lam, p))
@@ -908,7 +910,7 @@ def main():
     ap.add_argument("--form", choices=["default", "fp64", "fp32_modes"], default="default")
     ap.add_argument("--vec", type=int, default=0)
     ap.add_argument("--tile", type=int, default=-1, help="mode-ring tile (points); -1 = library default")
-    ap.add_argument("--grid-per-cu", type=int, default=16)
+    ap.add_argument("--grid-per-cu", type=int, default=0, help="blocks per CU cap; 0 = library default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the 3-D FP32/FP64 and forward+adjoint lines")
     ap.add_argument("--job", type=int, default=0, metavar="STEPS",

@@ -428,11 +428,12 @@ int64_t tfs_plan_tile(tfs_plan plan);
 
 /*
  * Launch tuning; does not change results beyond rounding-order-free choices:
- *   "vec"          points per lane: 0 = widest width the alignment of the fields allows
- *                  (default), or 1, 2 (and 4 for TFS_FP32_MODES); a width the alignment
- *                  does not allow falls back to 1 at launch.
+ *   "vec"          points per lane: 0 = widest width the alignment of the fields allows up
+ *                  to 2 (4 for 2-D TFS_FP32_MODES plans) (default), or 1, 2 (and 4 for
+ *                  TFS_FP32_MODES); a width the alignment does not allow falls back to 1 at launch.
  *   "adj_vec"      points per lane of the BDF2 adjoint: 0 (default: 2 for FP32 modes, 1 for FP64), 1 or 2.
- *   "grid_per_cu"  cap on blocks per compute unit of the grid-stride launches, 1..64.
+ *   "grid_per_cu"  cap on blocks per compute unit of the grid-stride launches, 1..64 (default:
+ *                  1 for TFS_FP64 plans, 16 for TFS_FP32_MODES plans).
  * Note: the diagnostic sum's rounding order depends on the grid; results of X, tau, Y do not.
  */
 tfs_status tfs_plan_tune(tfs_plan plan, const char* key, int64_t value);

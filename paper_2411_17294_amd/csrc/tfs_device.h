@@ -199,7 +199,9 @@ __device__ __forceinline__ WaveAddr wave_addr(int64_t pw, int lane, int64_t T, i
   const int64_t p = pw + (int64_t)lane * V;
   w.pw = pw;
   w.tw = (pw / T) * mcT + pw % T;
-  w.ox = (uint32_t)(lane * V * 8);
+  // opaque: per wave, so that no loop over waves hoists one 64-bit per-lane address per
+  // field plane out of it (they would stay live across the whole kernel)
+  w.ox = opaque((uint32_t)(lane * V * 8));
   w.om = (uint32_t)(((p / T) * mcT + p % T - w.tw) * (int64_t)sizeof(MT));
   return w;
 }

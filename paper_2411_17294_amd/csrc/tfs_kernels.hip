@@ -646,14 +646,16 @@ int grid_for(const tfs_plan_s* p, int64_t ngroups) {
 
 bool aligned(const void* ptr, size_t bytes) { return ptr == nullptr || ((uintptr_t)ptr % bytes) == 0; }
 
-// Points per lane: the requested width, else the widest one (4 for FP32 modes, 2 for
-// FP64: 16-byte mode accesses, fastest on MI355X) for which every plane start and every
-// group start is aligned to the vector size of each field (modes: V * sizeof(MT); the
-// velocity gradient: V * sizeof(KT); the other fields, FP64: V * 8).
+// Points per lane: the requested width, else the widest one (FP64: 2, 16-byte mode accesses;
+// FP32 modes: 4 in 2-D, 2 in 3-D, where 4 points of 6 components hold more registers than
+// two waves per SIMD allow, and two waves of 2 points stream faster on MI355X than one of 4)
+// for which every plane start and every group start is aligned to the vector size of each
+// field (modes: V * sizeof(MT); the velocity gradient: V * sizeof(KT); the other fields,
+// FP64: V * 8).
 template <int D, typename MT, typename KT>
 int pick_vec(const tfs_plan_s* p, const void* k0, const void* k1, const Levels& L, const void* tau,
              int max_v = 4) {
-  const int widest = std::min(max_v, sizeof(MT) == 4 ? 4 : 2);
+  const int widest = std::min(max_v, (sizeof(MT) == 4 && D == 2) ? 4 : 2);
   const int cand[3] = {widest, 2, 1};
   for (int V : cand) {
     if (V > widest) continue;

@@ -57,6 +57,7 @@ def test_noalloc_step_matches_step_twice_second_smaller(d, prec, scheme, kappa):
     # (num_cus * 16) and a tail launch follows; second run: a few hundred points
     for P, seed in ((4 * 256 * 256 * 16 + 13, 5), (389, 6)):
         plan = make_plan(d, P, m, prec, scheme, steps, kappa)
+        plan.tune("grid_per_cu", 16)              # the largest grid the static scratch allows
         print(f"noalloc d={d} {prec} {scheme} kappa {kappa} P={P}", flush=True)
         ka, kb, X0 = inputs(plan, seed)
         ref = run(plan, ka, kb, X0, steps, noalloc=False)
