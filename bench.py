@@ -29,11 +29,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def algorithmic_bytes_per_point(dim, m, mode_bytes, kappa_reads, kappa_bytes=8):
+def algorithmic_bytes_per_point(dim, m, mode_bytes, kappa_reads, kappa_bytes=8, x_levels=2):
     """Minimum HBM traffic of one step per point: two mode levels read and one written,
-    X at two levels read and one written, tau written, kappa read (1 or 2 levels)."""
+    X at x_levels levels read (2; 3 in the shifted mode form) and one written, tau written,
+    kappa read (1 or 2 levels)."""
     c = dim * (dim + 1) // 2
-    return 3 * m * c * mode_bytes + 3 * c * 8 + c * 8 + kappa_reads * dim * dim * kappa_bytes
+    return 3 * m * c * mode_bytes + (x_levels + 1) * c * 8 + c * 8 + kappa_reads * dim * dim * kappa_bytes
 
 
 def log(*a):
@@ -78,12 +79,14 @@ def exp_adjoint_bytes_per_point(dim, m, mode_bytes, kappa_bytes=8):
     return 3 * m * c * mode_bytes + 2 * c * 8 + 2 * c * 8 + 2 * dim * dim * kappa_bytes + 2 * dim * dim * 8
 
 
-def adjoint_bytes_per_point(dim, m, mode_bytes, kappa_bytes=8):
+def adjoint_bytes_per_point(dim, m, mode_bytes, kappa_bytes=8, x_levels=2):
     """Minimum HBM traffic of one adjoint step per point: four mode streams read (H^(n+1),
-    H^(n+2), Y^n, Y^(n-1)) and one written (H^(n)); X at three levels read, the two adjoint
-    X slots read and written; kappa at two levels read and its FP64 adjoint read and written."""
+    H^(n+2), Y^n, Y^(n-1)) and one written (H^(n)); X at x_levels + 1 levels read (n+1, n,
+    n-1 and, in the shifted mode form, n-2), the x_levels adjoint X slots read and written;
+    kappa at two levels read and its FP64 adjoint read and written."""
     c = dim * (dim + 1) // 2
-    return 5 * m * c * mode_bytes + 3 * c * 8 + 4 * c * 8 + 2 * dim * dim * kappa_bytes + 2 * dim * dim * 8
+    return (5 * m * c * mode_bytes + (x_levels + 1) * c * 8 + 2 * x_levels * c * 8 + 2 * dim * dim * kappa_bytes
+            + 2 * dim * dim * 8)
 
 
 def _timed(stream, fn, first, count):
@@ -184,7 +187,7 @@ def _fp32_vs_fp64(stream, steps):
             p.step(n, ka, kb, X, Y, tau)
         ms = _timed(stream, lambda n: p.step(n, ka, kb, X, Y, tau), 4, steps)
         mb = 8 if form == "fp64" else 4
-        nbytes = algorithmic_bytes_per_point(wl.dim, wl.nmodes, mb, 2, mb) * wl.npoints
+        nbytes = algorithmic_bytes_per_point(wl.dim, wl.nmodes, mb, 2, mb, p.x_levels) * wl.npoints
         gbs = nbytes / (ms * 1e-3) / 1e9
         prof = "bdf2_kernel_" + ("fp64_3d_256cube_m40" if form == "fp64" else wl.name)
         res[form] = {"ms_per_step": ms, "point_mode_updates_per_s": wl.npoints * wl.nmodes / (ms * 1e-3),
@@ -226,7 +229,8 @@ def _exp_vs_bdf2(stream, steps):
         for n in range(1, 4):
             p.step(n, ka, kb, X, Y, tau)
         ms = _timed(stream, lambda n: p.step(n, ka, kb, X, Y, tau), 4, steps)
-        bpp = (exp_bytes_per_point if scheme == "exp" else algorithmic_bytes_per_point)(wl.dim, wl.nmodes, 4, 2, 4)
+        bpp = (exp_bytes_per_point(wl.dim, wl.nmodes, 4, 2, 4) if scheme == "exp"
+               else algorithmic_bytes_per_point(wl.dim, wl.nmodes, 4, 2, 4, p.x_levels))
         nbytes = bpp * wl.npoints
         gbs = nbytes / (ms * 1e-3) / 1e9
         kern = "exp_kernel_" if scheme == "exp" else "bdf2_kernel_"
@@ -510,9 +514,9 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
         rb = fb - c * 8 * P
         ab = exp_adjoint_bytes_per_point(wl.dim, m, 4, 4) * P
     else:
-        fb = algorithmic_bytes_per_point(wl.dim, m, 4, 2, 4) * P
+        fb = algorithmic_bytes_per_point(wl.dim, m, 4, 2, 4, p.x_levels) * P
         rb = fb - c * 8 * P            # the recomputation writes no stress
-        ab = adjoint_bytes_per_point(wl.dim, m, 4, 4) * P
+        ab = adjoint_bytes_per_point(wl.dim, m, 4, 4, p.x_levels) * P
     tag = "fp32modes_3d_128cube_m32" if workload == 4 else "fp32modes_3d_384cube_m48_slab"
     kf, ka_ = ("exp_kernel_", "exp_adj_kernel_") if exp else ("bdf2_kernel_", "adj_kernel_")
     parts = {}
@@ -741,10 +745,11 @@ def headline_differentiation(args, stream, wl_id=5):
     if not bool(torch.isfinite(tau[:, :P]).all()) or d[5] != 0 or not d[2] > 0:
         raise SystemExit(f"non-finite or non-positive-definite state in the benchmark run (diag {d})")
     kb = 4
-    nbytes = {"forward": algorithmic_bytes_per_point(3, m, 4, 2, kb) * P,
+    xl = p.x_levels
+    nbytes = {"forward": algorithmic_bytes_per_point(3, m, 4, 2, kb, xl) * P,
               # no stress written by the recomputation
-              "recompute": (algorithmic_bytes_per_point(3, m, 4, 2, kb) - c * 8) * P,
-              "adjoint": adjoint_bytes_per_point(3, m, 4, kb) * P}
+              "recompute": (algorithmic_bytes_per_point(3, m, 4, 2, kb, xl) - c * 8) * P,
+              "adjoint": adjoint_bytes_per_point(3, m, 4, kb, xl) * P}
     kern = {"forward": "bdf2_kernel", "recompute": "bdf2_kernel", "adjoint": "adj_kernel"}
     parts = {}
     for name, lst in evs.items():
@@ -863,8 +868,8 @@ def forward_line(stream, wl_id, steps, warmup, form="default", tile=-1, vec=0, g
             raise SystemExit("non-finite stress in the benchmark run")
     nfields = len(wl.alphas)
     mode_bytes = 8 if form == "fp64" else 4
-    bytes_per_launch = algorithmic_bytes_per_point(wl.dim, wl.nmodes, mode_bytes, 2, 8 if kp == "fp64" else 4) * \
-        wl.npoints
+    bytes_per_launch = algorithmic_bytes_per_point(wl.dim, wl.nmodes, mode_bytes, 2, 8 if kp == "fp64" else 4,
+                                                   plans[0][3].x_levels) * wl.npoints
     avg_launch_s = ms * 1e-3 / (nfields * steps)
     achieved = bytes_per_launch / avg_launch_s / 1e9
     profile = "bdf2_kernel_" + wl.name + ("" if form == wl.precision else "_" + form)
