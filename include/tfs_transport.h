@@ -70,20 +70,24 @@ tfs_status tfs_transport_set_batched(tfs_transport tr, int on);
  * The solver of step 3: method 0 (the default) runs `iters` splitting iterations; method 1
  * runs GMRES on the same preconditioned system (the splitting's fixed-point equation, real
  * inner product over the coefficients) with at most `iters` Arnoldi steps (classical
- * Gram-Schmidt twice) from zero, stopping early at a relative residual of 1e-15.  GMRES
- * converges where the splitting contracts slowly or not at all (strong advection, small
- * eps); it synchronises the stream once per Arnoldi step for the small least-squares
- * problem and keeps iters + 1 basis vectors of 2 c nc doubles (allocated here).
+ * Gram-Schmidt, with a second pass where the first cancels more than half of the vector's
+ * squared norm) from zero, stopping early at a relative residual of 1e-15.  GMRES converges
+ * where the splitting contracts slowly or not at all (strong advection, small eps).  Its
+ * least-squares problem (Hessenberg matrix, Givens rotations, residual test, back
+ * substitution) stays on the device, so the Arnoldi steps are queued without waiting; the
+ * host reads the residual test every `every` steps (tfs_transport_set_tolerance) to stop
+ * early.  It keeps iters + 1 basis vectors of 2 c nc doubles (allocated here).
  * Errors: TFS_EINVAL (null object, unknown method, iters > 256 for GMRES), TFS_ENOMEM.
  */
 tfs_status tfs_transport_set_method(tfs_transport tr, int method);
 
 /*
  * Early exit of the solves: with tol > 0 the splitting stops once an iteration changes the
- * coefficients by at most tol relative to their norm, tested every `every` iterations (one
- * stream synchronisation per test), and GMRES once its relative residual is at most tol;
- * `iters` stays the cap.  tol = 0 (the default) restores the fixed counts (GMRES still stops
- * at 1e-15).  Errors: TFS_EINVAL (null object, tol < 0 or not finite, every < 1).
+ * coefficients by at most tol relative to their norm, and GMRES once its relative residual is
+ * at most tol; both are tested on the host every `every` iterations (one stream
+ * synchronisation per test; the default is 5); `iters` stays the cap.  tol = 0 (the default)
+ * restores the fixed counts (GMRES still stops at 1e-15, seen every `every` steps).
+ * Errors: TFS_EINVAL (null object, tol < 0 or not finite, every < 1).
  */
 tfs_status tfs_transport_set_tolerance(tfs_transport tr, double tol, int every);
 

@@ -44,9 +44,12 @@ struct tfs_transport_s {
   // spectral planes: right-hand side, iterate, fluctuation, extra term, inverse inputs (c + c d)
   double2 *rh = nullptr, *xh = nullptr, *fh = nullptr, *eh = nullptr, *iv = nullptr;
   double *part = nullptr, *mean = nullptr;   // spatial means of kappa~ (d*d) and u~ (d)
-  // GMRES (method 1): Krylov basis [iters + 1][2 c nc] doubles, dot partials, coefficients
+  // GMRES (method 1): Krylov basis [iters + 1][2 c nc] doubles, dot partials, the device-side
+  // state of the least-squares problem (gm_layout) and its flags (kGmFlags ints)
   int method = 0;
   double *basis = nullptr, *dpart = nullptr, *coef = nullptr;
+  int* gflag = nullptr;
+  hipStream_t last_stream = nullptr;   // stream of the last step (for the iteration count)
   // early exit: relative update (splitting) or residual (GMRES) below tol, tested every
   // `every` iterations (tol = 0: fixed counts; GMRES then stops at 1e-15); last_iters: the
   // most iterations one solve of the last step took
@@ -424,9 +427,11 @@ __global__ __launch_bounds__(kTBlock) void start_finish_kernel(const double* X0,
 // Hermitian part of a half spectrum), not over the complex numbers.
 constexpr int kDotBlocks = 512;
 
-// part[k * kDotBlocks + b] = block b's share of <w, V_k>, k < nvec (blockIdx.y = k).
+// part[k * kDotBlocks + b] = block b's share of <w, V_k>, k < gridDim.y (blockIdx.y = k).
+// run: null, or a device flag; the launch does nothing while it is 0.
 __global__ __launch_bounds__(kTBlock) void multi_dot_kernel(const double* V, int64_t nv, const double* w,
-                                                            double* part) {
+                                                            double* part, const int* run) {
+  if (run && *run == 0) return;
   __shared__ double red[kTBlock];
   const double* v = V + (int64_t)blockIdx.y * nv;
   double acc = 0.0;
@@ -449,22 +454,137 @@ __global__ void dot_finish_kernel(const double* part, int nvec, double* out) {
   out[k] = s;
 }
 
-// w -= sum_k coef[k] V_k (k < nvec), or with set: w = sum_k coef[k] V_k.
+// out[k] = the kDotBlocks partials of vector k folded in a fixed order; one block per vector.
+__global__ __launch_bounds__(kTBlock) void dot_fold_kernel(const double* part, double* out, const int* run) {
+  if (run && *run == 0) return;
+  __shared__ double red[kTBlock];
+  const double* q = part + (int64_t)blockIdx.x * kDotBlocks;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < kDotBlocks; b += kTBlock) a += q[b];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int h = kTBlock / 2; h > 0; h /= 2) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// w -= sum_k coef[k] V_k (k < nvec), or with set: w = sum_k coef[k] V_k.  nvec_dev: when not
+// null the count is read from there (the device-side iteration count).
 __global__ __launch_bounds__(kTBlock) void multi_axpy_kernel(const double* V, int64_t nv, int nvec,
-                                                             const double* coef, bool set, double* w) {
+                                                             const int* nvec_dev, const double* coef, bool set,
+                                                             double* w, const int* run) {
+  if (run && *run == 0) return;
+  const int n = nvec_dev ? *nvec_dev : nvec;
   for (int64_t i = (int64_t)blockIdx.x * kTBlock + threadIdx.x; i < nv; i += (int64_t)gridDim.x * kTBlock) {
     double a = 0.0;
-    for (int k = 0; k < nvec; ++k) a = fma(coef[k], V[(int64_t)k * nv + i], a);
+    for (int k = 0; k < n; ++k) a = fma(coef[k], V[(int64_t)k * nv + i], a);
     w[i] = set ? a : w[i] - a;
   }
 }
 
-// out = w / sqrt(nrm2[0]).
+// out = w / sqrt(nrm2[0]), unless the flag skip is set or the norm is zero.
 __global__ __launch_bounds__(kTBlock) void normalize_kernel(const double* w, int64_t nv, const double* nrm2,
-                                                            double* out) {
+                                                            const int* skip, double* out) {
+  if ((skip && *skip != 0) || !(nrm2[0] > 0.0)) return;
   const double f = 1.0 / sqrt(nrm2[0]);
   for (int64_t i = (int64_t)blockIdx.x * kTBlock + threadIdx.x; i < nv; i += (int64_t)gridDim.x * kTBlock)
     out[i] = w[i] * f;
+}
+
+// ---- device-side state of GMRES's least-squares problem (no host round trip per step)
+enum { kGmDone = 0, kGmK = 1, kGmReorth = 2, kGmKmax = 3, kGmFlags = 4 };
+
+struct GmState {
+  double *H, *cs, *sn, *g, *h1, *h2, *y, *nrm;   // nrm: |w'|^2, (unused), beta^2, |w_final|^2
+  int* flag;
+  int m;
+};
+
+// Layout of the state in one buffer of gm_doubles(m) doubles.
+inline int64_t gm_doubles(int m) { return (int64_t)(m + 1) * m + 2 * m + (m + 1) + (m + 2) + (m + 1) + m + 4; }
+
+GmState gm_layout(double* base, int* flag, int m) {
+  GmState S;
+  S.H = base;
+  S.cs = S.H + (int64_t)(m + 1) * m;
+  S.sn = S.cs + m;
+  S.g = S.sn + m;
+  S.h1 = S.g + (m + 1);
+  S.h2 = S.h1 + (m + 2);
+  S.y = S.h2 + (m + 1);
+  S.nrm = S.y + m;
+  S.flag = flag;
+  S.m = m;
+  return S;
+}
+
+// g = (beta, 0, ...); done when the right-hand side is zero (x = 0 is the solution).
+__global__ void gm_start_kernel(GmState S) {
+  if (threadIdx.x != 0) return;
+  const double beta = sqrt(S.nrm[2]);
+  for (int i = 0; i <= S.m; ++i) S.g[i] = 0.0;
+  S.g[0] = beta;
+  S.flag[kGmDone] = beta > 0.0 ? 0 : 1;
+  S.flag[kGmK] = 0;
+  S.flag[kGmReorth] = 0;
+}
+
+// Second Gram-Schmidt pass only where the first lost more than half of |w|^2 (h1[j + 1] holds
+// |w|^2 before it, nrm[0] after): the criterion of Daniel, Gragg, Kaufman and Stewart with
+// eta = 1/sqrt(2).
+__global__ void gm_reorth_kernel(GmState S, int j) {
+  if (threadIdx.x != 0) return;
+  S.flag[kGmReorth] = (S.flag[kGmDone] == 0 && S.nrm[0] < 0.5 * S.h1[j + 1]) ? 1 : 0;
+}
+
+// Column j of the Hessenberg matrix from the projections, the earlier Givens rotations applied
+// to it, a new rotation that zeroes its subdiagonal, and the residual test on g.
+__global__ void gm_column_kernel(GmState S, int j, double tol) {
+  if (threadIdx.x != 0 || S.flag[kGmDone] != 0) return;
+  const int m = S.m;
+  const bool re = S.flag[kGmReorth] != 0;
+  double p2 = 0.0;   // |V h2|^2: what the second pass took off |w'|^2 (V orthonormal, h2 small)
+  for (int i = 0; i <= j; ++i) {
+    S.H[(int64_t)i * m + j] = S.h1[i] + (re ? S.h2[i] : 0.0);
+    if (re) p2 = fma(S.h2[i], S.h2[i], p2);
+  }
+  const double n2 = S.nrm[0] - p2;
+  const double hn = sqrt(n2 > 0.0 ? n2 : 0.0);
+  S.nrm[3] = hn * hn;
+  S.H[(int64_t)(j + 1) * m + j] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = S.H[(int64_t)i * m + j], b = S.H[(int64_t)(i + 1) * m + j];
+    S.H[(int64_t)i * m + j] = S.cs[i] * a + S.sn[i] * b;
+    S.H[(int64_t)(i + 1) * m + j] = -S.sn[i] * a + S.cs[i] * b;
+  }
+  const double a = S.H[(int64_t)j * m + j], b = S.H[(int64_t)(j + 1) * m + j];
+  const double r = hypot(a, b);
+  S.cs[j] = r > 0.0 ? a / r : 1.0;
+  S.sn[j] = r > 0.0 ? b / r : 0.0;
+  S.H[(int64_t)j * m + j] = r;
+  S.H[(int64_t)(j + 1) * m + j] = 0.0;
+  S.g[j + 1] = -S.sn[j] * S.g[j];
+  S.g[j] = S.cs[j] * S.g[j];
+  S.flag[kGmK] = j + 1;
+  if (fabs(S.g[j + 1]) <= tol * sqrt(S.nrm[2]) || hn == 0.0) S.flag[kGmDone] = 1;   // |residual| / beta
+}
+
+// y from the k x k triangle (k = the steps taken) and g; the most steps of the step's solves.
+__global__ void gm_solve_kernel(GmState S) {
+  if (threadIdx.x != 0) return;
+  const int m = S.m, k = S.flag[kGmK];
+  for (int i = k - 1; i >= 0; --i) {
+    double acc = S.g[i];
+    for (int t = i + 1; t < k; ++t) acc -= S.H[(int64_t)i * m + t] * S.y[t];
+    S.y[i] = acc / S.H[(int64_t)i * m + i];
+  }
+  if (k > S.flag[kGmKmax]) S.flag[kGmKmax] = k;
+}
+
+__global__ void gm_reset_kernel(int* flag) {
+  if (threadIdx.x == 0) flag[kGmKmax] = 0;
 }
 
 // part[b] = block b's share of |x - y|^2, part[kDotBlocks + b] of |x|^2.
@@ -726,91 +846,67 @@ tfs_status apply_fluct(tfs_transport_s* s, hipStream_t st, const Lev& L, double 
 }
 
 // GMRES on the preconditioned system (I + P^{-1} F fluct F^{-1}) x = P^{-1} rhs_hat (the
-// splitting iteration's fixed-point equation) from x = 0, s->iters Arnoldi steps (classical
-// Gram-Schmidt, twice), early exit at a relative residual of 1e-15; x into s->xh.
+// splitting iteration's fixed-point equation) from x = 0, at most s->iters Arnoldi steps,
+// early exit at the relative residual s->tol (1e-15 when it is 0); x into s->xh.  Classical
+// Gram-Schmidt, with a second pass where the first cancelled more than half of |w|^2.  The
+// Hessenberg matrix, the Givens rotations, the residual test and the back substitution stay on
+// the device, so an Arnoldi step queues its kernels without waiting; the host reads the
+// residual test's flag every s->every steps to stop queueing (steps queued after convergence
+// change nothing).
 template <int D>
 tfs_status gmres(tfs_transport_s* s, hipStream_t st, const Lev& L, const PrecondArgs& A0) {
   constexpr int C = Sym<D>::C;
   const int64_t nv = (int64_t)2 * C * s->nc;
   const int m = s->iters, bs = blocks_for(s->nc), bv = blocks_for(nv);
   double* V = s->basis;
-  double* w = reinterpret_cast<double*>(s->fh);    // work vector: fh is free between applications
-  double* h = s->coef;                               // device: [m + 2] projections, then y
+  const GmState S = gm_layout(s->coef, s->gflag, m);
+  int* done = s->gflag + kGmDone;
+  int* reorth = s->gflag + kGmReorth;
+  const double tol = s->tol > 0.0 ? s->tol : 1e-15;
   // b' = P^{-1} rhs_hat is in s->xh (precond_kernel); v_0 = b' / |b'|
   const double* bp = reinterpret_cast<const double*>(s->xh);
-  hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, 1), dim3(kTBlock), 0, st, bp, nv, bp, s->dpart);
-  hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(kTBlock), 0, st, s->dpart, 1, h);
-  double beta2 = 0.0;
-  hipError_t e = hipMemcpyAsync(&beta2, h, sizeof(double), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, 1), dim3(kTBlock), 0, st, bp, nv, bp, s->dpart, nullptr);
+  hipLaunchKernelGGL(dot_fold_kernel, dim3(1), dim3(kTBlock), 0, st, s->dpart, S.nrm + 2, nullptr);
+  hipLaunchKernelGGL(gm_start_kernel, dim3(1), dim3(1), 0, st, S);
+  hipLaunchKernelGGL(normalize_kernel, dim3(bv), dim3(kTBlock), 0, st, bp, nv, S.nrm + 2, done, V);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "GMRES start");
-  const double beta = std::sqrt(beta2);
-  if (!(beta > 0.0)) return TFS_OK;                  // zero right-hand side: x = 0 = b'
-  hipLaunchKernelGGL(normalize_kernel, dim3(bv), dim3(kTBlock), 0, st, bp, nv, h, V);
-  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), hc1(m + 1), hc2(m + 1);
-  g[0] = beta;
-  int k = 0;
   for (int j = 0; j < m; ++j) {
     const double2* vj = reinterpret_cast<const double2*>(V + (int64_t)j * nv);
+    double* w = V + (int64_t)(j + 1) * nv;             // the candidate for v_{j+1}, in its slot
     tfs_status r = apply_fluct<D>(s, st, L, A0.b, vj);
     if (r != TFS_OK) return r;
     PrecondArgs A = A0;
     A.fh = s->fh;
     hipLaunchKernelGGL(gm_apply_kernel<D>, dim3(bs), dim3(kTBlock), 0, st, A, vj, reinterpret_cast<double2*>(w));
-    // two passes of classical Gram-Schmidt against v_0 .. v_j
-    for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, j + 1), dim3(kTBlock), 0, st, V, nv, w, s->dpart);
-      hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(kTBlock), 0, st, s->dpart, j + 1, h);
-      hipLaunchKernelGGL(multi_axpy_kernel, dim3(bv), dim3(kTBlock), 0, st, V, nv, j + 1, h, false, w);
-      e = hipMemcpyAsync(pass ? hc2.data() : hc1.data(), h, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st);
-      if (e != hipSuccess) return hip_fail(e, "GMRES projections");
-      if (pass == 0) {                               // h is reused by the second pass
-        e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "GMRES projections");
-      }
+    // pass 1: <v_i, w> for i <= j and |w|^2 (w is vector j + 1) in one launch, then w -= V h1
+    hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, j + 2), dim3(kTBlock), 0, st, V, nv, w, s->dpart, nullptr);
+    hipLaunchKernelGGL(dot_fold_kernel, dim3(j + 2), dim3(kTBlock), 0, st, s->dpart, S.h1, nullptr);
+    hipLaunchKernelGGL(multi_axpy_kernel, dim3(bv), dim3(kTBlock), 0, st, V, nv, j + 1, nullptr, S.h1, false, w,
+                       nullptr);
+    hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, 1), dim3(kTBlock), 0, st, w, nv, w, s->dpart, nullptr);
+    hipLaunchKernelGGL(dot_fold_kernel, dim3(1), dim3(kTBlock), 0, st, s->dpart, S.nrm, nullptr);
+    hipLaunchKernelGGL(gm_reorth_kernel, dim3(1), dim3(1), 0, st, S, j);
+    // pass 2 where the device decided it is needed
+    hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, j + 1), dim3(kTBlock), 0, st, V, nv, w, s->dpart, reorth);
+    hipLaunchKernelGGL(dot_fold_kernel, dim3(j + 1), dim3(kTBlock), 0, st, s->dpart, S.h2, reorth);
+    hipLaunchKernelGGL(multi_axpy_kernel, dim3(bv), dim3(kTBlock), 0, st, V, nv, j + 1, nullptr, S.h2, false, w,
+                       reorth);
+    hipLaunchKernelGGL(gm_column_kernel, dim3(1), dim3(1), 0, st, S, j, tol);
+    hipLaunchKernelGGL(normalize_kernel, dim3(bv), dim3(kTBlock), 0, st, w, nv, S.nrm + 3, done, w);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "GMRES step launch");
+    if (j + 1 < m && (j + 1) % s->every == 0) {
+      int h = 0;
+      e = hipMemcpyAsync(&h, done, sizeof(int), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_fail(e, "GMRES residual test");
+      if (h) break;
     }
-    hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, 1), dim3(kTBlock), 0, st, w, nv, w, s->dpart);
-    hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(kTBlock), 0, st, s->dpart, 1, h + m + 1);
-    double nrm2 = 0.0;
-    e = hipMemcpyAsync(&nrm2, h + m + 1, sizeof(double), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "GMRES norm");
-    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc1[i] + hc2[i];
-    const double hn = std::sqrt(nrm2);
-    H[(size_t)(j + 1) * m + j] = hn;
-    if (j + 1 < m + 1 && hn > 0.0)
-      hipLaunchKernelGGL(normalize_kernel, dim3(bv), dim3(kTBlock), 0, st, w, nv, h + m + 1, V + (int64_t)(j + 1) * nv);
-    // Givens rotations of column j
-    for (int i = 0; i < j; ++i) {
-      const double a = H[(size_t)i * m + j], bq = H[(size_t)(i + 1) * m + j];
-      H[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
-      H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bq;
-    }
-    const double a = H[(size_t)j * m + j], bq = H[(size_t)(j + 1) * m + j];
-    const double rr = std::hypot(a, bq);
-    cs[j] = rr > 0.0 ? a / rr : 1.0;
-    sn[j] = rr > 0.0 ? bq / rr : 0.0;
-    H[(size_t)j * m + j] = rr;
-    H[(size_t)(j + 1) * m + j] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    k = j + 1;
-    if (std::fabs(g[j + 1]) <= (s->tol > 0.0 ? s->tol : 1e-15) * beta || hn == 0.0) break;
   }
-  if (k > s->last_iters) s->last_iters = k;
-  // y from the k x k triangle, x = V y
-  std::vector<double> y(k, 0.0);
-  for (int i = k - 1; i >= 0; --i) {
-    double acc = g[i];
-    for (int t = i + 1; t < k; ++t) acc -= H[(size_t)i * m + t] * y[t];
-    y[i] = acc / H[(size_t)i * m + i];
-  }
-  e = hipMemcpyAsync(h, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return hip_fail(e, "GMRES solution");
-  hipLaunchKernelGGL(multi_axpy_kernel, dim3(bv), dim3(kTBlock), 0, st, V, nv, k, h, true,
-                     reinterpret_cast<double*>(s->xh));
-  e = hipStreamSynchronize(st);                      // y (host memory) stays alive until the copy ran
-  if (e != hipSuccess) return hip_fail(e, "GMRES solution");
+  // y from the triangle, x = V y over the steps taken (both counts read on the device)
+  hipLaunchKernelGGL(gm_solve_kernel, dim3(1), dim3(1), 0, st, S);
+  hipLaunchKernelGGL(multi_axpy_kernel, dim3(bv), dim3(kTBlock), 0, st, V, nv, 0, S.flag + kGmK, S.y, true,
+                     reinterpret_cast<double*>(s->xh), nullptr);
   hipLaunchKernelGGL(deriv_kernel<D>, dim3(bs), dim3(kTBlock), 0, st, geom(s), s->nc, 1.0, s->xh, true, s->iv);
   e = hipGetLastError();
   return e == hipSuccess ? TFS_OK : hip_fail(e, "GMRES launch");
@@ -963,6 +1059,7 @@ tfs_status tfs_transport_destroy(tfs_transport s) {
   drop_batched(s);
   for (double* b : {s->rg, s->x1g, s->fg, s->xg, s->part, s->mean, s->basis, s->dpart, s->coef, s->part2})
     if (b) (void)hipFree(b);
+  if (s->gflag) (void)hipFree(s->gflag);
   for (double2* b : {s->rh, s->xh, s->fh, s->eh, s->iv})
     if (b) (void)hipFree(b);
   delete s;
@@ -979,7 +1076,15 @@ tfs_status tfs_transport_set_tolerance(tfs_transport s, double tol, int every) {
   return TFS_OK;
 }
 
-int tfs_transport_last_iterations(tfs_transport s) { return s ? s->last_iters : -1; }
+int tfs_transport_last_iterations(tfs_transport s) {
+  if (!s) return -1;
+  if (s->method != 1 || !s->gflag) return s->last_iters;
+  // GMRES keeps its count on the device: read it once the last step's work is done
+  int k = 0;
+  hipError_t e = hipMemcpyAsync(&k, s->gflag + kGmKmax, sizeof(int), hipMemcpyDeviceToHost, s->last_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->last_stream);
+  return e == hipSuccess ? k : -1;
+}
 
 tfs_status tfs_transport_set_method(tfs_transport s, int method) {
   if (!s) return set_error(TFS_EINVAL, "null transport object");
@@ -990,10 +1095,13 @@ tfs_status tfs_transport_set_method(tfs_transport s, int method) {
     const int64_t nv = (int64_t)2 * c * s->nc;
     hipError_t e = hipMalloc((void**)&s->basis, sizeof(double) * nv * (s->iters + 1));
     if (e == hipSuccess) e = hipMalloc((void**)&s->dpart, sizeof(double) * kDotBlocks * (s->iters + 1));
-    if (e == hipSuccess) e = hipMalloc((void**)&s->coef, sizeof(double) * (s->iters + 2));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->coef, sizeof(double) * gm_doubles(s->iters));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->gflag, sizeof(int) * kGmFlags);
+    if (e == hipSuccess) e = hipMemset(s->gflag, 0, sizeof(int) * kGmFlags);
     if (e != hipSuccess) {
       for (double** b : {&s->basis, &s->dpart, &s->coef})
         if (*b) { (void)hipFree(*b); *b = nullptr; }
+      if (s->gflag) { (void)hipFree(s->gflag); s->gflag = nullptr; }
       return set_error(TFS_ENOMEM, "device allocation of the Krylov basis failed");
     }
   }
@@ -1065,6 +1173,8 @@ tfs_status tfs_transport_step(tfs_transport s, tfs_plan p, int64_t n, const doub
     lv.Yo = Yb + sm * ys * eb;
   }
   s->last_iters = 0;
+  s->last_stream = p->stream;
+  if (s->method == 1 && s->gflag) hipLaunchKernelGGL(gm_reset_kernel, dim3(1), dim3(1), 0, p->stream, s->gflag);
   tfs_status r;
   if (p->precision == TFS_FP64)
     r = s->dim == 2 ? step_d<2, double>(s, p, n, L, lv, tau, diag) : step_d<3, double>(s, p, n, L, lv, tau, diag);
