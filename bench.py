@@ -461,10 +461,9 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
     P = wl.npoints if npoints is None else npoints
     alpha = wl.alphas[0]
     w, lam, _, _, _ = tfs.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * wl.nsteps)
-    # mode-ring tile measured best per configuration: 4096 points for the 128^3, m = 32 grid
-    # (its BDF2 forward and recompute run 5-7% faster than with the 3-D default), the
-    # default 8192 for the 384^3 slab (its adjoint runs 8% slower with 4096)
-    tile = 4096 if workload == 4 else None
+    # the library's mode-ring tile (32 KB planes: 8192 FP32 points), measured best for the
+    # current kernels at both the 128^3 grid and the 384^3 slab
+    tile = None
     p = tfs.Plan(wl.dim, P, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=wl.precision,
                  scheme=scheme, tile=tile, kappa="fp32")
     exp = scheme == "exp"
@@ -679,7 +678,7 @@ def headline_differentiation(args, stream, wl_id=5):
         raise SystemExit(f"warmup + steps must stay below the workload's {wl.nsteps} time levels")
     w, lam, _, _, info = tfs.soe_fit(alpha, m, wl.dt, wl.dt * wl.nsteps)
     log(f"{wl.name}: SOE symbol rel err {info['symbol_relerr']:.2e}, kernel rel err {info['kernel_relerr']:.2e}")
-    tile = 4096 if wl_id == 4 else (None if args.tile < 0 else args.tile)
+    tile = None if args.tile < 0 else args.tile
     p = tfs.Plan(3, P, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision="fp32_modes", kappa="fp32",
                  tile=tile)
     if args.grid_per_cu:
