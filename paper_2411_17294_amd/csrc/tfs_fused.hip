@@ -28,6 +28,8 @@ constexpr int kRotTerms = 64;
 // Steps between fresh sincos evaluations of the rotated terms (bounds the drift of the
 // repeated rotation to a few tens of rounding errors).
 constexpr int kReseed = 32;
+// Largest field table (bytes) copied into each block's LDS.
+constexpr size_t kTabLdsMax = 32768;
 
 template <typename MT>
 struct FusedArgs {
@@ -67,41 +69,53 @@ __device__ __forceinline__ double lanes_sum(double v) {
 // sine comes from the later one by angle addition, sin(a - w dt) = sin a cos(w dt) -
 // cos a sin(w dt), so each term costs one sincos.  Lane h of the point's L lanes sums the
 // terms n = h, h + L, ...; the caller adds the lanes' sums.
-template <int D, int L>
-__device__ __forceinline__ void field_kappa(const double* f, int nterms, int h, const double (&x)[D], double t,
+// The field table is read from LDS (a block copy of it) or from global memory: the lanes of
+// a point read different terms, so global reads are vector loads, one memory round trip per
+// term.
+template <bool LF>
+struct FieldTab {
+  const double* t;                                   // LDS copy (LF) or global table
+  __device__ __forceinline__ double operator()(int i) const {
+    if constexpr (LF) return t[i];
+    else return load_uniform(opaque_ptr(t) + i);
+  }
+};
+
+template <int D, int L, typename FT>
+__device__ __forceinline__ void field_kappa(const FT& f, int nterms, int h, const double (&x)[D], double t,
                                             double ga, double gb, double (&kap)[D * D]) {
   constexpr int W = D + 4 + D * D;
 #pragma unroll
   for (int q = 0; q < D * D; ++q) kap[q] = 0.0;
   for (int n = h; n < nterms; n += L) {
-    const double* r = opaque_ptr(f) + n * W;
+    const int r = n * W;
     double th = 0.0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) th += x[j] * load_uniform(r + j);
-    th = th + load_uniform(r + D) + load_uniform(r + D + 1) * t;
+    for (int j = 0; j < D; ++j) th += x[j] * f(r + j);
+    th = th + f(r + D) + f(r + D + 1) * t;
     double sn, cn;
     sincos(th, &sn, &cn);
     double wgt = sn;
-    if (gb != 0.0) wgt = ga * sn + gb * (sn * load_uniform(r + D + 2) - cn * load_uniform(r + D + 3));
+    if (gb != 0.0) wgt = ga * sn + gb * (sn * f(r + D + 2) - cn * f(r + D + 3));
 #pragma unroll
-    for (int q = 0; q < D * D; ++q) kap[q] += wgt * load_uniform(r + D + 4 + q);
+    for (int q = 0; q < D * D; ++q) kap[q] += wgt * f(r + D + 4 + q);
   }
 #pragma unroll
   for (int q = 0; q < D * D; ++q) kap[q] = lanes_sum<L>(kap[q]);
 }
 
 // (sin, cos) of the lane's terms at time t into LDS (rot[i * kFusedBlock + lane]).
-template <int D, int L>
-__device__ __forceinline__ void rot_seed(const double* f, int nterms, int h, const double (&x)[D], double t,
+template <int D, int L, typename FT>
+__device__ __forceinline__ void rot_seed(const FT& f, int nterms, int h, const double (&x)[D], double t,
                                          double2* rot) {
   constexpr int W = D + 4 + D * D;
   int i = 0;
   for (int n = h; n < nterms; n += L, ++i) {
-    const double* r = opaque_ptr(f) + n * W;
+    const int r = n * W;
     double th = 0.0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) th += x[j] * load_uniform(r + j);
-    th = th + load_uniform(r + D) + load_uniform(r + D + 1) * t;
+    for (int j = 0; j < D; ++j) th += x[j] * f(r + j);
+    th = th + f(r + D) + f(r + D + 1) * t;
     double sn, cn;
     sincos(th, &sn, &cn);
     rot[i * kFusedBlock + threadIdx.x] = make_double2(sn, cn);
@@ -110,25 +124,24 @@ __device__ __forceinline__ void rot_seed(const double* f, int nterms, int h, con
 
 // kappa~ from the lane's rotated terms (their sin and cos at t_n), as field_kappa; then the
 // terms move to t_{n+1} by angle addition (the caller re-seeds them every kReseed steps).
-template <int D, int L>
-__device__ __forceinline__ void rot_kappa(const double* f, int nterms, int h, double ga, double gb, double2* rot,
+template <int D, int L, typename FT>
+__device__ __forceinline__ void rot_kappa(const FT& f, int nterms, int h, double ga, double gb, double2* rot,
                                           double (&kap)[D * D]) {
   constexpr int W = D + 4 + D * D;
 #pragma unroll
   for (int q = 0; q < D * D; ++q) kap[q] = 0.0;
   const int cnt = (nterms - h + L - 1) / L;
-  const double* fb = opaque_ptr(f) + h * W;
   // two terms in flight in 2-D (measured faster); one in 3-D, where registers are short
   constexpr int kU = D == 2 ? 2 : 1;
 #pragma unroll kU
   for (int i = 0; i < cnt; ++i) {
-    const double* r = fb + i * (L * W);
+    const int r = (h + i * L) * W;
     const double2 sc = rot[i * kFusedBlock + threadIdx.x];
-    const double cw = load_uniform(r + D + 2), sw = load_uniform(r + D + 3);
+    const double cw = f(r + D + 2), sw = f(r + D + 3);
     double wgt = sc.x;
     if (gb != 0.0) wgt = ga * sc.x + gb * (sc.x * cw - sc.y * sw);
 #pragma unroll
-    for (int q = 0; q < D * D; ++q) kap[q] += wgt * load_uniform(r + D + 4 + q);
+    for (int q = 0; q < D * D; ++q) kap[q] += wgt * f(r + D + 4 + q);
     rot[i * kFusedBlock + threadIdx.x] = make_double2(sc.x * cw + sc.y * sw, sc.y * cw - sc.x * sw);
   }
 #pragma unroll
@@ -167,16 +180,40 @@ __device__ __forceinline__ void mode_pass(const double* coef, int k0, const doub
   }
 }
 
+// Dynamic LDS of a fused launch: the field table (when it is copied, nterms W doubles,
+// rounded to 16 bytes), then the rotated terms.  Every thread of the block takes part in the
+// copy, before any returns.
+template <int D, bool LF, typename MT>
+__device__ __forceinline__ FieldTab<LF> stage_field(const FusedArgs<MT>& a, double2* smem, double2** rot) {
+  constexpr int W = D + 4 + D * D;
+  FieldTab<LF> f;
+  if constexpr (LF) {
+    const int tabn = a.nterms * W;
+    double* tab = reinterpret_cast<double*>(smem);
+    for (int i = threadIdx.x; i < tabn; i += kFusedBlock) tab[i] = a.field[i];
+    __syncthreads();
+    *rot = smem + (tabn + 1) / 2;
+    f.t = tab;
+  } else {
+    *rot = smem;
+    f.t = a.field;
+  }
+  return f;
+}
+
 // One point per L consecutive lanes; lane h of them holds modes [h M/L, (h+1) M/L) in
 // registers.  The lanes add their partial mode sums (H, G) and field terms, then both run
 // the point's c x c solve on the same values.
-template <int D, typename MT, int M, int L>
+template <int D, typename MT, int M, int L, bool LF>
 __global__ __launch_bounds__(kFusedBlock) void fused_exp_kernel(const FusedArgs<MT> a) {
   constexpr int C = Sym<D>::C;
   constexpr int MH = M / L;
   const int64_t g = (int64_t)blockIdx.x * kFusedBlock + threadIdx.x;
   const int64_t p = g / L;
   const int h = (int)(g % L);
+  extern __shared__ double2 smem[];
+  double2* rot;
+  const FieldTab<LF> f = stage_field<D, LF>(a, smem, &rot);
   if (p >= a.npoints) return;
   const int64_t st = a.stride, T = a.tile;
   const int64_t ym = (p / T) * (int64_t)M * C * T + p % T;   // mode (0, 0) of the point
@@ -204,11 +241,10 @@ __global__ __launch_bounds__(kFusedBlock) void fused_exp_kernel(const FusedArgs<
       for (int s = 0; s < C; ++s) y[k][s] = a.Y[ym + (int64_t)((k0 + k) * C + s) * T];
   }
   // a steady field is evaluated once; a time-varying one is rotated in LDS when it fits
-  extern __shared__ double2 rot[];
   const bool rotate = !a.steady && (a.nterms + L - 1) / L <= kRotTerms;
   double ks[D * D];
-  if (a.steady) field_kappa<D, L>(a.field, a.nterms, h, x, 0.0, 1.0, 0.0, ks);
-  if (rotate) rot_seed<D, L>(a.field, a.nterms, h, x, (double)a.n0 * a.dt, rot);
+  if (a.steady) field_kappa<D, L>(f, a.nterms, h, x, 0.0, 1.0, 0.0, ks);
+  if (rotate) rot_seed<D, L>(f, a.nterms, h, x, (double)a.n0 * a.dt, rot);
   const int64_t sn = (a.n0 + a.nsteps) % 2;
   double tout[C];
 #pragma unroll
@@ -227,12 +263,12 @@ __global__ __launch_bounds__(kFusedBlock) void fused_exp_kernel(const FusedArgs<
 #pragma unroll
       for (int q = 0; q < D * D; ++q) k[q] = first ? ks[q] : a.fa * ks[q] + a.fb * ks[q];
     } else if (rotate) {
-      rot_kappa<D, L>(a.field, a.nterms, h, a.fa, first ? 0.0 : a.fb, rot, k);
-      if ((j + 1) % kReseed == 0) rot_seed<D, L>(a.field, a.nterms, h, x, (double)(n + 1) * a.dt, rot);
+      rot_kappa<D, L>(f, a.nterms, h, a.fa, first ? 0.0 : a.fb, rot, k);
+      if ((j + 1) % kReseed == 0) rot_seed<D, L>(f, a.nterms, h, x, (double)(n + 1) * a.dt, rot);
     } else if (first) {
-      field_kappa<D, L>(a.field, a.nterms, h, x, 0.0, 1.0, 0.0, k);
+      field_kappa<D, L>(f, a.nterms, h, x, 0.0, 1.0, 0.0, k);
     } else {
-      field_kappa<D, L>(a.field, a.nterms, h, x, (double)n * a.dt, a.fa, a.fb, k);
+      field_kappa<D, L>(f, a.nterms, h, x, (double)n * a.dt, a.fa, a.fb, k);
     }
 
     double H[C], Gs[C], Ge[C];
@@ -302,9 +338,9 @@ __device__ __forceinline__ void bdf2_mode_pass(const double* coef, int k0, const
 
 // One fused BDF2 time level n -> n+1 of a point: kappa~ = 2 kappa(t_n) - kappa(t_{n-1}) from
 // the field, the modes (yn = level n, ym = level n-1, overwritten with n+1), the c x c solve.
-template <int D, typename MT, int M, int L>
-__device__ __forceinline__ void bdf2_fused_step(const FusedArgs<MT>& a, int h, int64_t n, int64_t j, bool rotate,
-                                                const double (&x)[D], const double (&ks)[D * D], double2* rot,
+template <int D, typename MT, int M, int L, typename FT>
+__device__ __forceinline__ void bdf2_fused_step(const FusedArgs<MT>& a, const FT& f, int h, int64_t n, int64_t j,
+                                                bool rotate, const double (&x)[D], const double (&ks)[D * D], double2* rot,
                                                 double (&Xn)[Sym<D>::C], double (&Xm)[Sym<D>::C],
                                                 const MT (&yn)[M / L][Sym<D>::C], MT (&ym)[M / L][Sym<D>::C],
                                                 double (&tout)[Sym<D>::C]) {
@@ -314,10 +350,10 @@ __device__ __forceinline__ void bdf2_fused_step(const FusedArgs<MT>& a, int h, i
 #pragma unroll
     for (int q = 0; q < D * D; ++q) k[q] = 2.0 * ks[q] - ks[q];
   } else if (rotate) {
-    rot_kappa<D, L>(a.field, a.nterms, h, 2.0, -1.0, rot, k);
-    if ((j + 1) % kReseed == 0) rot_seed<D, L>(a.field, a.nterms, h, x, (double)(n + 1) * a.dt, rot);
+    rot_kappa<D, L>(f, a.nterms, h, 2.0, -1.0, rot, k);
+    if ((j + 1) % kReseed == 0) rot_seed<D, L>(f, a.nterms, h, x, (double)(n + 1) * a.dt, rot);
   } else {
-    field_kappa<D, L>(a.field, a.nterms, h, x, (double)n * a.dt, 2.0, -1.0, k);
+    field_kappa<D, L>(f, a.nterms, h, x, (double)n * a.dt, 2.0, -1.0, k);
   }
   double P[C], Gs[C], Ge[C], G[C], AG[C], R[C];
 #pragma unroll
@@ -346,13 +382,16 @@ __device__ __forceinline__ void bdf2_fused_step(const FusedArgs<MT>& a, int h, i
 
 // Fused BDF2 levels n0 -> n0 + nsteps (n0 >= 1): L lanes per point, each with its share of
 // both mode levels in registers; level j returns to ring slot j % 2.
-template <int D, typename MT, int M, int L>
+template <int D, typename MT, int M, int L, bool LF>
 __global__ __launch_bounds__(kFusedBlock) void fused_bdf2_kernel(const FusedArgs<MT> a) {
   constexpr int C = Sym<D>::C;
   constexpr int MH = M / L;
   const int64_t g = (int64_t)blockIdx.x * kFusedBlock + threadIdx.x;
   const int64_t p = g / L;
   const int h = (int)(g % L);
+  extern __shared__ double2 smem[];
+  double2* rot;
+  const FieldTab<LF> f = stage_field<D, LF>(a, smem, &rot);
   if (p >= a.npoints) return;
   const int64_t st = a.stride, T = a.tile;
   const int64_t ys = (int64_t)M * C * st;                     // one ring slot
@@ -384,16 +423,15 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bdf2_kernel(const FusedArgs
       ya[k][s] = a.Y[sa * ys + ym0 + (int64_t)((k0 + k) * C + s) * T];
       yb[k][s] = a.Y[sb * ys + ym0 + (int64_t)((k0 + k) * C + s) * T];
     }
-  extern __shared__ double2 rot[];
   const bool rotate = !a.steady && (a.nterms + L - 1) / L <= kRotTerms;
   double ks[D * D];
-  if (a.steady) field_kappa<D, L>(a.field, a.nterms, h, x, 0.0, 1.0, 0.0, ks);
-  if (rotate) rot_seed<D, L>(a.field, a.nterms, h, x, (double)a.n0 * a.dt, rot);
+  if (a.steady) field_kappa<D, L>(f, a.nterms, h, x, 0.0, 1.0, 0.0, ks);
+  if (rotate) rot_seed<D, L>(f, a.nterms, h, x, (double)a.n0 * a.dt, rot);
   // ya holds level n and yb level n - 1; the step overwrites yb with n + 1, then the two swap
   // (register moves: calling the step with the roles exchanged every other step holds more
   // registers)
   for (int64_t j = 0; j < a.nsteps; ++j) {
-    bdf2_fused_step<D, MT, M, L>(a, h, a.n0 + j, j, rotate, x, ks, rot, Xn, Xm, ya, yb, tout);
+    bdf2_fused_step<D, MT, M, L>(a, f, h, a.n0 + j, j, rotate, x, ks, rot, Xn, Xm, ya, yb, tout);
 #pragma unroll
     for (int k = 0; k < MH; ++k)
 #pragma unroll
@@ -452,22 +490,33 @@ hipError_t fused_go(const tfs_plan_s* p, int64_t n0, int64_t nsteps, double* X, 
   a.eta = p->eta;
   a.s_ec = p->s_ec;
   if constexpr (BDF2) a.a_diag = p->a_diag;
-  const void* fn;
-  if constexpr (BDF2) fn = reinterpret_cast<const void*>(&fused_bdf2_kernel<D, MT, M, L>);
-  else fn = reinterpret_cast<const void*>(&fused_exp_kernel<D, MT, M, L>);
   const int64_t blocks = (p->npoints * L + kFusedBlock - 1) / kFusedBlock;
   const int per_lane = (p->field_terms + L - 1) / L;
-  const size_t lds = (!p->field_steady && per_lane <= kRotTerms) ? sizeof(double2) * per_lane * kFusedBlock : 0;
+  // the field table goes to LDS when it is small (64 terms: 8 KB in 3-D); with the largest
+  // rotated set (64 terms a lane, 128 KB) the block holds 160 KB, the CU's whole LDS
+  const size_t tab = sizeof(double2) * (((size_t)p->field_terms * (D + 4 + D * D) + 1) / 2);
+  const bool lf = tab <= kTabLdsMax;
+  const size_t lds = (lf ? tab : 0) +
+                     ((!p->field_steady && per_lane <= kRotTerms) ? sizeof(double2) * per_lane * kFusedBlock : 0);
+  const void* fn;
+  if constexpr (BDF2)
+    fn = lf ? reinterpret_cast<const void*>(&fused_bdf2_kernel<D, MT, M, L, true>)
+            : reinterpret_cast<const void*>(&fused_bdf2_kernel<D, MT, M, L, false>);
+  else
+    fn = lf ? reinterpret_cast<const void*>(&fused_exp_kernel<D, MT, M, L, true>)
+            : reinterpret_cast<const void*>(&fused_exp_kernel<D, MT, M, L, false>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  if constexpr (BDF2)
-    hipLaunchKernelGGL((fused_bdf2_kernel<D, MT, M, L>), dim3((unsigned)blocks), dim3(kFusedBlock), lds, p->stream,
-                       a);
-  else
-    hipLaunchKernelGGL((fused_exp_kernel<D, MT, M, L>), dim3((unsigned)blocks), dim3(kFusedBlock), lds, p->stream,
-                       a);
+  const dim3 gr((unsigned)blocks), bl(kFusedBlock);
+  if constexpr (BDF2) {
+    if (lf) hipLaunchKernelGGL((fused_bdf2_kernel<D, MT, M, L, true>), gr, bl, lds, p->stream, a);
+    else hipLaunchKernelGGL((fused_bdf2_kernel<D, MT, M, L, false>), gr, bl, lds, p->stream, a);
+  } else {
+    if (lf) hipLaunchKernelGGL((fused_exp_kernel<D, MT, M, L, true>), gr, bl, lds, p->stream, a);
+    else hipLaunchKernelGGL((fused_exp_kernel<D, MT, M, L, false>), gr, bl, lds, p->stream, a);
+  }
   return hipGetLastError();
 }
 

@@ -200,3 +200,46 @@ def test_fused_bdf2_needs_the_start_step():
     plan.set_field(ff.k, ff.phase, ff.omega, ff.coef(), 32, 0)
     with pytest.raises(tfs.TfsError):
         plan.run_fused(0, 3, *plan.alloc()[:3])
+
+
+def many_terms_field(d, nterms, seed, steady):
+    """A field of nterms terms (the workload's terms repeated at new phases and rates): its
+    table is too large for the fused kernels' LDS copy, so they read it from global memory."""
+    base = I.fourier_field(I.WORKLOADS[2 if d == 2 else 5])
+    rng = np.random.default_rng(seed)
+    reps = -(-nterms // len(base.amp))
+    k = np.tile(base.k, (reps, 1))[:nterms]
+    e = np.tile(base.e, (reps, 1))[:nterms]
+    amp = np.tile(base.amp, reps)[:nterms] / reps
+    phase = rng.uniform(0.0, 2.0 * np.pi, nterms)
+    omega = np.zeros(nterms) if steady else rng.uniform(0.5, 2.0, nterms)
+    return I.FourierField(d, k, e, amp, phase, omega)
+
+
+@pytest.mark.parametrize("scheme", ["exp", "bdf2"])
+@pytest.mark.parametrize("d,prec,nterms", [(3, "fp32_modes", 300), (2, "fp64", 450)])
+@pytest.mark.parametrize("steady", [True, False])
+def test_fused_large_field_table(d, prec, nterms, steady, scheme):
+    """A field table larger than the LDS copy (300 terms in 3-D, 450 in 2-D): the same results
+    against the oracle and the step-by-step path."""
+    ff = many_terms_field(d, nterms, 7 + d, steady)
+    grid = 12 if d == 3 else 32
+    P = grid ** d - 7
+    point0 = 5
+    chunks = (3, 4)
+    N = sum(chunks) + (1 if scheme == "bdf2" else 0)
+    dt = 2e-3
+    plan, w, lam = make_plan(d, P, 16, prec, dt, N, scheme=scheme)
+    X0 = I.random_symmetric_case(d, P, 47, kscale=0.6, xscale=2e-2)[1]
+    kl = levels(ff, grid, np.arange(point0, point0 + P), dt, N)
+    X, Y, tau, _ = fused_run(plan, ff, grid, point0, X0, chunks, kap0=kl[0] if scheme == "bdf2" else None)
+    Xs, Ys, taus = stepwise_run(plan, kl, X0, N)
+    o = O.run(d, w, lam, 1.0, 0.1, dt, N, kl, X0, startup="sdirk2" if scheme == "bdf2" else "exp")
+    bar = 1e-12 if prec == "fp64" else 1e-5
+    got = {"X": X[N % 2, :, :P].cpu().numpy(), "tau": tau[:, :P].cpu().numpy()}
+    step = {"X": Xs[N % 2, :, :P].cpu().numpy(), "tau": taus[:, :P].cpu().numpy()}
+    errs = {k: relerr(got[k], o["X"][0] if k == "X" else o[k]) for k in got}
+    errs_step = {k: relerr(got[k], step[k]) for k in got}
+    print("large table", d, prec, nterms, steady, scheme, "oracle", errs, "stepwise", errs_step, flush=True)
+    assert all(e < bar for e in errs.values()), errs
+    assert all(e < bar for e in errs_step.values()), errs_step
