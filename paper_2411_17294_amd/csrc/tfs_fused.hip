@@ -131,18 +131,54 @@ __device__ __forceinline__ void rot_kappa(const FT& f, int nterms, int h, double
 #pragma unroll
   for (int q = 0; q < D * D; ++q) kap[q] = 0.0;
   const int cnt = (nterms - h + L - 1) / L;
-  // two terms in flight in 2-D (measured faster); one in 3-D, where registers are short
-  constexpr int kU = D == 2 ? 2 : 1;
-#pragma unroll kU
-  for (int i = 0; i < cnt; ++i) {
-    const int r = (h + i * L) * W;
-    const double2 sc = rot[i * kFusedBlock + threadIdx.x];
-    const double cw = f(r + D + 2), sw = f(r + D + 3);
-    double wgt = sc.x;
-    if (gb != 0.0) wgt = ga * sc.x + gb * (sc.x * cw - sc.y * sw);
+  if constexpr (D == 3) {
+    // 3-D: term i + 1's reads are issued before term i's arithmetic (two register sets, the
+    // loop unrolled by two so that they alternate without copies).  Left to itself the
+    // scheduler interleaved reads and uses in the BDF2 kernel, one LDS round trip per read.
+    struct Term { double2 sc; double cw, sw, b[D * D]; };
+    auto read = [&](int i, Term& t) {
+      const int r = (h + i * L) * W;
+      t.sc = rot[i * kFusedBlock + threadIdx.x];
+      t.cw = f(r + D + 2);
+      t.sw = f(r + D + 3);
 #pragma unroll
-    for (int q = 0; q < D * D; ++q) kap[q] += wgt * f(r + D + 4 + q);
-    rot[i * kFusedBlock + threadIdx.x] = make_double2(sc.x * cw + sc.y * sw, sc.y * cw - sc.x * sw);
+      for (int q = 0; q < D * D; ++q) t.b[q] = f(r + D + 4 + q);
+    };
+    auto use = [&](int i, const Term& t) {
+      double wgt = t.sc.x;
+      if (gb != 0.0) wgt = ga * t.sc.x + gb * (t.sc.x * t.cw - t.sc.y * t.sw);
+#pragma unroll
+      for (int q = 0; q < D * D; ++q) kap[q] += wgt * t.b[q];
+      rot[i * kFusedBlock + threadIdx.x] =
+          make_double2(t.sc.x * t.cw + t.sc.y * t.sw, t.sc.y * t.cw - t.sc.x * t.sw);
+    };
+    if (cnt > 0) {
+      Term A, B;
+      read(0, A);
+      for (int i = 0; i < cnt; i += 2) {
+        read(min(i + 1, cnt - 1), B);      // (past the last term: a re-read, unused)
+        __builtin_amdgcn_sched_barrier(0);
+        use(i, A);
+        if (i + 1 < cnt) {
+          read(min(i + 2, cnt - 1), A);
+          __builtin_amdgcn_sched_barrier(0);
+          use(i + 1, B);
+        }
+      }
+    }
+  } else {
+    // 2-D: two terms in flight (measured faster than one)
+#pragma unroll 2
+    for (int i = 0; i < cnt; ++i) {
+      const int r = (h + i * L) * W;
+      const double2 sc = rot[i * kFusedBlock + threadIdx.x];
+      const double cw = f(r + D + 2), sw = f(r + D + 3);
+      double wgt = sc.x;
+      if (gb != 0.0) wgt = ga * sc.x + gb * (sc.x * cw - sc.y * sw);
+#pragma unroll
+      for (int q = 0; q < D * D; ++q) kap[q] += wgt * f(r + D + 4 + q);
+      rot[i * kFusedBlock + threadIdx.x] = make_double2(sc.x * cw + sc.y * sw, sc.y * cw - sc.x * sw);
+    }
   }
 #pragma unroll
   for (int q = 0; q < D * D; ++q) kap[q] = lanes_sum<L>(kap[q]);
