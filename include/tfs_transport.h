@@ -68,10 +68,12 @@ tfs_status tfs_transport_set_batched(tfs_transport tr, int on);
 
 /*
  * The solver of step 3: method 0 (the default) runs `iters` splitting iterations; method 1
- * runs GMRES on the same preconditioned system (the splitting's fixed-point equation, real
- * inner product over the coefficients) with at most `iters` Arnoldi steps (classical
- * Gram-Schmidt, with a second pass where the first cancels more than half of the vector's
- * squared norm) from zero, stopping early at a relative residual of 1e-15.  GMRES converges
+ * runs GMRES on the same preconditioned system (the splitting's fixed-point equation
+ * (I + N) x = b, real inner product over the coefficients) with at most `iters` Arnoldi steps
+ * from zero, stopping early at a relative residual of 1e-15.  The basis is built with N, whose
+ * Krylov space is that of I + N, and one is added to the Hessenberg matrix's diagonal
+ * (classical Gram-Schmidt, with a second pass where the first cancels more than half of the
+ * vector's squared norm).  GMRES converges
  * where the splitting contracts slowly or not at all (strong advection, small eps).  Its
  * least-squares problem (Hessenberg matrix, Givens rotations, residual test, back
  * substitution) stays on the device, so the Arnoldi steps are queued without waiting; the

@@ -539,15 +539,16 @@ __global__ void gm_reorth_kernel(GmState S, int j) {
   S.flag[kGmReorth] = (S.flag[kGmDone] == 0 && S.nrm[0] < 0.5 * S.h1[j + 1]) ? 1 : 0;
 }
 
-// Column j of the Hessenberg matrix from the projections, the earlier Givens rotations applied
-// to it, a new rotation that zeroes its subdiagonal, and the residual test on g.
+// Column j of the Hessenberg matrix of I + N from the projections of N v_j (one added on the
+// diagonal), the earlier Givens rotations applied to it, a new rotation that zeroes its
+// subdiagonal, and the residual test on g.
 __global__ void gm_column_kernel(GmState S, int j, double tol) {
   if (threadIdx.x != 0 || S.flag[kGmDone] != 0) return;
   const int m = S.m;
   const bool re = S.flag[kGmReorth] != 0;
   double p2 = 0.0;   // |V h2|^2: what the second pass took off |w'|^2 (V orthonormal, h2 small)
   for (int i = 0; i <= j; ++i) {
-    S.H[(int64_t)i * m + j] = S.h1[i] + (re ? S.h2[i] : 0.0);
+    S.H[(int64_t)i * m + j] = S.h1[i] + (re ? S.h2[i] : 0.0) + (i == j ? 1.0 : 0.0);
     if (re) p2 = fma(S.h2[i], S.h2[i], p2);
   }
   const double n2 = S.nrm[0] - p2;
@@ -613,9 +614,10 @@ __global__ __launch_bounds__(kTBlock) void diff_norm_kernel(const double* x, con
   }
 }
 
-// w = v + P(xi)^{-1} fh / points (the preconditioned operator applied to v).
+// w = P(xi)^{-1} fh / points: N v, the variable part of the preconditioned operator I + N
+// applied to v (fh holds the transformed fluct(v)).
 template <int D>
-__global__ __launch_bounds__(kTBlock) void gm_apply_kernel(const PrecondArgs A, const double2* v, double2* w) {
+__global__ __launch_bounds__(kTBlock) void gm_apply_kernel(const PrecondArgs A, double2* w) {
   constexpr int C = Sym<D>::C;
   double kb[D * D], ub[D];
 #pragma unroll
@@ -641,10 +643,7 @@ __global__ __launch_bounds__(kTBlock) void gm_apply_kernel(const PrecondArgs A, 
     build_M<D>(kb, A.a + A.b * A.eps * x2, A.b, M);
     solve_shifted<C>(M, A.b * xu, r);
 #pragma unroll
-    for (int s = 0; s < C; ++s) {
-      const double2 x = v[s * A.nc + q];
-      w[s * A.nc + q] = make_double2(x.x + r[s].x, x.y + r[s].y);
-    }
+    for (int s = 0; s < C; ++s) w[s * A.nc + q] = r[s];
   }
 }
 
@@ -845,10 +844,14 @@ tfs_status apply_fluct(tfs_transport_s* s, hipStream_t st, const Lev& L, double 
   return forward_planes(s, s->fg, s->fh, C);
 }
 
-// GMRES on the preconditioned system (I + P^{-1} F fluct F^{-1}) x = P^{-1} rhs_hat (the
-// splitting iteration's fixed-point equation) from x = 0, at most s->iters Arnoldi steps,
-// early exit at the relative residual s->tol (1e-15 when it is 0); x into s->xh.  Classical
-// Gram-Schmidt, with a second pass where the first cancelled more than half of |w|^2.  The
+// GMRES on the preconditioned system (I + N) x = P^{-1} rhs_hat, N = P^{-1} F fluct F^{-1}
+// (the splitting iteration's fixed-point equation), from x = 0, at most s->iters Arnoldi
+// steps, early exit at the relative residual s->tol (1e-15 when it is 0); x into s->xh.  The
+// basis is built with N, whose Krylov space is that of I + N, and the Hessenberg matrix of
+// I + N is that of N with one added on the diagonal: (I + N) v_j is close to v_j where the
+// splitting contracts, so orthogonalising it would cancel most of it and always call for the
+// second pass, while N v_j has no such part.  Classical Gram-Schmidt, with a second pass
+// where the first cancelled more than half of |w|^2.  The
 // Hessenberg matrix, the Givens rotations, the residual test and the back substitution stay on
 // the device, so an Arnoldi step queues its kernels without waiting; the host reads the
 // residual test's flag every s->every steps to stop queueing (steps queued after convergence
@@ -878,7 +881,7 @@ tfs_status gmres(tfs_transport_s* s, hipStream_t st, const Lev& L, const Precond
     if (r != TFS_OK) return r;
     PrecondArgs A = A0;
     A.fh = s->fh;
-    hipLaunchKernelGGL(gm_apply_kernel<D>, dim3(bs), dim3(kTBlock), 0, st, A, vj, reinterpret_cast<double2*>(w));
+    hipLaunchKernelGGL(gm_apply_kernel<D>, dim3(bs), dim3(kTBlock), 0, st, A, reinterpret_cast<double2*>(w));
     // pass 1: <v_i, w> for i <= j and |w|^2 (w is vector j + 1) in one launch, then w -= V h1
     hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, j + 2), dim3(kTBlock), 0, st, V, nv, w, s->dpart, nullptr);
     hipLaunchKernelGGL(dot_fold_kernel, dim3(j + 2), dim3(kTBlock), 0, st, s->dpart, S.h1, nullptr);
