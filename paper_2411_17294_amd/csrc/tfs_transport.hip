@@ -48,6 +48,7 @@ struct tfs_transport_s {
   // state of the least-squares problem (gm_layout) and its flags (kGmFlags ints)
   int method = 0;
   double *basis = nullptr, *dpart = nullptr, *coef = nullptr;
+  double* npart = nullptr;   // [kMaxBlocks] block partials of a norm taken by the update
   int* gflag = nullptr;
   hipStream_t last_stream = nullptr;   // stream of the last step (for the iteration count)
   // early exit: relative update (splitting) or residual (GMRES) below tol, tested every
@@ -426,6 +427,8 @@ __global__ __launch_bounds__(kTBlock) void start_finish_kernel(const double* X0,
 // product: the operator is linear over the reals (the inverse transform keeps only the
 // Hermitian part of a half spectrum), not over the complex numbers.
 constexpr int kDotBlocks = 512;
+// Most blocks of a grid-stride launch (blocks_for).
+constexpr int kMaxBlocks = 256 * 16;
 
 // part[k * kDotBlocks + b] = block b's share of <w, V_k>, k < gridDim.y (blockIdx.y = k).
 // run: null, or a device flag; the launch does nothing while it is 0.
@@ -484,6 +487,28 @@ __global__ __launch_bounds__(kTBlock) void multi_axpy_kernel(const double* V, in
   }
 }
 
+// w -= sum_k coef[k] V_k (k < nvec), as multi_axpy_kernel, and each block's share of |w|^2
+// afterwards into part[blockIdx.x] (folded by norm_fold_kernel).
+__global__ __launch_bounds__(kTBlock) void axpy_norm_kernel(const double* V, int64_t nv, int nvec, const double* coef,
+                                                            double* w, double* part) {
+  __shared__ double red[kTBlock];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kTBlock + threadIdx.x; i < nv; i += (int64_t)gridDim.x * kTBlock) {
+    double a = 0.0;
+    for (int k = 0; k < nvec; ++k) a = fma(coef[k], V[(int64_t)k * nv + i], a);
+    const double x = w[i] - a;
+    w[i] = x;
+    acc = fma(x, x, acc);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = kTBlock / 2; h > 0; h /= 2) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 // out = w / sqrt(nrm2[0]), unless the flag skip is set or the norm is zero.
 __global__ __launch_bounds__(kTBlock) void normalize_kernel(const double* w, int64_t nv, const double* nrm2,
                                                             const int* skip, double* out) {
@@ -531,45 +556,69 @@ __global__ void gm_start_kernel(GmState S) {
   S.flag[kGmReorth] = 0;
 }
 
-// Second Gram-Schmidt pass only where the first lost more than half of |w|^2 (h1[j + 1] holds
-// |w|^2 before it, nrm[0] after): the criterion of Daniel, Gragg, Kaufman and Stewart with
-// eta = 1/sqrt(2).
-__global__ void gm_reorth_kernel(GmState S, int j) {
-  if (threadIdx.x != 0) return;
-  S.flag[kGmReorth] = (S.flag[kGmDone] == 0 && S.nrm[0] < 0.5 * S.h1[j + 1]) ? 1 : 0;
+// |w'|^2 after the first Gram-Schmidt pass of step j (the nparts partials of
+// axpy_norm_kernel folded in a fixed order) into nrm[0], and the decision on the second pass:
+// it runs only where the first took off more than half of |w|^2 (h1[j + 1] holds |w|^2
+// before it), the criterion of Daniel, Gragg, Kaufman and Stewart with eta = 1/sqrt(2).
+__global__ __launch_bounds__(kTBlock) void norm_fold_kernel(GmState S, const double* part, int nparts, int j) {
+  __shared__ double red[kTBlock];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += kTBlock) a += part[b];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int h = kTBlock / 2; h > 0; h /= 2) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    S.nrm[0] = red[0];
+    S.flag[kGmReorth] = (S.flag[kGmDone] == 0 && red[0] < 0.5 * S.h1[j + 1]) ? 1 : 0;
+  }
 }
 
 // Column j of the Hessenberg matrix of I + N from the projections of N v_j (one added on the
 // diagonal), the earlier Givens rotations applied to it, a new rotation that zeroes its
-// subdiagonal, and the residual test on g.
-__global__ void gm_column_kernel(GmState S, int j, double tol) {
-  if (threadIdx.x != 0 || S.flag[kGmDone] != 0) return;
+// subdiagonal, and the residual test on g.  One wave stages the column and the rotations in
+// LDS; one lane applies them (each depends on the one before).
+__global__ __launch_bounds__(64) void gm_column_kernel(GmState S, int j, double tol) {
+  __shared__ double col[kTBlock + 2], cs[kTBlock], sn[kTBlock];
+  if (S.flag[kGmDone] != 0) return;
   const int m = S.m;
   const bool re = S.flag[kGmReorth] != 0;
-  double p2 = 0.0;   // |V h2|^2: what the second pass took off |w'|^2 (V orthonormal, h2 small)
-  for (int i = 0; i <= j; ++i) {
-    S.H[(int64_t)i * m + j] = S.h1[i] + (re ? S.h2[i] : 0.0) + (i == j ? 1.0 : 0.0);
-    if (re) p2 = fma(S.h2[i], S.h2[i], p2);
+  for (int i = threadIdx.x; i <= j; i += blockDim.x)
+    col[i] = S.h1[i] + (re ? S.h2[i] : 0.0) + (i == j ? 1.0 : 0.0);
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    cs[i] = S.cs[i];
+    sn[i] = S.sn[i];
   }
-  const double n2 = S.nrm[0] - p2;
-  const double hn = sqrt(n2 > 0.0 ? n2 : 0.0);
-  S.nrm[3] = hn * hn;
-  S.H[(int64_t)(j + 1) * m + j] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double a = S.H[(int64_t)i * m + j], b = S.H[(int64_t)(i + 1) * m + j];
-    S.H[(int64_t)i * m + j] = S.cs[i] * a + S.sn[i] * b;
-    S.H[(int64_t)(i + 1) * m + j] = -S.sn[i] * a + S.cs[i] * b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double p2 = 0.0;   // |V h2|^2: what the second pass took off |w'|^2 (V orthonormal, h2 small)
+    if (re)
+      for (int i = 0; i <= j; ++i) p2 = fma(S.h2[i], S.h2[i], p2);
+    const double n2 = S.nrm[0] - p2;
+    const double hn = sqrt(n2 > 0.0 ? n2 : 0.0);
+    S.nrm[3] = hn * hn;
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = col[i], b = col[i + 1];
+      col[i] = cs[i] * a + sn[i] * b;
+      col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double r = hypot(a, b);
+    const double c = r > 0.0 ? a / r : 1.0, z = r > 0.0 ? b / r : 0.0;
+    S.cs[j] = c;
+    S.sn[j] = z;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    S.g[j + 1] = -z * S.g[j];
+    S.g[j] = c * S.g[j];
+    S.flag[kGmK] = j + 1;
+    if (fabs(S.g[j + 1]) <= tol * sqrt(S.nrm[2]) || hn == 0.0) S.flag[kGmDone] = 1;   // |residual| / beta
   }
-  const double a = S.H[(int64_t)j * m + j], b = S.H[(int64_t)(j + 1) * m + j];
-  const double r = hypot(a, b);
-  S.cs[j] = r > 0.0 ? a / r : 1.0;
-  S.sn[j] = r > 0.0 ? b / r : 0.0;
-  S.H[(int64_t)j * m + j] = r;
-  S.H[(int64_t)(j + 1) * m + j] = 0.0;
-  S.g[j + 1] = -S.sn[j] * S.g[j];
-  S.g[j] = S.cs[j] * S.g[j];
-  S.flag[kGmK] = j + 1;
-  if (fabs(S.g[j + 1]) <= tol * sqrt(S.nrm[2]) || hn == 0.0) S.flag[kGmDone] = 1;   // |residual| / beta
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) S.H[(int64_t)i * m + j] = col[i];
 }
 
 // y from the k x k triangle (k = the steps taken) and g; the most steps of the step's solves.
@@ -713,7 +762,7 @@ __global__ __launch_bounds__(kTBlock) void diag_fold_kernel(const double* part, 
 
 int blocks_for(int64_t work) {
   const int64_t b = (work + kTBlock - 1) / kTBlock;
-  const int64_t cap = 256 * 16;
+  const int64_t cap = kMaxBlocks;
   return (int)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
@@ -768,6 +817,9 @@ tfs_status converged(tfs_transport_s* s, hipStream_t st, const double* x, const 
   *done = std::sqrt(h[0]) <= s->tol * std::sqrt(h[1]);
   return TFS_OK;
 }
+
+template <int D>
+tfs_status gmres(tfs_transport_s* s, hipStream_t st, const Lev& L, const PrecondArgs& A0);
 
 // Solve (a I - b K(kappa~) + b T) X = rhs with rhs = F^{-1}[F(rg) + alpha eps |xi|^2 E_hat]
 // (E_hat = s->eh when extra), X into out.
@@ -883,19 +935,17 @@ tfs_status gmres(tfs_transport_s* s, hipStream_t st, const Lev& L, const Precond
     A.fh = s->fh;
     hipLaunchKernelGGL(gm_apply_kernel<D>, dim3(bs), dim3(kTBlock), 0, st, A, reinterpret_cast<double2*>(w));
     // pass 1: <v_i, w> for i <= j and |w|^2 (w is vector j + 1) in one launch, then w -= V h1
+    // with the partials of |w'|^2, folded with the decision on the second pass
     hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, j + 2), dim3(kTBlock), 0, st, V, nv, w, s->dpart, nullptr);
     hipLaunchKernelGGL(dot_fold_kernel, dim3(j + 2), dim3(kTBlock), 0, st, s->dpart, S.h1, nullptr);
-    hipLaunchKernelGGL(multi_axpy_kernel, dim3(bv), dim3(kTBlock), 0, st, V, nv, j + 1, nullptr, S.h1, false, w,
-                       nullptr);
-    hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, 1), dim3(kTBlock), 0, st, w, nv, w, s->dpart, nullptr);
-    hipLaunchKernelGGL(dot_fold_kernel, dim3(1), dim3(kTBlock), 0, st, s->dpart, S.nrm, nullptr);
-    hipLaunchKernelGGL(gm_reorth_kernel, dim3(1), dim3(1), 0, st, S, j);
+    hipLaunchKernelGGL(axpy_norm_kernel, dim3(bv), dim3(kTBlock), 0, st, V, nv, j + 1, S.h1, w, s->npart);
+    hipLaunchKernelGGL(norm_fold_kernel, dim3(1), dim3(kTBlock), 0, st, S, s->npart, bv, j);
     // pass 2 where the device decided it is needed
     hipLaunchKernelGGL(multi_dot_kernel, dim3(kDotBlocks, j + 1), dim3(kTBlock), 0, st, V, nv, w, s->dpart, reorth);
     hipLaunchKernelGGL(dot_fold_kernel, dim3(j + 1), dim3(kTBlock), 0, st, s->dpart, S.h2, reorth);
     hipLaunchKernelGGL(multi_axpy_kernel, dim3(bv), dim3(kTBlock), 0, st, V, nv, j + 1, nullptr, S.h2, false, w,
                        reorth);
-    hipLaunchKernelGGL(gm_column_kernel, dim3(1), dim3(1), 0, st, S, j, tol);
+    hipLaunchKernelGGL(gm_column_kernel, dim3(1), dim3(64), 0, st, S, j, tol);
     hipLaunchKernelGGL(normalize_kernel, dim3(bv), dim3(kTBlock), 0, st, w, nv, S.nrm + 3, done, w);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "GMRES step launch");
     if (j + 1 < m && (j + 1) % s->every == 0) {
@@ -1060,7 +1110,8 @@ tfs_status tfs_transport_destroy(tfs_transport s) {
   if (s->have_fwd) hipfftDestroy(s->fwd);
   if (s->have_inv) hipfftDestroy(s->inv);
   drop_batched(s);
-  for (double* b : {s->rg, s->x1g, s->fg, s->xg, s->part, s->mean, s->basis, s->dpart, s->coef, s->part2})
+  for (double* b :
+       {s->rg, s->x1g, s->fg, s->xg, s->part, s->mean, s->basis, s->dpart, s->coef, s->part2, s->npart})
     if (b) (void)hipFree(b);
   if (s->gflag) (void)hipFree(s->gflag);
   for (double2* b : {s->rh, s->xh, s->fh, s->eh, s->iv})
@@ -1099,10 +1150,11 @@ tfs_status tfs_transport_set_method(tfs_transport s, int method) {
     hipError_t e = hipMalloc((void**)&s->basis, sizeof(double) * nv * (s->iters + 1));
     if (e == hipSuccess) e = hipMalloc((void**)&s->dpart, sizeof(double) * kDotBlocks * (s->iters + 1));
     if (e == hipSuccess) e = hipMalloc((void**)&s->coef, sizeof(double) * gm_doubles(s->iters));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->npart, sizeof(double) * kMaxBlocks);
     if (e == hipSuccess) e = hipMalloc((void**)&s->gflag, sizeof(int) * kGmFlags);
     if (e == hipSuccess) e = hipMemset(s->gflag, 0, sizeof(int) * kGmFlags);
     if (e != hipSuccess) {
-      for (double** b : {&s->basis, &s->dpart, &s->coef})
+      for (double** b : {&s->basis, &s->dpart, &s->coef, &s->npart})
         if (*b) { (void)hipFree(*b); *b = nullptr; }
       if (s->gflag) { (void)hipFree(s->gflag); s->gflag = nullptr; }
       return set_error(TFS_ENOMEM, "device allocation of the Krylov basis failed");
