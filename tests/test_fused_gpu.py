@@ -243,3 +243,32 @@ def test_fused_large_field_table(d, prec, nterms, steady, scheme):
     print("large table", d, prec, nterms, steady, scheme, "oracle", errs, "stepwise", errs_step, flush=True)
     assert all(e < bar for e in errs.values()), errs
     assert all(e < bar for e in errs_step.values()), errs_step
+
+
+@pytest.mark.parametrize("scheme,nterms", [("bdf2", 256), ("exp", 256), ("exp", 128), ("bdf2", 257)])
+def test_fused_lds_limits(scheme, nterms):
+    """The LDS a fused launch asks for at its limits in 3-D: the BDF2 kernel with 256
+    time-varying terms copies a 32 KB table and rotates 64 terms a lane (128 KB), 160 KB per
+    block; 257 terms no longer fit either, so the table stays in global memory and the terms
+    are evaluated directly; the exponential kernel with 128 terms rotates 64 a lane next to a
+    16 KB table, and with 256 evaluates them directly next to the 32 KB table."""
+    d, grid, prec = 3, 10, "fp32_modes"
+    ff = many_terms_field(d, nterms, 11 + nterms, False)
+    P = grid ** d - 3
+    point0 = 2
+    chunks = (5, 33)                              # passes a re-seed of the rotated terms
+    N = sum(chunks) + (1 if scheme == "bdf2" else 0)
+    dt = 2e-3
+    plan, w, lam = make_plan(d, P, 16, prec, dt, N, scheme=scheme)
+    X0 = I.random_symmetric_case(d, P, 53, kscale=0.6, xscale=2e-2)[1]
+    kl = levels(ff, grid, np.arange(point0, point0 + P), dt, N)
+    X, Y, tau, _ = fused_run(plan, ff, grid, point0, X0, chunks, kap0=kl[0] if scheme == "bdf2" else None)
+    Xs, Ys, taus = stepwise_run(plan, kl, X0, N)
+    o = O.run(d, w, lam, 1.0, 0.1, dt, N, kl, X0, startup="sdirk2" if scheme == "bdf2" else "exp")
+    got = {"X": X[N % 2, :, :P].cpu().numpy(), "tau": tau[:, :P].cpu().numpy()}
+    step = {"X": Xs[N % 2, :, :P].cpu().numpy(), "tau": taus[:, :P].cpu().numpy()}
+    errs = {k: relerr(got[k], o["X"][0] if k == "X" else o[k]) for k in got}
+    errs_step = {k: relerr(got[k], step[k]) for k in got}
+    print("lds limits", scheme, nterms, "oracle", errs, "stepwise", errs_step, flush=True)
+    assert all(e < 1e-5 for e in errs.values()), errs
+    assert all(e < 1e-5 for e in errs_step.values()), errs_step
