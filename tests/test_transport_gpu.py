@@ -184,6 +184,27 @@ def test_transport_exponential_scheme_uniform_fields_and_gmres(d, shape, extent,
     assert all(v < 1e-12 for v in errs.values()), errs
 
 
+@pytest.mark.parametrize("iters", [1, 2])
+@pytest.mark.parametrize("scheme", ["bdf2", "exp"])
+@pytest.mark.parametrize("d,shape,extent", [CASES[0], CASES[3]])
+def test_gmres_one_step_is_exact_on_uniform_fields(d, shape, extent, scheme, iters):
+    """Uniform u and kappa: the preconditioner inverts the operator, N = 0, and GMRES is exact
+    after one Arnoldi step (a breakdown: the Hessenberg matrix of I + N is the identity), also
+    with a cap of one step."""
+    P = int(np.prod(shape))
+    c = d * (d + 1) // 2
+    N, De, eta_p, eps, dt = 5, 0.8, 0.1, 0.05, 2e-3
+    w, lam, _ = osoe.soe_fit(0.5, 6, dt, dt * N)
+    u, kap = fields(d, shape, extent, N + 1, 97 + d, uniform=True)
+    X0 = np.random.default_rng(98).standard_normal((c, P)) * 0.05
+    g = gpu_run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, u, X0, "fp64", True, iters, method="gmres",
+                scheme=scheme)
+    o = mfp.run(d, shape, extent, eps, w, lam, De, eta_p, dt, N, kap, X0, want_modes=True, u=u, scheme=scheme)
+    errs = {"X": relerr(g["X"], o["X"]), "tau": relerr(g["tau"], o["tau"]), "modes": relerr(g["modes"], o["modes"][0])}
+    print("gmres uniform", scheme, d, iters, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert all(v < 1e-12 for v in errs.values()), errs
+
+
 @pytest.mark.parametrize("N", [1, 2, 9])
 @pytest.mark.parametrize("d,shape,extent", CASES)
 def test_transport_gmres_matches_spatial_oracle(d, shape, extent, N):
