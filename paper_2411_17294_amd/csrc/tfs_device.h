@@ -66,7 +66,10 @@ __device__ __forceinline__ void build_M(const double (&k)[D * D], double a, doub
 }
 
 // Solve M x = r in place (r becomes x) by Gaussian elimination with partial pivoting.
-// Row exchanges are selects, so every lane runs the same instruction stream.
+// Row exchanges are selects, so every lane runs the same instruction stream; a column's
+// selects are skipped where no lane of the wave exchanges rows there (they would change
+// nothing), which is the common case: the local operators are diagonally dominant at the
+// workloads' time steps.
 template <int N>
 __device__ __forceinline__ void solve_pivot(double (&M)[N][N], double (&r)[N]) {
 #pragma unroll
@@ -80,6 +83,7 @@ __device__ __forceinline__ void solve_pivot(double (&M)[N][N], double (&r)[N]) {
       best = gt ? v : best;
       p = gt ? i : p;
     }
+    if (__any(p != j))
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
       const bool sw = (p == i);

@@ -147,3 +147,49 @@ def test_alpha_chain_in_the_library(scheme):
     rc = tfs.lib().tfs_pbar_to_params(plan.handle, pb.ctypes.data_as(C.POINTER(C.c_double)), None, None, None,
                                       None, None, None, C.pointer(out))
     assert rc == tfs.TFS_EINVAL
+
+
+def per_point_magnitude(d, w, lam, De, eta_p, dt, N, kappa, X0, target, dw, dl):
+    """Sum over the points of |dL_p/dq| for the scalar parameters q (De, eta_p, alpha), from the
+    oracle's complex-step derivatives point by point (L is a sum over the points)."""
+    from oracle import oracle as O
+    from tests.grad_helpers import H_CS, pack_weights
+    wts = pack_weights(d)[:, None]
+    resid = O.run(d, w, lam, De, eta_p, dt, N, kappa, X0)["tau"] - target
+    out = {}
+    for name, dDe, dep, dwv, dlv in (("De", 1.0, 0.0, 0.0, 0.0), ("eta_p", 0.0, 1.0, 0.0, 0.0),
+                                     ("alpha", 0.0, 0.0, 1.0, 1.0)):
+        r = O.run_complex(d, np.asarray(w, complex) + 1j * H_CS * dwv * np.asarray(dw),
+                          np.asarray(lam, complex) + 1j * H_CS * dlv * np.asarray(dl), De + 1j * H_CS * dDe,
+                          eta_p + 1j * H_CS * dep, dt, N, kappa.astype(complex), X0.astype(complex))
+        out[name] = float(np.abs(np.sum(wts * resid * (r["tau"].imag / H_CS), axis=0)).sum())
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_adjoint_with_row_exchanges(d, prec):
+    """Velocity gradients from zero up to b max|kappa| = 1.5 a (the local operator a I - b K):
+    the transposed solves of a wave exchange rows at some points and not at others.  The
+    per-point gradients (kappa, X0) are held to the bar relative to their largest value; the
+    scalar gradients, sums over the points whose terms partly cancel here (by up to 7x), to
+    the bar relative to the sum of the per-point terms' magnitudes."""
+    P, N, m, dt, De = 389, 3, 5, 1e-2, 1.1
+    rng = np.random.default_rng(80 + d)
+    scale = np.linspace(0.0, 1.0, P)[rng.permutation(P)]
+    kappa = rng.standard_normal((d * d, P)) * scale[None, :]
+    _, X0, w, lam, dw, dl, target = setup(d, P, m, 81 + d, dt=dt)
+    b0 = 1.5
+    eta = sum(b0 * wk * dt / (b0 + lk * dt) for wk, lk in zip(w, lam))
+    kappa *= 1.5 * (b0 + eta / De) / (eta * np.abs(kappa).max())
+    print(f"adjoint row exchanges d={d} {prec}", flush=True)
+    o = oracle_gradients(d, w, lam, De, 0.1, dt, N, kappa, X0, target, dw_da=dw, dl_da=dl)
+    g = gpu_gradients(d, w, lam, 0.45, De, 0.1, dt, N, kappa, X0, target, precision=prec, dw_da=dw, dl_da=dl)
+    mag = per_point_magnitude(d, w, lam, De, 0.1, dt, N, kappa, X0, target, dw, dl)
+    errs = {"kappa": relerr(g["kappa"], o["kappa"]), "X0": relerr(g["X0"], o["X0"])}
+    for k in ("De", "eta_p", "alpha"):
+        errs[k] = abs(g[k] - o[k]) / mag[k]
+    print(f"adj row exchanges d={d} {prec}", {k: f"{v:.2e}" for k, v in errs.items()},
+          {k: f"cancellation {mag[k] / abs(o[k]):.1f}" for k in mag}, flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= BAR[prec]}
+    assert not bad, bad

@@ -470,3 +470,59 @@ def test_empty_plan():
     torch.cuda.synchronize()
     d = diag.cpu().numpy()
     assert math.isinf(d[0]) and d[3] == 0 and d[4] == 0 and d[5] == 0
+
+
+def _packed_pairs(d):
+    return [(0, 0), (1, 1), (0, 1)] if d == 2 else [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+
+
+def local_matrix(d, k, a, b):
+    """The step's local operator a I - b K(kappa) on packed symmetric tensors (row s: the
+    component (i, j) of a X - b (kappa X + X kappa^T))."""
+    pairs = _packed_pairs(d)
+    idx = {}
+    for s, (i, j) in enumerate(pairs):
+        idx[(i, j)] = idx[(j, i)] = s
+    M = a * np.eye(len(pairs))
+    for s, (i, j) in enumerate(pairs):
+        for l in range(d):
+            M[s, idx[(l, j)]] -= b * k[i * d + l]
+            M[s, idx[(i, l)]] -= b * k[j * d + l]
+    return M
+
+
+def partial_pivot_exchanges(M):
+    """Row exchanges of Gaussian elimination with partial pivoting (strict comparison)."""
+    A = M.copy()
+    n, swaps = A.shape[0], 0
+    for j in range(n):
+        p = j + int(np.argmax(np.abs(A[j:, j])))
+        if abs(A[p, j]) > abs(A[j, j]):
+            A[[j, p]] = A[[p, j]]
+            swaps += 1
+        A[j + 1:] -= np.outer(A[j + 1:, j] / A[j, j], A[j])
+    return swaps
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_local_solve_with_row_exchanges(d, prec):
+    """Velocity gradients from zero up to b max|kappa| = 1.5 a, where the local operator a I - b K
+    needs row exchanges: within one wave some points exchange rows and others do not, so the
+    solve's exchange selects run for some columns and are skipped for others."""
+    P, N, dt = 389, 3, 1e-2
+    rng = np.random.default_rng(70 + d)
+    scale = np.linspace(0.0, 1.0, P)[rng.permutation(P)]
+    kappa = rng.standard_normal((d * d, P)) * scale[None, :]
+    _, X0 = I.random_symmetric_case(d, P, 71 + d, kscale=0.5, xscale=1e-2)
+    w, lam, _ = osoe.soe_fit(0.45, 7, dt, 0.05)
+    plan = tfs.Plan(d, P, w, lam, 0.45, 1.0, 0.1, dt, N, precision=prec)
+    t = plan.tables()
+    # b max|kappa| = 1.5 a at the largest point, the others spread down to zero
+    kappa *= 1.5 * t["a_diag"] / (t["eta"] * np.abs(kappa).max())
+    swaps = np.array([partial_pivot_exchanges(local_matrix(d, kappa[:, p], t["a_diag"], t["eta"])) for p in range(P)])
+    print(f"row exchanges d={d} {prec}: points with exchanges {np.count_nonzero(swaps)} of {P}", flush=True)
+    assert 0.1 * P < np.count_nonzero(swaps) < 0.9 * P
+    g = run_gpu(d, w, lam, 1.0, 0.1, dt, N, kappa, X0, precision=prec, want_modes=True, alpha=0.45)
+    o = O.run(d, w, lam, 1.0, 0.1, dt, N, kappa, X0, want_modes=True)
+    compare(g, o, prec, diag=False, label=f"row exchanges d={d} {prec}")
