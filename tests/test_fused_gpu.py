@@ -272,3 +272,39 @@ def test_fused_lds_limits(scheme, nterms):
     print("lds limits", scheme, nterms, "oracle", errs, "stepwise", errs_step, flush=True)
     assert all(e < 1e-5 for e in errs.values()), errs
     assert all(e < 1e-5 for e in errs_step.values()), errs_step
+
+
+@pytest.mark.parametrize("scheme", ["exp", "bdf2"])
+def test_fused_with_row_exchanges(scheme):
+    """The 3-D field's amplitudes scaled until b max|kappa~| = 1.5 a in the local operator
+    a I - b K of the scheme's steps: the local solves exchange rows at some points (the
+    exchange selects run for those waves), against the step-by-step path and the oracle."""
+    d, grid, prec, m = 3, 10, "fp32_modes", 16
+    P = grid ** d - 3
+    point0 = 2
+    chunks = (4, 5)
+    N = sum(chunks) + (1 if scheme == "bdf2" else 0)
+    dt = 2e-3
+    plan, w, lam = make_plan(d, P, m, prec, dt, N, scheme=scheme)
+    t = plan.tables()
+    a, b = t["a_diag"], t["eta"]      # the operator's a and b (for the exponential scheme 1 + q/De and q)
+    ff = field_of(5, False)
+    kl = levels(ff, grid, np.arange(point0, point0 + P), dt, N)
+    ff.amp = ff.amp * (1.5 * a / (b * np.abs(kl).max()))
+    kl = levels(ff, grid, np.arange(point0, point0 + P), dt, N)
+    from tests.test_parity_gpu import local_matrix, partial_pivot_exchanges
+    kt = 2.0 * kl[2] - kl[1] if scheme == "bdf2" else 1.5 * kl[2] - 0.5 * kl[1]    # kappa~ of step 2
+    nsw = sum(partial_pivot_exchanges(local_matrix(d, kt[:, p], a, b)) > 0 for p in range(P))
+    assert 0.05 * P < nsw < 0.95 * P, nsw
+    X0 = I.random_symmetric_case(d, P, 57, kscale=0.6, xscale=2e-2)[1]
+    X, Y, tau, _ = fused_run(plan, ff, grid, point0, X0, chunks, kap0=kl[0] if scheme == "bdf2" else None)
+    Xs, Ys, taus = stepwise_run(plan, kl, X0, N)
+    o = O.run(d, w, lam, 1.0, 0.1, dt, N, kl, X0, startup="sdirk2" if scheme == "bdf2" else "exp")
+    got = {"X": X[N % 2, :, :P].cpu().numpy(), "tau": tau[:, :P].cpu().numpy()}
+    step = {"X": Xs[N % 2, :, :P].cpu().numpy(), "tau": taus[:, :P].cpu().numpy()}
+    errs = {k: relerr(got[k], o["X"][0] if k == "X" else o[k]) for k in got}
+    errs_step = {k: relerr(got[k], step[k]) for k in got}
+    print("fused row exchanges", scheme, "points exchanging at step 2", nsw, "oracle", errs, "stepwise",
+          errs_step, flush=True)
+    assert all(e < 1e-5 for e in errs.values()), errs
+    assert all(e < 1e-5 for e in errs_step.values()), errs_step
