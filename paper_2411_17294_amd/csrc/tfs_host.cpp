@@ -510,6 +510,8 @@ tfs_status tfs_plan_destroy(tfs_plan p) {
   (void)hipFree(p->d_dest_start);
   (void)hipFree(p->d_dest_exp);
   (void)hipFree(p->d_field);
+  (void)hipFree(p->d_field_roots);
+  (void)hipFree(p->d_field_k);
   (void)hipFree(p->d_zeta);
   delete p;
   if (e1 != hipSuccess) return hip_fail(e1, "hipStreamSynchronize");
@@ -562,15 +564,45 @@ tfs_status tfs_plan_set_field(tfs_plan p, const tfs_field* f) {
     if (e != hipSuccess) { (void)hipFree(dz); return hip_fail(e, "upload zeta"); }
     p->d_zeta = dz;
   }
-  double* df = nullptr;
+  // the lattice form where every wave vector is an integer vector, |sum_j k_j idx_j| stays in
+  // int32 and the roots of unity and the terms' rotations fit the evaluation's LDS
+  bool lattice = f->nterms > 0 && 16 * (f->grid + (int64_t)f->nterms) <= tfs::kFieldLatticeLds;
+  std::vector<int32_t> kint((size_t)std::max(1, f->nterms) * d, 0);
+  for (int n = 0; lattice && n < f->nterms; ++n)
+    for (int j = 0; j < d; ++j) {
+      const double kv = f->k[n * d + j];
+      if (kv != std::floor(kv) || std::fabs(kv) * (double)d * (double)f->grid >= 2147483647.0) lattice = false;
+      else kint[(size_t)n * d + j] = (int32_t)kv;
+    }
+  std::vector<double> roots(lattice ? (size_t)2 * f->grid : 0);
+  for (int64_t m = 0; lattice && m < f->grid; ++m) {   // in extended precision, rounded once
+    const long double a = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)f->grid;
+    roots[2 * m] = (double)std::cos(a);
+    roots[2 * m + 1] = (double)std::sin(a);
+  }
+  double *df = nullptr, *dr = nullptr;
+  int32_t* dk = nullptr;
+  auto drop = [&]() {
+    (void)hipFree(df);
+    (void)hipFree(dr);
+    (void)hipFree(dk);
+  };
   hipError_t e = hipMalloc(&df, sizeof(double) * tab.size());
-  if (e != hipSuccess) return fail(TFS_ENOMEM, "field table");
+  if (e == hipSuccess && lattice) e = hipMalloc(&dr, sizeof(double) * roots.size());
+  if (e == hipSuccess && lattice) e = hipMalloc(&dk, sizeof(int32_t) * kint.size());
+  if (e != hipSuccess) { drop(); return fail(TFS_ENOMEM, "field table"); }
   e = hipMemcpy(df, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) { (void)hipFree(df); return hip_fail(e, "upload field"); }
-  e = hipStreamSynchronize(p->stream);   // launches that read the old table have finished
-  if (e != hipSuccess) { (void)hipFree(df); return hip_fail(e, "hipStreamSynchronize"); }
+  if (e == hipSuccess && lattice) e = hipMemcpy(dr, roots.data(), sizeof(double) * roots.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && lattice) e = hipMemcpy(dk, kint.data(), sizeof(int32_t) * kint.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { drop(); return hip_fail(e, "upload field"); }
+  e = hipStreamSynchronize(p->stream);   // launches that read the old tables have finished
+  if (e != hipSuccess) { drop(); return hip_fail(e, "hipStreamSynchronize"); }
   (void)hipFree(p->d_field);
+  (void)hipFree(p->d_field_roots);
+  (void)hipFree(p->d_field_k);
   p->d_field = df;
+  p->d_field_roots = dr;
+  p->d_field_k = dk;
   p->field_terms = f->nterms;
   p->field_grid = f->grid;
   p->field_point0 = f->point0;

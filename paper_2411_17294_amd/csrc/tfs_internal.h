@@ -58,6 +58,9 @@ constexpr int kBlock = 256;
 // Upper bound of blocks per compute unit of the grid-stride launches (sizes the
 // diagnostic scratch).
 constexpr int kMaxBlocksPerCU = 64;
+// LDS (bytes) of the field evaluation's lattice form: the grid's roots of unity and one
+// rotation per term, 16 bytes each
+constexpr int64_t kFieldLatticeLds = 32768;
 // Scalar sums per block of one adjoint launch, and the scalar block of pbar.
 constexpr int kNumAdjScalars = 9;
 constexpr int kPbarScalars = 16;
@@ -149,6 +152,10 @@ struct tfs_plan_s {
   int field_terms = 0;
   int64_t field_grid = 0, field_point0 = 0;
   bool field_steady = false;
+  // lattice form of the field (integer wave vectors, small grid): the grid's roots of unity
+  // (cos, sin)(2 pi m / grid), m < grid, and the wave vectors as integers; null otherwise
+  double* d_field_roots = nullptr;   // device [field_grid][2]
+  int32_t* d_field_k = nullptr;      // device [field_terms][d]
   const double* sp_rate = nullptr;   // spatial form: extra relaxation rate per point (caller-owned)
   int64_t sp_source = -1;            // spatial form: the point with the mass-mode source, -1 = all
   int grid_per_cu = 16;

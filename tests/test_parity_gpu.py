@@ -526,3 +526,61 @@ def test_local_solve_with_row_exchanges(d, prec):
     g = run_gpu(d, w, lam, 1.0, 0.1, dt, N, kappa, X0, precision=prec, want_modes=True, alpha=0.45)
     o = O.run(d, w, lam, 1.0, 0.1, dt, N, kappa, X0, want_modes=True)
     compare(g, o, prec, diag=False, label=f"row exchanges d={d} {prec}")
+
+
+def field_extended(ff, grid, idx, t):
+    """kappa of the field at grid points idx and time t in extended precision, with the phase
+    k . x = 2 pi m / grid reduced exactly (m = k . idx mod grid, integer wave vectors)."""
+    ld = np.longdouble
+    pi = ld("3.141592653589793238462643383279502884")
+    m = (idx @ ff.k.T.astype(np.int64)) % grid
+    th = 2 * pi * m.astype(ld) / grid + ff.phase.astype(ld)[None] + ff.omega.astype(ld)[None] * ld(t)
+    B = ff.coef().reshape(len(ff.amp), -1).astype(ld)
+    return (np.sin(th) @ B).T
+
+
+@pytest.mark.parametrize("kappa", ["fp64", "fp32"])
+def test_field_lattice_form_against_extended_precision(kappa):
+    """The workloads' fields have integer wave vectors, which the library evaluates in the
+    lattice form (roots of unity of the grid times each term's rotation): against the field in
+    extended precision with the phase reduced exactly, FP64 within 4e-15 of max|kappa| (a few
+    ulp per term; an FP64 phase k . x + phi alone would cost ~1e-13), FP32 within its rounding."""
+    from paper_2411_17294_amd.device_inputs import DeviceKappa
+    dt = torch.float32 if kappa == "fp32" else torch.float64
+    tol = 1e-7 if kappa == "fp32" else 4e-15
+    for cid in (2, 5):
+        wl = I.WORKLOADS[cid]
+        ff = I.fourier_field(wl)
+        n = min(wl.npoints, 1 << 20)
+        off = (wl.npoints - n) // 3
+        dk = DeviceKappa(ff, wl.grid, n, offset=off)
+        out = torch.zeros((wl.dim ** 2, n), dtype=dt, device="cuda")
+        dk.fill(out, 0.37)
+        torch.cuda.synchronize()
+        pts = np.random.default_rng(10 + cid).integers(0, n, 500)
+        ref = field_extended(ff, wl.grid, I.grid_multi_index(wl.grid, wl.dim, off + pts), 0.37)
+        got = out[:, torch.from_numpy(pts).cuda()].double().cpu().numpy().astype(np.longdouble)
+        e = float(np.abs(got - ref).max() / np.abs(ref).max())
+        print(f"lattice form, workload {cid} kappa {kappa}: err {e:.1e}", flush=True)
+        assert e < tol
+
+
+def test_field_with_non_integer_wave_vectors():
+    """A wave vector off the lattice (k + 1/2 in one component): the field is evaluated with a
+    sine of each term's FP64 phase, against the host generator."""
+    wl = I.WORKLOADS[5]
+    ff = I.fourier_field(wl)
+    ff.k = ff.k.astype(np.float64)
+    ff.k[3, 1] += 0.5
+    g, P = wl.grid, 50000
+    w, lam, _ = osoe.soe_fit(0.3, 6, 1e-3, 1e-2)
+    plan = tfs.Plan(3, P, w, lam, 0.3, 1.0, 0.1, 1e-3, 8)
+    plan.set_field(ff.k, ff.phase, ff.omega, ff.coef(), g, 1234)
+    out = plan.kappa_tensor()
+    plan.field_eval(0.21, out)
+    torch.cuda.synchronize()
+    pts = np.random.default_rng(3).integers(0, P, 500)
+    ref = ff.kappa_at(I.grid_multi_index(g, 3, 1234 + pts), g, 0.21)
+    e = relerr(out[:, torch.from_numpy(pts).cuda()].cpu().numpy(), ref)
+    print(f"non-integer wave vector: rel err {e:.1e}", flush=True)
+    assert e < 1e-12
