@@ -215,8 +215,12 @@ tfs_status tfs_plan_set_field(tfs_plan plan, const tfs_field* field);
 
 /*
  * The plan's analytic velocity gradient (tfs_plan_set_field) at time t on the plan's points,
- * written for the step calls: kappa_out[q][p] = kappa_q(x_p, t) + add[q][p], each Fourier term's
- * phase and sine and the sums in FP64, rounded once to the plan's kappa precision.  This is
+ * written for the step calls: kappa_out[q][p] = kappa_q(x_p, t) + add[q][p], the sums in FP64,
+ * rounded once to the plan's kappa precision.  With integer wave vectors (and grid + nterms
+ * <= 2048) each term's sine is a root of unity of the grid, e^{2 pi i (k . idx mod grid)/grid},
+ * times the term's e^{i (phase + omega t)}: the phase is reduced exactly, within a few ulp of
+ * the field; otherwise the sine of each term's FP64 phase (whose rounding, |k . x| 2^-53, is
+ * the error there).  This is
  * input synthesis for callers whose gradient is that field (the benchmark workloads); the
  * update itself never calls it.
  * add        device [d*d][stride] FP64 (a steady perturbation of the field), or NULL.
