@@ -30,6 +30,10 @@ constexpr int kRotTerms = 64;
 constexpr int kReseed = 32;
 // Largest field table (bytes) copied into each block's LDS.
 constexpr size_t kTabLdsMax = 32768;
+// Doubles of padding per row of the LDS copy: a 3-D row is 16 doubles, 128 bytes, so the rows
+// that the lanes of a point read at once (consecutive terms) would all start on the same LDS
+// bank; 16 bytes more per row spreads four of them over distinct banks.
+constexpr int kTabPad = 2;
 
 template <typename MT>
 struct FusedArgs {
@@ -69,15 +73,15 @@ __device__ __forceinline__ double lanes_sum(double v) {
 // sine comes from the later one by angle addition, sin(a - w dt) = sin a cos(w dt) -
 // cos a sin(w dt), so each term costs one sincos.  Lane h of the point's L lanes sums the
 // terms n = h, h + L, ...; the caller adds the lanes' sums.
-// The field table is read from LDS (a block copy of it) or from global memory: the lanes of
-// a point read different terms, so global reads are vector loads, one memory round trip per
-// term.
-template <bool LF>
+// The field table is read from LDS (a block copy of it, rows padded by kTabPad) or from
+// global memory: the lanes of a point read different terms, so global reads are vector
+// loads, one memory round trip per term.  f(n, j): entry j of term n's row.
+template <bool LF, int W>
 struct FieldTab {
   const double* t;                                   // LDS copy (LF) or global table
-  __device__ __forceinline__ double operator()(int i) const {
-    if constexpr (LF) return t[i];
-    else return load_uniform(opaque_ptr(t) + i);
+  __device__ __forceinline__ double operator()(int n, int j) const {
+    if constexpr (LF) return t[n * (W + kTabPad) + j];
+    else return load_uniform(opaque_ptr(t) + n * W + j);
   }
 };
 
@@ -88,17 +92,16 @@ __device__ __forceinline__ void field_kappa(const FT& f, int nterms, int h, cons
 #pragma unroll
   for (int q = 0; q < D * D; ++q) kap[q] = 0.0;
   for (int n = h; n < nterms; n += L) {
-    const int r = n * W;
     double th = 0.0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) th += x[j] * f(r + j);
-    th = th + f(r + D) + f(r + D + 1) * t;
+    for (int j = 0; j < D; ++j) th += x[j] * f(n, j);
+    th = th + f(n, D) + f(n, D + 1) * t;
     double sn, cn;
     sincos(th, &sn, &cn);
     double wgt = sn;
-    if (gb != 0.0) wgt = ga * sn + gb * (sn * f(r + D + 2) - cn * f(r + D + 3));
+    if (gb != 0.0) wgt = ga * sn + gb * (sn * f(n, D + 2) - cn * f(n, D + 3));
 #pragma unroll
-    for (int q = 0; q < D * D; ++q) kap[q] += wgt * f(r + D + 4 + q);
+    for (int q = 0; q < D * D; ++q) kap[q] += wgt * f(n, D + 4 + q);
   }
 #pragma unroll
   for (int q = 0; q < D * D; ++q) kap[q] = lanes_sum<L>(kap[q]);
@@ -111,11 +114,10 @@ __device__ __forceinline__ void rot_seed(const FT& f, int nterms, int h, const d
   constexpr int W = D + 4 + D * D;
   int i = 0;
   for (int n = h; n < nterms; n += L, ++i) {
-    const int r = n * W;
     double th = 0.0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) th += x[j] * f(r + j);
-    th = th + f(r + D) + f(r + D + 1) * t;
+    for (int j = 0; j < D; ++j) th += x[j] * f(n, j);
+    th = th + f(n, D) + f(n, D + 1) * t;
     double sn, cn;
     sincos(th, &sn, &cn);
     rot[i * kFusedBlock + threadIdx.x] = make_double2(sn, cn);
@@ -137,12 +139,12 @@ __device__ __forceinline__ void rot_kappa(const FT& f, int nterms, int h, double
     // scheduler interleaved reads and uses in the BDF2 kernel, one LDS round trip per read.
     struct Term { double2 sc; double cw, sw, b[D * D]; };
     auto read = [&](int i, Term& t) {
-      const int r = (h + i * L) * W;
+      const int n = h + i * L;
       t.sc = rot[i * kFusedBlock + threadIdx.x];
-      t.cw = f(r + D + 2);
-      t.sw = f(r + D + 3);
+      t.cw = f(n, D + 2);
+      t.sw = f(n, D + 3);
 #pragma unroll
-      for (int q = 0; q < D * D; ++q) t.b[q] = f(r + D + 4 + q);
+      for (int q = 0; q < D * D; ++q) t.b[q] = f(n, D + 4 + q);
     };
     auto use = [&](int i, const Term& t) {
       double wgt = t.sc.x;
@@ -170,13 +172,13 @@ __device__ __forceinline__ void rot_kappa(const FT& f, int nterms, int h, double
     // 2-D: two terms in flight (measured faster than one)
 #pragma unroll 2
     for (int i = 0; i < cnt; ++i) {
-      const int r = (h + i * L) * W;
+      const int n = h + i * L;
       const double2 sc = rot[i * kFusedBlock + threadIdx.x];
-      const double cw = f(r + D + 2), sw = f(r + D + 3);
+      const double cw = f(n, D + 2), sw = f(n, D + 3);
       double wgt = sc.x;
       if (gb != 0.0) wgt = ga * sc.x + gb * (sc.x * cw - sc.y * sw);
 #pragma unroll
-      for (int q = 0; q < D * D; ++q) kap[q] += wgt * f(r + D + 4 + q);
+      for (int q = 0; q < D * D; ++q) kap[q] += wgt * f(n, D + 4 + q);
       rot[i * kFusedBlock + threadIdx.x] = make_double2(sc.x * cw + sc.y * sw, sc.y * cw - sc.x * sw);
     }
   }
@@ -216,19 +218,20 @@ __device__ __forceinline__ void mode_pass(const double* coef, int k0, const doub
   }
 }
 
-// Dynamic LDS of a fused launch: the field table (when it is copied, nterms W doubles,
-// rounded to 16 bytes), then the rotated terms.  Every thread of the block takes part in the
+// Dynamic LDS of a fused launch: the field table (when it is copied, nterms rows of W +
+// kTabPad doubles), then the rotated terms.  Every thread of the block takes part in the
 // copy, before any returns.
 template <int D, bool LF, typename MT>
-__device__ __forceinline__ FieldTab<LF> stage_field(const FusedArgs<MT>& a, double2* smem, double2** rot) {
+__device__ __forceinline__ FieldTab<LF, D + 4 + D * D> stage_field(const FusedArgs<MT>& a, double2* smem,
+                                                                   double2** rot) {
   constexpr int W = D + 4 + D * D;
-  FieldTab<LF> f;
+  FieldTab<LF, W> f;
   if constexpr (LF) {
     const int tabn = a.nterms * W;
     double* tab = reinterpret_cast<double*>(smem);
-    for (int i = threadIdx.x; i < tabn; i += kFusedBlock) tab[i] = a.field[i];
+    for (int i = threadIdx.x; i < tabn; i += kFusedBlock) tab[(i / W) * (W + kTabPad) + i % W] = a.field[i];
     __syncthreads();
-    *rot = smem + (tabn + 1) / 2;
+    *rot = smem + (a.nterms * (W + kTabPad) + 1) / 2;
     f.t = tab;
   } else {
     *rot = smem;
@@ -249,7 +252,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_exp_kernel(const FusedArgs<
   const int h = (int)(g % L);
   extern __shared__ double2 smem[];
   double2* rot;
-  const FieldTab<LF> f = stage_field<D, LF>(a, smem, &rot);
+  const auto f = stage_field<D, LF>(a, smem, &rot);
   if (p >= a.npoints) return;
   const int64_t st = a.stride, T = a.tile;
   const int64_t ym = (p / T) * (int64_t)M * C * T + p % T;   // mode (0, 0) of the point
@@ -427,7 +430,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bdf2_kernel(const FusedArgs
   const int h = (int)(g % L);
   extern __shared__ double2 smem[];
   double2* rot;
-  const FieldTab<LF> f = stage_field<D, LF>(a, smem, &rot);
+  const auto f = stage_field<D, LF>(a, smem, &rot);
   if (p >= a.npoints) return;
   const int64_t st = a.stride, T = a.tile;
   const int64_t ys = (int64_t)M * C * st;                     // one ring slot
@@ -528,9 +531,9 @@ hipError_t fused_go(const tfs_plan_s* p, int64_t n0, int64_t nsteps, double* X, 
   if constexpr (BDF2) a.a_diag = p->a_diag;
   const int64_t blocks = (p->npoints * L + kFusedBlock - 1) / kFusedBlock;
   const int per_lane = (p->field_terms + L - 1) / L;
-  // the field table goes to LDS when it is small (64 terms: 8 KB in 3-D); with the largest
-  // rotated set (64 terms a lane, 128 KB) the block holds 160 KB, the CU's whole LDS
-  const size_t tab = sizeof(double2) * (((size_t)p->field_terms * (D + 4 + D * D) + 1) / 2);
+  // the field table goes to LDS when it is small (64 terms: 9 KB in 3-D); with the largest
+  // rotated set (64 terms a lane, 128 KB) the block holds at most 160 KB, the CU's whole LDS
+  const size_t tab = sizeof(double2) * (((size_t)p->field_terms * (D + 4 + D * D + kTabPad) + 1) / 2);
   const bool lf = tab <= kTabLdsMax;
   const size_t lds = (lf ? tab : 0) +
                      ((!p->field_steady && per_lane <= kRotTerms) ? sizeof(double2) * per_lane * kFusedBlock : 0);

@@ -245,13 +245,13 @@ def test_fused_large_field_table(d, prec, nterms, steady, scheme):
     assert all(e < bar for e in errs_step.values()), errs_step
 
 
-@pytest.mark.parametrize("scheme,nterms", [("bdf2", 256), ("exp", 256), ("exp", 128), ("bdf2", 257)])
+@pytest.mark.parametrize("scheme,nterms", [("bdf2", 227), ("bdf2", 228), ("exp", 128), ("bdf2", 257)])
 def test_fused_lds_limits(scheme, nterms):
-    """The LDS a fused launch asks for at its limits in 3-D: the BDF2 kernel with 256
-    time-varying terms copies a 32 KB table and rotates 64 terms a lane (128 KB), 160 KB per
-    block; 257 terms no longer fit either, so the table stays in global memory and the terms
-    are evaluated directly; the exponential kernel with 128 terms rotates 64 a lane next to a
-    16 KB table, and with 256 evaluates them directly next to the 32 KB table."""
+    """The LDS a fused launch asks for at its limits in 3-D (table rows of 18 doubles): the BDF2
+    kernel with 227 time-varying terms copies a 32 688-byte table, just under the 32 KB limit,
+    and rotates 57 terms a lane (117 KB), 149 KB per block; with 228 the table stays in global
+    memory; with 257 (65 a lane) the terms are evaluated directly; the exponential kernel with
+    128 terms rotates 64 a lane (128 KB) next to an 18 KB table."""
     d, grid, prec = 3, 10, "fp32_modes"
     ff = many_terms_field(d, nterms, 11 + nterms, False)
     P = grid ** d - 3
