@@ -472,6 +472,32 @@ def test_empty_plan():
     assert math.isinf(d[0]) and d[3] == 0 and d[4] == 0 and d[5] == 0
 
 
+@pytest.mark.parametrize("scheme", ["bdf2", "exp"])
+def test_empty_plan_other_entry_points(scheme):
+    """Zero points: the adjoint (every level down to the start-up), the no-alloc step, the field
+    evaluation and a fused launch return without touching any buffer; the adjoint's
+    parameter gradients stay zero and the diagnostics are those of an empty set."""
+    w, lam, _ = osoe.soe_fit(0.5, 16, 1e-3, 0.1)
+    plan = tfs.Plan(2, 0, w, lam, 0.5, 1.0, 0.1, 1e-3, 6, scheme=scheme, mode_form="y")
+    dummy = torch.full((8,), 3.0, dtype=torch.float64, device="cuda")
+    pbar = torch.zeros(plan.pbar_size, dtype=torch.float64, device="cuda")
+    for n in (3, 2, 1, 0):
+        plan.step_adjoint(n, dummy, dummy if n > 0 else None, dummy, dummy if n > 0 else None, dummy,
+                          dummy if n > 0 else None, None, dummy, dummy, pbar, taubar=dummy, kappabar_a=dummy,
+                          kappabar_b=dummy)
+    diag = torch.full((6,), -7.0, dtype=torch.float64, device="cuda")
+    plan.step_noalloc(0, dummy, None, dummy, dummy, None, diag)
+    ff = I.fourier_field(I.WORKLOADS[2])
+    plan.set_field(ff.k, ff.phase, ff.omega, ff.coef(), 32, 0)
+    plan.field_eval(0.25, dummy)
+    plan.run_fused(1, 3, dummy, dummy, dummy)
+    torch.cuda.synchronize()
+    assert bool((dummy == 3.0).all())
+    assert bool((pbar == 0.0).all())
+    d = diag.cpu().numpy()
+    assert math.isinf(d[0]) and d[3] == 0 and d[4] == 0 and d[5] == 0
+
+
 def _packed_pairs(d):
     return [(0, 0), (1, 1), (0, 1)] if d == 2 else [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
 
