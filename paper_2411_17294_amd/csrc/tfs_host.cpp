@@ -564,14 +564,16 @@ tfs_status tfs_plan_set_field(tfs_plan p, const tfs_field* f) {
     if (e != hipSuccess) { (void)hipFree(dz); return hip_fail(e, "upload zeta"); }
     p->d_zeta = dz;
   }
-  // the lattice form where every wave vector is an integer vector, |sum_j k_j idx_j| stays in
-  // int32 and the roots of unity and the terms' rotations fit the evaluation's LDS
+  // the lattice form where every wave vector is an integer vector, |sum_j k_j idx_j| plus one
+  // grid length stays in int32 (the evaluation's floor(m / grid) grid may sit a grid length
+  // below m) and the roots of unity and the terms' rotations fit the evaluation's LDS
   bool lattice = f->nterms > 0 && 16 * (f->grid + (int64_t)f->nterms) <= tfs::kFieldLatticeLds;
   std::vector<int32_t> kint((size_t)std::max(1, f->nterms) * d, 0);
   for (int n = 0; lattice && n < f->nterms; ++n)
     for (int j = 0; j < d; ++j) {
       const double kv = f->k[n * d + j];
-      if (kv != std::floor(kv) || std::fabs(kv) * (double)d * (double)f->grid >= 2147483647.0) lattice = false;
+      if (kv != std::floor(kv) || (std::fabs(kv) * (double)d + 1.0) * (double)f->grid >= 2147483647.0)
+        lattice = false;
       else kint[(size_t)n * d + j] = (int32_t)kv;
     }
   std::vector<double> roots(lattice ? (size_t)2 * f->grid : 0);
