@@ -190,6 +190,74 @@ tfs_status tfs_plan_set_stream(tfs_plan plan, void* stream);
 tfs_status tfs_plan_set_spatial(tfs_plan plan, const double* rate, int64_t source_point);
 
 /*
+ * Fourier layout of the spatial form on a periodic box (Sec. 4.1, eq. FP_discrete with
+ * L = -eps Laplace - A(kappa~)): the basis tfs_plan_set_spatial takes, its rate field and
+ * the changes of basis before and after a run.
+ *
+ * A box of shape[0..dim-1] grid points (C order, last axis fastest), N = n_0 ... n_{d-1}
+ * of them, and extent[0..dim-1] lengths.  A real grid field f has the half spectrum
+ *     F_q = (1/N) sum_x f(x) exp(-i xi_q . x),
+ * q in C order over n_0 x ... x n_{d-2} x (n_{d-1}/2 + 1), so the zero wave vector holds
+ * the mean.  Coefficient q takes the points 2q (real part) and 2q + 1 (imaginary part):
+ * npoints = 2 n_0 ... n_{d-2} (n_{d-1}/2 + 1).  Integer wave numbers run 0, 1, .., -1 on the
+ * leading axes (the Nyquist index of an even axis reads -n/2) and 0 .. n/2 on the last;
+ * xi_j = 2 pi k_j / L_j.  Point 0, the constant function's coefficient, is the source
+ * point.  The way back sums F_q exp(i xi_q . x) over the whole spectrum, the missing half
+ * being the complex conjugate.  It assumes coefficients of a real field, conjugate-symmetric
+ * where the half spectrum holds both partners (the planes of zero and Nyquist wave number
+ * on the last axis); the steps of tfs_plan_set_spatial keep that symmetry, since both
+ * partners of a pair see the same rate and the source reaches only the real part of the
+ * zero wave vector.
+ *
+ * The object owns hipFFT (rocFFT) plans for one plane and a one-plane work buffer, both
+ * made at creation; the conversions allocate nothing.  Each call runs asynchronously on the
+ * stream it is given (a hipStream_t, NULL = default stream); calls on one object that
+ * overlap in time (several streams or threads) race on the work buffer.
+ */
+typedef struct tfs_spectral_s* tfs_spectral;
+
+/* Errors: TFS_EINVAL (dim not 2 or 3, null shape, extent or out, an axis outside 2 .. 2^20
+ * points, an extent not finite and > 0, more than 2^30 points), TFS_ENOMEM, TFS_EHIP (hipFFT
+ * plan creation included).  *out is NULL on error. */
+tfs_status tfs_spectral_create(int dim, const int64_t* shape, const double* extent, tfs_spectral* out);
+
+/* Release the object (NULL is accepted); synchronises the device first. */
+tfs_status tfs_spectral_destroy(tfs_spectral s);
+
+/* npoints of the layout (-1 for NULL). */
+int64_t tfs_spectral_npoints(tfs_spectral s);
+
+/*
+ * The rate field of tfs_plan_set_spatial: rate[2q] = rate[2q + 1] = eps |xi_q|^2, and zero
+ * at points npoints .. stride - 1.
+ * rate  device [stride] FP64, caller-owned.
+ * Errors: TFS_EINVAL (null object or rate, eps not finite and >= 0, stride < npoints).
+ */
+tfs_status tfs_spectral_rate(tfs_spectral s, double eps, double* rate, int64_t stride, void* stream);
+
+/*
+ * Grid fields to coefficients.
+ * grid    device [nfields][grid_stride] FP64 (grid_stride >= N), read only.
+ * points  device [nfields][point_stride] FP64 (point_stride >= npoints); points npoints ..
+ *         point_stride - 1 of each plane are left as they are.  It must not overlap grid.
+ * nfields 0 does nothing.
+ * Errors: TFS_EINVAL (null object, nfields < 0, a null buffer with nfields > 0, a stride too
+ * small), TFS_EHIP.
+ */
+tfs_status tfs_spectral_to_points(tfs_spectral s, const double* grid, int64_t nfields, int64_t grid_stride,
+                                  double* points, int64_t point_stride, void* stream);
+
+/*
+ * Coefficients to grid fields, the inverse of tfs_spectral_to_points.
+ * points  device [nfields][point_stride] FP64 (point_stride >= npoints), read only.
+ * grid    device [nfields][grid_stride] FP64 (grid_stride >= N); grid points N ..
+ *         grid_stride - 1 of each plane are left as they are.  It must not overlap points.
+ * Errors as tfs_spectral_to_points.
+ */
+tfs_status tfs_spectral_to_grid(tfs_spectral s, const double* points, int64_t nfields, int64_t point_stride,
+                                double* grid, int64_t grid_stride, void* stream);
+
+/*
  * Analytic velocity gradient for fused launches: a sum of Fourier terms on the periodic
  * grid [0, 2 pi)^d with `grid` points per axis,
  *     kappa_ij(x, t) = sum_n coef[n][i][j] sin(k[n] . x + phase[n] + omega[n] t),

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtfs.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("tfs_kernels.hip", "tfs_adjoint.hip", "tfs_fused.hip", "tfs_ns.hip", "tfs_transport.hip",
-                                                          "tfs_field.hip", "tfs_host.cpp")]
+                                                          "tfs_field.hip", "tfs_spectral.hip", "tfs_host.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -56,7 +56,7 @@ def build(verbose: bool = False, extra=None) -> str:
             print(out)
     if failed:
         raise RuntimeError("hipcc failed:\n" + "\n".join(failed))
-    # the coupled step's transforms: hipFFT (resolved against the copy already loaded by
+    # the transforms of the coupled step and the spectral layout: hipFFT (resolved against the copy already loaded by
     # torch when there is one, since the sonames agree)
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-L/opt/rocm/lib", "-lhipfft", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

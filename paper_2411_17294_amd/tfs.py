@@ -31,7 +31,9 @@ EXPORTS = ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_pl
            "tfs_ns_create", "tfs_ns_destroy", "tfs_ns_spectral_size", "tfs_ns_batched", "tfs_ns_set_batched", "tfs_ns_set_transport", "tfs_ns_init",
            "tfs_ns_step", "tfs_transport_create", "tfs_transport_destroy", "tfs_transport_step",
            "tfs_transport_batched", "tfs_transport_set_batched", "tfs_transport_set_method",
-           "tfs_transport_set_tolerance", "tfs_transport_last_iterations")
+           "tfs_transport_set_tolerance", "tfs_transport_last_iterations",
+           "tfs_spectral_create", "tfs_spectral_destroy", "tfs_spectral_npoints", "tfs_spectral_rate",
+           "tfs_spectral_to_points", "tfs_spectral_to_grid")
 
 
 # Mode-ring tile (points) used when the caller does not choose one: 32 KB mode planes
@@ -123,6 +125,13 @@ def lib():
     L.tfs_transport_last_iterations.restype = C.c_int
     L.tfs_ns_init.argtypes = [vp, vp, vp, vp, vp]
     L.tfs_ns_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.tfs_spectral_create.argtypes = [C.c_int, C.POINTER(i64), dp, C.POINTER(C.c_void_p)]
+    L.tfs_spectral_destroy.argtypes = [vp]
+    L.tfs_spectral_npoints.argtypes = [vp]
+    L.tfs_spectral_npoints.restype = i64
+    L.tfs_spectral_rate.argtypes = [vp, C.c_double, vp, i64, vp]
+    L.tfs_spectral_to_points.argtypes = [vp, vp, i64, i64, vp, i64, vp]
+    L.tfs_spectral_to_grid.argtypes = [vp, vp, i64, i64, vp, i64, vp]
     for name in ("tfs_plan_create", "tfs_plan_destroy", "tfs_plan_set_stream", "tfs_plan_set_spatial", "tfs_step",
                  "tfs_step_levels", "tfs_plan_set_field", "tfs_field_eval", "tfs_run_fused",
                  "tfs_step_adjoint", "tfs_pbar_to_params", "tfs_pbar_rate_gradient", "tfs_modes_to_plain",
@@ -130,7 +139,9 @@ def lib():
                  "tfs_ns_create", "tfs_ns_destroy", "tfs_ns_set_batched", "tfs_ns_set_transport", "tfs_ns_init", "tfs_ns_step",
                  "tfs_transport_create", "tfs_transport_destroy", "tfs_transport_step",
            "tfs_transport_batched", "tfs_transport_set_batched", "tfs_transport_set_method",
-           "tfs_transport_set_tolerance", "tfs_transport_last_iterations"):
+           "tfs_transport_set_tolerance", "tfs_transport_last_iterations",
+                 "tfs_spectral_create", "tfs_spectral_destroy", "tfs_spectral_rate", "tfs_spectral_to_points",
+                 "tfs_spectral_to_grid"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
