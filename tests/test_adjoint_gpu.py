@@ -25,7 +25,7 @@ def setup(d, P, m, seed, alpha=0.45, dt=2e-3, T=0.05):
     return kappa, X0, w, lam, dw, dl, target
 
 
-def compare(g, o, prec, per_mode=True, label=""):
+def compare(g, o, prec, per_mode=True, label="", bar=None):
     errs = {"kappa": relerr(g["kappa"], o["kappa"]), "X0": relerr(g["X0"], o["X0"]),
             "De": abs(g["De"] - o["De"]) / abs(o["De"]), "eta_p": abs(g["eta_p"] - o["eta_p"]) / abs(o["eta_p"])}
     if "alpha" in o:
@@ -34,7 +34,7 @@ def compare(g, o, prec, per_mode=True, label=""):
         errs["w"] = relerr(g["w"], o["w"])
         errs["lam"] = relerr(g["lam"], o["lam"])
     print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    bad = {k: v for k, v in errs.items() if not v <= BAR[prec]}
+    bad = {k: v for k, v in errs.items() if not v <= (bar or BAR[prec])}
     assert not bad, f"{label}: {bad}"
 
 
@@ -69,6 +69,37 @@ def test_adjoint_whole_waves_and_tail(d, prec, adj_vec, tile, m):
     g = gpu_gradients(d, w, lam, 0.45, 1.1, 0.1, 2e-3, N, kappa, X0, target, precision=prec, tile=tile,
                       dw_da=dw, dl_da=dl, tune={"adj_vec": adj_vec})
     compare(g, o, prec, per_mode=False, label=f"adj waves d={d} {prec} V={adj_vec} tile={tile} m={m}")
+
+
+@pytest.mark.parametrize("scheme", ["bdf2", "exp"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_modes"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_adjoint_maximum_mode_count(d, prec, scheme):
+    """m = 256, the most modes a plan takes (the adjoint's per-mode partials and its LDS at
+    their largest), 197 points, per-mode gradients included.
+
+    FP64 bar: the stress sums 256 modes that nearly cancel (poles up to 4e8), so the FP64
+    oracle's own stress is off by e_o = 5e-13 .. 1.1e-12 against its extended-precision run
+    here, and the loss's cotangents inherit that rounding; the gradients are held to
+    max(1e-12, 4 e_o), the rule of the full-size forward checks, with e_o measured below."""
+    from oracle import oracle as O
+    from tests.gpu_helpers import relerr_ref
+    m, P, N = 256, 197, 5
+    kappa, X0, w, lam, dw, dl, target = setup(d, P, m, 700 + d)
+    print(f"adjoint max modes d={d} {prec} {scheme}", flush=True)
+    o = oracle_gradients(d, w, lam, 1.1, 0.1, 2e-3, N, kappa, X0, target, dw_da=dw, dl_da=dl, per_mode=True,
+                         scheme=scheme)
+    g = gpu_gradients(d, w, lam, 0.45, 1.1, 0.1, 2e-3, N, kappa, X0, target, precision=prec, dw_da=dw, dl_da=dl,
+                      scheme=scheme)
+    bar = None
+    if prec == "fp64":
+        st = "exp" if scheme == "exp" else "sdirk2"
+        fo = O.run(d, w, lam, 1.1, 0.1, 2e-3, N, kappa, X0, startup=st)
+        fl = O.run_long(d, w, lam, 1.1, 0.1, 2e-3, N, kappa, X0, startup=st)
+        e_o = relerr_ref(fo["tau"], fl["tau"])
+        bar = max(BAR["fp64"], 4.0 * e_o)
+        print(f"  FP64 oracle stress error {e_o:.2e}, bar {bar:.2e}", flush=True)
+    compare(g, o, prec, label=f"adj max modes d={d} {prec} {scheme}", bar=bar)
 
 
 @pytest.mark.parametrize("scheme", ["bdf2", "exp"])
