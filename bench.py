@@ -127,9 +127,10 @@ def measure_forms(stream, steps=20, which="all"):
     * FP32 modes vs FP64: one forward step of the 256^3, m = 40 configuration in each form
       (same seeded inputs), the speedup, and the relative difference of the two stresses
       after the same steps.
-    * Forward + adjoint, 128^3, m = 32, FP32 modes: per time level the differentiation pass
-      runs one forward step (ring), one recomputed step into per-level buffers and one
-      adjoint step; each is timed and priced at its algorithmic bytes.
+    * Forward + adjoint, 128^3, m = 32, FP32 modes and FP64: per time level the
+      differentiation pass runs one forward step (ring), one recomputed step into per-level
+      buffers and one adjoint step; each is timed and priced at its algorithmic bytes, and
+      the FP32-mode time level is compared with the FP64 one.
     """
     import torch
     from paper_2411_17294_amd import inputs as I
@@ -140,6 +141,9 @@ def measure_forms(stream, steps=20, which="all"):
         out["fp32_vs_fp64_3d"] = _fp32_vs_fp64(stream, steps)
     if which in ("all", "fwd_adjoint"):
         out["fwd_adjoint_3d"] = _fwd_adjoint(stream, steps)
+        out["fwd_adjoint_3d_fp64"] = _fwd_adjoint(stream, steps, precision="fp64")
+        out["fwd_adjoint_3d"]["speedup_vs_fp64"] = (out["fwd_adjoint_3d_fp64"]["ms_per_time_level"]
+                                                    / out["fwd_adjoint_3d"]["ms_per_time_level"])
     if which in ("all", "exp_vs_bdf2"):
         out["exp_vs_bdf2_3d"] = _exp_vs_bdf2(stream, steps)
     if which in ("all", "fwd_adjoint_exp"):
@@ -449,9 +453,10 @@ def _fused(stream, K=50):
     return res
 
 
-def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
+def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2", precision=None):
     """Forward (ring), recompute (levels) and adjoint steps of a differentiation workload on
-    npoints points (default: the whole grid; a slab of the grid for the 384^3 case)."""
+    npoints points (default: the whole grid; a slab of the grid for the 384^3 case), in the
+    workload's precision form or the one given (FP64 plans read FP64 velocity gradients)."""
     import numpy as np
     import torch
     from paper_2411_17294_amd import inputs as I
@@ -460,12 +465,15 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
     wl = I.WORKLOADS[workload]
     P = wl.npoints if npoints is None else npoints
     alpha = wl.alphas[0]
+    prec = precision or wl.precision
+    f32 = prec == "fp32_modes"
+    mb = kb_ = 4 if f32 else 8                # mode and velocity-gradient bytes
     w, lam, _, _, _ = tfs.soe_fit(alpha, wl.nmodes, wl.dt, wl.dt * wl.nsteps)
     # the library's mode-ring tile (32 KB planes: 8192 FP32 points), measured best for the
     # current kernels at both the 128^3 grid and the 384^3 slab
     tile = None
-    p = tfs.Plan(wl.dim, P, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=wl.precision,
-                 scheme=scheme, tile=tile, kappa="fp32")
+    p = tfs.Plan(wl.dim, P, w, lam, alpha, wl.De, wl.eta_p, wl.dt, wl.nsteps, precision=prec,
+                 scheme=scheme, tile=tile, kappa="fp32" if f32 else "fp64")
     exp = scheme == "exp"
     ka, kb = p.kappa_tensor(), p.kappa_tensor()
     dk = DeviceKappa(I.fourier_field(wl), wl.grid, P)
@@ -509,14 +517,14 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
             p.step_adjoint(n, ka, kb, Xs[1], Xs[0], Xs[2], Ys[1], Ys[0], Xbar, Hbar, pbar, kappabar_a=kbar,
                            kappabar_b=kbar, X_nm2=Xs[3])
     if exp:
-        fb = exp_bytes_per_point(wl.dim, m, 4, 2, 4) * P
+        fb = exp_bytes_per_point(wl.dim, m, mb, 2, kb_) * P
         rb = fb - c * 8 * P
-        ab = exp_adjoint_bytes_per_point(wl.dim, m, 4, 4) * P
+        ab = exp_adjoint_bytes_per_point(wl.dim, m, mb, kb_) * P
     else:
-        fb = algorithmic_bytes_per_point(wl.dim, m, 4, 2, 4, p.x_levels) * P
+        fb = algorithmic_bytes_per_point(wl.dim, m, mb, 2, kb_, p.x_levels) * P
         rb = fb - c * 8 * P            # the recomputation writes no stress
-        ab = adjoint_bytes_per_point(wl.dim, m, 4, 4, p.x_levels) * P
-    tag = "fp32modes_3d_128cube_m32" if workload == 4 else "fp32modes_3d_384cube_m48_slab"
+        ab = adjoint_bytes_per_point(wl.dim, m, mb, kb_, p.x_levels) * P
+    tag = ("fp32modes" if f32 else "fp64") + ("_3d_128cube_m32" if workload == 4 else "_3d_384cube_m48_slab")
     kf, ka_ = ("exp_kernel_", "exp_adj_kernel_") if exp else ("bdf2_kernel_", "adj_kernel_")
     parts = {}
     for name, fn, nbytes, prof in (("forward", fwd, fb, kf + tag),
@@ -529,7 +537,7 @@ def _fwd_adjoint(stream, steps, workload=4, npoints=None, scheme="bdf2"):
         parts[name] = {"ms_per_step": ms, "bytes_per_launch": nbytes, "achieved_GBs": gbs,
                        "frac": gbs / HBM_PEAK_GBS, "traffic": profiled_traffic(prof)}
     total = sum(v["ms_per_step"] for v in parts.values())
-    out = {"workload": wl.name, "form": wl.precision, "scheme": scheme, "points": P, **parts,
+    out = {"workload": wl.name, "form": prec, "scheme": scheme, "points": P, **parts,
            "ms_per_time_level": total,
            "point_mode_updates_per_s": P * m / (total * 1e-3),
            "mode_form": "shifted (Z)" if p.x_levels == 3 else "Y",
