@@ -150,6 +150,11 @@ def measure_forms(stream, steps=20, which="all"):
         out["fwd_adjoint_3d_exp"] = _fwd_adjoint(stream, steps, scheme="exp")
     if which in ("all", "slab384"):
         out["fwd_adjoint_384cube_slab"] = _fwd_adjoint(stream, steps, workload=5, npoints=SLAB_384)
+        out["fwd_adjoint_384cube_slab_fp64"] = _fwd_adjoint(stream, steps, workload=5, npoints=SLAB_384,
+                                                            precision="fp64")
+        out["fwd_adjoint_384cube_slab"]["speedup_vs_fp64"] = (
+            out["fwd_adjoint_384cube_slab_fp64"]["ms_per_time_level"]
+            / out["fwd_adjoint_384cube_slab"]["ms_per_time_level"])
     if which in ("all", "mfp_2d"):
         out["mfp_spectral_2d"] = _mfp_2d(stream, steps)
     if which in ("all", "fused"):
