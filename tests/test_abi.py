@@ -104,3 +104,37 @@ def test_soe_fit_rejects_bad_arguments():
     assert e.value.status == tfs.TFS_EINVAL
     with pytest.raises(tfs.TfsError):
         tfs.soe_fit(0.5, 4, 1e-3, 1e-4)
+
+
+@pytest.mark.parametrize("dim,shape,extent", [(1, (8, 6), (1.0, 1.0)), (4, (8, 6), (1.0, 1.0)),
+                                              (2, (1, 6), (1.0, 1.0)), (2, (8, 2 ** 20 + 1), (1.0, 1.0)),
+                                              (3, (2 ** 10, 2 ** 10, 2 ** 11), (1.0, 1.0, 1.0)),
+                                              (2, (8, 6), (1.0, 0.0)), (2, (8, 6), (float("inf"), 1.0)),
+                                              (2, (8, 6), (1.0, float("nan")))])
+def test_spectral_layout_rejects_invalid_box(dim, shape, extent):
+    """The Fourier layout's box is checked before any device call (Sec. 4.1, the spatial form's
+    periodic grid): bad dimension, an axis outside 2 .. 2^20, more than 2^30 points, extents
+    that are not finite and positive."""
+    L = tfs.lib()
+    n = max(dim, len(shape))
+    sh = (C.c_int64 * n)(*(list(shape) + [8] * (n - len(shape))))
+    ex = (C.c_double * n)(*(list(extent) + [1.0] * (n - len(extent))))
+    h = C.c_void_p(123)
+    assert L.tfs_spectral_create(dim, sh, ex, C.byref(h)) == tfs.TFS_EINVAL
+    assert h.value is None
+    assert tfs.lib().tfs_last_error()
+
+
+def test_spectral_layout_null_arguments():
+    L = tfs.lib()
+    sh = (C.c_int64 * 2)(8, 6)
+    ex = (C.c_double * 2)(1.0, 1.0)
+    h = C.c_void_p()
+    assert L.tfs_spectral_create(2, None, ex, C.byref(h)) == tfs.TFS_EINVAL
+    assert L.tfs_spectral_create(2, sh, None, C.byref(h)) == tfs.TFS_EINVAL
+    assert L.tfs_spectral_create(2, sh, ex, None) == tfs.TFS_EINVAL
+    assert L.tfs_spectral_npoints(None) == -1
+    assert L.tfs_spectral_destroy(None) == tfs.TFS_OK
+    assert L.tfs_spectral_rate(None, 1.0, None, 64, None) == tfs.TFS_EINVAL
+    assert L.tfs_spectral_to_points(None, None, 0, 48, None, 64, None) == tfs.TFS_EINVAL
+    assert L.tfs_spectral_to_grid(None, None, 0, 64, None, 48, None) == tfs.TFS_EINVAL
